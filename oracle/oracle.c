@@ -1,0 +1,503 @@
+/*
+ * FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * Every function restates a definition of the AIRLab paper (arXiv
+ * 1806.09907) in the plainest form that still finishes in seconds at 128^3:
+ * the B-spline field is the direct sum over the 4^d controls whose kernel
+ * support contains the voxel (Sec. II-A eq. kernel_basis, Sec. III-C k_B1D);
+ * its adjoint is the same sum read per control; sampling is the zero-padded
+ * multilinear interpolation of a grid sampler (Sec. III-C Image Warping);
+ * NCC uses two-pass centred statistics; the diffusion term is evaluated
+ * voxel by voxel with forward differences (Sec. II-A eq. diffusion).
+ * Loops are parallel over the slowest axis only, and every reduction is
+ * summed per slab and then serially, so results do not depend on threads.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static int g_threads = 0;
+
+void airo_set_threads(int nthreads) { g_threads = nthreads > 0 ? nthreads : 0; }
+
+int airo_get_threads(void) {
+#ifdef _OPENMP
+    return g_threads > 0 ? g_threads : omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+#ifdef _OPENMP
+#define NTHREADS num_threads(airo_get_threads())
+#endif
+
+int airo_check(const airo_problem* p) {
+    if (!p) return 1;
+    if (p->dim != 2 && p->dim != 3) return 1;
+    for (int a = 0; a < p->dim; ++a) {
+        if (p->n[a] < 2) return 1;
+        if (p->transform == AIRO_TF_BSPLINE3 && p->spacing[a] < 1) return 1;
+    }
+    if (p->dim == 2 && p->n[2] != 1) return 1;
+    if (p->transform != AIRO_TF_BSPLINE3 && p->transform != AIRO_TF_DENSE) return 1;
+    if (p->similarity != AIRO_SIM_MSE && p->similarity != AIRO_SIM_NCC) return 1;
+    return 0;
+}
+
+int airo_ncontrol(const airo_problem* p, int axis) {
+    if (axis >= p->dim) return 1;
+    return (p->n[axis] - 1) / p->spacing[axis] + 4;
+}
+
+long airo_nvox(const airo_problem* p) {
+    long n = 1;
+    for (int a = 0; a < p->dim; ++a) n *= p->n[a];
+    return n;
+}
+
+static long ncontrols_total(const airo_problem* p) {
+    long n = 1;
+    for (int a = 0; a < p->dim; ++a) n *= airo_ncontrol(p, a);
+    return n;
+}
+
+long airo_param_count(const airo_problem* p) {
+    if (p->transform == AIRO_TF_DENSE) return (long)p->dim * airo_nvox(p);
+    return (long)p->dim * ncontrols_total(p);
+}
+
+/* k_B1D of Sec. III-C: 2/3 - |r|^2 + |r|^3/2 on [0,1), (2-|r|)^3/6 on [1,2). */
+double airo_bspline_kernel(double r) {
+    double a = fabs(r);
+    if (a < 1.0) return 2.0 / 3.0 - a * a + a * a * a / 2.0;
+    if (a < 2.0) return (2.0 - a) * (2.0 - a) * (2.0 - a) / 6.0;
+    return 0.0;
+}
+
+/* Position (voxels) of control j along an axis with spacing s. */
+static double control_pos(int j, int s) { return (double)(j - 1) * s; }
+
+/* For voxel coordinate x: its first supporting control index (floor(x/s))
+ * and the four kernel values k((x - pos(i+k)) / s), k = 0..3. */
+static int support(int x, int s, double w[4]) {
+    int i = x / s;
+    for (int k = 0; k < 4; ++k)
+        w[k] = airo_bspline_kernel(((double)x - control_pos(i + k, s)) / (double)s);
+    return i;
+}
+
+void airo_bspline_expand(const airo_problem* p, const double* theta, double* u) {
+    const int d = p->dim;
+    const int nx = p->n[0], ny = p->n[1], nz = (d == 3) ? p->n[2] : 1;
+    const int ncx = airo_ncontrol(p, 0), ncy = airo_ncontrol(p, 1);
+    const int ncz = (d == 3) ? airo_ncontrol(p, 2) : 1;
+    const long N = (long)nx * ny * nz;
+    const long NC = (long)ncx * ncy * ncz;
+    const int sx = p->spacing[0], sy = p->spacing[1], sz = (d == 3) ? p->spacing[2] : 1;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) NTHREADS
+#endif
+    for (int z = 0; z < nz; ++z) {
+        double wz[4] = {1.0, 0.0, 0.0, 0.0};
+        int iz = 0;
+        if (d == 3) iz = support(z, sz, wz);
+        for (int y = 0; y < ny; ++y) {
+            double wy[4];
+            int iy = support(y, sy, wy);
+            for (int x = 0; x < nx; ++x) {
+                double wx[4];
+                int ix = support(x, sx, wx);
+                for (int c = 0; c < d; ++c) {
+                    double acc = 0.0;
+                    for (int kz = 0; kz < (d == 3 ? 4 : 1); ++kz)
+                        for (int ky = 0; ky < 4; ++ky)
+                            for (int kx = 0; kx < 4; ++kx) {
+                                long j = ((long)(iz + kz) * ncy + (iy + ky)) * ncx + (ix + kx);
+                                acc += wz[kz] * wy[ky] * wx[kx] * theta[c * NC + j];
+                            }
+                    u[c * N + ((long)z * ny + y) * nx + x] = acc;
+                }
+            }
+        }
+    }
+}
+
+/* Voxel range [lo, hi] inside which control j has non-zero support. */
+static void control_support(int j, int s, int n, int* lo, int* hi) {
+    double c = control_pos(j, s);
+    int a = (int)floor(c - 2.0 * s);
+    int b = (int)ceil(c + 2.0 * s);
+    if (a < 0) a = 0;
+    if (b > n - 1) b = n - 1;
+    *lo = a;
+    *hi = b;
+}
+
+void airo_bspline_adjoint(const airo_problem* p, const double* g, double* out) {
+    const int d = p->dim;
+    const int nx = p->n[0], ny = p->n[1], nz = (d == 3) ? p->n[2] : 1;
+    const int ncx = airo_ncontrol(p, 0), ncy = airo_ncontrol(p, 1);
+    const int ncz = (d == 3) ? airo_ncontrol(p, 2) : 1;
+    const long N = (long)nx * ny * nz;
+    const long NC = (long)ncx * ncy * ncz;
+    const int sx = p->spacing[0], sy = p->spacing[1], sz = (d == 3) ? p->spacing[2] : 1;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic) NTHREADS
+#endif
+    for (int jz = 0; jz < ncz; ++jz) {
+        int z0 = 0, z1 = 0;
+        if (d == 3) control_support(jz, sz, nz, &z0, &z1);
+        for (int jy = 0; jy < ncy; ++jy) {
+            int y0, y1;
+            control_support(jy, sy, ny, &y0, &y1);
+            for (int jx = 0; jx < ncx; ++jx) {
+                int x0, x1;
+                control_support(jx, sx, nx, &x0, &x1);
+                double acc[3] = {0.0, 0.0, 0.0};
+                for (int z = z0; z <= z1; ++z) {
+                    double kz = (d == 3)
+                        ? airo_bspline_kernel(((double)z - control_pos(jz, sz)) / sz) : 1.0;
+                    if (kz == 0.0) continue;
+                    for (int y = y0; y <= y1; ++y) {
+                        double ky = airo_bspline_kernel(((double)y - control_pos(jy, sy)) / sy);
+                        if (ky == 0.0) continue;
+                        for (int x = x0; x <= x1; ++x) {
+                            double kx = airo_bspline_kernel(((double)x - control_pos(jx, sx)) / sx);
+                            if (kx == 0.0) continue;
+                            long v = ((long)z * ny + y) * nx + x;
+                            double w = kz * ky * kx;
+                            for (int c = 0; c < d; ++c) acc[c] += w * g[c * N + v];
+                        }
+                    }
+                }
+                long j = ((long)jz * ncy + jy) * ncx + jx;
+                for (int c = 0; c < d; ++c) out[c * NC + j] = acc[c];
+            }
+        }
+    }
+}
+
+void airo_displacement(const airo_problem* p, const double* theta, double* u) {
+    if (p->transform == AIRO_TF_DENSE)
+        memcpy(u, theta, sizeof(double) * (size_t)p->dim * (size_t)airo_nvox(p));
+    else
+        airo_bspline_expand(p, theta, u);
+}
+
+void airo_sample(const airo_problem* p, const double* moving, const double* u,
+                 double* warped, unsigned char* mask, double* dwdp) {
+    const int d = p->dim;
+    const int nx = p->n[0], ny = p->n[1], nz = (d == 3) ? p->n[2] : 1;
+    const int n[3] = {nx, ny, nz};
+    const long N = (long)nx * ny * nz;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) NTHREADS
+#endif
+    for (int z = 0; z < nz; ++z) {
+        for (int y = 0; y < ny; ++y) {
+            for (int x = 0; x < nx; ++x) {
+                const long v = ((long)z * ny + y) * nx + x;
+                const int idx[3] = {x, y, z};
+                double pt[3], f[3];
+                long j[3];
+                int inside = 1, finite = 1;
+                for (int a = 0; a < d; ++a) {
+                    pt[a] = idx[a] + u[a * N + v] * (n[a] - 1) / 2.0;
+                    if (!isfinite(pt[a])) finite = 0;
+                    if (!(pt[a] >= 0.0 && pt[a] <= n[a] - 1)) inside = 0;
+                    /* far outside: every corner is padding; keep floor() in range */
+                    if (pt[a] > 1e9) pt[a] = 1e9;
+                    if (pt[a] < -1e9) pt[a] = -1e9;
+                }
+                if (mask) mask[v] = (unsigned char)(inside && finite);
+                if (!finite) {
+                    if (warped) warped[v] = NAN;
+                    if (dwdp) for (int a = 0; a < d; ++a) dwdp[a * N + v] = NAN;
+                    continue;
+                }
+                for (int a = 0; a < d; ++a) {
+                    j[a] = (long)floor(pt[a]);
+                    f[a] = pt[a] - (double)j[a];
+                }
+                double W = 0.0, dW[3] = {0.0, 0.0, 0.0};
+                const int ncorner = 1 << d;
+                for (int c = 0; c < ncorner; ++c) {
+                    int bit[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+                    long q[3] = {0, 0, 0};
+                    int in_range = 1;
+                    for (int a = 0; a < d; ++a) {
+                        q[a] = j[a] + bit[a];
+                        if (q[a] < 0 || q[a] > n[a] - 1) in_range = 0;
+                    }
+                    double val = in_range ? moving[(q[2] * ny + q[1]) * nx + q[0]] : 0.0;
+                    double wgt = 1.0;
+                    for (int a = 0; a < d; ++a) wgt *= bit[a] ? f[a] : 1.0 - f[a];
+                    W += wgt * val;
+                    for (int a = 0; a < d; ++a) {
+                        double wa = bit[a] ? 1.0 : -1.0;
+                        for (int b = 0; b < d; ++b)
+                            if (b != a) wa *= bit[b] ? f[b] : 1.0 - f[b];
+                        dW[a] += wa * val;
+                    }
+                }
+                if (warped) warped[v] = W;
+                if (dwdp) for (int a = 0; a < d; ++a) dwdp[a * N + v] = dW[a];
+            }
+        }
+    }
+}
+
+void airo_warp(const airo_problem* p, const double* moving, const double* theta,
+               double* warped, unsigned char* mask) {
+    const long N = airo_nvox(p);
+    double* u = (double*)malloc(sizeof(double) * (size_t)p->dim * (size_t)N);
+    airo_displacement(p, theta, u);
+    airo_sample(p, moving, u, warped, mask, NULL);
+    free(u);
+}
+
+/* Per-slab partial sums, added serially in slab order. */
+static int slab_count(const airo_problem* p) { return p->dim == 3 ? p->n[2] : p->n[1]; }
+static long slab_size(const airo_problem* p) {
+    return p->dim == 3 ? (long)p->n[0] * p->n[1] : (long)p->n[0];
+}
+
+int airo_similarity(const airo_problem* p, const double* fixed, const double* warped,
+                    const unsigned char* mask, double* value, double* dsdw) {
+    const long N = airo_nvox(p);
+    const int ns = slab_count(p);
+    const long ss = slab_size(p);
+    int flags = 0;
+    double* part = (double*)calloc((size_t)ns * 6, sizeof(double));
+    /* pass 1: count, sums of F and W (and of squared error for MSE) */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) NTHREADS
+#endif
+    for (int s = 0; s < ns; ++s) {
+        double cnt = 0, sf = 0, sw = 0, se = 0;
+        for (long v = s * ss; v < (s + 1) * ss; ++v) {
+            if (!mask[v]) continue;
+            cnt += 1.0;
+            sf += fixed[v];
+            sw += warped[v];
+            se += (warped[v] - fixed[v]) * (warped[v] - fixed[v]);
+        }
+        part[6 * s + 0] = cnt;
+        part[6 * s + 1] = sf;
+        part[6 * s + 2] = sw;
+        part[6 * s + 3] = se;
+    }
+    double cnt = 0, sf = 0, sw = 0, se = 0;
+    for (int s = 0; s < ns; ++s) {
+        cnt += part[6 * s + 0];
+        sf += part[6 * s + 1];
+        sw += part[6 * s + 2];
+        se += part[6 * s + 3];
+    }
+    if (p->similarity == AIRO_SIM_MSE) {
+        /* Sec. II-A eq. (mse), over the masked set X' (normalised by N'). */
+        if (cnt < 1.0) {
+            *value = 0.0;
+            flags |= AIRO_FLAG_DEGENERATE;
+            if (dsdw) memset(dsdw, 0, sizeof(double) * (size_t)N);
+        } else {
+            *value = se / cnt;
+            if (dsdw)
+                for (long v = 0; v < N; ++v)
+                    dsdw[v] = mask[v] ? 2.0 * (warped[v] - fixed[v]) / cnt : 0.0;
+        }
+        free(part);
+        if (!isfinite(*value)) flags |= AIRO_FLAG_NONFINITE;
+        return flags;
+    }
+    /* NCC (Sec. III-B): Pearson correlation of F and W over X', loss -rho.
+     * pass 2: centred sums about the exact means. */
+    if (cnt < 2.0) {
+        *value = 0.0;
+        if (dsdw) memset(dsdw, 0, sizeof(double) * (size_t)N);
+        free(part);
+        return flags | AIRO_FLAG_DEGENERATE;
+    }
+    const double muf = sf / cnt, muw = sw / cnt;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) NTHREADS
+#endif
+    for (int s = 0; s < ns; ++s) {
+        double a = 0, b = 0, c = 0, ff = 0, ww = 0;
+        for (long v = s * ss; v < (s + 1) * ss; ++v) {
+            if (!mask[v]) continue;
+            double df = fixed[v] - muf, dw = warped[v] - muw;
+            a += df * dw;
+            b += df * df;
+            c += dw * dw;
+            ff += fixed[v] * fixed[v];
+            ww += warped[v] * warped[v];
+        }
+        part[6 * s + 0] = a;
+        part[6 * s + 1] = b;
+        part[6 * s + 2] = c;
+        part[6 * s + 3] = ff;
+        part[6 * s + 4] = ww;
+    }
+    double A = 0, B = 0, C = 0, FF = 0, WW = 0;
+    for (int s = 0; s < ns; ++s) {
+        A += part[6 * s + 0];
+        B += part[6 * s + 1];
+        C += part[6 * s + 2];
+        FF += part[6 * s + 3];
+        WW += part[6 * s + 4];
+    }
+    free(part);
+    /* Degenerate variance: a constant image on the masked set. */
+    if (!(B > 1e-10 * FF) || !(C > 1e-10 * WW)) {
+        *value = 0.0;
+        if (dsdw) memset(dsdw, 0, sizeof(double) * (size_t)N);
+        return flags | AIRO_FLAG_DEGENERATE;
+    }
+    const double sbc = sqrt(B * C);
+    const double rho = A / sbc;
+    *value = -rho;
+    if (dsdw) {
+        /* d(-rho)/dW(x) = -[(F - muF)/sqrt(BC) - rho (W - muW)/C] on X'. */
+        for (long v = 0; v < N; ++v)
+            dsdw[v] = mask[v]
+                ? -((fixed[v] - muf) / sbc - rho * (warped[v] - muw) / C) : 0.0;
+    }
+    if (!isfinite(*value)) flags |= AIRO_FLAG_NONFINITE;
+    return flags;
+}
+
+/* Sec. II-A eq. (diffusion_regularizer), forward differences over
+ * X_R = prod_a [0, n_a - 2], normalised by |X_R|; gradient with respect to
+ * u at every voxel (gather form of the derivative). */
+void airo_diffusion(const airo_problem* p, const double* u, double* value, double* grad_u) {
+    const int d = p->dim;
+    const int nx = p->n[0], ny = p->n[1], nz = (d == 3) ? p->n[2] : 1;
+    const int n[3] = {nx, ny, nz};
+    const long N = (long)nx * ny * nz;
+    const long stride[3] = {1, nx, (long)nx * ny};
+    double XR = 1.0;
+    for (int a = 0; a < d; ++a) XR *= (double)(n[a] - 1);
+    double* part = (double*)calloc((size_t)nz, sizeof(double));
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) NTHREADS
+#endif
+    for (int z = 0; z < nz; ++z) {
+        double acc = 0.0;
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const int idx[3] = {x, y, z};
+                int in_r = 1;
+                for (int a = 0; a < d; ++a)
+                    if (idx[a] > n[a] - 2) in_r = 0;
+                const long v = ((long)z * ny + y) * nx + x;
+                for (int c = 0; c < d; ++c) {
+                    const double* uc = u + c * N;
+                    double gsum = 0.0;
+                    for (int a = 0; a < d; ++a) {
+                        if (in_r) {
+                            double df = uc[v + stride[a]] - uc[v];
+                            acc += df * df;
+                            gsum -= df;           /* d/du(x) of (u(x+e)-u(x))^2 / 2 */
+                        }
+                        /* the difference that starts at x - e_a, if it is in X_R */
+                        int prev_in = idx[a] >= 1;
+                        for (int b = 0; b < d; ++b) {
+                            int ib = idx[b] - (b == a ? 1 : 0);
+                            if (ib > n[b] - 2) prev_in = 0;
+                        }
+                        if (prev_in) gsum += uc[v] - uc[v - stride[a]];
+                    }
+                    if (grad_u) grad_u[c * N + v] = 2.0 * gsum / XR;
+                }
+            }
+        part[z] = acc;
+    }
+    double total = 0.0;
+    for (int z = 0; z < nz; ++z) total += part[z];
+    free(part);
+    *value = total / XR;
+}
+
+void airo_regulariser(const airo_problem* p, const double* theta, double* value, double* grad) {
+    const long N = airo_nvox(p);
+    const size_t fb = sizeof(double) * (size_t)p->dim * (size_t)N;
+    if (p->transform == AIRO_TF_DENSE) {
+        airo_diffusion(p, theta, value, grad);
+        return;
+    }
+    double* u = (double*)malloc(fb);
+    double* gu = grad ? (double*)malloc(fb) : NULL;
+    airo_bspline_expand(p, theta, u);
+    airo_diffusion(p, u, value, gu);
+    if (grad) airo_bspline_adjoint(p, gu, grad);
+    free(u);
+    free(gu);
+}
+
+int airo_objective_and_grad(const airo_problem* p, const double* fixed,
+                            const double* moving, const double* theta,
+                            double* value, double* grad) {
+    const int d = p->dim;
+    const long N = airo_nvox(p);
+    const size_t fb = sizeof(double) * (size_t)d * (size_t)N;
+    double* u = (double*)malloc(fb);
+    double* dwdp = (double*)malloc(fb);
+    double* g = (double*)malloc(fb);
+    double* W = (double*)malloc(sizeof(double) * (size_t)N);
+    double* dsdw = (double*)malloc(sizeof(double) * (size_t)N);
+    unsigned char* mask = (unsigned char*)malloc((size_t)N);
+
+    airo_displacement(p, theta, u);                       /* stage 1 */
+    airo_sample(p, moving, u, W, mask, dwdp);             /* stage 2 */
+    double S = 0.0, R = 0.0;
+    int flags = airo_similarity(p, fixed, W, mask, &S, dsdw);   /* stage 3 */
+    airo_diffusion(p, u, &R, g);                          /* stage 4: g = dR/du */
+    *value = S + p->lambda_diff * R;                      /* eq. (objective) */
+    /* stage 5: g_a = dS/dW * dW/dp_a * (n_a - 1)/2 + lambda dR/du_a */
+    for (int a = 0; a < d; ++a) {
+        const double scale = (p->n[a] - 1) / 2.0;
+        for (long v = 0; v < N; ++v) {
+            double img = mask[v] ? dsdw[v] * dwdp[a * N + v] * scale : 0.0;
+            g[a * N + v] = img + p->lambda_diff * g[a * N + v];
+        }
+    }
+    if (p->transform == AIRO_TF_DENSE)
+        memcpy(grad, g, fb);
+    else
+        airo_bspline_adjoint(p, g, grad);
+    long np = airo_param_count(p);
+    if (!isfinite(*value)) flags |= AIRO_FLAG_NONFINITE;
+    for (long i = 0; i < np; ++i)
+        if (!isfinite(grad[i])) {
+            flags |= AIRO_FLAG_NONFINITE;
+            break;
+        }
+    free(u);
+    free(dwdp);
+    free(g);
+    free(W);
+    free(dsdw);
+    free(mask);
+    return flags;
+}
+
+/* Sec. III-G: Adam (Kingma & Ba) with bias correction. */
+void airo_adam_step(double* theta, const double* grad, double* m, double* v, long n,
+                    double lr, double b1, double b2, double eps, int step) {
+    const double bc1 = 1.0 - pow(b1, step);
+    const double bc2 = 1.0 - pow(b2, step);
+    for (long i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * grad[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * grad[i] * grad[i];
+        double mhat = m[i] / bc1;
+        double vhat = v[i] / bc2;
+        theta[i] -= lr * mhat / (sqrt(vhat) + eps);
+    }
+}

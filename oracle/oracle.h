@@ -1,0 +1,112 @@
+/*
+ * FP64 CPU oracle for the registration objective and its gradient.
+ *
+ * TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library. It shares no code,
+ * header, table or helper with the GPU library: every quantity is written
+ * out from the paper's definitions, in double precision, as plainly as
+ * possible (direct 4^d-term kernel sums, two-pass centred statistics, a
+ * voxel-level forward-difference regulariser).
+ *
+ * Paper: AIRLab, "Autograd Image Registration Laboratory" (arXiv 1806.09907).
+ *   objective            Sec. II-A, eq. (objective)
+ *   MSE                  Sec. II-A, eq. (mse); Sec. III-B
+ *   NCC                  Sec. III-B (the printed formula is garbled; read as
+ *                        the Pearson correlation, loss = -rho)
+ *   diffusion            Sec. II-A, eq. (diffusion_regularizer); Sec. III-F
+ *   interpolating basis  Sec. II-A, eq. (kernel_basis)
+ *   cubic B-spline       Sec. III-C, kernel k_B1D
+ *   warping + mask       Sec. III-C "Image Warping" (normalised [-1,1]^d
+ *                        coordinates, out-of-domain points masked out,
+ *                        linear interpolation via a grid sampler)
+ *   optimiser            Sec. III-G (Adam, Kingma & Ba)
+ *
+ * Conventions (shared readings of the paper, identical on both sides):
+ *   images     [nz][ny][nx], x fastest (2D: [ny][nx], n[2] == 1)
+ *   fields     [d][nz][ny][nx], components ordered (x, y, z)
+ *   controls   [d][ncz][ncy][ncx]; control j sits at voxel (j-1)*delta;
+ *              nc = floor((n-1)/delta) + 4
+ *   units      displacements and controls in normalised units; the sample
+ *              point of voxel i is p_a = i_a + u_a * (n_a - 1) / 2 (voxels)
+ *   mask       0 <= p_a <= n_a - 1 on every axis (inclusive)
+ *   sampling   linear on the cell [floor(p), floor(p)+1], zero outside
+ *   regulariser forward differences on u over X_R = prod_a [0, n_a - 2],
+ *              normalised by |X_R|
+ *
+ * Parity unpinned (fixed by the readings above, not by a value printed in
+ * the paper): the N' (masked) normalisation, the NCC loss sign/offset, the
+ * control-grid placement, the regulariser's discretisation and domain.
+ */
+#ifndef AIRO_ORACLE_H
+#define AIRO_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AIRO_SIM_MSE 0
+#define AIRO_SIM_NCC 1
+#define AIRO_TF_BSPLINE3 0
+#define AIRO_TF_DENSE 1
+
+#define AIRO_FLAG_NONFINITE 1
+#define AIRO_FLAG_DEGENERATE 2
+
+typedef struct {
+    int dim;          /* 2 or 3 */
+    int n[3];         /* voxels along x, y, z; n[2] == 1 in 2D */
+    int transform;    /* AIRO_TF_* */
+    int spacing[3];   /* control spacing (voxels) along x, y, z */
+    int similarity;   /* AIRO_SIM_* */
+    double lambda_diff;
+} airo_problem;
+
+int airo_check(const airo_problem* p);
+int airo_ncontrol(const airo_problem* p, int axis);
+long airo_nvox(const airo_problem* p);
+long airo_param_count(const airo_problem* p);
+
+/* k_B1D(r) of Sec. III-C, unit spacing. */
+double airo_bspline_kernel(double r);
+
+/* u = B theta  (Sec. II-A eq. kernel_basis with the cubic B-spline). */
+void airo_bspline_expand(const airo_problem* p, const double* theta, double* u);
+/* out = B^T g  (the adjoint of the expansion). */
+void airo_bspline_adjoint(const airo_problem* p, const double* g, double* out);
+/* u = B theta for B-spline problems, u = theta for dense ones. */
+void airo_displacement(const airo_problem* p, const double* theta, double* u);
+
+/* Sample `moving` at x + u(x); writes warped [N], mask [N] (nullable) and
+ * dwdp [d][N] (nullable): the derivative of the sample with respect to the
+ * sample point in voxel units, on the cell [floor(p), floor(p)+1]. */
+void airo_sample(const airo_problem* p, const double* moving, const double* u,
+                 double* warped, unsigned char* mask, double* dwdp);
+void airo_warp(const airo_problem* p, const double* moving, const double* theta,
+               double* warped, unsigned char* mask);
+
+/* Similarity over the masked set; dsdw [N] nullable. Returns flag bits. */
+int airo_similarity(const airo_problem* p, const double* fixed, const double* warped,
+                    const unsigned char* mask, double* value, double* dsdw);
+
+/* Diffusion regulariser of u (dense field), gradient with respect to u. */
+void airo_diffusion(const airo_problem* p, const double* u, double* value, double* grad_u);
+/* Regulariser as a function of the parameters (theta). grad nullable. */
+void airo_regulariser(const airo_problem* p, const double* theta, double* value, double* grad);
+
+/* L = S + lambda R and dL/dtheta. Returns flag bits. */
+int airo_objective_and_grad(const airo_problem* p, const double* fixed,
+                            const double* moving, const double* theta,
+                            double* value, double* grad);
+
+/* One bias-corrected Adam step, in place (step counts from 1). */
+void airo_adam_step(double* theta, const double* grad, double* m, double* v, long n,
+                    double lr, double b1, double b2, double eps, int step);
+
+/* Threads used by the parallel loops (OpenMP); 0 = runtime default. */
+void airo_set_threads(int nthreads);
+int airo_get_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

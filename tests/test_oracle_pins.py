@@ -1,0 +1,437 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's own formula: each check comes from a
+second definition (B_0^{*4} convolution, a transposed convolution, PyTorch's
+grid sampler, numpy's correlation coefficient), a closed form (linear
+reproduction, constant shifts), an invariant (partition of unity, affine
+invariance of NCC) or brute force on tiny inputs (all-control sums, central
+finite differences).
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1806_09907_amd import synth
+
+
+def prob(n, **kw):
+    d = len(n)
+    kw.setdefault("spacing", (4,) * d)
+    return O.Problem(n=tuple(n), **kw)
+
+
+# ---------------------------------------------------------------- B-spline basis
+
+def test_partition_of_unity(oracle):
+    """P1: the four cubic B-spline weights of any voxel sum to one (Sec. III-C)."""
+    for delta in (1, 3, 4, 8):
+        for i in range(delta):
+            t = i / delta
+            s = sum(O.bspline_kernel(t + 1 - k) for k in range(4))
+            assert abs(s - 1.0) < 1e-15
+    # constant controls reproduce the constant exactly
+    p = prob((21, 13, 9), spacing=(4, 3, 5), similarity=O.SIM_MSE)
+    theta = np.empty(p.param_shape())
+    for c in range(3):
+        theta[c] = 0.125 * (c + 1)
+    u = O.expand(p, theta)
+    for c in range(3):
+        assert np.max(np.abs(u[c] - 0.125 * (c + 1))) < 1e-15
+
+
+def test_box_convolution_defines_kernel(oracle):
+    """P2: B_3 = B_0 * B_0 * B_0 * B_0 with a width-delta box equals
+    delta^3 * k_B1D(r / delta) (Sec. III-C, arbitrary-order definition)."""
+    h = 1.0 / 512
+    delta = 1.0
+    r = np.arange(-2.5, 2.5 + h / 2, h)
+    box = (np.abs(r) < delta / 2).astype(np.float64)
+    b = box.copy()
+    for _ in range(3):
+        b = np.convolve(b, box, mode="same") * h
+    ref = np.array([O.bspline_kernel(x / delta) * delta ** 3 for x in r])
+    assert np.max(np.abs(b - ref)) < 4 * h
+
+
+def brute_expand(p, theta):
+    """u(x) = sum over ALL controls of theta_j prod_a k((x_a - X_a(j))/delta_a)."""
+    d = p.dim
+    nc = p.ncontrol()
+    u = np.zeros((d,) + p.shape)
+    for x in itertools.product(*[range(n) for n in p.n]):
+        for j in itertools.product(*[range(m) for m in nc]):
+            w = 1.0
+            for a in range(d):
+                w *= O.bspline_kernel((x[a] - (j[a] - 1) * p.spacing[a]) / p.spacing[a])
+            if w == 0.0:
+                continue
+            for c in range(d):
+                u[(c,) + tuple(reversed(x))] += w * theta[(c,) + tuple(reversed(j))]
+    return u
+
+
+def test_expand_matches_all_control_sum(oracle):
+    """Brute force: the oracle's 4^d-term sum equals the sum over every control."""
+    rng = np.random.default_rng(1)
+    for n, sp in (((9, 7), (3, 2)), ((6, 5, 7), (2, 3, 4))):
+        p = prob(n, spacing=sp, similarity=O.SIM_MSE)
+        theta = rng.normal(size=p.param_shape())
+        assert np.allclose(O.expand(p, theta), brute_expand(p, theta), rtol=0, atol=1e-14)
+
+
+def test_expand_is_transposed_convolution(oracle):
+    """P3: the expansion equals PyTorch's transposed convolution with the
+    delta-sampled kernel and stride delta (Sec. III-C), cropped by 3 delta;
+    its adjoint equals the strided convolution."""
+    rng = np.random.default_rng(2)
+    for n, delta in (((40, 33), 8), ((17, 20, 23), 4)):
+        d = len(n)
+        p = prob(n, spacing=(delta,) * d, similarity=O.SIM_MSE)
+        theta = rng.normal(size=p.param_shape())
+        k1 = torch.tensor([O.bspline_kernel((m - 2 * delta) / delta)
+                           for m in range(4 * delta + 1)], dtype=torch.float64)
+        if d == 2:
+            K = (k1[:, None] * k1[None, :])[None, None]
+            out = torch.nn.functional.conv_transpose2d(
+                torch.from_numpy(theta)[:, None], K, stride=delta)[:, 0]
+            ref = out[:, 3 * delta:3 * delta + n[1], 3 * delta:3 * delta + n[0]]
+        else:
+            K = (k1[:, None, None] * k1[None, :, None] * k1[None, None, :])[None, None]
+            out = torch.nn.functional.conv_transpose3d(
+                torch.from_numpy(theta)[:, None], K, stride=delta)[:, 0]
+            ref = out[:, 3 * delta:3 * delta + n[2], 3 * delta:3 * delta + n[1],
+                      3 * delta:3 * delta + n[0]]
+        u = O.expand(p, theta)
+        assert np.allclose(u, ref.numpy(), rtol=0, atol=1e-13)
+        # adjoint: zero-pad g by 3 delta in front, correlate with stride delta
+        g = rng.normal(size=(d,) + p.shape)
+        nc = p.ncontrol()
+        full = [(nc[a] - 1) * delta + 4 * delta + 1 for a in range(d)]
+        gp = torch.zeros((d, 1) + tuple(reversed(full)), dtype=torch.float64)
+        if d == 2:
+            gp[:, 0, 3 * delta:3 * delta + n[1], 3 * delta:3 * delta + n[0]] = torch.from_numpy(g)
+            ref_t = torch.nn.functional.conv2d(gp, K, stride=delta)[:, 0]
+        else:
+            gp[:, 0, 3 * delta:3 * delta + n[2], 3 * delta:3 * delta + n[1],
+               3 * delta:3 * delta + n[0]] = torch.from_numpy(g)
+            ref_t = torch.nn.functional.conv3d(gp, K, stride=delta)[:, 0]
+        assert np.allclose(O.adjoint(p, g), ref_t.numpy(), rtol=0, atol=1e-12)
+
+
+def test_adjoint_identity(oracle):
+    """P11: <B theta, v> = <theta, B^T v>."""
+    rng = np.random.default_rng(3)
+    for n, sp in (((33, 29), (8, 5)), ((19, 14, 23), (4, 4, 8))):
+        p = prob(n, spacing=sp, similarity=O.SIM_MSE)
+        theta = rng.normal(size=p.param_shape())
+        v = rng.normal(size=(p.dim,) + p.shape)
+        lhs = np.sum(O.expand(p, theta) * v)
+        rhs = np.sum(theta * O.adjoint(p, v))
+        assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_linear_reproduction_and_diffusion_closed_form(oracle):
+    """P8: controls on an affine function reproduce it exactly, and the
+    diffusion term of u = A x + b is sum_c sum_a A_ca^2."""
+    rng = np.random.default_rng(4)
+    for n, sp in (((37, 30), (8, 4)), ((20, 18, 23), (4, 5, 8))):
+        d = len(n)
+        p = prob(n, spacing=sp, similarity=O.SIM_MSE)
+        A = rng.normal(size=(d, d)) * 0.01
+        b = rng.normal(size=d)
+        nc = p.ncontrol()
+        theta = np.zeros(p.param_shape())
+        for j in itertools.product(*[range(m) for m in nc]):
+            pos = [(j[a] - 1) * sp[a] for a in range(d)]
+            for c in range(d):
+                theta[(c,) + tuple(reversed(j))] = A[c] @ pos + b[c]
+        u = O.expand(p, theta)
+        grids = np.meshgrid(*[np.arange(m) for m in reversed(n)], indexing="ij")
+        xs = list(reversed(grids))  # x, y, (z) coordinate arrays
+        for c in range(d):
+            lin = b[c] + sum(A[c, a] * xs[a] for a in range(d))
+            assert np.max(np.abs(u[c] - lin)) < 1e-13
+        R, _ = O.regulariser(p, theta)
+        assert abs(R - np.sum(A * A)) < 1e-13 * max(1.0, np.sum(A * A))
+        Rd, _ = O.diffusion(p, u)
+        assert abs(Rd - np.sum(A * A)) < 1e-13
+
+
+def test_diffusion_brute_force(oracle):
+    """Diffusion value by direct numpy differences, gradient by central FD."""
+    rng = np.random.default_rng(5)
+    for n in ((7, 6), (5, 6, 4)):
+        d = len(n)
+        p = prob(n, transform=O.TF_DENSE, similarity=O.SIM_MSE)
+        u = rng.normal(size=(d,) + p.shape)
+        R, g = O.diffusion(p, u)
+        core = tuple(slice(0, m - 1) for m in reversed(n))
+        tot = 0.0
+        for c in range(d):
+            for a in range(d):
+                ax = d - 1 - a
+                df = np.diff(u[c], axis=ax)
+                sl = list(core)
+                sl[ax] = slice(0, n[a] - 1)
+                tot += np.sum(df[tuple(sl)] ** 2)
+        XR = np.prod([m - 1 for m in n])
+        assert abs(R - tot / XR) < 1e-14 * tot
+        h = 1e-6
+        fd = np.zeros_like(u)
+        for idx in np.ndindex(u.shape):
+            up = u.copy(); up[idx] += h
+            um = u.copy(); um[idx] -= h
+            fd[idx] = (O.diffusion(p, up)[0] - O.diffusion(p, um)[0]) / (2 * h)
+        assert np.linalg.norm(fd - g) <= 1e-8 * np.linalg.norm(g)
+
+
+# ---------------------------------------------------------------- sampling
+
+def grid_sample_ref(p, moving, u):
+    """PyTorch grid_sample (bilinear, zeros, align_corners=True) in FP64:
+    warped image and d warped / d grid (normalised units)."""
+    d = p.dim
+    n = p.n
+    m = torch.from_numpy(np.asarray(moving, dtype=np.float64))[None, None]
+    axes = [torch.linspace(-1.0, 1.0, n[a], dtype=torch.float64) for a in range(d)]
+    mesh = torch.meshgrid(*reversed(axes), indexing="ij")  # slowest first
+    ident = torch.stack(list(reversed(mesh)), dim=-1)       # (..., x, y, z)
+    disp = torch.from_numpy(np.moveaxis(np.asarray(u, dtype=np.float64), 0, -1))
+    grid = (ident + disp)[None].clone().requires_grad_(True)
+    w = torch.nn.functional.grid_sample(m, grid, mode="bilinear",
+                                        padding_mode="zeros", align_corners=True)
+    w.sum().backward()
+    return w[0, 0].detach().numpy(), grid.grad[0].numpy()
+
+
+def test_sample_matches_grid_sampler(oracle):
+    """P4: values everywhere, and the derivative at non-integer sample
+    points, equal PyTorch's grid sampler (Sec. III-C Image Warping)."""
+    rng = np.random.default_rng(6)
+    for n in ((23, 17), (11, 9, 13)):
+        d = len(n)
+        p = prob(n, transform=O.TF_DENSE, similarity=O.SIM_MSE)
+        moving = rng.normal(size=p.shape)
+        u = rng.normal(size=(d,) + p.shape) * 0.3
+        w, mask, dw = O.sample(p, moving, u)
+        wr, gr = grid_sample_ref(p, moving, u)
+        assert np.max(np.abs(w - wr)) < 1e-13
+        # derivative: oracle is per voxel unit; grid sampler per normalised unit
+        pts = []
+        ok = np.ones(p.shape, dtype=bool)
+        grids = np.meshgrid(*[np.arange(m) for m in reversed(n)], indexing="ij")
+        for a in range(d):
+            pa = grids[d - 1 - a] + u[a] * (n[a] - 1) / 2
+            ok &= np.abs(pa - np.round(pa)) > 1e-6
+            pts.append(pa)
+        for a in range(d):
+            ours = dw[a] * (n[a] - 1) / 2
+            assert np.max(np.abs(ours[ok] - gr[..., a][ok])) < 1e-12
+        # mask: the normalised sample point lies in [-1, 1] on every axis
+        inside = np.ones(p.shape, dtype=bool)
+        for a in range(d):
+            inside &= (pts[a] >= 0) & (pts[a] <= n[a] - 1)
+        assert np.array_equal(mask.astype(bool), inside)
+
+
+def test_zero_displacement_is_identity(oracle):
+    """P5: u = 0 reproduces the moving image bitwise, with a full mask."""
+    rng = np.random.default_rng(7)
+    for n in ((31, 20), (9, 12, 7)):
+        p = prob(n, similarity=O.SIM_MSE)
+        moving = rng.normal(size=p.shape).astype(np.float32)
+        w, mask = O.warp(p, moving, np.zeros(p.param_shape()))
+        assert np.array_equal(w, moving.astype(np.float64))
+        assert mask.all()
+
+
+def test_integer_shift_is_array_shift(oracle):
+    """P6: a constant displacement of t voxels along an axis samples
+    M(x + t e_a); the vacated slab is masked out. Bitwise for n - 1 a power
+    of two."""
+    rng = np.random.default_rng(8)
+    for n in ((17, 33), (17, 9, 33)):
+        d = len(n)
+        p = prob(n, transform=O.TF_DENSE, similarity=O.SIM_MSE)
+        moving = rng.normal(size=p.shape)
+        for a in range(d):
+            for t in (-3, 2):
+                u = np.zeros((d,) + p.shape)
+                u[a] = 2.0 * t / (n[a] - 1)
+                w, mask, _ = O.sample(p, moving, u)
+                ax = d - 1 - a
+                idx = np.arange(n[a])
+                valid = (idx + t >= 0) & (idx + t <= n[a] - 1)
+                sel = [slice(None)] * d
+                sel[ax] = valid
+                src = [slice(None)] * d
+                src[ax] = idx[valid] + t
+                assert np.array_equal(w[tuple(sel)], moving[tuple(src)])
+                exp_mask = np.broadcast_to(
+                    valid.reshape([-1 if k == ax else 1 for k in range(d)]), p.shape)
+                assert np.array_equal(mask.astype(bool), exp_mask)
+
+
+def test_ramp_derivative(oracle):
+    """P9: on M = g * x_a, W = g * p_a and dW/dp_a = g in the interior."""
+    for n in ((15, 12), (9, 10, 11)):
+        d = len(n)
+        p = prob(n, transform=O.TF_DENSE, similarity=O.SIM_MSE)
+        grids = np.meshgrid(*[np.arange(m) for m in reversed(n)], indexing="ij")
+        rng = np.random.default_rng(9)
+        u = rng.uniform(-0.1, 0.1, size=(d,) + p.shape)
+        for a in range(d):
+            g = 0.75
+            moving = g * grids[d - 1 - a].astype(np.float64)
+            w, mask, dw = O.sample(p, moving, u)
+            pa = grids[d - 1 - a] + u[a] * (n[a] - 1) / 2
+            interior = (pa < n[a] - 1) & mask.astype(bool)
+            for b in range(d):
+                pb = grids[d - 1 - b] + u[b] * (n[b] - 1) / 2
+                interior &= pb < n[b] - 1
+            assert np.max(np.abs(w[interior] - g * pa[interior])) < 1e-13
+            assert np.max(np.abs(dw[a][interior] - g)) < 1e-13
+
+
+# ---------------------------------------------------------------- similarity
+
+def test_identical_images(oracle):
+    """P7: F = M with zero displacement gives MSE 0 and NCC loss -1."""
+    rng = np.random.default_rng(10)
+    for n in ((16, 16), (8, 9, 10)):
+        img = rng.normal(size=tuple(reversed(n)))
+        for sim, expect in ((O.SIM_MSE, 0.0), (O.SIM_NCC, -1.0)):
+            p = prob(n, similarity=sim)
+            v, g, flags = O.objective_and_grad(p, img, img, np.zeros(p.param_shape()))
+            assert flags == 0
+            assert abs(v - expect) < 1e-15
+
+
+def test_ncc_matches_corrcoef_and_affine_invariance(oracle):
+    """P7: NCC loss = -corrcoef on the masked voxels; invariant to aW + b."""
+    rng = np.random.default_rng(11)
+    n = (20, 15, 12)
+    p = prob(n, similarity=O.SIM_NCC)
+    F = rng.normal(size=p.shape)
+    W = 0.3 * F + rng.normal(size=p.shape)
+    mask = (rng.uniform(size=p.shape) < 0.8).astype(np.uint8)
+    v, _ = O.similarity(p, F, W, mask)
+    r = np.corrcoef(F[mask == 1], W[mask == 1])[0, 1]
+    assert abs(v + r) < 1e-14
+    v2, _ = O.similarity(p, F, 2.5 * W - 7.0, mask)
+    assert abs(v2 - v) < 1e-13
+    pm = prob(n, similarity=O.SIM_MSE)
+    vm, _ = O.similarity(pm, F, W, mask)
+    ref = np.mean((W - F)[mask == 1] ** 2)
+    assert abs(vm - ref) < 1e-14 * ref
+
+
+def test_similarity_gradient_fd(oracle):
+    """P12: dS/dW against central differences of S on random vectors."""
+    rng = np.random.default_rng(12)
+    n = (6, 5, 4)
+    for sim in (O.SIM_MSE, O.SIM_NCC):
+        p = prob(n, similarity=sim)
+        F = rng.normal(size=p.shape)
+        W = rng.normal(size=p.shape)
+        mask = (rng.uniform(size=p.shape) < 0.7).astype(np.uint8)
+        _, ds, _ = O.similarity(p, F, W, mask, want_grad=True)
+        h = 1e-6
+        fd = np.zeros_like(W)
+        for idx in np.ndindex(W.shape):
+            wp = W.copy(); wp[idx] += h
+            wm = W.copy(); wm[idx] -= h
+            fd[idx] = (O.similarity(p, F, wp, mask)[0] - O.similarity(p, F, wm, mask)[0]) / (2 * h)
+        assert np.linalg.norm(fd - ds) <= 1e-8 * np.linalg.norm(ds)
+
+
+def test_degenerate_cases(oracle):
+    """Empty mask and constant images: zero loss and gradient, flagged."""
+    n = (8, 8)
+    p = prob(n, transform=O.TF_DENSE, similarity=O.SIM_NCC)
+    F = np.ones(p.shape)
+    M = np.ones(p.shape)
+    v, g, flags = O.objective_and_grad(p, F, M, np.zeros(p.param_shape()))
+    assert v == 0.0 and np.all(g == 0.0) and flags & O.FLAG_DEGENERATE
+    # everything displaced out of the domain
+    u = np.full(p.param_shape(), 5.0)
+    for sim in (O.SIM_MSE, O.SIM_NCC):
+        q = prob(n, transform=O.TF_DENSE, similarity=sim)
+        v, g, flags = O.objective_and_grad(q, F, M, u)
+        assert v == 0.0 and np.all(g == 0.0) and flags & O.FLAG_DEGENERATE
+    # non-finite parameters are flagged
+    th = np.zeros(p.param_shape()); th[0, 3, 3] = np.nan
+    _, _, flags = O.objective_and_grad(prob(n, transform=O.TF_DENSE, similarity=O.SIM_MSE),
+                                       np.arange(64.0).reshape(8, 8), M, th)
+    assert flags & O.FLAG_NONFINITE
+
+
+# ---------------------------------------------------------------- objective gradient
+
+def _clean_theta(p, std_vox, seed, moving, h):
+    """A random theta whose sample points stay clear of cell boundaries and
+    of the mask boundary under +-h perturbations (kinks, R3)."""
+    for s in range(seed, seed + 200):
+        if p.transform == O.TF_DENSE:
+            th = synth.random_dense(p.n, std_vox, s).astype(np.float64)
+        else:
+            th = synth.random_theta(p.n, p.spacing, std_vox, s).astype(np.float64)
+        u = O.displacement(p, th)
+        grids = np.meshgrid(*[np.arange(m) for m in reversed(p.n)], indexing="ij")
+        ok = True
+        for a in range(p.dim):
+            pa = grids[p.dim - 1 - a] + u[a] * (p.n[a] - 1) / 2
+            if np.min(np.abs(pa - np.round(pa))) < 1e-4:
+                ok = False
+        if ok:
+            return th
+    raise RuntimeError("no clean theta found")
+
+
+@pytest.mark.parametrize("n,transform", [((16, 16), O.TF_BSPLINE3), ((8, 8, 8), O.TF_BSPLINE3),
+                                         ((10, 9), O.TF_DENSE), ((5, 6, 4), O.TF_DENSE)])
+@pytest.mark.parametrize("sim", [O.SIM_MSE, O.SIM_NCC])
+def test_objective_gradient_fd(oracle, n, transform, sim):
+    """P10: the whole objective's gradient against central differences
+    (random non-zero theta; never at zero, where every sample is on a kink)."""
+    d = len(n)
+    p = prob(n, transform=transform, similarity=sim, lambda_diff=0.3)
+    rng = np.random.default_rng(13)
+    shape = tuple(reversed(n))
+    F = synth.blobs(shape, 4, rng, sigma=(1.5, 3.0))
+    M = synth.blobs(shape, 4, rng, sigma=(1.5, 3.0))
+    h = 1e-6
+    th = _clean_theta(p, 0.5, 100, M, h)
+    v, g, flags = O.objective_and_grad(p, F, M, th)
+    assert flags == 0
+    fd = np.zeros_like(th)
+    base_mask = O.warp(p, M, th)[1]
+    for idx in np.ndindex(th.shape):
+        tp = th.copy(); tp[idx] += h
+        tm = th.copy(); tm[idx] -= h
+        assert np.array_equal(O.warp(p, M, tp)[1], base_mask)
+        assert np.array_equal(O.warp(p, M, tm)[1], base_mask)
+        fd[idx] = (O.objective_and_grad(p, F, M, tp)[0]
+                   - O.objective_and_grad(p, F, M, tm)[0]) / (2 * h)
+    assert np.linalg.norm(fd - g) <= 1e-6 * np.linalg.norm(g)
+
+
+def test_adam_matches_torch(oracle):
+    """Adam (Sec. III-G, Kingma & Ba) against torch.optim.Adam defaults."""
+    rng = np.random.default_rng(14)
+    theta = rng.normal(size=50)
+    t = torch.tensor(theta.copy(), requires_grad=True)
+    opt = torch.optim.Adam([t], lr=0.01)
+    m = np.zeros(50); v = np.zeros(50)
+    th = theta.copy()
+    for step in range(1, 6):
+        g = rng.normal(size=50)
+        opt.zero_grad()
+        t.grad = torch.tensor(g)
+        opt.step()
+        O.adam_step(th, g, m, v, lr=0.01, step=step)
+    assert np.max(np.abs(th - t.detach().numpy())) < 1e-14
