@@ -1,0 +1,165 @@
+/*
+ * airhip -- C-ABI of the MI355X (gfx950) library that evaluates the
+ * regularised image-registration objective of AIRLab (arXiv 1806.09907)
+ * and its gradient.
+ *
+ * The objective (Sec. II-A, eq. objective) is
+ *     L(theta) = S(M o f_theta, F) + lambda * R(f_theta)
+ * with
+ *   f_theta   a cubic B-spline field on a control grid (Sec. II-A eq.
+ *             kernel_basis, Sec. III-C kernel k_B1D) or a dense field
+ *             (Sec. III-C "Non-linear/dense");
+ *   M o f     backward warping in normalised [-1,1]^d coordinates with
+ *             linear interpolation and out-of-domain points masked out
+ *             (Sec. III-C "Image Warping");
+ *   S         MSE (Sec. II-A eq. mse) or NCC (Sec. III-B; loss -rho, the
+ *             Pearson correlation over the masked voxels);
+ *   R         the diffusion regulariser (Sec. II-A eq. diffusion_regularizer).
+ *
+ * Conventions (every entry point):
+ *   - images are FP32 [nz][ny][nx], x fastest (2D: [ny][nx], n[2] == 1);
+ *   - dense fields / parameters are FP32 [d][nz][ny][nx], components ordered
+ *     (x, y, z); B-spline parameters are FP32 [d][ncz][ncy][ncx] with
+ *     nc = floor((n - 1) / spacing) + 4, control j at voxel (j - 1) * spacing;
+ *   - displacements and controls are in normalised units: the sample point of
+ *     voxel i along axis a is p_a = i_a + u_a * (n_a - 1) / 2 voxels;
+ *   - a voxel is in the mask iff 0 <= p_a <= n_a - 1 on every axis; the
+ *     similarity is averaged over the masked voxels (N'); the mask is held
+ *     constant when differentiating; interpolation uses the cell
+ *     [floor(p), floor(p) + 1] with zero padding outside the volume;
+ *   - R uses forward differences of u (normalised units) over
+ *     X_R = prod_a [0, n_a - 2], divided by |X_R|;
+ *   - all tensor pointers are caller-owned DEVICE buffers, 16-byte aligned,
+ *     contiguous; outputs are overwritten; scalar outputs are device scalars;
+ *   - calls are asynchronous on `stream` (a hipStream_t; NULL = default
+ *     stream), do not synchronise the host and do not allocate, except the
+ *     first launching call with a plan on a device, which uploads the plan's
+ *     small constant tables (allocation + blocking copy) unless
+ *     air_plan_prepare() ran first on that device;
+ *   - argument errors return before any launch; a launch failure returns
+ *     AIR_ERR_LAUNCH; degenerate or non-finite results set bits in a device
+ *     flag word read by air_get_flags().
+ */
+#ifndef AIRHIP_H
+#define AIRHIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AIR_OK = 0,
+    AIR_ERR_INVALID_ARG = 1,  /* null/unknown argument or enum value */
+    AIR_ERR_SHAPE = 2,        /* sizes, spacing or pair index out of range */
+    AIR_ERR_ALIGN = 3,        /* a tensor pointer is not 16-byte aligned */
+    AIR_ERR_WORKSPACE = 4,    /* workspace missing or smaller than required */
+    AIR_ERR_UNSUPPORTED = 5,  /* valid but not implemented combination */
+    AIR_ERR_LAUNCH = 6,       /* the HIP runtime rejected a launch */
+    AIR_ERR_NONFINITE = 7,    /* returned by air_get_flags-based checks */
+    AIR_ERR_DEVICE = 8        /* device query, allocation or copy failed */
+} air_status;
+
+enum { AIR_SIM_MSE = 0, AIR_SIM_NCC = 1 };
+enum { AIR_TF_BSPLINE3 = 0, AIR_TF_DENSE = 1 };
+/* device flag bits (per pair) */
+enum { AIR_FLAG_NONFINITE = 1u, AIR_FLAG_DEGENERATE = 2u };
+
+typedef struct {
+    int32_t dim;          /* 2 or 3 */
+    int32_t n[3];         /* voxels along x, y, z (n[2] == 1 in 2D), each >= 2 */
+    int32_t transform;    /* AIR_TF_* */
+    int32_t spacing[3];   /* B-spline control spacing in voxels, 1..64 */
+    int32_t similarity;   /* AIR_SIM_* */
+    float lambda_diff;    /* weight of the diffusion regulariser, >= 0 */
+} air_problem;
+
+/* Opaque plan: host tables for one pair or a batch of pairs that share
+ * dim, transform and similarity (sizes, spacing and lambda may differ). */
+typedef struct air_plan air_plan;
+
+/* Create a plan for `npairs` problems (1 .. 4096). Host-only; no GPU needed. */
+air_status air_plan_create(const air_problem* probs, int32_t npairs, air_plan** out);
+void air_plan_destroy(air_plan* plan);
+/* Upload the plan's constant tables to the current device (allocates once). */
+air_status air_plan_prepare(air_plan* plan);
+/* Bytes of caller-owned device workspace the launching calls need. */
+air_status air_plan_workspace_bytes(const air_plan* plan, size_t* bytes);
+/* Number of FP32 parameters of pair `pair` (d * prod(nc) or d * N). */
+air_status air_plan_param_count(const air_plan* plan, int32_t pair, int64_t* count);
+/* Tile configurations of the fused kernel (the autotuner's search space). */
+int32_t air_tiling_count(int32_t dim);
+air_status air_tiling_describe(int32_t dim, int32_t id, int32_t* tile_x, int32_t* tile_y,
+                               int32_t* column_cells);
+/* Select a tile configuration; changes the workspace size and re-uploads. */
+air_status air_plan_set_tiling(air_plan* plan, int32_t id);
+air_status air_plan_get_tiling(const air_plan* plan, int32_t* id);
+
+/* Stage 1 + 2 (Sec. III-C Image Warping): warped = M(x + u(x)) with zero
+ * padding everywhere (also outside the mask); mask (nullable) = 1 where the
+ * sample point lies inside the volume. For pair `pair` of the plan. */
+air_status air_warp(const air_plan* plan, int32_t pair, const float* moving,
+                    const float* theta, float* warped, uint8_t* mask, void* stream);
+
+/* Stage 3 (Sec. II-A eq. mse / Sec. III-B NCC): similarity of `warped`
+ * against `fixed` over the voxels where mask != 0 (mask nullable = all). */
+air_status air_similarity(const air_plan* plan, int32_t pair, const float* fixed,
+                          const float* warped, const uint8_t* mask, float* value,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* Stage 4 (Sec. II-A eq. diffusion_regularizer): R(theta) and, if grad is
+ * not NULL, dR/dtheta (not scaled by lambda). */
+air_status air_regulariser(const air_plan* plan, int32_t pair, const float* theta,
+                           float* value, float* grad, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/* Stages 1-5 (Sec. II-A eq. objective): value = S + lambda R and
+ * grad = dL/dtheta, for a plan with exactly one pair. */
+air_status air_objective_and_grad(const air_plan* plan, const float* fixed,
+                                  const float* moving, const float* theta,
+                                  float* value, float* grad, void* ws, size_t ws_bytes,
+                                  void* stream);
+
+/* The same for every pair of the plan in one launch sequence. fixed, moving,
+ * theta and grads are DEVICE arrays of npairs device pointers; values is a
+ * device array of npairs floats. */
+air_status air_objective_and_grad_batched(const air_plan* plan,
+                                          const float* const* fixed,
+                                          const float* const* moving,
+                                          const float* const* theta, float* values,
+                                          float* const* grads, void* ws, size_t ws_bytes,
+                                          void* stream);
+
+/* Adam (Sec. III-G; Kingma & Ba) with bias correction, in place:
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * theta -= lr * (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps). step >= 1. */
+air_status air_adam_step(float* theta, const float* grad, float* m, float* v, int64_t n,
+                         float lr, float b1, float b2, float eps, int32_t step,
+                         void* stream);
+
+/* x[i] *= *s for i < n, with s a device scalar (autograd chain rule). */
+air_status air_scale(float* x, const float* s, int64_t n, void* stream);
+
+/* Copy the per-pair flag words (AIR_FLAG_*) of the last launching call to
+ * host memory `flags` [npairs]; synchronises `stream`. */
+air_status air_get_flags(const air_plan* plan, const void* ws, uint32_t* flags,
+                         void* stream);
+
+/* Kernel timing for benchmarks: reserve `launches` pairs of HIP events; each
+ * following objective call records one pair on its stream around its main
+ * kernel (the fused B-spline kernel, or the dense main pass) until the
+ * reserve is used up. 0 switches timing off. Creates events (not for the
+ * hot path). */
+air_status air_plan_timing(air_plan* plan, int32_t launches);
+/* Sum of the recorded main-kernel durations (ms) and their count; waits for
+ * the recorded events and rewinds the reserve. */
+air_status air_plan_timing_read(air_plan* plan, double* total_ms, int32_t* launches);
+
+const char* air_strerror(air_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -71,6 +71,8 @@ def lib():
             "airo_adam_step": (None, [dp, dp, dp, dp, ctypes.c_long, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_int]),
+            "airo_set_point_precision": (None, [ctypes.c_int]),
+            "airo_get_point_precision": (ctypes.c_int, []),
             "airo_set_threads": (None, [ctypes.c_int]),
             "airo_get_threads": (ctypes.c_int, []),
         }
@@ -134,6 +136,30 @@ def _check(prob: Problem):
     if lib().airo_check(ctypes.byref(pc)) != 0:
         raise ValueError(f"invalid problem {prob}")
     return pc
+
+
+def set_point_precision(bits: int) -> None:
+    """32 (default): cell and mask decided on the FP32-rounded sample point;
+    64: on the FP64 point (for pins against FP64 library references)."""
+    lib().airo_set_point_precision(int(bits))
+
+
+def get_point_precision() -> int:
+    return int(lib().airo_get_point_precision())
+
+
+class point_precision:
+    """Context manager that sets the sample-point precision temporarily."""
+
+    def __init__(self, bits: int):
+        self.bits = bits
+
+    def __enter__(self):
+        self.old = get_point_precision()
+        set_point_precision(self.bits)
+
+    def __exit__(self, *exc):
+        set_point_precision(self.old)
 
 
 def set_threads(n: int) -> None:

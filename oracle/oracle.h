@@ -28,7 +28,8 @@
  *              nc = floor((n-1)/delta) + 4
  *   units      displacements and controls in normalised units; the sample
  *              point of voxel i is p_a = i_a + u_a * (n_a - 1) / 2 (voxels)
- *   mask       0 <= p_a <= n_a - 1 on every axis (inclusive)
+ *   mask       0 <= p_a <= n_a - 1 on every axis (inclusive), decided on p
+ *              rounded to FP32 (the sampler's tensor precision), see below
  *   sampling   linear on the cell [floor(p), floor(p)+1], zero outside
  *   regulariser forward differences on u over X_R = prod_a [0, n_a - 2],
  *              normalised by |X_R|
@@ -101,6 +102,12 @@ int airo_objective_and_grad(const airo_problem* p, const double* fixed,
 /* One bias-corrected Adam step, in place (step counts from 1). */
 void airo_adam_step(double* theta, const double* grad, double* m, double* v, long n,
                     double lr, double b1, double b2, double eps, int step);
+
+/* Precision (32 or 64 bits) of the sample point on which the interpolation
+ * cell and the mask are decided; default 32 (a grid sampler over FP32
+ * tensors, Sec. III-C). Arithmetic after the decision is FP64 either way. */
+void airo_set_point_precision(int bits);
+int airo_get_point_precision(void);
 
 /* Threads used by the parallel loops (OpenMP); 0 = runtime default. */
 void airo_set_threads(int nthreads);

@@ -1,0 +1,98 @@
+// Internal device/host structures of the airhip library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/airhip.h"
+
+namespace air {
+
+constexpr int kMaxPairs = 4096;
+constexpr int kMaxSpacing = 64;
+constexpr int kBlock = 256;          // threads per block of every kernel
+constexpr int kStatWords = 8;        // doubles per tile statistics slot
+
+// Per-pair constants, uploaded once per plan and device.
+struct PairDesc {
+    int n[3];            // voxels (1 on absent axes)
+    int nc[3];           // controls (1 on absent axes); for dense: n
+    int sp[3];           // spacing (1 on absent axes)
+    float s[3];          // (n - 1) / 2 : normalised -> voxel units
+    int ntile[3];        // fused-kernel tiles along x, y and the column axis
+    int col_cells;       // cells per column chunk
+    int win[3];          // max control window of a tile (x, y, column)
+    int tile_begin;      // global index of the pair's first tile
+    int ntiles;          // tiles of this pair
+    int reg_begin;       // global index of the pair's first regulariser block
+    int nreg;            // regulariser blocks of this pair
+    int part_stride;     // floats per tile partial
+    long long part_off;  // float offset of the pair's partials
+    long long nvox;
+    long long nparam;    // parameters of the pair
+    long long param_off; // float offset of the pair in the reg-grad buffer
+    int gram_off[3];     // float offset of axis a's banded Gram tables (P then D)
+    int wtab_off[3];     // float offset of axis a's spacing weight table [sp][4]
+    float inv_xr;        // 1 / |X_R|
+    float lambda;        // regulariser weight
+    int regpart_off;     // double offset of the pair's regulariser partials
+    int dense_blk_off;   // first dense stats block slot of the pair
+    int dense_nblk;      // dense stats blocks of the pair
+    int pad_;
+};
+
+// Workspace layout (byte offsets into the caller's workspace).
+struct WsLayout {
+    size_t stats;        // double [ntiles_total][kStatWords]
+    size_t part;         // float  [sum part]
+    size_t reggrad;      // float  [sum nparam] (B-spline: lambda dR/dtheta)
+    size_t regpart;      // double [sum regblocks]
+    size_t flags;        // uint32 [npairs]
+    size_t scalars;      // double [npairs][8] (dense: global count / coefficients)
+    size_t dense_stats;  // double [sum dense blocks][kStatWords]
+    size_t generic;      // double [generic blocks][kStatWords] (similarity / reg calls)
+    size_t total;
+};
+
+struct DeviceTables {
+    PairDesc* pairs = nullptr;
+    float* consts = nullptr;   // Gram tables + weight tables
+    int device = -1;
+};
+
+struct LaunchCtx {
+    const PairDesc* pairs;     // device
+    const float* consts;       // device
+    int npairs;
+    int ntiles_total;
+    int nreg_total;
+    int dim;
+    int sim;
+    // single-pair pointers (used when the pointer tables are null)
+    const float* fixed0;
+    const float* moving0;
+    const float* theta0;
+    float* grad0;
+    float* value0;
+    const float* const* fixed_tab;
+    const float* const* moving_tab;
+    const float* const* theta_tab;
+    float* const* grad_tab;
+    float* values;
+    unsigned char* ws;
+    WsLayout L;
+};
+
+__host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+// round a float count up to a multiple of 4 (16-byte aligned LDS carve-up)
+__host__ __device__ inline int a4(int n) { return (n + 3) & ~3; }
+
+// Tile window: controls [c0, c0 + w) touched by voxels [v0, v1) (v1 exclusive).
+__host__ __device__ inline void ctrl_window(int v0, int v1, int sp, int* c0, int* w) {
+    int a = v0 / sp;
+    int b = (v1 - 1) / sp + 3;
+    *c0 = a;
+    *w = b - a + 1;
+}
+
+}  // namespace air

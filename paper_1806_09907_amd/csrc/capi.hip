@@ -1,0 +1,631 @@
+// Host side of the airhip C-ABI: plans, validation, workspace layout, the
+// per-device constant tables and the launch sequences.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "air_internal.h"
+
+namespace air {
+hipError_t launch_bspline(const LaunchCtx& C, int cfg, size_t lds, int max_ctrl, hipStream_t s,
+                          hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_reg_bspline(const PairDesc* dpairs, const PairDesc& hp, int pair,
+                              const float* consts, const float* theta, float* grad_out,
+                              double* regpart, float* value, int dim, size_t lds, hipStream_t s);
+hipError_t launch_dense(const LaunchCtx& C, int zc, int max_blk, hipStream_t s, hipEvent_t ev0,
+                        hipEvent_t ev1);
+hipError_t launch_reg_dense(const LaunchCtx& C, int pair_blocks, int zc, float* grad_out,
+                            float* value_out, hipStream_t s);
+hipError_t launch_warp(const PairDesc* dpairs, int pair, const PairDesc& hp, const float* consts,
+                       const float* M, const float* th, float* W, uint8_t* mask, int dim,
+                       int transform, hipStream_t s);
+hipError_t launch_similarity(const float* F, const float* W, const uint8_t* mask, long long N,
+                             int sim, double* slots, int nslots, float* value, uint32_t* flag,
+                             hipStream_t s);
+hipError_t launch_adam(float* th, const float* g, float* m, float* v, long long n, float lr_bc1,
+                       float b1, float b2, float inv_sqrt_bc2, float eps, hipStream_t s);
+hipError_t launch_scale(float* x, const float* s, long long n, hipStream_t st);
+
+// Tile configurations of the fused B-spline kernel: {kernel variant, TX, TY, column cells}.
+struct TileCfg {
+    int variant, tx, ty, cells;
+};
+static const TileCfg kCfg3[] = {
+    {0, 32, 8, 4}, {0, 32, 8, 8}, {0, 32, 8, 16}, {1, 64, 4, 4},
+    {1, 64, 4, 16}, {2, 16, 16, 4}, {2, 16, 16, 16}, {0, 32, 8, 2},
+};
+static const TileCfg kCfg2[] = {{0, 64, 1, 2}, {0, 64, 1, 4}, {0, 64, 1, 8}, {0, 64, 1, 16}};
+constexpr int kNumCfg3 = sizeof(kCfg3) / sizeof(kCfg3[0]);
+constexpr int kNumCfg2 = sizeof(kCfg2) / sizeof(kCfg2[0]);
+constexpr int kDenseZc = 16;
+constexpr int kGenericSlots = 1024;
+constexpr size_t kMaxLds = 64 * 1024;
+constexpr int kMaxDevices = 64;
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace air
+
+using namespace air;
+
+struct air_plan {
+    int npairs = 0, dim = 0, transform = 0, sim = 0;
+    int tiling = 0;
+    std::vector<air_problem> probs;
+    std::vector<PairDesc> pd;
+    std::vector<float> consts;
+    WsLayout L{};
+    int ntiles_total = 0, nreg_total = 0;
+    size_t lds_fused = 0, lds_reg = 0;
+    int max_ctrl = 0;
+    int max_dense_blk = 0;
+    std::mutex mu;
+    DeviceTables dev[kMaxDevices];
+    // optional event pairs around the main kernel of each objective launch
+    std::vector<hipEvent_t> ev;
+    int ev_next = 0;
+    int ev_device = -1;
+};
+
+// ------------------------------------------------------------------ tables
+// Cubic B-spline weights of a voxel at offset r in its cell (t = r / sp):
+// beta3(t + 1), beta3(t), beta3(1 - t), beta3(2 - t).
+static void spline_weights(int sp, std::vector<float>& out) {
+    for (int r = 0; r < sp; ++r) {
+        const double t = (double)r / sp;
+        const double w0 = (1 - t) * (1 - t) * (1 - t) / 6.0;
+        const double w1 = (3 * t * t * t - 6 * t * t + 4) / 6.0;
+        const double w2 = (-3 * t * t * t + 3 * t * t + 3 * t + 1) / 6.0;
+        const double w3 = t * t * t / 6.0;
+        out.push_back((float)w0);
+        out.push_back((float)w1);
+        out.push_back((float)w2);
+        out.push_back((float)w3);
+    }
+}
+
+// Banded Gram matrices of one axis over voxels [0, n - 2] (the regulariser
+// domain): P[j][k] = sum_x B(x,j) B(x,k); D[j][k] = sum_x dB(x,j) dB(x,k) with
+// dB(x,j) = B(x+1,j) - B(x,j). Stored as [j][k - j + 3], FP64 sums -> FP32.
+static void gram_tables(int n, int sp, int nc, std::vector<float>& out) {
+    auto basis = [&](int x, int j) -> double {  // B(x, j), x in [0, n-1]
+        const int i = x / sp;
+        const int k = j - i;
+        if (k < 0 || k > 3) return 0.0;
+        const double t = (double)(x - i * sp) / sp;
+        switch (k) {
+            case 0: return (1 - t) * (1 - t) * (1 - t) / 6.0;
+            case 1: return (3 * t * t * t - 6 * t * t + 4) / 6.0;
+            case 2: return (-3 * t * t * t + 3 * t * t + 3 * t + 1) / 6.0;
+            default: return t * t * t / 6.0;
+        }
+    };
+    std::vector<double> P((size_t)nc * 7, 0.0), D((size_t)nc * 7, 0.0);
+    for (int x = 0; x <= n - 2; ++x) {
+        const int i = x / sp;
+        for (int j = std::max(0, i - 1); j <= std::min(nc - 1, i + 4); ++j)
+            for (int k = std::max(0, j - 3); k <= std::min(nc - 1, j + 3); ++k) {
+                P[(size_t)j * 7 + (k - j + 3)] += basis(x, j) * basis(x, k);
+                D[(size_t)j * 7 + (k - j + 3)] +=
+                    (basis(x + 1, j) - basis(x, j)) * (basis(x + 1, k) - basis(x, k));
+            }
+    }
+    for (double v : P) out.push_back((float)v);
+    for (double v : D) out.push_back((float)v);
+}
+
+static air_status validate_problem(const air_problem& p) {
+    if (p.dim != 2 && p.dim != 3) return AIR_ERR_INVALID_ARG;
+    if (p.transform != AIR_TF_BSPLINE3 && p.transform != AIR_TF_DENSE) return AIR_ERR_INVALID_ARG;
+    if (p.similarity != AIR_SIM_MSE && p.similarity != AIR_SIM_NCC) return AIR_ERR_INVALID_ARG;
+    if (!(p.lambda_diff >= 0.f) || !isfinite(p.lambda_diff)) return AIR_ERR_INVALID_ARG;
+    long long N = 1;
+    for (int a = 0; a < p.dim; ++a) {
+        if (p.n[a] < 2 || p.n[a] > 65536) return AIR_ERR_SHAPE;
+        if (p.transform == AIR_TF_BSPLINE3 && (p.spacing[a] < 1 || p.spacing[a] > kMaxSpacing))
+            return AIR_ERR_SHAPE;
+        N *= p.n[a];
+    }
+    if (p.dim == 2 && p.n[2] != 1) return AIR_ERR_SHAPE;
+    if (N * 4 >= (1LL << 31)) return AIR_ERR_SHAPE;  // 32-bit byte offsets in the gathers
+    return AIR_OK;
+}
+
+static air_status build_tables(air_plan* P) {
+    const int d = P->dim;
+    const bool bs = P->transform == AIR_TF_BSPLINE3;
+    const TileCfg cfg = (d == 3) ? kCfg3[P->tiling] : kCfg2[P->tiling];
+    const int NF = P->sim == AIR_SIM_NCC ? 3 : 1;
+    P->pd.assign(P->npairs, PairDesc{});
+    P->consts.clear();
+    size_t stats_n = 0, part_n = 0, param_n = 0, regpart_n = 0, dense_n = 0;
+    int tiles = 0, regs = 0;
+    size_t lds_f = 0, lds_r = 0;
+    int max_ctrl = 0, max_dense = 0;
+    for (int i = 0; i < P->npairs; ++i) {
+        const air_problem& p = P->probs[i];
+        PairDesc& D = P->pd[i];
+        long long N = 1, NC = 1;
+        double xr = 1.0;
+        for (int a = 0; a < 3; ++a) {
+            const bool on = a < d;
+            D.n[a] = on ? p.n[a] : 1;
+            D.sp[a] = (on && bs) ? p.spacing[a] : 1;
+            D.nc[a] = on ? (bs ? (p.n[a] - 1) / p.spacing[a] + 4 : p.n[a]) : 1;
+            D.s[a] = on ? (float)((p.n[a] - 1) * 0.5) : 0.f;
+            if (on) {
+                N *= D.n[a];
+                NC *= D.nc[a];
+                xr *= (double)(p.n[a] - 1);
+            }
+        }
+        D.nvox = N;
+        D.nparam = (long long)d * (bs ? NC : N);
+        D.param_off = (long long)param_n;
+        param_n += (size_t)D.nparam;
+        D.inv_xr = (float)(1.0 / xr);
+        D.lambda = p.lambda_diff;
+        max_ctrl = std::max(max_ctrl, (int)NC);
+        if (bs) {
+            for (int a = 0; a < d; ++a) {
+                D.wtab_off[a] = (int)P->consts.size();
+                spline_weights(D.sp[a], P->consts);
+                while (P->consts.size() % 4) P->consts.push_back(0.f);
+                D.gram_off[a] = (int)P->consts.size();
+                gram_tables(D.n[a], D.sp[a], D.nc[a], P->consts);
+                while (P->consts.size() % 4) P->consts.push_back(0.f);
+            }
+            const int col = d - 1;
+            const int ncell = (D.n[col] - 1) / D.sp[col] + 1;
+            const int cells = std::min(cfg.cells, ncell);
+            D.col_cells = cells;
+            int wxm = 0, wym = 1;
+            const int ntx = cdiv(D.n[0], cfg.tx);
+            for (int t = 0; t < ntx; ++t) {
+                int c0, w;
+                ctrl_window(t * cfg.tx, std::min(t * cfg.tx + cfg.tx, D.n[0]), D.sp[0], &c0, &w);
+                wxm = std::max(wxm, w);
+            }
+            if (d == 3) {
+                const int nty = cdiv(D.n[1], cfg.ty);
+                for (int t = 0; t < nty; ++t) {
+                    int c0, w;
+                    ctrl_window(t * cfg.ty, std::min(t * cfg.ty + cfg.ty, D.n[1]), D.sp[1], &c0,
+                                &w);
+                    wym = std::max(wym, w);
+                }
+                D.ntile[0] = ntx;
+                D.ntile[1] = nty;
+                D.ntile[2] = cdiv(ncell, cells);
+            } else {
+                D.ntile[0] = ntx;
+                D.ntile[1] = cdiv(ncell, cells);
+                D.ntile[2] = 1;
+            }
+            D.win[0] = wxm;
+            D.win[1] = wym;
+            D.win[2] = cells + 3;
+            D.ntiles = D.ntile[0] * D.ntile[1] * D.ntile[2];
+            D.tile_begin = tiles;
+            tiles += D.ntiles;
+            D.part_stride = NF * d * D.win[2] * D.win[1] * D.win[0];
+            D.part_off = (long long)part_n;
+            part_n += (size_t)D.ntiles * D.part_stride;
+            D.nreg = (d == 3) ? 3 * D.nc[2] : 2;
+            D.reg_begin = regs;
+            regs += D.nreg;
+            D.regpart_off = (int)regpart_n;
+            regpart_n += D.nreg;
+            const int NT = cfg.tx * cfg.ty;
+            size_t f;
+            if (d == 3) {
+                f = a4(3 * D.win[2] * wym * cfg.tx) + a4(NF * 3 * cfg.ty * cfg.tx) +
+                    a4(NF * 3 * wym * cfg.tx) + a4(cfg.tx * wxm) + a4(cfg.ty * wym) +
+                    a4(4 * D.sp[2]);
+            } else {
+                f = a4(2 * D.win[2] * cfg.tx) + a4(NF * 2 * cfg.tx) + a4(cfg.tx * wxm) +
+                    a4(4 * D.sp[1]);
+            }
+            const size_t reg = 5 * (size_t)a4(D.nc[0] * D.nc[1]);
+            const size_t head = 8 * sizeof(double) * (NT / 64);
+            lds_f = std::max(lds_f, head + 4 * std::max(f, reg));
+            lds_r = std::max(lds_r, 8 * sizeof(double) * (kBlock / 64) + 4 * reg);
+            stats_n = tiles;
+        } else {
+            const int nbx = cdiv(D.n[0], 64), nby = cdiv(D.n[1], 4);
+            const int nbz = d == 3 ? cdiv(D.n[2], kDenseZc) : 1;
+            D.dense_nblk = nbx * nby * nbz;
+            D.dense_blk_off = (int)dense_n;
+            dense_n += D.dense_nblk;
+            max_dense = std::max(max_dense, D.dense_nblk);
+        }
+    }
+    if (lds_f > kMaxLds || lds_r > kMaxLds) return AIR_ERR_UNSUPPORTED;
+    P->ntiles_total = tiles;
+    P->nreg_total = regs;
+    P->lds_fused = lds_f;
+    P->lds_reg = lds_r;
+    P->max_ctrl = max_ctrl;
+    P->max_dense_blk = max_dense;
+    WsLayout& L = P->L;
+    size_t off = 0;
+    L.stats = off;       off = align256(off + std::max<size_t>(stats_n, 1) * kStatWords * 8);
+    L.part = off;        off = align256(off + std::max<size_t>(part_n, 1) * 4);
+    L.reggrad = off;     off = align256(off + (bs ? std::max<size_t>(param_n, 1) : 1) * 4);
+    L.regpart = off;     off = align256(off + std::max<size_t>(regpart_n, 1) * 8);
+    L.flags = off;       off = align256(off + (size_t)P->npairs * 4);
+    L.scalars = off;     off = align256(off + (size_t)P->npairs * 8 * 8);
+    L.dense_stats = off; off = align256(off + std::max<size_t>(dense_n, 1) * kStatWords * 8);
+    L.generic = off;     off = align256(off + (size_t)kGenericSlots * kStatWords * 8);
+    L.total = off;
+    return AIR_OK;
+}
+
+static void release_device(air_plan* P) {
+    for (int i = 0; i < kMaxDevices; ++i) {
+        DeviceTables& t = P->dev[i];
+        if (t.pairs || t.consts) {
+            int cur = -1;
+            (void)hipGetDevice(&cur);
+            (void)hipSetDevice(i);
+            (void)hipFree(t.pairs);
+            (void)hipFree(t.consts);
+            if (cur >= 0) (void)hipSetDevice(cur);
+        }
+        t = DeviceTables{};
+    }
+}
+
+static air_status ensure_device(const air_plan* cP, DeviceTables** out) {
+    air_plan* P = const_cast<air_plan*>(cP);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return AIR_ERR_DEVICE;
+    std::lock_guard<std::mutex> g(P->mu);
+    DeviceTables& t = P->dev[dev];
+    if (!t.pairs) {
+        const size_t pb = sizeof(PairDesc) * P->pd.size();
+        const size_t cb = sizeof(float) * std::max<size_t>(P->consts.size(), 4);
+        void* a = nullptr;
+        void* b = nullptr;
+        if (hipMalloc(&a, pb) != hipSuccess) return AIR_ERR_DEVICE;
+        if (hipMalloc(&b, cb) != hipSuccess) {
+            (void)hipFree(a);
+            return AIR_ERR_DEVICE;
+        }
+        if (hipMemcpy(a, P->pd.data(), pb, hipMemcpyHostToDevice) != hipSuccess ||
+            (!P->consts.empty() &&
+             hipMemcpy(b, P->consts.data(), sizeof(float) * P->consts.size(),
+                       hipMemcpyHostToDevice) != hipSuccess)) {
+            (void)hipFree(a);
+            (void)hipFree(b);
+            return AIR_ERR_DEVICE;
+        }
+        t.pairs = static_cast<PairDesc*>(a);
+        t.consts = static_cast<float*>(b);
+        t.device = dev;
+    }
+    *out = &t;
+    return AIR_OK;
+}
+
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+static LaunchCtx base_ctx(const air_plan* P, const DeviceTables* T, void* ws) {
+    LaunchCtx C{};
+    C.pairs = T->pairs;
+    C.consts = T->consts;
+    C.npairs = P->npairs;
+    C.ntiles_total = P->ntiles_total;
+    C.nreg_total = P->nreg_total;
+    C.dim = P->dim;
+    C.sim = P->sim;
+    C.ws = static_cast<unsigned char*>(ws);
+    C.L = P->L;
+    return C;
+}
+
+static air_status run_objective(const air_plan* cP, LaunchCtx& C, hipStream_t s) {
+    air_plan* P = const_cast<air_plan*>(cP);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!P->ev.empty() && P->ev_next + 2 <= (int)P->ev.size()) {
+        e0 = P->ev[P->ev_next];
+        e1 = P->ev[P->ev_next + 1];
+        P->ev_next += 2;
+    }
+    hipError_t e;
+    if (P->transform == AIR_TF_BSPLINE3) {
+        const int variant = (P->dim == 3) ? kCfg3[P->tiling].variant : 0;
+        e = launch_bspline(C, variant, P->lds_fused, P->max_ctrl, s, e0, e1);
+    } else {
+        e = launch_dense(C, kDenseZc, P->max_dense_blk, s, e0, e1);
+    }
+    return e == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+static void release_events(air_plan* P) {
+    for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
+    P->ev.clear();
+    P->ev_next = 0;
+}
+
+extern "C" {
+
+air_status air_plan_create(const air_problem* probs, int32_t npairs, air_plan** out) {
+    if (!out) return AIR_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!probs || npairs < 1 || npairs > kMaxPairs) return AIR_ERR_INVALID_ARG;
+    for (int i = 0; i < npairs; ++i) {
+        air_status st = validate_problem(probs[i]);
+        if (st != AIR_OK) return st;
+        if (probs[i].dim != probs[0].dim || probs[i].transform != probs[0].transform ||
+            probs[i].similarity != probs[0].similarity)
+            return AIR_ERR_UNSUPPORTED;
+    }
+    air_plan* P = new (std::nothrow) air_plan();
+    if (!P) return AIR_ERR_DEVICE;
+    P->npairs = npairs;
+    P->dim = probs[0].dim;
+    P->transform = probs[0].transform;
+    P->sim = probs[0].similarity;
+    P->probs.assign(probs, probs + npairs);
+    P->tiling = 0;
+    air_status st = build_tables(P);
+    if (st != AIR_OK) {
+        delete P;
+        return st;
+    }
+    *out = P;
+    return AIR_OK;
+}
+
+void air_plan_destroy(air_plan* plan) {
+    if (!plan) return;
+    release_events(plan);
+    release_device(plan);
+    delete plan;
+}
+
+air_status air_plan_prepare(air_plan* plan) {
+    if (!plan) return AIR_ERR_INVALID_ARG;
+    DeviceTables* t = nullptr;
+    return ensure_device(plan, &t);
+}
+
+air_status air_plan_workspace_bytes(const air_plan* plan, size_t* bytes) {
+    if (!plan || !bytes) return AIR_ERR_INVALID_ARG;
+    *bytes = plan->L.total;
+    return AIR_OK;
+}
+
+air_status air_plan_param_count(const air_plan* plan, int32_t pair, int64_t* count) {
+    if (!plan || !count) return AIR_ERR_INVALID_ARG;
+    if (pair < 0 || pair >= plan->npairs) return AIR_ERR_SHAPE;
+    *count = plan->pd[pair].nparam;
+    return AIR_OK;
+}
+
+int32_t air_tiling_count(int32_t dim) {
+    return dim == 3 ? kNumCfg3 : (dim == 2 ? kNumCfg2 : 0);
+}
+
+air_status air_tiling_describe(int32_t dim, int32_t id, int32_t* tile_x, int32_t* tile_y,
+                               int32_t* column_cells) {
+    if (id < 0 || id >= air_tiling_count(dim)) return AIR_ERR_INVALID_ARG;
+    const TileCfg c = dim == 3 ? kCfg3[id] : kCfg2[id];
+    if (tile_x) *tile_x = c.tx;
+    if (tile_y) *tile_y = c.ty;
+    if (column_cells) *column_cells = c.cells;
+    return AIR_OK;
+}
+
+air_status air_plan_set_tiling(air_plan* plan, int32_t id) {
+    if (!plan) return AIR_ERR_INVALID_ARG;
+    if (id < 0 || id >= air_tiling_count(plan->dim)) return AIR_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> g(plan->mu);
+    const int old = plan->tiling;
+    plan->tiling = id;
+    air_status st = build_tables(plan);
+    if (st != AIR_OK) {
+        plan->tiling = old;
+        build_tables(plan);
+        return st;
+    }
+    release_device(plan);
+    return AIR_OK;
+}
+
+air_status air_plan_get_tiling(const air_plan* plan, int32_t* id) {
+    if (!plan || !id) return AIR_ERR_INVALID_ARG;
+    *id = plan->tiling;
+    return AIR_OK;
+}
+
+air_status air_warp(const air_plan* plan, int32_t pair, const float* moving, const float* theta,
+                    float* warped, uint8_t* mask, void* stream) {
+    if (!plan || !moving || !theta || !warped) return AIR_ERR_INVALID_ARG;
+    if (pair < 0 || pair >= plan->npairs) return AIR_ERR_SHAPE;
+    if (!aligned16(moving) || !aligned16(theta) || !aligned16(warped) ||
+        (mask && !aligned16(mask)))
+        return AIR_ERR_ALIGN;
+    DeviceTables* T = nullptr;
+    air_status st = ensure_device(plan, &T);
+    if (st != AIR_OK) return st;
+    hipError_t e = launch_warp(T->pairs, pair, plan->pd[pair], T->consts, moving, theta, warped,
+                               mask, plan->dim, plan->transform, (hipStream_t)stream);
+    return e == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_similarity(const air_plan* plan, int32_t pair, const float* fixed,
+                          const float* warped, const uint8_t* mask, float* value, void* ws,
+                          size_t ws_bytes, void* stream) {
+    if (!plan || !fixed || !warped || !value) return AIR_ERR_INVALID_ARG;
+    if (pair < 0 || pair >= plan->npairs) return AIR_ERR_SHAPE;
+    if (!aligned16(fixed) || !aligned16(warped) || (mask && !aligned16(mask)))
+        return AIR_ERR_ALIGN;
+    if (!ws || ws_bytes < plan->L.total) return AIR_ERR_WORKSPACE;
+    unsigned char* w = static_cast<unsigned char*>(ws);
+    hipError_t e = launch_similarity(
+        fixed, warped, mask, plan->pd[pair].nvox, plan->sim,
+        reinterpret_cast<double*>(w + plan->L.generic), kGenericSlots, value,
+        reinterpret_cast<uint32_t*>(w + plan->L.flags) + pair, (hipStream_t)stream);
+    return e == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_regulariser(const air_plan* plan, int32_t pair, const float* theta, float* value,
+                           float* grad, void* ws, size_t ws_bytes, void* stream) {
+    if (!plan || !theta || !value) return AIR_ERR_INVALID_ARG;
+    if (pair < 0 || pair >= plan->npairs) return AIR_ERR_SHAPE;
+    if (!aligned16(theta) || (grad && !aligned16(grad))) return AIR_ERR_ALIGN;
+    if (!ws || ws_bytes < plan->L.total) return AIR_ERR_WORKSPACE;
+    DeviceTables* T = nullptr;
+    air_status st = ensure_device(plan, &T);
+    if (st != AIR_OK) return st;
+    unsigned char* w = static_cast<unsigned char*>(ws);
+    const PairDesc& hp = plan->pd[pair];
+    hipError_t e;
+    if (plan->transform == AIR_TF_BSPLINE3) {
+        float* g = grad ? grad : reinterpret_cast<float*>(w + plan->L.reggrad) + hp.param_off;
+        double* rp = reinterpret_cast<double*>(w + plan->L.regpart) + hp.regpart_off;
+        e = launch_reg_bspline(T->pairs, hp, pair, T->consts, theta, g, rp, value, plan->dim,
+                               plan->lds_reg, (hipStream_t)stream);
+    } else {
+        if (!grad) return AIR_ERR_INVALID_ARG;  // the dense stencil writes its gradient
+        LaunchCtx C = base_ctx(plan, T, ws);
+        C.pairs = T->pairs + pair;
+        C.npairs = 1;
+        C.theta0 = theta;
+        // the sub-context sees this pair at index 0; its slots keep their offsets
+        e = launch_reg_dense(C, hp.dense_nblk, kDenseZc, grad, value, (hipStream_t)stream);
+    }
+    return e == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_objective_and_grad(const air_plan* plan, const float* fixed, const float* moving,
+                                  const float* theta, float* value, float* grad, void* ws,
+                                  size_t ws_bytes, void* stream) {
+    if (!plan || !fixed || !moving || !theta || !value || !grad) return AIR_ERR_INVALID_ARG;
+    if (plan->npairs != 1) return AIR_ERR_INVALID_ARG;
+    if (!aligned16(fixed) || !aligned16(moving) || !aligned16(theta) || !aligned16(grad))
+        return AIR_ERR_ALIGN;
+    if (!ws || ws_bytes < plan->L.total) return AIR_ERR_WORKSPACE;
+    if (!aligned16(ws)) return AIR_ERR_ALIGN;
+    DeviceTables* T = nullptr;
+    air_status st = ensure_device(plan, &T);
+    if (st != AIR_OK) return st;
+    LaunchCtx C = base_ctx(plan, T, ws);
+    C.fixed0 = fixed;
+    C.moving0 = moving;
+    C.theta0 = theta;
+    C.grad0 = grad;
+    C.value0 = value;
+    return run_objective(plan, C, (hipStream_t)stream);
+}
+
+air_status air_objective_and_grad_batched(const air_plan* plan, const float* const* fixed,
+                                          const float* const* moving, const float* const* theta,
+                                          float* values, float* const* grads, void* ws,
+                                          size_t ws_bytes, void* stream) {
+    if (!plan || !fixed || !moving || !theta || !values || !grads) return AIR_ERR_INVALID_ARG;
+    if (((uintptr_t)fixed | (uintptr_t)moving | (uintptr_t)theta | (uintptr_t)grads) & 7u)
+        return AIR_ERR_ALIGN;
+    if (((uintptr_t)values & 3u) != 0) return AIR_ERR_ALIGN;
+    if (!ws || ws_bytes < plan->L.total) return AIR_ERR_WORKSPACE;
+    if (!aligned16(ws)) return AIR_ERR_ALIGN;
+    DeviceTables* T = nullptr;
+    air_status st = ensure_device(plan, &T);
+    if (st != AIR_OK) return st;
+    LaunchCtx C = base_ctx(plan, T, ws);
+    C.fixed_tab = fixed;
+    C.moving_tab = moving;
+    C.theta_tab = theta;
+    C.grad_tab = grads;
+    C.values = values;
+    return run_objective(plan, C, (hipStream_t)stream);
+}
+
+air_status air_adam_step(float* theta, const float* grad, float* m, float* v, int64_t n, float lr,
+                         float b1, float b2, float eps, int32_t step, void* stream) {
+    if (!theta || !grad || !m || !v) return AIR_ERR_INVALID_ARG;
+    if (n < 0 || step < 1) return AIR_ERR_SHAPE;
+    if (!(b1 >= 0.f && b1 < 1.f) || !(b2 >= 0.f && b2 < 1.f) || !(eps >= 0.f) || !(lr >= 0.f))
+        return AIR_ERR_INVALID_ARG;
+    if (!aligned16(theta) || !aligned16(grad) || !aligned16(m) || !aligned16(v))
+        return AIR_ERR_ALIGN;
+    if (n == 0) return AIR_OK;
+    const double bc1 = 1.0 - pow((double)b1, step);
+    const double bc2 = 1.0 - pow((double)b2, step);
+    hipError_t e = launch_adam(theta, grad, m, v, n, (float)(lr / bc1), b1, b2,
+                               (float)(1.0 / sqrt(bc2)), eps, (hipStream_t)stream);
+    return e == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_scale(float* x, const float* s, int64_t n, void* stream) {
+    if (!x || !s) return AIR_ERR_INVALID_ARG;
+    if (n < 0) return AIR_ERR_SHAPE;
+    if (!aligned16(x)) return AIR_ERR_ALIGN;
+    if (n == 0) return AIR_OK;
+    hipError_t e = launch_scale(x, s, n, (hipStream_t)stream);
+    return e == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_get_flags(const air_plan* plan, const void* ws, uint32_t* flags, void* stream) {
+    if (!plan || !ws || !flags) return AIR_ERR_INVALID_ARG;
+    const unsigned char* w = static_cast<const unsigned char*>(ws);
+    if (hipMemcpyAsync(flags, w + plan->L.flags, sizeof(uint32_t) * plan->npairs,
+                       hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess)
+        return AIR_ERR_DEVICE;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return AIR_ERR_DEVICE;
+    return AIR_OK;
+}
+
+air_status air_plan_timing(air_plan* plan, int32_t launches) {
+    if (!plan || launches < 0 || launches > 1000000) return AIR_ERR_INVALID_ARG;
+    release_events(plan);
+    for (int i = 0; i < 2 * launches; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) {
+            release_events(plan);
+            return AIR_ERR_DEVICE;
+        }
+        plan->ev.push_back(e);
+    }
+    return AIR_OK;
+}
+
+air_status air_plan_timing_read(air_plan* plan, double* total_ms, int32_t* launches) {
+    if (!plan || !total_ms || !launches) return AIR_ERR_INVALID_ARG;
+    double tot = 0.0;
+    const int n = plan->ev_next / 2;
+    for (int i = 0; i < n; ++i) {
+        if (hipEventSynchronize(plan->ev[2 * i + 1]) != hipSuccess) return AIR_ERR_DEVICE;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, plan->ev[2 * i], plan->ev[2 * i + 1]) != hipSuccess)
+            return AIR_ERR_DEVICE;
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = n;
+    plan->ev_next = 0;
+    return AIR_OK;
+}
+
+const char* air_strerror(air_status s) {
+    switch (s) {
+        case AIR_OK: return "ok";
+        case AIR_ERR_INVALID_ARG: return "invalid argument";
+        case AIR_ERR_SHAPE: return "shape, spacing or index out of range";
+        case AIR_ERR_ALIGN: return "pointer not 16-byte aligned";
+        case AIR_ERR_WORKSPACE: return "workspace missing or too small";
+        case AIR_ERR_UNSUPPORTED: return "unsupported combination";
+        case AIR_ERR_LAUNCH: return "kernel launch failed";
+        case AIR_ERR_NONFINITE: return "non-finite or degenerate result";
+        case AIR_ERR_DEVICE: return "device query, allocation or copy failed";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// Device helpers shared by the airhip kernels.
+#pragma once
+
+#include "air_internal.h"
+
+namespace air {
+
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+// Buffer resource over [base, base + bytes) for raw (untyped) loads. The
+// operands are made wave-uniform explicitly so that the descriptor lives in
+// SGPRs (a descriptor the compiler cannot prove uniform costs a
+// readfirstlane loop around every load).
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    const uint64_t p = reinterpret_cast<uint64_t>(base);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)p);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
+    const uint32_t nb = __builtin_amdgcn_readfirstlane(bytes);
+    void* q = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(q, (short)0, (int)nb, 0x00020000);
+}
+
+// Two consecutive floats at byte offset voff + soff (dword aligned).
+__device__ inline v2f load2(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(v2f, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// Sum K doubles over the block in a fixed order; every thread gets the totals.
+// scratch: K * (NT / 64) doubles of LDS.
+template <int NT, int K>
+__device__ inline void block_sum(double (&v)[K], double* scratch) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) scratch[k * NW + w] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < NW; ++i) s += scratch[k * NW + i];
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
+// Index of the pair owning global work item `item` (binary search on begin).
+template <bool REG>
+__device__ inline int find_pair(const PairDesc* pairs, int npairs, int item) {
+    int lo = 0, hi = npairs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        int b = REG ? pairs[mid].reg_begin : pairs[mid].tile_begin;
+        if (b <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Blocks are dealt round-robin to the 8 XCDs; remap so that each XCD works
+// on one contiguous range of items (neighbouring tiles share its L2).
+__device__ inline int xcd_remap(int b, int nb) {
+    constexpr int NX = 8;
+    const int q = nb / NX, r = nb % NX;
+    const int x = b % NX, i = b / NX;
+    // XCD x owns items [start(x), start(x) + q + (x < r))
+    const int start = x * q + (x < r ? x : r);
+    const int cnt = q + (x < r ? 1 : 0);
+    return i < cnt ? start + i : b;  // i >= cnt cannot happen for b < nb
+}
+
+}  // namespace air

@@ -1,0 +1,916 @@
+// Fused objective + gradient for the cubic B-spline transform.
+//
+// One work item is a tile of voxels: TX x TY lanes over (x, y) and a chunk of
+// control cells along the column axis (z in 3D, y in 2D), walked by every
+// lane. Per tile:
+//   1. the control window is x-interpolated into LDS (separable expansion of
+//      Sec. II-A eq. kernel_basis with the cubic B-spline of Sec. III-C);
+//   2. each lane keeps the four column-axis control values of its current
+//      cell in registers and forms u = sum_k w_k(t) V_k per voxel;
+//   3. the moving image is sampled at p = x + u (n - 1)/2 with two 8-byte
+//      buffer loads per corner pair (Sec. III-C Image Warping), giving W and
+//      dW/dp; out-of-domain voxels are masked out;
+//   4. similarity statistics are accumulated (MSE: sum of squared error;
+//      NCC: moments about a per-tile shift);
+//   5. the adjoint field (dS/dW dW/dp, split into 3 affine parts for NCC so
+//      that the global NCC coefficients can be applied afterwards) is
+//      transposed back onto the control window: per-voxel along the column,
+//      then along y and x in LDS when a column control is complete.
+// The per-tile partials are combined by k_finalize in a fixed order
+// (deterministic), together with the regulariser computed exactly in control
+// space from banded Gram matrices (blocks appended to the same launch).
+#include "device_common.h"
+
+namespace air {
+
+// --------------------------------------------------------------- regulariser
+// dR/dtheta_c = (2/|X_R|) sum_a K_a theta_c with K_a the Kronecker product of
+// per-axis banded Gram matrices: D (differences) on axis a, P on the others.
+// One block handles one control plane (3D: fixed kz) of one component.
+template <int NT>
+__device__ void reg_block(const PairDesc& P, const float* __restrict__ consts,
+                          const float* __restrict__ theta, float* __restrict__ out_grad,
+                          float scale, double* __restrict__ regpart, int r, int dim,
+                          float* lds, double* red) {
+    const int ncx = P.nc[0], ncy = P.nc[1], ncz = P.nc[2];
+    const int plane = ncx * ncy;
+    const float* Px = consts + P.gram_off[0];
+    const float* Dx = Px + 7 * ncx;
+    const float* Py = consts + P.gram_off[1];
+    const float* Dy = Py + 7 * ncy;
+    int c, kz;
+    if (dim == 3) { c = r / ncz; kz = r % ncz; } else { c = r; kz = 0; }
+    const float* th = theta + (long long)c * ncz * plane;
+    float* A = lds;              // P_z theta (3D) or theta (2D)
+    float* Cz = A + plane;       // D_z theta (3D only)
+    float* AP = Cz + plane;
+    float* AD = AP + plane;
+    float* CP = AD + plane;
+    const int tid = threadIdx.x;
+    if (dim == 3) {
+        const float* Pz = consts + P.gram_off[2];
+        const float* Dz = Pz + 7 * ncz;
+        for (int i = tid; i < plane; i += NT) {
+            float a = 0.f, b = 0.f;
+#pragma unroll
+            for (int o = -3; o <= 3; ++o) {
+                int k = kz + o;
+                if (k < 0 || k >= ncz) continue;
+                float t = th[(long long)k * plane + i];
+                a += Pz[kz * 7 + o + 3] * t;
+                b += Dz[kz * 7 + o + 3] * t;
+            }
+            A[i] = a;
+            Cz[i] = b;
+        }
+    } else {
+        for (int i = tid; i < plane; i += NT) A[i] = th[i];
+    }
+    __syncthreads();
+    for (int i = tid; i < plane; i += NT) {
+        const int ky = i / ncx, kx = i % ncx;
+        float ap = 0.f, ad = 0.f, cp = 0.f;
+#pragma unroll
+        for (int o = -3; o <= 3; ++o) {
+            int k = ky + o;
+            if (k < 0 || k >= ncy) continue;
+            float a = A[k * ncx + kx];
+            ap += Py[ky * 7 + o + 3] * a;
+            ad += Dy[ky * 7 + o + 3] * a;
+            if (dim == 3) cp += Py[ky * 7 + o + 3] * Cz[k * ncx + kx];
+        }
+        AP[i] = ap;
+        AD[i] = ad;
+        CP[i] = cp;
+    }
+    __syncthreads();
+    double acc[1] = {0.0};
+    const float* thp = th + (long long)kz * plane;
+    float* gp = out_grad + (long long)c * ncz * plane + (long long)kz * plane;
+    for (int i = tid; i < plane; i += NT) {
+        const int ky = i / ncx, kx = i % ncx;
+        float o_ = 0.f;
+#pragma unroll
+        for (int o = -3; o <= 3; ++o) {
+            int k = kx + o;
+            if (k < 0 || k >= ncx) continue;
+            const int j = ky * ncx + k;
+            o_ += Dx[kx * 7 + o + 3] * AP[j] + Px[kx * 7 + o + 3] * (AD[j] + CP[j]);
+        }
+        gp[i] = scale * o_;
+        acc[0] += (double)thp[i] * (double)o_;
+    }
+    block_sum<NT, 1>(acc, red);
+    if (tid == 0) regpart[r] = acc[0];
+}
+
+// --------------------------------------------------------------- fused 3D
+template <int TX, int TY, int SIM>
+__global__ void __launch_bounds__(TX* TY)
+k_fused3(const LaunchCtx C) {
+    constexpr int NT = TX * TY;
+    constexpr int NF = (SIM == AIR_SIM_NCC) ? 3 : 1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* red = reinterpret_cast<double*>(smem_raw);          // 8 * NT/64 doubles
+    float* lds = reinterpret_cast<float*>(smem_raw + 8 * sizeof(double) * (NT / 64));
+    const int tid = threadIdx.x;
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+
+    if (item >= C.ntiles_total) {
+        const int r = item - C.ntiles_total;
+        const int pair = find_pair<true>(C.pairs, C.npairs, r);
+        const PairDesc P = C.pairs[pair];
+        const float* theta = C.theta_tab ? C.theta_tab[pair] : C.theta0;
+        float* rg = reinterpret_cast<float*>(C.ws + C.L.reggrad) + P.param_off;
+        double* rp = reinterpret_cast<double*>(C.ws + C.L.regpart) + P.regpart_off;
+        reg_block<NT>(P, C.consts, theta, rg, P.lambda * 2.0f * P.inv_xr, rp,
+                      r - P.reg_begin, 3, lds, red);
+        return;
+    }
+    const int pair = find_pair<false>(C.pairs, C.npairs, item);
+    const PairDesc P = C.pairs[pair];
+    const float* __restrict__ F = C.fixed_tab ? C.fixed_tab[pair] : C.fixed0;
+    const float* __restrict__ M = C.moving_tab ? C.moving_tab[pair] : C.moving0;
+    const float* __restrict__ theta = C.theta_tab ? C.theta_tab[pair] : C.theta0;
+
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    const int sx = P.sp[0], sy = P.sp[1], sz = P.sp[2];
+    const int ncx = P.nc[0], ncy = P.nc[1];
+    const int WxM = P.win[0], WyM = P.win[1], WzM = P.win[2];
+
+    int t = item - P.tile_begin;
+    if (t == 0 && tid == 0) reinterpret_cast<uint32_t*>(C.ws + C.L.flags)[pair] = 0u;
+    const int tx = t % P.ntile[0];
+    t /= P.ntile[0];
+    const int ty = t % P.ntile[1];
+    const int tz = t / P.ntile[1];
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int ncell_z = (nz - 1) / sz + 1;
+    const int cz_b = tz * P.col_cells;
+    const int cz_e = min(cz_b + P.col_cells, ncell_z);
+    int cx0, Wx, cy0, Wy;
+    ctrl_window(x0, min(x0 + TX, nx), sx, &cx0, &Wx);
+    ctrl_window(y0, min(y0 + TY, ny), sy, &cy0, &Wy);
+    const int cz0 = cz_b, Wz = cz_e - cz_b + 3;
+
+    // LDS carve-up
+    float* T1 = lds;                              // [3][WzM][WyM][TX]
+    float* E = T1 + a4(3 * WzM * WyM * TX);       // [NF*3][TY][TX]
+    float* G = E + a4(NF * 3 * TY * TX);          // [NF*3][WyM][TX]
+    float* WXT = G + a4(NF * 3 * WyM * TX);       // [TX][WxM]
+    float* WYT = WXT + a4(TX * WxM);              // [TY][WyM]
+    float* WZT = WYT + a4(TY * WyM);              // [sz][4]
+
+    const int lx = tid % TX, ly = tid / TX;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool act = (x < nx) && (y < ny);
+    const int xc = min(x, nx - 1), yc = min(y, ny - 1);
+    const int ix = xc / sx, iy = yc / sy;
+    const float* wtx = C.consts + P.wtab_off[0] + (xc - ix * sx) * 4;
+    const float* wty = C.consts + P.wtab_off[1] + (yc - iy * sy) * 4;
+    const float wx0 = wtx[0], wx1 = wtx[1], wx2 = wtx[2], wx3 = wtx[3];
+    const float wy[4] = {wty[0], wty[1], wty[2], wty[3]};
+    const int ky0 = iy - cy0;
+
+    // transposition weight tables (zero where a lane does not support a control)
+    for (int i = tid; i < TX * WxM; i += NT) {
+        const int q = i / WxM, k = i % WxM;
+        float w = 0.f;
+        const int xq = x0 + q;
+        if (xq < nx) {
+            const int kk = k - (xq / sx - cx0);
+            if (kk >= 0 && kk < 4) w = C.consts[P.wtab_off[0] + (xq % sx) * 4 + kk];
+        }
+        WXT[i] = w;
+    }
+    for (int i = tid; i < TY * WyM; i += NT) {
+        const int q = i / WyM, k = i % WyM;
+        float w = 0.f;
+        const int yq = y0 + q;
+        if (yq < ny) {
+            const int kk = k - (yq / sy - cy0);
+            if (kk >= 0 && kk < 4) w = C.consts[P.wtab_off[1] + (yq % sy) * 4 + kk];
+        }
+        WYT[i] = w;
+    }
+    for (int i = tid; i < sz * 4; i += NT) WZT[i] = C.consts[P.wtab_off[2] + i];
+
+    // 1. x-pass of the control window: T1[c][kz][ky][lx]
+    {
+        const long long NC = (long long)ncx * ncy * P.nc[2];
+        for (int r = ly; r < 3 * Wz * Wy; r += TY) {
+            const int c = r / (Wz * Wy);
+            const int rem = r - c * Wz * Wy;
+            const int kz = rem / Wy, ky = rem - kz * Wy;
+            float v = 0.f;
+            if (x < nx) {
+                const float* th = theta + c * NC +
+                                  ((long long)(cz0 + kz) * ncy + (cy0 + ky)) * ncx + ix;
+                v = wx0 * th[0] + wx1 * th[1] + wx2 * th[2] + wx3 * th[3];
+            }
+            T1[((c * WzM + kz) * WyM + ky) * TX + lx] = v;
+        }
+    }
+    // per-tile shift for the NCC moments (a sample of F and M in the tile)
+    float shF = 0.f, shW = 0.f;
+    if (SIM == AIR_SIM_NCC) {
+        const int xs = min(x0 + TX / 2, nx - 1), ys = min(y0 + TY / 2, ny - 1);
+        const int zs = min((cz_b * sz + min(cz_e * sz, nz)) / 2, nz - 1);
+        const long long vs = ((long long)zs * ny + ys) * nx + xs;
+        shF = F[vs];
+        shW = M[vs];
+    }
+    __syncthreads();
+
+    auto vcol = [&](int c, int kz) -> float {
+        const float* r = T1 + ((c * WzM + kz) * WyM + ky0) * TX + lx;
+        return wy[0] * r[0] + wy[1] * r[TX] + wy[2] * r[2 * TX] + wy[3] * r[3 * TX];
+    };
+    float V[3][4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) V[c][k] = vcol(c, k);
+    float acc[NF][3][4];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[f][c][k] = 0.f;
+
+    int cnt = 0;
+    float m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f;
+    const float snx = P.s[0], sny = P.s[1], snz = P.s[2];
+    const float hx = (float)(nx - 2), hy = (float)(ny - 2), hz = (float)(nz - 2);
+    const int nx4 = nx * 4, nxy4 = nx * ny * 4;
+    const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, (uint32_t)(P.nvox * 4));
+    float* part = reinterpret_cast<float*>(C.ws + C.L.part) + P.part_off +
+                  (long long)(item - P.tile_begin) * P.part_stride;
+
+    auto flush = [&](int kzl) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) E[((f * 3 + c) * TY + ly) * TX + lx] = acc[f][c][0];
+        __syncthreads();
+        for (int o = tid; o < NF * 3 * Wy * TX; o += NT) {
+            const int q = o % TX;
+            const int t2 = o / TX;
+            const int ky = t2 % Wy, fc = t2 / Wy;
+            float s = 0.f;
+#pragma unroll
+            for (int r = 0; r < TY; ++r) s += WYT[r * WyM + ky] * E[(fc * TY + r) * TX + q];
+            G[(fc * WyM + ky) * TX + q] = s;
+        }
+        __syncthreads();
+        for (int o = tid; o < NF * 3 * Wy * Wx; o += NT) {
+            const int kx = o % Wx;
+            const int t2 = o / Wx;
+            const int ky = t2 % Wy, fc = t2 / Wy;
+            const float* g = G + (fc * WyM + ky) * TX;
+            // lanes whose voxels lie in the support of control cx0 + kx
+            const int q0 = max(0, (cx0 + kx - 3) * sx - x0);
+            const int q1 = min(TX, (cx0 + kx + 1) * sx - x0);
+            float s = 0.f;
+            for (int q = q0; q < q1; ++q) s += WXT[q * WxM + kx] * g[q];
+            part[((fc * WzM + kzl) * WyM + ky) * WxM + kx] = s;
+        }
+    };
+
+    for (int cz = cz_b; cz < cz_e; ++cz) {
+        const int kzl = cz - cz0;
+        const int zb = cz * sz, ze = min(zb + sz, nz);
+        for (int z = zb; z < ze; ++z) {
+            const float4 wz = *reinterpret_cast<const float4*>(WZT + (z - zb) * 4);
+            if (act) {
+                const long long v = ((long long)z * ny + y) * nx + x;
+                const float Fv = F[v];
+                float u[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    u[c] = wz.x * V[c][0] + wz.y * V[c][1] + wz.z * V[c][2] + wz.w * V[c][3];
+                const float px = fmaf(u[0], snx, (float)x);
+                const float py = fmaf(u[1], sny, (float)y);
+                const float pz = fmaf(u[2], snz, (float)z);
+                const float flx = floorf(px), fly = floorf(py), flz = floorf(pz);
+                const float jxf = fminf(flx, hx), jyf = fminf(fly, hy), jzf = fminf(flz, hz);
+                const float fx = px - jxf, fy = py - jyf, fz = pz - jzf;
+                const bool in = (flx >= 0.f) & (fly >= 0.f) & (flz >= 0.f) &
+                                (fx <= 1.f) & (fy <= 1.f) & (fz <= 1.f);
+                if (in) {
+                    const int jx = (int)jxf, jy = (int)jyf, jz = (int)jzf;
+                    const int off = ((jz * ny + jy) * nx + jx) * 4;
+                    const v2f a00 = load2(rM, off, 0);
+                    const v2f a10 = load2(rM, off, nx4);
+                    const v2f a01 = load2(rM, off, nxy4);
+                    const v2f a11 = load2(rM, off, nxy4 + nx4);
+                    // corners c[z][y][x]
+                    const float dz00 = a01.x - a00.x, dz01 = a01.y - a00.y;
+                    const float dz10 = a11.x - a10.x, dz11 = a11.y - a10.y;
+                    const float e00 = a00.x + fz * dz00, e01 = a00.y + fz * dz01;
+                    const float e10 = a10.x + fz * dz10, e11 = a10.y + fz * dz11;
+                    const float dy0 = e10 - e00, dy1 = e11 - e01;
+                    const float g0 = e00 + fy * dy0, g1 = e01 + fy * dy1;
+                    const float W = g0 + fx * (g1 - g0);
+                    float d[3];
+                    d[0] = g1 - g0;
+                    d[1] = dy0 + fx * (dy1 - dy0);
+                    const float h0 = dz00 + fy * (dz10 - dz00);
+                    const float h1 = dz01 + fy * (dz11 - dz01);
+                    d[2] = h0 + fx * (h1 - h0);
+                    // sample exactly on the last voxel: right-sided cell, zero padding
+                    if (fx == 1.f) d[0] = -W;
+                    if (fy == 1.f) d[1] = -W;
+                    if (fz == 1.f) d[2] = -W;
+                    cnt += 1;
+                    if (SIM == AIR_SIM_NCC) {
+                        const float dF = Fv - shF, dW = W - shW;
+                        m1 += dF;
+                        m2 += dW;
+                        m3 += dF * dF;
+                        m4 += dW * dW;
+                        m5 += dF * dW;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            const float gF = dF * d[c], gW = dW * d[c], g1_ = d[c];
+                            acc[0][c][0] += wz.x * gF;
+                            acc[0][c][1] += wz.y * gF;
+                            acc[0][c][2] += wz.z * gF;
+                            acc[0][c][3] += wz.w * gF;
+                            acc[1][c][0] += wz.x * gW;
+                            acc[1][c][1] += wz.y * gW;
+                            acc[1][c][2] += wz.z * gW;
+                            acc[1][c][3] += wz.w * gW;
+                            acc[NF - 1][c][0] += wz.x * g1_;
+                            acc[NF - 1][c][1] += wz.y * g1_;
+                            acc[NF - 1][c][2] += wz.z * g1_;
+                            acc[NF - 1][c][3] += wz.w * g1_;
+                        }
+                    } else {
+                        const float e = W - Fv;
+                        m1 += e * e;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            const float g = e * d[c];
+                            acc[0][c][0] += wz.x * g;
+                            acc[0][c][1] += wz.y * g;
+                            acc[0][c][2] += wz.z * g;
+                            acc[0][c][3] += wz.w * g;
+                        }
+                    }
+                }
+            }
+        }
+        flush(kzl);
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                acc[f][c][0] = acc[f][c][1];
+                acc[f][c][1] = acc[f][c][2];
+                acc[f][c][2] = acc[f][c][3];
+                acc[f][c][3] = 0.f;
+            }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            V[c][0] = V[c][1];
+            V[c][1] = V[c][2];
+            V[c][2] = V[c][3];
+            V[c][3] = (kzl + 4 < Wz) ? vcol(c, kzl + 4) : 0.f;
+        }
+    }
+    // the last three column controls of the window
+    for (int k = Wz - 3; k < Wz; ++k) {
+        flush(k);
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                acc[f][c][0] = acc[f][c][1];
+                acc[f][c][1] = acc[f][c][2];
+                acc[f][c][2] = acc[f][c][3];
+                acc[f][c][3] = 0.f;
+            }
+    }
+    // tile statistics
+    double st[6] = {(double)cnt, (double)m1, (double)m2, (double)m3, (double)m4, (double)m5};
+    block_sum<NT, 6>(st, red);
+    if (tid == 0) {
+        double* slot = reinterpret_cast<double*>(C.ws + C.L.stats) + (long long)item * kStatWords;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) slot[k] = st[k];
+        slot[6] = shF;
+        slot[7] = shW;
+    }
+}
+
+// --------------------------------------------------------------- fused 2D
+// Lanes over x (TX), the column axis is y.
+template <int TX, int SIM>
+__global__ void __launch_bounds__(TX)
+k_fused2(const LaunchCtx C) {
+    constexpr int NT = TX;
+    constexpr int NF = (SIM == AIR_SIM_NCC) ? 3 : 1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* red = reinterpret_cast<double*>(smem_raw);
+    float* lds = reinterpret_cast<float*>(smem_raw + 8 * sizeof(double) * (NT / 64));
+    const int tid = threadIdx.x;
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+
+    if (item >= C.ntiles_total) {
+        const int r = item - C.ntiles_total;
+        const int pair = find_pair<true>(C.pairs, C.npairs, r);
+        const PairDesc P = C.pairs[pair];
+        const float* theta = C.theta_tab ? C.theta_tab[pair] : C.theta0;
+        float* rg = reinterpret_cast<float*>(C.ws + C.L.reggrad) + P.param_off;
+        double* rp = reinterpret_cast<double*>(C.ws + C.L.regpart) + P.regpart_off;
+        reg_block<NT>(P, C.consts, theta, rg, P.lambda * 2.0f * P.inv_xr, rp,
+                      r - P.reg_begin, 2, lds, red);
+        return;
+    }
+    const int pair = find_pair<false>(C.pairs, C.npairs, item);
+    const PairDesc P = C.pairs[pair];
+    const float* __restrict__ F = C.fixed_tab ? C.fixed_tab[pair] : C.fixed0;
+    const float* __restrict__ M = C.moving_tab ? C.moving_tab[pair] : C.moving0;
+    const float* __restrict__ theta = C.theta_tab ? C.theta_tab[pair] : C.theta0;
+    const int nx = P.n[0], ny = P.n[1];
+    const int sx = P.sp[0], sy = P.sp[1];
+    const int ncx = P.nc[0];
+    const int WxM = P.win[0], WyM = P.win[2];  // column window stored in win[2]
+    int t = item - P.tile_begin;
+    if (t == 0 && tid == 0) reinterpret_cast<uint32_t*>(C.ws + C.L.flags)[pair] = 0u;
+    const int tx = t % P.ntile[0];
+    const int tyc = t / P.ntile[0];
+    const int x0 = tx * TX;
+    const int ncell_y = (ny - 1) / sy + 1;
+    const int cy_b = tyc * P.col_cells;
+    const int cy_e = min(cy_b + P.col_cells, ncell_y);
+    int cx0, Wx;
+    ctrl_window(x0, min(x0 + TX, nx), sx, &cx0, &Wx);
+    const int cy0 = cy_b, Wy = cy_e - cy_b + 3;
+
+    float* T1 = lds;                     // [2][WyM][TX]
+    float* E = T1 + a4(2 * WyM * TX);    // [NF*2][TX]
+    float* WXT = E + a4(NF * 2 * TX);    // [TX][WxM]
+    float* WYT = WXT + a4(TX * WxM);     // [sy][4]
+    const int lx = tid, x = x0 + lx;
+    const bool act = x < nx;
+    const int xc = min(x, nx - 1), ix = xc / sx;
+    const float* wtx = C.consts + P.wtab_off[0] + (xc - ix * sx) * 4;
+    const float wx0 = wtx[0], wx1 = wtx[1], wx2 = wtx[2], wx3 = wtx[3];
+    for (int i = tid; i < TX * WxM; i += NT) {
+        const int q = i / WxM, k = i % WxM;
+        float w = 0.f;
+        const int xq = x0 + q;
+        if (xq < nx) {
+            const int kk = k - (xq / sx - cx0);
+            if (kk >= 0 && kk < 4) w = C.consts[P.wtab_off[0] + (xq % sx) * 4 + kk];
+        }
+        WXT[i] = w;
+    }
+    for (int i = tid; i < sy * 4; i += NT) WYT[i] = C.consts[P.wtab_off[1] + i];
+    {
+        const long long NC = (long long)ncx * P.nc[1];
+        for (int r = 0; r < 2 * Wy; ++r) {
+            const int c = r / Wy, ky = r % Wy;
+            float v = 0.f;
+            if (act) {
+                const float* th = theta + c * NC + (long long)(cy0 + ky) * ncx + ix;
+                v = wx0 * th[0] + wx1 * th[1] + wx2 * th[2] + wx3 * th[3];
+            }
+            T1[(c * WyM + ky) * TX + lx] = v;
+        }
+    }
+    float shF = 0.f, shW = 0.f;
+    if (SIM == AIR_SIM_NCC) {
+        const int xs = min(x0 + TX / 2, nx - 1);
+        const int ys = min((cy_b * sy + min(cy_e * sy, ny)) / 2, ny - 1);
+        shF = F[(long long)ys * nx + xs];
+        shW = M[(long long)ys * nx + xs];
+    }
+    __syncthreads();
+    float V[2][4];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) V[c][k] = T1[(c * WyM + k) * TX + lx];
+    float acc[NF][2][4];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[f][c][k] = 0.f;
+    int cnt = 0;
+    float m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f;
+    const float snx = P.s[0], sny = P.s[1];
+    const float hx = (float)(nx - 2), hy = (float)(ny - 2);
+    const int nx4 = nx * 4;
+    const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, (uint32_t)(P.nvox * 4));
+    float* part = reinterpret_cast<float*>(C.ws + C.L.part) + P.part_off +
+                  (long long)(item - P.tile_begin) * P.part_stride;
+    auto flush = [&](int kyl) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) E[(f * 2 + c) * TX + lx] = acc[f][c][0];
+        __syncthreads();
+        for (int o = tid; o < NF * 2 * Wx; o += NT) {
+            const int kx = o % Wx, fc = o / Wx;
+            const int q0 = max(0, (cx0 + kx - 3) * sx - x0);
+            const int q1 = min(TX, (cx0 + kx + 1) * sx - x0);
+            float s = 0.f;
+            for (int q = q0; q < q1; ++q) s += WXT[q * WxM + kx] * E[fc * TX + q];
+            part[(fc * WyM + kyl) * WxM + kx] = s;
+        }
+        __syncthreads();
+    };
+    for (int cy = cy_b; cy < cy_e; ++cy) {
+        const int kyl = cy - cy0;
+        const int yb = cy * sy, ye = min(yb + sy, ny);
+        for (int y = yb; y < ye; ++y) {
+            const float4 wy = *reinterpret_cast<const float4*>(WYT + (y - yb) * 4);
+            if (act) {
+                const long long v = (long long)y * nx + x;
+                const float Fv = F[v];
+                float u[2];
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    u[c] = wy.x * V[c][0] + wy.y * V[c][1] + wy.z * V[c][2] + wy.w * V[c][3];
+                const float px = fmaf(u[0], snx, (float)x);
+                const float py = fmaf(u[1], sny, (float)y);
+                const float flx = floorf(px), fly = floorf(py);
+                const float jxf = fminf(flx, hx), jyf = fminf(fly, hy);
+                const float fx = px - jxf, fy = py - jyf;
+                const bool in = (flx >= 0.f) & (fly >= 0.f) & (fx <= 1.f) & (fy <= 1.f);
+                if (in) {
+                    const int jx = (int)jxf, jy = (int)jyf;
+                    const int off = (jy * nx + jx) * 4;
+                    const v2f a0 = load2(rM, off, 0);
+                    const v2f a1 = load2(rM, off, nx4);
+                    const float dy0 = a1.x - a0.x, dy1 = a1.y - a0.y;
+                    const float g0 = a0.x + fy * dy0, g1 = a0.y + fy * dy1;
+                    const float W = g0 + fx * (g1 - g0);
+                    float d[2];
+                    d[0] = g1 - g0;
+                    d[1] = dy0 + fx * (dy1 - dy0);
+                    if (fx == 1.f) d[0] = -W;
+                    if (fy == 1.f) d[1] = -W;
+                    cnt += 1;
+                    if (SIM == AIR_SIM_NCC) {
+                        const float dF = Fv - shF, dW = W - shW;
+                        m1 += dF;
+                        m2 += dW;
+                        m3 += dF * dF;
+                        m4 += dW * dW;
+                        m5 += dF * dW;
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const float gg[3] = {dF * d[c], dW * d[c], d[c]};
+#pragma unroll
+                            for (int f = 0; f < 3; ++f) {
+                                acc[f][c][0] += wy.x * gg[f];
+                                acc[f][c][1] += wy.y * gg[f];
+                                acc[f][c][2] += wy.z * gg[f];
+                                acc[f][c][3] += wy.w * gg[f];
+                            }
+                        }
+                    } else {
+                        const float e = W - Fv;
+                        m1 += e * e;
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const float g = e * d[c];
+                            acc[0][c][0] += wy.x * g;
+                            acc[0][c][1] += wy.y * g;
+                            acc[0][c][2] += wy.z * g;
+                            acc[0][c][3] += wy.w * g;
+                        }
+                    }
+                }
+            }
+        }
+        flush(kyl);
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                acc[f][c][0] = acc[f][c][1];
+                acc[f][c][1] = acc[f][c][2];
+                acc[f][c][2] = acc[f][c][3];
+                acc[f][c][3] = 0.f;
+            }
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            V[c][0] = V[c][1];
+            V[c][1] = V[c][2];
+            V[c][2] = V[c][3];
+            V[c][3] = (kyl + 4 < Wy) ? T1[(c * WyM + kyl + 4) * TX + lx] : 0.f;
+        }
+    }
+    for (int k = Wy - 3; k < Wy; ++k) {
+        flush(k);
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                acc[f][c][0] = acc[f][c][1];
+                acc[f][c][1] = acc[f][c][2];
+                acc[f][c][2] = acc[f][c][3];
+                acc[f][c][3] = 0.f;
+            }
+    }
+    double st[6] = {(double)cnt, (double)m1, (double)m2, (double)m3, (double)m4, (double)m5};
+    block_sum<NT, 6>(st, red);
+    if (tid == 0) {
+        double* slot = reinterpret_cast<double*>(C.ws + C.L.stats) + (long long)item * kStatWords;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) slot[k] = st[k];
+        slot[6] = shF;
+        slot[7] = shW;
+    }
+}
+
+// --------------------------------------------------------------- finalize
+// Global similarity coefficients from the tile statistics (FP64, fixed order),
+// then every control gathers the partials of the tiles whose window holds it.
+struct Coef {
+    double S;      // similarity value
+    double alpha;  // NCC: coefficient of (F - shift_F); MSE: 2 / N'
+    double beta;   // NCC: coefficient of (W - shift_W)
+    double muF, muW;
+    bool degenerate;
+};
+
+template <int NT, int SIM>
+__device__ Coef pair_coef(const PairDesc& P, const double* stats, double* red) {
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int t = threadIdx.x; t < P.ntiles; t += NT) {
+        const double* s = stats + (long long)(P.tile_begin + t) * kStatWords;
+        const double n = s[0];
+        if (SIM == AIR_SIM_NCC) {
+            const double a = s[6], b = s[7];
+            v[0] += n;
+            v[1] += s[1] + n * a;                                   // sum F
+            v[2] += s[2] + n * b;                                   // sum W
+            v[3] += s[3] + 2.0 * a * s[1] + n * a * a;              // sum F^2
+            v[4] += s[4] + 2.0 * b * s[2] + n * b * b;              // sum W^2
+            v[5] += s[5] + a * s[2] + b * s[1] + n * a * b;         // sum F W
+        } else {
+            v[0] += n;
+            v[1] += s[1];
+        }
+    }
+    block_sum<NT, 6>(v, red);
+    Coef k{0.0, 0.0, 0.0, 0.0, 0.0, false};
+    const double N = v[0];
+    if (SIM == AIR_SIM_MSE) {
+        if (N < 1.0) { k.degenerate = true; return k; }
+        k.S = v[1] / N;
+        k.alpha = 2.0 / N;
+        return k;
+    }
+    if (N < 2.0) { k.degenerate = true; return k; }
+    const double muF = v[1] / N, muW = v[2] / N;
+    const double B = v[3] - N * muF * muF;
+    const double Cc = v[4] - N * muW * muW;
+    const double A = v[5] - N * muF * muW;
+    if (!(B > 1e-10 * v[3]) || !(Cc > 1e-10 * v[4])) { k.degenerate = true; return k; }
+    const double sbc = sqrt(B * Cc);
+    const double rho = A / sbc;
+    k.S = -rho;
+    k.alpha = -1.0 / sbc;
+    k.beta = rho / Cc;
+    k.muF = muF;
+    k.muW = muW;
+    return k;
+}
+
+template <int NT>
+__device__ double pair_reg(const PairDesc& P, const double* regpart, double* red) {
+    double v[1] = {0.0};
+    for (int i = threadIdx.x; i < P.nreg; i += NT) v[0] += regpart[P.regpart_off + i];
+    block_sum<NT, 1>(v, red);
+    return v[0] * (double)P.inv_xr;
+}
+
+// scalars[pair]: [0] S, [1] alpha, [2] beta, [3] muF, [4] muW, [5] R, [6] degenerate
+template <int SIM>
+__global__ void __launch_bounds__(kBlock)
+k_pair_coef(const LaunchCtx C) {
+    __shared__ double red[8 * (kBlock / 64)];
+    const int pair = blockIdx.x;
+    const PairDesc P = C.pairs[pair];
+    const Coef k = pair_coef<kBlock, SIM>(P, reinterpret_cast<const double*>(C.ws + C.L.stats), red);
+    const double R = pair_reg<kBlock>(P, reinterpret_cast<const double*>(C.ws + C.L.regpart), red);
+    if (threadIdx.x == 0) {
+        double* out = reinterpret_cast<double*>(C.ws + C.L.scalars) + (long long)pair * 8;
+        out[0] = k.S;
+        out[1] = k.alpha;
+        out[2] = k.beta;
+        out[3] = k.muF;
+        out[4] = k.muW;
+        out[5] = R;
+        out[6] = k.degenerate ? 1.0 : 0.0;
+        out[7] = 0.0;
+        uint32_t fl = k.degenerate ? AIR_FLAG_DEGENERATE : 0u;
+        const double value = k.S + (double)P.lambda * R;
+        if (!isfinite((float)value)) fl |= AIR_FLAG_NONFINITE;
+        if (fl) atomicOr(reinterpret_cast<uint32_t*>(C.ws + C.L.flags) + pair, fl);
+        float* vout = C.values ? C.values + pair : C.value0;
+        *vout = (float)value;
+    }
+}
+
+// Range of tiles (along one axis) whose voxel range meets the support of
+// control j: voxels [(j - 3) sp, (j + 1) sp - 1].
+__device__ inline void tile_range(int j, int sp, int n, int T, int* lo, int* hi) {
+    const int a = max(0, (j - 3) * sp);
+    const int b = min(n - 1, (j + 1) * sp - 1);
+    *lo = a / T;
+    *hi = (b >= a) ? b / T : -1;
+}
+
+template <int TX, int TY, int SIM, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_finalize(const LaunchCtx C) {
+    constexpr int NT = kBlock;
+    constexpr int NF = (SIM == AIR_SIM_NCC) ? 3 : 1;
+    const int pair = blockIdx.y;
+    const PairDesc P = C.pairs[pair];
+    const double* stats = reinterpret_cast<const double*>(C.ws + C.L.stats);
+    const double* sc = reinterpret_cast<const double*>(C.ws + C.L.scalars) + (long long)pair * 8;
+    Coef k;
+    k.S = sc[0];
+    k.alpha = sc[1];
+    k.beta = sc[2];
+    k.muF = sc[3];
+    k.muW = sc[4];
+    k.degenerate = sc[6] != 0.0;
+    uint32_t* flags = reinterpret_cast<uint32_t*>(C.ws + C.L.flags) + pair;
+    const int nctrl = P.nc[0] * P.nc[1] * (DIM == 3 ? P.nc[2] : 1);
+    const int j = blockIdx.x * NT + threadIdx.x;
+    if (j >= nctrl) return;
+    const int jx = j % P.nc[0];
+    const int jy = (j / P.nc[0]) % P.nc[1];
+    const int jz = (DIM == 3) ? j / (P.nc[0] * P.nc[1]) : 0;
+    const float* part = reinterpret_cast<const float*>(C.ws + C.L.part) + P.part_off;
+    const float* rg = reinterpret_cast<const float*>(C.ws + C.L.reggrad) + P.param_off;
+    float* grad = C.grad_tab ? C.grad_tab[pair] : C.grad0;
+    const int WxM = P.win[0], WyM = (DIM == 3) ? P.win[1] : 1, WzM = P.win[2];
+    double g[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) g[c] = 0.0;
+    // column axis: z in 3D, y in 2D
+    const int colax = DIM - 1;
+    const int jc = (DIM == 3) ? jz : jy;
+    const int ncell = (P.n[colax] - 1) / P.sp[colax] + 1;
+    const int tc_lo = max(0, jc - 3) / P.col_cells;
+    const int tc_hi = min(ncell - 1, jc) / P.col_cells;
+    int tx_lo, tx_hi, ty_lo = 0, ty_hi = 0;
+    tile_range(jx, P.sp[0], P.n[0], TX, &tx_lo, &tx_hi);
+    if (DIM == 3) tile_range(jy, P.sp[1], P.n[1], TY, &ty_lo, &ty_hi);
+    if (!k.degenerate) {
+        for (int tc = tc_lo; tc <= tc_hi; ++tc) {
+            const int kcl = jc - tc * P.col_cells;
+            for (int ty = ty_lo; ty <= ty_hi; ++ty) {
+                int kyl = 0;
+                if (DIM == 3) {
+                    int cy0, Wy;
+                    ctrl_window(ty * TY, min(ty * TY + TY, P.n[1]), P.sp[1], &cy0, &Wy);
+                    kyl = jy - cy0;
+                    if (kyl < 0 || kyl >= Wy) continue;
+                }
+                for (int tx = tx_lo; tx <= tx_hi; ++tx) {
+                    const int cells_t = min(P.col_cells, ncell - tc * P.col_cells);
+                    if (kcl >= cells_t + 3) continue;
+                    int cx0, Wx;
+                    ctrl_window(tx * TX, min(tx * TX + TX, P.n[0]), P.sp[0], &cx0, &Wx);
+                    const int kxl = jx - cx0;
+                    if (kxl < 0 || kxl >= Wx) continue;
+                    const int tl = (DIM == 3) ? (tc * P.ntile[1] + ty) * P.ntile[0] + tx
+                                              : tc * P.ntile[0] + tx;
+                    const float* pt = part + (long long)tl * P.part_stride;
+                    double cF = k.alpha, cW = k.beta, c1 = 0.0;
+                    if (SIM == AIR_SIM_NCC) {
+                        const double* s = stats + (long long)(P.tile_begin + tl) * kStatWords;
+                        c1 = k.alpha * (s[6] - k.muF) + k.beta * (s[7] - k.muW);
+                    }
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) {
+                        const long long base = ((long long)kcl * WyM + kyl) * WxM + kxl;
+                        const long long fstride = (long long)DIM * WzM * WyM * WxM;
+                        const long long cstride = (long long)WzM * WyM * WxM;
+                        if (SIM == AIR_SIM_NCC) {
+                            g[c] += cF * pt[c * cstride + base] +
+                                    cW * pt[fstride + c * cstride + base] +
+                                    c1 * pt[2 * fstride + c * cstride + base];
+                        } else {
+                            g[c] += cF * pt[c * cstride + base];
+                        }
+                    }
+                }
+            }
+        }
+    }
+    uint32_t bad = 0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        const float out = (float)(g[c] * (double)P.s[c]) + rg[(long long)c * nctrl + j];
+        grad[(long long)c * nctrl + j] = out;
+        if (!isfinite(out)) bad = 1;
+    }
+    (void)NF;
+    if (bad) atomicOr(flags, AIR_FLAG_NONFINITE);
+}
+
+// --------------------------------------------------------------- launchers
+template <int TX, int TY, int SIM>
+static hipError_t launch3(const LaunchCtx& C, size_t lds, hipStream_t s) {
+    const int nblk = C.ntiles_total + C.nreg_total;
+    hipLaunchKernelGGL((k_fused3<TX, TY, SIM>), dim3(nblk), dim3(TX * TY), lds, s, C);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return hipSuccess;
+}
+
+template <int TX, int TY, int SIM, int DIM>
+static hipError_t launch_fin(const LaunchCtx& C, int max_ctrl, hipStream_t s) {
+    hipLaunchKernelGGL((k_pair_coef<SIM>), dim3(C.npairs), dim3(kBlock), 0, s, C);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dim3 grid(cdiv(max_ctrl, kBlock), C.npairs);
+    hipLaunchKernelGGL((k_finalize<TX, TY, SIM, DIM>), grid, dim3(kBlock), 0, s, C);
+    return hipGetLastError();
+}
+
+// Tile configurations (id -> TX, TY). Column cells come from the plan.
+hipError_t launch_bspline(const LaunchCtx& C, int cfg, size_t lds, int max_ctrl,
+                          hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    hipError_t e = hipSuccess;
+    if (ev0) (void)hipEventRecord(ev0, s);
+    if (C.dim == 3) {
+        const bool ncc = C.sim == AIR_SIM_NCC;
+        switch (cfg) {
+            case 0: e = ncc ? launch3<32, 8, 1>(C, lds, s) : launch3<32, 8, 0>(C, lds, s); break;
+            case 1: e = ncc ? launch3<64, 4, 1>(C, lds, s) : launch3<64, 4, 0>(C, lds, s); break;
+            case 2: e = ncc ? launch3<16, 16, 1>(C, lds, s) : launch3<16, 16, 0>(C, lds, s); break;
+            default: return hipErrorInvalidValue;
+        }
+        if (e != hipSuccess) return e;
+        if (ev1) (void)hipEventRecord(ev1, s);
+        switch (cfg) {
+            case 0: return ncc ? launch_fin<32, 8, 1, 3>(C, max_ctrl, s) : launch_fin<32, 8, 0, 3>(C, max_ctrl, s);
+            case 1: return ncc ? launch_fin<64, 4, 1, 3>(C, max_ctrl, s) : launch_fin<64, 4, 0, 3>(C, max_ctrl, s);
+            default: return ncc ? launch_fin<16, 16, 1, 3>(C, max_ctrl, s) : launch_fin<16, 16, 0, 3>(C, max_ctrl, s);
+        }
+    }
+    const int nblk = C.ntiles_total + C.nreg_total;
+    if (C.sim == AIR_SIM_NCC)
+        hipLaunchKernelGGL((k_fused2<64, 1>), dim3(nblk), dim3(64), lds, s, C);
+    else
+        hipLaunchKernelGGL((k_fused2<64, 0>), dim3(nblk), dim3(64), lds, s, C);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev1) (void)hipEventRecord(ev1, s);
+    return C.sim == AIR_SIM_NCC ? launch_fin<64, 1, 1, 2>(C, max_ctrl, s)
+                                : launch_fin<64, 1, 0, 2>(C, max_ctrl, s);
+}
+
+// Regulariser only (B-spline): Gram-form blocks of one pair, unscaled output.
+template <int NT>
+__global__ void __launch_bounds__(NT)
+k_reg_only(const PairDesc* pairs, int pair, const float* consts, const float* theta,
+           float* grad_out, double* regpart, int dim) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* red = reinterpret_cast<double*>(smem_raw);
+    float* lds = reinterpret_cast<float*>(smem_raw + 8 * sizeof(double) * (NT / 64));
+    const PairDesc P = pairs[pair];
+    reg_block<NT>(P, consts, theta, grad_out, 2.0f * P.inv_xr, regpart, blockIdx.x, dim,
+                  lds, red);
+}
+
+__global__ void k_reg_value(const PairDesc* pairs, int pair, const double* regpart,
+                            float* value) {
+    __shared__ double red[8 * (kBlock / 64)];
+    const PairDesc P = pairs[pair];
+    double v[1] = {0.0};
+    for (int i = threadIdx.x; i < P.nreg; i += kBlock) v[0] += regpart[i];
+    block_sum<kBlock, 1>(v, red);
+    if (threadIdx.x == 0) *value = (float)(v[0] * (double)P.inv_xr);
+}
+
+hipError_t launch_reg_bspline(const PairDesc* dpairs, const PairDesc& hp, int pair,
+                              const float* consts, const float* theta, float* grad_out,
+                              double* regpart, float* value, int dim, size_t lds,
+                              hipStream_t s) {
+    hipLaunchKernelGGL((k_reg_only<kBlock>), dim3(hp.nreg), dim3(kBlock), lds, s, dpairs, pair,
+                       consts, theta, grad_out, regpart, dim);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reg_value, dim3(1), dim3(kBlock), 0, s, dpairs, pair, regpart, value);
+    return hipGetLastError();
+}
+
+}  // namespace air

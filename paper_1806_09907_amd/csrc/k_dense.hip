@@ -1,0 +1,553 @@
+// Objective + gradient for the dense (non-parametric) transform, u = theta
+// (Sec. III-C "Non-linear/dense"). The per-voxel gradient needs the global
+// similarity coefficients (MSE: 2/N' over the masked voxels; NCC: the
+// Pearson coefficients), so the evaluation takes three passes:
+//   pre   MSE: count masked voxels (reads theta only); NCC: forward moments;
+//   coef  one block per pair turns the block partials into coefficients;
+//   main  per voxel: sample, similarity adjoint, diffusion stencil adjoint
+//         (Sec. II-A eq. diffusion_regularizer, forward differences over
+//         X_R), writes the gradient and the value partials;
+//   fin   one block per pair writes the objective value.
+// Lanes cover 64 x 4 voxels in (x, y); each lane walks a chunk of z and keeps
+// u at z-1, z, z+1 in registers.
+#include "device_common.h"
+
+namespace air {
+
+constexpr int DTX = 64, DTY = 4;
+
+struct DenseTile {
+    int x, y, z0, z1;
+    bool act;
+};
+
+__device__ inline DenseTile dense_tile(const PairDesc& P, int blk, int zc, int dim) {
+    const int nbx = cdiv(P.n[0], DTX), nby = cdiv(P.n[1], DTY);
+    const int bx = blk % nbx;
+    const int rest = blk / nbx;
+    const int by = rest % nby;
+    const int bz = rest / nby;
+    DenseTile T;
+    T.x = bx * DTX + (threadIdx.x % DTX);
+    T.y = by * DTY + (threadIdx.x / DTX);
+    if (dim == 3) {
+        T.z0 = bz * zc;
+        T.z1 = min(T.z0 + zc, P.n[2]);
+    } else {
+        T.z0 = 0;
+        T.z1 = 1;
+    }
+    T.act = (T.x < P.n[0]) && (T.y < P.n[1]);
+    return T;
+}
+
+// Zero-padded multilinear sample at p (voxel units) with derivative; also
+// reports whether p lies inside the volume. Used where speed is secondary.
+template <int DIM>
+__device__ inline float sample_general(const float* __restrict__ M, const int* n,
+                                       const float* p, bool* inside, float* dW) {
+    float f[3];
+    int j[3];
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const float pa = fminf(fmaxf(p[a], -1e9f), 1e9f);
+        if (!(p[a] >= 0.f && p[a] <= (float)(n[a] - 1))) in = false;
+        const float fl = floorf(pa);
+        j[a] = (int)fl;
+        f[a] = pa - fl;
+    }
+    *inside = in;
+    float W = 0.f;
+    float d[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < (1 << DIM); ++c) {
+        int q[3] = {0, 0, 0};
+        bool ok = true;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            q[a] = j[a] + ((c >> a) & 1);
+            if (q[a] < 0 || q[a] > n[a] - 1) ok = false;
+        }
+        float val = 0.f;
+        if (ok) {
+            long long idx = q[0] + (long long)n[0] * (q[1] + (DIM == 3 ? (long long)n[1] * q[2] : 0));
+            val = M[idx];
+        }
+        float w = 1.f;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) w *= ((c >> a) & 1) ? f[a] : 1.f - f[a];
+        W += w * val;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            float wa = ((c >> a) & 1) ? 1.f : -1.f;
+#pragma unroll
+            for (int b = 0; b < DIM; ++b)
+                if (b != a) wa *= ((c >> b) & 1) ? f[b] : 1.f - f[b];
+            d[a] += wa * val;
+        }
+    }
+    if (dW) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) dW[a] = d[a];
+    }
+    return W;
+}
+
+template <int DIM, int SIM>
+__global__ void __launch_bounds__(DTX* DTY)
+k_dense_pre(const LaunchCtx C, int zc) {
+    constexpr int NT = DTX * DTY;
+    __shared__ double red[8 * (NT / 64)];
+    const int pair = blockIdx.y;
+    const PairDesc P = C.pairs[pair];
+    if ((int)blockIdx.x >= P.dense_nblk) return;
+    const float* __restrict__ F = C.fixed_tab ? C.fixed_tab[pair] : C.fixed0;
+    const float* __restrict__ M = C.moving_tab ? C.moving_tab[pair] : C.moving0;
+    const float* __restrict__ th = C.theta_tab ? C.theta_tab[pair] : C.theta0;
+    const DenseTile T = dense_tile(P, blockIdx.x, zc, DIM);
+    const long long N = P.nvox;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (T.act) {
+        for (int z = T.z0; z < T.z1; ++z) {
+            const long long vi = ((long long)z * P.n[1] + T.y) * P.n[0] + T.x;
+            float p[3];
+            const int idx[3] = {T.x, T.y, z};
+            bool in = true;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                p[a] = fmaf(th[a * N + vi], P.s[a], (float)idx[a]);
+                if (!(p[a] >= 0.f && p[a] <= (float)(P.n[a] - 1))) in = false;
+            }
+            if (SIM == AIR_SIM_MSE) {
+                if (in) v[0] += 1.0;
+            } else if (in) {
+                bool in2;
+                const float W = sample_general<DIM>(M, P.n, p, &in2, nullptr);
+                const double f = F[vi], w = W;
+                v[0] += 1.0;
+                v[1] += f;
+                v[2] += w;
+                v[3] += f * f;
+                v[4] += w * w;
+                v[5] += f * w;
+            }
+        }
+    }
+    block_sum<NT, 6>(v, red);
+    if (threadIdx.x == 0) {
+        double* slot = reinterpret_cast<double*>(C.ws + C.L.dense_stats) +
+                       (long long)(P.dense_blk_off + blockIdx.x) * kStatWords;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) slot[k] = v[k];
+    }
+}
+
+// scalars[pair]: [0] alpha, [1] beta, [2] muF, [3] muW, [4] S, [5] N, [6] degenerate
+template <int SIM>
+__global__ void __launch_bounds__(kBlock)
+k_dense_coef(const LaunchCtx C) {
+    __shared__ double red[8 * (kBlock / 64)];
+    const int pair = blockIdx.x;
+    const PairDesc P = C.pairs[pair];
+    const double* st = reinterpret_cast<const double*>(C.ws + C.L.dense_stats);
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < P.dense_nblk; b += kBlock) {
+        const double* s = st + (long long)(P.dense_blk_off + b) * kStatWords;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[k] += s[k];
+    }
+    block_sum<kBlock, 6>(v, red);
+    if (threadIdx.x != 0) return;
+    double* out = reinterpret_cast<double*>(C.ws + C.L.scalars) + (long long)pair * 8;
+    const double N = v[0];
+    for (int k = 0; k < 8; ++k) out[k] = 0.0;
+    out[5] = N;
+    if (SIM == AIR_SIM_MSE) {
+        if (N < 1.0) { out[6] = 1.0; return; }
+        out[0] = 2.0 / N;
+        return;
+    }
+    if (N < 2.0) { out[6] = 1.0; return; }
+    const double muF = v[1] / N, muW = v[2] / N;
+    const double B = v[3] - N * muF * muF, Cc = v[4] - N * muW * muW;
+    const double A = v[5] - N * muF * muW;
+    if (!(B > 1e-10 * v[3]) || !(Cc > 1e-10 * v[4])) { out[6] = 1.0; return; }
+    const double sbc = sqrt(B * Cc), rho = A / sbc;
+    out[0] = -1.0 / sbc;
+    out[1] = rho / Cc;
+    out[2] = muF;
+    out[3] = muW;
+    out[4] = -rho;
+}
+
+template <int DIM, int SIM>
+__global__ void __launch_bounds__(DTX* DTY)
+k_dense_main(const LaunchCtx C, int zc, int reg_only, float* reg_grad_out) {
+    constexpr int NT = DTX * DTY;
+    __shared__ double red[8 * (NT / 64)];
+    const int pair = blockIdx.y;
+    const PairDesc P = C.pairs[pair];
+    if ((int)blockIdx.x >= P.dense_nblk) return;
+    const float* __restrict__ F = C.fixed_tab ? C.fixed_tab[pair] : C.fixed0;
+    const float* __restrict__ M = C.moving_tab ? C.moving_tab[pair] : C.moving0;
+    const float* __restrict__ th = C.theta_tab ? C.theta_tab[pair] : C.theta0;
+    float* __restrict__ grad = reg_only ? reg_grad_out
+                                        : (C.grad_tab ? C.grad_tab[pair] : C.grad0);
+    const DenseTile T = dense_tile(P, blockIdx.x, zc, DIM);
+    const long long N = P.nvox;
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    const long long sy = nx, sz = (long long)nx * ny;
+    double a = 0, b = 0, cc = 0, dd = 0;
+    float beta = 0.f, muF = 0.f, muW = 0.f;
+    bool degenerate = true;
+    if (!reg_only) {
+        const double* sc = reinterpret_cast<const double*>(C.ws + C.L.scalars) + (long long)pair * 8;
+        a = sc[0];
+        b = sc[1];
+        cc = sc[2];
+        dd = sc[3];
+        degenerate = sc[6] != 0.0;
+        beta = (float)b;
+        muF = (float)cc;
+        muW = (float)dd;
+    }
+    const float alpha = (float)a;
+    const float rscale = (reg_only ? 1.0f : P.lambda) * 2.0f * P.inv_xr;
+    double acc[2] = {0.0, 0.0};   // [0] MSE sum of squares, [1] regulariser sum
+    if (T.act) {
+        const int x = T.x, y = T.y;
+        const bool inx = x <= nx - 2, iny = y <= ny - 2;
+        float um[3], u0[3], up[3];
+        long long vi = ((long long)T.z0 * ny + y) * nx + x;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            u0[c] = th[c * N + vi];
+            um[c] = (DIM == 3 && T.z0 > 0) ? th[c * N + vi - sz] : 0.f;
+        }
+        for (int z = T.z0; z < T.z1; ++z, vi += sz) {
+            const bool has_zp = DIM == 3 && z + 1 < nz;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) up[c] = has_zp ? th[c * N + vi + sz] : 0.f;
+            // regulariser adjoint: sum_a [x-e_a in X_R](u - u_-a) - [x in X_R](u_+a - u)
+            const bool inz = DIM == 2 || z <= nz - 2;
+            const bool in_r = inx && iny && inz;
+            const bool prev_x = x >= 1 && iny && inz;
+            const bool prev_y = y >= 1 && inx && inz;
+            const bool prev_z = DIM == 3 && z >= 1 && inx && iny;
+            float gr[3];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                const float* tc = th + c * N;
+                const float uxp = (x + 1 < nx) ? tc[vi + 1] : 0.f;
+                const float uxm = (x >= 1) ? tc[vi - 1] : 0.f;
+                const float uyp = (y + 1 < ny) ? tc[vi + sy] : 0.f;
+                const float uym = (y >= 1) ? tc[vi - sy] : 0.f;
+                float g = 0.f;
+                if (in_r) {
+                    const float dx = uxp - u0[c], dy = uyp - u0[c];
+                    g -= dx + dy;
+                    float r2 = dx * dx + dy * dy;
+                    if (DIM == 3) {
+                        const float dz = up[c] - u0[c];
+                        g -= dz;
+                        r2 += dz * dz;
+                    }
+                    acc[1] += r2;
+                }
+                if (prev_x) g += u0[c] - uxm;
+                if (prev_y) g += u0[c] - uym;
+                if (prev_z) g += u0[c] - um[c];
+                gr[c] = rscale * g;
+            }
+            float gi[3] = {0.f, 0.f, 0.f};
+            if (!reg_only) {
+                float p[3];
+                const int idx[3] = {x, y, z};
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) p[c] = fmaf(u0[c], P.s[c], (float)idx[c]);
+                bool in;
+                float dW[3];
+                const float W = sample_general<DIM>(M, P.n, p, &in, dW);
+                if (in) {
+                    const float Fv = F[vi];
+                    float e;
+                    if (SIM == AIR_SIM_MSE) {
+                        const float r = W - Fv;
+                        acc[0] += (double)r * (double)r;
+                        e = alpha * r;
+                    } else {
+                        e = alpha * (Fv - muF) + beta * (W - muW);
+                    }
+                    if (degenerate) e = 0.f;
+                    // sample on the last voxel: right-sided cell with zero padding
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) gi[c] = e * dW[c] * P.s[c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                grad[c * N + vi] = gi[c] + gr[c];
+                um[c] = u0[c];
+                u0[c] = up[c];
+            }
+        }
+    }
+    block_sum<NT, 2>(acc, red);
+    if (threadIdx.x == 0) {
+        double* slot = reinterpret_cast<double*>(C.ws + C.L.dense_stats) +
+                       (long long)(P.dense_blk_off + blockIdx.x) * kStatWords;
+        slot[0] = acc[0];
+        slot[1] = acc[1];
+    }
+}
+
+template <int SIM>
+__global__ void __launch_bounds__(kBlock)
+k_dense_fin(const LaunchCtx C, int reg_only, float* reg_value_out) {
+    __shared__ double red[8 * (kBlock / 64)];
+    const int pair = blockIdx.x;
+    const PairDesc P = C.pairs[pair];
+    const double* st = reinterpret_cast<const double*>(C.ws + C.L.dense_stats);
+    double v[2] = {0, 0};
+    for (int b = threadIdx.x; b < P.dense_nblk; b += kBlock) {
+        const double* s = st + (long long)(P.dense_blk_off + b) * kStatWords;
+        v[0] += s[0];
+        v[1] += s[1];
+    }
+    block_sum<kBlock, 2>(v, red);
+    if (threadIdx.x != 0) return;
+    const double R = v[1] * (double)P.inv_xr;
+    if (reg_only) {
+        *reg_value_out = (float)R;
+        return;
+    }
+    const double* sc = reinterpret_cast<const double*>(C.ws + C.L.scalars) + (long long)pair * 8;
+    const bool degenerate = sc[6] != 0.0;
+    double S = 0.0;
+    if (!degenerate) S = (SIM == AIR_SIM_MSE) ? v[0] / sc[5] : sc[4];
+    const double value = S + (double)P.lambda * R;
+    float* vout = C.values ? C.values + pair : C.value0;
+    *vout = (float)value;
+    uint32_t fl = degenerate ? AIR_FLAG_DEGENERATE : 0u;
+    if (!isfinite((float)value)) fl |= AIR_FLAG_NONFINITE;
+    reinterpret_cast<uint32_t*>(C.ws + C.L.flags)[pair] = fl;
+}
+
+template <int DIM, int SIM>
+static hipError_t dense_run(const LaunchCtx& C, int zc, int max_blk, hipStream_t s,
+                            hipEvent_t ev0, hipEvent_t ev1) {
+    dim3 grid(max_blk, C.npairs);
+    hipLaunchKernelGGL((k_dense_pre<DIM, SIM>), grid, dim3(DTX * DTY), 0, s, C, zc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_dense_coef<SIM>), dim3(C.npairs), dim3(kBlock), 0, s, C);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev0) (void)hipEventRecord(ev0, s);
+    hipLaunchKernelGGL((k_dense_main<DIM, SIM>), grid, dim3(DTX * DTY), 0, s, C, zc, 0,
+                       (float*)nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev1) (void)hipEventRecord(ev1, s);
+    hipLaunchKernelGGL((k_dense_fin<SIM>), dim3(C.npairs), dim3(kBlock), 0, s, C, 0,
+                       (float*)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense(const LaunchCtx& C, int zc, int max_blk, hipStream_t s, hipEvent_t ev0,
+                        hipEvent_t ev1) {
+    if (C.dim == 3)
+        return C.sim == AIR_SIM_NCC ? dense_run<3, 1>(C, zc, max_blk, s, ev0, ev1)
+                                    : dense_run<3, 0>(C, zc, max_blk, s, ev0, ev1);
+    return C.sim == AIR_SIM_NCC ? dense_run<2, 1>(C, zc, max_blk, s, ev0, ev1)
+                                : dense_run<2, 0>(C, zc, max_blk, s, ev0, ev1);
+}
+
+// Regulariser of a dense field for one pair (context holds that pair only).
+hipError_t launch_reg_dense(const LaunchCtx& C, int pair_blocks, int zc, float* grad_out,
+                            float* value_out, hipStream_t s) {
+    dim3 grid(pair_blocks, 1);
+    if (C.dim == 3)
+        hipLaunchKernelGGL((k_dense_main<3, 0>), grid, dim3(DTX * DTY), 0, s, C, zc, 1, grad_out);
+    else
+        hipLaunchKernelGGL((k_dense_main<2, 0>), grid, dim3(DTX * DTY), 0, s, C, zc, 1, grad_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_dense_fin<0>), dim3(1), dim3(kBlock), 0, s, C, 1, value_out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ warp
+template <int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_warp(const PairDesc* pairs, int pair, const float* consts, const float* __restrict__ M,
+       const float* __restrict__ th, float* __restrict__ W, uint8_t* __restrict__ mask,
+       int transform) {
+    const PairDesc P = pairs[pair];
+    const long long N = P.nvox;
+    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < N;
+         v += (long long)gridDim.x * kBlock) {
+        const int x = (int)(v % P.n[0]);
+        const int y = (int)((v / P.n[0]) % P.n[1]);
+        const int z = (DIM == 3) ? (int)(v / ((long long)P.n[0] * P.n[1])) : 0;
+        const int idx[3] = {x, y, z};
+        float u[3] = {0.f, 0.f, 0.f};
+        if (transform == AIR_TF_DENSE) {
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) u[c] = th[c * N + v];
+        } else {
+            int i0[3];
+            const float* w[3];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                i0[a] = idx[a] / P.sp[a];
+                w[a] = consts + P.wtab_off[a] + (idx[a] - i0[a] * P.sp[a]) * 4;
+            }
+            const long long NC = (long long)P.nc[0] * P.nc[1] * P.nc[2];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                float acc = 0.f;
+                for (int kz = 0; kz < (DIM == 3 ? 4 : 1); ++kz) {
+                    const float wz = (DIM == 3) ? w[2][kz] : 1.f;
+                    const int jz = (DIM == 3) ? i0[2] + kz : 0;
+                    for (int ky = 0; ky < 4; ++ky) {
+                        const float* row = th + c * NC +
+                                           ((long long)jz * P.nc[1] + i0[1] + ky) * P.nc[0] + i0[0];
+                        const float wyz = wz * w[1][ky];
+                        acc += wyz * (w[0][0] * row[0] + w[0][1] * row[1] + w[0][2] * row[2] +
+                                      w[0][3] * row[3]);
+                    }
+                }
+                u[c] = acc;
+            }
+        }
+        float p[3];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) p[a] = fmaf(u[a], P.s[a], (float)idx[a]);
+        bool in;
+        const float val = sample_general<DIM>(M, P.n, p, &in, nullptr);
+        W[v] = val;
+        if (mask) mask[v] = in ? 1 : 0;
+    }
+}
+
+hipError_t launch_warp(const PairDesc* dpairs, int pair, const PairDesc& hp, const float* consts,
+                       const float* M, const float* th, float* W, uint8_t* mask, int dim,
+                       int transform, hipStream_t s) {
+    const long long nb = (hp.nvox + kBlock - 1) / kBlock;
+    const int grid = (int)(nb < 65536 ? nb : 65536);
+    if (dim == 3)
+        hipLaunchKernelGGL((k_warp<3>), dim3(grid), dim3(kBlock), 0, s, dpairs, pair, consts, M, th,
+                           W, mask, transform);
+    else
+        hipLaunchKernelGGL((k_warp<2>), dim3(grid), dim3(kBlock), 0, s, dpairs, pair, consts, M, th,
+                           W, mask, transform);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ similarity
+__global__ void __launch_bounds__(kBlock)
+k_sim_stats(const float* __restrict__ F, const float* __restrict__ W,
+            const uint8_t* __restrict__ mask, long long N, double* slots) {
+    __shared__ double red[8 * (kBlock / 64)];
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < N;
+         i += (long long)gridDim.x * kBlock) {
+        if (mask && !mask[i]) continue;
+        const double f = F[i], w = W[i];
+        v[0] += 1.0;
+        v[1] += f;
+        v[2] += w;
+        v[3] += f * f;
+        v[4] += w * w;
+        v[5] += f * w;
+        v[6] += (w - f) * (w - f);
+    }
+    block_sum<kBlock, 7>(v, red);
+    if (threadIdx.x == 0) {
+        double* s = slots + (long long)blockIdx.x * kStatWords;
+        for (int k = 0; k < 7; ++k) s[k] = v[k];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_sim_fin(const double* slots, int nblk, int sim, float* value, uint32_t* flag) {
+    __shared__ double red[8 * (kBlock / 64)];
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblk; b += kBlock)
+        for (int k = 0; k < 7; ++k) v[k] += slots[(long long)b * kStatWords + k];
+    block_sum<kBlock, 7>(v, red);
+    if (threadIdx.x != 0) return;
+    const double N = v[0];
+    double S = 0.0;
+    uint32_t fl = 0;
+    if (sim == AIR_SIM_MSE) {
+        if (N < 1.0) fl |= AIR_FLAG_DEGENERATE; else S = v[6] / N;
+    } else {
+        if (N < 2.0) {
+            fl |= AIR_FLAG_DEGENERATE;
+        } else {
+            const double muF = v[1] / N, muW = v[2] / N;
+            const double B = v[3] - N * muF * muF, Cc = v[4] - N * muW * muW;
+            const double A = v[5] - N * muF * muW;
+            if (!(B > 1e-10 * v[3]) || !(Cc > 1e-10 * v[4])) fl |= AIR_FLAG_DEGENERATE;
+            else S = -A / sqrt(B * Cc);
+        }
+    }
+    if (!isfinite((float)S)) fl |= AIR_FLAG_NONFINITE;
+    *value = (float)S;
+    if (flag) *flag = fl;
+}
+
+hipError_t launch_similarity(const float* F, const float* W, const uint8_t* mask, long long N,
+                             int sim, double* slots, int nslots, float* value, uint32_t* flag,
+                             hipStream_t s) {
+    long long nb = (N + kBlock - 1) / kBlock;
+    const int grid = (int)(nb < nslots ? nb : nslots);
+    hipLaunchKernelGGL(k_sim_stats, dim3(grid), dim3(kBlock), 0, s, F, W, mask, N, slots);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sim_fin, dim3(1), dim3(kBlock), 0, s, slots, grid, sim, value, flag);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Adam, scale
+__global__ void __launch_bounds__(kBlock)
+k_adam(float* __restrict__ th, const float* __restrict__ g, float* __restrict__ m,
+       float* __restrict__ v, long long n, float lr_bc1, float b1, float b2, float inv_sqrt_bc2,
+       float eps) {
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kBlock) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        th[i] -= lr_bc1 * mi / (sqrtf(vi) * inv_sqrt_bc2 + eps);
+    }
+}
+
+hipError_t launch_adam(float* th, const float* g, float* m, float* v, long long n, float lr_bc1,
+                       float b1, float b2, float inv_sqrt_bc2, float eps, hipStream_t s) {
+    long long nb = (n + kBlock - 1) / kBlock;
+    const int grid = (int)(nb < 16384 ? nb : 16384);
+    hipLaunchKernelGGL(k_adam, dim3(grid), dim3(kBlock), 0, s, th, g, m, v, n, lr_bc1, b1, b2,
+                       inv_sqrt_bc2, eps);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_scale(float* __restrict__ x, const float* __restrict__ sc, long long n) {
+    const float s = *sc;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kBlock)
+        x[i] *= s;
+}
+
+hipError_t launch_scale(float* x, const float* s, long long n, hipStream_t st) {
+    long long nb = (n + kBlock - 1) / kBlock;
+    const int grid = (int)(nb < 16384 ? nb : 16384);
+    hipLaunchKernelGGL(k_scale, dim3(grid), dim3(kBlock), 0, st, x, s, n);
+    return hipGetLastError();
+}
+
+}  // namespace air

@@ -1,0 +1,114 @@
+"""Host-side checks of the C-ABI (no GPU needed): the library loads, exports
+every symbol include/airhip.h declares, and rejects bad arguments before any
+device call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1806_09907_amd import _lib
+from paper_1806_09907_amd.api import Problem, Plan, SIM_MSE, SIM_NCC, TF_BSPLINE3, TF_DENSE
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "airhip.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(air_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in _lib.SIGNATURES, f"binding lacks {n}"
+
+
+def P(**kw):
+    kw.setdefault("n", (32, 24, 20))
+    kw.setdefault("spacing", (8, 8, 8))
+    return Problem(**kw)
+
+
+def test_plan_create_and_queries():
+    plan = Plan(P())
+    assert plan.workspace_bytes > 0
+    nc = P().ncontrol()
+    assert plan.param_count(0) == 3 * nc[0] * nc[1] * nc[2]
+    dense = Plan(P(transform=TF_DENSE))
+    assert dense.param_count(0) == 3 * 32 * 24 * 20
+    two = Plan(Problem(n=(64, 64), spacing=(8, 8), similarity=SIM_MSE))
+    assert two.param_count(0) == 2 * 11 * 11
+    for d in (2, 3):
+        cnt = _lib.lib().air_tiling_count(d)
+        assert cnt >= 3
+        for t in range(cnt):
+            plan_t = Plan(P() if d == 3 else Problem(n=(64, 64), spacing=(8, 8)), tiling=t)
+            assert plan_t.tiling == t
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(n=(1, 24, 20)), 2),
+    (dict(spacing=(0, 8, 8)), 2),
+    (dict(spacing=(65, 8, 8)), 2),
+    (dict(similarity=5), 1),
+    (dict(transform=9), 1),
+    (dict(lambda_diff=-1.0), 1),
+    (dict(n=(2048, 2048, 2048)), 2),
+])
+def test_plan_rejects_bad_problems(bad, code):
+    with pytest.raises(_lib.AirError) as e:
+        Plan(P(**bad))
+    assert e.value.status == code
+
+
+def test_plan_rejects_mixed_batches():
+    with pytest.raises(_lib.AirError) as e:
+        Plan([P(), P(similarity=SIM_MSE)])
+    assert e.value.status == 5
+
+
+def test_entry_points_validate_before_launch():
+    L = _lib.lib()
+    plan = Plan(P())
+    h = plan.handle
+    A = 0x1000000  # aligned fake device address, never dereferenced on error paths
+    ws = plan.workspace_bytes
+    # null arguments
+    assert L.air_objective_and_grad(h, None, A, A, A, A, A, ws, None) == 1
+    assert L.air_warp(h, 0, None, A, A, None, None) == 1
+    # pair index
+    assert L.air_warp(h, 3, A, A, A, None, None) == 2
+    # misaligned tensor
+    assert L.air_objective_and_grad(h, A + 4, A, A, A, A, A, ws, None) == 3
+    # workspace too small / missing
+    assert L.air_objective_and_grad(h, A, A, A, A, A, A, ws - 1, None) == 4
+    assert L.air_objective_and_grad(h, A, A, A, A, A, None, ws, None) == 4
+    assert L.air_similarity(h, 0, A, A, None, A, A, 16, None) == 4
+    assert L.air_regulariser(h, 0, A, A, A, A, 16, None) == 4
+    # batched entry needs a batch-sized workspace and 8-byte aligned tables
+    assert L.air_objective_and_grad_batched(h, A + 4, A, A, A, A, A, ws, None) == 3
+    # Adam and scale argument checks
+    assert L.air_adam_step(A, A, A, A, 10, 0.01, 0.9, 0.999, 1e-8, 0, None) == 2
+    assert L.air_adam_step(A, A, A, A, 10, 0.01, 1.5, 0.999, 1e-8, 1, None) == 1
+    assert L.air_scale(A + 8, A, 4, None) == 3
+    assert L.air_scale(None, A, 4, None) == 1
+    assert L.air_get_flags(h, None, None, None) == 1
+
+
+def test_single_pair_entry_rejects_batch_plans():
+    L = _lib.lib()
+    plan = Plan([P(), P(n=(40, 24, 20))])
+    A = 0x1000000
+    assert L.air_objective_and_grad(plan.handle, A, A, A, A, A, A, plan.workspace_bytes, None) == 1
+
+
+def test_strerror_names_every_status():
+    L = _lib.lib()
+    for s in range(9):
+        assert L.air_strerror(s) not in (None, b"unknown status")
