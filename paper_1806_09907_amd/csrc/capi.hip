@@ -30,15 +30,34 @@ hipError_t launch_adam(float* th, const float* g, float* m, float* v, long long 
                        float b1, float b2, float inv_sqrt_bc2, float eps, hipStream_t s);
 hipError_t launch_scale(float* x, const float* s, long long n, hipStream_t st);
 
-// Tile configurations of the fused B-spline kernel: {kernel variant, TX, TY, column cells}.
+// Tile configurations of the fused B-spline kernel: {TX, TY, column cells,
+// minimum waves per SIMD requested from the register allocator (1 = no
+// limit)}. The kernel variant follows from the shape and the spacing: a
+// spacing-8 specialisation for cell-aligned (32 x 8, 16 x 16) tiles, else the
+// generic kernel (which ignores the occupancy request).
 struct TileCfg {
-    int variant, tx, ty, cells;
+    int tx, ty, cells, wpe;
 };
 static const TileCfg kCfg3[] = {
-    {0, 32, 8, 4}, {0, 32, 8, 8}, {0, 32, 8, 16}, {1, 64, 4, 4},
-    {1, 64, 4, 16}, {2, 16, 16, 4}, {2, 16, 16, 16}, {0, 32, 8, 2},
+    {32, 8, 4, 1}, {32, 8, 8, 1}, {32, 8, 16, 1}, {64, 4, 4, 1}, {64, 4, 16, 1},
+    {16, 16, 4, 1}, {16, 16, 16, 1}, {32, 8, 2, 1}, {16, 16, 8, 1}, {16, 16, 2, 1},
+    {32, 8, 4, 3}, {32, 8, 8, 3}, {16, 16, 4, 3}, {16, 16, 8, 3},
+    {32, 8, 4, 4}, {32, 8, 8, 4}, {16, 16, 4, 4}, {16, 16, 8, 4},
 };
-static const TileCfg kCfg2[] = {{0, 64, 1, 2}, {0, 64, 1, 4}, {0, 64, 1, 8}, {0, 64, 1, 16}};
+static const TileCfg kCfg2[] = {{64, 1, 2, 1}, {64, 1, 4, 1}, {64, 1, 8, 1}, {64, 1, 16, 1}};
+
+// kernel variant ids understood by launch_bspline (3D)
+static int variant_of(const TileCfg& c, bool all_s8) {
+    if (c.tx == 32 && c.ty == 8) {
+        if (!all_s8) return 0;
+        return c.wpe >= 4 ? 7 : (c.wpe == 3 ? 5 : 3);
+    }
+    if (c.tx == 16 && c.ty == 16) {
+        if (!all_s8) return 2;
+        return c.wpe >= 4 ? 8 : (c.wpe == 3 ? 6 : 4);
+    }
+    return 1;  // 64 x 4
+}
 constexpr int kNumCfg3 = sizeof(kCfg3) / sizeof(kCfg3[0]);
 constexpr int kNumCfg2 = sizeof(kCfg2) / sizeof(kCfg2[0]);
 constexpr int kDenseZc = 16;
@@ -63,6 +82,7 @@ struct air_plan {
     size_t lds_fused = 0, lds_reg = 0;
     int max_ctrl = 0;
     int max_dense_blk = 0;
+    int variant = 0;
     std::mutex mu;
     DeviceTables dev[kMaxDevices];
     // optional event pairs around the main kernel of each objective launch
@@ -140,6 +160,12 @@ static air_status build_tables(air_plan* P) {
     const bool bs = P->transform == AIR_TF_BSPLINE3;
     const TileCfg cfg = (d == 3) ? kCfg3[P->tiling] : kCfg2[P->tiling];
     const int NF = P->sim == AIR_SIM_NCC ? 3 : 1;
+    bool all_s8 = bs && d == 3;
+    for (int i = 0; i < P->npairs && all_s8; ++i)
+        for (int a = 0; a < 3; ++a)
+            if (P->probs[i].spacing[a] != 8) all_s8 = false;
+    P->variant = (d == 3) ? variant_of(cfg, all_s8) : 0;
+    const bool s8 = P->variant >= 3 && P->variant != 1;
     P->pd.assign(P->npairs, PairDesc{});
     P->consts.clear();
     size_t stats_n = 0, part_n = 0, param_n = 0, regpart_n = 0, dense_n = 0;
@@ -222,7 +248,11 @@ static air_status build_tables(air_plan* P) {
             regpart_n += D.nreg;
             const int NT = cfg.tx * cfg.ty;
             size_t f;
-            if (d == 3) {
+            if (d == 3 && s8) {
+                const int wyc = cfg.ty / 8 + 3, gp = cfg.tx + 4;
+                f = a4(3 * D.win[2] * wyc * cfg.tx) + a4(NF * 3 * cfg.ty * cfg.tx) +
+                    a4(NF * 3 * wyc * gp);
+            } else if (d == 3) {
                 f = a4(3 * D.win[2] * wym * cfg.tx) + a4(NF * 3 * cfg.ty * cfg.tx) +
                     a4(NF * 3 * wym * cfg.tx) + a4(cfg.tx * wxm) + a4(cfg.ty * wym) +
                     a4(4 * D.sp[2]);
@@ -338,8 +368,7 @@ static air_status run_objective(const air_plan* cP, LaunchCtx& C, hipStream_t s)
     }
     hipError_t e;
     if (P->transform == AIR_TF_BSPLINE3) {
-        const int variant = (P->dim == 3) ? kCfg3[P->tiling].variant : 0;
-        e = launch_bspline(C, variant, P->lds_fused, P->max_ctrl, s, e0, e1);
+        e = launch_bspline(C, P->variant, P->lds_fused, P->max_ctrl, s, e0, e1);
     } else {
         e = launch_dense(C, kDenseZc, P->max_dense_blk, s, e0, e1);
     }

@@ -67,16 +67,27 @@ __device__ inline int find_pair(const PairDesc* pairs, int npairs, int item) {
     return lo;
 }
 
-// Blocks are dealt round-robin to the 8 XCDs; remap so that each XCD works
-// on one contiguous range of items (neighbouring tiles share its L2).
-__device__ inline int xcd_remap(int b, int nb) {
+// Blocks are dealt round-robin to the 8 XCDs (block b runs on XCD b % 8).
+// The grid is 8 * (ceil(T/8) + ceil(R/8)) blocks for T tiles and R
+// regulariser blocks: the i-th block of XCD x takes tile x*ceil(T/8) + i while
+// i < ceil(T/8), then regulariser block x*ceil(R/8) + (i - ceil(T/8)). Each
+// XCD works on one contiguous run of tiles (neighbouring tiles share its L2)
+// and every XCD gets the same number of tiles. Returns the tile index, or
+// T + regulariser index, or -1 for an idle block.
+__device__ inline int xcd_item(int b, int T, int R) {
     constexpr int NX = 8;
-    const int q = nb / NX, r = nb % NX;
+    const int tq = (T + NX - 1) / NX, rq = (R + NX - 1) / NX;
     const int x = b % NX, i = b / NX;
-    // XCD x owns items [start(x), start(x) + q + (x < r))
-    const int start = x * q + (x < r ? x : r);
-    const int cnt = q + (x < r ? 1 : 0);
-    return i < cnt ? start + i : b;  // i >= cnt cannot happen for b < nb
+    if (i < tq) {
+        const int t = x * tq + i;
+        return t < T ? t : -1;
+    }
+    const int r = x * rq + (i - tq);
+    return (i - tq < rq && r < R) ? T + r : -1;
+}
+
+__host__ __device__ inline int xcd_grid(int T, int R) {
+    return 8 * ((T + 7) / 8 + (R + 7) / 8);
 }
 
 }  // namespace air

@@ -114,7 +114,8 @@ k_fused3(const LaunchCtx C) {
     double* red = reinterpret_cast<double*>(smem_raw);          // 8 * NT/64 doubles
     float* lds = reinterpret_cast<float*>(smem_raw + 8 * sizeof(double) * (NT / 64));
     const int tid = threadIdx.x;
-    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const int item = xcd_item(blockIdx.x, C.ntiles_total, C.nreg_total);
+    if (item < 0) return;
 
     if (item >= C.ntiles_total) {
         const int r = item - C.ntiles_total;
@@ -274,7 +275,7 @@ k_fused3(const LaunchCtx C) {
             const int q1 = min(TX, (cx0 + kx + 1) * sx - x0);
             float s = 0.f;
             for (int q = q0; q < q1; ++q) s += WXT[q * WxM + kx] * g[q];
-            part[((fc * WzM + kzl) * WyM + ky) * WxM + kx] = s;
+            part[((kzl * WyM + ky) * WxM + kx) * (NF * 3) + fc] = s;
         }
     };
 
@@ -405,6 +406,365 @@ k_fused3(const LaunchCtx C) {
     }
 }
 
+// --------------------------------------------------------------- fused 3D, spacing 8
+// The same computation as k_fused3 for control spacing 8 on every axis with
+// cell-aligned tiles (TX, TY multiples of 8): the cell structure and the
+// cubic weights w_k(r/8) are compile-time, the column loop is unrolled per
+// cell, and the LDS transposes read each staged value once.
+struct W8 {
+    float w[8][4];
+};
+constexpr W8 make_w8() {
+    W8 t{};
+    for (int r = 0; r < 8; ++r) {
+        const double x = r / 8.0;
+        t.w[r][0] = (float)((1 - x) * (1 - x) * (1 - x) / 6.0);
+        t.w[r][1] = (float)((3 * x * x * x - 6 * x * x + 4) / 6.0);
+        t.w[r][2] = (float)((-3 * x * x * x + 3 * x * x + 3 * x + 1) / 6.0);
+        t.w[r][3] = (float)(x * x * x / 6.0);
+    }
+    return t;
+}
+constexpr W8 kW8 = make_w8();
+
+template <int TX, int TY, int SIM, int WPE>
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+k_fused3_s8(const LaunchCtx C) {
+    constexpr int S = 8;
+    constexpr int NT = TX * TY;
+    constexpr int NF = (SIM == AIR_SIM_NCC) ? 3 : 1;
+    constexpr int FC = NF * 3;
+    constexpr int WXC = TX / S + 3, WYC = TY / S + 3;
+    constexpr int GP = TX + 4;  // padded G rows (16-byte aligned, spread over banks)
+    static_assert(TX % S == 0 && TY % S == 0, "cell-aligned tiles");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* red = reinterpret_cast<double*>(smem_raw);
+    float* lds = reinterpret_cast<float*>(smem_raw + 8 * sizeof(double) * (NT / 64));
+    const int tid = threadIdx.x;
+    const int item = xcd_item(blockIdx.x, C.ntiles_total, C.nreg_total);
+    if (item < 0) return;
+
+    if (item >= C.ntiles_total) {
+        const int r = item - C.ntiles_total;
+        const int pair = find_pair<true>(C.pairs, C.npairs, r);
+        const PairDesc P = C.pairs[pair];
+        const float* theta = C.theta_tab ? C.theta_tab[pair] : C.theta0;
+        float* rg = reinterpret_cast<float*>(C.ws + C.L.reggrad) + P.param_off;
+        double* rp = reinterpret_cast<double*>(C.ws + C.L.regpart) + P.regpart_off;
+        reg_block<NT>(P, C.consts, theta, rg, P.lambda * 2.0f * P.inv_xr, rp,
+                      r - P.reg_begin, 3, lds, red);
+        return;
+    }
+    const int pair = find_pair<false>(C.pairs, C.npairs, item);
+    const PairDesc P = C.pairs[pair];
+    const float* __restrict__ F = C.fixed_tab ? C.fixed_tab[pair] : C.fixed0;
+    const float* __restrict__ M = C.moving_tab ? C.moving_tab[pair] : C.moving0;
+    const float* __restrict__ theta = C.theta_tab ? C.theta_tab[pair] : C.theta0;
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    const int ncx = P.nc[0], ncy = P.nc[1];
+    const int WxM = P.win[0], WyM = P.win[1], WzM = P.win[2];
+    int t = item - P.tile_begin;
+    if (t == 0 && tid == 0) reinterpret_cast<uint32_t*>(C.ws + C.L.flags)[pair] = 0u;
+    const int tx = t % P.ntile[0];
+    t /= P.ntile[0];
+    const int ty = t % P.ntile[1];
+    const int tz = t / P.ntile[1];
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int ncell_z = (nz - 1) / S + 1;
+    const int cz_b = tz * P.col_cells;
+    const int cz_e = min(cz_b + P.col_cells, ncell_z);
+    const int cx0 = x0 / S, cy0 = y0 / S;
+    const int Wx = (min(x0 + TX, nx) - 1) / S + 4 - cx0;
+    const int Wy = (min(y0 + TY, ny) - 1) / S + 4 - cy0;
+    const int cz0 = cz_b, Wz = cz_e - cz_b + 3;
+
+    float* T1 = lds;                       // [3][WzM][WYC][TX]
+    float* E = T1 + a4(3 * WzM * WYC * TX);  // [FC][TY][TX]
+    float* G = E + a4(FC * TY * TX);         // [FC][WYC][GP]
+
+    const int lx = tid % TX, ly = tid / TX;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool act = (x < nx) && (y < ny);
+    const int xc = min(x, nx - 1), yc = min(y, ny - 1);
+    const int ix = xc / S, iy = yc / S;
+    float wx[4], wy[4];
+    {
+        const float* a = C.consts + P.wtab_off[0] + (xc - ix * S) * 4;
+        const float* b = C.consts + P.wtab_off[1] + (yc - iy * S) * 4;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            wx[k] = a[k];
+            wy[k] = b[k];
+        }
+    }
+    const int ky0 = iy - cy0;
+    {
+        const long long NC = (long long)ncx * ncy * P.nc[2];
+        for (int r = ly; r < 3 * Wz * Wy; r += TY) {
+            const int c = r / (Wz * Wy);
+            const int rem = r - c * Wz * Wy;
+            const int kz = rem / Wy, ky = rem - kz * Wy;
+            float v = 0.f;
+            if (x < nx) {
+                const float* th = theta + c * NC +
+                                  ((long long)(cz0 + kz) * ncy + (cy0 + ky)) * ncx + ix;
+                v = wx[0] * th[0] + wx[1] * th[1] + wx[2] * th[2] + wx[3] * th[3];
+            }
+            T1[((c * WzM + kz) * WYC + ky) * TX + lx] = v;
+        }
+    }
+    float shF = 0.f, shW = 0.f;
+    if (SIM == AIR_SIM_NCC) {
+        const int xs = min(x0 + TX / 2, nx - 1), ys = min(y0 + TY / 2, ny - 1);
+        const int zs = min((cz_b * S + min(cz_e * S, nz)) / 2, nz - 1);
+        const long long vs = ((long long)zs * ny + ys) * nx + xs;
+        shF = F[vs];
+        shW = M[vs];
+    }
+    __syncthreads();
+
+    auto vcol = [&](int c, int kz) -> float {
+        const float* r = T1 + ((c * WzM + kz) * WYC + ky0) * TX + lx;
+        return wy[0] * r[0] + wy[1] * r[TX] + wy[2] * r[2 * TX] + wy[3] * r[3 * TX];
+    };
+    float V[3][4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) V[c][k] = vcol(c, k);
+    float acc[NF][3][4];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[f][c][k] = 0.f;
+
+    float cnt = 0.f;
+    float m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f;
+    const float snx = P.s[0], sny = P.s[1], snz = P.s[2];
+    const float nxm1 = (float)(nx - 1), nym1 = (float)(ny - 1), nzm1 = (float)(nz - 1);
+    // the sample point lies in [0, n - 1] iff its (non-negative) float bits do
+    const uint32_t limx = __float_as_uint((float)(nx - 1));
+    const uint32_t limy = __float_as_uint((float)(ny - 1));
+    const uint32_t limz = __float_as_uint((float)(nz - 1));
+    const int nx4 = nx * 4, nxy4 = nx * ny * 4;
+    const float xf = (float)x, yf = (float)y;
+    const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, (uint32_t)(P.nvox * 4));
+    float* part = reinterpret_cast<float*>(C.ws + C.L.part) + P.part_off +
+                  (long long)(item - P.tile_begin) * P.part_stride;
+    const float* Fcol = F + (long long)yc * nx + xc;
+    const long long nxy = (long long)nx * ny;
+
+    auto flush = [&](int kzl) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) E[((f * 3 + c) * TY + ly) * TX + lx] = acc[f][c][0];
+        __syncthreads();
+        // y: task (fc, lane column q) -> WYC outputs
+        for (int task = tid; task < FC * TX; task += NT) {
+            const int q = task % TX, fc = task / TX;
+            float o[WYC];
+#pragma unroll
+            for (int k = 0; k < WYC; ++k) o[k] = 0.f;
+#pragma unroll
+            for (int r = 0; r < TY; ++r) {
+                const float e = E[(fc * TY + r) * TX + q];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) o[r / S + k] += kW8.w[r % S][k] * e;
+            }
+#pragma unroll
+            for (int k = 0; k < WYC; ++k) G[(fc * WYC + k) * GP + q] = o[k];
+        }
+        __syncthreads();
+        // x: task (fc, ky) -> Wx outputs of one partial row
+        for (int task = tid; task < FC * Wy; task += NT) {
+            const int ky = task % Wy, fc = task / Wy;
+            const float* g = G + (fc * WYC + ky) * GP;
+            float o[WXC];
+#pragma unroll
+            for (int k = 0; k < WXC; ++k) o[k] = 0.f;
+#pragma unroll
+            for (int q4 = 0; q4 < TX; q4 += 4) {
+                const float4 gv = *reinterpret_cast<const float4*>(g + q4);
+                const float gg[4] = {gv.x, gv.y, gv.z, gv.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int q = q4 + i;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) o[q / S + k] += kW8.w[q % S][k] * gg[i];
+                }
+            }
+            float* dst = part + ((long long)(kzl * WyM + ky) * WxM) * FC + fc;
+#pragma unroll
+            for (int k = 0; k < WXC; ++k)
+                if (k < Wx) dst[k * FC] = o[k];
+        }
+    };
+
+    for (int cz = cz_b; cz < cz_e; ++cz) {
+        const int kzl = cz - cz0;
+        // Two-stage pipeline over the cell's S layers: stage 1 of layer r + 1
+        // (sample point, cell, its four gathers) is issued before stage 2 of
+        // layer r (interpolation, statistics, adjoint), so two layers of
+        // gathers are in flight.
+        struct Prep {
+            v2f a00, a10, a01, a11;
+            float fx, fy, fz, m, Fv;
+            bool ex, ey, ez;
+        };
+        auto prep = [&](int r, float dep) -> Prep {
+            // Branch-free: the sample point is clamped into the volume so every
+            // load is in range; m = 1 inside the mask, 0 outside (or for
+            // lanes / layers past the volume) scales every contribution.
+            const int z = cz * S + r;
+            Prep q;
+            q.Fv = __builtin_nontemporal_load(Fcol + (long long)min(z, nz - 1) * nxy);
+            float w0 = kW8.w[r][0], w1 = kW8.w[r][1], w2 = kW8.w[r][2], w3 = kW8.w[r][3];
+            float sx_ = snx, sy_ = sny, sz_ = snz;
+            // every uniform input of this stage passes through an empty asm that
+            // also reads `dep` (produced by the previous layer's stage 2), so
+            // neither the arithmetic nor the gathers of this layer can be
+            // hoisted more than one layer ahead of their use
+            asm volatile("" : "+s"(w0), "+s"(w1), "+s"(w2), "+s"(w3), "+s"(sx_), "+s"(sy_),
+                              "+s"(sz_) : "v"(dep));
+            float u[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                u[c] = w0 * V[c][0] + w1 * V[c][1] + w2 * V[c][2] + w3 * V[c][3];
+            const float px = fmaf(u[0], sx_, xf);
+            const float py = fmaf(u[1], sy_, yf);
+            const float pz = fmaf(u[2], sz_, (float)z);
+            const bool in = act && z < nz && (__float_as_uint(px) <= limx) &&
+                            (__float_as_uint(py) <= limy) && (__float_as_uint(pz) <= limz);
+            q.m = in ? 1.f : 0.f;
+            const float qx = __builtin_amdgcn_fmed3f(px, 0.f, nxm1);
+            const float qy = __builtin_amdgcn_fmed3f(py, 0.f, nym1);
+            const float qz = __builtin_amdgcn_fmed3f(pz, 0.f, nzm1);
+            // q >= 0, so truncation is floor; the last voxel uses the cell
+            // [n-2, n-1] with f = 1 and a right-sided (zero-padded) derivative
+            const int tx_ = (int)qx, ty_ = (int)qy, tz_ = (int)qz;
+            q.ex = tx_ == nx - 1;
+            q.ey = ty_ == ny - 1;
+            q.ez = tz_ == nz - 1;
+            const int jx = min(tx_, nx - 2), jy = min(ty_, ny - 2), jz = min(tz_, nz - 2);
+            q.fx = qx - (float)jx;
+            q.fy = qy - (float)jy;
+            q.fz = qz - (float)jz;
+            const int off = (int)(__umul24(__umul24(jz, ny) + jy, nx) + jx) * 4;
+            q.a00 = load2(rM, off, 0);
+            q.a10 = load2(rM, off, nx4);
+            q.a01 = load2(rM, off, nxy4);
+            q.a11 = load2(rM, off, nxy4 + nx4);
+            return q;
+        };
+        auto finish = [&](int r, const Prep& q) {
+            const float w0 = kW8.w[r][0], w1 = kW8.w[r][1], w2 = kW8.w[r][2], w3 = kW8.w[r][3];
+            const float Fv = q.Fv;
+            const float m = q.m, fx = q.fx, fy = q.fy, fz = q.fz;
+            const v2f a00 = q.a00, a10 = q.a10, a01 = q.a01, a11 = q.a11;
+            const float dz00 = a01.x - a00.x, dz01 = a01.y - a00.y;
+            const float dz10 = a11.x - a10.x, dz11 = a11.y - a10.y;
+            const float e00 = a00.x + fz * dz00, e01 = a00.y + fz * dz01;
+            const float e10 = a10.x + fz * dz10, e11 = a10.y + fz * dz11;
+            const float dy0 = e10 - e00, dy1 = e11 - e01;
+            const float g0 = e00 + fy * dy0, g1 = e01 + fy * dy1;
+            const float W = g0 + fx * (g1 - g0);
+            const float h0 = dz00 + fy * (dz10 - dz00);
+            const float h1 = dz01 + fy * (dz11 - dz01);
+            float d[3];
+            d[0] = m * (q.ex ? -W : g1 - g0);
+            d[1] = m * (q.ey ? -W : dy0 + fx * (dy1 - dy0));
+            d[2] = m * (q.ez ? -W : h0 + fx * (h1 - h0));
+            cnt += m;
+            if (SIM == AIR_SIM_NCC) {
+                const float dF = m * (Fv - shF), dW = m * (W - shW);
+                m1 += dF;
+                m2 += dW;
+                m3 += dF * dF;
+                m4 += dW * dW;
+                m5 += dF * dW;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float gF = dF * d[c], gW = dW * d[c], g1_ = d[c];
+                    acc[0][c][0] += w0 * gF;
+                    acc[0][c][1] += w1 * gF;
+                    acc[0][c][2] += w2 * gF;
+                    acc[0][c][3] += w3 * gF;
+                    acc[1][c][0] += w0 * gW;
+                    acc[1][c][1] += w1 * gW;
+                    acc[1][c][2] += w2 * gW;
+                    acc[1][c][3] += w3 * gW;
+                    acc[NF - 1][c][0] += w0 * g1_;
+                    acc[NF - 1][c][1] += w1 * g1_;
+                    acc[NF - 1][c][2] += w2 * g1_;
+                    acc[NF - 1][c][3] += w3 * g1_;
+                }
+            } else {
+                const float e = m * (W - Fv);
+                m1 += e * e;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float g = (W - Fv) * d[c];
+                    acc[0][c][0] += w0 * g;
+                    acc[0][c][1] += w1 * g;
+                    acc[0][c][2] += w2 * g;
+                    acc[0][c][3] += w3 * g;
+                }
+            }
+        };
+        // a running statistic that depends on the previous layer's gathers
+        auto dep = [&]() -> float { return SIM == AIR_SIM_NCC ? m2 : m1; };
+        Prep cur = prep(0, dep());
+#pragma unroll 2
+        for (int r = 0; r < S; ++r) {
+            Prep nxt = cur;
+            if (r + 1 < S) nxt = prep(r + 1, dep());
+            finish(r, cur);
+            cur = nxt;
+        }
+        flush(kzl);
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                acc[f][c][0] = acc[f][c][1];
+                acc[f][c][1] = acc[f][c][2];
+                acc[f][c][2] = acc[f][c][3];
+                acc[f][c][3] = 0.f;
+            }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            V[c][0] = V[c][1];
+            V[c][1] = V[c][2];
+            V[c][2] = V[c][3];
+            V[c][3] = (kzl + 4 < Wz) ? vcol(c, kzl + 4) : 0.f;
+        }
+    }
+    for (int k = Wz - 3; k < Wz; ++k) {
+        flush(k);
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                acc[f][c][0] = acc[f][c][1];
+                acc[f][c][1] = acc[f][c][2];
+                acc[f][c][2] = acc[f][c][3];
+                acc[f][c][3] = 0.f;
+            }
+    }
+    double st[6] = {(double)cnt, (double)m1, (double)m2, (double)m3, (double)m4, (double)m5};
+    block_sum<NT, 6>(st, red);
+    if (tid == 0) {
+        double* slot = reinterpret_cast<double*>(C.ws + C.L.stats) + (long long)item * kStatWords;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) slot[k] = st[k];
+        slot[6] = shF;
+        slot[7] = shW;
+    }
+}
+
 // --------------------------------------------------------------- fused 2D
 // Lanes over x (TX), the column axis is y.
 template <int TX, int SIM>
@@ -416,7 +776,8 @@ k_fused2(const LaunchCtx C) {
     double* red = reinterpret_cast<double*>(smem_raw);
     float* lds = reinterpret_cast<float*>(smem_raw + 8 * sizeof(double) * (NT / 64));
     const int tid = threadIdx.x;
-    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const int item = xcd_item(blockIdx.x, C.ntiles_total, C.nreg_total);
+    if (item < 0) return;
 
     if (item >= C.ntiles_total) {
         const int r = item - C.ntiles_total;
@@ -522,7 +883,7 @@ k_fused2(const LaunchCtx C) {
             const int q1 = min(TX, (cx0 + kx + 1) * sx - x0);
             float s = 0.f;
             for (int q = q0; q < q1; ++q) s += WXT[q * WxM + kx] * E[fc * TX + q];
-            part[(fc * WyM + kyl) * WxM + kx] = s;
+            part[(kyl * WxM + kx) * (NF * 2) + fc] = s;
         }
         __syncthreads();
     };
@@ -797,18 +1158,14 @@ k_finalize(const LaunchCtx C) {
                         const double* s = stats + (long long)(P.tile_begin + tl) * kStatWords;
                         c1 = k.alpha * (s[6] - k.muF) + k.beta * (s[7] - k.muW);
                     }
+                    // partial layout [column][y][x][field * DIM + component]
+                    const float* q = pt + (((long long)kcl * WyM + kyl) * WxM + kxl) * (NF * DIM);
 #pragma unroll
                     for (int c = 0; c < DIM; ++c) {
-                        const long long base = ((long long)kcl * WyM + kyl) * WxM + kxl;
-                        const long long fstride = (long long)DIM * WzM * WyM * WxM;
-                        const long long cstride = (long long)WzM * WyM * WxM;
-                        if (SIM == AIR_SIM_NCC) {
-                            g[c] += cF * pt[c * cstride + base] +
-                                    cW * pt[fstride + c * cstride + base] +
-                                    c1 * pt[2 * fstride + c * cstride + base];
-                        } else {
-                            g[c] += cF * pt[c * cstride + base];
-                        }
+                        if (SIM == AIR_SIM_NCC)
+                            g[c] += cF * q[c] + cW * q[DIM + c] + c1 * q[2 * DIM + c];
+                        else
+                            g[c] += cF * q[c];
                     }
                 }
             }
@@ -828,11 +1185,18 @@ k_finalize(const LaunchCtx C) {
 // --------------------------------------------------------------- launchers
 template <int TX, int TY, int SIM>
 static hipError_t launch3(const LaunchCtx& C, size_t lds, hipStream_t s) {
-    const int nblk = C.ntiles_total + C.nreg_total;
+    const int nblk = xcd_grid(C.ntiles_total, C.nreg_total);
     hipLaunchKernelGGL((k_fused3<TX, TY, SIM>), dim3(nblk), dim3(TX * TY), lds, s, C);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return hipSuccess;
+}
+
+template <int TX, int TY, int SIM, int WPE>
+static hipError_t launch3s8(const LaunchCtx& C, size_t lds, hipStream_t s) {
+    const int nblk = xcd_grid(C.ntiles_total, C.nreg_total);
+    hipLaunchKernelGGL((k_fused3_s8<TX, TY, SIM, WPE>), dim3(nblk), dim3(TX * TY), lds, s, C);
+    return hipGetLastError();
 }
 
 template <int TX, int TY, int SIM, int DIM>
@@ -856,17 +1220,23 @@ hipError_t launch_bspline(const LaunchCtx& C, int cfg, size_t lds, int max_ctrl,
             case 0: e = ncc ? launch3<32, 8, 1>(C, lds, s) : launch3<32, 8, 0>(C, lds, s); break;
             case 1: e = ncc ? launch3<64, 4, 1>(C, lds, s) : launch3<64, 4, 0>(C, lds, s); break;
             case 2: e = ncc ? launch3<16, 16, 1>(C, lds, s) : launch3<16, 16, 0>(C, lds, s); break;
+            case 3: e = ncc ? launch3s8<32, 8, 1, 1>(C, lds, s) : launch3s8<32, 8, 0, 1>(C, lds, s); break;
+            case 4: e = ncc ? launch3s8<16, 16, 1, 1>(C, lds, s) : launch3s8<16, 16, 0, 1>(C, lds, s); break;
+            case 5: e = ncc ? launch3s8<32, 8, 1, 3>(C, lds, s) : launch3s8<32, 8, 0, 3>(C, lds, s); break;
+            case 6: e = ncc ? launch3s8<16, 16, 1, 3>(C, lds, s) : launch3s8<16, 16, 0, 3>(C, lds, s); break;
+            case 7: e = ncc ? launch3s8<32, 8, 1, 4>(C, lds, s) : launch3s8<32, 8, 0, 4>(C, lds, s); break;
+            case 8: e = ncc ? launch3s8<16, 16, 1, 4>(C, lds, s) : launch3s8<16, 16, 0, 4>(C, lds, s); break;
             default: return hipErrorInvalidValue;
         }
         if (e != hipSuccess) return e;
         if (ev1) (void)hipEventRecord(ev1, s);
         switch (cfg) {
-            case 0: return ncc ? launch_fin<32, 8, 1, 3>(C, max_ctrl, s) : launch_fin<32, 8, 0, 3>(C, max_ctrl, s);
+            case 0: case 3: case 5: case 7: return ncc ? launch_fin<32, 8, 1, 3>(C, max_ctrl, s) : launch_fin<32, 8, 0, 3>(C, max_ctrl, s);
             case 1: return ncc ? launch_fin<64, 4, 1, 3>(C, max_ctrl, s) : launch_fin<64, 4, 0, 3>(C, max_ctrl, s);
             default: return ncc ? launch_fin<16, 16, 1, 3>(C, max_ctrl, s) : launch_fin<16, 16, 0, 3>(C, max_ctrl, s);
         }
     }
-    const int nblk = C.ntiles_total + C.nreg_total;
+    const int nblk = xcd_grid(C.ntiles_total, C.nreg_total);
     if (C.sim == AIR_SIM_NCC)
         hipLaunchKernelGGL((k_fused2<64, 1>), dim3(nblk), dim3(64), lds, s, C);
     else
