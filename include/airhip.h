@@ -147,6 +147,21 @@ air_status air_scale(float* x, const float* s, int64_t n, void* stream);
 air_status air_get_flags(const air_plan* plan, const void* ws, uint32_t* flags,
                          void* stream);
 
+/* Multi-resolution (Sec. IV-A: the FFD experiment's multi-resolution
+ * strategy). One Gaussian pyramid level of a 3D volume in = [n2][n1][n0]:
+ * separable Gaussian of std `sigma` voxels (taps to ceil(3 sigma), weights
+ * normalised, borders clamped), then every second voxel from 0; out has
+ * extent (n_a + 1) / 2 per axis. Needs air_pyramid_workspace_bytes(n) of
+ * caller-owned device scratch. */
+air_status air_pyramid_workspace_bytes(const int32_t n[3], size_t* bytes);
+air_status air_pyramid_down(const float* in, const int32_t n[3], float sigma, float* out,
+                            void* ws, size_t ws_bytes, void* stream);
+/* Linear transfer of a displacement field [3][n2][n1][n0] (normalised units,
+ * so no rescaling) to the grid m: voxel j of m samples the point
+ * j (n - 1) / (m - 1) of n (align-corners convention). */
+air_status air_field_resample(const float* in, const int32_t n[3], const int32_t m[3],
+                              float* out, void* stream);
+
 /* Kernel timing for benchmarks: reserve `launches` pairs of HIP events; each
  * following objective call records one pair on its stream around its main
  * kernel (the fused B-spline kernel, or the dense main pass) until the

@@ -71,6 +71,9 @@ def lib():
             "airo_adam_step": (None, [dp, dp, dp, dp, ctypes.c_long, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_int]),
+            "airo_pyramid_down": (None, [dp, ctypes.POINTER(ctypes.c_int), ctypes.c_double, dp]),
+            "airo_field_resample": (None, [dp, ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_int), dp]),
             "airo_set_point_precision": (None, [ctypes.c_int]),
             "airo_get_point_precision": (ctypes.c_int, []),
             "airo_set_threads": (None, [ctypes.c_int]),
@@ -288,3 +291,24 @@ def warp_fn_fp32(n_xyz, spacing, moving32, theta32) -> np.ndarray:
                    similarity=SIM_MSE)
     w, _ = warp(prob, moving32, theta32)
     return w.astype(np.float32)
+
+
+def pyramid_down(vol, sigma: float = 1.0) -> np.ndarray:
+    """Gaussian (std sigma, clamped borders) then every second voxel."""
+    v = _f64(vol)
+    assert v.ndim == 3
+    n = (ctypes.c_int * 3)(v.shape[2], v.shape[1], v.shape[0])
+    out = np.empty(tuple((s + 1) // 2 for s in v.shape), dtype=np.float64)
+    lib().airo_pyramid_down(_ptr(v), n, float(sigma), _ptr(out))
+    return out
+
+
+def field_resample(u, m_xyz) -> np.ndarray:
+    """Linear transfer of a [3][nz][ny][nx] field to the grid m_xyz."""
+    u = _f64(u)
+    assert u.ndim == 4 and u.shape[0] == 3
+    n = (ctypes.c_int * 3)(u.shape[3], u.shape[2], u.shape[1])
+    m = (ctypes.c_int * 3)(*m_xyz)
+    out = np.empty((3, m_xyz[2], m_xyz[1], m_xyz[0]), dtype=np.float64)
+    lib().airo_field_resample(_ptr(u), n, m, _ptr(out))
+    return out

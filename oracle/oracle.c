@@ -512,3 +512,84 @@ void airo_adam_step(double* theta, const double* grad, double* m, double* v, lon
         theta[i] -= lr * mhat / (sqrt(vhat) + eps);
     }
 }
+
+/* ---------------------------------------------------------------- pyramid */
+void airo_pyramid_down(const double* in, const int n[3], double sigma, double* out) {
+    const int r = (int)ceil(3.0 * sigma);
+    double* w = (double*)malloc(sizeof(double) * (size_t)(2 * r + 1));
+    double s = 0.0;
+    for (int k = -r; k <= r; ++k) {
+        w[k + r] = exp(-0.5 * (double)k * (double)k / (sigma * sigma));
+        s += w[k + r];
+    }
+    for (int k = 0; k <= 2 * r; ++k) w[k] /= s;
+    const long N = (long)n[0] * n[1] * n[2];
+    double* a = (double*)malloc(sizeof(double) * (size_t)N);
+    double* b = (double*)malloc(sizeof(double) * (size_t)N);
+    memcpy(a, in, sizeof(double) * (size_t)N);
+    const long stride[3] = {1, n[0], (long)n[0] * n[1]};
+    for (int ax = 0; ax < 3; ++ax) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) NTHREADS
+#endif
+        for (int z = 0; z < n[2]; ++z)
+            for (int y = 0; y < n[1]; ++y)
+                for (int x = 0; x < n[0]; ++x) {
+                    const int idx[3] = {x, y, z};
+                    const long v = ((long)z * n[1] + y) * n[0] + x;
+                    double acc = 0.0;
+                    for (int k = -r; k <= r; ++k) {
+                        int q = idx[ax] + k;
+                        if (q < 0) q = 0;
+                        if (q > n[ax] - 1) q = n[ax] - 1;
+                        acc += w[k + r] * a[v + (long)(q - idx[ax]) * stride[ax]];
+                    }
+                    b[v] = acc;
+                }
+        double* t = a;
+        a = b;
+        b = t;
+    }
+    const int m[3] = {(n[0] + 1) / 2, (n[1] + 1) / 2, (n[2] + 1) / 2};
+    for (int z = 0; z < m[2]; ++z)
+        for (int y = 0; y < m[1]; ++y)
+            for (int x = 0; x < m[0]; ++x)
+                out[((long)z * m[1] + y) * m[0] + x] =
+                    a[((long)(2 * z) * n[1] + 2 * y) * n[0] + 2 * x];
+    free(a);
+    free(b);
+    free(w);
+}
+
+void airo_field_resample(const double* in, const int n[3], const int m[3], double* out) {
+    const long Nn = (long)n[0] * n[1] * n[2];
+    const long Nm = (long)m[0] * m[1] * m[2];
+    for (int c = 0; c < 3; ++c) {
+        const double* f = in + c * Nn;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) NTHREADS
+#endif
+        for (int z = 0; z < m[2]; ++z)
+            for (int y = 0; y < m[1]; ++y)
+                for (int x = 0; x < m[0]; ++x) {
+                    const int idx[3] = {x, y, z};
+                    double p[3], fr[3];
+                    int j[3];
+                    for (int a = 0; a < 3; ++a) {
+                        p[a] = (m[a] > 1) ? (double)idx[a] * (n[a] - 1) / (double)(m[a] - 1) : 0.0;
+                        j[a] = (int)floor(p[a]);
+                        if (j[a] > n[a] - 2) j[a] = n[a] - 2;
+                        if (j[a] < 0) j[a] = 0;
+                        fr[a] = p[a] - j[a];
+                    }
+                    double acc = 0.0;
+                    for (int q = 0; q < 8; ++q) {
+                        const int bx = q & 1, by = (q >> 1) & 1, bz = (q >> 2) & 1;
+                        const double wq = (bx ? fr[0] : 1 - fr[0]) * (by ? fr[1] : 1 - fr[1]) *
+                                          (bz ? fr[2] : 1 - fr[2]);
+                        acc += wq * f[((long)(j[2] + bz) * n[1] + j[1] + by) * n[0] + j[0] + bx];
+                    }
+                    out[c * Nm + ((long)z * m[1] + y) * m[0] + x] = acc;
+                }
+    }
+}

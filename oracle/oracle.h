@@ -103,6 +103,17 @@ int airo_objective_and_grad(const airo_problem* p, const double* fixed,
 void airo_adam_step(double* theta, const double* grad, double* m, double* v, long n,
                     double lr, double b1, double b2, double eps, int step);
 
+/* Multi-resolution helpers (Sec. IV-A: the FFD experiment's multi-resolution
+ * strategy). Gaussian pyramid level: separable Gaussian of std `sigma`
+ * (voxels), taps truncated at ceil(3 sigma), weights normalised to sum 1,
+ * borders clamped (edge voxels repeated), then every second voxel from 0:
+ * out n_out = (n + 1) / 2 per axis. 3D volumes [nz][ny][nx]. */
+void airo_pyramid_down(const double* in, const int n[3], double sigma, double* out);
+/* Transfer a displacement field [3][nz][ny][nx] (normalised units) to a
+ * finer grid m[3] by linear interpolation in normalised coordinates
+ * (align-corners convention: voxel j of m maps to j (n-1)/(m-1) of n). */
+void airo_field_resample(const double* in, const int n[3], const int m[3], double* out);
+
 /* Precision (32 or 64 bits) of the sample point on which the interpolation
  * cell and the mask are decided; default 32 (a grid sampler over FP32
  * tensors, Sec. III-C). Arithmetic after the decision is FP64 either way. */

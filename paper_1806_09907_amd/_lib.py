@@ -58,6 +58,9 @@ SIGNATURES = {
     "air_adam_step": (_i32, [_vp, _vp, _vp, _vp, _i64, _f32, _f32, _f32, _f32, _i32, _vp]),
     "air_scale": (_i32, [_vp, _vp, _i64, _vp]),
     "air_get_flags": (_i32, [_vp, _vp, _vp, _vp]),
+    "air_pyramid_workspace_bytes": (_i32, [_vp, ctypes.POINTER(_sz)]),
+    "air_pyramid_down": (_i32, [_vp, _vp, _f32, _vp, _vp, _sz, _vp]),
+    "air_field_resample": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "air_plan_timing": (_i32, [_vp, _i32]),
     "air_plan_timing_read": (_i32, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)]),
     "air_strerror": (ctypes.c_char_p, [_i32]),

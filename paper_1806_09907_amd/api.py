@@ -284,3 +284,34 @@ def get_flags(plan: Plan) -> List[int]:
     out = (ctypes.c_uint32 * plan.npairs)()
     check(lib().air_get_flags(plan.handle, _ptr(ws), out, _stream()), "air_get_flags")
     return list(out)
+
+
+def _int3(v):
+    return (ctypes.c_int32 * 3)(*[int(x) for x in v])
+
+
+def pyramid_down(vol: torch.Tensor, sigma: float = 1.0) -> torch.Tensor:
+    """One Gaussian pyramid level of a 3D FP32 volume [nz][ny][nx]."""
+    _need(vol, None, name="vol")
+    if vol.dim() != 3:
+        raise ValueError("vol must be 3D")
+    n = _int3(reversed(vol.shape))
+    need = ctypes.c_size_t()
+    check(lib().air_pyramid_workspace_bytes(n, ctypes.byref(need)), "air_pyramid_workspace_bytes")
+    ws = torch.empty(max(int(need.value), 16), dtype=torch.uint8, device=vol.device)
+    out = torch.empty(tuple((s + 1) // 2 for s in vol.shape), dtype=torch.float32,
+                      device=vol.device)
+    check(lib().air_pyramid_down(_ptr(vol), n, float(sigma), _ptr(out), _ptr(ws), ws.numel(),
+                                 _stream()), "air_pyramid_down")
+    return out
+
+
+def field_resample(u: torch.Tensor, m_xyz) -> torch.Tensor:
+    """Linear transfer of a [3][nz][ny][nx] displacement field to grid m_xyz."""
+    _need(u, None, name="u")
+    if u.dim() != 4 or u.shape[0] != 3:
+        raise ValueError("u must be [3][nz][ny][nx]")
+    out = torch.empty((3, m_xyz[2], m_xyz[1], m_xyz[0]), dtype=torch.float32, device=u.device)
+    check(lib().air_field_resample(_ptr(u), _int3(reversed(u.shape[1:])), _int3(m_xyz), _ptr(out),
+                                   _stream()), "air_field_resample")
+    return out

@@ -473,3 +473,28 @@ def test_fp32_point_decision_mode(oracle):
             u0[0] = 2.0 * 3 / (n[0] - 1)
             w, mask, _ = O.sample(p, moving, u0)
         assert np.array_equal(w[..., :n[0] - 3], moving[..., 3:])
+
+
+def test_pyramid_down_matches_scipy(oracle):
+    """Pyramid level = scipy's Gaussian filter (clamped borders, 3 sigma
+    truncation) along each axis, then every second voxel."""
+    from scipy.ndimage import gaussian_filter1d
+
+    rng = np.random.default_rng(16)
+    vol = rng.normal(size=(9, 12, 15))
+    for sigma in (1.0, 1.5):
+        ref = vol.copy()
+        for ax in range(3):
+            ref = gaussian_filter1d(ref, sigma, axis=ax, mode="nearest", truncate=3.0)
+        ref = ref[::2, ::2, ::2]
+        assert np.max(np.abs(O.pyramid_down(vol, sigma) - ref)) < 1e-13
+
+
+def test_field_resample_matches_torch_interpolate(oracle):
+    """Linear field transfer = trilinear interpolation with aligned corners."""
+    rng = np.random.default_rng(17)
+    u = rng.normal(size=(3, 5, 7, 6))
+    m = (11, 13, 9)
+    ref = torch.nn.functional.interpolate(torch.from_numpy(u)[None], size=(m[2], m[1], m[0]),
+                                          mode="trilinear", align_corners=True)[0].numpy()
+    assert np.max(np.abs(O.field_resample(u, m) - ref)) < 1e-13
