@@ -162,6 +162,68 @@ air_status air_pyramid_down(const float* in, const int32_t n[3], float sigma, fl
 air_status air_field_resample(const float* in, const int32_t n[3], const int32_t m[3],
                               float* out, void* stream);
 
+/* ---- Learned initialisation CNN (BF16 operands, FP32 accumulation). ----
+ * Not part of the paper's method: the paper lists learning-based
+ * registration as an upcoming feature (Sec. III-I). A small 3D encoder-
+ * decoder maps a fixed/moving pair to a starting control grid that the
+ * plain registration then refines.
+ * Activations are NDHWC bf16 (uint16_t storage) [z][y][x][C], C a multiple
+ * of 8; weights are Wt[co][k], k = tap * C_in + ci, tap = (dz*3+dy)*3+dx.
+ *
+ * 3x3x3 convolution, stride 1, zero padding 1, on BF16 MFMA (16x16x32)
+ * with FP32 accumulation: y = act(conv(x) + bias). act: 0 none, 1 LeakyReLU
+ * 0.1. Outputs (either may be NULL): bf16 y_bf16[v * ldy + yoff + co] and
+ * FP32 y_f32[v * ldyf + co]. bias nullable. dims = (nx, ny, nz). */
+air_status air_conv3d_fwd(const uint16_t* x, const int32_t dims[3], int32_t cin,
+                          const uint16_t* wt, const float* bias, int32_t cout, int32_t act,
+                          uint16_t* y_bf16, int32_t ldy, int32_t yoff, float* y_f32,
+                          int32_t ldyf, void* stream);
+/* Backward-data of the convolution = air_conv3d_fwd on the gradient with
+ * these weights: wf[ci][tap' * C_out + co] = bf16(wt[co][(26 - tap') C_in + ci]). */
+air_status air_conv3d_flip_weights(const float* wt, int32_t cin, int32_t cout, uint16_t* wf,
+                                   void* stream);
+/* Backward-weight: dwt[co][k] = sum_v dy[v][co] x[v + off(tap)][ci] (FP32),
+ * db[co] = sum_v dy[v][co] (nullable). Voxels are reduced in chunks of
+ * `chunk` (multiple of 32) into workspace partials summed in a fixed order. */
+air_status air_conv3d_bwd_weight_workspace(const int32_t dims[3], int32_t cin, int32_t cout,
+                                           int32_t chunk, size_t* bytes);
+air_status air_conv3d_bwd_weight(const uint16_t* x, const int32_t dims[3], int32_t cin,
+                                 const uint16_t* dy, int32_t cout, int32_t chunk, float* dwt,
+                                 float* db, void* ws, size_t ws_bytes, void* stream);
+/* y = bf16(x), round to nearest even. */
+air_status air_cast_bf16(const float* x, uint16_t* y, int64_t n, void* stream);
+/* 2x average pooling (even dims) of the channel slice x[v * ldx + xoff + c]
+ * into a contiguous y, and its adjoint into the FP32 slice
+ * dx[v * ldx + xoff + c] (written, or added when accumulate != 0). */
+air_status air_pool2(const uint16_t* x, const int32_t dims[3], int32_t c, int32_t ldx,
+                     int32_t xoff, uint16_t* y, void* stream);
+air_status air_pool2_bwd(const float* dy, const int32_t dims[3], int32_t c, float* dx,
+                         int32_t ldx, int32_t xoff, int32_t accumulate, void* stream);
+/* Nearest 2x upsampling of x (dims = coarse size) into the channel slice
+ * y[v * ldy + yoff + c], and its adjoint (sum of the 8 children, FP32). */
+air_status air_up2(const uint16_t* x, const int32_t dims[3], int32_t c, uint16_t* y, int32_t ldy,
+                   int32_t yoff, void* stream);
+air_status air_up2_bwd(const float* dy, const int32_t dims[3], int32_t c, int32_t ldy,
+                       int32_t yoff, float* dx, void* stream);
+/* dx = bf16(dy * (a > 0 ? 1 : 0.1)) with dy read from the FP32 slice
+ * dy[v * ld + off + c] and the stored activation a = yact[v * ldyact + yoff + c]. */
+air_status air_lrelu_bwd(const float* dy, int32_t ld, int32_t off, const uint16_t* yact,
+                         int32_t ldyact, int32_t yoff, int64_t nvox, int32_t c, uint16_t* dx,
+                         void* stream);
+/* Network input: (fixed, moving) FP32 volumes (dims even) -> 2x averaged,
+ * 8-channel bf16 tensor (fixed, moving, six zero channels). */
+air_status air_cnn_input(const float* fixed, const float* moving, const int32_t dims[3],
+                         uint16_t* x, void* stream);
+/* Network output: FP32 features g [gz][gy][gx][ld] (one cell per control
+ * cell; channels 0..2 used) -> control grid theta [3][gz+3][gy+3][gx+3]:
+ * theta[c][j] = scale * g[clamp(j - 1, 0, g - 1)][c] per axis; and its adjoint. */
+air_status air_cnn_output(const float* g, const int32_t gdims[3], int32_t ld, float scale,
+                          float* theta, void* stream);
+air_status air_cnn_output_bwd(const float* dtheta, const int32_t gdims[3], int32_t ld,
+                              float scale, float* dg, void* stream);
+/* a += b (FP32). */
+air_status air_add_f32(float* a, const float* b, int64_t n, void* stream);
+
 /* Kernel timing for benchmarks: reserve `launches` pairs of HIP events; each
  * following objective call records one pair on its stream around its main
  * kernel (the fused B-spline kernel, or the dense main pass) until the

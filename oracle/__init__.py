@@ -74,6 +74,10 @@ def lib():
             "airo_pyramid_down": (None, [dp, ctypes.POINTER(ctypes.c_int), ctypes.c_double, dp]),
             "airo_field_resample": (None, [dp, ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(ctypes.c_int), dp]),
+            "airo_conv3d_fwd": (None, [dp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, dp, dp,
+                                       ctypes.c_int, ctypes.c_int, dp]),
+            "airo_conv3d_bwd": (None, [dp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, dp,
+                                       ctypes.c_int, dp, dp, dp, dp]),
             "airo_set_point_precision": (None, [ctypes.c_int]),
             "airo_get_point_precision": (ctypes.c_int, []),
             "airo_set_threads": (None, [ctypes.c_int]),
@@ -312,3 +316,33 @@ def field_resample(u, m_xyz) -> np.ndarray:
     out = np.empty((3, m_xyz[2], m_xyz[1], m_xyz[0]), dtype=np.float64)
     lib().airo_field_resample(_ptr(u), n, m, _ptr(out))
     return out
+
+
+def conv3d_fwd(x, wt, bias=None, act=0):
+    """x [nz][ny][nx][cin], wt [cout][27*cin] -> y [nz][ny][nx][cout] (FP64)."""
+    x = _f64(x)
+    wt = _f64(wt)
+    cin = x.shape[3]
+    cout = wt.shape[0]
+    assert wt.shape[1] == 27 * cin
+    n = (ctypes.c_int * 3)(x.shape[2], x.shape[1], x.shape[0])
+    y = np.empty(x.shape[:3] + (cout,), dtype=np.float64)
+    b = _f64(bias) if bias is not None else None
+    lib().airo_conv3d_fwd(_ptr(x), n, cin, _ptr(wt), _ptr(b) if b is not None else None, cout,
+                          int(act), _ptr(y))
+    return y
+
+
+def conv3d_bwd(x, wt, dy):
+    """Gradients (dx, dwt, db) for dy = dL/d(pre-activation) (FP64)."""
+    x = _f64(x)
+    wt = _f64(wt)
+    dy = _f64(dy)
+    cin = x.shape[3]
+    cout = wt.shape[0]
+    n = (ctypes.c_int * 3)(x.shape[2], x.shape[1], x.shape[0])
+    dx = np.empty_like(x)
+    dwt = np.empty_like(wt)
+    db = np.empty(cout, dtype=np.float64)
+    lib().airo_conv3d_bwd(_ptr(x), n, cin, _ptr(wt), cout, _ptr(dy), _ptr(dx), _ptr(dwt), _ptr(db))
+    return dx, dwt, db

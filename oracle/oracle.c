@@ -593,3 +593,96 @@ void airo_field_resample(const double* in, const int n[3], const int m[3], doubl
                 }
     }
 }
+
+/* ---------------------------------------------------------------- conv3d */
+void airo_conv3d_fwd(const double* x, const int n[3], int cin, const double* wt,
+                     const double* bias, int cout, int act, double* y) {
+    const int nx = n[0], ny = n[1], nz = n[2];
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) NTHREADS
+#endif
+    for (int z = 0; z < nz; ++z)
+        for (int yy = 0; yy < ny; ++yy)
+            for (int xx = 0; xx < nx; ++xx) {
+                const long v = ((long)z * ny + yy) * nx + xx;
+                for (int co = 0; co < cout; ++co) {
+                    double acc = bias ? bias[co] : 0.0;
+                    for (int dz = -1; dz <= 1; ++dz)
+                        for (int dy = -1; dy <= 1; ++dy)
+                            for (int dx = -1; dx <= 1; ++dx) {
+                                const int sz = z + dz, sy = yy + dy, sx = xx + dx;
+                                if (sz < 0 || sz >= nz || sy < 0 || sy >= ny || sx < 0 || sx >= nx)
+                                    continue;
+                                const int tap = ((dz + 1) * 3 + dy + 1) * 3 + dx + 1;
+                                const long s = ((long)sz * ny + sy) * nx + sx;
+                                for (int ci = 0; ci < cin; ++ci)
+                                    acc += wt[(long)co * 27 * cin + tap * cin + ci] * x[s * cin + ci];
+                            }
+                    if (act == 1 && acc < 0.0) acc *= 0.1;
+                    y[v * cout + co] = acc;
+                }
+            }
+}
+
+void airo_conv3d_bwd(const double* x, const int n[3], int cin, const double* wt, int cout,
+                     const double* dy, double* dx, double* dwt, double* db) {
+    const int nx = n[0], ny = n[1], nz = n[2];
+    const long N = (long)nx * ny * nz;
+    if (dx) {
+        /* dx[s][ci] = sum over outputs v that read s: dy[v][co] wt[co][tap][ci] */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) NTHREADS
+#endif
+        for (int z = 0; z < nz; ++z)
+            for (int yy = 0; yy < ny; ++yy)
+                for (int xx = 0; xx < nx; ++xx) {
+                    const long s = ((long)z * ny + yy) * nx + xx;
+                    for (int ci = 0; ci < cin; ++ci) {
+                        double acc = 0.0;
+                        for (int dz = -1; dz <= 1; ++dz)
+                            for (int dyy = -1; dyy <= 1; ++dyy)
+                                for (int dxx = -1; dxx <= 1; ++dxx) {
+                                    /* output v = s - d reads s through tap d */
+                                    const int vz = z - dz, vy = yy - dyy, vx = xx - dxx;
+                                    if (vz < 0 || vz >= nz || vy < 0 || vy >= ny || vx < 0 || vx >= nx)
+                                        continue;
+                                    const int tap = ((dz + 1) * 3 + dyy + 1) * 3 + dxx + 1;
+                                    const long v = ((long)vz * ny + vy) * nx + vx;
+                                    for (int co = 0; co < cout; ++co)
+                                        acc += dy[v * cout + co] * wt[(long)co * 27 * cin + tap * cin + ci];
+                                }
+                        dx[s * cin + ci] = acc;
+                    }
+                }
+    }
+    if (dwt) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) NTHREADS
+#endif
+        for (int co = 0; co < cout; ++co)
+            for (int tap = 0; tap < 27; ++tap) {
+                const int dz = tap / 9 - 1, dyy = (tap / 3) % 3 - 1, dxx = tap % 3 - 1;
+                for (int ci = 0; ci < cin; ++ci) {
+                    double acc = 0.0;
+                    for (int z = 0; z < nz; ++z)
+                        for (int yy = 0; yy < ny; ++yy)
+                            for (int xx = 0; xx < nx; ++xx) {
+                                const int sz = z + dz, sy = yy + dyy, sx = xx + dxx;
+                                if (sz < 0 || sz >= nz || sy < 0 || sy >= ny || sx < 0 || sx >= nx)
+                                    continue;
+                                const long v = ((long)z * ny + yy) * nx + xx;
+                                const long s = ((long)sz * ny + sy) * nx + sx;
+                                acc += dy[v * cout + co] * x[s * cin + ci];
+                            }
+                    dwt[(long)co * 27 * cin + tap * cin + ci] = acc;
+                }
+            }
+    }
+    if (db) {
+        for (int co = 0; co < cout; ++co) {
+            double acc = 0.0;
+            for (long v = 0; v < N; ++v) acc += dy[v * cout + co];
+            db[co] = acc;
+        }
+    }
+}

@@ -114,6 +114,16 @@ void airo_pyramid_down(const double* in, const int n[3], double sigma, double* o
  * (align-corners convention: voxel j of m maps to j (n-1)/(m-1) of n). */
 void airo_field_resample(const double* in, const int n[3], const int m[3], double* out);
 
+/* 3x3x3 convolution, stride 1, zero padding 1, channel-last tensors
+ * x [nz][ny][nx][cin], weights wt [cout][27 * cin] (k = tap * cin + ci,
+ * tap = (dz*3 + dy)*3 + dx), y [nz][ny][nx][cout]; act 1 = LeakyReLU 0.1.
+ * Backward takes dy = dL/d(pre-activation) and writes dx, dwt, db
+ * (each nullable). Used to check the learned-initialisation network. */
+void airo_conv3d_fwd(const double* x, const int n[3], int cin, const double* wt,
+                     const double* bias, int cout, int act, double* y);
+void airo_conv3d_bwd(const double* x, const int n[3], int cin, const double* wt, int cout,
+                     const double* dy, double* dx, double* dwt, double* db);
+
 /* Precision (32 or 64 bits) of the sample point on which the interpolation
  * cell and the mask are decided; default 32 (a grid sampler over FP32
  * tensors, Sec. III-C). Arithmetic after the decision is FP64 either way. */

@@ -61,6 +61,20 @@ SIGNATURES = {
     "air_pyramid_workspace_bytes": (_i32, [_vp, ctypes.POINTER(_sz)]),
     "air_pyramid_down": (_i32, [_vp, _vp, _f32, _vp, _vp, _sz, _vp]),
     "air_field_resample": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "air_conv3d_fwd": (_i32, [_vp, _vp, _i32, _vp, _vp, _i32, _i32, _vp, _i32, _i32, _vp, _i32, _vp]),
+    "air_conv3d_flip_weights": (_i32, [_vp, _i32, _i32, _vp, _vp]),
+    "air_conv3d_bwd_weight_workspace": (_i32, [_vp, _i32, _i32, _i32, ctypes.POINTER(_sz)]),
+    "air_conv3d_bwd_weight": (_i32, [_vp, _vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "air_cast_bf16": (_i32, [_vp, _vp, _i64, _vp]),
+    "air_pool2": (_i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp]),
+    "air_pool2_bwd": (_i32, [_vp, _vp, _i32, _vp, _i32, _i32, _i32, _vp]),
+    "air_up2": (_i32, [_vp, _vp, _i32, _vp, _i32, _i32, _vp]),
+    "air_up2_bwd": (_i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp]),
+    "air_lrelu_bwd": (_i32, [_vp, _i32, _i32, _vp, _i32, _i32, _i64, _i32, _vp, _vp]),
+    "air_cnn_input": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "air_cnn_output": (_i32, [_vp, _vp, _i32, _f32, _vp, _vp]),
+    "air_cnn_output_bwd": (_i32, [_vp, _vp, _i32, _f32, _vp, _vp]),
+    "air_add_f32": (_i32, [_vp, _vp, _i64, _vp]),
     "air_plan_timing": (_i32, [_vp, _i32]),
     "air_plan_timing_read": (_i32, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)]),
     "air_strerror": (ctypes.c_char_p, [_i32]),

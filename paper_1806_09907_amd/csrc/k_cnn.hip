@@ -1,0 +1,540 @@
+// Learned-initialisation CNN kernels (BF16 operands, FP32 accumulation).
+//
+// Activations are NDHWC bf16 [z][y][x][C] with C a multiple of 8; 3x3x3
+// convolutions have stride 1 and zero padding 1. Weights are stored
+// output-major with the reduction index contiguous: Wt[co][k], k = tap*C_in +
+// ci, tap = (dz*3 + dy)*3 + dx.
+//
+// conv forward (implicit GEMM): Y[m][co] = b[co] + sum_k A[m][k] Wt[co][k],
+// A[m][k] = X[voxel m shifted by tap][ci]; one wave computes 16 voxels x all
+// output channels with v_mfma_f32_16x16x32_bf16 (A: lane l holds row l%16,
+// reduction elements 8*(l/16)..+8; B: column l%16, the same reduction range;
+// D: column l%16, rows 4*(l/16)..+4). Each lane's 8 reduction elements are 8
+// consecutive channels of one tap, i.e. one 16-byte load.
+// conv backward-data = the forward kernel on the gradient with flipped,
+// transposed weights (Wf[ci][tap'*C_out + co] = Wt[co][(26 - tap')*C_in + ci]).
+// conv backward-weight: dWt[co][k] = sum_m dY[m][co] A[m][k], an MFMA GEMM
+// that reduces over chunks of voxels into per-chunk partials, summed in a
+// fixed order by a second kernel.
+#include "device_common.h"
+
+namespace air {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16;
+
+__device__ inline float bf2f(u16 v) { return __uint_as_float(((uint32_t)v) << 16); }
+// round to nearest even (inputs are finite in this network)
+__device__ inline u16 f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (u16)(u >> 16);  // inf / nan kept
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (u16)(u >> 16);
+}
+
+struct ConvDims {
+    int nx, ny, nz;
+    int cin, cout;
+    int K, Kpad;     // 27 * cin, rounded up to a multiple of 32
+};
+
+__device__ inline bf16x8 load_a(const u16* __restrict__ X, const ConvDims& D, int vx, int vy,
+                                int vz, bool valid, int k) {
+    bf16x8 r;
+    const int tap = k / D.cin, ci = k - tap * D.cin;
+    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    const int x = vx + dx, y = vy + dy, z = vz + dz;
+    const bool in = valid && tap < 27 && (unsigned)x < (unsigned)D.nx &&
+                    (unsigned)y < (unsigned)D.ny && (unsigned)z < (unsigned)D.nz;
+    if (in) {
+        const long long v = ((long long)z * D.ny + y) * D.nx + x;
+        const uint4 q = *reinterpret_cast<const uint4*>(X + v * D.cin + ci);
+        r = __builtin_bit_cast(bf16x8, q);
+    } else {
+        r = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+    }
+    return r;
+}
+
+// One block = 4 waves = 64 output voxels; NT16 = ceil(cout / 16) column tiles.
+template <int NT16>
+__global__ void __launch_bounds__(256)
+k_conv_fwd(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ Wt,
+           const float* __restrict__ bias, int act, u16* __restrict__ Ybf, int ldy, int yoff,
+           float* __restrict__ Yf, int ldyf) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long N = (long long)D.nx * D.ny * D.nz;
+    const long long m0 = ((long long)blockIdx.x * 4 + wave) * 16;
+    if (m0 >= N) return;
+    const long long m = m0 + (lane & 15);
+    const bool valid = m < N;
+    const int vx = (int)(m % D.nx), vy = (int)((m / D.nx) % D.ny), vz = (int)(m / ((long long)D.nx * D.ny));
+    const int g = lane >> 4;
+    f32x4 acc[NT16];
+#pragma unroll
+    for (int t = 0; t < NT16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < D.Kpad; kc += 32) {
+        const int k = kc + 8 * g;
+        const bf16x8 a = load_a(X, D, vx, vy, vz, valid, k);
+#pragma unroll
+        for (int t = 0; t < NT16; ++t) {
+            const int co = t * 16 + (lane & 15);
+            bf16x8 b;
+            if (co < D.cout && k < D.K) {
+                const uint4 q = *reinterpret_cast<const uint4*>(Wt + (long long)co * D.K + k);
+                b = __builtin_bit_cast(bf16x8, q);
+            } else {
+                b = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+            }
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT16; ++t) {
+        const int co = t * 16 + (lane & 15);
+        if (co >= D.cout) continue;
+        const float b = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const long long row = m0 + 4 * g + i;
+            if (row >= N) continue;
+            float v = acc[t][i] + b;
+            if (act == 1) v = v > 0.f ? v : 0.1f * v;
+            if (Ybf) Ybf[row * ldy + yoff + co] = f2bf(v);
+            if (Yf) Yf[row * ldyf + co] = v;
+        }
+    }
+}
+
+// dWt partial for voxel chunk `blockIdx.z`: one wave per (16 co) x (16 k) tile.
+__global__ void __launch_bounds__(64)
+k_conv_bwdw(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ dY, int chunk,
+            float* __restrict__ part) {
+    const int lane = threadIdx.x;
+    const int co0 = blockIdx.y * 16, k0 = blockIdx.x * 16;
+    const long long N = (long long)D.nx * D.ny * D.nz;
+    const long long mb = (long long)blockIdx.z * chunk;
+    const long long me = mb + chunk < N ? mb + chunk : N;
+    const int g = lane >> 4;
+    const int co = co0 + (lane & 15);
+    const int k = k0 + (lane & 15);
+    const bool kok = k < D.K;
+    const int tap = kok ? k / D.cin : 0, ci = kok ? k - tap * D.cin : 0;
+    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (long long mc = mb; mc < me; mc += 32) {
+        bf16x8 a, b;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const long long mm = mc + 8 * g + i;
+            u16 av = 0, bv = 0;
+            if (mm < me) {
+                if (co < D.cout) av = dY[mm * D.cout + co];
+                if (kok) {
+                    const int vx = (int)(mm % D.nx), vy = (int)((mm / D.nx) % D.ny),
+                              vz = (int)(mm / ((long long)D.nx * D.ny));
+                    const int x = vx + dx, y = vy + dy, z = vz + dz;
+                    if ((unsigned)x < (unsigned)D.nx && (unsigned)y < (unsigned)D.ny &&
+                        (unsigned)z < (unsigned)D.nz)
+                        bv = X[(((long long)z * D.ny + y) * D.nx + x) * D.cin + ci];
+                }
+            }
+            a[i] = __builtin_bit_cast(__bf16, av);
+            b[i] = __builtin_bit_cast(__bf16, bv);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    }
+    // D: rows co0 + 4g + i, column k0 + lane%16
+    float* P = part + (long long)blockIdx.z * D.cout * D.K;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = co0 + 4 * g + i;
+        if (r < D.cout && kok) P[(long long)r * D.K + k] = acc[i];
+    }
+}
+
+// dWt = sum over chunks (fixed order); db[co] = sum over voxels of dY.
+__global__ void __launch_bounds__(kBlock)
+k_conv_bwdw_reduce(const float* __restrict__ part, int nchunk, int total, float* __restrict__ dW) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= total) return;
+    float s = 0.f;
+    for (int c = 0; c < nchunk; ++c) s += part[(long long)c * total + i];
+    dW[i] = s;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_bias_grad(const u16* __restrict__ dY, long long N, int cout, float* __restrict__ db) {
+    __shared__ double red[8 * (kBlock / 64)];
+    const int co = blockIdx.x;
+    double v[1] = {0.0};
+    for (long long m = threadIdx.x; m < N; m += kBlock) v[0] += bf2f(dY[m * cout + co]);
+    block_sum<kBlock, 1>(v, red);
+    if (threadIdx.x == 0) db[co] = (float)v[0];
+}
+
+// Wf[ci][tap'*cout + co] = Wt[co][(26 - tap')*cin + ci] (as bf16).
+__global__ void __launch_bounds__(kBlock)
+k_flip_weights(const float* __restrict__ Wt, int cin, int cout, u16* __restrict__ Wf) {
+    const int total = cin * 27 * cout;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= total) return;
+    const int ci = i / (27 * cout);
+    const int r = i - ci * 27 * cout;
+    const int tp = r / cout, co = r - tp * cout;
+    Wf[i] = f2bf(Wt[(long long)co * 27 * cin + (26 - tp) * cin + ci]);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_cast_bf16(const float* __restrict__ x, u16* __restrict__ y, long long n) {
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kBlock)
+        y[i] = f2bf(x[i]);
+}
+
+// 2x average pooling of [n][C] -> [(n+1)/2][C] per axis (n even here).
+__global__ void __launch_bounds__(kBlock)
+k_pool2(const u16* __restrict__ X, int nx, int ny, int nz, int C, int ldx, int xoff,
+        u16* __restrict__ Y) {
+    const int mx = nx / 2, my = ny / 2, mz = nz / 2;
+    const long long total = (long long)mx * my * mz * C;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (long long)gridDim.x * kBlock) {
+        const int c = (int)(i % C);
+        const long long v = i / C;
+        const int x = (int)(v % mx), y = (int)((v / mx) % my), z = (int)(v / ((long long)mx * my));
+        float s = 0.f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int xx = 2 * x + (q & 1), yy = 2 * y + ((q >> 1) & 1), zz = 2 * z + (q >> 2);
+            s += bf2f(X[(((long long)zz * ny + yy) * nx + xx) * ldx + xoff + c]);
+        }
+        Y[i] = f2bf(0.125f * s);
+    }
+}
+
+// pool backward: dX[v] (+)= dY[v/2] / 8 (FP32 output, optionally accumulating)
+__global__ void __launch_bounds__(kBlock)
+k_pool2_bwd(const float* __restrict__ dY, int nx, int ny, int nz, int C, float* __restrict__ dX,
+            int ldx, int xoff, int accumulate) {
+    const long long total = (long long)nx * ny * nz * C;
+    const int mx = nx / 2, my = ny / 2;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (long long)gridDim.x * kBlock) {
+        const int c = (int)(i % C);
+        const long long v = i / C;
+        const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((long long)nx * ny));
+        const float g = 0.125f * dY[(((long long)(z / 2) * my + y / 2) * mx + x / 2) * C + c];
+        float* d = dX + v * ldx + xoff + c;
+        *d = accumulate ? *d + g : g;
+    }
+}
+
+// nearest 2x upsampling into a channel slice: Y[v][yoff + c] = X[v/2][c]
+__global__ void __launch_bounds__(kBlock)
+k_up2(const u16* __restrict__ X, int mx, int my, int mz, int C, u16* __restrict__ Y, int ldy,
+      int yoff) {
+    const int nx = 2 * mx, ny = 2 * my, nz = 2 * mz;
+    const long long total = (long long)nx * ny * nz * C;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (long long)gridDim.x * kBlock) {
+        const int c = (int)(i % C);
+        const long long v = i / C;
+        const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((long long)nx * ny));
+        Y[v * ldy + yoff + c] = X[(((long long)(z / 2) * my + y / 2) * mx + x / 2) * C + c];
+    }
+}
+
+// up backward: dX[u][c] = sum of the 8 children dY[v][yoff + c] (FP32)
+__global__ void __launch_bounds__(kBlock)
+k_up2_bwd(const float* __restrict__ dY, int mx, int my, int mz, int C, int ldy, int yoff,
+          float* __restrict__ dX) {
+    const int nx = 2 * mx, ny = 2 * my;
+    const long long total = (long long)mx * my * mz * C;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (long long)gridDim.x * kBlock) {
+        const int c = (int)(i % C);
+        const long long u = i / C;
+        const int x = (int)(u % mx), y = (int)((u / mx) % my), z = (int)(u / ((long long)mx * my));
+        float s = 0.f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int xx = 2 * x + (q & 1), yy = 2 * y + ((q >> 1) & 1), zz = 2 * z + (q >> 2);
+            s += dY[(((long long)zz * ny + yy) * nx + xx) * ldy + yoff + c];
+        }
+        dX[i] = s;
+    }
+}
+
+// gradient through LeakyReLU(0.1), using the sign of the stored activation,
+// from an FP32 slice dY[v][off + c] (row stride ld) into bf16 [v][C]
+__global__ void __launch_bounds__(kBlock)
+k_lrelu_bwd(const float* __restrict__ dY, int ld, int off, const u16* __restrict__ Yact,
+            int ldyact, int yoff, long long nvox, int C, u16* __restrict__ dX) {
+    const long long total = nvox * C;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (long long)gridDim.x * kBlock) {
+        const int c = (int)(i % C);
+        const long long v = i / C;
+        const float g = dY[v * ld + off + c];
+        const float a = bf2f(Yact[v * ldyact + yoff + c]);
+        dX[i] = f2bf(a > 0.f ? g : 0.1f * g);
+    }
+}
+
+// input: (F, M) FP32 [n^3] -> 2x average pooled, 8 channels bf16 (F, M, 0...)
+__global__ void __launch_bounds__(kBlock)
+k_cnn_input(const float* __restrict__ F, const float* __restrict__ M, int nx, int ny, int nz,
+            u16* __restrict__ X) {
+    const int mx = nx / 2, my = ny / 2, mz = nz / 2;
+    const long long total = (long long)mx * my * mz;
+    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < total;
+         v += (long long)gridDim.x * kBlock) {
+        const int x = (int)(v % mx), y = (int)((v / mx) % my), z = (int)(v / ((long long)mx * my));
+        float sf = 0.f, sm = 0.f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const long long s = ((long long)(2 * z + (q >> 2)) * ny + 2 * y + ((q >> 1) & 1)) * nx +
+                                2 * x + (q & 1);
+            sf += F[s];
+            sm += M[s];
+        }
+        u16* o = X + v * 8;
+        o[0] = f2bf(0.125f * sf);
+        o[1] = f2bf(0.125f * sm);
+#pragma unroll
+        for (int c = 2; c < 8; ++c) o[c] = 0;
+    }
+}
+
+// output map: feature grid g (cells of the control spacing) [gz][gy][gx][ld]
+// (first 3 channels) -> controls theta [3][gz+3][gy+3][gx+3] with
+// theta[j] = scale * g[clamp(j - 1, 0, g - 1)] per axis (edge replication).
+__global__ void __launch_bounds__(kBlock)
+k_cnn_output(const float* __restrict__ G, int gx, int gy, int gz, int ld, float scale,
+             float* __restrict__ theta) {
+    const int cx = gx + 3, cy = gy + 3, cz = gz + 3;
+    const long long total = 3LL * cx * cy * cz;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (long long)gridDim.x * kBlock) {
+        const int c = (int)(i / ((long long)cx * cy * cz));
+        const long long j = i - (long long)c * cx * cy * cz;
+        const int jx = (int)(j % cx), jy = (int)((j / cx) % cy), jz = (int)(j / ((long long)cx * cy));
+        const int x = min(max(jx - 1, 0), gx - 1), y = min(max(jy - 1, 0), gy - 1),
+                  z = min(max(jz - 1, 0), gz - 1);
+        theta[i] = scale * G[(((long long)z * gy + y) * gx + x) * ld + c];
+    }
+}
+
+// adjoint of k_cnn_output: dG[v][c] = scale * sum of the controls mapped to v
+// (written for c < 3, zero for the other ld - 3 channels), as FP32.
+__global__ void __launch_bounds__(kBlock)
+k_cnn_output_bwd(const float* __restrict__ dtheta, int gx, int gy, int gz, int ld, float scale,
+                 float* __restrict__ dG) {
+    const int cx = gx + 3, cy = gy + 3, cz = gz + 3;
+    const long long total = (long long)gx * gy * gz * ld;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (long long)gridDim.x * kBlock) {
+        const int c = (int)(i % ld);
+        const long long v = i / ld;
+        if (c >= 3) { dG[i] = 0.f; continue; }
+        const int x = (int)(v % gx), y = (int)((v / gx) % gy), z = (int)(v / ((long long)gx * gy));
+        // controls j with clamp(j - 1) == x: j = x + 1, plus j = 0 at x = 0,
+        // plus j in [gx + 1, gx + 2] at x = gx - 1
+        int jx0 = x + 1, jx1 = x + 1, jy0 = y + 1, jy1 = y + 1, jz0 = z + 1, jz1 = z + 1;
+        if (x == 0) jx0 = 0;
+        if (x == gx - 1) jx1 = gx + 2;
+        if (y == 0) jy0 = 0;
+        if (y == gy - 1) jy1 = gy + 2;
+        if (z == 0) jz0 = 0;
+        if (z == gz - 1) jz1 = gz + 2;
+        float s = 0.f;
+        for (int jz = jz0; jz <= jz1; ++jz)
+            for (int jy = jy0; jy <= jy1; ++jy)
+                for (int jx = jx0; jx <= jx1; ++jx)
+                    s += dtheta[(((long long)c * cz + jz) * cy + jy) * cx + jx];
+        dG[i] = scale * s;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_add_f32(float* __restrict__ a, const float* __restrict__ b, long long n) {
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kBlock)
+        a[i] += b[i];
+}
+
+static int grid1(long long n) {
+    long long b = (n + kBlock - 1) / kBlock;
+    return (int)(b < 16384 ? b : 16384);
+}
+
+static bool a16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+}  // namespace air
+
+using namespace air;
+
+extern "C" {
+
+air_status air_conv3d_fwd(const uint16_t* x, const int32_t dims[3], int32_t cin,
+                          const uint16_t* wt, const float* bias, int32_t cout, int32_t act,
+                          uint16_t* y_bf16, int32_t ldy, int32_t yoff, float* y_f32,
+                          int32_t ldyf, void* stream) {
+    if (!x || !dims || !wt || (!y_bf16 && !y_f32)) return AIR_ERR_INVALID_ARG;
+    if (cin < 8 || cin % 8 || cout < 1 || cout > 128 || act < 0 || act > 1)
+        return AIR_ERR_SHAPE;
+    if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1) return AIR_ERR_SHAPE;
+    if (y_bf16 && (ldy < yoff + cout || yoff < 0)) return AIR_ERR_SHAPE;
+    if (y_f32 && ldyf < cout) return AIR_ERR_SHAPE;
+    if (!a16(x) || !a16(wt)) return AIR_ERR_ALIGN;
+    ConvDims D{dims[0], dims[1], dims[2], cin, cout, 27 * cin, (27 * cin + 31) / 32 * 32};
+    if ((27 * cin) % 8) return AIR_ERR_SHAPE;
+    const long long N = (long long)D.nx * D.ny * D.nz;
+    const int nblk = (int)((N + 63) / 64);
+    hipStream_t s = (hipStream_t)stream;
+    const int nt = (cout + 15) / 16;
+    switch (nt) {
+#define CASE(T) case T: hipLaunchKernelGGL(k_conv_fwd<T>, dim3(nblk), dim3(256), 0, s, (const u16*)x, D, \
+        (const u16*)wt, bias, act, (u16*)y_bf16, ldy, yoff, y_f32, ldyf); break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        default: return AIR_ERR_SHAPE;
+    }
+    return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_conv3d_bwd_weight_workspace(const int32_t dims[3], int32_t cin, int32_t cout,
+                                           int32_t chunk, size_t* bytes) {
+    if (!dims || !bytes || chunk < 32 || chunk % 32) return AIR_ERR_INVALID_ARG;
+    const long long N = (long long)dims[0] * dims[1] * dims[2];
+    const long long nch = (N + chunk - 1) / chunk;
+    *bytes = (size_t)(4LL * nch * cout * 27 * cin);
+    return AIR_OK;
+}
+
+air_status air_conv3d_bwd_weight(const uint16_t* x, const int32_t dims[3], int32_t cin,
+                                 const uint16_t* dy, int32_t cout, int32_t chunk, float* dwt,
+                                 float* db, void* ws, size_t ws_bytes, void* stream) {
+    if (!x || !dims || !dy || !dwt) return AIR_ERR_INVALID_ARG;
+    if (cin < 8 || cin % 8 || cout < 1 || cout > 128) return AIR_ERR_SHAPE;
+    size_t need = 0;
+    air_status st = air_conv3d_bwd_weight_workspace(dims, cin, cout, chunk, &need);
+    if (st != AIR_OK) return st;
+    if (!ws || ws_bytes < need) return AIR_ERR_WORKSPACE;
+    ConvDims D{dims[0], dims[1], dims[2], cin, cout, 27 * cin, (27 * cin + 31) / 32 * 32};
+    const long long N = (long long)D.nx * D.ny * D.nz;
+    const int nch = (int)((N + chunk - 1) / chunk);
+    hipStream_t s = (hipStream_t)stream;
+    dim3 grid((D.K + 15) / 16, (cout + 15) / 16, nch);
+    hipLaunchKernelGGL(k_conv_bwdw, grid, dim3(64), 0, s, (const u16*)x, D, (const u16*)dy, chunk,
+                       (float*)ws);
+    const int total = cout * D.K;
+    hipLaunchKernelGGL(k_conv_bwdw_reduce, dim3((total + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                       (const float*)ws, nch, total, dwt);
+    if (db)
+        hipLaunchKernelGGL(k_bias_grad, dim3(cout), dim3(kBlock), 0, s, (const u16*)dy, N, cout, db);
+    return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_conv3d_flip_weights(const float* wt, int32_t cin, int32_t cout, uint16_t* wf,
+                                   void* stream) {
+    if (!wt || !wf || cin < 1 || cout < 1) return AIR_ERR_INVALID_ARG;
+    const int total = cin * 27 * cout;
+    hipLaunchKernelGGL(k_flip_weights, dim3((total + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                       (hipStream_t)stream, wt, cin, cout, (u16*)wf);
+    return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_cast_bf16(const float* x, uint16_t* y, int64_t n, void* stream) {
+    if (!x || !y || n < 0) return AIR_ERR_INVALID_ARG;
+    if (n == 0) return AIR_OK;
+    hipLaunchKernelGGL(k_cast_bf16, dim3(grid1(n)), dim3(kBlock), 0, (hipStream_t)stream, x, (u16*)y, n);
+    return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_pool2(const uint16_t* x, const int32_t dims[3], int32_t c, int32_t ldx,
+                     int32_t xoff, uint16_t* y, void* stream) {
+    if (!x || !dims || !y || c < 1 || xoff < 0 || ldx < xoff + c) return AIR_ERR_INVALID_ARG;
+    if (dims[0] % 2 || dims[1] % 2 || dims[2] % 2) return AIR_ERR_SHAPE;
+    const long long t = (long long)dims[0] * dims[1] * dims[2] / 8 * c;
+    hipLaunchKernelGGL(k_pool2, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream, (const u16*)x,
+                       dims[0], dims[1], dims[2], c, ldx, xoff, (u16*)y);
+    return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_pool2_bwd(const float* dy, const int32_t dims[3], int32_t c, float* dx,
+                         int32_t ldx, int32_t xoff, int32_t accumulate, void* stream) {
+    if (!dy || !dims || !dx || c < 1 || xoff < 0 || ldx < xoff + c) return AIR_ERR_INVALID_ARG;
+    if (dims[0] % 2 || dims[1] % 2 || dims[2] % 2) return AIR_ERR_SHAPE;
+    const long long t = (long long)dims[0] * dims[1] * dims[2] * c;
+    hipLaunchKernelGGL(k_pool2_bwd, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream, dy,
+                       dims[0], dims[1], dims[2], c, dx, ldx, xoff, accumulate);
+    return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_up2(const uint16_t* x, const int32_t dims[3], int32_t c, uint16_t* y, int32_t ldy,
+                   int32_t yoff, void* stream) {
+    if (!x || !dims || !y || c < 1 || ldy < yoff + c) return AIR_ERR_INVALID_ARG;
+    const long long t = 8LL * dims[0] * dims[1] * dims[2] * c;
+    hipLaunchKernelGGL(k_up2, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream, (const u16*)x,
+                       dims[0], dims[1], dims[2], c, (u16*)y, ldy, yoff);
+    return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_up2_bwd(const float* dy, const int32_t dims[3], int32_t c, int32_t ldy,
+                       int32_t yoff, float* dx, void* stream) {
+    if (!dy || !dims || !dx || c < 1 || ldy < yoff + c) return AIR_ERR_INVALID_ARG;
+    const long long t = (long long)dims[0] * dims[1] * dims[2] * c;
+    hipLaunchKernelGGL(k_up2_bwd, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream, dy,
+                       dims[0], dims[1], dims[2], c, ldy, yoff, dx);
+    return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_lrelu_bwd(const float* dy, int32_t ld, int32_t off, const uint16_t* yact,
+                         int32_t ldyact, int32_t yoff, int64_t nvox, int32_t c, uint16_t* dx,
+                         void* stream) {
+    if (!dy || !yact || !dx || c < 1 || nvox < 0) return AIR_ERR_INVALID_ARG;
+    if (ld < off + c || ldyact < yoff + c) return AIR_ERR_SHAPE;
+    hipLaunchKernelGGL(k_lrelu_bwd, dim3(grid1(nvox * c)), dim3(kBlock), 0, (hipStream_t)stream, dy,
+                       ld, off, (const u16*)yact, ldyact, yoff, nvox, c, (u16*)dx);
+    return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_cnn_input(const float* fixed, const float* moving, const int32_t dims[3],
+                         uint16_t* x, void* stream) {
+    if (!fixed || !moving || !dims || !x) return AIR_ERR_INVALID_ARG;
+    if (dims[0] % 2 || dims[1] % 2 || dims[2] % 2) return AIR_ERR_SHAPE;
+    const long long t = (long long)dims[0] * dims[1] * dims[2] / 8;
+    hipLaunchKernelGGL(k_cnn_input, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream, fixed,
+                       moving, dims[0], dims[1], dims[2], (u16*)x);
+    return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_cnn_output(const float* g, const int32_t gdims[3], int32_t ld, float scale,
+                          float* theta, void* stream) {
+    if (!g || !gdims || !theta || ld < 3) return AIR_ERR_INVALID_ARG;
+    const long long t = 3LL * (gdims[0] + 3) * (gdims[1] + 3) * (gdims[2] + 3);
+    hipLaunchKernelGGL(k_cnn_output, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream, g,
+                       gdims[0], gdims[1], gdims[2], ld, scale, theta);
+    return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_cnn_output_bwd(const float* dtheta, const int32_t gdims[3], int32_t ld, float scale,
+                              float* dg, void* stream) {
+    if (!dtheta || !gdims || !dg || ld < 3) return AIR_ERR_INVALID_ARG;
+    const long long t = (long long)gdims[0] * gdims[1] * gdims[2] * ld;
+    hipLaunchKernelGGL(k_cnn_output_bwd, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream,
+                       dtheta, gdims[0], gdims[1], gdims[2], ld, scale, dg);
+    return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_add_f32(float* a, const float* b, int64_t n, void* stream) {
+    if (!a || !b || n < 0) return AIR_ERR_INVALID_ARG;
+    if (n == 0) return AIR_OK;
+    hipLaunchKernelGGL(k_add_f32, dim3(grid1(n)), dim3(kBlock), 0, (hipStream_t)stream, a, b, n);
+    return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+}  // extern "C"

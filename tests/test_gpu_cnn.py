@@ -1,0 +1,217 @@
+"""GPU checks of the learned-initialisation network's kernels against the
+FP64 oracle, on BF16-rounded operands (the kernels accumulate in FP32)."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1806_09907_amd import api, cnn
+from paper_1806_09907_amd._lib import check, lib
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def bf16_round(a):
+    """Round to bfloat16 (nearest even) and widen to float64."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def to_bf16_tensor(a):
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    return torch.from_numpy(u.view(np.int16)).to(DEV)
+
+
+def from_bf16_tensor(t):
+    u = t.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    return u.view(np.float32).astype(np.float64)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+SHAPES = [(8, 16, (10, 9, 11)), (16, 32, (7, 8, 9)), (32, 48, (6, 5, 7)),
+          (48, 64, (4, 4, 4)), (112, 48, (5, 6, 4)), (48, 16, (6, 6, 6))]
+
+
+@pytest.mark.parametrize("cin,cout,dims", SHAPES)
+def test_conv_forward_parity(cin, cout, dims):
+    rng = np.random.default_rng(cin + cout)
+    nx, ny, nz = dims
+    x = bf16_round(rng.normal(size=(nz, ny, nx, cin)))
+    wt = bf16_round(rng.normal(size=(cout, 27 * cin)) / np.sqrt(27 * cin))
+    b = rng.normal(size=cout).astype(np.float32).astype(np.float64)
+    for act in (0, 1):
+        y = torch.empty(nz * ny * nx * cout, dtype=torch.float32, device=DEV)
+        ybf = torch.empty(nz * ny * nx * cout, dtype=torch.int16, device=DEV)
+        cnn.conv_fwd(to_bf16_tensor(x), dims, cin, to_bf16_tensor(wt),
+                     torch.tensor(b, dtype=torch.float32, device=DEV), cout, act,
+                     y_bf=ybf, y_f32=y)
+        ref = O.conv3d_fwd(x, wt, b, act)
+        got = y.double().cpu().numpy().reshape(ref.shape)
+        assert rel(got, ref) <= 1e-5
+        # the bf16 copy is the FP32 output rounded to nearest even
+        assert np.array_equal(from_bf16_tensor(ybf).reshape(ref.shape), bf16_round(got))
+
+
+@pytest.mark.parametrize("cin,cout,dims", SHAPES)
+def test_conv_backward_parity(cin, cout, dims):
+    rng = np.random.default_rng(100 + cin + cout)
+    nx, ny, nz = dims
+    x = bf16_round(rng.normal(size=(nz, ny, nx, cin)))
+    wt = rng.normal(size=(cout, 27 * cin)).astype(np.float32).astype(np.float64)
+    dy = bf16_round(rng.normal(size=(nz, ny, nx, cout)))
+    # backward-data: the forward kernel with flipped weights
+    wf = torch.empty(cin * 27 * cout, dtype=torch.int16, device=DEV)
+    check(lib().air_conv3d_flip_weights(torch.tensor(wt, dtype=torch.float32, device=DEV).data_ptr(),
+                                        cin, cout, wf.data_ptr(), None), "flip")
+    dx = torch.empty(nz * ny * nx * cin, dtype=torch.float32, device=DEV)
+    cnn.conv_fwd(to_bf16_tensor(dy), dims, cout, wf, None, cin, 0, y_f32=dx)
+    rdx, rdw, rdb = O.conv3d_bwd(x, bf16_round(wt), dy)
+    assert rel(dx.double().cpu().numpy().reshape(rdx.shape), rdx) <= 1e-5
+    # backward-weight
+    dw = torch.empty((cout, 27 * cin), dtype=torch.float32, device=DEV)
+    db = torch.empty(cout, dtype=torch.float32, device=DEV)
+    ws = cnn.Workspace(torch.device(DEV))
+    cnn.conv_bwd_weight(to_bf16_tensor(x), dims, cin, to_bf16_tensor(dy), cout, dw, db, ws)
+    assert rel(dw.double().cpu().numpy(), rdw) <= 1e-5
+    assert rel(db.double().cpu().numpy(), rdb) <= 1e-5
+
+
+def test_pool_up_lrelu():
+    rng = np.random.default_rng(7)
+    n, c = 8, 16
+    x = bf16_round(rng.normal(size=(n, n, n, c)))
+    y = torch.empty((n // 2) ** 3 * c, dtype=torch.int16, device=DEV)
+    check(lib().air_pool2(to_bf16_tensor(x).data_ptr(), cnn._i3((n, n, n)), c, c, 0, y.data_ptr(),
+                          None), "pool")
+    ref = bf16_round(x.reshape(n // 2, 2, n // 2, 2, n // 2, 2, c).mean(axis=(1, 3, 5)))
+    assert np.array_equal(from_bf16_tensor(y).reshape(ref.shape), ref)
+    up = torch.empty(n ** 3 * c, dtype=torch.int16, device=DEV)
+    check(lib().air_up2(y.data_ptr(), cnn._i3((n // 2,) * 3), c, up.data_ptr(), c, 0, None), "up")
+    refu = np.repeat(np.repeat(np.repeat(ref, 2, 0), 2, 1), 2, 2)
+    assert np.array_equal(from_bf16_tensor(up).reshape(refu.shape), refu)
+    g = rng.normal(size=(n, n, n, c)).astype(np.float32)
+    gt = torch.from_numpy(g).to(DEV)
+    out = torch.empty(n ** 3 * c, dtype=torch.int16, device=DEV)
+    check(lib().air_lrelu_bwd(gt.data_ptr(), c, 0, to_bf16_tensor(x).data_ptr(), c, 0, n ** 3, c,
+                              out.data_ptr(), None), "lrelu")
+    refl = bf16_round(np.where(x > 0, g, 0.1 * g.astype(np.float64)))
+    assert np.array_equal(from_bf16_tensor(out).reshape(refl.shape), refl)
+
+
+# ---------------------------------------------------------------- whole network
+
+def oracle_net(params, F, M, dtheta, n):
+    """FP64 network with bf16 rounding at the points the kernels round."""
+    def conv(x, name, act):
+        return O.conv3d_fwd(x, bf16_round(params[name]["w"]), params[name]["b"], act)
+
+    def pool(x):
+        s = x.shape
+        return bf16_round(x.reshape(s[0] // 2, 2, s[1] // 2, 2, s[2] // 2, 2, s[3]).mean(axis=(1, 3, 5)))
+
+    def up(x):
+        return np.repeat(np.repeat(np.repeat(x, 2, 0), 2, 1), 2, 2)
+
+    h = n // 2
+    x0 = np.zeros((h, h, h, 8))
+    x0[..., 0] = F.reshape(h, 2, h, 2, h, 2).mean(axis=(1, 3, 5))
+    x0[..., 1] = M.reshape(h, 2, h, 2, h, 2).mean(axis=(1, 3, 5))
+    x0 = bf16_round(x0)
+    a1 = bf16_round(conv(x0, "e1", 1)); p1 = pool(a1)
+    a2 = bf16_round(conv(p1, "e2", 1)); p2 = pool(a2)
+    a3 = bf16_round(conv(p2, "e3", 1)); p3 = pool(a3)
+    a4 = bf16_round(conv(p3, "e4", 1))
+    cat = np.concatenate([a3, up(a4)], axis=3)
+    d1 = bf16_round(conv(cat, "d1", 1))
+    out = conv(d1, "d2", 0)
+    g = n // 8
+    idx = np.clip(np.arange(g + 3) - 1, 0, g - 1)
+    theta = cnn.OUT_SCALE * np.moveaxis(out[..., :3], 3, 0)[:, idx][:, :, idx][:, :, :, idx]
+    # backward
+    gout = np.zeros_like(out)
+    for c in range(3):
+        for jz in range(g + 3):
+            for jy in range(g + 3):
+                for jx in range(g + 3):
+                    gout[idx[jz], idx[jy], idx[jx], c] += cnn.OUT_SCALE * dtheta[c, jz, jy, jx]
+    grads = {}
+
+    def back(x, name, gy_pre):
+        wq = bf16_round(params[name]["w"])
+        dx, dw, db = O.conv3d_bwd(x, wq, gy_pre)
+        grads[name] = (dw, db)
+        return dx
+
+    def lrelu_b(g_, a):
+        return bf16_round(np.where(a > 0, g_, 0.1 * g_))
+
+    g_d1 = back(d1, "d2", bf16_round(gout))
+    g_cat = back(cat, "d1", lrelu_b(g_d1, d1))
+    g_a4 = g_cat[..., 48:].reshape(g // 2, 2, g // 2, 2, g // 2, 2, 64).sum(axis=(1, 3, 5))
+    g_p3 = back(p3, "e4", lrelu_b(g_a4, a4))
+    g_a3 = g_cat[..., :48] + up(g_p3) / 8.0
+    g_p2 = back(p2, "e3", lrelu_b(g_a3, a3))
+    g_p1 = back(p1, "e2", lrelu_b(up(g_p2) / 8.0, a2))
+    back(x0, "e1", lrelu_b(up(g_p1) / 8.0, a1))
+    return theta, grads
+
+
+def test_network_forward_backward_matches_oracle():
+    n = 32
+    net = cnn.InitNet(n=n, seed=3)
+    # give the output layer real weights so every path carries signal
+    rng = np.random.default_rng(4)
+    d2 = net.params["d2"]
+    w = np.zeros((16, 27 * 48), dtype=np.float32)
+    w[:3] = rng.normal(0, 0.05, size=(3, 27 * 48))
+    d2.w.copy_(torch.from_numpy(w))
+    net._refresh(d2, 48, 16)
+    F = rng.uniform(size=(n, n, n)).astype(np.float32)
+    M = rng.uniform(size=(n, n, n)).astype(np.float32)
+    theta = net.forward(torch.from_numpy(F).to(DEV), torch.from_numpy(M).to(DEV)).clone()
+    g = n // 8
+    dtheta = rng.normal(size=(3, g + 3, g + 3, g + 3)).astype(np.float32)
+    net.backward(torch.from_numpy(dtheta).to(DEV))
+    torch.cuda.synchronize()
+    params = {k: {"w": v.w.double().cpu().numpy(), "b": v.b.double().cpu().numpy()}
+              for k, v in net.params.items()}
+    ref_theta, ref_grads = oracle_net(params, F.astype(np.float64), M.astype(np.float64),
+                                      dtheta.astype(np.float64), n)
+    assert rel(theta.double().cpu().numpy(), ref_theta) <= 1e-2
+    for name in ("d2", "d1", "e4", "e3", "e2", "e1"):
+        dw, db = ref_grads[name]
+        gw = net.params[name].gw.double().cpu().numpy()
+        gb = net.params[name].gb.double().cpu().numpy()
+        print(name, rel(gw, dw), rel(gb, db))
+        assert rel(gw, dw) <= 2e-2, name
+        assert rel(gb, db) <= 2e-2, name
+
+
+def test_training_steps_reduce_objective():
+    """A few Adam steps on one pair lower the registration objective at the
+    predicted start (the network can learn through the hand-written adjoint)."""
+    from paper_1806_09907_amd import learned
+
+    n = 64
+    net = cnn.InitNet(n=n, seed=1)
+    gen = learned.PairGenerator(n, torch.device(DEV))
+    F, M, _ = gen.pair(12345)
+    prob = api.Problem(n=(n, n, n), spacing=(8, 8, 8), similarity=api.SIM_NCC, lambda_diff=0.05)
+    plan = api.Plan(prob)
+    vals = []
+    for _ in range(30):
+        th = net.forward(F, M)
+        v, gth = api.objective_and_grad(plan, F, M, th)
+        vals.append(float(v))
+        net.backward(gth)
+        net.adam_step(1e-3)
+    print(vals[0], vals[-1])
+    assert vals[-1] < vals[0]

@@ -498,3 +498,34 @@ def test_field_resample_matches_torch_interpolate(oracle):
     ref = torch.nn.functional.interpolate(torch.from_numpy(u)[None], size=(m[2], m[1], m[0]),
                                           mode="trilinear", align_corners=True)[0].numpy()
     assert np.max(np.abs(O.field_resample(u, m) - ref)) < 1e-13
+
+
+def _torch_weight(wt, cin):
+    cout = wt.shape[0]
+    # wt[co][tap*cin + ci], tap = (dz*3 + dy)*3 + dx -> weight[co][ci][dz][dy][dx]
+    return torch.from_numpy(wt.reshape(cout, 3, 3, 3, cin).transpose(0, 4, 1, 2, 3).copy())
+
+
+def test_conv3d_matches_torch(oracle):
+    """The network's convolution (3x3x3, stride 1, zero padding 1) equals
+    torch's conv3d in FP64, forward and backward (autograd)."""
+    rng = np.random.default_rng(18)
+    x = rng.normal(size=(5, 6, 7, 8))     # nz, ny, nx, cin
+    wt = rng.normal(size=(16, 27 * 8))
+    b = rng.normal(size=16)
+    for act in (0, 1):
+        y = O.conv3d_fwd(x, wt, b, act)
+        xt = torch.from_numpy(np.moveaxis(x, 3, 0)[None].copy()).requires_grad_(True)
+        W = _torch_weight(wt, 8).requires_grad_(True)
+        bt = torch.from_numpy(b).requires_grad_(True)
+        pre = torch.nn.functional.conv3d(xt, W, bt, padding=1)
+        out = torch.nn.functional.leaky_relu(pre, 0.1) if act else pre
+        ref = np.moveaxis(out[0].detach().numpy(), 0, 3)
+        assert np.max(np.abs(y - ref)) < 1e-12
+    g = rng.normal(size=y.shape)
+    pre.backward(torch.from_numpy(np.moveaxis(g, 3, 0)[None].copy()))
+    dx, dwt, db = O.conv3d_bwd(x, wt, g)
+    assert np.max(np.abs(dx - np.moveaxis(xt.grad[0].numpy(), 0, 3))) < 1e-11
+    ref_w = W.grad.numpy().transpose(0, 2, 3, 4, 1).reshape(16, 27 * 8)
+    assert np.max(np.abs(dwt - ref_w)) < 1e-10
+    assert np.max(np.abs(db - bt.grad.numpy())) < 1e-11
