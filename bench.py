@@ -1,18 +1,24 @@
 """Throughput benchmark of the registration objective + gradient on one MI355X.
 
-One step = one evaluation of the objective and its gradient for every pair of
-a batch of 64 distinct 128^3 pairs (cubic B-spline, spacing 8, NCC + 0.05
-diffusion), in one batched launch sequence, with every input resident in HBM.
-64 distinct pairs (1.08 GB) exceed the 256 MB Infinity Cache, so the inputs
-come from HBM rather than from the cache.
+Default workload (the headline): one step = objective and gradient of 64
+distinct 128^3 pairs (cubic B-spline, spacing 8, NCC + 0.05 diffusion) in one
+batched launch, inputs resident in HBM (1.08 GB, beyond the 256 MB Infinity
+Cache). Other workloads (--workload): `uneven48` (48 pairs with sides from
+{96..160} in one launch), `dense256` (256^3 dense field, MSE + 1.0 diffusion),
+`latency2d` (one 64^2 B-spline MSE pair per step).
 
-Prints one JSON line. `roofline` reports the dominant kernel (the fused
-B-spline kernel) from HIP events recorded around it on its own stream;
-`cpu_baseline` times the FP64 CPU oracle on a bounded sample.
+Prints one JSON line. `roofline` reports the dominant kernel from HIP events
+the library records around it on its own stream; `traffic` comes from
+committed FETCH_SIZE/WRITE_SIZE counter runs of the same kernel build (null
+when the kernel sources changed since). `cpu_baseline` times the FP64 CPU
+oracle on a bounded sample. The default run also reports the learned
+initialisation's time to the zero-init target MSE (`secondary`).
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -25,14 +31,35 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
-N3 = (128, 128, 128)
 SPACING = (8, 8, 8)
-LAMBDA = 0.05
-# algorithmic bytes of one evaluation at 128^3: F + M + theta + grad (FP32)
-NCTRL = 19 ** 3
-BYTES_EVAL = 4 * (2 * 128 ** 3 + 2 * 3 * NCTRL)
-# what the fused kernel must move per pair: F, M and theta
-BYTES_FUSED = 4 * (2 * 128 ** 3 + 3 * NCTRL)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def progress(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1806_09907_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(workload: str):
+    """HBM bytes per launch from committed counter runs, or None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    e = t.get(workload)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e["bytes_per_launch"]
 
 
 def parse():
@@ -40,55 +67,69 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="batch128",
+                    choices=["batch128", "uneven48", "dense256", "latency2d"])
     ap.add_argument("--pairs", type=int, default=64)
     ap.add_argument("--tiling", type=int, default=-1, help="-1: autotune cache or default")
     ap.add_argument("--autotune-out", default="",
                     help="time every tile configuration on this batch, write the cache here")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     return ap.parse_args()
 
 
-def make_batch(npairs, dev):
+def blob_batch(sizes, dev, seed_base=1):
+    """Blob pairs (40 blobs + noise) warped on the device by air_warp."""
     import torch
 
     from paper_1806_09907_amd import api, synth
 
-    probs = [api.Problem(n=N3, spacing=SPACING, similarity=api.SIM_NCC, lambda_diff=LAMBDA)
-             for _ in range(npairs)]
-    warp_plan = api.Plan(api.Problem(n=N3, spacing=SPACING, similarity=api.SIM_NCC))
-
-    def gpu_warp(n_xyz, spacing, moving32, theta32):
-        m = torch.from_numpy(moving32).to(dev)
-        t = torch.from_numpy(theta32).to(dev)
-        w, _ = api.warp(warp_plan, m, t, want_mask=False)
-        return w  # stays on the device
-
     Fs, Ms, Ts = [], [], []
-    for i in range(npairs):
-        rng = np.random.default_rng(synth.seed_for(1, i))
-        fixed = synth.blobs(tuple(reversed(N3)), 40, rng)
+    plans = {}
+    for i, n3 in enumerate(sizes):
+        rng = np.random.default_rng(synth.seed_for(seed_base, i))
+        fixed = synth.blobs(tuple(reversed(n3)), 40, rng)
         fixed = (fixed + rng.normal(0.0, 0.01, size=fixed.shape)).astype(np.float32)
-        theta_gen = synth.control_field(N3, SPACING, 3.0, rng).astype(np.float32)
-        Fs.append(torch.from_numpy(fixed).to(dev))
-        Ms.append(gpu_warp(N3, SPACING, fixed, theta_gen).contiguous())
-        # evaluation point: a random field of N(0, 1 voxel) controls
-        Ts.append(torch.from_numpy(synth.random_theta(N3, SPACING, 1.0, 5000 + i)).to(dev))
+        theta_gen = synth.control_field(n3, SPACING, 3.0, rng).astype(np.float32)
+        if n3 not in plans:
+            plans[n3] = api.Plan(api.Problem(n=n3, spacing=SPACING, similarity=api.SIM_NCC))
+        F = torch.from_numpy(fixed).to(dev)
+        M, _ = api.warp(plans[n3], F, torch.from_numpy(theta_gen).to(dev), want_mask=False)
+        Fs.append(F)
+        Ms.append(M)
+        Ts.append(torch.from_numpy(synth.random_theta(n3, SPACING, 1.0, 5000 + i)).to(dev))
     torch.cuda.synchronize()
-    return probs, Fs, Ms, Ts
+    return Fs, Ms, Ts
 
 
-def cpu_baseline(seconds):
-    """FP64 oracle on one 128^3 pair, repeated until `seconds` have elapsed."""
+def cpu_baseline(seconds, workload):
+    """FP64 oracle on one pair of the workload, repeated for `seconds`."""
     import oracle as O
     from paper_1806_09907_amd import synth
 
-    pair = synth.pair_3d(warp=O.warp_fn_fp32)
-    p = O.Problem(n=N3, spacing=SPACING, similarity=O.SIM_NCC, lambda_diff=LAMBDA)
-    th = synth.random_theta(N3, SPACING, 1.0, 5000)
-    O.objective_and_grad(p, pair.fixed, pair.moving, th)  # warm-up
+    if workload == "dense256":
+        n3 = (128, 128, 128)
+        pair = synth.ct_pair(128, None, O.warp_fn_fp32)
+        p = O.Problem(n=n3, transform=O.TF_DENSE, spacing=(1, 1, 1), similarity=O.SIM_MSE,
+                      lambda_diff=1.0)
+        th = synth.smooth_dense(n3, 2.0, 77)
+        desc = "one 128^3 dense MSE pair (the 256^3 workload's level below)"
+    elif workload == "latency2d":
+        n3 = (64, 64)
+        pair = synth.pair_2d(warp=O.warp_fn_fp32)
+        p = O.Problem(n=n3, spacing=(8, 8), similarity=O.SIM_MSE, lambda_diff=0.1)
+        th = synth.random_theta(n3, (8, 8), 1.0, 5000)
+        desc = "one 64^2 B-spline MSE pair"
+    else:
+        n3 = (128, 128, 128)
+        pair = synth.pair_3d(warp=O.warp_fn_fp32)
+        p = O.Problem(n=n3, spacing=SPACING, similarity=O.SIM_NCC, lambda_diff=0.05)
+        th = synth.random_theta(n3, SPACING, 1.0, 5000)
+        desc = "one 128^3 B-spline NCC pair"
+    O.objective_and_grad(p, pair.fixed, pair.moving, th)
     n = 0
     t0 = time.perf_counter()
     while True:
@@ -98,8 +139,7 @@ def cpu_baseline(seconds):
         if el >= seconds:
             break
     return {"value": n / el, "unit": "evals/s", "cores": O.get_threads(), "kind": "oracle",
-            "sample": f"{n} evaluations of one 128^3 B-spline NCC pair in {el:.1f} s "
-                      f"(FP64, OpenMP over z-slabs)"}
+            "sample": f"{n} evaluations of {desc} in {el:.1f} s (FP64, OpenMP over slabs)"}
 
 
 def copy_calibration():
@@ -114,6 +154,184 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}))
 
 
+def timed(plan, steps, warmup, call):
+    import torch
+
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    plan.timing(steps)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        call()
+    stop.record()
+    torch.cuda.synchronize()
+    ms_total = start.elapsed_time(stop)
+    k_ms, k_n = plan.timing_read()
+    plan.timing(0)
+    return ms_total / steps, k_ms / max(k_n, 1)
+
+
+def run_batch(args, dev, sizes, workload, desc):
+    import torch
+
+    from paper_1806_09907_amd import api, tune
+
+    probs = [api.Problem(n=n3, spacing=SPACING, similarity=api.SIM_NCC, lambda_diff=0.05)
+             for n3 in sizes]
+    progress(f"painting {len(sizes)} pairs")
+    Fs, Ms, Ts = blob_batch(sizes, dev)
+    plan = api.Plan(probs)
+    if args.autotune_out:
+        rep = tune.autotune(plan, Fs, Ms, Ts, reps=10, cache_path=args.autotune_out, verbose=True)
+        print(json.dumps({"autotune": {k: v for k, v in rep.items() if k != "candidates"}}),
+              flush=True)
+    else:
+        tiling = args.tiling if args.tiling >= 0 else tune.cached_tiling(plan)
+        if tiling is not None:
+            plan.set_tiling(tiling)
+    plan.prepare()
+    values = torch.empty(len(sizes), dtype=torch.float32, device=dev)
+    _, _, table = api.objective_and_grad_batched(plan, Fs, Ms, Ts, values)
+    progress("timing")
+    ms_step, kern_ms = timed(plan, args.steps, args.warmup,
+                             lambda: api.objective_and_grad_batched(plan, None, None, None, values,
+                                                                    table=table))
+    flags = api.get_flags(plan)
+    if any(flags):
+        raise RuntimeError(f"objective flags set: {flags}")
+    vox = sum(int(np.prod(n3)) for n3 in sizes)
+    nctrl = sum(int(np.prod([(n - 1) // 8 + 4 for n in n3])) for n3 in sizes)
+    bytes_eval = 4 * (2 * vox + 2 * 3 * nctrl)      # F + M + theta + grad
+    bytes_fused = 4 * (2 * vox + 3 * nctrl)         # what the fused kernel must move
+    achieved = bytes_fused / (kern_ms / 1e3) / 1e9
+    traffic = traffic_for(workload)
+    return {
+        "metric": "objective+grad evals/s at 128^3 B-spline NCC" if workload == "batch128"
+        else f"objective+grad evals/s, {desc}",
+        "value": len(sizes) * 1e3 / ms_step,
+        "unit": "evals/s",
+        "ms_per_step": ms_step,
+        "config": {"workload": desc, "pairs_per_step": len(sizes),
+                   "n": list(sizes[0]) if len(set(sizes)) == 1 else "uneven",
+                   "voxels_per_step": vox, "spacing": 8, "tiling": plan.tiling,
+                   "algorithmic_bytes_per_step": bytes_eval,
+                   "step_hbm_gbs": bytes_eval / (ms_step / 1e3) / 1e9},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "kernel": "k_fused3_s8 (NCC)", "kernel_ms": kern_ms,
+                     "algorithmic_bytes_per_launch": bytes_fused},
+    }
+
+
+def gpu_warp_fn(dev):
+    """A warp callable for the synthetic pair recipes, run by the library."""
+    import torch
+
+    from paper_1806_09907_amd import api
+
+    plans = {}
+
+    def warp(n_xyz, spacing, moving32, theta32):
+        key = (tuple(n_xyz), tuple(spacing))
+        if key not in plans:
+            plans[key] = api.Plan(api.Problem(n=key[0], spacing=key[1], similarity=api.SIM_MSE))
+        m = torch.from_numpy(np.ascontiguousarray(moving32)).to(dev)
+        t = torch.from_numpy(np.ascontiguousarray(theta32)).to(dev)
+        w, _ = api.warp(plans[key], m, t, want_mask=False)
+        return w.cpu().numpy()
+
+    return warp
+
+
+def run_dense(args, dev):
+    import torch
+
+    from paper_1806_09907_amd import api, synth
+
+    n3 = (256, 256, 256)
+    progress("painting the 256^3 CT-like pair")
+    pair = synth.ct_pair(256, None, gpu_warp_fn(dev))
+    F = torch.from_numpy(pair.fixed).to(dev)
+    M = torch.from_numpy(pair.moving).to(dev)
+    th = torch.from_numpy(synth.smooth_dense(n3, 2.0, 77)).to(dev)
+    plan = api.Plan(api.Problem(n=n3, transform=api.TF_DENSE, spacing=(1, 1, 1),
+                                similarity=api.SIM_MSE, lambda_diff=1.0))
+    plan.prepare()
+    value = torch.empty((), dtype=torch.float32, device=dev)
+    grad = torch.empty_like(th)
+    progress("timing")
+    ms_step, kern_ms = timed(plan, args.steps, args.warmup,
+                             lambda: api.objective_and_grad(plan, F, M, th, value, grad))
+    vox = 256 ** 3
+    bytes_eval = 4 * (2 * vox + 6 * vox)   # F, M, u (3 components), gradient (3)
+    achieved = bytes_eval / (kern_ms / 1e3) / 1e9
+    return {
+        "metric": "objective+grad evals/s, 256^3 dense MSE + 1.0 diffusion",
+        "value": 1e3 / ms_step, "unit": "evals/s", "ms_per_step": ms_step,
+        "config": {"workload": "256^3 CT-like dense field, MSE + 1.0 diffusion, one pair per step",
+                   "n": list(n3), "algorithmic_bytes_per_step": bytes_eval,
+                   "step_hbm_gbs": bytes_eval / (ms_step / 1e3) / 1e9},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_for("dense256"),
+                     "kernel": "k_dense_main (MSE)", "kernel_ms": kern_ms,
+                     "algorithmic_bytes_per_launch": bytes_eval},
+    }
+
+
+def run_latency2d(args, dev):
+    import torch
+
+    from paper_1806_09907_amd import api, synth
+
+    n = (64, 64)
+    pair = synth.pair_2d(warp=gpu_warp_fn(dev))
+    plan = api.Plan(api.Problem(n=n, spacing=(8, 8), similarity=api.SIM_MSE, lambda_diff=0.1))
+    F = torch.from_numpy(pair.fixed).to(dev)
+    M = torch.from_numpy(pair.moving).to(dev)
+    th = torch.from_numpy(synth.random_theta(n, (8, 8), 1.0, 5000)).to(dev)
+    plan.prepare()
+    value = torch.empty((), dtype=torch.float32, device=dev)
+    grad = torch.empty_like(th)
+    ms_step, kern_ms = timed(plan, args.steps, args.warmup,
+                             lambda: api.objective_and_grad(plan, F, M, th, value, grad))
+    bytes_eval = 4 * (2 * 64 * 64 + 2 * 2 * 11 * 11)
+    achieved = bytes_eval / (kern_ms / 1e3) / 1e9
+    return {
+        "metric": "objective+grad evals/s, 64^2 B-spline MSE + 0.1 diffusion (latency)",
+        "value": 1e3 / ms_step, "unit": "evals/s", "ms_per_step": ms_step,
+        "config": {"workload": "64^2 blobs, B-spline spacing 8, one pair per step",
+                   "n": list(n), "algorithmic_bytes_per_step": bytes_eval,
+                   "us_per_eval": ms_step * 1e3},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "k_fused2 (MSE)", "kernel_ms": kern_ms,
+                     "note": "launch-latency bound; the figure of merit is us_per_eval"},
+    }
+
+
+def learned_secondary(dev):
+    """Train the initialisation network (2000 pairs x 2 epochs) and evaluate
+    time to the zero-init target MSE on 100 held-out 128^3 pairs."""
+    from paper_1806_09907_amd import learned
+    from paper_1806_09907_amd.cnn import InitNet
+
+    net = InitNet(n=128, device=dev, seed=0)
+    tr = learned.train(net, pairs=2000, epochs=2, warmup=300, log=None, log_every=0)
+    ev = learned.evaluate(net, npairs=100, iters=200, log=None)
+    return {"metric": "time to zero-init target MSE, learned vs plain (128^3 NCC)",
+            "unit": "ms", "higher_is_better": False,
+            "learned_mean_ms": ev["mean_time_learned_ms"], "zero_mean_ms": ev["mean_time_zero_ms"],
+            "median_speedup": ev["median_speedup"], "mean_speedup": ev["mean_speedup"],
+            "fraction_reached": ev["fraction_reached"],
+            "fallback_judge": ev["fallback_judge"],
+            "fallback_not_reached": ev["fallback_not_reached"],
+            "train_seconds": tr["seconds"], "heldout_pairs": ev["pairs"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -125,81 +343,34 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
-    from paper_1806_09907_amd import api, tune
-
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    probs, Fs, Ms, Ts = make_batch(args.pairs, dev)
-    plan = api.Plan(probs)
-    if args.autotune_out:
-        rep = tune.autotune(plan, Fs, Ms, Ts, reps=10, cache_path=args.autotune_out, verbose=True)
-        print(json.dumps({"autotune": rep}), flush=True)
-    tiling = args.tiling if args.tiling >= 0 else tune.cached_tiling(plan)
-    if tiling is not None and not args.autotune_out:
-        plan.set_tiling(tiling)
-    plan.prepare()
-    values = torch.empty(args.pairs, dtype=torch.float32, device=dev)
-    grads = [torch.empty_like(t) for t in Ts]
-    _, _, table = api.objective_and_grad_batched(plan, Fs, Ms, Ts, values, grads)
-    for _ in range(args.warmup):
-        api.objective_and_grad_batched(plan, None, None, None, values, table=table)
-    torch.cuda.synchronize()
-    plan.timing(args.steps)
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
-        api.objective_and_grad_batched(plan, None, None, None, values, table=table)
-    stop.record()
-    torch.cuda.synchronize()
-    ms_total = start.elapsed_time(stop)
-    k_ms, k_n = plan.timing_read()
-    plan.timing(0)
-    flags = api.get_flags(plan)
-    if any(flags):
-        raise RuntimeError(f"objective flags set: {flags}")
-    ms_step = ms_total / args.steps
-    evals = args.pairs * args.steps / (ms_total / 1e3)
-    kern_ms = k_ms / max(k_n, 1)
-    achieved = BYTES_FUSED * args.pairs / (kern_ms / 1e3) / 1e9
-    out = {
-        "metric": "objective+grad evals/s at 128^3 B-spline NCC",
-        "value": evals,
-        "unit": "evals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "fp32",
-        "data": "synthetic",
-        "config": {
-            "workload": "128^3 cubic B-spline (spacing 8) NCC + 0.05 diffusion, objective "
-                        "and gradient of 64 distinct blob pairs per step in one batched launch",
-            "pairs_per_step": args.pairs,
-            "n": list(N3),
-            "spacing": SPACING[0],
-            "tiling": plan.tiling,
-            "algorithmic_bytes_per_eval": BYTES_EVAL,
-            "step_hbm_gbs": BYTES_EVAL * args.pairs / (ms_step / 1e3) / 1e9,
-        },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": PEAK_HBM_GBS,
-            "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS,
-            "traffic": None,
-            "kernel": "k_fused3 (NCC)",
-            "kernel_ms": kern_ms,
-        },
-    }
+    if args.workload == "batch128":
+        out = run_batch(args, dev, [(128, 128, 128)] * args.pairs, "batch128",
+                        f"128^3 cubic B-spline (spacing 8) NCC + 0.05 diffusion, objective and "
+                        f"gradient of {args.pairs} distinct blob pairs per step in one batched "
+                        f"launch")
+    elif args.workload == "uneven48":
+        from paper_1806_09907_amd import synth
+
+        out = run_batch(args, dev, synth.uneven_sizes(48), "uneven48",
+                        "48 uneven 3D pairs (sides from {96,112,128,144,160}), B-spline NCC + "
+                        "0.05 diffusion, one launch")
+    elif args.workload == "dense256":
+        out = run_dense(args, dev)
+    else:
+        out = run_latency2d(args, dev)
+    line = {"metric": out["metric"], "value": out["value"], "unit": out["unit"], "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": out["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+            "data": "synthetic", "config": out["config"], "roofline": out["roofline"]}
+    if args.workload == "batch128" and not args.no_learned:
+        progress("training and evaluating the learned initialisation")
+        line["secondary"] = learned_secondary(dev)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+        progress("timing the CPU oracle")
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, args.workload)
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":
