@@ -30,32 +30,23 @@ hipError_t launch_adam(float* th, const float* g, float* m, float* v, long long 
                        float b1, float b2, float inv_sqrt_bc2, float eps, hipStream_t s);
 hipError_t launch_scale(float* x, const float* s, long long n, hipStream_t st);
 
-// Tile configurations of the fused B-spline kernel: {TX, TY, column cells,
-// minimum waves per SIMD requested from the register allocator (1 = no
-// limit)}. The kernel variant follows from the shape and the spacing: a
-// spacing-8 specialisation for cell-aligned (32 x 8, 16 x 16) tiles, else the
-// generic kernel (which ignores the occupancy request).
+// Tile configurations of the fused B-spline kernel: {TX, TY, column cells}.
+// The kernel variant follows from the shape and the spacing: a spacing-8
+// specialisation for cell-aligned (32 x 8, 16 x 16) tiles, else the generic
+// kernel.
 struct TileCfg {
-    int tx, ty, cells, wpe;
+    int tx, ty, cells;
 };
 static const TileCfg kCfg3[] = {
-    {32, 8, 4, 1}, {32, 8, 8, 1}, {32, 8, 16, 1}, {64, 4, 4, 1}, {64, 4, 16, 1},
-    {16, 16, 4, 1}, {16, 16, 16, 1}, {32, 8, 2, 1}, {16, 16, 8, 1}, {16, 16, 2, 1},
-    {32, 8, 4, 3}, {32, 8, 8, 3}, {16, 16, 4, 3}, {16, 16, 8, 3},
-    {32, 8, 4, 4}, {32, 8, 8, 4}, {16, 16, 4, 4}, {16, 16, 8, 4},
+    {32, 8, 4}, {32, 8, 8}, {32, 8, 16}, {64, 4, 4}, {64, 4, 16},
+    {16, 16, 4}, {16, 16, 16}, {32, 8, 2}, {16, 16, 8}, {16, 16, 2},
 };
-static const TileCfg kCfg2[] = {{64, 1, 2, 1}, {64, 1, 4, 1}, {64, 1, 8, 1}, {64, 1, 16, 1}};
+static const TileCfg kCfg2[] = {{64, 1, 2}, {64, 1, 4}, {64, 1, 8}, {64, 1, 16}};
 
 // kernel variant ids understood by launch_bspline (3D)
 static int variant_of(const TileCfg& c, bool all_s8) {
-    if (c.tx == 32 && c.ty == 8) {
-        if (!all_s8) return 0;
-        return c.wpe >= 4 ? 7 : (c.wpe == 3 ? 5 : 3);
-    }
-    if (c.tx == 16 && c.ty == 16) {
-        if (!all_s8) return 2;
-        return c.wpe >= 4 ? 8 : (c.wpe == 3 ? 6 : 4);
-    }
+    if (c.tx == 32 && c.ty == 8) return all_s8 ? 3 : 0;
+    if (c.tx == 16 && c.ty == 16) return all_s8 ? 4 : 2;
     return 1;  // 64 x 4
 }
 constexpr int kNumCfg3 = sizeof(kCfg3) / sizeof(kCfg3[0]);

@@ -6,6 +6,7 @@
 namespace air {
 
 typedef float v2f __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 // Buffer resource over [base, base + bytes) for raw (untyped) loads. The
 // operands are made wave-uniform explicitly so that the descriptor lives in

@@ -19,6 +19,8 @@
 // The per-tile partials are combined by k_finalize in a fixed order
 // (deterministic), together with the regulariser computed exactly in control
 // space from banded Gram matrices (blocks appended to the same launch).
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace air {
@@ -409,14 +411,17 @@ k_fused3(const LaunchCtx C) {
 // --------------------------------------------------------------- fused 3D, spacing 8
 // The same computation as k_fused3 for control spacing 8 on every axis with
 // cell-aligned tiles (TX, TY multiples of 8): the cell structure and the
-// cubic weights w_k(r/8) are compile-time, the column loop is unrolled per
-// cell, and the LDS transposes read each staged value once.
+// cubic weights w_k(r/8) are compile-time, the voxel body is branch-free, the
+// gathers of the next layer are in flight while the current one finishes,
+// the per-plane register slots rotate instead of shifting, and the LDS
+// transposes read each staged value once. The kernel is bound by VALU issue
+// (about 125 vector instructions per voxel for NCC), not by HBM.
 struct W8 {
-    float w[8][4];
+    float w[9][4];  // row 8 (t = 1) is the next cell's first layer
 };
 constexpr W8 make_w8() {
     W8 t{};
-    for (int r = 0; r < 8; ++r) {
+    for (int r = 0; r <= 8; ++r) {
         const double x = r / 8.0;
         t.w[r][0] = (float)((1 - x) * (1 - x) * (1 - x) / 6.0);
         t.w[r][1] = (float)((3 * x * x * x - 6 * x * x + 4) / 6.0);
@@ -427,8 +432,8 @@ constexpr W8 make_w8() {
 }
 constexpr W8 kW8 = make_w8();
 
-template <int TX, int TY, int SIM, int WPE>
-__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+template <int TX, int TY, int SIM>
+__global__ void __launch_bounds__(TX* TY)
 k_fused3_s8(const LaunchCtx C) {
     constexpr int S = 8;
     constexpr int NT = TX * TY;
@@ -532,13 +537,19 @@ k_fused3_s8(const LaunchCtx C) {
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int k = 0; k < 4; ++k) V[c][k] = vcol(c, k);
-    float acc[NF][3][4];
+    v4f acc[NF][3];
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) acc[f][c][k] = 0.f;
+        for (int c = 0; c < 3; ++c) acc[f][c] = v4f{0.f, 0.f, 0.f, 0.f};
+    // Accumulator and control slots rotate with the cell: control plane kz
+    // (local) lives in slot kz mod 4 of V and of every acc, so moving to the
+    // next cell only refills one slot. The cell loop is unrolled four times
+    // to keep every slot index a compile-time constant.
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
 
     float cnt = 0.f;
     float m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f;
@@ -556,11 +567,9 @@ k_fused3_s8(const LaunchCtx C) {
     const float* Fcol = F + (long long)yc * nx + xc;
     const long long nxy = (long long)nx * ny;
 
-    auto flush = [&](int kzl) {
-#pragma unroll
-        for (int f = 0; f < NF; ++f)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) E[((f * 3 + c) * TY + ly) * TX + lx] = acc[f][c][0];
+    // y and x passes of control plane kzl, whose z sums the threads have
+    // written to E
+    auto flush_xy = [&](int kzl) {
         __syncthreads();
         // y: task (fc, lane column q) -> WYC outputs
         for (int task = tid; task < FC * TX; task += NT) {
@@ -603,156 +612,161 @@ k_fused3_s8(const LaunchCtx C) {
         }
     };
 
-    for (int cz = cz_b; cz < cz_e; ++cz) {
-        const int kzl = cz - cz0;
-        // Two-stage pipeline over the cell's S layers: stage 1 of layer r + 1
-        // (sample point, cell, its four gathers) is issued before stage 2 of
-        // layer r (interpolation, statistics, adjoint), so two layers of
-        // gathers are in flight.
-        struct Prep {
-            v2f a00, a10, a01, a11;
-            float fx, fy, fz, m, Fv;
-            bool ex, ey, ez;
+    // Two-stage pipeline over the layers: stage 1 of the next layer (sample
+    // point, cell, its four gathers) is issued before stage 2 of the current
+    // one (interpolation, statistics, adjoint), so two layers of gathers are
+    // in flight.
+    struct Prep {
+        v2f a00, a10, a01, a11;
+        float fx, fy, fz, m, Fv;
+        bool ex, ey, ez;
+    };
+    int cz = cz_b;
+    // a running statistic that depends on the previous layer's gathers
+    auto dep = [&]() -> float { return SIM == AIR_SIM_NCC ? m2 : m1; };
+    // stage 1 of layer r of cell cz; tap k of the cell is V slot (k + PH) & 3
+    auto prep = [&](int r, float dv, auto ph) -> Prep {
+        constexpr int PH = decltype(ph)::value;
+        // Branch-free: the sample point is clamped into the volume so every
+        // load is in range; m = 1 inside the mask, 0 outside (or for
+        // lanes / layers past the volume) scales every contribution.
+        const int z = cz * S + r;
+        Prep q;
+        q.Fv = __builtin_nontemporal_load(Fcol + (long long)min(z, nz - 1) * nxy);
+        float w0 = kW8.w[r][0], w1 = kW8.w[r][1], w2 = kW8.w[r][2], w3 = kW8.w[r][3];
+        float sx_ = snx, sy_ = sny, sz_ = snz;
+        // every uniform input of this stage passes through an empty asm that
+        // also reads `dv` (produced by the previous layer's stage 2), so
+        // neither the arithmetic nor the gathers of this layer can be
+        // hoisted more than one layer ahead of their use
+        asm volatile("" : "+s"(w0), "+s"(w1), "+s"(w2), "+s"(w3), "+s"(sx_), "+s"(sy_),
+                          "+s"(sz_) : "v"(dv));
+        float u[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            u[c] = w0 * V[c][PH] + w1 * V[c][(PH + 1) & 3] + w2 * V[c][(PH + 2) & 3] +
+                   w3 * V[c][(PH + 3) & 3];
+        const float px = fmaf(u[0], sx_, xf);
+        const float py = fmaf(u[1], sy_, yf);
+        const float pz = fmaf(u[2], sz_, (float)z);
+        const bool in = act && z < nz && (__float_as_uint(px) <= limx) &&
+                        (__float_as_uint(py) <= limy) && (__float_as_uint(pz) <= limz);
+        q.m = in ? 1.f : 0.f;
+        const float qx = __builtin_amdgcn_fmed3f(px, 0.f, nxm1);
+        const float qy = __builtin_amdgcn_fmed3f(py, 0.f, nym1);
+        const float qz = __builtin_amdgcn_fmed3f(pz, 0.f, nzm1);
+        // q >= 0, so truncation is floor; the last voxel uses the cell
+        // [n-2, n-1] with f = 1 and a right-sided (zero-padded) derivative
+        const int tx_ = (int)qx, ty_ = (int)qy, tz_ = (int)qz;
+        q.ex = tx_ == nx - 1;
+        q.ey = ty_ == ny - 1;
+        q.ez = tz_ == nz - 1;
+        const int jx = min(tx_, nx - 2), jy = min(ty_, ny - 2), jz = min(tz_, nz - 2);
+        q.fx = qx - (float)jx;
+        q.fy = qy - (float)jy;
+        q.fz = qz - (float)jz;
+        const int off = (int)(__umul24(__umul24(jz, ny) + jy, nx) + jx) * 4;
+        q.a00 = load2(rM, off, 0);
+        q.a10 = load2(rM, off, nx4);
+        q.a01 = load2(rM, off, nxy4);
+        q.a11 = load2(rM, off, nxy4 + nx4);
+        return q;
+    };
+    // stage 2 of layer r: interpolation, statistics and the z taps of the
+    // adjoint into acc slot (k + PH) & 3
+    auto finish = [&](int r, const Prep& q, auto ph) {
+        constexpr int PH = decltype(ph)::value;
+        const float w0 = kW8.w[r][0], w1 = kW8.w[r][1], w2 = kW8.w[r][2], w3 = kW8.w[r][3];
+        auto tap = [&](v4f& a, float g) {
+            a[PH] += w0 * g;
+            a[(PH + 1) & 3] += w1 * g;
+            a[(PH + 2) & 3] += w2 * g;
+            a[(PH + 3) & 3] += w3 * g;
         };
-        auto prep = [&](int r, float dep) -> Prep {
-            // Branch-free: the sample point is clamped into the volume so every
-            // load is in range; m = 1 inside the mask, 0 outside (or for
-            // lanes / layers past the volume) scales every contribution.
-            const int z = cz * S + r;
-            Prep q;
-            q.Fv = __builtin_nontemporal_load(Fcol + (long long)min(z, nz - 1) * nxy);
-            float w0 = kW8.w[r][0], w1 = kW8.w[r][1], w2 = kW8.w[r][2], w3 = kW8.w[r][3];
-            float sx_ = snx, sy_ = sny, sz_ = snz;
-            // every uniform input of this stage passes through an empty asm that
-            // also reads `dep` (produced by the previous layer's stage 2), so
-            // neither the arithmetic nor the gathers of this layer can be
-            // hoisted more than one layer ahead of their use
-            asm volatile("" : "+s"(w0), "+s"(w1), "+s"(w2), "+s"(w3), "+s"(sx_), "+s"(sy_),
-                              "+s"(sz_) : "v"(dep));
-            float u[3];
+        const float Fv = q.Fv;
+        const float m = q.m, fx = q.fx, fy = q.fy, fz = q.fz;
+        const v2f a00 = q.a00, a10 = q.a10, a01 = q.a01, a11 = q.a11;
+        const float dz00 = a01.x - a00.x, dz01 = a01.y - a00.y;
+        const float dz10 = a11.x - a10.x, dz11 = a11.y - a10.y;
+        const float e00 = a00.x + fz * dz00, e01 = a00.y + fz * dz01;
+        const float e10 = a10.x + fz * dz10, e11 = a10.y + fz * dz11;
+        const float dy0 = e10 - e00, dy1 = e11 - e01;
+        const float g0 = e00 + fy * dy0, g1 = e01 + fy * dy1;
+        const float W = g0 + fx * (g1 - g0);
+        const float h0 = dz00 + fy * (dz10 - dz00);
+        const float h1 = dz01 + fy * (dz11 - dz01);
+        float d[3];
+        d[0] = m * (q.ex ? -W : g1 - g0);
+        d[1] = m * (q.ey ? -W : dy0 + fx * (dy1 - dy0));
+        d[2] = m * (q.ez ? -W : h0 + fx * (h1 - h0));
+        cnt += m;
+        if (SIM == AIR_SIM_NCC) {
+            const float dF = m * (Fv - shF), dW = m * (W - shW);
+            m1 += dF;
+            m2 += dW;
+            m3 += dF * dF;
+            m4 += dW * dW;
+            m5 += dF * dW;
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                u[c] = w0 * V[c][0] + w1 * V[c][1] + w2 * V[c][2] + w3 * V[c][3];
-            const float px = fmaf(u[0], sx_, xf);
-            const float py = fmaf(u[1], sy_, yf);
-            const float pz = fmaf(u[2], sz_, (float)z);
-            const bool in = act && z < nz && (__float_as_uint(px) <= limx) &&
-                            (__float_as_uint(py) <= limy) && (__float_as_uint(pz) <= limz);
-            q.m = in ? 1.f : 0.f;
-            const float qx = __builtin_amdgcn_fmed3f(px, 0.f, nxm1);
-            const float qy = __builtin_amdgcn_fmed3f(py, 0.f, nym1);
-            const float qz = __builtin_amdgcn_fmed3f(pz, 0.f, nzm1);
-            // q >= 0, so truncation is floor; the last voxel uses the cell
-            // [n-2, n-1] with f = 1 and a right-sided (zero-padded) derivative
-            const int tx_ = (int)qx, ty_ = (int)qy, tz_ = (int)qz;
-            q.ex = tx_ == nx - 1;
-            q.ey = ty_ == ny - 1;
-            q.ez = tz_ == nz - 1;
-            const int jx = min(tx_, nx - 2), jy = min(ty_, ny - 2), jz = min(tz_, nz - 2);
-            q.fx = qx - (float)jx;
-            q.fy = qy - (float)jy;
-            q.fz = qz - (float)jz;
-            const int off = (int)(__umul24(__umul24(jz, ny) + jy, nx) + jx) * 4;
-            q.a00 = load2(rM, off, 0);
-            q.a10 = load2(rM, off, nx4);
-            q.a01 = load2(rM, off, nxy4);
-            q.a11 = load2(rM, off, nxy4 + nx4);
-            return q;
-        };
-        auto finish = [&](int r, const Prep& q) {
-            const float w0 = kW8.w[r][0], w1 = kW8.w[r][1], w2 = kW8.w[r][2], w3 = kW8.w[r][3];
-            const float Fv = q.Fv;
-            const float m = q.m, fx = q.fx, fy = q.fy, fz = q.fz;
-            const v2f a00 = q.a00, a10 = q.a10, a01 = q.a01, a11 = q.a11;
-            const float dz00 = a01.x - a00.x, dz01 = a01.y - a00.y;
-            const float dz10 = a11.x - a10.x, dz11 = a11.y - a10.y;
-            const float e00 = a00.x + fz * dz00, e01 = a00.y + fz * dz01;
-            const float e10 = a10.x + fz * dz10, e11 = a10.y + fz * dz11;
-            const float dy0 = e10 - e00, dy1 = e11 - e01;
-            const float g0 = e00 + fy * dy0, g1 = e01 + fy * dy1;
-            const float W = g0 + fx * (g1 - g0);
-            const float h0 = dz00 + fy * (dz10 - dz00);
-            const float h1 = dz01 + fy * (dz11 - dz01);
-            float d[3];
-            d[0] = m * (q.ex ? -W : g1 - g0);
-            d[1] = m * (q.ey ? -W : dy0 + fx * (dy1 - dy0));
-            d[2] = m * (q.ez ? -W : h0 + fx * (h1 - h0));
-            cnt += m;
-            if (SIM == AIR_SIM_NCC) {
-                const float dF = m * (Fv - shF), dW = m * (W - shW);
-                m1 += dF;
-                m2 += dW;
-                m3 += dF * dF;
-                m4 += dW * dW;
-                m5 += dF * dW;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const float gF = dF * d[c], gW = dW * d[c], g1_ = d[c];
-                    acc[0][c][0] += w0 * gF;
-                    acc[0][c][1] += w1 * gF;
-                    acc[0][c][2] += w2 * gF;
-                    acc[0][c][3] += w3 * gF;
-                    acc[1][c][0] += w0 * gW;
-                    acc[1][c][1] += w1 * gW;
-                    acc[1][c][2] += w2 * gW;
-                    acc[1][c][3] += w3 * gW;
-                    acc[NF - 1][c][0] += w0 * g1_;
-                    acc[NF - 1][c][1] += w1 * g1_;
-                    acc[NF - 1][c][2] += w2 * g1_;
-                    acc[NF - 1][c][3] += w3 * g1_;
-                }
-            } else {
-                const float e = m * (W - Fv);
-                m1 += e * e;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const float g = (W - Fv) * d[c];
-                    acc[0][c][0] += w0 * g;
-                    acc[0][c][1] += w1 * g;
-                    acc[0][c][2] += w2 * g;
-                    acc[0][c][3] += w3 * g;
-                }
+            for (int c = 0; c < 3; ++c) {
+                tap(acc[0][c], dF * d[c]);
+                tap(acc[1][c], dW * d[c]);
+                tap(acc[NF - 1][c], d[c]);
             }
-        };
-        // a running statistic that depends on the previous layer's gathers
-        auto dep = [&]() -> float { return SIM == AIR_SIM_NCC ? m2 : m1; };
-        Prep cur = prep(0, dep());
-#pragma unroll 2
-        for (int r = 0; r < S; ++r) {
-            Prep nxt = cur;
-            if (r + 1 < S) nxt = prep(r + 1, dep());
-            finish(r, cur);
-            cur = nxt;
+        } else {
+            const float e = m * (W - Fv);
+            m1 += e * e;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) tap(acc[0][c], (W - Fv) * d[c]);
         }
-        flush(kzl);
+    };
+    Prep A = prep(0, dep(), I0{});
+    // one cell (S layers) of local index kzl, whose first control plane is
+    // in slot PH = kzl & 3; afterwards that plane is complete and flushed,
+    // and its slots take control plane kzl + 4
+    auto cell = [&](int kzl, auto ph) {
+        constexpr int PH = decltype(ph)::value;
+        cz = cz0 + kzl;
+        // Double buffer without copies: B (odd layer) is issued before the
+        // even layer finishes, A (next even layer) before the odd one. Layer
+        // S of this cell (weights row t = 1, same V) is the next cell's layer
+        // 0; past the last cell it is a clamped, in-range dummy.
+        for (int r = 0; r < S; r += 2) {
+            Prep B = prep(r + 1, dep(), ph);
+            finish(r, A, ph);
+            A = prep(r + 2, dep(), ph);
+            finish(r + 1, B, ph);
+        }
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                acc[f][c][0] = acc[f][c][1];
-                acc[f][c][1] = acc[f][c][2];
-                acc[f][c][2] = acc[f][c][3];
-                acc[f][c][3] = 0.f;
+                E[((f * 3 + c) * TY + ly) * TX + lx] = acc[f][c][PH];
+                acc[f][c][PH] = 0.f;
             }
+        flush_xy(kzl);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            V[c][0] = V[c][1];
-            V[c][1] = V[c][2];
-            V[c][2] = V[c][3];
-            V[c][3] = (kzl + 4 < Wz) ? vcol(c, kzl + 4) : 0.f;
-        }
+        for (int c = 0; c < 3; ++c) V[c][PH] = (kzl + 4 < Wz) ? vcol(c, kzl + 4) : 0.f;
+    };
+    const int ncell = cz_e - cz_b;
+    for (int kzl = 0; kzl < ncell; kzl += 4) {
+        cell(kzl, I0{});
+        if (kzl + 1 < ncell) cell(kzl + 1, I1{});
+        if (kzl + 2 < ncell) cell(kzl + 2, I2{});
+        if (kzl + 3 < ncell) cell(kzl + 3, I3{});
     }
-    for (int k = Wz - 3; k < Wz; ++k) {
-        flush(k);
+    // the last three control planes, in slots (ncell + j) & 3
+    for (int j = 0; j < 3; ++j) {
+        const int sl = (ncell + j) & 3;
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                acc[f][c][0] = acc[f][c][1];
-                acc[f][c][1] = acc[f][c][2];
-                acc[f][c][2] = acc[f][c][3];
-                acc[f][c][3] = 0.f;
+                const v4f a = acc[f][c];
+                E[((f * 3 + c) * TY + ly) * TX + lx] =
+                    sl == 0 ? a[0] : (sl == 1 ? a[1] : (sl == 2 ? a[2] : a[3]));
             }
+        flush_xy(ncell + j);
     }
     double st[6] = {(double)cnt, (double)m1, (double)m2, (double)m3, (double)m4, (double)m5};
     block_sum<NT, 6>(st, red);
@@ -1192,10 +1206,10 @@ static hipError_t launch3(const LaunchCtx& C, size_t lds, hipStream_t s) {
     return hipSuccess;
 }
 
-template <int TX, int TY, int SIM, int WPE>
+template <int TX, int TY, int SIM>
 static hipError_t launch3s8(const LaunchCtx& C, size_t lds, hipStream_t s) {
     const int nblk = xcd_grid(C.ntiles_total, C.nreg_total);
-    hipLaunchKernelGGL((k_fused3_s8<TX, TY, SIM, WPE>), dim3(nblk), dim3(TX * TY), lds, s, C);
+    hipLaunchKernelGGL((k_fused3_s8<TX, TY, SIM>), dim3(nblk), dim3(TX * TY), lds, s, C);
     return hipGetLastError();
 }
 
@@ -1220,18 +1234,14 @@ hipError_t launch_bspline(const LaunchCtx& C, int cfg, size_t lds, int max_ctrl,
             case 0: e = ncc ? launch3<32, 8, 1>(C, lds, s) : launch3<32, 8, 0>(C, lds, s); break;
             case 1: e = ncc ? launch3<64, 4, 1>(C, lds, s) : launch3<64, 4, 0>(C, lds, s); break;
             case 2: e = ncc ? launch3<16, 16, 1>(C, lds, s) : launch3<16, 16, 0>(C, lds, s); break;
-            case 3: e = ncc ? launch3s8<32, 8, 1, 1>(C, lds, s) : launch3s8<32, 8, 0, 1>(C, lds, s); break;
-            case 4: e = ncc ? launch3s8<16, 16, 1, 1>(C, lds, s) : launch3s8<16, 16, 0, 1>(C, lds, s); break;
-            case 5: e = ncc ? launch3s8<32, 8, 1, 3>(C, lds, s) : launch3s8<32, 8, 0, 3>(C, lds, s); break;
-            case 6: e = ncc ? launch3s8<16, 16, 1, 3>(C, lds, s) : launch3s8<16, 16, 0, 3>(C, lds, s); break;
-            case 7: e = ncc ? launch3s8<32, 8, 1, 4>(C, lds, s) : launch3s8<32, 8, 0, 4>(C, lds, s); break;
-            case 8: e = ncc ? launch3s8<16, 16, 1, 4>(C, lds, s) : launch3s8<16, 16, 0, 4>(C, lds, s); break;
+            case 3: e = ncc ? launch3s8<32, 8, 1>(C, lds, s) : launch3s8<32, 8, 0>(C, lds, s); break;
+            case 4: e = ncc ? launch3s8<16, 16, 1>(C, lds, s) : launch3s8<16, 16, 0>(C, lds, s); break;
             default: return hipErrorInvalidValue;
         }
         if (e != hipSuccess) return e;
         if (ev1) (void)hipEventRecord(ev1, s);
         switch (cfg) {
-            case 0: case 3: case 5: case 7: return ncc ? launch_fin<32, 8, 1, 3>(C, max_ctrl, s) : launch_fin<32, 8, 0, 3>(C, max_ctrl, s);
+            case 0: case 3: return ncc ? launch_fin<32, 8, 1, 3>(C, max_ctrl, s) : launch_fin<32, 8, 0, 3>(C, max_ctrl, s);
             case 1: return ncc ? launch_fin<64, 4, 1, 3>(C, max_ctrl, s) : launch_fin<64, 4, 0, 3>(C, max_ctrl, s);
             default: return ncc ? launch_fin<16, 16, 1, 3>(C, max_ctrl, s) : launch_fin<16, 16, 0, 3>(C, max_ctrl, s);
         }
