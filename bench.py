@@ -111,12 +111,12 @@ def cpu_baseline(seconds, workload):
     from paper_1806_09907_amd import synth
 
     if workload == "dense256":
-        n3 = (128, 128, 128)
-        pair = synth.ct_pair(128, None, O.warp_fn_fp32)
+        n3 = (256, 256, 256)
+        pair = synth.ct_pair(256, None, O.warp_fn_fp32)
         p = O.Problem(n=n3, transform=O.TF_DENSE, spacing=(1, 1, 1), similarity=O.SIM_MSE,
                       lambda_diff=1.0)
         th = synth.smooth_dense(n3, 2.0, 77)
-        desc = "one 128^3 dense MSE pair (the 256^3 workload's level below)"
+        desc = "one 256^3 dense MSE pair"
     elif workload == "latency2d":
         n3 = (64, 64)
         pair = synth.pair_2d(warp=O.warp_fn_fp32)

@@ -12,6 +12,9 @@ constexpr int kMaxPairs = 4096;
 constexpr int kMaxSpacing = 64;
 constexpr int kBlock = 256;          // threads per block of every kernel
 constexpr int kStatWords = 8;        // doubles per tile statistics slot
+// dense-field passes: a block owns kDenseTX x kDenseTY voxels of (x, y) and
+// walks kDenseZc of z
+constexpr int kDenseTX = 64, kDenseTY = 4, kDenseZc = 32;
 
 // Per-pair constants, uploaded once per plan and device.
 struct PairDesc {

@@ -51,7 +51,6 @@ static int variant_of(const TileCfg& c, bool all_s8) {
 }
 constexpr int kNumCfg3 = sizeof(kCfg3) / sizeof(kCfg3[0]);
 constexpr int kNumCfg2 = sizeof(kCfg2) / sizeof(kCfg2[0]);
-constexpr int kDenseZc = 16;
 constexpr int kGenericSlots = 1024;
 constexpr size_t kMaxLds = 64 * 1024;
 constexpr int kMaxDevices = 64;
@@ -257,7 +256,7 @@ static air_status build_tables(air_plan* P) {
             lds_r = std::max(lds_r, 8 * sizeof(double) * (kBlock / 64) + 4 * reg);
             stats_n = tiles;
         } else {
-            const int nbx = cdiv(D.n[0], 64), nby = cdiv(D.n[1], 4);
+            const int nbx = cdiv(D.n[0], kDenseTX), nby = cdiv(D.n[1], kDenseTY);
             const int nbz = d == 3 ? cdiv(D.n[2], kDenseZc) : 1;
             D.dense_nblk = nbx * nby * nbz;
             D.dense_blk_off = (int)dense_n;

@@ -8,13 +8,14 @@
 //         (Sec. II-A eq. diffusion_regularizer, forward differences over
 //         X_R), writes the gradient and the value partials;
 //   fin   one block per pair writes the objective value.
-// Lanes cover 64 x 4 voxels in (x, y); each lane walks a chunk of z and keeps
-// u at z-1, z, z+1 in registers.
+// Lanes cover kDenseTX x kDenseTY voxels in (x, y); each lane walks a chunk
+// of z and keeps u at z-1, z, z+1 in registers. In 3D the plane of u at z
+// (with a one-voxel x / y halo) is staged in LDS for the stencil.
 #include "device_common.h"
 
 namespace air {
 
-constexpr int DTX = 64, DTY = 4;
+constexpr int DTX = kDenseTX, DTY = kDenseTY;
 
 struct DenseTile {
     int x, y, z0, z1;
@@ -94,6 +95,74 @@ __device__ inline float sample_general(const float* __restrict__ M, const int* n
     return W;
 }
 
+// Trilinear sample of M at p (voxel units) with its gradient, branch-free:
+// the point is clamped into the volume so every load is in range, and m = 1
+// iff it lay inside [0, n-1]^3. At p_a = n_a - 1 the cell is
+// [n_a - 2, n_a - 1] with f = 1 and the derivative along a is the
+// right-sided, zero-padded difference -W.
+struct Sample3 {
+    float W, m, d[3];
+};
+// the sampler in two stages, so that the gathers of one point can be in
+// flight while another finishes
+struct Gather3 {
+    v2f a00, a10, a01, a11;
+    float fx, fy, fz, m;
+    bool ex, ey, ez;
+};
+__device__ inline Gather3 sample3_issue(__amdgpu_buffer_rsrc_t rM, float px, float py, float pz,
+                                        int nx, int ny, int nz) {
+    Gather3 g;
+    const bool in = (__float_as_uint(px) <= __float_as_uint((float)(nx - 1))) &&
+                    (__float_as_uint(py) <= __float_as_uint((float)(ny - 1))) &&
+                    (__float_as_uint(pz) <= __float_as_uint((float)(nz - 1)));
+    g.m = in ? 1.f : 0.f;
+    const float qx = __builtin_amdgcn_fmed3f(px, 0.f, (float)(nx - 1));
+    const float qy = __builtin_amdgcn_fmed3f(py, 0.f, (float)(ny - 1));
+    const float qz = __builtin_amdgcn_fmed3f(pz, 0.f, (float)(nz - 1));
+    const int tx = (int)qx, ty = (int)qy, tz = (int)qz;
+    g.ex = tx == nx - 1;
+    g.ey = ty == ny - 1;
+    g.ez = tz == nz - 1;
+    const int jx = min(tx, nx - 2), jy = min(ty, ny - 2), jz = min(tz, nz - 2);
+    g.fx = qx - (float)jx;
+    g.fy = qy - (float)jy;
+    g.fz = qz - (float)jz;
+    const int off = (int)(__umul24(__umul24(jz, ny) + jy, nx) + jx) * 4;
+    const int sx4 = nx * 4, sxy4 = nx * ny * 4;
+    g.a00 = load2(rM, off, 0);
+    g.a10 = load2(rM, off, sx4);
+    g.a01 = load2(rM, off, sxy4);
+    g.a11 = load2(rM, off, sxy4 + sx4);
+    return g;
+}
+__device__ inline Sample3 sample3_finish(const Gather3& g) {
+    Sample3 r;
+    const float fx = g.fx, fy = g.fy, fz = g.fz;
+    const float dz00 = g.a01.x - g.a00.x, dz01 = g.a01.y - g.a00.y;
+    const float dz10 = g.a11.x - g.a10.x, dz11 = g.a11.y - g.a10.y;
+    const float e00 = g.a00.x + fz * dz00, e01 = g.a00.y + fz * dz01;
+    const float e10 = g.a10.x + fz * dz10, e11 = g.a10.y + fz * dz11;
+    const float dy0 = e10 - e00, dy1 = e11 - e01;
+    const float g0 = e00 + fy * dy0, g1 = e01 + fy * dy1;
+    r.W = g0 + fx * (g1 - g0);
+    r.m = g.m;
+    const float h0 = dz00 + fy * (dz10 - dz00), h1 = dz01 + fy * (dz11 - dz01);
+    r.d[0] = g.ex ? -r.W : g1 - g0;
+    r.d[1] = g.ey ? -r.W : dy0 + fx * (dy1 - dy0);
+    r.d[2] = g.ez ? -r.W : h0 + fx * (h1 - h0);
+    return r;
+}
+// Trilinear sample of M at p (voxel units) with its gradient, branch-free:
+// the point is clamped into the volume so every load is in range, and m = 1
+// iff it lay inside [0, n-1]^3. At p_a = n_a - 1 the cell is
+// [n_a - 2, n_a - 1] with f = 1 and the derivative along a is the
+// right-sided, zero-padded difference -W.
+__device__ inline Sample3 sample3(__amdgpu_buffer_rsrc_t rM, float px, float py, float pz,
+                                  int nx, int ny, int nz) {
+    return sample3_finish(sample3_issue(rM, px, py, pz, nx, ny, nz));
+}
+
 template <int DIM, int SIM>
 __global__ void __launch_bounds__(DTX* DTY)
 k_dense_pre(const LaunchCtx C, int zc) {
@@ -101,13 +170,16 @@ k_dense_pre(const LaunchCtx C, int zc) {
     __shared__ double red[8 * (NT / 64)];
     const int pair = blockIdx.y;
     const PairDesc P = C.pairs[pair];
-    if ((int)blockIdx.x >= P.dense_nblk) return;
+    const int blk = xcd_item(blockIdx.x, P.dense_nblk, 0);
+    if (blk < 0) return;
     const float* __restrict__ F = C.fixed_tab ? C.fixed_tab[pair] : C.fixed0;
     const float* __restrict__ M = C.moving_tab ? C.moving_tab[pair] : C.moving0;
     const float* __restrict__ th = C.theta_tab ? C.theta_tab[pair] : C.theta0;
-    const DenseTile T = dense_tile(P, blockIdx.x, zc, DIM);
+    const DenseTile T = dense_tile(P, blk, zc, DIM);
     const long long N = P.nvox;
     double v[6] = {0, 0, 0, 0, 0, 0};
+    const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, (uint32_t)(N * 4));
+    float cnt = 0.f;   // at most zc per lane: exact in FP32
     if (T.act) {
         for (int z = T.z0; z < T.z1; ++z) {
             const long long vi = ((long long)z * P.n[1] + T.y) * P.n[0] + T.x;
@@ -120,10 +192,15 @@ k_dense_pre(const LaunchCtx C, int zc) {
                 if (!(p[a] >= 0.f && p[a] <= (float)(P.n[a] - 1))) in = false;
             }
             if (SIM == AIR_SIM_MSE) {
-                if (in) v[0] += 1.0;
+                cnt += in ? 1.f : 0.f;
             } else if (in) {
-                bool in2;
-                const float W = sample_general<DIM>(M, P.n, p, &in2, nullptr);
+                float W;
+                if constexpr (DIM == 3) {
+                    W = sample3(rM, p[0], p[1], p[2], P.n[0], P.n[1], P.n[2]).W;
+                } else {
+                    bool in2;
+                    W = sample_general<DIM>(M, P.n, p, &in2, nullptr);
+                }
                 const double f = F[vi], w = W;
                 v[0] += 1.0;
                 v[1] += f;
@@ -134,10 +211,11 @@ k_dense_pre(const LaunchCtx C, int zc) {
             }
         }
     }
+    if (SIM == AIR_SIM_MSE) v[0] = (double)cnt;
     block_sum<NT, 6>(v, red);
     if (threadIdx.x == 0) {
         double* slot = reinterpret_cast<double*>(C.ws + C.L.dense_stats) +
-                       (long long)(P.dense_blk_off + blockIdx.x) * kStatWords;
+                       (long long)(P.dense_blk_off + blk) * kStatWords;
 #pragma unroll
         for (int k = 0; k < 6; ++k) slot[k] = v[k];
     }
@@ -188,13 +266,16 @@ k_dense_main(const LaunchCtx C, int zc, int reg_only, float* reg_grad_out) {
     __shared__ double red[8 * (NT / 64)];
     const int pair = blockIdx.y;
     const PairDesc P = C.pairs[pair];
-    if ((int)blockIdx.x >= P.dense_nblk) return;
+    // consecutive tiles share one XCD, so the stencil's x / y halo and the
+    // displaced gathers of neighbouring tiles hit the same L2
+    const int blk = xcd_item(blockIdx.x, P.dense_nblk, 0);
+    if (blk < 0) return;
     const float* __restrict__ F = C.fixed_tab ? C.fixed_tab[pair] : C.fixed0;
     const float* __restrict__ M = C.moving_tab ? C.moving_tab[pair] : C.moving0;
     const float* __restrict__ th = C.theta_tab ? C.theta_tab[pair] : C.theta0;
     float* __restrict__ grad = reg_only ? reg_grad_out
                                         : (C.grad_tab ? C.grad_tab[pair] : C.grad0);
-    const DenseTile T = dense_tile(P, blockIdx.x, zc, DIM);
+    const DenseTile T = dense_tile(P, blk, zc, DIM);
     const long long N = P.nvox;
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
     const long long sy = nx, sz = (long long)nx * ny;
@@ -214,7 +295,9 @@ k_dense_main(const LaunchCtx C, int zc, int reg_only, float* reg_grad_out) {
     }
     const float alpha = (float)a;
     const float rscale = (reg_only ? 1.0f : P.lambda) * 2.0f * P.inv_xr;
-    double acc[2] = {0.0, 0.0};   // [0] MSE sum of squares, [1] regulariser sum
+    const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, (uint32_t)(N * 4));
+    // per-lane sums over the z chunk in FP32, widened once per chunk
+    float sq = 0.f, rr = 0.f;   // MSE sum of squares, regulariser sum
     if (T.act) {
         const int x = T.x, y = T.y;
         const bool inx = x <= nx - 2, iny = y <= ny - 2;
@@ -253,7 +336,7 @@ k_dense_main(const LaunchCtx C, int zc, int reg_only, float* reg_grad_out) {
                         g -= dz;
                         r2 += dz * dz;
                     }
-                    acc[1] += r2;
+                    rr += r2;
                 }
                 if (prev_x) g += u0[c] - uxm;
                 if (prev_y) g += u0[c] - uym;
@@ -262,28 +345,36 @@ k_dense_main(const LaunchCtx C, int zc, int reg_only, float* reg_grad_out) {
             }
             float gi[3] = {0.f, 0.f, 0.f};
             if (!reg_only) {
-                float p[3];
-                const int idx[3] = {x, y, z};
+                const float Fv = F[vi];
+                float W, m, dW[3];
+                if constexpr (DIM == 3) {
+                    const Sample3 q = sample3(rM, fmaf(u0[0], P.s[0], (float)x),
+                                              fmaf(u0[1], P.s[1], (float)y),
+                                              fmaf(u0[2], P.s[2], (float)z), nx, ny, nz);
+                    W = q.W;
+                    m = q.m;
 #pragma unroll
-                for (int c = 0; c < DIM; ++c) p[c] = fmaf(u0[c], P.s[c], (float)idx[c]);
-                bool in;
-                float dW[3];
-                const float W = sample_general<DIM>(M, P.n, p, &in, dW);
-                if (in) {
-                    const float Fv = F[vi];
-                    float e;
-                    if (SIM == AIR_SIM_MSE) {
-                        const float r = W - Fv;
-                        acc[0] += (double)r * (double)r;
-                        e = alpha * r;
-                    } else {
-                        e = alpha * (Fv - muF) + beta * (W - muW);
-                    }
-                    if (degenerate) e = 0.f;
-                    // sample on the last voxel: right-sided cell with zero padding
+                    for (int c = 0; c < 3; ++c) dW[c] = q.d[c];
+                } else {
+                    float p[3];
+                    const int idx[3] = {x, y, z};
 #pragma unroll
-                    for (int c = 0; c < DIM; ++c) gi[c] = e * dW[c] * P.s[c];
+                    for (int c = 0; c < DIM; ++c) p[c] = fmaf(u0[c], P.s[c], (float)idx[c]);
+                    bool in;
+                    W = sample_general<DIM>(M, P.n, p, &in, dW);
+                    m = in ? 1.f : 0.f;
                 }
+                float e;
+                if (SIM == AIR_SIM_MSE) {
+                    const float r = m * (W - Fv);
+                    sq += r * r;
+                    e = alpha * r;
+                } else {
+                    e = m * (alpha * (Fv - muF) + beta * (W - muW));
+                }
+                if (degenerate) e = 0.f;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) gi[c] = e * dW[c] * P.s[c];
             }
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
@@ -293,10 +384,178 @@ k_dense_main(const LaunchCtx C, int zc, int reg_only, float* reg_grad_out) {
             }
         }
     }
+    double acc[2] = {(double)sq, (double)rr};
     block_sum<NT, 2>(acc, red);
     if (threadIdx.x == 0) {
         double* slot = reinterpret_cast<double*>(C.ws + C.L.dense_stats) +
-                       (long long)(P.dense_blk_off + blockIdx.x) * kStatWords;
+                       (long long)(P.dense_blk_off + blk) * kStatWords;
+        slot[0] = acc[0];
+        slot[1] = acc[1];
+    }
+}
+
+// 3D main pass. Each block owns a kDenseTX x kDenseTY column of (x, y) and
+// walks its z chunk; per z step the plane of u (three components, with a
+// one-voxel x / y halo, zero outside the volume) goes to one of two LDS
+// buffers, so the stencil's x and y neighbours come from LDS and z -+ 1 from
+// registers. The next plane (own voxel and halo) is loaded one step ahead.
+// Consecutive tiles share one XCD, so halo rows and the displaced gathers of
+// neighbouring tiles hit the same L2.
+template <int SIM>
+__global__ void __launch_bounds__(kDenseTX* kDenseTY)
+k_dense_main3(const LaunchCtx C, int zc, int reg_only, float* reg_grad_out) {
+    constexpr int TX = kDenseTX, TY = kDenseTY;
+    constexpr int TXh = TX + 2, PL = TXh * (TY + 2);
+    constexpr int NT = TX * TY;
+    constexpr int NH = 2 * TX + 2 * TY;  // halo cells of a plane (no corners)
+    __shared__ float pl[2][3][PL];
+    __shared__ double red[8 * (NT / 64)];
+    const int tid = threadIdx.x;
+    const int pair = blockIdx.y;
+    const PairDesc P = C.pairs[pair];
+    const int blk = xcd_item(blockIdx.x, P.dense_nblk, 0);
+    if (blk < 0) return;
+    const float* __restrict__ F = C.fixed_tab ? C.fixed_tab[pair] : C.fixed0;
+    const float* __restrict__ M = C.moving_tab ? C.moving_tab[pair] : C.moving0;
+    const float* __restrict__ th = C.theta_tab ? C.theta_tab[pair] : C.theta0;
+    float* __restrict__ grad = reg_only ? reg_grad_out
+                                        : (C.grad_tab ? C.grad_tab[pair] : C.grad0);
+    const long long N = P.nvox;
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    const long long sz = (long long)nx * ny;
+    const int nbx = cdiv(nx, TX), nby = cdiv(ny, TY);
+    const int x0 = (blk % nbx) * TX, y0 = ((blk / nbx) % nby) * TY;
+    const int z0 = (blk / (nbx * nby)) * zc, z1 = min(z0 + zc, nz);
+    const int lx = tid % TX, ly = tid / TX;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool act = x < nx && y < ny;
+    const long long vxy = (long long)y * nx + x;
+    // this thread's halo cell (tid < NH): plane-local (hx, hy), global (gx, gy)
+    int hx = 0, hy = 0, gx = -1, gy = -1;
+    if (tid < TX) {
+        hx = tid + 1; hy = 0; gx = x0 + tid; gy = y0 - 1;
+    } else if (tid < 2 * TX) {
+        hx = tid - TX + 1; hy = TY + 1; gx = x0 + tid - TX; gy = y0 + TY;
+    } else if (tid < 2 * TX + TY) {
+        hx = 0; hy = tid - 2 * TX + 1; gx = x0 - 1; gy = y0 + tid - 2 * TX;
+    } else if (tid < NH) {
+        hx = TX + 1; hy = tid - 2 * TX - TY + 1; gx = x0 + TX; gy = y0 + tid - 2 * TX - TY;
+    }
+    const bool hact = tid < NH && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    const long long hxy = hact ? (long long)gy * nx + gx : 0;
+    const int own = (ly + 1) * TXh + lx + 1;
+    const int hcell = hy * TXh + hx;
+
+    double a = 0, b = 0, cc = 0, dd = 0;
+    bool degenerate = true;
+    if (!reg_only) {
+        const double* sc = reinterpret_cast<const double*>(C.ws + C.L.scalars) + (long long)pair * 8;
+        a = sc[0];
+        b = sc[1];
+        cc = sc[2];
+        dd = sc[3];
+        degenerate = sc[6] != 0.0;
+    }
+    const float alpha = (float)a, beta = (float)b, muF = (float)cc, muW = (float)dd;
+    const float rscale = (reg_only ? 1.0f : P.lambda) * 2.0f * P.inv_xr;
+    const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, (uint32_t)(N * 4));
+    // regulariser domain X_R = prod [0, n_a - 2] as per-lane 0/1 weights
+    const float wxin = (act && x <= nx - 2) ? 1.f : 0.f, wyin = (act && y <= ny - 2) ? 1.f : 0.f;
+    const float wx1 = (act && x >= 1) ? 1.f : 0.f, wy1 = (act && y >= 1) ? 1.f : 0.f;
+    const float wxy = wxin * wyin;
+
+    // Registers hold u at z - 1, z, z + 1 (um, u0, up); each step loads u at
+    // z + 2, the halo of plane z + 1, F at z + 1 and the gathers of z + 1,
+    // so all of a step's memory traffic is in flight a step ahead of its use.
+    float um[3], u0[3], up[3], upp[3], h0[3], hp[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float* tc = th + c * N;
+        um[c] = (act && z0 > 0) ? tc[(z0 - 1) * sz + vxy] : 0.f;
+        u0[c] = act ? tc[z0 * sz + vxy] : 0.f;
+        up[c] = (act && z0 + 1 < nz) ? tc[(z0 + 1) * sz + vxy] : 0.f;
+        h0[c] = hact ? tc[z0 * sz + hxy] : 0.f;
+    }
+    const float* Fc = F + vxy;
+    const float s0 = P.s[0], s1 = P.s[1], s2 = P.s[2];
+    const float xf = (float)x, yf = (float)y;
+    // regulariser-only calls have no images (F and M may be null): no loads
+    float Fv = (act && !reg_only) ? Fc[z0 * sz] : 0.f;
+    Gather3 G{};
+    if (!reg_only)
+        G = sample3_issue(rM, fmaf(u0[0], s0, xf), fmaf(u0[1], s1, yf), fmaf(u0[2], s2, (float)z0),
+                          nx, ny, nz);
+    float sq = 0.f, rr = 0.f;   // per-lane MSE and regulariser sums over the chunk
+    for (int z = z0; z < z1; ++z) {
+        const int bsel = (z - z0) & 1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float* tc = th + c * N;
+            upp[c] = (act && z + 2 < nz) ? tc[(z + 2) * sz + vxy] : 0.f;
+            hp[c] = (hact && z + 1 < nz) ? tc[(z + 1) * sz + hxy] : 0.f;
+        }
+        // next point (clamped, in range even past the chunk or the volume)
+        const float Fn = (act && !reg_only) ? Fc[min(z + 1, nz - 1) * sz] : 0.f;
+        Gather3 Gn{};
+        if (!reg_only)
+            Gn = sample3_issue(rM, fmaf(up[0], s0, xf), fmaf(up[1], s1, yf),
+                               fmaf(up[2], s2, (float)(z + 1)), nx, ny, nz);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            pl[bsel][c][own] = u0[c];
+            if (tid < NH) pl[bsel][c][hcell] = h0[c];
+        }
+        __syncthreads();
+        const float wzin = z <= nz - 2 ? 1.f : 0.f, wz1 = z >= 1 ? 1.f : 0.f;
+        const float w_in = wxy * wzin, w_px = wx1 * wyin * wzin, w_py = wy1 * wxin * wzin;
+        const float w_pz = wz1 * wxy;
+        float gr[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float* q = pl[bsel][c];
+            const float uxm = q[own - 1], uxp = q[own + 1];
+            const float uym = q[own - TXh], uyp = q[own + TXh];
+            const float dxp = uxp - u0[c], dyp = uyp - u0[c], dzp = up[c] - u0[c];
+            rr += w_in * (dxp * dxp + dyp * dyp + dzp * dzp);
+            const float g = w_px * (u0[c] - uxm) + w_py * (u0[c] - uym) +
+                            w_pz * (u0[c] - um[c]) - w_in * (dxp + dyp + dzp);
+            gr[c] = rscale * g;
+        }
+        if (act) {
+            const long long vi = z * sz + vxy;
+            float gi[3] = {0.f, 0.f, 0.f};
+            if (!reg_only) {
+                const Sample3 s3 = sample3_finish(G);
+                float e;
+                if (SIM == AIR_SIM_MSE) {
+                    const float r = s3.m * (s3.W - Fv);
+                    sq += r * r;
+                    e = alpha * r;
+                } else {
+                    e = s3.m * (alpha * (Fv - muF) + beta * (s3.W - muW));
+                }
+                if (degenerate) e = 0.f;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) gi[c] = e * s3.d[c] * P.s[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) grad[c * N + vi] = gi[c] + gr[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            um[c] = u0[c];
+            u0[c] = up[c];
+            up[c] = upp[c];
+            h0[c] = hp[c];
+        }
+        G = Gn;
+        Fv = Fn;
+    }
+    double acc[2] = {(double)sq, (double)rr};
+    block_sum<NT, 2>(acc, red);
+    if (tid == 0) {
+        double* slot = reinterpret_cast<double*>(C.ws + C.L.dense_stats) +
+                       (long long)(P.dense_blk_off + blk) * kStatWords;
         slot[0] = acc[0];
         slot[1] = acc[1];
     }
@@ -337,15 +596,19 @@ k_dense_fin(const LaunchCtx C, int reg_only, float* reg_value_out) {
 template <int DIM, int SIM>
 static hipError_t dense_run(const LaunchCtx& C, int zc, int max_blk, hipStream_t s,
                             hipEvent_t ev0, hipEvent_t ev1) {
-    dim3 grid(max_blk, C.npairs);
+    dim3 grid(xcd_grid(max_blk, 0), C.npairs);
     hipLaunchKernelGGL((k_dense_pre<DIM, SIM>), grid, dim3(DTX * DTY), 0, s, C, zc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_dense_coef<SIM>), dim3(C.npairs), dim3(kBlock), 0, s, C);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev0) (void)hipEventRecord(ev0, s);
-    hipLaunchKernelGGL((k_dense_main<DIM, SIM>), grid, dim3(DTX * DTY), 0, s, C, zc, 0,
-                       (float*)nullptr);
+    if (DIM == 3)
+        hipLaunchKernelGGL((k_dense_main3<SIM>), grid, dim3(DTX * DTY), 0, s, C, zc, 0,
+                           (float*)nullptr);
+    else
+        hipLaunchKernelGGL((k_dense_main<DIM, SIM>), grid, dim3(DTX * DTY), 0, s, C, zc, 0,
+                           (float*)nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev1) (void)hipEventRecord(ev1, s);
     hipLaunchKernelGGL((k_dense_fin<SIM>), dim3(C.npairs), dim3(kBlock), 0, s, C, 0,
@@ -365,9 +628,9 @@ hipError_t launch_dense(const LaunchCtx& C, int zc, int max_blk, hipStream_t s, 
 // Regulariser of a dense field for one pair (context holds that pair only).
 hipError_t launch_reg_dense(const LaunchCtx& C, int pair_blocks, int zc, float* grad_out,
                             float* value_out, hipStream_t s) {
-    dim3 grid(pair_blocks, 1);
+    dim3 grid(xcd_grid(pair_blocks, 0), 1);
     if (C.dim == 3)
-        hipLaunchKernelGGL((k_dense_main<3, 0>), grid, dim3(DTX * DTY), 0, s, C, zc, 1, grad_out);
+        hipLaunchKernelGGL((k_dense_main3<0>), grid, dim3(DTX * DTY), 0, s, C, zc, 1, grad_out);
     else
         hipLaunchKernelGGL((k_dense_main<2, 0>), grid, dim3(DTX * DTY), 0, s, C, zc, 1, grad_out);
     hipError_t e = hipGetLastError();
