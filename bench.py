@@ -372,6 +372,54 @@ def run_latency2d(args, dev):
     }
 
 
+def cnn_flops(n=128):
+    """Multiply-add FLOPs of the network's 3x3x3 convolutions (forward), as
+    executed (the input layer's 8 channels include 6 zero pads)."""
+    from paper_1806_09907_amd.cnn import LAYERS
+
+    res = {"e1": n // 2, "e2": n // 4, "e3": n // 8, "e4": n // 16, "d1": n // 8, "d2": n // 8}
+    fwd = sum(2 * 27 * cin * cout * res[name] ** 3 for name, cin, cout, _ in LAYERS)
+    e1 = next(2 * 27 * cin * cout * res[name] ** 3 for name, cin, cout, _ in LAYERS
+              if name == "e1")
+    # backward: weight gradients of every layer, data gradients of all but the first
+    return fwd, 2 * fwd - e1
+
+
+def cnn_throughput(net, dev, reps=20):
+    import torch
+
+    from paper_1806_09907_amd import synth
+    from paper_1806_09907_amd.learned import PairGenerator
+
+    F, M, _ = PairGenerator(net.n, dev).pair(synth.heldout_seed(0))
+    dth = torch.full_like(net.forward(F, M), 1e-3)
+    fwd_fl, bwd_fl = cnn_flops(net.n)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    for _ in range(3):
+        net.forward(F, M)
+        net.backward(dth)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        net.forward(F, M)
+    ev[1].record()
+    for _ in range(reps):
+        net.forward(F, M)
+        net.backward(dth)
+    ev[2].record()
+    torch.cuda.synchronize()
+    t_f = ev[0].elapsed_time(ev[1]) / reps / 1e3
+    t_fb = ev[1].elapsed_time(ev[2]) / reps / 1e3
+    return {"forward_ms": t_f * 1e3, "forward_backward_ms": t_fb * 1e3,
+            "forward_gflop": fwd_fl / 1e9, "backward_gflop": bwd_fl / 1e9,
+            "forward_tflops": fwd_fl / t_f / 1e12,
+            "forward_backward_tflops": (fwd_fl + bwd_fl) / t_fb / 1e12,
+            "peak_tflops_bf16": 2500.0,
+            "frac_forward_backward": (fwd_fl + bwd_fl) / t_fb / 1e12 / 2500.0,
+            "note": "includes the pooling, upsampling, activation and cast kernels between "
+                    "the convolutions"}
+
+
 def learned_secondary(dev):
     """Train the initialisation network (2000 pairs x 2 epochs) and evaluate
     time to the zero-init target MSE on 100 held-out 128^3 pairs."""
@@ -382,6 +430,7 @@ def learned_secondary(dev):
     tr = learned.train(net, pairs=2000, epochs=2, warmup=300, log=None, log_every=0)
     ev = learned.evaluate(net, npairs=100, iters=200, log=None)
     return {"metric": "time to zero-init target MSE, learned vs plain (128^3 NCC)",
+            "cnn": cnn_throughput(net, dev),
             "unit": "ms", "higher_is_better": False,
             "learned_mean_ms": ev["mean_time_learned_ms"], "zero_mean_ms": ev["mean_time_zero_ms"],
             "median_speedup": ev["median_speedup"], "mean_speedup": ev["mean_speedup"],

@@ -183,8 +183,11 @@ air_status air_conv3d_fwd(const uint16_t* x, const int32_t dims[3], int32_t cin,
 air_status air_conv3d_flip_weights(const float* wt, int32_t cin, int32_t cout, uint16_t* wf,
                                    void* stream);
 /* Backward-weight: dwt[co][k] = sum_v dy[v][co] x[v + off(tap)][ci] (FP32),
- * db[co] = sum_v dy[v][co] (nullable). Voxels are reduced in chunks of
- * `chunk` (multiple of 32) into workspace partials summed in a fixed order. */
+ * db[co] = sum_v dy[v][co] (nullable). x is bf16 [v][cin], dy bf16 [v][cout],
+ * both 16-byte aligned; cin and cout multiples of 8, cout <= 128 (else
+ * AIR_ERR_SHAPE / AIR_ERR_ALIGN). Voxels are reduced in chunks of `chunk`
+ * (multiple of 32) into workspace partials (cout * (27 cin + 1) floats per
+ * chunk) summed in a fixed order. */
 air_status air_conv3d_bwd_weight_workspace(const int32_t dims[3], int32_t cin, int32_t cout,
                                            int32_t chunk, size_t* bytes);
 air_status air_conv3d_bwd_weight(const uint16_t* x, const int32_t dims[3], int32_t cin,

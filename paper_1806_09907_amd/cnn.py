@@ -42,7 +42,7 @@ LAYERS = [  # name, cin, cout, activation
 ]
 CAT = 112
 OUT_SCALE = 0.05
-BWDW_CHUNK = 4096
+BWDW_CHUNK = 256
 
 
 def _i3(v):

@@ -107,71 +107,206 @@ k_conv_fwd(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ Wt,
     }
 }
 
-// dWt partial for voxel chunk `blockIdx.z`: one wave per (16 co) x (16 k) tile.
+// Split-K form for small volumes (too few 64-voxel blocks to fill the
+// chip): a block takes 16 voxels, its four waves take every fourth 32-wide
+// reduction step, and the four partial tiles are added in wave order through
+// LDS before the same epilogue.
+template <int NT16>
+__global__ void __launch_bounds__(256)
+k_conv_fwd_sk(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ Wt,
+              const float* __restrict__ bias, int act, u16* __restrict__ Ybf, int ldy, int yoff,
+              float* __restrict__ Yf, int ldyf) {
+    __shared__ f32x4 red[4][NT16][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long N = (long long)D.nx * D.ny * D.nz;
+    const long long m0 = (long long)blockIdx.x * 16;
+    const long long m = m0 + (lane & 15);
+    const bool valid = m < N;
+    const int vx = (int)(m % D.nx), vy = (int)((m / D.nx) % D.ny), vz = (int)(m / ((long long)D.nx * D.ny));
+    const int g = lane >> 4;
+    f32x4 acc[NT16];
+#pragma unroll
+    for (int t = 0; t < NT16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 32 * wave; kc < D.Kpad; kc += 128) {
+        const int k = kc + 8 * g;
+        const bf16x8 a = load_a(X, D, vx, vy, vz, valid, k);
+#pragma unroll
+        for (int t = 0; t < NT16; ++t) {
+            const int co = t * 16 + (lane & 15);
+            bf16x8 b;
+            if (co < D.cout && k < D.K) {
+                const uint4 q = *reinterpret_cast<const uint4*>(Wt + (long long)co * D.K + k);
+                b = __builtin_bit_cast(bf16x8, q);
+            } else {
+                b = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+            }
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT16; ++t) red[wave][t][lane] = acc[t];
+    __syncthreads();
+    for (int t = wave; t < NT16; t += 4) {
+        const f32x4 v = ((red[0][t][lane] + red[1][t][lane]) + red[2][t][lane]) + red[3][t][lane];
+        const int co = t * 16 + (lane & 15);
+        if (co >= D.cout) continue;
+        const float b = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const long long row = m0 + 4 * g + i;
+            if (row >= N) continue;
+            float y = v[i] + b;
+            if (act == 1) y = y > 0.f ? y : 0.1f * y;
+            if (Ybf) Ybf[row * ldy + yoff + co] = f2bf(y);
+            if (Yf) Yf[row * ldyf + co] = y;
+        }
+    }
+}
+
+// dWt partial for voxel chunk `blockIdx.z`: one wave computes the 16 output
+// channels co0.. of tile blockIdx.y against BWK k-tiles of 16 reduction
+// columns (k = tap * C_in + ci). Per step of 32 voxels every lane loads one
+// 16-byte channel vector of dY and of each shifted input, the wave transposes
+// them through LDS into [channel][voxel] tiles, and each MFMA operand is one
+// 16-byte LDS read (8 consecutive voxels of one channel). The k-group-0 wave
+// of each co tile also sums dY over the chunk for the bias gradient.
+constexpr int BWK = 7;    // k tiles per wave
+constexpr int BWP = 40;   // LDS row pitch in bf16 (32 voxels + pad, 16-byte multiple)
 __global__ void __launch_bounds__(64)
 k_conv_bwdw(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ dY, int chunk,
             float* __restrict__ part) {
+    __shared__ __align__(16) u16 sA[16 * BWP];
+    __shared__ __align__(16) u16 sB[BWK * 16 * BWP];
     const int lane = threadIdx.x;
-    const int co0 = blockIdx.y * 16, k0 = blockIdx.x * 16;
+    const int co0 = blockIdx.y * 16, kt0 = blockIdx.x * BWK;
     const long long N = (long long)D.nx * D.ny * D.nz;
     const long long mb = (long long)blockIdx.z * chunk;
     const long long me = mb + chunk < N ? mb + chunk : N;
-    const int g = lane >> 4;
-    const int co = co0 + (lane & 15);
-    const int k = k0 + (lane & 15);
-    const bool kok = k < D.K;
-    const int tap = kok ? k / D.cin : 0, ci = kok ? k - tap * D.cin : 0;
-    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (long long mc = mb; mc < me; mc += 32) {
-        bf16x8 a, b;
+    const int g = lane >> 4, r = lane & 15;
+    // loader role: voxel lv of the step, channel half lh (8 channels)
+    const int lv = lane >> 1, lh = lane & 1;
+    const bool co_ok = co0 + 8 * lh < D.cout;
+    // each loader's B rows: k = (kt0 + t) * 16 + 8 * lh .. + 8, one tap
+    int ltap[BWK], lci[BWK];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const long long mm = mc + 8 * g + i;
-            u16 av = 0, bv = 0;
-            if (mm < me) {
-                if (co < D.cout) av = dY[mm * D.cout + co];
-                if (kok) {
-                    const int vx = (int)(mm % D.nx), vy = (int)((mm / D.nx) % D.ny),
-                              vz = (int)(mm / ((long long)D.nx * D.ny));
-                    const int x = vx + dx, y = vy + dy, z = vz + dz;
-                    if ((unsigned)x < (unsigned)D.nx && (unsigned)y < (unsigned)D.ny &&
-                        (unsigned)z < (unsigned)D.nz)
-                        bv = X[(((long long)z * D.ny + y) * D.nx + x) * D.cin + ci];
-                }
+    for (int t = 0; t < BWK; ++t) {
+        const int k = (kt0 + t) * 16 + 8 * lh;
+        ltap[t] = k < D.K ? k / D.cin : 27;
+        lci[t] = k < D.K ? k - ltap[t] * D.cin : 0;
+    }
+    f32x4 acc[BWK];
+#pragma unroll
+    for (int t = 0; t < BWK; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+    // this lane's 16-byte vectors of one 32-voxel step (zero past the chunk)
+    struct Step {
+        uint4 a, b[BWK];
+    };
+    auto load = [&](long long mc) -> Step {
+        Step q;
+        const long long m = mc + lv;
+        const bool vok = m < me;
+        const int vx = (int)(m % D.nx), vy = (int)((m / D.nx) % D.ny);
+        const int vz = (int)(m / ((long long)D.nx * D.ny));
+        q.a = make_uint4(0, 0, 0, 0);
+        if (vok && co_ok) q.a = *reinterpret_cast<const uint4*>(dY + m * D.cout + co0 + 8 * lh);
+#pragma unroll
+        for (int t = 0; t < BWK; ++t) {
+            q.b[t] = make_uint4(0, 0, 0, 0);
+            const int tap = ltap[t];
+            const int x = vx + tap % 3 - 1, y = vy + (tap / 3) % 3 - 1, z = vz + tap / 9 - 1;
+            if (vok && tap < 27 && (unsigned)x < (unsigned)D.nx && (unsigned)y < (unsigned)D.ny &&
+                (unsigned)z < (unsigned)D.nz) {
+                const long long v = ((long long)z * D.ny + y) * D.nx + x;
+                q.b[t] = *reinterpret_cast<const uint4*>(X + v * D.cin + lci[t]);
             }
-            a[i] = __builtin_bit_cast(__bf16, av);
-            b[i] = __builtin_bit_cast(__bf16, bv);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-    }
-    // D: rows co0 + 4g + i, column k0 + lane%16
-    float* P = part + (long long)blockIdx.z * D.cout * D.K;
+        return q;
+    };
+    auto process = [&](const Step& q) {
+        __syncthreads();  // the previous step's operand reads are done
+        {
+            const u16* e = reinterpret_cast<const u16*>(&q.a);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = co0 + 4 * g + i;
-        if (r < D.cout && kok) P[(long long)r * D.K + k] = acc[i];
+            for (int j = 0; j < 8; ++j) sA[(8 * lh + j) * BWP + lv] = e[j];
+        }
+#pragma unroll
+        for (int t = 0; t < BWK; ++t) {
+            const u16* e = reinterpret_cast<const u16*>(&q.b[t]);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sB[(t * 16 + 8 * lh + j) * BWP + lv] = e[j];
+        }
+        __syncthreads();
+        // A operand: row co0 + r, voxels 8g..8g+7; B: column k, same voxels
+        const uint4 av = *reinterpret_cast<const uint4*>(sA + r * BWP + 8 * g);
+        const bf16x8 av8 = __builtin_bit_cast(bf16x8, av);
+        if (blockIdx.x == 0) {
+            const u16* e = reinterpret_cast<const u16*>(&av);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) bsum += bf2f(e[j]);
+        }
+#pragma unroll
+        for (int t = 0; t < BWK; ++t) {
+            const uint4 bv = *reinterpret_cast<const uint4*>(sB + (t * 16 + r) * BWP + 8 * g);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av8, __builtin_bit_cast(bf16x8, bv),
+                                                            acc[t], 0, 0, 0);
+        }
+    };
+    // two register sets: the loads of the next step are in flight while the
+    // current one is transposed and multiplied
+    Step q0 = load(mb);
+    for (long long mc = mb; mc < me; mc += 64) {
+        const Step q1 = load(mc + 32);
+        process(q0);
+        q0 = load(mc + 64);
+        if (mc + 32 < me) process(q1);
+    }
+    // partial layout per chunk: dWt [cout][K], then db [cout]
+    float* P = part + (long long)blockIdx.z * D.cout * (D.K + 1);
+#pragma unroll
+    for (int t = 0; t < BWK; ++t) {
+        const int k = (kt0 + t) * 16 + r;
+        if (k >= D.K) continue;
+        // D: rows co0 + 4g + i, column k
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = co0 + 4 * g + i;
+            if (row < D.cout) P[(long long)row * D.K + k] = acc[t][i];
+        }
+    }
+    if (blockIdx.x == 0) {
+        // lanes r, r + 16, r + 32, r + 48 hold the four voxel groups of row r
+        bsum += __shfl_xor(bsum, 16, 64);
+        bsum += __shfl_xor(bsum, 32, 64);
+        if (g == 0 && co0 + r < D.cout) P[(long long)D.cout * D.K + co0 + r] = bsum;
     }
 }
 
-// dWt = sum over chunks (fixed order); db[co] = sum over voxels of dY.
-__global__ void __launch_bounds__(kBlock)
-k_conv_bwdw_reduce(const float* __restrict__ part, int nchunk, int total, float* __restrict__ dW) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= total) return;
+// dWt and db = sums of the chunk partials: a block takes 64 outputs, its 16
+// waves sum every 16th chunk, and the 16 sums are added in wave order (a
+// fixed order, so the result is repeatable).
+constexpr int kRedThreads = 1024;
+__global__ void __launch_bounds__(kRedThreads)
+k_conv_bwdw_reduce(const float* __restrict__ part, int nchunk, int cout, int K,
+                   float* __restrict__ dW, float* __restrict__ db) {
+    constexpr int NW = kRedThreads / 64;
+    __shared__ float red[kRedThreads];
+    const int total = cout * (K + 1);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
     float s = 0.f;
-    for (int c = 0; c < nchunk; ++c) s += part[(long long)c * total + i];
-    dW[i] = s;
-}
-
-__global__ void __launch_bounds__(kBlock)
-k_bias_grad(const u16* __restrict__ dY, long long N, int cout, float* __restrict__ db) {
-    __shared__ double red[8 * (kBlock / 64)];
-    const int co = blockIdx.x;
-    double v[1] = {0.0};
-    for (long long m = threadIdx.x; m < N; m += kBlock) v[0] += bf2f(dY[m * cout + co]);
-    block_sum<kBlock, 1>(v, red);
-    if (threadIdx.x == 0) db[co] = (float)v[0];
+    if (i < total)
+        for (int c = w; c < nchunk; c += NW) s += part[(long long)c * total + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (w != 0 || i >= total) return;
+    s = red[lane];
+    for (int k = 1; k < NW; ++k) s += red[k * 64 + lane];
+    if (i < cout * K) {
+        dW[i] = s;
+    } else if (db) {
+        db[i - cout * K] = s;
+    }
 }
 
 // Wf[ci][tap'*cout + co] = Wt[co][(26 - tap')*cin + ci] (as bf16).
@@ -395,9 +530,16 @@ air_status air_conv3d_fwd(const uint16_t* x, const int32_t dims[3], int32_t cin,
     const int nblk = (int)((N + 63) / 64);
     hipStream_t s = (hipStream_t)stream;
     const int nt = (cout + 15) / 16;
+    // below 1024 blocks of 64 voxels the split-K form keeps the chip busy
+    const bool sk = nblk < 1024;
+    const int nsk = (int)((N + 15) / 16);
     switch (nt) {
-#define CASE(T) case T: hipLaunchKernelGGL(k_conv_fwd<T>, dim3(nblk), dim3(256), 0, s, (const u16*)x, D, \
-        (const u16*)wt, bias, act, (u16*)y_bf16, ldy, yoff, y_f32, ldyf); break;
+#define CASE(T) case T: \
+        if (sk) hipLaunchKernelGGL(k_conv_fwd_sk<T>, dim3(nsk), dim3(256), 0, s, (const u16*)x, D, \
+            (const u16*)wt, bias, act, (u16*)y_bf16, ldy, yoff, y_f32, ldyf); \
+        else hipLaunchKernelGGL(k_conv_fwd<T>, dim3(nblk), dim3(256), 0, s, (const u16*)x, D, \
+            (const u16*)wt, bias, act, (u16*)y_bf16, ldy, yoff, y_f32, ldyf); \
+        break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
         default: return AIR_ERR_SHAPE;
@@ -410,7 +552,7 @@ air_status air_conv3d_bwd_weight_workspace(const int32_t dims[3], int32_t cin, i
     if (!dims || !bytes || chunk < 32 || chunk % 32) return AIR_ERR_INVALID_ARG;
     const long long N = (long long)dims[0] * dims[1] * dims[2];
     const long long nch = (N + chunk - 1) / chunk;
-    *bytes = (size_t)(4LL * nch * cout * 27 * cin);
+    *bytes = (size_t)(4LL * nch * cout * (27LL * cin + 1));
     return AIR_OK;
 }
 
@@ -418,7 +560,8 @@ air_status air_conv3d_bwd_weight(const uint16_t* x, const int32_t dims[3], int32
                                  const uint16_t* dy, int32_t cout, int32_t chunk, float* dwt,
                                  float* db, void* ws, size_t ws_bytes, void* stream) {
     if (!x || !dims || !dy || !dwt) return AIR_ERR_INVALID_ARG;
-    if (cin < 8 || cin % 8 || cout < 1 || cout > 128) return AIR_ERR_SHAPE;
+    if (cin < 8 || cin % 8 || cout < 8 || cout % 8 || cout > 128) return AIR_ERR_SHAPE;
+    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(dy)) & 15) return AIR_ERR_ALIGN;
     size_t need = 0;
     air_status st = air_conv3d_bwd_weight_workspace(dims, cin, cout, chunk, &need);
     if (st != AIR_OK) return st;
@@ -427,14 +570,13 @@ air_status air_conv3d_bwd_weight(const uint16_t* x, const int32_t dims[3], int32
     const long long N = (long long)D.nx * D.ny * D.nz;
     const int nch = (int)((N + chunk - 1) / chunk);
     hipStream_t s = (hipStream_t)stream;
-    dim3 grid((D.K + 15) / 16, (cout + 15) / 16, nch);
+    const int ktiles = (D.K + 15) / 16;
+    dim3 grid((ktiles + BWK - 1) / BWK, (cout + 15) / 16, nch);
     hipLaunchKernelGGL(k_conv_bwdw, grid, dim3(64), 0, s, (const u16*)x, D, (const u16*)dy, chunk,
                        (float*)ws);
-    const int total = cout * D.K;
-    hipLaunchKernelGGL(k_conv_bwdw_reduce, dim3((total + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                       (const float*)ws, nch, total, dwt);
-    if (db)
-        hipLaunchKernelGGL(k_bias_grad, dim3(cout), dim3(kBlock), 0, s, (const u16*)dy, N, cout, db);
+    const int total = cout * (D.K + 1);
+    hipLaunchKernelGGL(k_conv_bwdw_reduce, dim3((total + 63) / 64), dim3(kRedThreads), 0, s,
+                       (const float*)ws, nch, cout, D.K, dwt, db);
     return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
 }
 

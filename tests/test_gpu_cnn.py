@@ -60,6 +60,21 @@ def test_conv_forward_parity(cin, cout, dims):
         assert np.array_equal(from_bf16_tensor(ybf).reshape(ref.shape), bf16_round(got))
 
 
+@pytest.mark.parametrize("cin,cout,dims", [(8, 16, (64, 32, 32)), (16, 32, (32, 32, 72))])
+def test_conv_forward_parity_large(cin, cout, dims):
+    """Volumes of at least 1024 blocks of 64 voxels take the plain (not split-K) kernel."""
+    rng = np.random.default_rng(cin * 7 + cout)
+    nx, ny, nz = dims
+    x = bf16_round(rng.normal(size=(nz, ny, nx, cin)))
+    wt = bf16_round(rng.normal(size=(cout, 27 * cin)) / np.sqrt(27 * cin))
+    b = rng.normal(size=cout).astype(np.float32).astype(np.float64)
+    y = torch.empty(nz * ny * nx * cout, dtype=torch.float32, device=DEV)
+    cnn.conv_fwd(to_bf16_tensor(x), dims, cin, to_bf16_tensor(wt),
+                 torch.tensor(b, dtype=torch.float32, device=DEV), cout, 1, y_f32=y)
+    ref = O.conv3d_fwd(x, wt, b, 1)
+    assert rel(y.double().cpu().numpy().reshape(ref.shape), ref) <= 1e-5
+
+
 @pytest.mark.parametrize("cin,cout,dims", SHAPES)
 def test_conv_backward_parity(cin, cout, dims):
     rng = np.random.default_rng(100 + cin + cout)
