@@ -38,7 +38,8 @@ def build(force: bool = True) -> str:
 class _Problem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3),
                 ("transform", ctypes.c_int), ("spacing", ctypes.c_int * 3),
-                ("similarity", ctypes.c_int), ("lambda_diff", ctypes.c_double)]
+                ("similarity", ctypes.c_int), ("lambda_diff", ctypes.c_double),
+                ("diffeo_steps", ctypes.c_int)]
 
 
 _lib = None
@@ -62,6 +63,10 @@ def lib():
             "airo_bspline_expand": (None, [P, dp, dp]),
             "airo_bspline_adjoint": (None, [P, dp, dp]),
             "airo_displacement": (None, [P, dp, dp]),
+            "airo_velocity": (None, [P, dp, dp]),
+            "airo_compose": (None, [P, dp, dp]),
+            "airo_compose_adjoint": (None, [P, dp, dp, dp]),
+            "airo_exp": (None, [P, dp, ctypes.c_int, dp, dp]),
             "airo_sample": (None, [P, dp, dp, dp, u8, dp]),
             "airo_warp": (None, [P, dp, dp, dp, u8]),
             "airo_similarity": (ctypes.c_int, [P, dp, dp, u8, dp, dp]),
@@ -99,6 +104,7 @@ class Problem:
     spacing: tuple = (8, 8, 8)
     similarity: int = SIM_NCC
     lambda_diff: float = 0.0
+    diffeo_steps: int = 0      # > 0: f = exp(field) with this many squarings
 
     @property
     def dim(self) -> int:
@@ -123,7 +129,7 @@ class Problem:
         sp = list(self.spacing[:d]) + [1] * (3 - d)
         return _Problem(d, (ctypes.c_int * 3)(*n), int(self.transform),
                         (ctypes.c_int * 3)(*sp), int(self.similarity),
-                        float(self.lambda_diff))
+                        float(self.lambda_diff), int(self.diffeo_steps))
 
 
 def _f64(a) -> np.ndarray:
@@ -206,6 +212,48 @@ def displacement(prob: Problem, theta) -> np.ndarray:
     u = np.empty((prob.dim,) + prob.shape, dtype=np.float64)
     lib().airo_displacement(ctypes.byref(pc), _ptr(th), _ptr(u))
     return u
+
+
+def velocity(prob: Problem, theta) -> np.ndarray:
+    """The field before the exponential (B theta, or theta for dense)."""
+    pc = _check(prob)
+    th = _f64(theta)
+    assert th.shape == prob.param_shape()
+    v = np.empty((prob.dim,) + prob.shape, dtype=np.float64)
+    lib().airo_velocity(ctypes.byref(pc), _ptr(th), _ptr(v))
+    return v
+
+
+def compose(prob: Problem, u) -> np.ndarray:
+    """One squaring: u(x) + u(x + u(x)) (Sec. III-D)."""
+    pc = _check(prob)
+    u = _f64(u)
+    assert u.shape == (prob.dim,) + prob.shape
+    out = np.empty_like(u)
+    lib().airo_compose(ctypes.byref(pc), _ptr(u), _ptr(out))
+    return out
+
+
+def compose_adjoint(prob: Problem, u, gout) -> np.ndarray:
+    pc = _check(prob)
+    u = _f64(u)
+    g = _f64(gout)
+    assert u.shape == (prob.dim,) + prob.shape and g.shape == u.shape
+    out = np.empty_like(u)
+    lib().airo_compose_adjoint(ctypes.byref(pc), _ptr(u), _ptr(g), _ptr(out))
+    return out
+
+
+def exp_field(prob: Problem, v, steps: int, history: bool = False):
+    """exp(v) by scaling and squaring; optionally also u_0 .. u_K."""
+    pc = _check(prob)
+    v = _f64(v)
+    assert v.shape == (prob.dim,) + prob.shape
+    u = np.empty_like(v)
+    hist = np.empty((steps + 1,) + v.shape, dtype=np.float64) if history else None
+    lib().airo_exp(ctypes.byref(pc), _ptr(v), int(steps), _ptr(u),
+                   _ptr(hist) if history else None)
+    return (u, hist) if history else u
 
 
 def sample(prob: Problem, moving, u):

@@ -56,6 +56,7 @@ int airo_check(const airo_problem* p) {
     if (p->dim == 2 && p->n[2] != 1) return 1;
     if (p->transform != AIRO_TF_BSPLINE3 && p->transform != AIRO_TF_DENSE) return 1;
     if (p->similarity != AIRO_SIM_MSE && p->similarity != AIRO_SIM_NCC) return 1;
+    if (p->diffeo_steps < 0 || p->diffeo_steps > 30) return 1;
     return 0;
 }
 
@@ -192,11 +193,23 @@ void airo_bspline_adjoint(const airo_problem* p, const double* g, double* out) {
     }
 }
 
-void airo_displacement(const airo_problem* p, const double* theta, double* u) {
+void airo_velocity(const airo_problem* p, const double* theta, double* v) {
     if (p->transform == AIRO_TF_DENSE)
-        memcpy(u, theta, sizeof(double) * (size_t)p->dim * (size_t)airo_nvox(p));
+        memcpy(v, theta, sizeof(double) * (size_t)p->dim * (size_t)airo_nvox(p));
     else
-        airo_bspline_expand(p, theta, u);
+        airo_bspline_expand(p, theta, v);
+}
+
+void airo_displacement(const airo_problem* p, const double* theta, double* u) {
+    if (p->diffeo_steps <= 0) {
+        airo_velocity(p, theta, u);
+        return;
+    }
+    const size_t fb = sizeof(double) * (size_t)p->dim * (size_t)airo_nvox(p);
+    double* v = (double*)malloc(fb);
+    airo_velocity(p, theta, v);
+    airo_exp(p, v, p->diffeo_steps, u, NULL);
+    free(v);
 }
 
 void airo_sample(const airo_problem* p, const double* moving, const double* u,
@@ -271,6 +284,137 @@ void airo_warp(const airo_problem* p, const double* moving, const double* theta,
     airo_displacement(p, theta, u);
     airo_sample(p, moving, u, warped, mask, NULL);
     free(u);
+}
+
+/* ---- Sec. III-D: f = exp(v) by scaling and squaring ---------------- */
+
+/* One squaring: out_c(x) = u_c(x) + [u_c sampled at x + u(x)], each
+ * component sampled with the image sampler (zero outside, no mask). */
+void airo_compose(const airo_problem* p, const double* u, double* out) {
+    const int d = p->dim;
+    const long N = airo_nvox(p);
+    double* s = (double*)malloc(sizeof(double) * (size_t)N);
+    for (int c = 0; c < d; ++c) {
+        airo_sample(p, u + c * N, u, s, NULL, NULL);
+        for (long v = 0; v < N; ++v) out[c * N + v] = u[c * N + v] + s[v];
+    }
+    free(s);
+}
+
+/* Adjoint of one squaring. With s_a = (n_a - 1)/2 and w_q(p) the linear
+ * weights of corner q:
+ *   gin_c(x) += gout_c(x)                                  (identity term)
+ *   gin_a(x) += s_a sum_c gout_c(x) d[u_c sampled](p(x))/dp_a   (sample point)
+ *   gin_c(q) += w_q(p(x)) gout_c(x) for every in-range corner q of p(x)
+ *                                                          (interpolation^T)
+ * The scatter runs serially in voxel order. */
+void airo_compose_adjoint(const airo_problem* p, const double* u, const double* gout,
+                          double* gin) {
+    const int d = p->dim;
+    const int nx = p->n[0], ny = p->n[1], nz = (d == 3) ? p->n[2] : 1;
+    const int n[3] = {nx, ny, nz};
+    const long N = airo_nvox(p);
+    double* dsdp = (double*)malloc(sizeof(double) * (size_t)d * (size_t)N);
+    double* tmp = (double*)malloc(sizeof(double) * (size_t)N);
+    for (long i = 0; i < (long)d * N; ++i) gin[i] = gout[i];
+    for (int c = 0; c < d; ++c) {
+        airo_sample(p, u + c * N, u, tmp, NULL, dsdp);
+        for (int a = 0; a < d; ++a) {
+            const double sa = (n[a] - 1) / 2.0;
+            for (long v = 0; v < N; ++v) gin[a * N + v] += sa * gout[c * N + v] * dsdp[a * N + v];
+        }
+    }
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const long v = ((long)z * ny + y) * nx + x;
+                const int idx[3] = {x, y, z};
+                double pt[3], f[3];
+                long j[3];
+                int finite = 1;
+                for (int a = 0; a < d; ++a) {
+                    pt[a] = idx[a] + u[a * N + v] * (n[a] - 1) / 2.0;
+                    if (g_point_bits == 32 && isfinite(pt[a]) && fabs(pt[a]) < 1e30)
+                        pt[a] = (double)(float)pt[a];
+                    if (!isfinite(pt[a])) finite = 0;
+                    if (pt[a] > 1e9) pt[a] = 1e9;
+                    if (pt[a] < -1e9) pt[a] = -1e9;
+                }
+                if (!finite) continue;
+                for (int a = 0; a < d; ++a) {
+                    j[a] = (long)floor(pt[a]);
+                    f[a] = pt[a] - (double)j[a];
+                }
+                for (int cnr = 0; cnr < (1 << d); ++cnr) {
+                    int bit[3] = {cnr & 1, (cnr >> 1) & 1, (cnr >> 2) & 1};
+                    long q[3] = {0, 0, 0};
+                    int in_range = 1;
+                    for (int a = 0; a < d; ++a) {
+                        q[a] = j[a] + bit[a];
+                        if (q[a] < 0 || q[a] > n[a] - 1) in_range = 0;
+                    }
+                    if (!in_range) continue;
+                    double wgt = 1.0;
+                    for (int a = 0; a < d; ++a) wgt *= bit[a] ? f[a] : 1.0 - f[a];
+                    const long qi = (q[2] * ny + q[1]) * nx + q[0];
+                    for (int c = 0; c < d; ++c) gin[c * N + qi] += wgt * gout[c * N + v];
+                }
+            }
+    free(dsdp);
+    free(tmp);
+}
+
+void airo_exp(const airo_problem* p, const double* v, int K, double* u, double* hist) {
+    const long dN = (long)p->dim * airo_nvox(p);
+    double* a = (double*)malloc(sizeof(double) * (size_t)dN);
+    double* b = (double*)malloc(sizeof(double) * (size_t)dN);
+    const double scale = ldexp(1.0, -K);
+    for (long i = 0; i < dN; ++i) a[i] = v[i] * scale;
+    if (hist) memcpy(hist, a, sizeof(double) * (size_t)dN);
+    for (int k = 0; k < K; ++k) {
+        airo_compose(p, a, b);
+        double* t = a;
+        a = b;
+        b = t;
+        if (hist) memcpy(hist + (long)(k + 1) * dN, a, sizeof(double) * (size_t)dN);
+    }
+    memcpy(u, a, sizeof(double) * (size_t)dN);
+    free(a);
+    free(b);
+}
+
+/* dL/dtheta from dL/du (u the displacement): back through the squarings
+ * (if any) and the B-spline expansion (if any). */
+static void displacement_adjoint(const airo_problem* p, const double* theta, const double* gu,
+                                 double* grad) {
+    const long dN = (long)p->dim * airo_nvox(p);
+    const size_t fb = sizeof(double) * (size_t)dN;
+    double* gv = (double*)malloc(fb);
+    if (p->diffeo_steps > 0) {
+        const int K = p->diffeo_steps;
+        double* v = (double*)malloc(fb);
+        double* hist = (double*)malloc(fb * (size_t)(K + 1));
+        double* t = (double*)malloc(fb);
+        airo_velocity(p, theta, v);
+        airo_exp(p, v, K, t, hist);
+        memcpy(gv, gu, fb);
+        for (int k = K - 1; k >= 0; --k) {
+            airo_compose_adjoint(p, hist + (long)k * dN, gv, t);
+            memcpy(gv, t, fb);
+        }
+        const double scale = ldexp(1.0, -K);
+        for (long i = 0; i < dN; ++i) gv[i] *= scale;
+        free(v);
+        free(hist);
+        free(t);
+    } else {
+        memcpy(gv, gu, fb);
+    }
+    if (p->transform == AIRO_TF_DENSE)
+        memcpy(grad, gv, fb);
+    else
+        airo_bspline_adjoint(p, gv, grad);
+    free(gv);
 }
 
 /* Per-slab partial sums, added serially in slab order. */
@@ -439,15 +583,15 @@ void airo_diffusion(const airo_problem* p, const double* u, double* value, doubl
 void airo_regulariser(const airo_problem* p, const double* theta, double* value, double* grad) {
     const long N = airo_nvox(p);
     const size_t fb = sizeof(double) * (size_t)p->dim * (size_t)N;
-    if (p->transform == AIRO_TF_DENSE) {
+    if (p->transform == AIRO_TF_DENSE && p->diffeo_steps <= 0) {
         airo_diffusion(p, theta, value, grad);
         return;
     }
     double* u = (double*)malloc(fb);
     double* gu = grad ? (double*)malloc(fb) : NULL;
-    airo_bspline_expand(p, theta, u);
+    airo_displacement(p, theta, u);
     airo_diffusion(p, u, value, gu);
-    if (grad) airo_bspline_adjoint(p, gu, grad);
+    if (grad) displacement_adjoint(p, theta, gu, grad);
     free(u);
     free(gu);
 }
@@ -479,10 +623,7 @@ int airo_objective_and_grad(const airo_problem* p, const double* fixed,
             g[a * N + v] = img + p->lambda_diff * g[a * N + v];
         }
     }
-    if (p->transform == AIRO_TF_DENSE)
-        memcpy(grad, g, fb);
-    else
-        airo_bspline_adjoint(p, g, grad);
+    displacement_adjoint(p, theta, g, grad);
     long np = airo_param_count(p);
     if (!isfinite(*value)) flags |= AIRO_FLAG_NONFINITE;
     for (long i = 0; i < np; ++i)

@@ -20,6 +20,8 @@
  *                        coordinates, out-of-domain points masked out,
  *                        linear interpolation via a grid sampler)
  *   optimiser            Sec. III-G (Adam, Kingma & Ba)
+ *   diffeomorphic        Sec. III-D (f = exp(v), scaling and squaring; the
+ *                        number of squarings is a problem parameter)
  *
  * Conventions (shared readings of the paper, identical on both sides):
  *   images     [nz][ny][nx], x fastest (2D: [ny][nx], n[2] == 1)
@@ -60,6 +62,8 @@ typedef struct {
     int spacing[3];   /* control spacing (voxels) along x, y, z */
     int similarity;   /* AIRO_SIM_* */
     double lambda_diff;
+    int diffeo_steps; /* 0: f = the field itself; K > 0: f = exp(field) by
+                         scaling and squaring with K squarings (Sec. III-D) */
 } airo_problem;
 
 int airo_check(const airo_problem* p);
@@ -74,8 +78,25 @@ double airo_bspline_kernel(double r);
 void airo_bspline_expand(const airo_problem* p, const double* theta, double* u);
 /* out = B^T g  (the adjoint of the expansion). */
 void airo_bspline_adjoint(const airo_problem* p, const double* g, double* out);
-/* u = B theta for B-spline problems, u = theta for dense ones. */
+/* The field before the exponential: B theta (B-spline) or theta (dense). */
+void airo_velocity(const airo_problem* p, const double* theta, double* v);
+/* The displacement f_theta: the velocity itself, or its exponential when
+ * diffeo_steps > 0. */
 void airo_displacement(const airo_problem* p, const double* theta, double* u);
+
+/* Diffeomorphic transform (Sec. III-D, f = exp(v) for a stationary velocity
+ * field v), by scaling and squaring: u_0 = v / 2^K, then K times
+ *     u_{k+1}(x) = u_k(x) + u_k(x + u_k(x)),
+ * the second term sampled like an image (sample point p_a = x_a + u_a (n_a-1)/2,
+ * linear on [floor(p), floor(p)+1], zero outside; no mask).
+ * airo_compose: one squaring. airo_compose_adjoint: given gout = dL/du_{k+1},
+ * gin = dL/du_k (the identity term, the term through the sample point, and
+ * the transpose of the interpolation, scattered voxel by voxel).
+ * airo_exp: u = exp(v); hist (nullable) receives u_0 .. u_K ((K+1) d N). */
+void airo_compose(const airo_problem* p, const double* u, double* out);
+void airo_compose_adjoint(const airo_problem* p, const double* u, const double* gout,
+                          double* gin);
+void airo_exp(const airo_problem* p, const double* v, int K, double* u, double* hist);
 
 /* Sample `moving` at x + u(x); writes warped [N], mask [N] (nullable) and
  * dwdp [d][N] (nullable): the derivative of the sample with respect to the
