@@ -14,7 +14,9 @@
  *             (Sec. III-C "Image Warping");
  *   S         MSE (Sec. II-A eq. mse) or NCC (Sec. III-B; loss -rho, the
  *             Pearson correlation over the masked voxels);
- *   R         the diffusion regulariser (Sec. II-A eq. diffusion_regularizer).
+ *   R         the diffusion regulariser (Sec. II-A eq. diffusion_regularizer);
+ *   f = exp(v) optionally, for a stationary velocity field v given by either
+ *             model (Sec. III-D), by scaling and squaring.
  *
  * Conventions (every entry point):
  *   - images are FP32 [nz][ny][nx], x fastest (2D: [ny][nx], n[2] == 1);
@@ -74,6 +76,12 @@ typedef struct {
     int32_t spacing[3];   /* B-spline control spacing in voxels, 1..64 */
     int32_t similarity;   /* AIR_SIM_* */
     float lambda_diff;    /* weight of the diffusion regulariser, >= 0 */
+    int32_t diffeo_steps; /* 0: f is the field itself. K in 1..16: f = exp(v)
+                             (Sec. III-D, stationary velocity v = the field)
+                             by scaling and squaring: u_0 = v / 2^K, then K
+                             times u <- u(x) + u(x + u(x)), sampled like an
+                             image (zero outside, no mask). R then acts on
+                             f = u_K. Plans with K > 0 hold one pair. */
 } air_problem;
 
 /* Opaque plan: host tables for one pair or a batch of pairs that share
@@ -99,9 +107,18 @@ air_status air_plan_get_tiling(const air_plan* plan, int32_t* id);
 
 /* Stage 1 + 2 (Sec. III-C Image Warping): warped = M(x + u(x)) with zero
  * padding everywhere (also outside the mask); mask (nullable) = 1 where the
- * sample point lies inside the volume. For pair `pair` of the plan. */
+ * sample point lies inside the volume. For pair `pair` of the plan.
+ * Diffeomorphic plans return AIR_ERR_UNSUPPORTED: materialise f with
+ * air_displacement and warp with a dense plan of the same size. */
 air_status air_warp(const air_plan* plan, int32_t pair, const float* moving,
                     const float* theta, float* warped, uint8_t* mask, void* stream);
+
+/* Stage 1 (Sec. II-A eq. kernel_basis, Sec. III-C, Sec. III-D): the dense
+ * displacement u = f_theta [d][nz][ny][nx] in normalised units -- B theta,
+ * theta, or their exponential for diffeomorphic plans. ws may be NULL for
+ * plans without the exponential. */
+air_status air_displacement(const air_plan* plan, int32_t pair, const float* theta, float* u,
+                            void* ws, size_t ws_bytes, void* stream);
 
 /* Stage 3 (Sec. II-A eq. mse / Sec. III-B NCC): similarity of `warped`
  * against `fixed` over the voxels where mask != 0 (mask nullable = all). */

@@ -29,7 +29,8 @@ class AirError(RuntimeError):
 class AirProblem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3),
                 ("transform", ctypes.c_int32), ("spacing", ctypes.c_int32 * 3),
-                ("similarity", ctypes.c_int32), ("lambda_diff", ctypes.c_float)]
+                ("similarity", ctypes.c_int32), ("lambda_diff", ctypes.c_float),
+                ("diffeo_steps", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -51,6 +52,7 @@ SIGNATURES = {
     "air_plan_set_tiling": (_i32, [_vp, _i32]),
     "air_plan_get_tiling": (_i32, [_vp, ctypes.POINTER(_i32)]),
     "air_warp": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "air_displacement": (_i32, [_vp, _i32, _vp, _vp, _vp, _sz, _vp]),
     "air_similarity": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "air_regulariser": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "air_objective_and_grad": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),

@@ -28,6 +28,7 @@ class Problem:
     spacing: Tuple[int, ...] = (8, 8, 8)
     similarity: int = SIM_NCC
     lambda_diff: float = 0.0
+    diffeo_steps: int = 0      # > 0: f = exp(field), this many squarings (Sec. III-D)
 
     @property
     def dim(self) -> int:
@@ -51,7 +52,7 @@ class Problem:
         sp = list(self.spacing[:d]) + [1] * (3 - d)
         return AirProblem(d, (ctypes.c_int32 * 3)(*n), int(self.transform),
                           (ctypes.c_int32 * 3)(*sp), int(self.similarity),
-                          float(self.lambda_diff))
+                          float(self.lambda_diff), int(self.diffeo_steps))
 
 
 def _stream() -> ctypes.c_void_p:
@@ -174,6 +175,17 @@ def warp(plan: Plan, moving: torch.Tensor, theta: torch.Tensor, pair: int = 0,
     check(lib().air_warp(plan.handle, pair, _ptr(moving), _ptr(theta), _ptr(out), _ptr(mask),
                          _stream()), "air_warp")
     return out, mask
+
+
+def displacement(plan: Plan, theta: torch.Tensor, pair: int = 0) -> torch.Tensor:
+    """The dense displacement f_theta [d][nz][ny][nx] (normalised units)."""
+    p = plan.problems[pair]
+    _need(theta, p.param_shape(), name="theta")
+    u = torch.empty((p.dim,) + p.shape, dtype=torch.float32, device=theta.device)
+    ws = plan.workspace(theta.device)
+    check(lib().air_displacement(plan.handle, pair, _ptr(theta), _ptr(u), _ptr(ws), ws.numel(),
+                                 _stream()), "air_displacement")
+    return u
 
 
 def similarity(plan: Plan, fixed: torch.Tensor, warped: torch.Tensor,

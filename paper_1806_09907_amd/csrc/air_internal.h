@@ -54,6 +54,10 @@ struct WsLayout {
     size_t scalars;      // double [npairs][8] (dense: global count / coefficients)
     size_t dense_stats;  // double [sum dense blocks][kStatWords]
     size_t generic;      // double [generic blocks][kStatWords] (similarity / reg calls)
+    size_t fields;       // float [K + 1][d N]: u_0 .. u_K of the exponential (K > 0)
+    size_t gfield;       // float [2][d N]: gradients going back through the squarings
+    size_t bsadj1;       // float [d][nz][ny][ncx]: transposed expansion, after x
+    size_t bsadj2;       // float [d][nz][ncy][ncx]: after y
     size_t total;
 };
 

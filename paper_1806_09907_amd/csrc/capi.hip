@@ -29,6 +29,14 @@ hipError_t launch_similarity(const float* F, const float* W, const uint8_t* mask
 hipError_t launch_adam(float* th, const float* g, float* m, float* v, long long n, float lr_bc1,
                        float b1, float b2, float inv_sqrt_bc2, float eps, hipStream_t s);
 hipError_t launch_scale(float* x, const float* s, long long n, hipStream_t st);
+hipError_t launch_velocity(const PairDesc& P, const float* consts_dev, int transform, int dim,
+                           const float* theta, float scale, float* out, hipStream_t s);
+hipError_t launch_compose(const PairDesc& P, int dim, const float* u, float* out, hipStream_t s);
+hipError_t launch_compose_adjoint(const PairDesc& P, int dim, const float* u, const float* gout,
+                                  float* gin, hipStream_t s);
+hipError_t launch_velocity_adjoint(const PairDesc& P, const float* consts_dev, int transform,
+                                   int dim, const float* g, float scale, float* t1, float* t2,
+                                   float* grad, hipStream_t s);
 
 // Tile configurations of the fused B-spline kernel: {TX, TY, column cells}.
 // The kernel variant follows from the shape and the spacing: a spacing-8
@@ -63,6 +71,7 @@ using namespace air;
 
 struct air_plan {
     int npairs = 0, dim = 0, transform = 0, sim = 0;
+    int diffeo = 0;  // squarings of the exponential (0: none)
     int tiling = 0;
     std::vector<air_problem> probs;
     std::vector<PairDesc> pd;
@@ -133,6 +142,7 @@ static air_status validate_problem(const air_problem& p) {
     if (p.transform != AIR_TF_BSPLINE3 && p.transform != AIR_TF_DENSE) return AIR_ERR_INVALID_ARG;
     if (p.similarity != AIR_SIM_MSE && p.similarity != AIR_SIM_NCC) return AIR_ERR_INVALID_ARG;
     if (!(p.lambda_diff >= 0.f) || !isfinite(p.lambda_diff)) return AIR_ERR_INVALID_ARG;
+    if (p.diffeo_steps < 0 || p.diffeo_steps > 16) return AIR_ERR_INVALID_ARG;
     long long N = 1;
     for (int a = 0; a < p.dim; ++a) {
         if (p.n[a] < 2 || p.n[a] > 65536) return AIR_ERR_SHAPE;
@@ -255,7 +265,9 @@ static air_status build_tables(air_plan* P) {
             lds_f = std::max(lds_f, head + 4 * std::max(f, reg));
             lds_r = std::max(lds_r, 8 * sizeof(double) * (kBlock / 64) + 4 * reg);
             stats_n = tiles;
-        } else {
+        }
+        // dense passes: dense models, and the objective at exp(v) of either model
+        if (!bs || P->diffeo > 0) {
             const int nbx = cdiv(D.n[0], kDenseTX), nby = cdiv(D.n[1], kDenseTY);
             const int nbz = d == 3 ? cdiv(D.n[2], kDenseZc) : 1;
             D.dense_nblk = nbx * nby * nbz;
@@ -281,6 +293,16 @@ static air_status build_tables(air_plan* P) {
     L.scalars = off;     off = align256(off + (size_t)P->npairs * 8 * 8);
     L.dense_stats = off; off = align256(off + std::max<size_t>(dense_n, 1) * kStatWords * 8);
     L.generic = off;     off = align256(off + (size_t)kGenericSlots * kStatWords * 8);
+    if (P->diffeo > 0) {
+        const PairDesc& D = P->pd[0];
+        const size_t dN = (size_t)d * (size_t)D.nvox;
+        L.fields = off;  off = align256(off + (size_t)(P->diffeo + 1) * dN * 4);
+        L.gfield = off;  off = align256(off + 2 * dN * 4);
+        const size_t t1 = bs ? (size_t)d * D.n[2] * D.n[1] * D.nc[0] : 1;
+        const size_t t2 = bs ? (size_t)d * D.n[2] * D.nc[1] * D.nc[0] : 1;
+        L.bsadj1 = off;  off = align256(off + t1 * 4);
+        L.bsadj2 = off;  off = align256(off + t2 * 4);
+    }
     L.total = off;
     return AIR_OK;
 }
@@ -348,6 +370,60 @@ static LaunchCtx base_ctx(const air_plan* P, const DeviceTables* T, void* ws) {
     return C;
 }
 
+// u_K = exp(v) into the workspace fields u_0 .. u_K (Sec. III-D). Returns u_K.
+static hipError_t diffeo_forward(const air_plan* P, const DeviceTables* T, unsigned char* w,
+                                 const float* theta, hipStream_t s, float** uK) {
+    const PairDesc& hp = P->pd[0];
+    const long long dN = (long long)P->dim * hp.nvox;
+    float* U = reinterpret_cast<float*>(w + P->L.fields);
+    hipError_t e = launch_velocity(hp, T->consts, P->transform, P->dim, theta,
+                                   ldexpf(1.f, -P->diffeo), U, s);
+    for (int k = 0; k < P->diffeo && e == hipSuccess; ++k)
+        e = launch_compose(hp, P->dim, U + k * dN, U + (k + 1) * dN, s);
+    *uK = U + P->diffeo * dN;
+    return e;
+}
+
+// Objective (or, with reg_only, the regulariser) of a diffeomorphic plan:
+// u_K = exp(v), the dense-field evaluation at u_K giving dL/du_K, then back
+// through the squarings and the velocity model to dL/dtheta.
+static hipError_t run_diffeo(const air_plan* P, const DeviceTables* T, void* ws,
+                             const float* fixed, const float* moving, const float* theta,
+                             float* value, float* grad, bool reg_only, hipStream_t s) {
+    unsigned char* w = static_cast<unsigned char*>(ws);
+    const PairDesc& hp = P->pd[0];
+    const long long dN = (long long)P->dim * hp.nvox;
+    float* uK = nullptr;
+    hipError_t e = diffeo_forward(P, T, w, theta, s, &uK);
+    if (e != hipSuccess) return e;
+    float* g = reinterpret_cast<float*>(w + P->L.gfield);
+    float* o = g + dN;
+    LaunchCtx C = base_ctx(P, T, ws);
+    C.theta0 = uK;
+    if (reg_only) {
+        e = launch_reg_dense(C, hp.dense_nblk, kDenseZc, g, value, s);
+    } else {
+        C.fixed0 = fixed;
+        C.moving0 = moving;
+        C.grad0 = g;
+        C.value0 = value;
+        e = launch_dense(C, kDenseZc, P->max_dense_blk, s, nullptr, nullptr);
+    }
+    if (e != hipSuccess || !grad) return e;
+    const float* U = reinterpret_cast<const float*>(w + P->L.fields);
+    for (int k = P->diffeo - 1; k >= 0 && e == hipSuccess; --k) {
+        e = launch_compose_adjoint(hp, P->dim, U + k * dN, g, o, s);
+        float* t = g;
+        g = o;
+        o = t;
+    }
+    if (e != hipSuccess) return e;
+    return launch_velocity_adjoint(hp, T->consts, P->transform, P->dim, g,
+                                   ldexpf(1.f, -P->diffeo),
+                                   reinterpret_cast<float*>(w + P->L.bsadj1),
+                                   reinterpret_cast<float*>(w + P->L.bsadj2), grad, s);
+}
+
 static air_status run_objective(const air_plan* cP, LaunchCtx& C, hipStream_t s) {
     air_plan* P = const_cast<air_plan*>(cP);
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -357,6 +433,16 @@ static air_status run_objective(const air_plan* cP, LaunchCtx& C, hipStream_t s)
         P->ev_next += 2;
     }
     hipError_t e;
+    if (P->diffeo > 0) {
+        // the whole evaluation is timed: it is a sequence of comparable passes
+        if (e0) (void)hipEventRecord(e0, s);
+        DeviceTables T{};
+        T.pairs = const_cast<PairDesc*>(C.pairs);
+        T.consts = const_cast<float*>(C.consts);
+        e = run_diffeo(P, &T, C.ws, C.fixed0, C.moving0, C.theta0, C.value0, C.grad0, false, s);
+        if (e1) (void)hipEventRecord(e1, s);
+        return e == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+    }
     if (P->transform == AIR_TF_BSPLINE3) {
         e = launch_bspline(C, P->variant, P->lds_fused, P->max_ctrl, s, e0, e1);
     } else {
@@ -384,12 +470,14 @@ air_status air_plan_create(const air_problem* probs, int32_t npairs, air_plan** 
             probs[i].similarity != probs[0].similarity)
             return AIR_ERR_UNSUPPORTED;
     }
+    if (probs[0].diffeo_steps > 0 && npairs != 1) return AIR_ERR_UNSUPPORTED;
     air_plan* P = new (std::nothrow) air_plan();
     if (!P) return AIR_ERR_DEVICE;
     P->npairs = npairs;
     P->dim = probs[0].dim;
     P->transform = probs[0].transform;
     P->sim = probs[0].similarity;
+    P->diffeo = probs[0].diffeo_steps;
     P->probs.assign(probs, probs + npairs);
     P->tiling = 0;
     air_status st = build_tables(P);
@@ -467,6 +555,7 @@ air_status air_warp(const air_plan* plan, int32_t pair, const float* moving, con
                     float* warped, uint8_t* mask, void* stream) {
     if (!plan || !moving || !theta || !warped) return AIR_ERR_INVALID_ARG;
     if (pair < 0 || pair >= plan->npairs) return AIR_ERR_SHAPE;
+    if (plan->diffeo > 0) return AIR_ERR_UNSUPPORTED;
     if (!aligned16(moving) || !aligned16(theta) || !aligned16(warped) ||
         (mask && !aligned16(mask)))
         return AIR_ERR_ALIGN;
@@ -475,6 +564,30 @@ air_status air_warp(const air_plan* plan, int32_t pair, const float* moving, con
     if (st != AIR_OK) return st;
     hipError_t e = launch_warp(T->pairs, pair, plan->pd[pair], T->consts, moving, theta, warped,
                                mask, plan->dim, plan->transform, (hipStream_t)stream);
+    return e == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_displacement(const air_plan* plan, int32_t pair, const float* theta, float* u,
+                            void* ws, size_t ws_bytes, void* stream) {
+    if (!plan || !theta || !u) return AIR_ERR_INVALID_ARG;
+    if (pair < 0 || pair >= plan->npairs) return AIR_ERR_SHAPE;
+    if (!aligned16(theta) || !aligned16(u)) return AIR_ERR_ALIGN;
+    if (plan->diffeo > 0 && (!ws || ws_bytes < plan->L.total)) return AIR_ERR_WORKSPACE;
+    if (ws && !aligned16(ws)) return AIR_ERR_ALIGN;
+    DeviceTables* T = nullptr;
+    air_status st = ensure_device(plan, &T);
+    if (st != AIR_OK) return st;
+    const PairDesc& hp = plan->pd[pair];
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (plan->diffeo == 0) {
+        e = launch_velocity(hp, T->consts, plan->transform, plan->dim, theta, 1.f, u, s);
+    } else {
+        float* uK = nullptr;
+        e = diffeo_forward(plan, T, static_cast<unsigned char*>(ws), theta, s, &uK);
+        if (e == hipSuccess)
+            e = launch_velocity(hp, T->consts, AIR_TF_DENSE, plan->dim, uK, 1.f, u, s);
+    }
     return e == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
 }
 
@@ -506,7 +619,10 @@ air_status air_regulariser(const air_plan* plan, int32_t pair, const float* thet
     unsigned char* w = static_cast<unsigned char*>(ws);
     const PairDesc& hp = plan->pd[pair];
     hipError_t e;
-    if (plan->transform == AIR_TF_BSPLINE3) {
+    if (plan->diffeo > 0) {
+        e = run_diffeo(plan, T, ws, nullptr, nullptr, theta, value, grad, true,
+                       (hipStream_t)stream);
+    } else if (plan->transform == AIR_TF_BSPLINE3) {
         float* g = grad ? grad : reinterpret_cast<float*>(w + plan->L.reggrad) + hp.param_off;
         double* rp = reinterpret_cast<double*>(w + plan->L.regpart) + hp.regpart_off;
         e = launch_reg_bspline(T->pairs, hp, pair, T->consts, theta, g, rp, value, plan->dim,
@@ -549,6 +665,7 @@ air_status air_objective_and_grad_batched(const air_plan* plan, const float* con
                                           float* values, float* const* grads, void* ws,
                                           size_t ws_bytes, void* stream) {
     if (!plan || !fixed || !moving || !theta || !values || !grads) return AIR_ERR_INVALID_ARG;
+    if (plan->diffeo > 0) return AIR_ERR_UNSUPPORTED;
     if (((uintptr_t)fixed | (uintptr_t)moving | (uintptr_t)theta | (uintptr_t)grads) & 7u)
         return AIR_ERR_ALIGN;
     if (((uintptr_t)values & 3u) != 0) return AIR_ERR_ALIGN;

@@ -1,0 +1,340 @@
+// Diffeomorphic transform (Sec. III-D): f = exp(v) for a stationary velocity
+// field v, by scaling and squaring. u_0 = v / 2^K, then K squarings
+//     u_{k+1}(x) = u_k(x) + u_k(x + u_k(x)),
+// the second term sampled like an image (sample point p_a = x_a +
+// u_a (n_a - 1)/2, linear on [floor(p), floor(p) + 1], zero outside the
+// volume, no mask). For a B-spline model v is the expanded control field.
+// The exponential cannot stay inside one fused pass (each squaring samples
+// the whole previous field), so the fields u_0 .. u_K live in the workspace;
+// the objective at u_K runs on the dense-field kernels, and its gradient goes
+// back through the squarings: each adjoint step adds the identity term, the
+// term through the sample point (written per voxel) and the transposed
+// interpolation (scattered with FP32 atomics, so the summation order -- and
+// the last bits of the result -- vary from run to run).
+#include "device_common.h"
+
+namespace air {
+
+namespace {
+
+constexpr int kDiffeoBlocks = 8192;  // grid-stride launches
+
+__host__ inline int grid_for(long long total) {
+    const long long b = (total + kBlock - 1) / kBlock;
+    return (int)(b < kDiffeoBlocks ? (b < 1 ? 1 : b) : kDiffeoBlocks);
+}
+
+// Zero-padded multilinear sample of the DIM components of field u at p
+// (voxel units); with DERIV also dval[c][a] = d sample_c / d p_a on the cell
+// [floor(p), floor(p) + 1]. Returns false for a non-finite point (the values
+// are then NaN).
+template <int DIM, bool DERIV>
+__device__ inline bool field_sample(const float* __restrict__ u, long long N, const PairDesc& P,
+                                    const float* p, float* val, float (*dval)[3], int* j,
+                                    float* f) {
+    bool finite = true;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        float pa = p[a];
+        if (!(pa == pa) || pa == INFINITY || pa == -INFINITY) finite = false;
+        pa = fminf(fmaxf(pa, -1e9f), 1e9f);
+        const float fl = floorf(pa);
+        j[a] = (int)fl;
+        f[a] = pa - fl;
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        val[c] = 0.f;
+        if (DERIV)
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) dval[c][a] = 0.f;
+    }
+    if (!finite) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            val[c] = NAN;
+            if (DERIV)
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) dval[c][a] = NAN;
+        }
+        return false;
+    }
+#pragma unroll
+    for (int cn = 0; cn < (1 << DIM); ++cn) {
+        int q[3] = {0, 0, 0};
+        bool in = true;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            q[a] = j[a] + ((cn >> a) & 1);
+            if (q[a] < 0 || q[a] > P.n[a] - 1) in = false;
+        }
+        if (!in) continue;
+        const long long idx = q[0] + (long long)P.n[0] * (q[1] + (DIM == 3 ? (long long)P.n[1] * q[2] : 0));
+        float w = 1.f;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) w *= ((cn >> a) & 1) ? f[a] : 1.f - f[a];
+        float wa[3];
+        if (DERIV) {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                float t = ((cn >> a) & 1) ? 1.f : -1.f;
+#pragma unroll
+                for (int b = 0; b < DIM; ++b)
+                    if (b != a) t *= ((cn >> b) & 1) ? f[b] : 1.f - f[b];
+                wa[a] = t;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const float uv = u[c * N + idx];
+            val[c] += w * uv;
+            if (DERIV)
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) dval[c][a] += wa[a] * uv;
+        }
+    }
+    return true;
+}
+
+template <int DIM>
+__device__ inline void voxel_coords(const PairDesc& P, long long v, int* idx) {
+    idx[0] = (int)(v % P.n[0]);
+    idx[1] = (int)((v / P.n[0]) % P.n[1]);
+    idx[2] = DIM == 3 ? (int)(v / ((long long)P.n[0] * P.n[1])) : 0;
+}
+
+// u = scale * B theta (direct sum over the 4^d supporting controls).
+template <int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_bs_field(const PairDesc P, const float* __restrict__ consts, const float* __restrict__ th,
+           float scale, float* __restrict__ out) {
+    const long long N = P.nvox;
+    const long long NC = (long long)P.nc[0] * P.nc[1] * P.nc[2];
+    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < N;
+         v += (long long)gridDim.x * kBlock) {
+        int idx[3];
+        voxel_coords<DIM>(P, v, idx);
+        int i0[3];
+        const float* w[3];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            i0[a] = idx[a] / P.sp[a];
+            w[a] = consts + P.wtab_off[a] + (idx[a] - i0[a] * P.sp[a]) * 4;
+        }
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            float acc = 0.f;
+            for (int kz = 0; kz < (DIM == 3 ? 4 : 1); ++kz) {
+                const float wz = DIM == 3 ? w[2][kz] : 1.f;
+                const int jz = DIM == 3 ? i0[2] + kz : 0;
+                for (int ky = 0; ky < 4; ++ky) {
+                    const float* row = th + c * NC + ((long long)jz * P.nc[1] + i0[1] + ky) * P.nc[0] + i0[0];
+                    const float wyz = wz * w[1][ky];
+                    acc += wyz * (w[0][0] * row[0] + w[0][1] * row[1] + w[0][2] * row[2] +
+                                  w[0][3] * row[3]);
+                }
+            }
+            out[c * N + v] = scale * acc;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_scale_copy(const float* __restrict__ in, float scale, long long n, float* __restrict__ out) {
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kBlock)
+        out[i] = scale * in[i];
+}
+
+// One squaring: out(x) = u(x) + u(x + u(x)).
+template <int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_compose(const PairDesc P, const float* __restrict__ u, float* __restrict__ out) {
+    const long long N = P.nvox;
+    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < N;
+         v += (long long)gridDim.x * kBlock) {
+        int idx[3];
+        voxel_coords<DIM>(P, v, idx);
+        float p[3], val[3], f[3];
+        int j[3];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) p[a] = fmaf(u[a * N + v], P.s[a], (float)idx[a]);
+        field_sample<DIM, false>(u, N, P, p, val, nullptr, j, f);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) out[c * N + v] = u[c * N + v] + val[c];
+    }
+}
+
+// Adjoint of one squaring, per voxel part: gin_a(x) = gout_a(x) +
+// s_a sum_c gout_c(x) d[u_c sampled](p(x)) / dp_a.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_compose_adj_point(const PairDesc P, const float* __restrict__ u, const float* __restrict__ gout,
+                    float* __restrict__ gin) {
+    const long long N = P.nvox;
+    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < N;
+         v += (long long)gridDim.x * kBlock) {
+        int idx[3];
+        voxel_coords<DIM>(P, v, idx);
+        float p[3], val[3], f[3], dv[3][3];
+        int j[3];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) p[a] = fmaf(u[a * N + v], P.s[a], (float)idx[a]);
+        field_sample<DIM, true>(u, N, P, p, val, dv, j, f);
+        float go[3];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) go[c] = gout[c * N + v];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            float t = 0.f;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) t += go[c] * dv[c][a];
+            gin[a * N + v] = go[a] + P.s[a] * t;
+        }
+    }
+}
+
+// Adjoint of one squaring, scattered part: gin_c(q) += w_q(p(x)) gout_c(x)
+// for the in-range corners q of every voxel's sample point (FP32 atomics).
+template <int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_compose_adj_scatter(const PairDesc P, const float* __restrict__ u,
+                      const float* __restrict__ gout, float* gin) {
+    const long long N = P.nvox;
+    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < N;
+         v += (long long)gridDim.x * kBlock) {
+        int idx[3];
+        voxel_coords<DIM>(P, v, idx);
+        float p[3], f[3];
+        int j[3];
+        bool finite = true;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            p[a] = fmaf(u[a * N + v], P.s[a], (float)idx[a]);
+            if (!(p[a] == p[a]) || p[a] == INFINITY || p[a] == -INFINITY) finite = false;
+            const float pa = fminf(fmaxf(p[a], -1e9f), 1e9f);
+            const float fl = floorf(pa);
+            j[a] = (int)fl;
+            f[a] = pa - fl;
+        }
+        if (!finite) continue;
+        float go[3];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) go[c] = gout[c * N + v];
+#pragma unroll
+        for (int cn = 0; cn < (1 << DIM); ++cn) {
+            int q[3] = {0, 0, 0};
+            bool in = true;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                q[a] = j[a] + ((cn >> a) & 1);
+                if (q[a] < 0 || q[a] > P.n[a] - 1) in = false;
+            }
+            if (!in) continue;
+            float w = 1.f;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) w *= ((cn >> a) & 1) ? f[a] : 1.f - f[a];
+            const long long qi = q[0] + (long long)P.n[0] * (q[1] + (DIM == 3 ? (long long)P.n[1] * q[2] : 0));
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) atomicAdd(gin + c * N + qi, w * go[c]);
+        }
+    }
+}
+
+// Transposed B-spline expansion, one axis at a time. Input [d][A][L][B]
+// (L the axis being contracted, length n), output [d][A][nc][B]: out[.][j][.]
+// = sum over voxels x of control j's support of w(x, j) in[.][x][.], where
+// voxel x in cell i = x / sp with offset r carries weight table[r][j - i].
+__global__ void __launch_bounds__(kBlock)
+k_bs_adjoint_axis(const float* __restrict__ in, int d, long long A, int n, long long B, int nc,
+                  int sp, const float* __restrict__ wtab, float scale, float* __restrict__ out) {
+    const long long total = (long long)d * A * nc * B;
+    for (long long o = (long long)blockIdx.x * kBlock + threadIdx.x; o < total;
+         o += (long long)gridDim.x * kBlock) {
+        const long long b = o % B;
+        const int jc = (int)((o / B) % nc);
+        const long long ca = o / (B * nc);  // c * A + a
+        const int x0 = max(0, (jc - 3) * sp), x1 = min(n - 1, (jc + 1) * sp - 1);
+        float acc = 0.f;
+        for (int x = x0; x <= x1; ++x) {
+            const int i = x / sp;
+            acc += wtab[(x - i * sp) * 4 + (jc - i)] * in[(ca * n + x) * B + b];
+        }
+        out[o] = scale * acc;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_velocity(const PairDesc& P, const float* consts_dev, int transform, int dim,
+                           const float* theta, float scale, float* out, hipStream_t s) {
+    if (transform == AIR_TF_DENSE) {
+        const long long n = (long long)dim * P.nvox;
+        hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n)), dim3(kBlock), 0, s, theta, scale, n,
+                           out);
+    } else if (dim == 3) {
+        hipLaunchKernelGGL(k_bs_field<3>, dim3(grid_for(P.nvox)), dim3(kBlock), 0, s, P,
+                           consts_dev, theta, scale, out);
+    } else {
+        hipLaunchKernelGGL(k_bs_field<2>, dim3(grid_for(P.nvox)), dim3(kBlock), 0, s, P,
+                           consts_dev, theta, scale, out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_compose(const PairDesc& P, int dim, const float* u, float* out, hipStream_t s) {
+    if (dim == 3)
+        hipLaunchKernelGGL(k_compose<3>, dim3(grid_for(P.nvox)), dim3(kBlock), 0, s, P, u, out);
+    else
+        hipLaunchKernelGGL(k_compose<2>, dim3(grid_for(P.nvox)), dim3(kBlock), 0, s, P, u, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_compose_adjoint(const PairDesc& P, int dim, const float* u, const float* gout,
+                                  float* gin, hipStream_t s) {
+    const int g = grid_for(P.nvox);
+    if (dim == 3) {
+        hipLaunchKernelGGL(k_compose_adj_point<3>, dim3(g), dim3(kBlock), 0, s, P, u, gout, gin);
+        hipLaunchKernelGGL(k_compose_adj_scatter<3>, dim3(g), dim3(kBlock), 0, s, P, u, gout, gin);
+    } else {
+        hipLaunchKernelGGL(k_compose_adj_point<2>, dim3(g), dim3(kBlock), 0, s, P, u, gout, gin);
+        hipLaunchKernelGGL(k_compose_adj_scatter<2>, dim3(g), dim3(kBlock), 0, s, P, u, gout, gin);
+    }
+    return hipGetLastError();
+}
+
+// grad = scale * (dL/dv -> dL/dtheta): dense: a scaled copy; B-spline: the
+// transposed expansion, x then y (then z), through t1 [d][nz][ny][ncx] and
+// t2 [d][nz][ncy][ncx].
+hipError_t launch_velocity_adjoint(const PairDesc& P, const float* consts_dev, int transform,
+                                   int dim, const float* g, float scale, float* t1, float* t2,
+                                   float* grad, hipStream_t s) {
+    if (transform == AIR_TF_DENSE) {
+        const long long n = (long long)dim * P.nvox;
+        hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n)), dim3(kBlock), 0, s, g, scale, n, grad);
+        return hipGetLastError();
+    }
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    const int cx = P.nc[0], cy = P.nc[1], cz = P.nc[2];
+    // x: [d][nz*ny][nx][1] -> [d][nz*ny][cx][1]
+    long long tot = (long long)dim * nz * ny * cx;
+    hipLaunchKernelGGL(k_bs_adjoint_axis, dim3(grid_for(tot)), dim3(kBlock), 0, s, g, dim,
+                       (long long)nz * ny, nx, 1LL, cx, P.sp[0], consts_dev + P.wtab_off[0], 1.f,
+                       t1);
+    // y: [d][nz][ny][cx] -> [d][nz][cy][cx]
+    tot = (long long)dim * nz * cy * cx;
+    float* ydst = dim == 3 ? t2 : grad;
+    hipLaunchKernelGGL(k_bs_adjoint_axis, dim3(grid_for(tot)), dim3(kBlock), 0, s, t1, dim,
+                       (long long)nz, ny, (long long)cx, cy, P.sp[1], consts_dev + P.wtab_off[1],
+                       dim == 3 ? 1.f : scale, ydst);
+    if (dim == 3) {
+        // z: [d][1][nz][cy*cx] -> [d][1][cz][cy*cx]
+        tot = (long long)dim * cz * cy * cx;
+        hipLaunchKernelGGL(k_bs_adjoint_axis, dim3(grid_for(tot)), dim3(kBlock), 0, s, t2, dim,
+                           1LL, nz, (long long)cy * cx, cz, P.sp[2], consts_dev + P.wtab_off[2],
+                           scale, grad);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace air

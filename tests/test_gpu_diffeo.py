@@ -1,0 +1,151 @@
+"""GPU parity of the diffeomorphic transform (Sec. III-D, f = exp(v) by
+scaling and squaring) against the FP64 oracle on the same seeded FP32 inputs.
+
+Tolerances as for the other paths: objective relative error <= 1e-5,
+gradient norm-wise relative error <= 1e-4, displacement norm-wise <= 1e-5.
+The adjoint scatters with FP32 atomics, so repeated GPU runs agree to
+rounding, not bitwise.
+"""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1806_09907_amd import api, synth
+from paper_1806_09907_amd._lib import AirError
+
+pytestmark = pytest.mark.gpu
+
+VAL_TOL = 1e-5
+GRAD_TOL = 1e-4
+DEV = "cuda"
+
+
+def oprob(p: api.Problem) -> O.Problem:
+    return O.Problem(n=p.n, transform=p.transform, spacing=p.spacing,
+                     similarity=p.similarity, lambda_diff=p.lambda_diff,
+                     diffeo_steps=p.diffeo_steps)
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-30)
+
+
+@functools.lru_cache(maxsize=None)
+def inputs(n, seed):
+    d = len(n)
+    pair = synth.blob_pair(n, seed, O.warp_fn_fp32, nblobs=12 if d == 2 else 40,
+                           disp_std_vox=1.5, noise_std=0.01, spacing=8)
+    return pair.fixed, pair.moving
+
+
+def theta_for(p, seed, std_vox=1.5):
+    if p.transform == api.TF_DENSE:
+        return synth.smooth_dense(p.n, std_vox, seed, sigma=3.0)
+    return synth.random_theta(p.n, p.spacing, std_vox, seed)
+
+
+CASES = [
+    # n, transform, spacing, similarity, lambda, K
+    ((48, 40), api.TF_DENSE, (1, 1), api.SIM_MSE, 0.5, 4),
+    ((48, 40), api.TF_BSPLINE3, (8, 8), api.SIM_NCC, 0.1, 6),
+    ((33, 30, 28), api.TF_DENSE, (1, 1, 1), api.SIM_MSE, 1.0, 3),
+    ((33, 30, 28), api.TF_DENSE, (1, 1, 1), api.SIM_NCC, 0.2, 6),
+    ((40, 36, 44), api.TF_BSPLINE3, (8, 8, 8), api.SIM_NCC, 0.05, 6),
+    ((37, 29, 23), api.TF_BSPLINE3, (5, 3, 7), api.SIM_MSE, 0.3, 4),
+]
+
+
+@pytest.mark.parametrize("n,tf,sp,sim,lam,K", CASES)
+def test_displacement_parity(n, tf, sp, sim, lam, K):
+    print(f"case displacement n={n} tf={tf} K={K}", flush=True)
+    p = api.Problem(n=n, transform=tf, spacing=sp, similarity=sim, lambda_diff=lam,
+                    diffeo_steps=K)
+    th = theta_for(p, 1)
+    u = api.displacement(api.Plan(p), gpu(th)).double().cpu().numpy()
+    uo = O.displacement(oprob(p), th)
+    assert rel(u, uo) <= 1e-5
+    # K = 0 is the velocity itself
+    p0 = api.Problem(n=n, transform=tf, spacing=sp, similarity=sim, lambda_diff=lam)
+    u0 = api.displacement(api.Plan(p0), gpu(th)).double().cpu().numpy()
+    assert rel(u0, O.velocity(oprob(p0), th)) <= 1e-6
+
+
+@pytest.mark.parametrize("n,tf,sp,sim,lam,K", CASES)
+def test_objective_parity(n, tf, sp, sim, lam, K):
+    print(f"case objective n={n} tf={tf} sim={sim} K={K}", flush=True)
+    p = api.Problem(n=n, transform=tf, spacing=sp, similarity=sim, lambda_diff=lam,
+                    diffeo_steps=K)
+    F, M = inputs(n, 7)
+    th = theta_for(p, 2)
+    plan = api.Plan(p)
+    v, g = api.objective_and_grad(plan, gpu(F), gpu(M), gpu(th))
+    torch.cuda.synchronize()
+    vo, go, flags = O.objective_and_grad(oprob(p), F, M, th)
+    assert flags == 0 and api.get_flags(plan)[0] == 0
+    assert abs(float(v) - vo) <= VAL_TOL * abs(vo)
+    assert rel(g.double().cpu().numpy(), go) <= GRAD_TOL
+
+
+def test_objective_parity_128_bspline_ncc():
+    """The 128^3 B-spline NCC workload with f = exp(v), 6 squarings."""
+    n = (128, 128, 128)
+    print("case objective 128^3 bspline NCC K=6", flush=True)
+    p = api.Problem(n=n, spacing=(8, 8, 8), similarity=api.SIM_NCC, lambda_diff=0.05,
+                    diffeo_steps=6)
+    pair = synth.pair_3d(warp=O.warp_fn_fp32)
+    th = synth.random_theta(n, (8, 8, 8), 1.0, 5000)
+    plan = api.Plan(p)
+    v, g = api.objective_and_grad(plan, gpu(pair.fixed), gpu(pair.moving), gpu(th))
+    torch.cuda.synchronize()
+    vo, go, flags = O.objective_and_grad(oprob(p), pair.fixed, pair.moving, th)
+    assert flags == 0
+    assert abs(float(v) - vo) <= VAL_TOL * abs(vo)
+    assert rel(g.double().cpu().numpy(), go) <= GRAD_TOL
+
+
+@pytest.mark.parametrize("tf", [api.TF_DENSE, api.TF_BSPLINE3])
+def test_regulariser_parity(tf):
+    n = (30, 26, 22)
+    sp = (1, 1, 1) if tf == api.TF_DENSE else (4, 4, 4)
+    p = api.Problem(n=n, transform=tf, spacing=sp, similarity=api.SIM_MSE, lambda_diff=1.0,
+                    diffeo_steps=5)
+    th = theta_for(p, 3)
+    R, g = api.regulariser(api.Plan(p), gpu(th))
+    Ro, go = O.regulariser(oprob(p), th)
+    assert abs(float(R) - Ro) <= VAL_TOL * abs(Ro)
+    assert rel(g.double().cpu().numpy(), go) <= GRAD_TOL
+
+
+def test_repeat_runs_agree_to_rounding():
+    """The atomic scatter makes runs differ only in the last bits."""
+    n = (33, 30, 28)
+    p = api.Problem(n=n, transform=api.TF_DENSE, spacing=(1, 1, 1), similarity=api.SIM_MSE,
+                    lambda_diff=1.0, diffeo_steps=6)
+    F, M = inputs(n, 7)
+    th = gpu(theta_for(p, 2))
+    plan = api.Plan(p)
+    v1, g1 = api.objective_and_grad(plan, gpu(F), gpu(M), th)
+    g1 = g1.clone()
+    v2, g2 = api.objective_and_grad(plan, gpu(F), gpu(M), th)
+    assert float(v1) == float(v2)   # the forward has no atomics
+    assert rel(g2.double().cpu().numpy(), g1.double().cpu().numpy()) <= 1e-6
+
+
+def test_unsupported_combinations():
+    n = (20, 18, 16)
+    p = api.Problem(n=n, transform=api.TF_DENSE, spacing=(1, 1, 1), similarity=api.SIM_MSE,
+                    diffeo_steps=3)
+    plan = api.Plan(p)
+    th = gpu(np.zeros(p.param_shape()))
+    M = gpu(np.zeros(p.shape))
+    with pytest.raises(AirError):
+        api.warp(plan, M, th)
+    with pytest.raises(AirError):
+        api.Plan([p, p])
