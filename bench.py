@@ -5,7 +5,9 @@ distinct 128^3 pairs (cubic B-spline, spacing 8, NCC + 0.05 diffusion) in one
 batched launch, inputs resident in HBM (1.08 GB, beyond the 256 MB Infinity
 Cache). Other workloads (--workload): `uneven48` (48 pairs with sides from
 {96..160} in one launch), `dense256` (256^3 dense field, MSE + 1.0 diffusion),
-`latency2d` (one 64^2 B-spline MSE pair per step).
+`latency2d` (one 64^2 B-spline MSE pair per step), `diffeo256` / `diffeo2d`
+(the dense 256^3 / 4096^2 evaluation with f = exp(v), beside the same
+evaluation without the exponential).
 
 Prints one JSON line. `roofline` reports the dominant kernel from HIP events
 the library records around it on its own stream; `traffic` comes from
@@ -68,7 +70,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batch128",
-                    choices=["batch128", "uneven48", "dense256", "latency2d"])
+                    choices=["batch128", "uneven48", "dense256", "latency2d", "diffeo256",
+                             "diffeo2d"])
     ap.add_argument("--pairs", type=int, default=64)
     ap.add_argument("--tiling", type=int, default=-1, help="-1: autotune cache or default")
     ap.add_argument("--autotune-out", default="",
@@ -110,7 +113,28 @@ def cpu_baseline(seconds, workload):
     import oracle as O
     from paper_1806_09907_amd import synth
 
-    if workload == "dense256":
+    scale = 1.0
+    if workload in ("diffeo256", "diffeo2d"):
+        # a quarter of the voxels per axis pair (2D) or an eighth (3D), same
+        # recipe and squarings; the rate is scaled by the voxel ratio
+        if workload == "diffeo256":
+            n3 = (128, 128, 128)
+            pair = synth.ct_pair(128, None, O.warp_fn_fp32)
+            scale = 1.0 / 8.0
+        else:
+            n3 = (2048, 2048)
+            rng = np.random.default_rng(synth.seed_for(0))
+            fixed = synth.blobs(tuple(reversed(n3)), 12, rng).astype(np.float32)
+            wp = O.Problem(n=n3, transform=O.TF_DENSE, spacing=(1, 1), similarity=O.SIM_MSE)
+            moving = O.warp(wp, fixed, synth.smooth_dense(n3, 2.0, 78))[0].astype(np.float32)
+            pair = synth.Pair(fixed, moving, None, n3, (1, 1), synth.seed_for(0))
+            scale = 1.0 / 4.0
+        p = O.Problem(n=n3, transform=O.TF_DENSE, spacing=(1,) * len(n3), similarity=O.SIM_MSE,
+                      lambda_diff=1.0, diffeo_steps=6)
+        th = synth.smooth_dense(n3, 2.0, 77)
+        desc = (f"one {'x'.join(map(str, n3))} dense MSE pair with exp by 6 squarings, "
+                f"rate scaled by the voxel ratio {scale}")
+    elif workload == "dense256":
         n3 = (256, 256, 256)
         pair = synth.ct_pair(256, None, O.warp_fn_fp32)
         p = O.Problem(n=n3, transform=O.TF_DENSE, spacing=(1, 1, 1), similarity=O.SIM_MSE,
@@ -146,9 +170,9 @@ def cpu_baseline(seconds, workload):
     O.set_threads(1)
     n1, el1 = rate(seconds / 3)
     O.set_threads(cores)
-    return {"value": n / el, "unit": "evals/s", "cores": cores, "kind": "oracle",
+    return {"value": scale * n / el, "unit": "evals/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} evaluations of {desc} in {el:.1f} s (FP64, OpenMP over slabs)",
-            "value_one_core": n1 / el1,
+            "value_one_core": scale * n1 / el1,
             "sample_one_core": f"{n1} evaluations in {el1:.1f} s on one thread"}
 
 
@@ -341,6 +365,78 @@ def run_dense(args, dev):
     }
 
 
+def run_diffeo(args, dev, three_d: bool):
+    """Dense MSE + 1.0 diffusion with f = exp(v) (6 squarings) against the same
+    evaluation without the exponential, as the paper's Table I compares
+    them; 256^3 CT-like in 3D, 4096^2 blobs in 2D."""
+    import torch
+
+    from paper_1806_09907_amd import api, synth
+
+    K = 6
+    if three_d:
+        n = (256, 256, 256)
+        progress("painting the 256^3 CT-like pair")
+        pair = synth.ct_pair(256, None, gpu_warp_fn(dev))
+        th = synth.smooth_dense(n, 2.0, 77)
+        desc = "256^3 CT-like, dense velocity, exp by 6 squarings, MSE + 1.0 diffusion"
+    else:
+        n = (4096, 4096)
+        progress("painting the 4096^2 blob pair")
+        # moving = fixed warped by a smooth dense field (a 2D B-spline plan keeps
+        # its whole control grid in LDS for the regulariser: at most ~57^2
+        # controls, too few for spacing 8 at this size)
+        rng = np.random.default_rng(synth.seed_for(0))
+        fixed = synth.blobs(tuple(reversed(n)), 12, rng).astype(np.float32)
+        wplan = api.Plan(api.Problem(n=n, transform=api.TF_DENSE, spacing=(1, 1),
+                                     similarity=api.SIM_MSE))
+        Fg = torch.from_numpy(fixed).to(dev)
+        Mg, _ = api.warp(wplan, Fg, torch.from_numpy(synth.smooth_dense(n, 2.0, 78)).to(dev),
+                         want_mask=False)
+        pair = synth.Pair(fixed, Mg.cpu().numpy(), None, n, (1, 1), synth.seed_for(0))
+        th = synth.smooth_dense(n, 2.0, 77)
+        desc = "4096^2 blobs, dense velocity, exp by 6 squarings, MSE + 1.0 diffusion"
+    F = torch.from_numpy(pair.fixed).to(dev)
+    M = torch.from_numpy(pair.moving).to(dev)
+    tht = torch.from_numpy(th).to(dev)
+    d = len(n)
+    sp = (1,) * d
+    value = torch.empty((), dtype=torch.float32, device=dev)
+    grad = torch.empty_like(tht)
+    plain = api.Plan(api.Problem(n=n, transform=api.TF_DENSE, spacing=sp, similarity=api.SIM_MSE,
+                                 lambda_diff=1.0))
+    diff = api.Plan(api.Problem(n=n, transform=api.TF_DENSE, spacing=sp, similarity=api.SIM_MSE,
+                                lambda_diff=1.0, diffeo_steps=K))
+    plain.prepare()
+    diff.prepare()
+    progress("timing")
+    ms_plain, _ = timed(plain, args.steps, args.warmup,
+                        lambda: api.objective_and_grad(plain, F, M, tht, value, grad))
+    ms_diff, ev_ms = timed(diff, args.steps, args.warmup,
+                           lambda: api.objective_and_grad(diff, F, M, tht, value, grad))
+    N = int(np.prod(n))
+    dN4 = 4 * d * N
+    # algorithmic bytes of one evaluation: v -> u_0 (read + write), K squarings
+    # (read u_k, write u_k+1), the dense evaluation at u_K (F, M, u, gradient,
+    # and the count pass over u), K adjoint steps (point term: u_k, g, write;
+    # scatter: u_k, g, and a read-modify-write of the target), the scaled copy out
+    bytes_eval = (2 * dN4 + K * 2 * dN4 + (8 * N + 2 * dN4) + dN4 + K * (3 * dN4 + 4 * dN4)
+                  + 2 * dN4)
+    achieved = bytes_eval / (ev_ms / 1e3) / 1e9
+    return {
+        "metric": f"objective+grad evals/s, {desc}",
+        "value": 1e3 / ms_diff, "unit": "evals/s", "ms_per_step": ms_diff,
+        "config": {"workload": desc, "n": list(n), "squarings": K,
+                   "plain_ms_per_eval": ms_plain, "diffeo_over_plain": ms_diff / ms_plain,
+                   "algorithmic_bytes_per_step": bytes_eval},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "whole diffeomorphic evaluation (velocity, squarings, dense "
+                               "evaluation, adjoint steps)", "kernel_ms": ev_ms,
+                     "algorithmic_bytes_per_launch": bytes_eval},
+    }
+
+
 def run_latency2d(args, dev):
     import torch
 
@@ -466,6 +562,8 @@ def main():
                         "0.05 diffusion, one launch")
     elif args.workload == "dense256":
         out = run_dense(args, dev)
+    elif args.workload in ("diffeo256", "diffeo2d"):
+        out = run_diffeo(args, dev, args.workload == "diffeo256")
     else:
         out = run_latency2d(args, dev)
     line = {"metric": out["metric"], "value": out["value"], "unit": out["unit"], "n_gpus": 1,

@@ -58,6 +58,7 @@ struct WsLayout {
     size_t gfield;       // float [2][d N]: gradients going back through the squarings
     size_t bsadj1;       // float [d][nz][ny][ncx]: transposed expansion, after x
     size_t bsadj2;       // float [d][nz][ncy][ncx]: after y
+    size_t reach;        // uint32 [K + 1]: largest displacement of each u_k (float bits)
     size_t total;
 };
 

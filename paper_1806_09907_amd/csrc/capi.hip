@@ -32,8 +32,10 @@ hipError_t launch_scale(float* x, const float* s, long long n, hipStream_t st);
 hipError_t launch_velocity(const PairDesc& P, const float* consts_dev, int transform, int dim,
                            const float* theta, float scale, float* out, hipStream_t s);
 hipError_t launch_compose(const PairDesc& P, int dim, const float* u, float* out, hipStream_t s);
+hipError_t launch_field_reach(const PairDesc& P, int dim, const float* u, int nfields,
+                              unsigned int* dmax, hipStream_t s);
 hipError_t launch_compose_adjoint(const PairDesc& P, int dim, const float* u, const float* gout,
-                                  float* gin, hipStream_t s);
+                                  const unsigned int* dmax, float* gin, hipStream_t s);
 hipError_t launch_velocity_adjoint(const PairDesc& P, const float* consts_dev, int transform,
                                    int dim, const float* g, float scale, float* t1, float* t2,
                                    float* grad, hipStream_t s);
@@ -302,6 +304,7 @@ static air_status build_tables(air_plan* P) {
         const size_t t2 = bs ? (size_t)d * D.n[2] * D.nc[1] * D.nc[0] : 1;
         L.bsadj1 = off;  off = align256(off + t1 * 4);
         L.bsadj2 = off;  off = align256(off + t2 * 4);
+        L.reach = off;   off = align256(off + (size_t)(P->diffeo + 1) * 4);
     }
     L.total = off;
     return AIR_OK;
@@ -411,8 +414,10 @@ static hipError_t run_diffeo(const air_plan* P, const DeviceTables* T, void* ws,
     }
     if (e != hipSuccess || !grad) return e;
     const float* U = reinterpret_cast<const float*>(w + P->L.fields);
+    unsigned int* reach = reinterpret_cast<unsigned int*>(w + P->L.reach);
+    e = launch_field_reach(hp, P->dim, U, P->diffeo, reach, s);
     for (int k = P->diffeo - 1; k >= 0 && e == hipSuccess; --k) {
-        e = launch_compose_adjoint(hp, P->dim, U + k * dN, g, o, s);
+        e = launch_compose_adjoint(hp, P->dim, U + k * dN, g, reach + k, o, s);
         float* t = g;
         g = o;
         o = t;

@@ -7,10 +7,13 @@
 // The exponential cannot stay inside one fused pass (each squaring samples
 // the whole previous field), so the fields u_0 .. u_K live in the workspace;
 // the objective at u_K runs on the dense-field kernels, and its gradient goes
-// back through the squarings: each adjoint step adds the identity term, the
-// term through the sample point (written per voxel) and the transposed
-// interpolation (scattered with FP32 atomics, so the summation order -- and
-// the last bits of the result -- vary from run to run).
+// back through the squarings. Each adjoint step is owner-computes: a block
+// owns a tile of target voxels, adds into LDS the transposed-interpolation
+// contributions of every source voxel whose sample point can reach the tile
+// (the reach is bounded by the field's largest displacement, measured once
+// per field), then adds the identity and sample-point terms and writes each
+// target once. The LDS additions are atomic, so the summation order -- and
+// the last bits of the result -- vary from run to run.
 #include "device_common.h"
 
 namespace air {
@@ -59,6 +62,11 @@ __device__ inline bool field_sample(const float* __restrict__ u, long long N, co
         }
         return false;
     }
+    // every corner inside the volume (the common case): no per-corner tests
+    bool interior = true;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+        if (j[a] < 0 || j[a] > P.n[a] - 2) interior = false;
 #pragma unroll
     for (int cn = 0; cn < (1 << DIM); ++cn) {
         int q[3] = {0, 0, 0};
@@ -66,7 +74,7 @@ __device__ inline bool field_sample(const float* __restrict__ u, long long N, co
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
             q[a] = j[a] + ((cn >> a) & 1);
-            if (q[a] < 0 || q[a] > P.n[a] - 1) in = false;
+            if (!interior && (q[a] < 0 || q[a] > P.n[a] - 1)) in = false;
         }
         if (!in) continue;
         const long long idx = q[0] + (long long)P.n[0] * (q[1] + (DIM == 3 ? (long long)P.n[1] * q[2] : 0));
@@ -165,59 +173,98 @@ k_compose(const PairDesc P, const float* __restrict__ u, float* __restrict__ out
     }
 }
 
-// Adjoint of one squaring, per voxel part: gin_a(x) = gout_a(x) +
-// s_a sum_c gout_c(x) d[u_c sampled](p(x)) / dp_a.
+// Largest displacement of field u in voxels (max over voxels and axes of
+// |u_a| (n_a - 1)/2), as the bits of a non-negative float (ordered like
+// unsigned integers; NaN compares above every finite value). `out` must be
+// zero before the launch.
 template <int DIM>
 __global__ void __launch_bounds__(kBlock)
-k_compose_adj_point(const PairDesc P, const float* __restrict__ u, const float* __restrict__ gout,
-                    float* __restrict__ gin) {
+k_absmax(const PairDesc P, const float* __restrict__ u, unsigned int* out) {
+    __shared__ unsigned int red[kBlock / 64];
     const long long N = P.nvox;
+    float m = 0.f;
     for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < N;
          v += (long long)gridDim.x * kBlock) {
-        int idx[3];
-        voxel_coords<DIM>(P, v, idx);
-        float p[3], val[3], f[3], dv[3][3];
-        int j[3];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) p[a] = fmaf(u[a * N + v], P.s[a], (float)idx[a]);
-        field_sample<DIM, true>(u, N, P, p, val, dv, j, f);
-        float go[3];
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) go[c] = gout[c * N + v];
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            float t = 0.f;
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) t += go[c] * dv[c][a];
-            gin[a * N + v] = go[a] + P.s[a] * t;
+            const float t = fabsf(u[a * N + v]) * P.s[a];
+            m = (t > m || !(t == t)) ? t : m;
         }
+    }
+    unsigned int b = __float_as_uint(m) & 0x7fffffffu;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) b = max(b, (unsigned int)__shfl_xor((int)b, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int r = red[0];
+        for (int w = 1; w < kBlock / 64; ++w) r = max(r, red[w]);
+        atomicMax(out, r);
     }
 }
 
-// Adjoint of one squaring, scattered part: gin_c(q) += w_q(p(x)) gout_c(x)
-// for the in-range corners q of every voxel's sample point (FP32 atomics).
+__global__ void k_zero_u32(unsigned int* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// Owner-computes adjoint of one squaring. The block owns target tile T (TS
+// voxels per axis); every source voxel x within `reach` of T computes its
+// sample point and adds w_q(p(x)) gout(x) into LDS for its corners q inside T;
+// then each target q gets gin(q) = gout(q) + s_a sum_c gout_c(q) du_c/dp_a
+// at p(q) + the accumulated transpose.
 template <int DIM>
 __global__ void __launch_bounds__(kBlock)
-k_compose_adj_scatter(const PairDesc P, const float* __restrict__ u,
-                      const float* __restrict__ gout, float* gin) {
+k_compose_adj_tile(const PairDesc P, const float* __restrict__ u, const float* __restrict__ gout,
+                   const unsigned int* __restrict__ dmax_bits, float* __restrict__ gin) {
+    constexpr int TS = DIM == 3 ? 16 : 64;  // 4096 targets per tile
+    constexpr int TV = DIM == 3 ? TS * TS * TS : TS * TS;
+    __shared__ float acc[DIM][TV];
     const long long N = P.nvox;
-    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < N;
-         v += (long long)gridDim.x * kBlock) {
-        int idx[3];
-        voxel_coords<DIM>(P, v, idx);
-        float p[3], f[3];
+    const int nt0 = cdiv(P.n[0], TS), nt1 = cdiv(P.n[1], TS);
+    const int b = blockIdx.x;
+    int o[3] = {(b % nt0) * TS, ((b / nt0) % nt1) * TS, DIM == 3 ? (b / (nt0 * nt1)) * TS : 0};
+    for (int i = threadIdx.x; i < DIM * TV; i += kBlock) (&acc[0][0])[i] = 0.f;
+    // reach: corners lie within floor(p) .. floor(p) + 1 and |p - x| <= dmax
+    const float dm = __uint_as_float(*dmax_bits);
+    int h = (dm == dm && dm < 1e6f) ? (int)ceilf(dm) + 1 : (1 << 20);
+    int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        lo[a] = max(0, o[a] - h);
+        const int hi = min(P.n[a], o[a] + TS + h);
+        ext[a] = hi - lo[a];
+    }
+    __syncthreads();
+    // the box holds at most N < 2^29 voxels: 32-bit index arithmetic
+    const int box = ext[0] * ext[1] * ext[2];
+    const int e01 = ext[0] * ext[1];
+    for (int i = threadIdx.x; i < box; i += kBlock) {
+        int x[3];
+        const int r = i / ext[0];
+        x[0] = lo[0] + (i - r * ext[0]);
+        x[1] = lo[1] + (DIM == 3 ? r % ext[1] : r);
+        x[2] = DIM == 3 ? lo[2] + i / e01 : 0;
+        const long long v = x[0] + (long long)P.n[0] * (x[1] + (DIM == 3 ? (long long)P.n[1] * x[2] : 0));
+        float f[3];
         int j[3];
         bool finite = true;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            p[a] = fmaf(u[a * N + v], P.s[a], (float)idx[a]);
-            if (!(p[a] == p[a]) || p[a] == INFINITY || p[a] == -INFINITY) finite = false;
-            const float pa = fminf(fmaxf(p[a], -1e9f), 1e9f);
+            const float pa0 = fmaf(u[a * N + v], P.s[a], (float)x[a]);
+            if (!(pa0 == pa0) || pa0 == INFINITY || pa0 == -INFINITY) finite = false;
+            const float pa = fminf(fmaxf(pa0, -1e9f), 1e9f);
             const float fl = floorf(pa);
             j[a] = (int)fl;
             f[a] = pa - fl;
         }
         if (!finite) continue;
+        // skip sources whose cell misses the tile
+        bool near = true;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+            if (j[a] + 1 < o[a] || j[a] > o[a] + TS - 1) near = false;
+        if (!near) continue;
         float go[3];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) go[c] = gout[c * N + v];
@@ -228,15 +275,39 @@ k_compose_adj_scatter(const PairDesc P, const float* __restrict__ u,
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
                 q[a] = j[a] + ((cn >> a) & 1);
-                if (q[a] < 0 || q[a] > P.n[a] - 1) in = false;
+                if (q[a] < o[a] || q[a] > o[a] + TS - 1 || q[a] > P.n[a] - 1) in = false;
             }
             if (!in) continue;
             float w = 1.f;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) w *= ((cn >> a) & 1) ? f[a] : 1.f - f[a];
-            const long long qi = q[0] + (long long)P.n[0] * (q[1] + (DIM == 3 ? (long long)P.n[1] * q[2] : 0));
+            const int t = (q[0] - o[0]) + TS * ((q[1] - o[1]) + (DIM == 3 ? TS * (q[2] - o[2]) : 0));
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) atomicAdd(gin + c * N + qi, w * go[c]);
+            for (int c = 0; c < DIM; ++c) atomicAdd(&acc[c][t], w * go[c]);
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < TV; t += kBlock) {
+        int x[3];
+        x[0] = o[0] + t % TS;
+        x[1] = o[1] + (t / TS) % TS;
+        x[2] = DIM == 3 ? o[2] + t / (TS * TS) : 0;
+        if (x[0] >= P.n[0] || x[1] >= P.n[1] || (DIM == 3 && x[2] >= P.n[2])) continue;
+        const long long v = x[0] + (long long)P.n[0] * (x[1] + (DIM == 3 ? (long long)P.n[1] * x[2] : 0));
+        float p[3], val[3], f[3], dv[3][3];
+        int j[3];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) p[a] = fmaf(u[a * N + v], P.s[a], (float)x[a]);
+        field_sample<DIM, true>(u, N, P, p, val, dv, j, f);
+        float go[3];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) go[c] = gout[c * N + v];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            float tsum = 0.f;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) tsum += go[c] * dv[c][a];
+            gin[a * N + v] = go[a] + P.s[a] * tsum + acc[a][t];
         }
     }
 }
@@ -290,15 +361,32 @@ hipError_t launch_compose(const PairDesc& P, int dim, const float* u, float* out
     return hipGetLastError();
 }
 
+// dmax[k] (uint bits of a float) = largest displacement of field k, for the
+// nfields fields u + k * dim * N.
+hipError_t launch_field_reach(const PairDesc& P, int dim, const float* u, int nfields,
+                              unsigned int* dmax, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, dmax, nfields);
+    const long long dN = (long long)dim * P.nvox;
+    const int g = grid_for(P.nvox) < 1024 ? grid_for(P.nvox) : 1024;
+    for (int k = 0; k < nfields; ++k) {
+        if (dim == 3)
+            hipLaunchKernelGGL(k_absmax<3>, dim3(g), dim3(kBlock), 0, s, P, u + k * dN, dmax + k);
+        else
+            hipLaunchKernelGGL(k_absmax<2>, dim3(g), dim3(kBlock), 0, s, P, u + k * dN, dmax + k);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_compose_adjoint(const PairDesc& P, int dim, const float* u, const float* gout,
-                                  float* gin, hipStream_t s) {
-    const int g = grid_for(P.nvox);
+                                  const unsigned int* dmax, float* gin, hipStream_t s) {
     if (dim == 3) {
-        hipLaunchKernelGGL(k_compose_adj_point<3>, dim3(g), dim3(kBlock), 0, s, P, u, gout, gin);
-        hipLaunchKernelGGL(k_compose_adj_scatter<3>, dim3(g), dim3(kBlock), 0, s, P, u, gout, gin);
+        const int nt = cdiv(P.n[0], 16) * cdiv(P.n[1], 16) * cdiv(P.n[2], 16);
+        hipLaunchKernelGGL(k_compose_adj_tile<3>, dim3(nt), dim3(kBlock), 0, s, P, u, gout, dmax,
+                           gin);
     } else {
-        hipLaunchKernelGGL(k_compose_adj_point<2>, dim3(g), dim3(kBlock), 0, s, P, u, gout, gin);
-        hipLaunchKernelGGL(k_compose_adj_scatter<2>, dim3(g), dim3(kBlock), 0, s, P, u, gout, gin);
+        const int nt = cdiv(P.n[0], 64) * cdiv(P.n[1], 64);
+        hipLaunchKernelGGL(k_compose_adj_tile<2>, dim3(nt), dim3(kBlock), 0, s, P, u, gout, dmax,
+                           gin);
     }
     return hipGetLastError();
 }
