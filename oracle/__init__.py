@@ -21,6 +21,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SIM_MSE, SIM_NCC = 0, 1
 TF_BSPLINE3, TF_DENSE = 0, 1
 FLAG_NONFINITE, FLAG_DEGENERATE = 1, 2
+REG_DIFFUSION, REG_ANISO_TV, REG_ISO_TV = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -39,7 +40,7 @@ class _Problem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3),
                 ("transform", ctypes.c_int), ("spacing", ctypes.c_int * 3),
                 ("similarity", ctypes.c_int), ("lambda_diff", ctypes.c_double),
-                ("diffeo_steps", ctypes.c_int)]
+                ("diffeo_steps", ctypes.c_int), ("regulariser", ctypes.c_int)]
 
 
 _lib = None
@@ -71,6 +72,7 @@ def lib():
             "airo_warp": (None, [P, dp, dp, dp, u8]),
             "airo_similarity": (ctypes.c_int, [P, dp, dp, u8, dp, dp]),
             "airo_diffusion": (None, [P, dp, dp, dp]),
+            "airo_tv": (None, [P, dp, ctypes.c_int, dp, dp]),
             "airo_regulariser": (None, [P, dp, dp, dp]),
             "airo_objective_and_grad": (ctypes.c_int, [P, dp, dp, dp, dp, dp]),
             "airo_adam_step": (None, [dp, dp, dp, dp, ctypes.c_long, ctypes.c_double,
@@ -105,6 +107,7 @@ class Problem:
     similarity: int = SIM_NCC
     lambda_diff: float = 0.0
     diffeo_steps: int = 0      # > 0: f = exp(field) with this many squarings
+    regulariser: int = 0       # REG_DIFFUSION, REG_ANISO_TV or REG_ISO_TV
 
     @property
     def dim(self) -> int:
@@ -129,7 +132,8 @@ class Problem:
         sp = list(self.spacing[:d]) + [1] * (3 - d)
         return _Problem(d, (ctypes.c_int * 3)(*n), int(self.transform),
                         (ctypes.c_int * 3)(*sp), int(self.similarity),
-                        float(self.lambda_diff), int(self.diffeo_steps))
+                        float(self.lambda_diff), int(self.diffeo_steps),
+                        int(self.regulariser))
 
 
 def _f64(a) -> np.ndarray:
@@ -301,6 +305,16 @@ def diffusion(prob: Problem, u):
     val = ctypes.c_double(0.0)
     g = np.empty_like(u)
     lib().airo_diffusion(ctypes.byref(pc), _ptr(u), ctypes.byref(val), _ptr(g))
+    return val.value, g
+
+
+def tv(prob: Problem, u, kind: int):
+    """Total variation (REG_ANISO_TV / REG_ISO_TV) of a dense field and its gradient."""
+    pc = _check(prob)
+    u = _f64(u)
+    val = ctypes.c_double(0.0)
+    g = np.empty_like(u)
+    lib().airo_tv(ctypes.byref(pc), _ptr(u), int(kind), ctypes.byref(val), _ptr(g))
     return val.value, g
 
 

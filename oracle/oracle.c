@@ -57,6 +57,7 @@ int airo_check(const airo_problem* p) {
     if (p->transform != AIRO_TF_BSPLINE3 && p->transform != AIRO_TF_DENSE) return 1;
     if (p->similarity != AIRO_SIM_MSE && p->similarity != AIRO_SIM_NCC) return 1;
     if (p->diffeo_steps < 0 || p->diffeo_steps > 30) return 1;
+    if (p->regulariser < AIRO_REG_DIFFUSION || p->regulariser > AIRO_REG_ISO_TV) return 1;
     return 0;
 }
 
@@ -580,17 +581,87 @@ void airo_diffusion(const airo_problem* p, const double* u, double* value, doubl
     *value = total / XR;
 }
 
+void airo_tv(const airo_problem* p, const double* u, int kind, double* value, double* grad_u) {
+    const int d = p->dim;
+    const int nx = p->n[0], ny = p->n[1], nz = (d == 3) ? p->n[2] : 1;
+    const int n[3] = {nx, ny, nz};
+    const long N = (long)nx * ny * nz;
+    const long stride[3] = {1, nx, (long)nx * ny};
+    double XR = 1.0;
+    for (int a = 0; a < d; ++a) XR *= (double)(n[a] - 1);
+    /* per-voxel coefficient of each difference in the gradient:
+     * aniso: sign(D); iso: D / ||J|| (0 where the term is 0) */
+    double* coef = (double*)calloc((size_t)d * d * (size_t)N, sizeof(double));
+    double total = 0.0;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const int idx[3] = {x, y, z};
+                int in_r = 1;
+                for (int a = 0; a < d; ++a)
+                    if (idx[a] > n[a] - 2) in_r = 0;
+                if (!in_r) continue;
+                const long v = ((long)z * ny + y) * nx + x;
+                double D[3][3], ss = 0.0, l1 = 0.0;
+                for (int c = 0; c < d; ++c)
+                    for (int a = 0; a < d; ++a) {
+                        D[c][a] = u[c * N + v + stride[a]] - u[c * N + v];
+                        ss += D[c][a] * D[c][a];
+                        l1 += fabs(D[c][a]);
+                    }
+                if (kind == AIRO_REG_ANISO_TV) {
+                    total += l1;
+                    for (int c = 0; c < d; ++c)
+                        for (int a = 0; a < d; ++a)
+                            coef[((long)c * d + a) * N + v] =
+                                D[c][a] > 0.0 ? 1.0 : (D[c][a] < 0.0 ? -1.0 : 0.0);
+                } else {
+                    const double nrm = sqrt(ss);
+                    total += nrm;
+                    for (int c = 0; c < d; ++c)
+                        for (int a = 0; a < d; ++a)
+                            coef[((long)c * d + a) * N + v] = nrm > 0.0 ? D[c][a] / nrm : 0.0;
+                }
+            }
+    *value = total / XR;
+    if (grad_u) {
+        /* d/du_c(x) of the term at y: -coef at y = x, +coef at y = x - e_a */
+        for (long i = 0; i < (long)d * N; ++i) grad_u[i] = 0.0;
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    const long v = ((long)z * ny + y) * nx + x;
+                    for (int c = 0; c < d; ++c)
+                        for (int a = 0; a < d; ++a) {
+                            const double k = coef[((long)c * d + a) * N + v];
+                            if (k == 0.0) continue;
+                            grad_u[c * N + v] -= k / XR;
+                            grad_u[c * N + v + stride[a]] += k / XR;
+                        }
+                }
+    }
+    free(coef);
+}
+
+/* The regulariser the problem names, on a dense displacement u. */
+static void reg_field(const airo_problem* p, const double* u, double* value, double* grad_u) {
+    if (p->regulariser == AIRO_REG_DIFFUSION)
+        airo_diffusion(p, u, value, grad_u);
+    else
+        airo_tv(p, u, p->regulariser, value, grad_u);
+}
+
 void airo_regulariser(const airo_problem* p, const double* theta, double* value, double* grad) {
     const long N = airo_nvox(p);
     const size_t fb = sizeof(double) * (size_t)p->dim * (size_t)N;
     if (p->transform == AIRO_TF_DENSE && p->diffeo_steps <= 0) {
-        airo_diffusion(p, theta, value, grad);
+        reg_field(p, theta, value, grad);
         return;
     }
     double* u = (double*)malloc(fb);
     double* gu = grad ? (double*)malloc(fb) : NULL;
     airo_displacement(p, theta, u);
-    airo_diffusion(p, u, value, gu);
+    reg_field(p, u, value, gu);
     if (grad) displacement_adjoint(p, theta, gu, grad);
     free(u);
     free(gu);
@@ -613,7 +684,7 @@ int airo_objective_and_grad(const airo_problem* p, const double* fixed,
     airo_sample(p, moving, u, W, mask, dwdp);             /* stage 2 */
     double S = 0.0, R = 0.0;
     int flags = airo_similarity(p, fixed, W, mask, &S, dsdw);   /* stage 3 */
-    airo_diffusion(p, u, &R, g);                          /* stage 4: g = dR/du */
+    reg_field(p, u, &R, g);                               /* stage 4: g = dR/du */
     *value = S + p->lambda_diff * R;                      /* eq. (objective) */
     /* stage 5: g_a = dS/dW * dW/dp_a * (n_a - 1)/2 + lambda dR/du_a */
     for (int a = 0; a < d; ++a) {

@@ -64,7 +64,12 @@ typedef struct {
     double lambda_diff;
     int diffeo_steps; /* 0: f = the field itself; K > 0: f = exp(field) by
                          scaling and squaring with K squarings (Sec. III-D) */
+    int regulariser;  /* AIRO_REG_*: the term lambda_diff weights (Sec. III-F) */
 } airo_problem;
+
+#define AIRO_REG_DIFFUSION 0
+#define AIRO_REG_ANISO_TV 1
+#define AIRO_REG_ISO_TV 2
 
 int airo_check(const airo_problem* p);
 int airo_ncontrol(const airo_problem* p, int axis);
@@ -112,6 +117,12 @@ int airo_similarity(const airo_problem* p, const double* fixed, const double* wa
 
 /* Diffusion regulariser of u (dense field), gradient with respect to u. */
 void airo_diffusion(const airo_problem* p, const double* u, double* value, double* grad_u);
+/* Total variation of u (Sec. III-F) on the forward differences
+ * D_a u_c(x) = u_c(x + e_a) - u_c(x) over X_R, divided by |X_R|:
+ *   kind AIRO_REG_ANISO_TV: sum_c sum_a |D_a u_c(x)|;
+ *   kind AIRO_REG_ISO_TV:   sqrt(sum_c sum_a D_a u_c(x)^2)  (one norm per voxel).
+ * Gradient with the subgradient 0 where the term is 0. grad_u nullable. */
+void airo_tv(const airo_problem* p, const double* u, int kind, double* value, double* grad_u);
 /* Regulariser as a function of the parameters (theta). grad nullable. */
 void airo_regulariser(const airo_problem* p, const double* theta, double* value, double* grad);
 
