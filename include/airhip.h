@@ -66,6 +66,11 @@ typedef enum {
 
 enum { AIR_SIM_MSE = 0, AIR_SIM_NCC = 1 };
 enum { AIR_TF_BSPLINE3 = 0, AIR_TF_DENSE = 1 };
+/* Regularisers on the displacement f (Sec. III-F), on the forward
+ * differences D_a f_c(x) = f_c(x + e_a) - f_c(x) over X_R, divided by |X_R|:
+ * diffusion sum_c sum_a D^2; anisotropic TV sum_c sum_a |D|; isotropic TV
+ * sqrt(sum_c sum_a D^2) per voxel; TV takes the subgradient 0 at 0. */
+enum { AIR_REG_DIFFUSION = 0, AIR_REG_ANISO_TV = 1, AIR_REG_ISO_TV = 2 };
 /* device flag bits (per pair) */
 enum { AIR_FLAG_NONFINITE = 1u, AIR_FLAG_DEGENERATE = 2u };
 
@@ -75,13 +80,14 @@ typedef struct {
     int32_t transform;    /* AIR_TF_* */
     int32_t spacing[3];   /* B-spline control spacing in voxels, 1..64 */
     int32_t similarity;   /* AIR_SIM_* */
-    float lambda_diff;    /* weight of the diffusion regulariser, >= 0 */
+    float lambda_diff;    /* weight of the regulariser, >= 0 */
     int32_t diffeo_steps; /* 0: f is the field itself. K in 1..16: f = exp(v)
                              (Sec. III-D, stationary velocity v = the field)
                              by scaling and squaring: u_0 = v / 2^K, then K
                              times u <- u(x) + u(x + u(x)), sampled like an
                              image (zero outside, no mask). R then acts on
                              f = u_K. Plans with K > 0 hold one pair. */
+    int32_t regulariser;  /* AIR_REG_*; plans with a TV term hold one pair */
 } air_problem;
 
 /* Opaque plan: host tables for one pair or a batch of pairs that share
@@ -126,8 +132,10 @@ air_status air_similarity(const air_plan* plan, int32_t pair, const float* fixed
                           const float* warped, const uint8_t* mask, float* value,
                           void* ws, size_t ws_bytes, void* stream);
 
-/* Stage 4 (Sec. II-A eq. diffusion_regularizer): R(theta) and, if grad is
- * not NULL, dR/dtheta (not scaled by lambda). */
+/* Stage 4 (Sec. II-A eq. diffusion_regularizer; Sec. III-F for the TV
+ * terms): R(theta) of the plan's regulariser kind and, if grad is not NULL,
+ * dR/dtheta (not scaled by lambda). Dense plans require grad
+ * (AIR_ERR_INVALID_ARG otherwise). */
 air_status air_regulariser(const air_plan* plan, int32_t pair, const float* theta,
                            float* value, float* grad, void* ws, size_t ws_bytes,
                            void* stream);

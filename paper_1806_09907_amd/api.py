@@ -17,6 +17,7 @@ from ._lib import AirProblem, check, lib
 
 SIM_MSE, SIM_NCC = 0, 1
 TF_BSPLINE3, TF_DENSE = 0, 1
+REG_DIFFUSION, REG_ANISO_TV, REG_ISO_TV = 0, 1, 2
 FLAG_NONFINITE, FLAG_DEGENERATE = 1, 2
 
 
@@ -29,6 +30,7 @@ class Problem:
     similarity: int = SIM_NCC
     lambda_diff: float = 0.0
     diffeo_steps: int = 0      # > 0: f = exp(field), this many squarings (Sec. III-D)
+    regulariser: int = 0       # REG_DIFFUSION, REG_ANISO_TV or REG_ISO_TV (Sec. III-F)
 
     @property
     def dim(self) -> int:
@@ -52,7 +54,8 @@ class Problem:
         sp = list(self.spacing[:d]) + [1] * (3 - d)
         return AirProblem(d, (ctypes.c_int32 * 3)(*n), int(self.transform),
                           (ctypes.c_int32 * 3)(*sp), int(self.similarity),
-                          float(self.lambda_diff), int(self.diffeo_steps))
+                          float(self.lambda_diff), int(self.diffeo_steps),
+                          int(self.regulariser))
 
 
 def _stream() -> ctypes.c_void_p:

@@ -59,6 +59,7 @@ struct WsLayout {
     size_t bsadj1;       // float [d][nz][ny][ncx]: transposed expansion, after x
     size_t bsadj2;       // float [d][nz][ncy][ncx]: after y
     size_t reach;        // uint32 [K + 1]: largest displacement of each u_k (float bits)
+    size_t tvpart;       // double [TV blocks]: partial sums of a TV term
     size_t total;
 };
 

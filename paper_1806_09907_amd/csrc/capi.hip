@@ -38,7 +38,11 @@ hipError_t launch_compose_adjoint(const PairDesc& P, int dim, const float* u, co
                                   const unsigned int* dmax, float* gin, hipStream_t s);
 hipError_t launch_velocity_adjoint(const PairDesc& P, const float* consts_dev, int transform,
                                    int dim, const float* g, float scale, float* t1, float* t2,
-                                   float* grad, hipStream_t s);
+                                   float* grad, hipStream_t s, bool accumulate);
+int tv_partials();
+hipError_t launch_tv(const PairDesc& P, int dim, int kind, const float* u, float scale,
+                     float* grad, bool accumulate_grad, double* partial, float weight,
+                     float* value, bool accumulate_value, hipStream_t s);
 
 // Tile configurations of the fused B-spline kernel: {TX, TY, column cells}.
 // The kernel variant follows from the shape and the spacing: a spacing-8
@@ -74,6 +78,8 @@ using namespace air;
 struct air_plan {
     int npairs = 0, dim = 0, transform = 0, sim = 0;
     int diffeo = 0;  // squarings of the exponential (0: none)
+    int reg = AIR_REG_DIFFUSION;  // regulariser kind
+    float reg_weight = 0.f;       // its weight (TV plans; diffusion weights live per pair)
     int tiling = 0;
     std::vector<air_problem> probs;
     std::vector<PairDesc> pd;
@@ -145,6 +151,8 @@ static air_status validate_problem(const air_problem& p) {
     if (p.similarity != AIR_SIM_MSE && p.similarity != AIR_SIM_NCC) return AIR_ERR_INVALID_ARG;
     if (!(p.lambda_diff >= 0.f) || !isfinite(p.lambda_diff)) return AIR_ERR_INVALID_ARG;
     if (p.diffeo_steps < 0 || p.diffeo_steps > 16) return AIR_ERR_INVALID_ARG;
+    if (p.regulariser < AIR_REG_DIFFUSION || p.regulariser > AIR_REG_ISO_TV)
+        return AIR_ERR_INVALID_ARG;
     long long N = 1;
     for (int a = 0; a < p.dim; ++a) {
         if (p.n[a] < 2 || p.n[a] > 65536) return AIR_ERR_SHAPE;
@@ -196,7 +204,8 @@ static air_status build_tables(air_plan* P) {
         D.param_off = (long long)param_n;
         param_n += (size_t)D.nparam;
         D.inv_xr = (float)(1.0 / xr);
-        D.lambda = p.lambda_diff;
+        // the fused and dense kernels evaluate only the diffusion term
+        D.lambda = P->reg == AIR_REG_DIFFUSION ? p.lambda_diff : 0.f;
         max_ctrl = std::max(max_ctrl, (int)NC);
         if (bs) {
             for (int a = 0; a < d; ++a) {
@@ -295,7 +304,8 @@ static air_status build_tables(air_plan* P) {
     L.scalars = off;     off = align256(off + (size_t)P->npairs * 8 * 8);
     L.dense_stats = off; off = align256(off + std::max<size_t>(dense_n, 1) * kStatWords * 8);
     L.generic = off;     off = align256(off + (size_t)kGenericSlots * kStatWords * 8);
-    if (P->diffeo > 0) {
+    // the fields of the exponential, or the expanded B-spline field of a TV term
+    if (P->diffeo > 0 || (P->reg != AIR_REG_DIFFUSION && bs)) {
         const PairDesc& D = P->pd[0];
         const size_t dN = (size_t)d * (size_t)D.nvox;
         L.fields = off;  off = align256(off + (size_t)(P->diffeo + 1) * dN * 4);
@@ -305,6 +315,9 @@ static air_status build_tables(air_plan* P) {
         L.bsadj1 = off;  off = align256(off + t1 * 4);
         L.bsadj2 = off;  off = align256(off + t2 * 4);
         L.reach = off;   off = align256(off + (size_t)(P->diffeo + 1) * 4);
+    }
+    if (P->reg != AIR_REG_DIFFUSION) {
+        L.tvpart = off;  off = align256(off + (size_t)tv_partials() * 8);
     }
     L.total = off;
     return AIR_OK;
@@ -403,14 +416,21 @@ static hipError_t run_diffeo(const air_plan* P, const DeviceTables* T, void* ws,
     float* o = g + dN;
     LaunchCtx C = base_ctx(P, T, ws);
     C.theta0 = uK;
+    double* tvp = reinterpret_cast<double*>(w + P->L.tvpart);
     if (reg_only) {
-        e = launch_reg_dense(C, hp.dense_nblk, kDenseZc, g, value, s);
+        if (P->reg == AIR_REG_DIFFUSION)
+            e = launch_reg_dense(C, hp.dense_nblk, kDenseZc, g, value, s);
+        else
+            e = launch_tv(hp, P->dim, P->reg, uK, 1.f, g, false, tvp, 1.f, value, false, s);
     } else {
         C.fixed0 = fixed;
         C.moving0 = moving;
         C.grad0 = g;
         C.value0 = value;
         e = launch_dense(C, kDenseZc, P->max_dense_blk, s, nullptr, nullptr);
+        if (e == hipSuccess && P->reg != AIR_REG_DIFFUSION)
+            e = launch_tv(hp, P->dim, P->reg, uK, P->reg_weight, g, true, tvp, P->reg_weight,
+                          value, true, s);
     }
     if (e != hipSuccess || !grad) return e;
     const float* U = reinterpret_cast<const float*>(w + P->L.fields);
@@ -426,7 +446,33 @@ static hipError_t run_diffeo(const air_plan* P, const DeviceTables* T, void* ws,
     return launch_velocity_adjoint(hp, T->consts, P->transform, P->dim, g,
                                    ldexpf(1.f, -P->diffeo),
                                    reinterpret_cast<float*>(w + P->L.bsadj1),
-                                   reinterpret_cast<float*>(w + P->L.bsadj2), grad, s);
+                                   reinterpret_cast<float*>(w + P->L.bsadj2), grad, s, false);
+}
+
+// TV term of a plan without the exponential, after the similarity pass:
+// value += lambda R(f) and grad += lambda dR/dtheta (reg_only: value = R,
+// grad = dR/dtheta). Dense: f = theta. B-spline: f = B theta on the voxel
+// grid, and dR/dtheta = B^T dR/df.
+static hipError_t run_tv(const air_plan* P, const DeviceTables* T, void* ws, const float* theta,
+                         float* value, float* grad, bool reg_only, hipStream_t s) {
+    unsigned char* w = static_cast<unsigned char*>(ws);
+    const PairDesc& hp = P->pd[0];
+    double* tvp = reinterpret_cast<double*>(w + P->L.tvpart);
+    const float lam = reg_only ? 1.f : P->reg_weight;
+    if (P->transform == AIR_TF_DENSE) {
+        // callers pass a gradient buffer for dense plans (the stencil writes it)
+        return launch_tv(hp, P->dim, P->reg, theta, lam, grad, !reg_only, tvp, lam, value,
+                         !reg_only, s);
+    }
+    float* U = reinterpret_cast<float*>(w + P->L.fields);
+    float* G = reinterpret_cast<float*>(w + P->L.gfield);
+    hipError_t e = launch_velocity(hp, T->consts, AIR_TF_BSPLINE3, P->dim, theta, 1.f, U, s);
+    if (e == hipSuccess)
+        e = launch_tv(hp, P->dim, P->reg, U, lam, G, false, tvp, lam, value, !reg_only, s);
+    if (e != hipSuccess || !grad) return e;
+    return launch_velocity_adjoint(hp, T->consts, AIR_TF_BSPLINE3, P->dim, G, 1.f,
+                                   reinterpret_cast<float*>(w + P->L.bsadj1),
+                                   reinterpret_cast<float*>(w + P->L.bsadj2), grad, s, !reg_only);
 }
 
 static air_status run_objective(const air_plan* cP, LaunchCtx& C, hipStream_t s) {
@@ -453,6 +499,12 @@ static air_status run_objective(const air_plan* cP, LaunchCtx& C, hipStream_t s)
     } else {
         e = launch_dense(C, kDenseZc, P->max_dense_blk, s, e0, e1);
     }
+    if (e == hipSuccess && P->reg != AIR_REG_DIFFUSION) {
+        DeviceTables T{};
+        T.pairs = const_cast<PairDesc*>(C.pairs);
+        T.consts = const_cast<float*>(C.consts);
+        e = run_tv(P, &T, C.ws, C.theta0, C.value0, C.grad0, false, s);
+    }
     return e == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
 }
 
@@ -475,7 +527,12 @@ air_status air_plan_create(const air_problem* probs, int32_t npairs, air_plan** 
             probs[i].similarity != probs[0].similarity)
             return AIR_ERR_UNSUPPORTED;
     }
-    if (probs[0].diffeo_steps > 0 && npairs != 1) return AIR_ERR_UNSUPPORTED;
+    for (int i = 1; i < npairs; ++i)
+        if (probs[i].diffeo_steps != probs[0].diffeo_steps ||
+            probs[i].regulariser != probs[0].regulariser)
+            return AIR_ERR_UNSUPPORTED;
+    if ((probs[0].diffeo_steps > 0 || probs[0].regulariser != AIR_REG_DIFFUSION) && npairs != 1)
+        return AIR_ERR_UNSUPPORTED;
     air_plan* P = new (std::nothrow) air_plan();
     if (!P) return AIR_ERR_DEVICE;
     P->npairs = npairs;
@@ -483,6 +540,8 @@ air_status air_plan_create(const air_problem* probs, int32_t npairs, air_plan** 
     P->transform = probs[0].transform;
     P->sim = probs[0].similarity;
     P->diffeo = probs[0].diffeo_steps;
+    P->reg = probs[0].regulariser;
+    P->reg_weight = probs[0].lambda_diff;
     P->probs.assign(probs, probs + npairs);
     P->tiling = 0;
     air_status st = build_tables(P);
@@ -627,6 +686,9 @@ air_status air_regulariser(const air_plan* plan, int32_t pair, const float* thet
     if (plan->diffeo > 0) {
         e = run_diffeo(plan, T, ws, nullptr, nullptr, theta, value, grad, true,
                        (hipStream_t)stream);
+    } else if (plan->reg != AIR_REG_DIFFUSION) {
+        if (!grad && plan->transform == AIR_TF_DENSE) return AIR_ERR_INVALID_ARG;
+        e = run_tv(plan, T, ws, theta, value, grad, true, (hipStream_t)stream);
     } else if (plan->transform == AIR_TF_BSPLINE3) {
         float* g = grad ? grad : reinterpret_cast<float*>(w + plan->L.reggrad) + hp.param_off;
         double* rp = reinterpret_cast<double*>(w + plan->L.regpart) + hp.regpart_off;
@@ -670,7 +732,7 @@ air_status air_objective_and_grad_batched(const air_plan* plan, const float* con
                                           float* values, float* const* grads, void* ws,
                                           size_t ws_bytes, void* stream) {
     if (!plan || !fixed || !moving || !theta || !values || !grads) return AIR_ERR_INVALID_ARG;
-    if (plan->diffeo > 0) return AIR_ERR_UNSUPPORTED;
+    if (plan->diffeo > 0 || plan->reg != AIR_REG_DIFFUSION) return AIR_ERR_UNSUPPORTED;
     if (((uintptr_t)fixed | (uintptr_t)moving | (uintptr_t)theta | (uintptr_t)grads) & 7u)
         return AIR_ERR_ALIGN;
     if (((uintptr_t)values & 3u) != 0) return AIR_ERR_ALIGN;

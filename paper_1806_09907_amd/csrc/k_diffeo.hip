@@ -148,10 +148,11 @@ k_bs_field(const PairDesc P, const float* __restrict__ consts, const float* __re
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_scale_copy(const float* __restrict__ in, float scale, long long n, float* __restrict__ out) {
+k_scale_copy(const float* __restrict__ in, float scale, long long n, int accumulate,
+             float* __restrict__ out) {
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
          i += (long long)gridDim.x * kBlock)
-        out[i] = scale * in[i];
+        out[i] = accumulate ? out[i] + scale * in[i] : scale * in[i];
 }
 
 // One squaring: out(x) = u(x) + u(x + u(x)).
@@ -318,7 +319,8 @@ k_compose_adj_tile(const PairDesc P, const float* __restrict__ u, const float* _
 // voxel x in cell i = x / sp with offset r carries weight table[r][j - i].
 __global__ void __launch_bounds__(kBlock)
 k_bs_adjoint_axis(const float* __restrict__ in, int d, long long A, int n, long long B, int nc,
-                  int sp, const float* __restrict__ wtab, float scale, float* __restrict__ out) {
+                  int sp, const float* __restrict__ wtab, float scale, int accumulate,
+                  float* __restrict__ out) {
     const long long total = (long long)d * A * nc * B;
     for (long long o = (long long)blockIdx.x * kBlock + threadIdx.x; o < total;
          o += (long long)gridDim.x * kBlock) {
@@ -331,7 +333,7 @@ k_bs_adjoint_axis(const float* __restrict__ in, int d, long long A, int n, long 
             const int i = x / sp;
             acc += wtab[(x - i * sp) * 4 + (jc - i)] * in[(ca * n + x) * B + b];
         }
-        out[o] = scale * acc;
+        out[o] = accumulate ? out[o] + scale * acc : scale * acc;
     }
 }
 
@@ -342,7 +344,7 @@ hipError_t launch_velocity(const PairDesc& P, const float* consts_dev, int trans
     if (transform == AIR_TF_DENSE) {
         const long long n = (long long)dim * P.nvox;
         hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n)), dim3(kBlock), 0, s, theta, scale, n,
-                           out);
+                           0, out);
     } else if (dim == 3) {
         hipLaunchKernelGGL(k_bs_field<3>, dim3(grid_for(P.nvox)), dim3(kBlock), 0, s, P,
                            consts_dev, theta, scale, out);
@@ -391,15 +393,17 @@ hipError_t launch_compose_adjoint(const PairDesc& P, int dim, const float* u, co
     return hipGetLastError();
 }
 
-// grad = scale * (dL/dv -> dL/dtheta): dense: a scaled copy; B-spline: the
-// transposed expansion, x then y (then z), through t1 [d][nz][ny][ncx] and
-// t2 [d][nz][ncy][ncx].
+// grad (+)= scale * (dL/dv -> dL/dtheta): dense: a scaled copy; B-spline:
+// the transposed expansion, x then y (then z), through t1 [d][nz][ny][ncx]
+// and t2 [d][nz][ncy][ncx].
 hipError_t launch_velocity_adjoint(const PairDesc& P, const float* consts_dev, int transform,
                                    int dim, const float* g, float scale, float* t1, float* t2,
-                                   float* grad, hipStream_t s) {
+                                   float* grad, hipStream_t s, bool accumulate) {
+    const int acc = accumulate ? 1 : 0;
     if (transform == AIR_TF_DENSE) {
         const long long n = (long long)dim * P.nvox;
-        hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n)), dim3(kBlock), 0, s, g, scale, n, grad);
+        hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n)), dim3(kBlock), 0, s, g, scale, n,
+                           acc, grad);
         return hipGetLastError();
     }
     const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
@@ -408,19 +412,19 @@ hipError_t launch_velocity_adjoint(const PairDesc& P, const float* consts_dev, i
     long long tot = (long long)dim * nz * ny * cx;
     hipLaunchKernelGGL(k_bs_adjoint_axis, dim3(grid_for(tot)), dim3(kBlock), 0, s, g, dim,
                        (long long)nz * ny, nx, 1LL, cx, P.sp[0], consts_dev + P.wtab_off[0], 1.f,
-                       t1);
+                       0, t1);
     // y: [d][nz][ny][cx] -> [d][nz][cy][cx]
     tot = (long long)dim * nz * cy * cx;
     float* ydst = dim == 3 ? t2 : grad;
     hipLaunchKernelGGL(k_bs_adjoint_axis, dim3(grid_for(tot)), dim3(kBlock), 0, s, t1, dim,
                        (long long)nz, ny, (long long)cx, cy, P.sp[1], consts_dev + P.wtab_off[1],
-                       dim == 3 ? 1.f : scale, ydst);
+                       dim == 3 ? 1.f : scale, dim == 3 ? 0 : acc, ydst);
     if (dim == 3) {
         // z: [d][1][nz][cy*cx] -> [d][1][cz][cy*cx]
         tot = (long long)dim * cz * cy * cx;
         hipLaunchKernelGGL(k_bs_adjoint_axis, dim3(grid_for(tot)), dim3(kBlock), 0, s, t2, dim,
                            1LL, nz, (long long)cy * cx, cz, P.sp[2], consts_dev + P.wtab_off[2],
-                           scale, grad);
+                           scale, acc, grad);
     }
     return hipGetLastError();
 }

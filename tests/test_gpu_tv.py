@@ -1,0 +1,116 @@
+"""GPU parity of the total-variation regularisers (Sec. III-F) against the
+FP64 oracle: the regulariser alone and inside the objective, dense and
+B-spline fields, with and without the exponential (Sec. III-D)."""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1806_09907_amd import api, synth
+from paper_1806_09907_amd._lib import AirError
+
+pytestmark = pytest.mark.gpu
+
+VAL_TOL = 1e-5
+GRAD_TOL = 1e-4
+DEV = "cuda"
+
+
+def oprob(p):
+    return O.Problem(n=p.n, transform=p.transform, spacing=p.spacing, similarity=p.similarity,
+                     lambda_diff=p.lambda_diff, diffeo_steps=p.diffeo_steps,
+                     regulariser=p.regulariser)
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-30)
+
+
+@functools.lru_cache(maxsize=None)
+def inputs(n, seed):
+    d = len(n)
+    pair = synth.blob_pair(n, seed, O.warp_fn_fp32, nblobs=12 if d == 2 else 40,
+                           disp_std_vox=1.5, noise_std=0.01, spacing=8)
+    return pair.fixed, pair.moving
+
+
+def theta_for(p, seed):
+    if p.transform == api.TF_DENSE:
+        return synth.smooth_dense(p.n, 1.5, seed, sigma=3.0)
+    return synth.random_theta(p.n, p.spacing, 1.5, seed)
+
+
+KINDS = [api.REG_ANISO_TV, api.REG_ISO_TV]
+CASES = [
+    # n, transform, spacing, similarity, lambda, K
+    ((48, 40), api.TF_DENSE, (1, 1), api.SIM_MSE, 0.05, 0),
+    ((48, 40), api.TF_BSPLINE3, (8, 8), api.SIM_NCC, 0.02, 0),
+    ((33, 30, 28), api.TF_DENSE, (1, 1, 1), api.SIM_MSE, 0.05, 0),
+    ((40, 36, 44), api.TF_BSPLINE3, (8, 8, 8), api.SIM_NCC, 0.02, 0),
+    ((37, 29, 23), api.TF_BSPLINE3, (5, 3, 7), api.SIM_MSE, 0.05, 0),
+    ((33, 30, 28), api.TF_DENSE, (1, 1, 1), api.SIM_NCC, 0.05, 4),
+    ((40, 36, 44), api.TF_BSPLINE3, (8, 8, 8), api.SIM_MSE, 0.02, 3),
+]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("n,tf,sp,sim,lam,K", CASES)
+def test_objective_parity_tv(kind, n, tf, sp, sim, lam, K):
+    print(f"case tv objective kind={kind} n={n} tf={tf} K={K}", flush=True)
+    p = api.Problem(n=n, transform=tf, spacing=sp, similarity=sim, lambda_diff=lam,
+                    diffeo_steps=K, regulariser=kind)
+    F, M = inputs(n, 7)
+    th = theta_for(p, 2)
+    plan = api.Plan(p)
+    v, g = api.objective_and_grad(plan, gpu(F), gpu(M), gpu(th))
+    torch.cuda.synchronize()
+    vo, go, flags = O.objective_and_grad(oprob(p), F, M, th)
+    assert flags == 0
+    assert abs(float(v) - vo) <= VAL_TOL * abs(vo)
+    assert rel(g.double().cpu().numpy(), go) <= GRAD_TOL
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("tf,K", [(api.TF_DENSE, 0), (api.TF_BSPLINE3, 0), (api.TF_DENSE, 3)])
+def test_regulariser_parity_tv(kind, tf, K):
+    n = (30, 26, 22)
+    sp = (1, 1, 1) if tf == api.TF_DENSE else (4, 4, 4)
+    p = api.Problem(n=n, transform=tf, spacing=sp, similarity=api.SIM_MSE, lambda_diff=1.0,
+                    diffeo_steps=K, regulariser=kind)
+    th = theta_for(p, 3)
+    R, g = api.regulariser(api.Plan(p), gpu(th))
+    Ro, go = O.regulariser(oprob(p), th)
+    assert abs(float(R) - Ro) <= VAL_TOL * abs(Ro)
+    assert rel(g.double().cpu().numpy(), go) <= GRAD_TOL
+
+
+def test_tv_128_bspline_ncc():
+    """The 128^3 B-spline NCC workload with anisotropic TV (the paper's FFD
+    recipe: B-spline, NCC, anisotropic TV)."""
+    n = (128, 128, 128)
+    p = api.Problem(n=n, spacing=(8, 8, 8), similarity=api.SIM_NCC, lambda_diff=0.02,
+                    regulariser=api.REG_ANISO_TV)
+    pair = synth.pair_3d(warp=O.warp_fn_fp32)
+    th = synth.random_theta(n, (8, 8, 8), 1.0, 5000)
+    plan = api.Plan(p)
+    v, g = api.objective_and_grad(plan, gpu(pair.fixed), gpu(pair.moving), gpu(th))
+    torch.cuda.synchronize()
+    vo, go, _ = O.objective_and_grad(oprob(p), pair.fixed, pair.moving, th)
+    assert abs(float(v) - vo) <= VAL_TOL * abs(vo)
+    assert rel(g.double().cpu().numpy(), go) <= GRAD_TOL
+
+
+def test_tv_rejections():
+    p = api.Problem(n=(20, 18, 16), transform=api.TF_DENSE, spacing=(1, 1, 1),
+                    similarity=api.SIM_MSE, regulariser=api.REG_ISO_TV)
+    with pytest.raises(AirError):
+        api.Plan([p, p])
+    plan = api.Plan(p)
+    with pytest.raises(AirError):
+        api.regulariser(plan, gpu(np.zeros(p.param_shape())), want_grad=False)
