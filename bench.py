@@ -7,7 +7,8 @@ Cache). Other workloads (--workload): `uneven48` (48 pairs with sides from
 {96..160} in one launch), `dense256` (256^3 dense field, MSE + 1.0 diffusion),
 `latency2d` (one 64^2 B-spline MSE pair per step), `diffeo256` / `diffeo2d`
 (the dense 256^3 / 4096^2 evaluation with f = exp(v), beside the same
-evaluation without the exponential).
+evaluation without the exponential), `tv128` (one 128^3 B-spline NCC pair
+with anisotropic TV, beside the same pair with diffusion).
 
 Prints one JSON line. `roofline` reports the dominant kernel from HIP events
 the library records around it on its own stream; `traffic` comes from
@@ -71,7 +72,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batch128",
                     choices=["batch128", "uneven48", "dense256", "latency2d", "diffeo256",
-                             "diffeo2d"])
+                             "diffeo2d", "tv128"])
     ap.add_argument("--pairs", type=int, default=64)
     ap.add_argument("--tiling", type=int, default=-1, help="-1: autotune cache or default")
     ap.add_argument("--autotune-out", default="",
@@ -141,6 +142,13 @@ def cpu_baseline(seconds, workload):
                       lambda_diff=1.0)
         th = synth.smooth_dense(n3, 2.0, 77)
         desc = "one 256^3 dense MSE pair"
+    elif workload == "tv128":
+        n3 = (128, 128, 128)
+        pair = synth.pair_3d(warp=O.warp_fn_fp32)
+        p = O.Problem(n=n3, spacing=SPACING, similarity=O.SIM_NCC, lambda_diff=0.02,
+                      regulariser=O.REG_ANISO_TV)
+        th = synth.random_theta(n3, SPACING, 1.0, 5000)
+        desc = "one 128^3 B-spline NCC + anisotropic TV pair"
     elif workload == "latency2d":
         n3 = (64, 64)
         pair = synth.pair_2d(warp=O.warp_fn_fp32)
@@ -437,6 +445,49 @@ def run_diffeo(args, dev, three_d: bool):
     }
 
 
+def run_tv128(args, dev):
+    """One 128^3 pair, cubic B-spline (spacing 8), NCC + 0.02 anisotropic TV
+    (the paper's FFD recipe), beside the same pair with 0.05 diffusion."""
+    import torch
+
+    from paper_1806_09907_amd import api
+
+    n = (128, 128, 128)
+    Fs, Ms, Ts = blob_batch([n], dev)
+    value = torch.empty((), dtype=torch.float32, device=dev)
+    grad = torch.empty_like(Ts[0])
+    tv = api.Plan(api.Problem(n=n, spacing=SPACING, similarity=api.SIM_NCC, lambda_diff=0.02,
+                              regulariser=api.REG_ANISO_TV))
+    df = api.Plan(api.Problem(n=n, spacing=SPACING, similarity=api.SIM_NCC, lambda_diff=0.05))
+    tv.prepare()
+    df.prepare()
+    progress("timing")
+    ms_df, _ = timed(df, args.steps, args.warmup,
+                     lambda: api.objective_and_grad(df, Fs[0], Ms[0], Ts[0], value, grad))
+    ms_tv, fused_ms = timed(tv, args.steps, args.warmup,
+                            lambda: api.objective_and_grad(tv, Fs[0], Ms[0], Ts[0], value, grad))
+    N = 128 ** 3
+    nctrl = 19 ** 3
+    # fused pass (F, M, theta), expansion (write u), TV pass (read u, write
+    # dR/du), transposed expansion (read dR/du), gradient read-modify-write
+    bytes_eval = 4 * (2 * N + 3 * nctrl) + 4 * 3 * N * 4 + 4 * 2 * 3 * nctrl
+    achieved = bytes_eval / (ms_tv / 1e3) / 1e9
+    return {
+        "metric": "objective+grad evals/s, 128^3 B-spline NCC + anisotropic TV, one pair",
+        "value": 1e3 / ms_tv, "unit": "evals/s", "ms_per_step": ms_tv,
+        "config": {"workload": "one 128^3 blob pair, cubic B-spline spacing 8, NCC + 0.02 "
+                               "anisotropic TV (the FFD recipe of the paper's experiments)",
+                   "n": list(n), "diffusion_ms_per_eval": ms_df,
+                   "tv_over_diffusion": ms_tv / ms_df, "algorithmic_bytes_per_step": bytes_eval},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "whole evaluation (fused pass, expansion, TV pass, transposed "
+                               "expansion); one pair, so partly served from the Infinity Cache",
+                     "kernel_ms": ms_tv, "fused_kernel_ms": fused_ms,
+                     "algorithmic_bytes_per_launch": bytes_eval},
+    }
+
+
 def run_latency2d(args, dev):
     import torch
 
@@ -564,6 +615,8 @@ def main():
         out = run_dense(args, dev)
     elif args.workload in ("diffeo256", "diffeo2d"):
         out = run_diffeo(args, dev, args.workload == "diffeo256")
+    elif args.workload == "tv128":
+        out = run_tv128(args, dev)
     else:
         out = run_latency2d(args, dev)
     line = {"metric": out["metric"], "value": out["value"], "unit": out["unit"], "n_gpus": 1,
