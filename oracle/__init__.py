@@ -7,6 +7,7 @@ GPU library. Every array is handed to the C code as float64, C-contiguous.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -19,7 +20,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 SIM_MSE, SIM_NCC = 0, 1
-TF_BSPLINE3, TF_DENSE = 0, 1
+TF_BSPLINE3, TF_DENSE, TF_WENDLAND = 0, 1, 2
 FLAG_NONFINITE, FLAG_DEGENERATE = 1, 2
 REG_DIFFUSION, REG_ANISO_TV, REG_ISO_TV = 0, 1, 2
 
@@ -40,7 +41,8 @@ class _Problem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3),
                 ("transform", ctypes.c_int), ("spacing", ctypes.c_int * 3),
                 ("similarity", ctypes.c_int), ("lambda_diff", ctypes.c_double),
-                ("diffeo_steps", ctypes.c_int), ("regulariser", ctypes.c_int)]
+                ("diffeo_steps", ctypes.c_int), ("regulariser", ctypes.c_int),
+                ("sigma", ctypes.c_double * 3)]
 
 
 _lib = None
@@ -63,6 +65,9 @@ def lib():
             "airo_bspline_kernel": (ctypes.c_double, [ctypes.c_double]),
             "airo_bspline_expand": (None, [P, dp, dp]),
             "airo_bspline_adjoint": (None, [P, dp, dp]),
+            "airo_wendland_kernel": (ctypes.c_double, [ctypes.c_double]),
+            "airo_wendland_expand": (None, [P, dp, dp]),
+            "airo_wendland_adjoint": (None, [P, dp, dp]),
             "airo_displacement": (None, [P, dp, dp]),
             "airo_velocity": (None, [P, dp, dp]),
             "airo_compose": (None, [P, dp, dp]),
@@ -108,6 +113,7 @@ class Problem:
     lambda_diff: float = 0.0
     diffeo_steps: int = 0      # > 0: f = exp(field) with this many squarings
     regulariser: int = 0       # REG_DIFFUSION, REG_ANISO_TV or REG_ISO_TV
+    sigma: tuple = ()          # Wendland support radius per axis (voxels)
 
     @property
     def dim(self) -> int:
@@ -119,6 +125,13 @@ class Problem:
         return tuple(reversed(self.n))
 
     def ncontrol(self) -> tuple:
+        if self.transform == TF_WENDLAND:
+            out = []
+            for a in range(self.dim):
+                s, dl = float(self.sigma[a]), self.spacing[a]
+                m = math.ceil(s / dl) - 1
+                out.append(m + math.ceil((self.n[a] - 1 + s) / dl))
+            return tuple(out)
         return tuple((self.n[a] - 1) // self.spacing[a] + 4 for a in range(self.dim))
 
     def param_shape(self) -> tuple:
@@ -130,10 +143,11 @@ class Problem:
         d = self.dim
         n = list(self.n) + [1] * (3 - d)
         sp = list(self.spacing[:d]) + [1] * (3 - d)
+        sg = [float(x) for x in self.sigma[:d]] + [1.0] * (3 - len(self.sigma[:d]))
         return _Problem(d, (ctypes.c_int * 3)(*n), int(self.transform),
                         (ctypes.c_int * 3)(*sp), int(self.similarity),
                         float(self.lambda_diff), int(self.diffeo_steps),
-                        int(self.regulariser))
+                        int(self.regulariser), (ctypes.c_double * 3)(*sg))
 
 
 def _f64(a) -> np.ndarray:
@@ -191,21 +205,29 @@ def bspline_kernel(r: float) -> float:
     return float(lib().airo_bspline_kernel(float(r)))
 
 
+def wendland_kernel(r: float) -> float:
+    return float(lib().airo_wendland_kernel(float(r)))
+
+
 def expand(prob: Problem, theta) -> np.ndarray:
+    """u = B theta for the problem's interpolating basis."""
     pc = _check(prob)
     th = _f64(theta)
     assert th.shape == prob.param_shape(), (th.shape, prob.param_shape())
     u = np.empty((prob.dim,) + prob.shape, dtype=np.float64)
-    lib().airo_bspline_expand(ctypes.byref(pc), _ptr(th), _ptr(u))
+    f = lib().airo_wendland_expand if prob.transform == TF_WENDLAND else lib().airo_bspline_expand
+    f(ctypes.byref(pc), _ptr(th), _ptr(u))
     return u
 
 
 def adjoint(prob: Problem, g) -> np.ndarray:
+    """B^T g for the problem's interpolating basis."""
     pc = _check(prob)
     g = _f64(g)
     assert g.shape == (prob.dim,) + prob.shape
     out = np.empty((prob.dim,) + tuple(reversed(prob.ncontrol())), dtype=np.float64)
-    lib().airo_bspline_adjoint(ctypes.byref(pc), _ptr(g), _ptr(out))
+    f = lib().airo_wendland_adjoint if prob.transform == TF_WENDLAND else lib().airo_bspline_adjoint
+    f(ctypes.byref(pc), _ptr(g), _ptr(out))
     return out
 
 

@@ -51,18 +51,32 @@ int airo_check(const airo_problem* p) {
     if (p->dim != 2 && p->dim != 3) return 1;
     for (int a = 0; a < p->dim; ++a) {
         if (p->n[a] < 2) return 1;
-        if (p->transform == AIRO_TF_BSPLINE3 && p->spacing[a] < 1) return 1;
+        if (p->transform != AIRO_TF_DENSE && p->spacing[a] < 1) return 1;
+        if (p->transform == AIRO_TF_WENDLAND && !(p->sigma[a] > 0.0 && p->sigma[a] < 1e6))
+            return 1;
     }
     if (p->dim == 2 && p->n[2] != 1) return 1;
-    if (p->transform != AIRO_TF_BSPLINE3 && p->transform != AIRO_TF_DENSE) return 1;
+    if (p->transform != AIRO_TF_BSPLINE3 && p->transform != AIRO_TF_DENSE &&
+        p->transform != AIRO_TF_WENDLAND)
+        return 1;
     if (p->similarity != AIRO_SIM_MSE && p->similarity != AIRO_SIM_NCC) return 1;
     if (p->diffeo_steps < 0 || p->diffeo_steps > 30) return 1;
     if (p->regulariser < AIRO_REG_DIFFUSION || p->regulariser > AIRO_REG_ISO_TV) return 1;
     return 0;
 }
 
+/* Wendland controls along an axis: the first sits m spacings before voxel 0,
+ * m = ceil(sigma/delta) - 1, the last control lies less than sigma beyond
+ * voxel n-1; every control within sigma (open) of a voxel is present. */
+static int wendland_first(const airo_problem* p, int axis) {
+    return (int)ceil(p->sigma[axis] / p->spacing[axis]) - 1;
+}
+
 int airo_ncontrol(const airo_problem* p, int axis) {
     if (axis >= p->dim) return 1;
+    if (p->transform == AIRO_TF_WENDLAND)
+        return wendland_first(p, axis) +
+               (int)ceil((p->n[axis] - 1 + p->sigma[axis]) / p->spacing[axis]);
     return (p->n[axis] - 1) / p->spacing[axis] + 4;
 }
 
@@ -194,9 +208,134 @@ void airo_bspline_adjoint(const airo_problem* p, const double* g, double* out) {
     }
 }
 
+/* ---- Sec. III-C: the Wendland kernel psi_{3,2} -------------------- */
+
+double airo_wendland_kernel(double r) {
+    if (r >= 1.0) return 0.0;
+    const double t = 1.0 - r;
+    return t * t * t * t * t * t * (3.0 + 18.0 * r + 35.0 * r * r) / 3.0;
+}
+
+/* Position (voxels) of Wendland control j along axis a. */
+static double wendland_pos(const airo_problem* p, int a, int j) {
+    return (double)(j - wendland_first(p, a)) * p->spacing[a];
+}
+
+/* The controls along axis a within sigma (open) of coordinate x: [*lo, *hi]
+ * (empty when *lo > *hi), found by testing every control. */
+static void wendland_range(const airo_problem* p, int a, double x, int* lo, int* hi) {
+    const int nc = airo_ncontrol(p, a);
+    *lo = nc;
+    *hi = -1;
+    for (int j = 0; j < nc; ++j)
+        if (fabs(x - wendland_pos(p, a, j)) < p->sigma[a]) {
+            if (j < *lo) *lo = j;
+            *hi = j;
+        }
+}
+
+/* psi(||(x - c) / sigma||) for a voxel x and a control at c (both [3]). */
+static double wendland_weight(const airo_problem* p, const double* x, const double* c) {
+    double r2 = 0.0;
+    for (int a = 0; a < p->dim; ++a) {
+        const double q = (x[a] - c[a]) / p->sigma[a];
+        r2 += q * q;
+    }
+    return airo_wendland_kernel(sqrt(r2));
+}
+
+void airo_wendland_expand(const airo_problem* p, const double* theta, double* u) {
+    const int d = p->dim;
+    const int nx = p->n[0], ny = p->n[1], nz = (d == 3) ? p->n[2] : 1;
+    const int ncx = airo_ncontrol(p, 0), ncy = airo_ncontrol(p, 1);
+    const long N = (long)nx * ny * nz;
+    const long NC = ncontrols_total(p);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) NTHREADS
+#endif
+    for (int z = 0; z < nz; ++z) {
+        int z0 = 0, z1 = 0;
+        if (d == 3) wendland_range(p, 2, z, &z0, &z1);
+        for (int y = 0; y < ny; ++y) {
+            int y0, y1;
+            wendland_range(p, 1, y, &y0, &y1);
+            for (int x = 0; x < nx; ++x) {
+                int x0, x1;
+                wendland_range(p, 0, x, &x0, &x1);
+                const double pt[3] = {x, y, z};
+                double acc[3] = {0.0, 0.0, 0.0};
+                for (int jz = z0; jz <= z1; ++jz)
+                    for (int jy = y0; jy <= y1; ++jy)
+                        for (int jx = x0; jx <= x1; ++jx) {
+                            const double c[3] = {wendland_pos(p, 0, jx), wendland_pos(p, 1, jy),
+                                                 d == 3 ? wendland_pos(p, 2, jz) : 0.0};
+                            const double w = wendland_weight(p, pt, c);
+                            const long j = ((long)jz * ncy + jy) * ncx + jx;
+                            for (int k = 0; k < d; ++k) acc[k] += w * theta[k * NC + j];
+                        }
+                const long v = ((long)z * ny + y) * nx + x;
+                for (int k = 0; k < d; ++k) u[k * N + v] = acc[k];
+            }
+        }
+    }
+}
+
+/* The voxels along axis a within sigma (open) of a control at c. */
+static void voxel_range(const airo_problem* p, int a, double c, int* lo, int* hi) {
+    const int n = p->n[a];
+    *lo = n;
+    *hi = -1;
+    for (int x = 0; x < n; ++x)
+        if (fabs((double)x - c) < p->sigma[a]) {
+            if (x < *lo) *lo = x;
+            *hi = x;
+        }
+}
+
+void airo_wendland_adjoint(const airo_problem* p, const double* g, double* out) {
+    const int d = p->dim;
+    const int nx = p->n[0], ny = p->n[1], nz = (d == 3) ? p->n[2] : 1;
+    const int ncx = airo_ncontrol(p, 0), ncy = airo_ncontrol(p, 1);
+    const int ncz = (d == 3) ? airo_ncontrol(p, 2) : 1;
+    const long N = (long)nx * ny * nz;
+    const long NC = ncontrols_total(p);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic) NTHREADS
+#endif
+    for (int jz = 0; jz < ncz; ++jz) {
+        const double cz = (d == 3) ? wendland_pos(p, 2, jz) : 0.0;
+        int z0 = 0, z1 = 0;
+        if (d == 3) voxel_range(p, 2, cz, &z0, &z1);
+        for (int jy = 0; jy < ncy; ++jy) {
+            const double cy = wendland_pos(p, 1, jy);
+            int y0, y1;
+            voxel_range(p, 1, cy, &y0, &y1);
+            for (int jx = 0; jx < ncx; ++jx) {
+                const double cx = wendland_pos(p, 0, jx);
+                int x0, x1;
+                voxel_range(p, 0, cx, &x0, &x1);
+                const double c[3] = {cx, cy, cz};
+                double acc[3] = {0.0, 0.0, 0.0};
+                for (int z = z0; z <= z1; ++z)
+                    for (int y = y0; y <= y1; ++y)
+                        for (int x = x0; x <= x1; ++x) {
+                            const double pt[3] = {x, y, z};
+                            const double w = wendland_weight(p, pt, c);
+                            const long v = ((long)z * ny + y) * nx + x;
+                            for (int k = 0; k < d; ++k) acc[k] += w * g[k * N + v];
+                        }
+                const long j = ((long)jz * ncy + jy) * ncx + jx;
+                for (int k = 0; k < d; ++k) out[k * NC + j] = acc[k];
+            }
+        }
+    }
+}
+
 void airo_velocity(const airo_problem* p, const double* theta, double* v) {
     if (p->transform == AIRO_TF_DENSE)
         memcpy(v, theta, sizeof(double) * (size_t)p->dim * (size_t)airo_nvox(p));
+    else if (p->transform == AIRO_TF_WENDLAND)
+        airo_wendland_expand(p, theta, v);
     else
         airo_bspline_expand(p, theta, v);
 }
@@ -413,6 +552,8 @@ static void displacement_adjoint(const airo_problem* p, const double* theta, con
     }
     if (p->transform == AIRO_TF_DENSE)
         memcpy(grad, gv, fb);
+    else if (p->transform == AIRO_TF_WENDLAND)
+        airo_wendland_adjoint(p, gv, grad);
     else
         airo_bspline_adjoint(p, gv, grad);
     free(gv);

@@ -22,12 +22,17 @@
  *   optimiser            Sec. III-G (Adam, Kingma & Ba)
  *   diffeomorphic        Sec. III-D (f = exp(v), scaling and squaring; the
  *                        number of squarings is a problem parameter)
+ *   total variation      Sec. III-F (anisotropic and isotropic)
+ *   Wendland basis       Sec. III-C, kernel psi_{3,2} with per-axis sigma
  *
  * Conventions (shared readings of the paper, identical on both sides):
  *   images     [nz][ny][nx], x fastest (2D: [ny][nx], n[2] == 1)
  *   fields     [d][nz][ny][nx], components ordered (x, y, z)
- *   controls   [d][ncz][ncy][ncx]; control j sits at voxel (j-1)*delta;
- *              nc = floor((n-1)/delta) + 4
+ *   controls   [d][ncz][ncy][ncx]; B-spline: control j sits at voxel
+ *              (j-1)*delta, nc = floor((n-1)/delta) + 4. Wendland: control j
+ *              sits at (j-m)*delta with m = ceil(sigma/delta) - 1 and
+ *              nc = m + ceil((n-1+sigma)/delta): exactly the controls within
+ *              sigma (open) of some voxel on that axis
  *   units      displacements and controls in normalised units; the sample
  *              point of voxel i is p_a = i_a + u_a * (n_a - 1) / 2 (voxels)
  *   mask       0 <= p_a <= n_a - 1 on every axis (inclusive), decided on p
@@ -51,6 +56,7 @@ extern "C" {
 #define AIRO_SIM_NCC 1
 #define AIRO_TF_BSPLINE3 0
 #define AIRO_TF_DENSE 1
+#define AIRO_TF_WENDLAND 2
 
 #define AIRO_FLAG_NONFINITE 1
 #define AIRO_FLAG_DEGENERATE 2
@@ -65,6 +71,7 @@ typedef struct {
     int diffeo_steps; /* 0: f = the field itself; K > 0: f = exp(field) by
                          scaling and squaring with K squarings (Sec. III-D) */
     int regulariser;  /* AIRO_REG_*: the term lambda_diff weights (Sec. III-F) */
+    double sigma[3];  /* Wendland support radius (voxels) along x, y, z */
 } airo_problem;
 
 #define AIRO_REG_DIFFUSION 0
@@ -83,7 +90,16 @@ double airo_bspline_kernel(double r);
 void airo_bspline_expand(const airo_problem* p, const double* theta, double* u);
 /* out = B^T g  (the adjoint of the expansion). */
 void airo_bspline_adjoint(const airo_problem* p, const double* g, double* out);
-/* The field before the exponential: B theta (B-spline) or theta (dense). */
+/* psi_{3,2}(r) of Sec. III-C: (1-r)^6_+ (3 + 18 r + 35 r^2) / 3. */
+double airo_wendland_kernel(double r);
+/* u = B theta with the Wendland basis (Sec. II-A eq. kernel_basis):
+ *   u_c(x) = sum_j theta_c,j psi(||(x - c_j) / sigma||),
+ * the division per axis (anisotropic support). */
+void airo_wendland_expand(const airo_problem* p, const double* theta, double* u);
+/* out = B^T g for the Wendland basis. */
+void airo_wendland_adjoint(const airo_problem* p, const double* g, double* out);
+/* The field before the exponential: B theta (interpolating bases) or theta
+ * (dense). */
 void airo_velocity(const airo_problem* p, const double* theta, double* v);
 /* The displacement f_theta: the velocity itself, or its exponential when
  * diffeo_steps > 0. */
