@@ -19,7 +19,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-SIM_MSE, SIM_NCC = 0, 1
+SIM_MSE, SIM_NCC, SIM_LCC = 0, 1, 2
+LCC_EPS = 1e-10
 TF_BSPLINE3, TF_DENSE, TF_WENDLAND = 0, 1, 2
 FLAG_NONFINITE, FLAG_DEGENERATE = 1, 2
 REG_DIFFUSION, REG_ANISO_TV, REG_ISO_TV = 0, 1, 2
@@ -42,7 +43,7 @@ class _Problem(ctypes.Structure):
                 ("transform", ctypes.c_int), ("spacing", ctypes.c_int * 3),
                 ("similarity", ctypes.c_int), ("lambda_diff", ctypes.c_double),
                 ("diffeo_steps", ctypes.c_int), ("regulariser", ctypes.c_int),
-                ("sigma", ctypes.c_double * 3)]
+                ("sigma", ctypes.c_double * 3), ("lcc_radius", ctypes.c_int)]
 
 
 _lib = None
@@ -114,6 +115,7 @@ class Problem:
     diffeo_steps: int = 0      # > 0: f = exp(field) with this many squarings
     regulariser: int = 0       # REG_DIFFUSION, REG_ANISO_TV or REG_ISO_TV
     sigma: tuple = ()          # Wendland support radius per axis (voxels)
+    lcc_radius: int = 2        # LCC window |y - x|_inf <= lcc_radius
 
     @property
     def dim(self) -> int:
@@ -147,7 +149,8 @@ class Problem:
         return _Problem(d, (ctypes.c_int * 3)(*n), int(self.transform),
                         (ctypes.c_int * 3)(*sp), int(self.similarity),
                         float(self.lambda_diff), int(self.diffeo_steps),
-                        int(self.regulariser), (ctypes.c_double * 3)(*sg))
+                        int(self.regulariser), (ctypes.c_double * 3)(*sg),
+                        int(self.lcc_radius))
 
 
 def _f64(a) -> np.ndarray:

@@ -59,7 +59,10 @@ int airo_check(const airo_problem* p) {
     if (p->transform != AIRO_TF_BSPLINE3 && p->transform != AIRO_TF_DENSE &&
         p->transform != AIRO_TF_WENDLAND)
         return 1;
-    if (p->similarity != AIRO_SIM_MSE && p->similarity != AIRO_SIM_NCC) return 1;
+    if (p->similarity != AIRO_SIM_MSE && p->similarity != AIRO_SIM_NCC &&
+        p->similarity != AIRO_SIM_LCC)
+        return 1;
+    if (p->similarity == AIRO_SIM_LCC && (p->lcc_radius < 1 || p->lcc_radius > 64)) return 1;
     if (p->diffeo_steps < 0 || p->diffeo_steps > 30) return 1;
     if (p->regulariser < AIRO_REG_DIFFUSION || p->regulariser > AIRO_REG_ISO_TV) return 1;
     return 0;
@@ -565,8 +568,115 @@ static long slab_size(const airo_problem* p) {
     return p->dim == 3 ? (long)p->n[0] * p->n[1] : (long)p->n[0];
 }
 
+/* Sec. III-B, LCC: local statistics over each window, centred about the
+ * window's own means (two passes per window); the gradient with respect to
+ * W(y) gathers, over the windows that contain y,
+ *   d rho(x)/dW(y) = (F(y) - muF(x)) / (n s) - rho varF (W(y) - muW(x)) / (n V)
+ * with V = varF varW + eps and s = sqrt(V). */
+static int lcc(const airo_problem* p, const double* F, const double* W,
+               const unsigned char* mask, double* value, double* dsdw) {
+    const int d = p->dim;
+    const int nx = p->n[0], ny = p->n[1], nz = (d == 3) ? p->n[2] : 1;
+    const long N = airo_nvox(p);
+    const int r = p->lcc_radius;
+    const int rz = (d == 3) ? r : 0;
+    double* st = (double*)malloc(sizeof(double) * 6 * (size_t)N);  /* muF muW n rho varF V */
+    double* part = (double*)calloc((size_t)nz, 2 * sizeof(double));
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic) NTHREADS
+#endif
+    for (int z = 0; z < nz; ++z) {
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const long v = ((long)z * ny + y) * nx + x;
+                double* o = st + 6 * v;
+                o[2] = 0.0;
+                if (!mask[v]) continue;
+                const int z0 = z - rz < 0 ? 0 : z - rz, z1 = z + rz > nz - 1 ? nz - 1 : z + rz;
+                const int y0 = y - r < 0 ? 0 : y - r, y1 = y + r > ny - 1 ? ny - 1 : y + r;
+                const int x0 = x - r < 0 ? 0 : x - r, x1 = x + r > nx - 1 ? nx - 1 : x + r;
+                double n = 0.0, sf = 0.0, sw = 0.0;
+                for (int c = z0; c <= z1; ++c)
+                    for (int b = y0; b <= y1; ++b)
+                        for (int a = x0; a <= x1; ++a) {
+                            const long q = ((long)c * ny + b) * nx + a;
+                            if (!mask[q]) continue;
+                            n += 1.0;
+                            sf += F[q];
+                            sw += W[q];
+                        }
+                const double mf = sf / n, mw = sw / n;
+                double vf = 0.0, vw = 0.0, cv = 0.0;
+                for (int c = z0; c <= z1; ++c)
+                    for (int b = y0; b <= y1; ++b)
+                        for (int a = x0; a <= x1; ++a) {
+                            const long q = ((long)c * ny + b) * nx + a;
+                            if (!mask[q]) continue;
+                            vf += (F[q] - mf) * (F[q] - mf);
+                            vw += (W[q] - mw) * (W[q] - mw);
+                            cv += (F[q] - mf) * (W[q] - mw);
+                        }
+                vf /= n;
+                vw /= n;
+                cv /= n;
+                const double V = vf * vw + AIRO_LCC_EPS;
+                o[0] = mf;
+                o[1] = mw;
+                o[2] = n;
+                o[3] = cv / sqrt(V);
+                o[4] = vf;
+                o[5] = V;
+                part[2 * z] += 1.0;
+                part[2 * z + 1] += o[3];
+            }
+    }
+    double cnt = 0.0, srho = 0.0;
+    for (int z = 0; z < nz; ++z) {
+        cnt += part[2 * z];
+        srho += part[2 * z + 1];
+    }
+    free(part);
+    if (cnt < 1.0) {
+        *value = 0.0;
+        if (dsdw) memset(dsdw, 0, sizeof(double) * (size_t)N);
+        free(st);
+        return AIRO_FLAG_DEGENERATE;
+    }
+    *value = -srho / cnt;
+    if (dsdw) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic) NTHREADS
+#endif
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    const long v = ((long)z * ny + y) * nx + x;
+                    dsdw[v] = 0.0;
+                    if (!mask[v]) continue;
+                    const int z0 = z - rz < 0 ? 0 : z - rz, z1 = z + rz > nz - 1 ? nz - 1 : z + rz;
+                    const int y0 = y - r < 0 ? 0 : y - r, y1 = y + r > ny - 1 ? ny - 1 : y + r;
+                    const int x0 = x - r < 0 ? 0 : x - r, x1 = x + r > nx - 1 ? nx - 1 : x + r;
+                    double acc = 0.0;
+                    for (int c = z0; c <= z1; ++c)
+                        for (int b = y0; b <= y1; ++b)
+                            for (int a = x0; a <= x1; ++a) {
+                                const long q = ((long)c * ny + b) * nx + a;
+                                const double* o = st + 6 * q;
+                                if (!mask[q]) continue;
+                                const double n = o[2], s = sqrt(o[5]);
+                                acc += (F[v] - o[0]) / (n * s) -
+                                       o[3] * o[4] * (W[v] - o[1]) / (n * o[5]);
+                            }
+                    dsdw[v] = -acc / cnt;
+                }
+    }
+    free(st);
+    return isfinite(*value) ? 0 : AIRO_FLAG_NONFINITE;
+}
+
 int airo_similarity(const airo_problem* p, const double* fixed, const double* warped,
                     const unsigned char* mask, double* value, double* dsdw) {
+    if (p->similarity == AIRO_SIM_LCC) return lcc(p, fixed, warped, mask, value, dsdw);
     const long N = airo_nvox(p);
     const int ns = slab_count(p);
     const long ss = slab_size(p);

@@ -24,6 +24,8 @@
  *                        number of squarings is a problem parameter)
  *   total variation      Sec. III-F (anisotropic and isotropic)
  *   Wendland basis       Sec. III-C, kernel psi_{3,2} with per-axis sigma
+ *   LCC                  Sec. III-B (local NCC: mean, variance and
+ *                        covariance over a cube window around each voxel)
  *
  * Conventions (shared readings of the paper, identical on both sides):
  *   images     [nz][ny][nx], x fastest (2D: [ny][nx], n[2] == 1)
@@ -54,6 +56,9 @@ extern "C" {
 
 #define AIRO_SIM_MSE 0
 #define AIRO_SIM_NCC 1
+#define AIRO_SIM_LCC 2
+/* epsilon of the LCC denominator sqrt(varF varW + eps) (image units^4) */
+#define AIRO_LCC_EPS 1e-10
 #define AIRO_TF_BSPLINE3 0
 #define AIRO_TF_DENSE 1
 #define AIRO_TF_WENDLAND 2
@@ -72,6 +77,7 @@ typedef struct {
                          scaling and squaring with K squarings (Sec. III-D) */
     int regulariser;  /* AIRO_REG_*: the term lambda_diff weights (Sec. III-F) */
     double sigma[3];  /* Wendland support radius (voxels) along x, y, z */
+    int lcc_radius;   /* LCC window: the cube |y - x|_inf <= lcc_radius */
 } airo_problem;
 
 #define AIRO_REG_DIFFUSION 0
@@ -127,7 +133,12 @@ void airo_sample(const airo_problem* p, const double* moving, const double* u,
 void airo_warp(const airo_problem* p, const double* moving, const double* theta,
                double* warped, unsigned char* mask);
 
-/* Similarity over the masked set; dsdw [N] nullable. Returns flag bits. */
+/* Similarity over the masked set; dsdw [N] nullable. Returns flag bits.
+ * LCC (Sec. III-B, the local version of NCC): for x in the masked set X',
+ * the window N(x) = {y in X' : |y - x|_inf <= lcc_radius}, n = |N(x)|, the
+ * means, variances and covariance of F and W over N(x) (divided by n),
+ *   rho(x) = cov / sqrt(varF varW + AIRO_LCC_EPS),
+ * and S = -(1/|X'|) sum_{x in X'} rho(x). */
 int airo_similarity(const airo_problem* p, const double* fixed, const double* warped,
                     const unsigned char* mask, double* value, double* dsdw);
 
