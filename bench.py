@@ -8,7 +8,10 @@ Cache). Other workloads (--workload): `uneven48` (48 pairs with sides from
 `latency2d` (one 64^2 B-spline MSE pair per step), `diffeo256` / `diffeo2d`
 (the dense 256^3 / 4096^2 evaluation with f = exp(v), beside the same
 evaluation without the exponential), `tv128` (one 128^3 B-spline NCC pair
-with anisotropic TV, beside the same pair with diffusion).
+with anisotropic TV, beside the same pair with diffusion), `wendland128` (one
+128^3 NCC pair on the Wendland basis, spacing 8 and sigma 16, beside the same
+pair on the cubic B-spline), `lcc128` (one 128^3 B-spline pair with LCC,
+window radius 3, beside the same pair with NCC).
 
 Prints one JSON line. `roofline` reports the dominant kernel from HIP events
 the library records around it on its own stream; `traffic` comes from
@@ -35,6 +38,8 @@ import numpy as np  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
 SPACING = (8, 8, 8)
+WEND_SIGMA = (16.0, 16.0, 16.0)   # Wendland support radius (voxels) of the wendland128 workload
+LCC_RADIUS = 3                    # LCC window radius (voxels) of the lcc128 workload
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -72,7 +77,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batch128",
                     choices=["batch128", "uneven48", "dense256", "latency2d", "diffeo256",
-                             "diffeo2d", "tv128"])
+                             "diffeo2d", "tv128", "wendland128", "lcc128"])
     ap.add_argument("--pairs", type=int, default=64)
     ap.add_argument("--tiling", type=int, default=-1, help="-1: autotune cache or default")
     ap.add_argument("--autotune-out", default="",
@@ -149,6 +154,20 @@ def cpu_baseline(seconds, workload):
                       regulariser=O.REG_ANISO_TV)
         th = synth.random_theta(n3, SPACING, 1.0, 5000)
         desc = "one 128^3 B-spline NCC + anisotropic TV pair"
+    elif workload == "wendland128":
+        n3 = (128, 128, 128)
+        pair = synth.pair_3d(warp=O.warp_fn_fp32)
+        p = O.Problem(n=n3, transform=O.TF_WENDLAND, spacing=SPACING, sigma=WEND_SIGMA,
+                      similarity=O.SIM_NCC, lambda_diff=0.05)
+        th = synth.random_controls(n3, p.ncontrol(), 1.0, 5000)
+        desc = "one 128^3 Wendland (spacing 8, sigma 16) NCC pair"
+    elif workload == "lcc128":
+        n3 = (128, 128, 128)
+        pair = synth.pair_3d(warp=O.warp_fn_fp32)
+        p = O.Problem(n=n3, spacing=SPACING, similarity=O.SIM_LCC, lcc_radius=LCC_RADIUS,
+                      lambda_diff=0.05)
+        th = synth.random_theta(n3, SPACING, 1.0, 5000)
+        desc = f"one 128^3 B-spline LCC (radius {LCC_RADIUS}) pair"
     elif workload == "latency2d":
         n3 = (64, 64)
         pair = synth.pair_2d(warp=O.warp_fn_fp32)
@@ -488,6 +507,100 @@ def run_tv128(args, dev):
     }
 
 
+def run_wendland128(args, dev):
+    """One 128^3 pair on the Wendland basis (spacing 8, sigma 16 voxels),
+    NCC + 0.05 diffusion, beside the same pair on the cubic B-spline."""
+    import torch
+
+    from paper_1806_09907_amd import api, synth
+
+    n = (128, 128, 128)
+    Fs, Ms, Ts = blob_batch([n], dev)
+    pw = api.Problem(n=n, transform=api.TF_WENDLAND, spacing=SPACING, sigma=WEND_SIGMA,
+                     similarity=api.SIM_NCC, lambda_diff=0.05)
+    th = torch.from_numpy(synth.random_controls(n, pw.ncontrol(), 1.0, 5000)).to(dev)
+    value = torch.empty((), dtype=torch.float32, device=dev)
+    grad = torch.empty_like(th)
+    gbs = torch.empty_like(Ts[0])
+    wp = api.Plan(pw)
+    bs = api.Plan(api.Problem(n=n, spacing=SPACING, similarity=api.SIM_NCC, lambda_diff=0.05))
+    wp.prepare()
+    bs.prepare()
+    progress("timing")
+    ms_bs, _ = timed(bs, args.steps, args.warmup,
+                     lambda: api.objective_and_grad(bs, Fs[0], Ms[0], Ts[0], value, gbs))
+    ms_w, _ = timed(wp, args.steps, args.warmup,
+                    lambda: api.objective_and_grad(wp, Fs[0], Ms[0], th, value, grad))
+    N = 128 ** 3
+    nctrl = 1
+    for c in pw.ncontrol():
+        nctrl *= c
+    # expansion (write u), dense pass (read F, M, u; write dL/du), transposed
+    # contraction (read dL/du), controls read and gradient written
+    bytes_eval = 4 * 3 * N + 4 * (2 + 3 + 3) * N + 4 * 3 * N + 4 * 2 * 3 * nctrl
+    achieved = bytes_eval / (ms_w / 1e3) / 1e9
+    return {
+        "metric": "objective+grad evals/s, 128^3 Wendland NCC + 0.05 diffusion, one pair",
+        "value": 1e3 / ms_w, "unit": "evals/s", "ms_per_step": ms_w,
+        "config": {"workload": "one 128^3 blob pair, Wendland psi_{3,2} basis, spacing 8, "
+                               "sigma 16 voxels per axis, NCC + 0.05 diffusion",
+                   "n": list(n), "bspline_ms_per_eval": ms_bs,
+                   "wendland_over_bspline": ms_w / ms_bs, "algorithmic_bytes_per_step": bytes_eval},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "whole evaluation (expansion, dense pass, transposed contraction "
+                               "and gather); one pair, so partly served from the Infinity Cache",
+                     "kernel_ms": ms_w, "algorithmic_bytes_per_launch": bytes_eval},
+    }
+
+
+def run_lcc128(args, dev):
+    """One 128^3 B-spline pair (spacing 8) with LCC (window radius 3) + 0.05
+    diffusion, beside the same pair with NCC."""
+    import torch
+
+    from paper_1806_09907_amd import api
+
+    n = (128, 128, 128)
+    Fs, Ms, Ts = blob_batch([n], dev)
+    value = torch.empty((), dtype=torch.float32, device=dev)
+    grad = torch.empty_like(Ts[0])
+    lp = api.Plan(api.Problem(n=n, spacing=SPACING, similarity=api.SIM_LCC,
+                              lcc_radius=LCC_RADIUS, lambda_diff=0.05))
+    nc = api.Plan(api.Problem(n=n, spacing=SPACING, similarity=api.SIM_NCC, lambda_diff=0.05))
+    lp.prepare()
+    nc.prepare()
+    progress("timing")
+    ms_nc, _ = timed(nc, args.steps, args.warmup,
+                     lambda: api.objective_and_grad(nc, Fs[0], Ms[0], Ts[0], value, grad))
+    ms_l, _ = timed(lp, args.steps, args.warmup,
+                    lambda: api.objective_and_grad(lp, Fs[0], Ms[0], Ts[0], value, grad))
+    N = 128 ** 3
+    nctrl = 19 ** 3
+    # expansion (write u); diffusion pass (read u, write dR/du); sample (read
+    # u and M, write W, mask, dW/dp); statistics (read F, W, mask; box sums
+    # out and back, FP64); coefficients out and back; gradient pass (read W,
+    # F, mask, dW/dp, dR/du; write dL/du); transposed expansion (read dL/du)
+    bytes_eval = (4 * 3 * N + 4 * 6 * N + (4 * 4 + 4 + 1 + 12) * N + (9 + 2 * 48) * N
+                  + (12 + 2 * 24) * N + (9 + 12 + 12 + 12) * N + 12 * N + 4 * 2 * 3 * nctrl)
+    achieved = bytes_eval / (ms_l / 1e3) / 1e9
+    return {
+        "metric": "objective+grad evals/s, 128^3 B-spline LCC (radius 3) + 0.05 diffusion, "
+                  "one pair",
+        "value": 1e3 / ms_l, "unit": "evals/s", "ms_per_step": ms_l,
+        "config": {"workload": "one 128^3 blob pair, cubic B-spline spacing 8, LCC over 7^3 "
+                               "windows + 0.05 diffusion",
+                   "n": list(n), "lcc_radius": LCC_RADIUS, "ncc_ms_per_eval": ms_nc,
+                   "lcc_over_ncc": ms_l / ms_nc, "algorithmic_bytes_per_step": bytes_eval},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "whole evaluation (expansion, diffusion, sample, LCC box passes, "
+                               "transposed expansion); one pair, partly served from the "
+                               "Infinity Cache",
+                     "kernel_ms": ms_l, "algorithmic_bytes_per_launch": bytes_eval},
+    }
+
+
 def run_latency2d(args, dev):
     import torch
 
@@ -617,6 +730,10 @@ def main():
         out = run_diffeo(args, dev, args.workload == "diffeo256")
     elif args.workload == "tv128":
         out = run_tv128(args, dev)
+    elif args.workload == "wendland128":
+        out = run_wendland128(args, dev)
+    elif args.workload == "lcc128":
+        out = run_lcc128(args, dev)
     else:
         out = run_latency2d(args, dev)
     line = {"metric": out["metric"], "value": out["value"], "unit": out["unit"], "n_gpus": 1,

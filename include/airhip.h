@@ -64,8 +64,23 @@ typedef enum {
     AIR_ERR_DEVICE = 8        /* device query, allocation or copy failed */
 } air_status;
 
-enum { AIR_SIM_MSE = 0, AIR_SIM_NCC = 1 };
-enum { AIR_TF_BSPLINE3 = 0, AIR_TF_DENSE = 1 };
+/* Similarities (Sec. II-A, III-B) over the masked set X' (sample points
+ * inside the moving image): MSE; NCC (loss -rho, rho the Pearson correlation
+ * of F and W over X'); LCC (local NCC: for x in X' the mean, variance and
+ * covariance over N(x) = {y in X' : |y - x|_inf <= lcc_radius}, divided by
+ * |N(x)|, rho(x) = cov / sqrt(varF varW + 1e-10), S = -mean of rho over X').
+ * LCC plans hold one pair and evaluate the objective on the field expanded
+ * to the voxel grid. */
+enum { AIR_SIM_MSE = 0, AIR_SIM_NCC = 1, AIR_SIM_LCC = 2 };
+/* Transformations: cubic B-spline (Sec. III-C, kernel k_B1D; control j at
+ * voxel (j-1) delta, nc = floor((n-1)/delta) + 4 per axis), dense (one
+ * vector per voxel), Wendland (Sec. III-C, psi_{3,2}(r) = (1-r)^6_+
+ * (3 + 18r + 35r^2)/3 at r = ||(x - c_j) / sigma|| with sigma per axis;
+ * control j at (j - m) delta with m = ceil(sigma/delta) - 1 and
+ * nc = m + ceil((n - 1 + sigma)/delta) per axis: every control within sigma
+ * of a voxel on that axis). Parameters are [d][ncz][ncy][ncx] (interpolating
+ * bases) or [d][nz][ny][nx] (dense), components ordered (x, y, z). */
+enum { AIR_TF_BSPLINE3 = 0, AIR_TF_DENSE = 1, AIR_TF_WENDLAND = 2 };
 /* Regularisers on the displacement f (Sec. III-F), on the forward
  * differences D_a f_c(x) = f_c(x + e_a) - f_c(x) over X_R, divided by |X_R|:
  * diffusion sum_c sum_a D^2; anisotropic TV sum_c sum_a |D|; isotropic TV
@@ -78,7 +93,8 @@ typedef struct {
     int32_t dim;          /* 2 or 3 */
     int32_t n[3];         /* voxels along x, y, z (n[2] == 1 in 2D), each >= 2 */
     int32_t transform;    /* AIR_TF_* */
-    int32_t spacing[3];   /* B-spline control spacing in voxels, 1..64 */
+    int32_t spacing[3];   /* control spacing delta in voxels, 1..64 (B-spline,
+                             Wendland) */
     int32_t similarity;   /* AIR_SIM_* */
     float lambda_diff;    /* weight of the regulariser, >= 0 */
     int32_t diffeo_steps; /* 0: f is the field itself. K in 1..16: f = exp(v)
@@ -88,6 +104,19 @@ typedef struct {
                              image (zero outside, no mask). R then acts on
                              f = u_K. Plans with K > 0 hold one pair. */
     int32_t regulariser;  /* AIR_REG_*; plans with a TV term hold one pair */
+    float sigma[3];       /* Wendland support radius in voxels along x, y, z,
+                             finite and > 0 (read only for AIR_TF_WENDLAND).
+                             The voxel-to-control weight table has
+                             prod_a delta_a * prod_a K_a entries, K_a the
+                             controls a cell sees along axis a (about
+                             2 sigma_a / delta_a + 1); plans beyond 2^21 entries
+                             are AIR_ERR_UNSUPPORTED. Wendland plans hold one
+                             pair and, like plans with K > 0, evaluate the
+                             objective on the field expanded to the voxel grid;
+                             air_warp is AIR_ERR_UNSUPPORTED for them (use
+                             air_displacement and a dense plan). */
+    int32_t lcc_radius;   /* LCC window radius in voxels, 1..8 (read only for
+                             AIR_SIM_LCC) */
 } air_problem;
 
 /* Opaque plan: host tables for one pair or a batch of pairs that share

@@ -30,7 +30,8 @@ class AirProblem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3),
                 ("transform", ctypes.c_int32), ("spacing", ctypes.c_int32 * 3),
                 ("similarity", ctypes.c_int32), ("lambda_diff", ctypes.c_float),
-                ("diffeo_steps", ctypes.c_int32), ("regulariser", ctypes.c_int32)]
+                ("diffeo_steps", ctypes.c_int32), ("regulariser", ctypes.c_int32),
+                ("sigma", ctypes.c_float * 3), ("lcc_radius", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p

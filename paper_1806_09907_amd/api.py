@@ -8,6 +8,7 @@ device memory and the stream.
 from __future__ import annotations
 
 import ctypes
+import math
 from dataclasses import dataclass
 from typing import List, Optional, Sequence, Tuple, Union
 
@@ -15,8 +16,8 @@ import torch
 
 from ._lib import AirProblem, check, lib
 
-SIM_MSE, SIM_NCC = 0, 1
-TF_BSPLINE3, TF_DENSE = 0, 1
+SIM_MSE, SIM_NCC, SIM_LCC = 0, 1, 2
+TF_BSPLINE3, TF_DENSE, TF_WENDLAND = 0, 1, 2
 REG_DIFFUSION, REG_ANISO_TV, REG_ISO_TV = 0, 1, 2
 FLAG_NONFINITE, FLAG_DEGENERATE = 1, 2
 
@@ -31,6 +32,8 @@ class Problem:
     lambda_diff: float = 0.0
     diffeo_steps: int = 0      # > 0: f = exp(field), this many squarings (Sec. III-D)
     regulariser: int = 0       # REG_DIFFUSION, REG_ANISO_TV or REG_ISO_TV (Sec. III-F)
+    sigma: Tuple[float, ...] = ()  # Wendland support radius per axis, voxels (Sec. III-C)
+    lcc_radius: int = 2        # LCC window |y - x|_inf <= lcc_radius (Sec. III-B)
 
     @property
     def dim(self) -> int:
@@ -41,6 +44,13 @@ class Problem:
         return tuple(reversed(self.n))
 
     def ncontrol(self) -> Tuple[int, ...]:
+        if self.transform == TF_WENDLAND:
+            out = []
+            for a in range(self.dim):
+                s = ctypes.c_float(self.sigma[a]).value   # the library reads FP32
+                m = math.ceil(s / self.spacing[a]) - 1
+                out.append(m + math.ceil((self.n[a] - 1 + s) / self.spacing[a]))
+            return tuple(out)
         return tuple((self.n[a] - 1) // self.spacing[a] + 4 for a in range(self.dim))
 
     def param_shape(self) -> Tuple[int, ...]:
@@ -52,10 +62,12 @@ class Problem:
         d = self.dim
         n = list(self.n) + [1] * (3 - d)
         sp = list(self.spacing[:d]) + [1] * (3 - d)
+        sg = [float(x) for x in self.sigma[:d]] + [1.0] * (3 - len(self.sigma[:d]))
         return AirProblem(d, (ctypes.c_int32 * 3)(*n), int(self.transform),
                           (ctypes.c_int32 * 3)(*sp), int(self.similarity),
                           float(self.lambda_diff), int(self.diffeo_steps),
-                          int(self.regulariser))
+                          int(self.regulariser), (ctypes.c_float * 3)(*sg),
+                          int(self.lcc_radius))
 
 
 def _stream() -> ctypes.c_void_p:

@@ -41,7 +41,13 @@ struct PairDesc {
     int regpart_off;     // double offset of the pair's regulariser partials
     int dense_blk_off;   // first dense stats block slot of the pair
     int dense_nblk;      // dense stats blocks of the pair
-    int pad_;
+    // Wendland basis: voxel cells of size sp, each seeing controls c + [0, wK)
+    int wncell[3];       // cells per axis, ceil(n / sp)
+    int wK[3];           // controls a cell sees per axis
+    int wncp[3];         // padded control grid of the expansion (zeros beyond nc)
+    int wpad[2];         // phases prod(sp) and prod(wK), rounded up to 64
+    int wend_off[2];     // float offsets of W [K^d][wpad0] and W^T [wpad0][wpad1]
+    int wpad_;
 };
 
 // Workspace layout (byte offsets into the caller's workspace).
@@ -57,9 +63,19 @@ struct WsLayout {
     size_t fields;       // float [K + 1][d N]: u_0 .. u_K of the exponential (K > 0)
     size_t gfield;       // float [2][d N]: gradients going back through the squarings
     size_t bsadj1;       // float [d][nz][ny][ncx]: transposed expansion, after x
+                         // (Wendland: the padded, scaled controls)
     size_t bsadj2;       // float [d][nz][ncy][ncx]: after y
+                         // (Wendland: per-cell sums H [d][cells][K^d])
     size_t reach;        // uint32 [K + 1]: largest displacement of each u_k (float bits)
     size_t tvpart;       // double [TV blocks]: partial sums of a TV term
+    // LCC passes (similarity AIR_SIM_LCC)
+    size_t lcc_w;        // float [N]: warped image
+    size_t lcc_mask;     // uint8 [N]: sample point inside the moving image
+    size_t lcc_dw;       // float [d][N]: dW/dp (voxel units)
+    size_t lcc_s;        // double [6][N]: box sums (statistics, then coefficients)
+    size_t lcc_a;        // float [3][N]: coefficient maps
+    size_t lcc_part;     // double [2 * blocks]: (count, sum rho) per block
+    size_t lcc_scal;     // double [1]: 1 / |X'|
     size_t total;
 };
 

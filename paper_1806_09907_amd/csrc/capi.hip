@@ -39,6 +39,22 @@ hipError_t launch_compose_adjoint(const PairDesc& P, int dim, const float* u, co
 hipError_t launch_velocity_adjoint(const PairDesc& P, const float* consts_dev, int transform,
                                    int dim, const float* g, float scale, float* t1, float* t2,
                                    float* grad, hipStream_t s, bool accumulate);
+hipError_t launch_wendland_expand(const PairDesc& P, const float* consts_dev, int dim,
+                                  const float* theta, float scale, float* thp, float* u,
+                                  hipStream_t s);
+hipError_t launch_wendland_adjoint(const PairDesc& P, const float* consts_dev, int dim,
+                                   const float* g, float scale, float* H, float* grad,
+                                   bool accumulate, hipStream_t s);
+int wendland_cells_per_wave();
+int lcc_partials(const PairDesc& P);
+size_t lcc_lds_bytes(int r);
+hipError_t launch_lcc(const PairDesc& P, int dim, int r, const float* F, const float* M,
+                      const float* u, float* Wb, uint8_t* mk, float* dW, double* S, float* A,
+                      double* part, double* scal, uint32_t* flag, float lambda, bool lam_acc,
+                      float* value, float* grad, hipStream_t s);
+hipError_t launch_lcc_value(const PairDesc& P, int dim, int r, const float* F, const float* Wimg,
+                            const uint8_t* mk, double* S, float* A, double* part, double* scal,
+                            uint32_t* flag, float* value, hipStream_t s);
 int tv_partials();
 hipError_t launch_tv(const PairDesc& P, int dim, int kind, const float* u, float scale,
                      float* grad, bool accumulate_grad, double* partial, float weight,
@@ -67,6 +83,8 @@ constexpr int kNumCfg3 = sizeof(kCfg3) / sizeof(kCfg3[0]);
 constexpr int kNumCfg2 = sizeof(kCfg2) / sizeof(kCfg2[0]);
 constexpr int kGenericSlots = 1024;
 constexpr size_t kMaxLds = 64 * 1024;
+constexpr long long kMaxWendTable = 1LL << 21;  // entries of each Wendland weight table
+constexpr int kMaxLccRadius = 8;
 constexpr int kMaxDevices = 64;
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -96,6 +114,11 @@ struct air_plan {
     std::vector<hipEvent_t> ev;
     int ev_next = 0;
     int ev_device = -1;
+    int lcc_radius = 0;
+    // the displacement needs workspace fields (exponential or Wendland)
+    bool expanded() const { return diffeo > 0 || transform == AIR_TF_WENDLAND; }
+    // the objective is evaluated on the field expanded to the voxel grid
+    bool field_route() const { return expanded() || sim == AIR_SIM_LCC; }
 };
 
 // ------------------------------------------------------------------ tables
@@ -145,10 +168,90 @@ static void gram_tables(int n, int sp, int nc, std::vector<float>& out) {
     for (double v : D) out.push_back((float)v);
 }
 
+// Wendland kernel psi_{3,2} (Sec. III-C), in double for the host tables.
+static double wendland_psi(double r) {
+    if (r >= 1.0) return 0.0;
+    const double t = 1.0 - r;
+    const double t2 = t * t;
+    return t2 * t2 * t2 * (3.0 + r * (18.0 + 35.0 * r)) / 3.0;
+}
+
+// One axis of a Wendland grid: controls nc, lattice offset m (control j at
+// (j - m) sp), the controls a cell sees (j - c in [0, K) for cell c) and the
+// number of cells. A control within sig (open) of a voxel is seen.
+static void wendland_axis(int n, int sp, double sig, int* nc, int* m, int* K, int* ncell) {
+    *m = (int)ceil(sig / sp) - 1;
+    *nc = *m + (int)ceil((n - 1 + sig) / sp);
+    int qhi = -(*m);
+    for (int r = 0; r < sp; ++r)
+        for (int q = -(*m); q <= *m + 2; ++q)  // q = j - m - c
+            if (fabs((double)r - (double)q * sp) < sig) qhi = std::max(qhi, q);
+    *K = qhi + *m + 1;
+    *ncell = (n + sp - 1) / sp;
+}
+
+static int round64(long long x) { return (int)((x + 63) / 64 * 64); }
+
+// W[qq][r] and W^T of a Wendland pair (see k_wendland.hip); false if too big.
+static bool wendland_tables(const air_problem& p, PairDesc& D, std::vector<float>& consts) {
+    const int d = p.dim;
+    int m[3] = {0, 0, 0};
+    for (int a = 0; a < d; ++a) {
+        int nc, K, ncell;
+        wendland_axis(p.n[a], p.spacing[a], (double)p.sigma[a], &nc, &m[a], &K, &ncell);
+        D.wK[a] = K;
+        D.wncell[a] = ncell;
+    }
+    for (int a = d; a < 3; ++a) {
+        D.wK[a] = 1;
+        D.wncell[a] = 1;
+    }
+    const int cw = wendland_cells_per_wave();
+    D.wncp[0] = std::max(D.nc[0], cdiv(D.wncell[0], cw) * cw + D.wK[0] - 1);
+    for (int a = 1; a < 3; ++a) D.wncp[a] = std::max(D.nc[a], D.wncell[a] + D.wK[a] - 1);
+    const long long P3 = (long long)D.sp[0] * D.sp[1] * D.sp[2];
+    const long long Q = (long long)D.wK[0] * D.wK[1] * D.wK[2];
+    const long long Ppad = round64(P3), Qpad = round64(Q);
+    if (Q * Ppad > kMaxWendTable || Ppad * Qpad > kMaxWendTable) return false;
+    D.wpad[0] = (int)Ppad;
+    D.wpad[1] = (int)Qpad;
+    std::vector<float> W((size_t)(Q * Ppad), 0.f);
+    for (long long qq = 0; qq < Q; ++qq) {
+        const int qi[3] = {(int)(qq % D.wK[0]), (int)((qq / D.wK[0]) % D.wK[1]),
+                           (int)(qq / ((long long)D.wK[0] * D.wK[1]))};
+        for (long long r = 0; r < P3; ++r) {
+            const int ri[3] = {(int)(r % D.sp[0]), (int)((r / D.sp[0]) % D.sp[1]),
+                               (int)(r / ((long long)D.sp[0] * D.sp[1]))};
+            double r2 = 0.0;
+            for (int a = 0; a < d; ++a) {
+                const double o = (double)ri[a] - (double)(qi[a] - m[a]) * D.sp[a];
+                const double q = o / (double)p.sigma[a];
+                r2 += q * q;
+            }
+            W[(size_t)(qq * Ppad + r)] = (float)wendland_psi(sqrt(r2));
+        }
+    }
+    while (consts.size() % 4) consts.push_back(0.f);
+    D.wend_off[0] = (int)consts.size();
+    consts.insert(consts.end(), W.begin(), W.end());
+    D.wend_off[1] = (int)consts.size();
+    consts.resize(consts.size() + (size_t)(Ppad * Qpad), 0.f);
+    float* WT = consts.data() + D.wend_off[1];
+    for (long long qq = 0; qq < Q; ++qq)
+        for (long long r = 0; r < Ppad; ++r) WT[r * Qpad + qq] = W[(size_t)(qq * Ppad + r)];
+    return true;
+}
+
 static air_status validate_problem(const air_problem& p) {
     if (p.dim != 2 && p.dim != 3) return AIR_ERR_INVALID_ARG;
-    if (p.transform != AIR_TF_BSPLINE3 && p.transform != AIR_TF_DENSE) return AIR_ERR_INVALID_ARG;
-    if (p.similarity != AIR_SIM_MSE && p.similarity != AIR_SIM_NCC) return AIR_ERR_INVALID_ARG;
+    if (p.transform != AIR_TF_BSPLINE3 && p.transform != AIR_TF_DENSE &&
+        p.transform != AIR_TF_WENDLAND)
+        return AIR_ERR_INVALID_ARG;
+    if (p.similarity != AIR_SIM_MSE && p.similarity != AIR_SIM_NCC &&
+        p.similarity != AIR_SIM_LCC)
+        return AIR_ERR_INVALID_ARG;
+    if (p.similarity == AIR_SIM_LCC && (p.lcc_radius < 1 || p.lcc_radius > kMaxLccRadius))
+        return AIR_ERR_INVALID_ARG;
     if (!(p.lambda_diff >= 0.f) || !isfinite(p.lambda_diff)) return AIR_ERR_INVALID_ARG;
     if (p.diffeo_steps < 0 || p.diffeo_steps > 16) return AIR_ERR_INVALID_ARG;
     if (p.regulariser < AIR_REG_DIFFUSION || p.regulariser > AIR_REG_ISO_TV)
@@ -156,8 +259,11 @@ static air_status validate_problem(const air_problem& p) {
     long long N = 1;
     for (int a = 0; a < p.dim; ++a) {
         if (p.n[a] < 2 || p.n[a] > 65536) return AIR_ERR_SHAPE;
-        if (p.transform == AIR_TF_BSPLINE3 && (p.spacing[a] < 1 || p.spacing[a] > kMaxSpacing))
+        if (p.transform != AIR_TF_DENSE && (p.spacing[a] < 1 || p.spacing[a] > kMaxSpacing))
             return AIR_ERR_SHAPE;
+        if (p.transform == AIR_TF_WENDLAND &&
+            (!isfinite(p.sigma[a]) || !(p.sigma[a] > 0.f) || p.sigma[a] > 65536.f))
+            return AIR_ERR_INVALID_ARG;
         N *= p.n[a];
     }
     if (p.dim == 2 && p.n[2] != 1) return AIR_ERR_SHAPE;
@@ -168,6 +274,7 @@ static air_status validate_problem(const air_problem& p) {
 static air_status build_tables(air_plan* P) {
     const int d = P->dim;
     const bool bs = P->transform == AIR_TF_BSPLINE3;
+    const bool wend = P->transform == AIR_TF_WENDLAND;
     const TileCfg cfg = (d == 3) ? kCfg3[P->tiling] : kCfg2[P->tiling];
     const int NF = P->sim == AIR_SIM_NCC ? 3 : 1;
     bool all_s8 = bs && d == 3;
@@ -190,8 +297,13 @@ static air_status build_tables(air_plan* P) {
         for (int a = 0; a < 3; ++a) {
             const bool on = a < d;
             D.n[a] = on ? p.n[a] : 1;
-            D.sp[a] = (on && bs) ? p.spacing[a] : 1;
+            D.sp[a] = (on && (bs || wend)) ? p.spacing[a] : 1;
             D.nc[a] = on ? (bs ? (p.n[a] - 1) / p.spacing[a] + 4 : p.n[a]) : 1;
+            if (on && wend) {
+                int m, K, ncell;
+                wendland_axis(p.n[a], p.spacing[a], (double)p.sigma[a], &D.nc[a], &m, &K,
+                              &ncell);
+            }
             D.s[a] = on ? (float)((p.n[a] - 1) * 0.5) : 0.f;
             if (on) {
                 N *= D.n[a];
@@ -200,7 +312,8 @@ static air_status build_tables(air_plan* P) {
             }
         }
         D.nvox = N;
-        D.nparam = (long long)d * (bs ? NC : N);
+        D.nparam = (long long)d * ((bs || wend) ? NC : N);
+        if (wend && !wendland_tables(p, D, P->consts)) return AIR_ERR_UNSUPPORTED;
         D.param_off = (long long)param_n;
         param_n += (size_t)D.nparam;
         D.inv_xr = (float)(1.0 / xr);
@@ -277,8 +390,8 @@ static air_status build_tables(air_plan* P) {
             lds_r = std::max(lds_r, 8 * sizeof(double) * (kBlock / 64) + 4 * reg);
             stats_n = tiles;
         }
-        // dense passes: dense models, and the objective at exp(v) of either model
-        if (!bs || P->diffeo > 0) {
+        // dense passes: dense models, and the objective at exp(v) or with LCC
+        if (!bs || P->field_route()) {
             const int nbx = cdiv(D.n[0], kDenseTX), nby = cdiv(D.n[1], kDenseTY);
             const int nbz = d == 3 ? cdiv(D.n[2], kDenseZc) : 1;
             D.dense_nblk = nbx * nby * nbz;
@@ -288,6 +401,7 @@ static air_status build_tables(air_plan* P) {
         }
     }
     if (lds_f > kMaxLds || lds_r > kMaxLds) return AIR_ERR_UNSUPPORTED;
+    if (P->sim == AIR_SIM_LCC && lcc_lds_bytes(P->lcc_radius) > kMaxLds) return AIR_ERR_UNSUPPORTED;
     P->ntiles_total = tiles;
     P->nreg_total = regs;
     P->lds_fused = lds_f;
@@ -304,20 +418,37 @@ static air_status build_tables(air_plan* P) {
     L.scalars = off;     off = align256(off + (size_t)P->npairs * 8 * 8);
     L.dense_stats = off; off = align256(off + std::max<size_t>(dense_n, 1) * kStatWords * 8);
     L.generic = off;     off = align256(off + (size_t)kGenericSlots * kStatWords * 8);
-    // the fields of the exponential, or the expanded B-spline field of a TV term
-    if (P->diffeo > 0 || (P->reg != AIR_REG_DIFFUSION && bs)) {
+    // the fields of the exponential, the expanded Wendland field, or the
+    // expanded B-spline field of a TV term
+    if (P->field_route() || (P->reg != AIR_REG_DIFFUSION && bs)) {
         const PairDesc& D = P->pd[0];
         const size_t dN = (size_t)d * (size_t)D.nvox;
         L.fields = off;  off = align256(off + (size_t)(P->diffeo + 1) * dN * 4);
         L.gfield = off;  off = align256(off + 2 * dN * 4);
-        const size_t t1 = bs ? (size_t)d * D.n[2] * D.n[1] * D.nc[0] : 1;
-        const size_t t2 = bs ? (size_t)d * D.n[2] * D.nc[1] * D.nc[0] : 1;
+        size_t t1 = bs ? (size_t)d * D.n[2] * D.n[1] * D.nc[0] : 1;
+        size_t t2 = bs ? (size_t)d * D.n[2] * D.nc[1] * D.nc[0] : 1;
+        if (wend) {
+            t1 = (size_t)d * D.wncp[0] * D.wncp[1] * D.wncp[2];
+            t2 = (size_t)d * D.wncell[0] * D.wncell[1] * D.wncell[2] * D.wK[0] * D.wK[1] *
+                 D.wK[2];
+        }
         L.bsadj1 = off;  off = align256(off + t1 * 4);
         L.bsadj2 = off;  off = align256(off + t2 * 4);
         L.reach = off;   off = align256(off + (size_t)(P->diffeo + 1) * 4);
     }
     if (P->reg != AIR_REG_DIFFUSION) {
         L.tvpart = off;  off = align256(off + (size_t)tv_partials() * 8);
+    }
+    if (P->sim == AIR_SIM_LCC) {
+        const PairDesc& D = P->pd[0];
+        const size_t N = (size_t)D.nvox;
+        L.lcc_w = off;     off = align256(off + N * 4);
+        L.lcc_mask = off;  off = align256(off + N);
+        L.lcc_dw = off;    off = align256(off + (size_t)d * N * 4);
+        L.lcc_s = off;     off = align256(off + 6 * N * 8);
+        L.lcc_a = off;     off = align256(off + 3 * N * 4);
+        L.lcc_part = off;  off = align256(off + 2 * (size_t)lcc_partials(D) * 8);
+        L.lcc_scal = off;  off = align256(off + 8);
     }
     L.total = off;
     return AIR_OK;
@@ -386,23 +517,50 @@ static LaunchCtx base_ctx(const air_plan* P, const DeviceTables* T, void* ws) {
     return C;
 }
 
-// u_K = exp(v) into the workspace fields u_0 .. u_K (Sec. III-D). Returns u_K.
+// out = scale * (the field of theta on the voxel grid): B theta for the
+// interpolating bases, theta for dense.
+static hipError_t expand_field(const air_plan* P, const DeviceTables* T, unsigned char* w,
+                               const float* theta, float scale, float* out, hipStream_t s) {
+    const PairDesc& hp = P->pd[0];
+    if (P->transform == AIR_TF_WENDLAND)
+        return launch_wendland_expand(hp, T->consts, P->dim, theta, scale,
+                                      reinterpret_cast<float*>(w + P->L.bsadj1), out, s);
+    return launch_velocity(hp, T->consts, P->transform, P->dim, theta, scale, out, s);
+}
+
+// grad (+)= scale * (the transpose of expand_field) g.
+static hipError_t field_adjoint(const air_plan* P, const DeviceTables* T, unsigned char* w,
+                                const float* g, float scale, float* grad, bool accumulate,
+                                hipStream_t s) {
+    const PairDesc& hp = P->pd[0];
+    if (P->transform == AIR_TF_WENDLAND)
+        return launch_wendland_adjoint(hp, T->consts, P->dim, g, scale,
+                                       reinterpret_cast<float*>(w + P->L.bsadj2), grad,
+                                       accumulate, s);
+    return launch_velocity_adjoint(hp, T->consts, P->transform, P->dim, g, scale,
+                                   reinterpret_cast<float*>(w + P->L.bsadj1),
+                                   reinterpret_cast<float*>(w + P->L.bsadj2), grad, s,
+                                   accumulate);
+}
+
+// u_K = exp(v) into the workspace fields u_0 .. u_K (Sec. III-D); with K = 0
+// u_0 is the field itself. Returns u_K.
 static hipError_t diffeo_forward(const air_plan* P, const DeviceTables* T, unsigned char* w,
                                  const float* theta, hipStream_t s, float** uK) {
     const PairDesc& hp = P->pd[0];
     const long long dN = (long long)P->dim * hp.nvox;
     float* U = reinterpret_cast<float*>(w + P->L.fields);
-    hipError_t e = launch_velocity(hp, T->consts, P->transform, P->dim, theta,
-                                   ldexpf(1.f, -P->diffeo), U, s);
+    hipError_t e = expand_field(P, T, w, theta, ldexpf(1.f, -P->diffeo), U, s);
     for (int k = 0; k < P->diffeo && e == hipSuccess; ++k)
         e = launch_compose(hp, P->dim, U + k * dN, U + (k + 1) * dN, s);
     *uK = U + P->diffeo * dN;
     return e;
 }
 
-// Objective (or, with reg_only, the regulariser) of a diffeomorphic plan:
-// u_K = exp(v), the dense-field evaluation at u_K giving dL/du_K, then back
-// through the squarings and the velocity model to dL/dtheta.
+// Objective (or, with reg_only, the regulariser) of a plan evaluated on the
+// expanded field: u_K = exp(v) (u_0 = v when K = 0), the dense-field
+// evaluation at u_K giving dL/du_K, then back through the squarings and the
+// field model to dL/dtheta.
 static hipError_t run_diffeo(const air_plan* P, const DeviceTables* T, void* ws,
                              const float* fixed, const float* moving, const float* theta,
                              float* value, float* grad, bool reg_only, hipStream_t s) {
@@ -422,6 +580,24 @@ static hipError_t run_diffeo(const air_plan* P, const DeviceTables* T, void* ws,
             e = launch_reg_dense(C, hp.dense_nblk, kDenseZc, g, value, s);
         else
             e = launch_tv(hp, P->dim, P->reg, uK, 1.f, g, false, tvp, 1.f, value, false, s);
+    } else if (P->sim == AIR_SIM_LCC) {
+        // the diffusion term first (value = R, g = dR/du), then the LCC
+        // passes add S and dS/du with R and dR/du weighted by lambda
+        const bool diff = P->reg == AIR_REG_DIFFUSION && P->probs[0].lambda_diff != 0.f;
+        if (diff) e = launch_reg_dense(C, hp.dense_nblk, kDenseZc, g, value, s);
+        if (e == hipSuccess)
+            e = launch_lcc(hp, P->dim, P->lcc_radius, fixed, moving, uK,
+                           reinterpret_cast<float*>(w + P->L.lcc_w), w + P->L.lcc_mask,
+                           reinterpret_cast<float*>(w + P->L.lcc_dw),
+                           reinterpret_cast<double*>(w + P->L.lcc_s),
+                           reinterpret_cast<float*>(w + P->L.lcc_a),
+                           reinterpret_cast<double*>(w + P->L.lcc_part),
+                           reinterpret_cast<double*>(w + P->L.lcc_scal),
+                           reinterpret_cast<uint32_t*>(w + P->L.flags), P->probs[0].lambda_diff,
+                           diff, value, g, s);
+        if (e == hipSuccess && P->reg != AIR_REG_DIFFUSION)
+            e = launch_tv(hp, P->dim, P->reg, uK, P->reg_weight, g, true, tvp, P->reg_weight,
+                          value, true, s);
     } else {
         C.fixed0 = fixed;
         C.moving0 = moving;
@@ -435,7 +611,7 @@ static hipError_t run_diffeo(const air_plan* P, const DeviceTables* T, void* ws,
     if (e != hipSuccess || !grad) return e;
     const float* U = reinterpret_cast<const float*>(w + P->L.fields);
     unsigned int* reach = reinterpret_cast<unsigned int*>(w + P->L.reach);
-    e = launch_field_reach(hp, P->dim, U, P->diffeo, reach, s);
+    if (P->diffeo > 0) e = launch_field_reach(hp, P->dim, U, P->diffeo, reach, s);
     for (int k = P->diffeo - 1; k >= 0 && e == hipSuccess; --k) {
         e = launch_compose_adjoint(hp, P->dim, U + k * dN, g, reach + k, o, s);
         float* t = g;
@@ -443,10 +619,7 @@ static hipError_t run_diffeo(const air_plan* P, const DeviceTables* T, void* ws,
         o = t;
     }
     if (e != hipSuccess) return e;
-    return launch_velocity_adjoint(hp, T->consts, P->transform, P->dim, g,
-                                   ldexpf(1.f, -P->diffeo),
-                                   reinterpret_cast<float*>(w + P->L.bsadj1),
-                                   reinterpret_cast<float*>(w + P->L.bsadj2), grad, s, false);
+    return field_adjoint(P, T, w, g, ldexpf(1.f, -P->diffeo), grad, false, s);
 }
 
 // TV term of a plan without the exponential, after the similarity pass:
@@ -484,7 +657,7 @@ static air_status run_objective(const air_plan* cP, LaunchCtx& C, hipStream_t s)
         P->ev_next += 2;
     }
     hipError_t e;
-    if (P->diffeo > 0) {
+    if (P->field_route()) {
         // the whole evaluation is timed: it is a sequence of comparable passes
         if (e0) (void)hipEventRecord(e0, s);
         DeviceTables T{};
@@ -531,7 +704,9 @@ air_status air_plan_create(const air_problem* probs, int32_t npairs, air_plan** 
         if (probs[i].diffeo_steps != probs[0].diffeo_steps ||
             probs[i].regulariser != probs[0].regulariser)
             return AIR_ERR_UNSUPPORTED;
-    if ((probs[0].diffeo_steps > 0 || probs[0].regulariser != AIR_REG_DIFFUSION) && npairs != 1)
+    if ((probs[0].diffeo_steps > 0 || probs[0].regulariser != AIR_REG_DIFFUSION ||
+         probs[0].transform == AIR_TF_WENDLAND || probs[0].similarity == AIR_SIM_LCC) &&
+        npairs != 1)
         return AIR_ERR_UNSUPPORTED;
     air_plan* P = new (std::nothrow) air_plan();
     if (!P) return AIR_ERR_DEVICE;
@@ -542,6 +717,7 @@ air_status air_plan_create(const air_problem* probs, int32_t npairs, air_plan** 
     P->diffeo = probs[0].diffeo_steps;
     P->reg = probs[0].regulariser;
     P->reg_weight = probs[0].lambda_diff;
+    P->lcc_radius = probs[0].similarity == AIR_SIM_LCC ? probs[0].lcc_radius : 0;
     P->probs.assign(probs, probs + npairs);
     P->tiling = 0;
     air_status st = build_tables(P);
@@ -619,7 +795,7 @@ air_status air_warp(const air_plan* plan, int32_t pair, const float* moving, con
                     float* warped, uint8_t* mask, void* stream) {
     if (!plan || !moving || !theta || !warped) return AIR_ERR_INVALID_ARG;
     if (pair < 0 || pair >= plan->npairs) return AIR_ERR_SHAPE;
-    if (plan->diffeo > 0) return AIR_ERR_UNSUPPORTED;
+    if (plan->expanded()) return AIR_ERR_UNSUPPORTED;
     if (!aligned16(moving) || !aligned16(theta) || !aligned16(warped) ||
         (mask && !aligned16(mask)))
         return AIR_ERR_ALIGN;
@@ -636,7 +812,7 @@ air_status air_displacement(const air_plan* plan, int32_t pair, const float* the
     if (!plan || !theta || !u) return AIR_ERR_INVALID_ARG;
     if (pair < 0 || pair >= plan->npairs) return AIR_ERR_SHAPE;
     if (!aligned16(theta) || !aligned16(u)) return AIR_ERR_ALIGN;
-    if (plan->diffeo > 0 && (!ws || ws_bytes < plan->L.total)) return AIR_ERR_WORKSPACE;
+    if (plan->expanded() && (!ws || ws_bytes < plan->L.total)) return AIR_ERR_WORKSPACE;
     if (ws && !aligned16(ws)) return AIR_ERR_ALIGN;
     DeviceTables* T = nullptr;
     air_status st = ensure_device(plan, &T);
@@ -644,7 +820,7 @@ air_status air_displacement(const air_plan* plan, int32_t pair, const float* the
     const PairDesc& hp = plan->pd[pair];
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
-    if (plan->diffeo == 0) {
+    if (!plan->expanded()) {
         e = launch_velocity(hp, T->consts, plan->transform, plan->dim, theta, 1.f, u, s);
     } else {
         float* uK = nullptr;
@@ -664,6 +840,16 @@ air_status air_similarity(const air_plan* plan, int32_t pair, const float* fixed
         return AIR_ERR_ALIGN;
     if (!ws || ws_bytes < plan->L.total) return AIR_ERR_WORKSPACE;
     unsigned char* w = static_cast<unsigned char*>(ws);
+    if (plan->sim == AIR_SIM_LCC) {
+        if (!mask) return AIR_ERR_INVALID_ARG;  // the windows need the masked set
+        hipError_t e = launch_lcc_value(
+            plan->pd[pair], plan->dim, plan->lcc_radius, fixed, warped, mask,
+            reinterpret_cast<double*>(w + plan->L.lcc_s), reinterpret_cast<float*>(w + plan->L.lcc_a),
+            reinterpret_cast<double*>(w + plan->L.lcc_part),
+            reinterpret_cast<double*>(w + plan->L.lcc_scal),
+            reinterpret_cast<uint32_t*>(w + plan->L.flags) + pair, value, (hipStream_t)stream);
+        return e == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+    }
     hipError_t e = launch_similarity(
         fixed, warped, mask, plan->pd[pair].nvox, plan->sim,
         reinterpret_cast<double*>(w + plan->L.generic), kGenericSlots, value,
@@ -683,7 +869,7 @@ air_status air_regulariser(const air_plan* plan, int32_t pair, const float* thet
     unsigned char* w = static_cast<unsigned char*>(ws);
     const PairDesc& hp = plan->pd[pair];
     hipError_t e;
-    if (plan->diffeo > 0) {
+    if (plan->field_route()) {
         e = run_diffeo(plan, T, ws, nullptr, nullptr, theta, value, grad, true,
                        (hipStream_t)stream);
     } else if (plan->reg != AIR_REG_DIFFUSION) {
@@ -732,7 +918,7 @@ air_status air_objective_and_grad_batched(const air_plan* plan, const float* con
                                           float* values, float* const* grads, void* ws,
                                           size_t ws_bytes, void* stream) {
     if (!plan || !fixed || !moving || !theta || !values || !grads) return AIR_ERR_INVALID_ARG;
-    if (plan->diffeo > 0 || plan->reg != AIR_REG_DIFFUSION) return AIR_ERR_UNSUPPORTED;
+    if (plan->field_route() || plan->reg != AIR_REG_DIFFUSION) return AIR_ERR_UNSUPPORTED;
     if (((uintptr_t)fixed | (uintptr_t)moving | (uintptr_t)theta | (uintptr_t)grads) & 7u)
         return AIR_ERR_ALIGN;
     if (((uintptr_t)values & 3u) != 0) return AIR_ERR_ALIGN;

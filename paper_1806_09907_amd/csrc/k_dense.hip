@@ -42,59 +42,6 @@ __device__ inline DenseTile dense_tile(const PairDesc& P, int blk, int zc, int d
     return T;
 }
 
-// Zero-padded multilinear sample at p (voxel units) with derivative; also
-// reports whether p lies inside the volume. Used where speed is secondary.
-template <int DIM>
-__device__ inline float sample_general(const float* __restrict__ M, const int* n,
-                                       const float* p, bool* inside, float* dW) {
-    float f[3];
-    int j[3];
-    bool in = true;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        const float pa = fminf(fmaxf(p[a], -1e9f), 1e9f);
-        if (!(p[a] >= 0.f && p[a] <= (float)(n[a] - 1))) in = false;
-        const float fl = floorf(pa);
-        j[a] = (int)fl;
-        f[a] = pa - fl;
-    }
-    *inside = in;
-    float W = 0.f;
-    float d[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int c = 0; c < (1 << DIM); ++c) {
-        int q[3] = {0, 0, 0};
-        bool ok = true;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            q[a] = j[a] + ((c >> a) & 1);
-            if (q[a] < 0 || q[a] > n[a] - 1) ok = false;
-        }
-        float val = 0.f;
-        if (ok) {
-            long long idx = q[0] + (long long)n[0] * (q[1] + (DIM == 3 ? (long long)n[1] * q[2] : 0));
-            val = M[idx];
-        }
-        float w = 1.f;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) w *= ((c >> a) & 1) ? f[a] : 1.f - f[a];
-        W += w * val;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            float wa = ((c >> a) & 1) ? 1.f : -1.f;
-#pragma unroll
-            for (int b = 0; b < DIM; ++b)
-                if (b != a) wa *= ((c >> b) & 1) ? f[b] : 1.f - f[b];
-            d[a] += wa * val;
-        }
-    }
-    if (dW) {
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) dW[a] = d[a];
-    }
-    return W;
-}
-
 // Trilinear sample of M at p (voxel units) with its gradient, branch-free:
 // the point is clamped into the volume so every load is in range, and m = 1
 // iff it lay inside [0, n-1]^3. At p_a = n_a - 1 the cell is

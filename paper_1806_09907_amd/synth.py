@@ -202,6 +202,18 @@ def random_theta(n_xyz: Sequence[int], spacing: Sequence[int], std_vox: float,
     return control_field(tuple(n_xyz), tuple(spacing), std_vox, rng).astype(np.float32)
 
 
+def random_controls(n_xyz: Sequence[int], nc_xyz: Sequence[int], std_vox: float,
+                    seed: int) -> np.ndarray:
+    """Random control values on a grid of nc_xyz controls (given by the
+    caller), N(0, std_vox) voxels in normalised units, [d][nc_z][nc_y][nc_x]."""
+    rng = np.random.default_rng(seed)
+    d = len(n_xyz)
+    theta = rng.normal(0.0, std_vox, size=(d,) + tuple(reversed(tuple(nc_xyz))))
+    for a in range(d):
+        theta[a] *= 2.0 / (n_xyz[a] - 1)
+    return theta.astype(np.float32)
+
+
 def random_dense(n_xyz: Sequence[int], std_vox: float, seed: int) -> np.ndarray:
     """A random dense displacement [d][nz][ny][nx] in normalised units."""
     rng = np.random.default_rng(seed)

@@ -112,3 +112,54 @@ def test_strerror_names_every_status():
     L = _lib.lib()
     for s in range(9):
         assert L.air_strerror(s) not in (None, b"unknown status")
+
+
+@pytest.mark.parametrize("n,sp,sig", [((20, 18, 16), (4, 4, 4), (8.0, 6.5, 9.0)),
+                                      ((23, 17), (5, 3), (10.0, 4.5)),
+                                      ((128, 128, 128), (8, 8, 8), (16.0, 16.0, 16.0)),
+                                      ((9, 11, 7), (2, 3, 1), (2.5, 3.0, 1.5))])
+def test_wendland_plan_parameter_count(n, sp, sig):
+    """The library's control count is the one the Python problem states (and
+    that the oracle's pins check against a brute-force enumeration)."""
+    p = Problem(n=n, transform=2, spacing=sp, sigma=sig, similarity=SIM_MSE)
+    plan = Plan(p)
+    count = 1
+    for s in p.param_shape():
+        count *= s
+    assert plan.param_count(0) == count
+    assert plan.workspace_bytes > 0
+
+
+@pytest.mark.parametrize("sig,code", [((0.0, 8.0, 8.0), 1), ((-1.0, 8.0, 8.0), 1),
+                                      ((float("nan"), 8.0, 8.0), 1),
+                                      ((float("inf"), 8.0, 8.0), 1)])
+def test_wendland_rejects_bad_sigma(sig, code):
+    with pytest.raises(_lib.AirError) as e:
+        Plan(P(transform=2, sigma=sig))
+    assert e.value.status == code
+
+
+def test_wendland_rejects_oversized_table_and_batches():
+    # 64^3 phases, 2 controls per cell and axis: the transposed table has
+    # 2^18 x 64 entries, beyond the 2^21 limit
+    with pytest.raises(_lib.AirError) as e:
+        Plan(P(n=(200, 200, 200), transform=2, spacing=(64, 64, 64), sigma=(64.0, 64.0, 64.0)))
+    assert e.value.status == 5
+    w = P(transform=2, sigma=(8.0, 8.0, 8.0))
+    with pytest.raises(_lib.AirError) as e:
+        Plan([w, w])
+    assert e.value.status == 5
+
+
+@pytest.mark.parametrize("radius,code", [(0, 1), (9, 1), (-1, 1)])
+def test_lcc_rejects_bad_radius(radius, code):
+    with pytest.raises(_lib.AirError) as e:
+        Plan(P(similarity=2, lcc_radius=radius))
+    assert e.value.status == code
+
+
+def test_lcc_plans_hold_one_pair():
+    Plan(P(similarity=2, lcc_radius=8))
+    with pytest.raises(_lib.AirError) as e:
+        Plan([P(similarity=2), P(similarity=2)])
+    assert e.value.status == 5
