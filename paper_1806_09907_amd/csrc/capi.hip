@@ -192,20 +192,12 @@ static void wendland_axis(int n, int sp, double sig, int* nc, int* m, int* K, in
 
 static int round64(long long x) { return (int)((x + 63) / 64 * 64); }
 
-// W[qq][r] and W^T of a Wendland pair (see k_wendland.hip); false if too big.
-static bool wendland_tables(const air_problem& p, PairDesc& D, std::vector<float>& consts) {
-    const int d = p.dim;
-    int m[3] = {0, 0, 0};
-    for (int a = 0; a < d; ++a) {
-        int nc, K, ncell;
-        wendland_axis(p.n[a], p.spacing[a], (double)p.sigma[a], &nc, &m[a], &K, &ncell);
-        D.wK[a] = K;
-        D.wncell[a] = ncell;
-    }
-    for (int a = d; a < 3; ++a) {
-        D.wK[a] = 1;
-        D.wncell[a] = 1;
-    }
+// The cell-contraction tables of an interpolating basis whose lattice is
+// aligned with voxel cells (see k_wendland.hip): wK and wncell must be set;
+// weight(qi, ri) is the weight between phase ri of a cell and its control
+// qi. Writes W[qq][r] and W^T to the constants; false if they are too big.
+template <typename Weight>
+static bool cell_tables(int d, PairDesc& D, std::vector<float>& consts, Weight weight) {
     const int cw = wendland_cells_per_wave();
     D.wncp[0] = std::max(D.nc[0], cdiv(D.wncell[0], cw) * cw + D.wK[0] - 1);
     for (int a = 1; a < 3; ++a) D.wncp[a] = std::max(D.nc[a], D.wncell[a] + D.wK[a] - 1);
@@ -213,8 +205,6 @@ static bool wendland_tables(const air_problem& p, PairDesc& D, std::vector<float
     const long long Q = (long long)D.wK[0] * D.wK[1] * D.wK[2];
     const long long Ppad = round64(P3), Qpad = round64(Q);
     if (Q * Ppad > kMaxWendTable || Ppad * Qpad > kMaxWendTable) return false;
-    D.wpad[0] = (int)Ppad;
-    D.wpad[1] = (int)Qpad;
     std::vector<float> W((size_t)(Q * Ppad), 0.f);
     for (long long qq = 0; qq < Q; ++qq) {
         const int qi[3] = {(int)(qq % D.wK[0]), (int)((qq / D.wK[0]) % D.wK[1]),
@@ -222,15 +212,12 @@ static bool wendland_tables(const air_problem& p, PairDesc& D, std::vector<float
         for (long long r = 0; r < P3; ++r) {
             const int ri[3] = {(int)(r % D.sp[0]), (int)((r / D.sp[0]) % D.sp[1]),
                                (int)(r / ((long long)D.sp[0] * D.sp[1]))};
-            double r2 = 0.0;
-            for (int a = 0; a < d; ++a) {
-                const double o = (double)ri[a] - (double)(qi[a] - m[a]) * D.sp[a];
-                const double q = o / (double)p.sigma[a];
-                r2 += q * q;
-            }
-            W[(size_t)(qq * Ppad + r)] = (float)wendland_psi(sqrt(r2));
+            W[(size_t)(qq * Ppad + r)] = (float)weight(qi, ri);
         }
     }
+    (void)d;
+    D.wpad[0] = (int)Ppad;
+    D.wpad[1] = (int)Qpad;
     while (consts.size() % 4) consts.push_back(0.f);
     D.wend_off[0] = (int)consts.size();
     consts.insert(consts.end(), W.begin(), W.end());
@@ -240,6 +227,54 @@ static bool wendland_tables(const air_problem& p, PairDesc& D, std::vector<float
     for (long long qq = 0; qq < Q; ++qq)
         for (long long r = 0; r < Ppad; ++r) WT[r * Qpad + qq] = W[(size_t)(qq * Ppad + r)];
     return true;
+}
+
+// Wendland: weight psi(||(r - (qq - m) sp) / sigma||).
+static bool wendland_tables(const air_problem& p, PairDesc& D, std::vector<float>& consts) {
+    const int d = p.dim;
+    int m[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+        D.wK[a] = 1;
+        D.wncell[a] = 1;
+    }
+    for (int a = 0; a < d; ++a) {
+        int nc, K, ncell;
+        wendland_axis(p.n[a], p.spacing[a], (double)p.sigma[a], &nc, &m[a], &K, &ncell);
+        D.wK[a] = K;
+        D.wncell[a] = ncell;
+    }
+    return cell_tables(d, D, consts, [&](const int* qi, const int* ri) {
+        double r2 = 0.0;
+        for (int a = 0; a < d; ++a) {
+            const double o = (double)ri[a] - (double)(qi[a] - m[a]) * D.sp[a];
+            const double q = o / (double)p.sigma[a];
+            r2 += q * q;
+        }
+        return wendland_psi(sqrt(r2));
+    });
+}
+
+// Cubic B-spline: a cell sees its controls c .. c + 3 (control j at (j - 1)
+// sp); the weight is the product over axes of beta3 at the phase.
+static bool bspline_cell_tables(int d, PairDesc& D, std::vector<float>& consts) {
+    for (int a = 0; a < 3; ++a) {
+        D.wK[a] = a < d ? 4 : 1;
+        D.wncell[a] = a < d ? cdiv(D.n[a], D.sp[a]) : 1;
+    }
+    auto beta = [](int sp, int r, int k) {
+        const double t = (double)r / sp;
+        switch (k) {
+            case 0: return (1 - t) * (1 - t) * (1 - t) / 6.0;
+            case 1: return (3 * t * t * t - 6 * t * t + 4) / 6.0;
+            case 2: return (-3 * t * t * t + 3 * t * t + 3 * t + 1) / 6.0;
+            default: return t * t * t / 6.0;
+        }
+    };
+    return cell_tables(d, D, consts, [&](const int* qi, const int* ri) {
+        double w = 1.0;
+        for (int a = 0; a < d; ++a) w *= beta(D.sp[a], ri[a], qi[a]);
+        return w;
+    });
 }
 
 static air_status validate_problem(const air_problem& p) {
@@ -390,6 +425,11 @@ static air_status build_tables(air_plan* P) {
             lds_r = std::max(lds_r, 8 * sizeof(double) * (kBlock / 64) + 4 * reg);
             stats_n = tiles;
         }
+        // B-spline fields expanded to the voxel grid (exponential, LCC, TV) use
+        // the cell contraction when its table fits (wpad[0] == 0: it does not)
+        if (!wend) D.wpad[0] = D.wpad[1] = 0;
+        if (bs && (P->field_route() || P->reg != AIR_REG_DIFFUSION))
+            (void)bspline_cell_tables(d, D, P->consts);
         // dense passes: dense models, and the objective at exp(v) or with LCC
         if (!bs || P->field_route()) {
             const int nbx = cdiv(D.n[0], kDenseTX), nby = cdiv(D.n[1], kDenseTY);
@@ -427,10 +467,10 @@ static air_status build_tables(air_plan* P) {
         L.gfield = off;  off = align256(off + 2 * dN * 4);
         size_t t1 = bs ? (size_t)d * D.n[2] * D.n[1] * D.nc[0] : 1;
         size_t t2 = bs ? (size_t)d * D.n[2] * D.nc[1] * D.nc[0] : 1;
-        if (wend) {
-            t1 = (size_t)d * D.wncp[0] * D.wncp[1] * D.wncp[2];
-            t2 = (size_t)d * D.wncell[0] * D.wncell[1] * D.wncell[2] * D.wK[0] * D.wK[1] *
-                 D.wK[2];
+        if (D.wpad[0] > 0) {  // cell contraction: padded controls, per-cell sums
+            t1 = std::max(t1, (size_t)d * D.wncp[0] * D.wncp[1] * D.wncp[2]);
+            t2 = std::max(t2, (size_t)d * D.wncell[0] * D.wncell[1] * D.wncell[2] * D.wK[0] *
+                                  D.wK[1] * D.wK[2]);
         }
         L.bsadj1 = off;  off = align256(off + t1 * 4);
         L.bsadj2 = off;  off = align256(off + t2 * 4);
@@ -522,7 +562,7 @@ static LaunchCtx base_ctx(const air_plan* P, const DeviceTables* T, void* ws) {
 static hipError_t expand_field(const air_plan* P, const DeviceTables* T, unsigned char* w,
                                const float* theta, float scale, float* out, hipStream_t s) {
     const PairDesc& hp = P->pd[0];
-    if (P->transform == AIR_TF_WENDLAND)
+    if (P->transform != AIR_TF_DENSE && hp.wpad[0] > 0)
         return launch_wendland_expand(hp, T->consts, P->dim, theta, scale,
                                       reinterpret_cast<float*>(w + P->L.bsadj1), out, s);
     return launch_velocity(hp, T->consts, P->transform, P->dim, theta, scale, out, s);
@@ -533,7 +573,7 @@ static hipError_t field_adjoint(const air_plan* P, const DeviceTables* T, unsign
                                 const float* g, float scale, float* grad, bool accumulate,
                                 hipStream_t s) {
     const PairDesc& hp = P->pd[0];
-    if (P->transform == AIR_TF_WENDLAND)
+    if (P->transform != AIR_TF_DENSE && hp.wpad[0] > 0)
         return launch_wendland_adjoint(hp, T->consts, P->dim, g, scale,
                                        reinterpret_cast<float*>(w + P->L.bsadj2), grad,
                                        accumulate, s);
@@ -639,13 +679,11 @@ static hipError_t run_tv(const air_plan* P, const DeviceTables* T, void* ws, con
     }
     float* U = reinterpret_cast<float*>(w + P->L.fields);
     float* G = reinterpret_cast<float*>(w + P->L.gfield);
-    hipError_t e = launch_velocity(hp, T->consts, AIR_TF_BSPLINE3, P->dim, theta, 1.f, U, s);
+    hipError_t e = expand_field(P, T, w, theta, 1.f, U, s);
     if (e == hipSuccess)
         e = launch_tv(hp, P->dim, P->reg, U, lam, G, false, tvp, lam, value, !reg_only, s);
     if (e != hipSuccess || !grad) return e;
-    return launch_velocity_adjoint(hp, T->consts, AIR_TF_BSPLINE3, P->dim, G, 1.f,
-                                   reinterpret_cast<float*>(w + P->L.bsadj1),
-                                   reinterpret_cast<float*>(w + P->L.bsadj2), grad, s, !reg_only);
+    return field_adjoint(P, T, w, G, 1.f, grad, !reg_only, s);
 }
 
 static air_status run_objective(const air_plan* cP, LaunchCtx& C, hipStream_t s) {
