@@ -46,7 +46,7 @@ struct PairDesc {
     int wK[3];           // controls a cell sees per axis
     int wncp[3];         // padded control grid of the expansion (zeros beyond nc)
     int wpad[2];         // phases prod(sp) and prod(wK), rounded up to 64
-    int wend_off[2];     // float offsets of W [K^d][wpad0] and W^T [wpad0][wpad1]
+    int wend_off[2];     // float offsets of W [wpad1][wpad0] and W^T [wpad0][wpad1]
     int wpad_;
 };
 

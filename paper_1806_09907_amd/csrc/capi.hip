@@ -204,8 +204,8 @@ static bool cell_tables(int d, PairDesc& D, std::vector<float>& consts, Weight w
     const long long P3 = (long long)D.sp[0] * D.sp[1] * D.sp[2];
     const long long Q = (long long)D.wK[0] * D.wK[1] * D.wK[2];
     const long long Ppad = round64(P3), Qpad = round64(Q);
-    if (Q * Ppad > kMaxWendTable || Ppad * Qpad > kMaxWendTable) return false;
-    std::vector<float> W((size_t)(Q * Ppad), 0.f);
+    if (Ppad * Qpad > kMaxWendTable) return false;
+    std::vector<float> W((size_t)(Qpad * Ppad), 0.f);  // rows Q .. Qpad - 1 stay 0
     for (long long qq = 0; qq < Q; ++qq) {
         const int qi[3] = {(int)(qq % D.wK[0]), (int)((qq / D.wK[0]) % D.wK[1]),
                            (int)(qq / ((long long)D.wK[0] * D.wK[1]))};

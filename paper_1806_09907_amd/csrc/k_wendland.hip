@@ -18,7 +18,7 @@ namespace air {
 
 namespace {
 
-constexpr int kWCells = 8;   // cells along x per wave (both contractions)
+constexpr int kWCells = 16;  // cells along x per wave (one MFMA tile; both contractions)
 constexpr int kWaves = kBlock / 64;
 
 // theta -> zero-padded copy [d][ncp_z][ncp_y][ncp_x], scaled.
@@ -43,13 +43,42 @@ k_wend_pad(const PairDesc P, const float* __restrict__ theta, float scale,
     }
 }
 
-// u(c, r) = sum_qq W[qq][r] thp(c + qq). One wave owns kWCells cells along x
-// of one (cy, cz) row and 64 consecutive phases; theta is read wave-uniformly.
+// Per-axis coordinates (x fastest) of a linear index i in an nx x ny x .
+// grid, and their update for i += 4 (the step of every lane in the loops
+// below), so that no loop divides.
+struct Idx3 {
+    int x, y, z;
+};
+__device__ inline Idx3 idx3(int i, int nx, int ny) {
+    return Idx3{i % nx, (i / nx) % ny, i / (nx * ny)};
+}
+__device__ inline void idx3_add4(Idx3& c, int nx, int ny) {
+    c.x += 4;
+    while (c.x >= nx) {
+        c.x -= nx;
+        ++c.y;
+    }
+    while (c.y >= ny) {
+        c.y -= ny;
+        ++c.z;
+    }
+}
+
+// Both contractions run on v_mfma_f32_16x16x4f32 (full FP32). Lane l holds
+// A[l % 16][l / 16] of the 16x4 A tile, B[l / 16][l % 16] of the 4x16 B tile
+// and D[4 (l / 16) + v][l % 16], v = 0..3, of the 16x16 result.
+__device__ inline v4f mfma4(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// u(c, r) = sum_qq W[qq][r] thp(c + qq): per wave M = 64 phases (4 tiles),
+// N = kWCells cells (one tile per component), K = the controls qq.
 template <int DIM>
 __global__ void __launch_bounds__(kBlock)
 k_wend_expand(const PairDesc P, const float* __restrict__ W, const float* __restrict__ thp,
               float* __restrict__ u) {
     const int lane = threadIdx.x & 63;
+    const int i16 = lane & 15, k4 = lane >> 4;
     const int gw = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
     const int npc = P.wpad[0] / 64;             // phase chunks
     const int ngx = cdiv(P.wncell[0], kWCells);
@@ -60,58 +89,81 @@ k_wend_expand(const PairDesc P, const float* __restrict__ W, const float* __rest
     const int cx0 = (g % ngx) * kWCells;
     const int cy = (g / ngx) % P.wncell[1];
     const int cz = g / (ngx * P.wncell[1]);
-    const int r = pc * 64 + lane;
     const int Ppad = P.wpad[0];
-    const int Kx = P.wK[0], Ky = P.wK[1], Kz = P.wK[2];
+    const int Q = P.wK[0] * P.wK[1] * P.wK[2];
     const long long sx = P.wncp[0], sy = (long long)P.wncp[0] * P.wncp[1];
     const long long NCp = sy * P.wncp[2];
-    float acc[kWCells][DIM];
+    v4f acc[4][DIM];
 #pragma unroll
-    for (int t = 0; t < kWCells; ++t)
+    for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) acc[t][c] = 0.f;
-    int qq = 0;
-    for (int qz = 0; qz < Kz; ++qz)
-        for (int qy = 0; qy < Ky; ++qy) {
-            const float* row = thp + (cz + qz) * sy + (cy + qy) * sx + cx0;
-            for (int qx = 0; qx < Kx; ++qx, ++qq) {
-                const float w = W[(long long)qq * Ppad + r];
+        for (int c = 0; c < DIM; ++c) acc[m][c] = v4f{0.f, 0.f, 0.f, 0.f};
+    const float* Wr = W + pc * 64 + i16;
+    // operands of the K step whose control for this lane is q (coordinates
+    // qc); branch-free: an invalid control reads a valid address, then 0
+    // (the validity select is applied when the operands are used, so the
+    // loads stay in flight)
+    auto load = [&](int q, const Idx3& qc, float* a, float* b, bool& ok) {
+        const int qw = min(q, P.wpad[1] - 1);  // rows >= Q are 0; past the end: clamped
 #pragma unroll
-                for (int c = 0; c < DIM; ++c) {
-                    const float* th = row + c * NCp + qx;
+        for (int m = 0; m < 4; ++m) a[m] = Wr[(long long)qw * Ppad + m * 16];
+        ok = q < Q;
+        const float* th = ok ? thp + (cz + qc.z) * sy + (cy + qc.y) * sx + cx0 + i16 + qc.x : thp;
 #pragma unroll
-                    for (int t = 0; t < kWCells; ++t) acc[t][c] = fmaf(w, th[t], acc[t][c]);
-                }
-            }
-        }
-    const int P3 = P.sp[0] * P.sp[1] * P.sp[2];
-    if (r >= P3) return;
-    const int rx = r % P.sp[0], ry = (r / P.sp[0]) % P.sp[1], rz = r / (P.sp[0] * P.sp[1]);
-    const int y = cy * P.sp[1] + ry, z = cz * P.sp[2] + rz;
-    if (y >= P.n[1] || z >= P.n[2]) return;
-    const long long N = P.nvox;
-    const long long rowv = ((long long)z * P.n[1] + y) * P.n[0];
+        for (int c = 0; c < DIM; ++c) b[c] = th[c * NCp];
+    };
+    auto step = [&](const float* a, const float* b, bool ok) {
 #pragma unroll
-    for (int t = 0; t < kWCells; ++t) {
-        const int x = (cx0 + t) * P.sp[0] + rx;
-        if (x < P.n[0]) {
+        for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) u[c * N + rowv + x] = acc[t][c];
-        }
+            for (int c = 0; c < DIM; ++c) acc[m][c] = mfma4(a[m], ok ? b[c] : 0.f, acc[m][c]);
+    };
+    // two operand sets in turn: the loads of step k + 1 are in flight during
+    // the MFMAs of step k
+    const int nst = (Q + 3) / 4;
+    Idx3 qn = idx3(k4, P.wK[0], P.wK[1]);
+    float a0[4], b0[DIM], a1[4], b1[DIM];
+    bool ok0 = false, ok1 = false;
+    load(k4, qn, a0, b0, ok0);
+    for (int st = 0; st < nst; st += 2) {
+        idx3_add4(qn, P.wK[0], P.wK[1]);
+        load((st + 1) * 4 + k4, qn, a1, b1, ok1);   // unconditional: no join for the
+        step(a0, b0, ok0);                          // wait counters to merge
+        if (st + 1 >= nst) break;
+        idx3_add4(qn, P.wK[0], P.wK[1]);
+        load((st + 2) * 4 + k4, qn, a0, b0, ok0);
+        step(a1, b1, ok1);
     }
+    const int P3 = P.sp[0] * P.sp[1] * P.sp[2];
+    const long long N = P.nvox;
+    const int x0 = (cx0 + i16) * P.sp[0];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = pc * 64 + m * 16 + 4 * k4 + v;
+            if (r >= P3) continue;
+            const Idx3 rc = idx3(r, P.sp[0], P.sp[1]);
+            const int x = x0 + rc.x, y = cy * P.sp[1] + rc.y, z = cz * P.sp[2] + rc.z;
+            if (x >= P.n[0] || y >= P.n[1] || z >= P.n[2]) continue;
+            const long long vox = ((long long)z * P.n[1] + y) * P.n[0] + x;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) u[c * N + vox] = acc[m][c][v];
+        }
 }
 
-// H(c, qq) = sum_r W[qq][r] g(c, r) for kWCells cells along x and 64 values
-// of qq (one lane each). The phases are split over the block's waves in
-// chunks of 64, each chunk of g staged in LDS ([r][cell][component]) and read
-// wave-uniformly; the four partial sums are added in LDS in a fixed order.
+// H(qq, c) = sum_r W[qq][r] g(c, r) for kWCells cells along x and 64 values
+// of qq: per wave M = 64 qq (4 tiles), N = kWCells cells (one tile per
+// component), K = the phases, split over the block's waves; the waves'
+// results are added in LDS in a fixed order.
 template <int DIM>
 __global__ void __launch_bounds__(kBlock)
 k_wend_cells_t(const PairDesc P, const float* __restrict__ WT, const float* __restrict__ g,
                float* __restrict__ H) {
-    constexpr int NV = kWCells * DIM;
-    __shared__ float stage[kWaves][64 * NV];
+    constexpr int NA = 4 * DIM * 4;   // accumulator floats per lane
+    __shared__ float red[kWaves * 64 * NA];
     const int lane = threadIdx.x & 63;
+    const int i16 = lane & 15, k4 = lane >> 4;
     const int w = threadIdx.x >> 6;
     const int nqc = P.wpad[1] / 64;
     const int ngx = cdiv(P.wncell[0], kWCells);
@@ -120,73 +172,74 @@ k_wend_cells_t(const PairDesc P, const float* __restrict__ WT, const float* __re
     const int cx0 = (grp % ngx) * kWCells;
     const int cy = (grp / ngx) % P.wncell[1];
     const int cz = grp / (ngx * P.wncell[1]);
-    const int q = qc * 64 + lane;
     const int Qpad = P.wpad[1];
     const int P3 = P.sp[0] * P.sp[1] * P.sp[2];
-    const int nrc = P.wpad[0] / 64;
+    const int nstep = P.wpad[0] / 4;
+    const int s0 = w * nstep / kWaves, s1 = (w + 1) * nstep / kWaves;
     const long long N = P.nvox;
-    float acc[NV];
+    const int cxl = cx0 + i16;                 // this lane's cell of the B tile
+    const bool cell_ok = cxl < P.wncell[0];
+    v4f acc[4][DIM];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = 0.f;
-    float* st = stage[w];
-    for (int it = 0; it < cdiv(nrc, kWaves); ++it) {
-        const int rc = it * kWaves + w;
-        // stage g at phase r = rc * 64 + lane of every cell (0 outside the grid)
-        {
-            const int r = rc * 64 + lane;
-            float v[NV];
+    for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int k = 0; k < NV; ++k) v[k] = 0.f;
-            if (rc < nrc && r < P3) {
-                const int rx = r % P.sp[0], ry = (r / P.sp[0]) % P.sp[1],
-                          rz = r / (P.sp[0] * P.sp[1]);
-                const int y = cy * P.sp[1] + ry, z = cz * P.sp[2] + rz;
-                if (y < P.n[1] && z < P.n[2]) {
-                    const long long rowv = ((long long)z * P.n[1] + y) * P.n[0];
+        for (int c = 0; c < DIM; ++c) acc[m][c] = v4f{0.f, 0.f, 0.f, 0.f};
+    const float* Wq = WT + qc * 64 + i16;
+    // operands of the K step whose phase for this lane is r (coordinates rc);
+    // branch-free: a phase outside the grid reads voxel 0, then 0
+    // (the validity select is applied when the operands are used, so the
+    // loads stay in flight)
+    auto load = [&](int r, const Idx3& rc, float* a, float* b, bool& ok) {
+        const int rw = min(r, P.wpad[0] - 1);  // rows >= P3 are 0; past the end: clamped
 #pragma unroll
-                    for (int t = 0; t < kWCells; ++t) {
-                        const int x = (cx0 + t) * P.sp[0] + rx;
-                        if (x < P.n[0]) {
+        for (int m = 0; m < 4; ++m) a[m] = Wq[(long long)rw * Qpad + m * 16];
+        const int x = cxl * P.sp[0] + rc.x, y = cy * P.sp[1] + rc.y, z = cz * P.sp[2] + rc.z;
+        ok = r < P3 && cell_ok && x < P.n[0] && y < P.n[1] && z < P.n[2];
+        const long long vox = ok ? ((long long)z * P.n[1] + y) * P.n[0] + x : 0;
 #pragma unroll
-                            for (int c = 0; c < DIM; ++c) v[t * DIM + c] = g[c * N + rowv + x];
-                        }
-                    }
-                }
-            }
+        for (int c = 0; c < DIM; ++c) b[c] = g[c * N + vox];
+    };
+    auto step = [&](const float* a, const float* b, bool ok) {
 #pragma unroll
-            for (int k = 0; k < NV; ++k) st[lane * NV + k] = v[k];
-        }
-        __syncthreads();
-        if (rc < nrc) {
-            const float* wt = WT + (long long)rc * 64 * Qpad + q;
-            for (int rl = 0; rl < 64; ++rl) {
-                const float wv = wt[(long long)rl * Qpad];
-                const float* sv = st + rl * NV;
+        for (int m = 0; m < 4; ++m)
 #pragma unroll
-                for (int k = 0; k < NV; ++k) acc[k] = fmaf(wv, sv[k], acc[k]);
-            }
-        }
-        __syncthreads();
+            for (int c = 0; c < DIM; ++c) acc[m][c] = mfma4(a[m], ok ? b[c] : 0.f, acc[m][c]);
+    };
+    Idx3 rn = idx3(s0 * 4 + k4, P.sp[0], P.sp[1]);
+    float a0[4], b0[DIM], a1[4], b1[DIM];
+    bool ok0 = false, ok1 = false;
+    if (s0 < s1) load(s0 * 4 + k4, rn, a0, b0, ok0);
+    for (int st = s0; st < s1; st += 2) {
+        idx3_add4(rn, P.sp[0], P.sp[1]);
+        load((st + 1) * 4 + k4, rn, a1, b1, ok1);   // unconditional: no join for the
+        step(a0, b0, ok0);                          // wait counters to merge
+        if (st + 1 >= s1) break;
+        idx3_add4(rn, P.sp[0], P.sp[1]);
+        load((st + 2) * 4 + k4, rn, a0, b0, ok0);
+        step(a1, b1, ok1);
     }
-    // reduce the waves' partial sums: red[w][lane][k]
-    float* red = &stage[0][0];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) red[(w * 64 + lane) * NV + k] = acc[k];
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) red[(w * 64 + lane) * NA + (m * DIM + c) * 4 + v] = acc[m][c][v];
     __syncthreads();
     const int Q = P.wK[0] * P.wK[1] * P.wK[2];
     const long long ncells = (long long)P.wncell[0] * P.wncell[1] * P.wncell[2];
     const long long row = ((long long)cz * P.wncell[1] + cy) * P.wncell[0] + cx0;
     // consecutive threads take consecutive cells of one (component, qq) row
-    for (int i = threadIdx.x; i < 64 * NV; i += kBlock) {
-        const int t = i % kWCells;
-        const int c = (i / kWCells) % DIM;
-        const int ql = i / (kWCells * DIM);
-        const int k = t * DIM + c;
-        float s = 0.f;
+    for (int o = threadIdx.x; o < 64 * kWCells * DIM; o += kBlock) {
+        const int t = o % kWCells;
+        const int c = (o / kWCells) % DIM;
+        const int ql = o / (kWCells * DIM);
+        const int m = ql / 16, k4o = (ql % 16) / 4, v = ql % 4;
+        const int src = (k4o * 16 + t) * NA + (m * DIM + c) * 4 + v;
+        float sum = 0.f;
 #pragma unroll
-        for (int ww = 0; ww < kWaves; ++ww) s += red[(ww * 64 + ql) * NV + k];
+        for (int ww = 0; ww < kWaves; ++ww) sum += red[ww * 64 * NA + src];
         const int qv = qc * 64 + ql;
-        if (qv < Q && cx0 + t < P.wncell[0]) H[((long long)c * Q + qv) * ncells + row + t] = s;
+        if (qv < Q && cx0 + t < P.wncell[0]) H[((long long)c * Q + qv) * ncells + row + t] = sum;
     }
 }
 
@@ -213,10 +266,9 @@ k_wend_gather(const PairDesc P, const float* __restrict__ H, float scale, int ac
         const int jy = (int)((j / P.nc[0]) % P.nc[1]);
         const int jz = (int)(j / ((long long)P.nc[0] * P.nc[1]));
         const float* Hc = H + (long long)c * Q * ncells;
-        for (int qq = w; qq < Q; qq += kWaves) {
-            const int qx = qq % P.wK[0], qy = (qq / P.wK[0]) % P.wK[1],
-                      qz = qq / (P.wK[0] * P.wK[1]);
-            const int cx = jx - qx, cy = jy - qy, cz = jz - qz;
+        Idx3 qi = idx3(w, P.wK[0], P.wK[1]);
+        for (int qq = w; qq < Q; qq += kWaves, idx3_add4(qi, P.wK[0], P.wK[1])) {
+            const int cx = jx - qi.x, cy = jy - qi.y, cz = jz - qi.z;
             if (cx < 0 || cx >= P.wncell[0] || cy < 0 || cy >= P.wncell[1] || cz < 0 ||
                 cz >= P.wncell[2])
                 continue;
