@@ -46,6 +46,7 @@ hipError_t launch_wendland_adjoint(const PairDesc& P, const float* consts_dev, i
                                    const float* g, float scale, float* H, float* grad,
                                    bool accumulate, hipStream_t s);
 int wendland_cells_per_wave();
+int wendland_h_parts();
 int lcc_partials(const PairDesc& P);
 size_t lcc_lds_bytes(int r);
 hipError_t launch_lcc(const PairDesc& P, int dim, int r, const float* F, const float* M,
@@ -469,8 +470,8 @@ static air_status build_tables(air_plan* P) {
         size_t t2 = bs ? (size_t)d * D.n[2] * D.nc[1] * D.nc[0] : 1;
         if (D.wpad[0] > 0) {  // cell contraction: padded controls, per-cell sums
             t1 = std::max(t1, (size_t)d * D.wncp[0] * D.wncp[1] * D.wncp[2]);
-            t2 = std::max(t2, (size_t)d * D.wncell[0] * D.wncell[1] * D.wncell[2] * D.wK[0] *
-                                  D.wK[1] * D.wK[2]);
+            t2 = std::max(t2, (size_t)wendland_h_parts() * d * D.wncell[0] * D.wncell[1] *
+                                  D.wncell[2] * D.wK[0] * D.wK[1] * D.wK[2]);
         }
         L.bsadj1 = off;  off = align256(off + t1 * 4);
         L.bsadj2 = off;  off = align256(off + t2 * 4);

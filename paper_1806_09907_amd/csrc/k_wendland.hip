@@ -9,7 +9,8 @@
 // every cell. Both directions are therefore per-cell contractions with one
 // fixed table, built once per plan on the host:
 //   expand:    u(c, r) = sum_qq W[qq][r] theta(c + qq)
-//   transpose: H(qq, c) = sum_r W[qq][r] g(c, r);
+//   transpose: H(qq, c) = sum_r W[qq][r] g(c, r) (in two partial sums over
+//              halves of the phases);
 //              out(j)   = sum_qq H(j - qq, qq)   over cells inside the grid.
 // No kernel value is evaluated on the device.
 #include "device_common.h"
@@ -20,6 +21,7 @@ namespace {
 
 constexpr int kWCells = 16;  // cells along x per wave (one MFMA tile; both contractions)
 constexpr int kWaves = kBlock / 64;
+constexpr int kTSplit = 2;   // blocks sharing one cell group's phases in the transpose
 
 // theta -> zero-padded copy [d][ncp_z][ncp_y][ncp_x], scaled.
 template <int DIM>
@@ -51,6 +53,17 @@ struct Idx3 {
 };
 __device__ inline Idx3 idx3(int i, int nx, int ny) {
     return Idx3{i % nx, (i / nx) % ny, i / (nx * ny)};
+}
+__device__ inline void idx3_add(Idx3& c, int step, int nx, int ny) {
+    c.x += step;
+    while (c.x >= nx) {
+        c.x -= nx;
+        ++c.y;
+    }
+    while (c.y >= ny) {
+        c.y -= ny;
+        ++c.z;
+    }
 }
 __device__ inline void idx3_add4(Idx3& c, int nx, int ny) {
     c.x += 4;
@@ -99,18 +112,20 @@ k_wend_expand(const PairDesc P, const float* __restrict__ W, const float* __rest
 #pragma unroll
         for (int c = 0; c < DIM; ++c) acc[m][c] = v4f{0.f, 0.f, 0.f, 0.f};
     const float* Wr = W + pc * 64 + i16;
+    const int isy = (int)sy, isx = (int)sx, incp = (int)NCp;   // offsets fit in 32 bits
+    const float* thb = thp + cx0 + i16;
     // operands of the K step whose control for this lane is q (coordinates
-    // qc); branch-free: an invalid control reads a valid address, then 0
-    // (the validity select is applied when the operands are used, so the
-    // loads stay in flight)
+    // qc). Branch-free: a control past Q reads a valid address and is zeroed
+    // where it is used, so the loads stay in flight until then.
     auto load = [&](int q, const Idx3& qc, float* a, float* b, bool& ok) {
         const int qw = min(q, P.wpad[1] - 1);  // rows >= Q are 0; past the end: clamped
 #pragma unroll
-        for (int m = 0; m < 4; ++m) a[m] = Wr[(long long)qw * Ppad + m * 16];
+        for (int m = 0; m < 4; ++m) a[m] = Wr[qw * Ppad + m * 16];
         ok = q < Q;
-        const float* th = ok ? thp + (cz + qc.z) * sy + (cy + qc.y) * sx + cx0 + i16 + qc.x : thp;
+        // a mask, not a branch: the loads must not wait for a join
+        const int off = ((cz + qc.z) * isy + (cy + qc.y) * isx + qc.x) & -(int)ok;
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) b[c] = th[c * NCp];
+        for (int c = 0; c < DIM; ++c) b[c] = thb[off + c * incp];
     };
     auto step = [&](const float* a, const float* b, bool ok) {
 #pragma unroll
@@ -118,18 +133,18 @@ k_wend_expand(const PairDesc P, const float* __restrict__ W, const float* __rest
 #pragma unroll
             for (int c = 0; c < DIM; ++c) acc[m][c] = mfma4(a[m], ok ? b[c] : 0.f, acc[m][c]);
     };
-    // two operand sets in turn: the loads of step k + 1 are in flight during
-    // the MFMAs of step k
-    const int nst = (Q + 3) / 4;
+    // two operand sets rotate over an even number of K steps (a padding step
+    // past Q contributes 0): each set is reloaded right after its MFMAs
+    // issue, so its loads have a whole step of MFMAs to land
+    const int nst = ((Q + 3) / 4 + 1) & ~1;
     Idx3 qn = idx3(k4, P.wK[0], P.wK[1]);
     float a0[4], b0[DIM], a1[4], b1[DIM];
-    bool ok0 = false, ok1 = false;
+    bool ok0, ok1;
     load(k4, qn, a0, b0, ok0);
     for (int st = 0; st < nst; st += 2) {
         idx3_add4(qn, P.wK[0], P.wK[1]);
-        load((st + 1) * 4 + k4, qn, a1, b1, ok1);   // unconditional: no join for the
-        step(a0, b0, ok0);                          // wait counters to merge
-        if (st + 1 >= nst) break;
+        load((st + 1) * 4 + k4, qn, a1, b1, ok1);
+        step(a0, b0, ok0);
         idx3_add4(qn, P.wK[0], P.wK[1]);
         load((st + 2) * 4 + k4, qn, a0, b0, ok0);
         step(a1, b1, ok1);
@@ -137,13 +152,15 @@ k_wend_expand(const PairDesc P, const float* __restrict__ W, const float* __rest
     const int P3 = P.sp[0] * P.sp[1] * P.sp[2];
     const long long N = P.nvox;
     const int x0 = (cx0 + i16) * P.sp[0];
+    // phases r = pc 64 + 16 m + 4 k4 + v in increasing order, coordinates stepped
+    Idx3 rc = idx3(pc * 64 + 4 * k4, P.sp[0], P.sp[1]);
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
+            if (m + v > 0) idx3_add(rc, v == 0 ? 13 : 1, P.sp[0], P.sp[1]);
             const int r = pc * 64 + m * 16 + 4 * k4 + v;
             if (r >= P3) continue;
-            const Idx3 rc = idx3(r, P.sp[0], P.sp[1]);
             const int x = x0 + rc.x, y = cy * P.sp[1] + rc.y, z = cz * P.sp[2] + rc.z;
             if (x >= P.n[0] || y >= P.n[1] || z >= P.n[2]) continue;
             const long long vox = ((long long)z * P.n[1] + y) * P.n[0] + x;
@@ -167,15 +184,17 @@ k_wend_cells_t(const PairDesc P, const float* __restrict__ WT, const float* __re
     const int w = threadIdx.x >> 6;
     const int nqc = P.wpad[1] / 64;
     const int ngx = cdiv(P.wncell[0], kWCells);
-    const int qc = blockIdx.x % nqc;
-    const int grp = blockIdx.x / nqc;
+    const int part = blockIdx.x % kTSplit;     // which share of the phases
+    const int qc = (blockIdx.x / kTSplit) % nqc;
+    const int grp = blockIdx.x / (kTSplit * nqc);
     const int cx0 = (grp % ngx) * kWCells;
     const int cy = (grp / ngx) % P.wncell[1];
     const int cz = grp / (ngx * P.wncell[1]);
     const int Qpad = P.wpad[1];
     const int P3 = P.sp[0] * P.sp[1] * P.sp[2];
     const int nstep = P.wpad[0] / 4;
-    const int s0 = w * nstep / kWaves, s1 = (w + 1) * nstep / kWaves;
+    const int nsub = kTSplit * kWaves;         // K ranges: one per wave of the split blocks
+    const int s0 = (part * kWaves + w) * nstep / nsub, s1 = (part * kWaves + w + 1) * nstep / nsub;
     const long long N = P.nvox;
     const int cxl = cx0 + i16;                 // this lane's cell of the B tile
     const bool cell_ok = cxl < P.wncell[0];
@@ -185,19 +204,21 @@ k_wend_cells_t(const PairDesc P, const float* __restrict__ WT, const float* __re
 #pragma unroll
         for (int c = 0; c < DIM; ++c) acc[m][c] = v4f{0.f, 0.f, 0.f, 0.f};
     const float* Wq = WT + qc * 64 + i16;
-    // operands of the K step whose phase for this lane is r (coordinates rc);
-    // branch-free: a phase outside the grid reads voxel 0, then 0
-    // (the validity select is applied when the operands are used, so the
-    // loads stay in flight)
+    const int nx = P.n[0], nxy = P.n[0] * P.n[1], iN = (int)N;  // < 2^31 (plan check)
+    const int bx = cxl * P.sp[0], by = cy * P.sp[1], bz = cz * P.sp[2];
+    // operands of the K step whose phase for this lane is r (coordinates rc).
+    // Branch-free: a phase outside the grid reads voxel 0 and is zeroed where
+    // it is used, so the loads stay in flight until then.
     auto load = [&](int r, const Idx3& rc, float* a, float* b, bool& ok) {
         const int rw = min(r, P.wpad[0] - 1);  // rows >= P3 are 0; past the end: clamped
 #pragma unroll
-        for (int m = 0; m < 4; ++m) a[m] = Wq[(long long)rw * Qpad + m * 16];
-        const int x = cxl * P.sp[0] + rc.x, y = cy * P.sp[1] + rc.y, z = cz * P.sp[2] + rc.z;
+        for (int m = 0; m < 4; ++m) a[m] = Wq[rw * Qpad + m * 16];
+        const int x = bx + rc.x, y = by + rc.y, z = bz + rc.z;
         ok = r < P3 && cell_ok && x < P.n[0] && y < P.n[1] && z < P.n[2];
-        const long long vox = ok ? ((long long)z * P.n[1] + y) * P.n[0] + x : 0;
+        // a mask, not a branch: the loads must not wait for a join
+        const int vox = (z * nxy + y * nx + x) & -(int)ok;
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) b[c] = g[c * N + vox];
+        for (int c = 0; c < DIM; ++c) b[c] = g[c * iN + vox];
     };
     auto step = [&](const float* a, const float* b, bool ok) {
 #pragma unroll
@@ -205,17 +226,23 @@ k_wend_cells_t(const PairDesc P, const float* __restrict__ WT, const float* __re
 #pragma unroll
             for (int c = 0; c < DIM; ++c) acc[m][c] = mfma4(a[m], ok ? b[c] : 0.f, acc[m][c]);
     };
+    // two operand sets rotate over an even number of K steps (a padding step
+    // past this wave's range contributes 0): each set is reloaded right after
+    // its MFMAs issue, so its loads have a whole step of MFMAs to land
+    const int s2 = s0 + ((s1 - s0 + 1) & ~1);
     Idx3 rn = idx3(s0 * 4 + k4, P.sp[0], P.sp[1]);
     float a0[4], b0[DIM], a1[4], b1[DIM];
-    bool ok0 = false, ok1 = false;
-    if (s0 < s1) load(s0 * 4 + k4, rn, a0, b0, ok0);
-    for (int st = s0; st < s1; st += 2) {
+    bool ok0, ok1;
+    load(s0 * 4 + k4, rn, a0, b0, ok0);
+    ok0 = ok0 && s0 < s1;
+    for (int st = s0; st < s2; st += 2) {
         idx3_add4(rn, P.sp[0], P.sp[1]);
-        load((st + 1) * 4 + k4, rn, a1, b1, ok1);   // unconditional: no join for the
-        step(a0, b0, ok0);                          // wait counters to merge
-        if (st + 1 >= s1) break;
+        load((st + 1) * 4 + k4, rn, a1, b1, ok1);
+        ok1 = ok1 && st + 1 < s1;
+        step(a0, b0, ok0);
         idx3_add4(rn, P.sp[0], P.sp[1]);
         load((st + 2) * 4 + k4, rn, a0, b0, ok0);
+        ok0 = ok0 && st + 2 < s1;
         step(a1, b1, ok1);
     }
 #pragma unroll
@@ -239,7 +266,8 @@ k_wend_cells_t(const PairDesc P, const float* __restrict__ WT, const float* __re
 #pragma unroll
         for (int ww = 0; ww < kWaves; ++ww) sum += red[ww * 64 * NA + src];
         const int qv = qc * 64 + ql;
-        if (qv < Q && cx0 + t < P.wncell[0]) H[((long long)c * Q + qv) * ncells + row + t] = sum;
+        if (qv < Q && cx0 + t < P.wncell[0])
+            H[(((long long)part * DIM + c) * Q + qv) * ncells + row + t] = sum;
     }
 }
 
@@ -265,6 +293,7 @@ k_wend_gather(const PairDesc P, const float* __restrict__ H, float scale, int ac
         const int jx = (int)(j % P.nc[0]);
         const int jy = (int)((j / P.nc[0]) % P.nc[1]);
         const int jz = (int)(j / ((long long)P.nc[0] * P.nc[1]));
+        const long long hpart = (long long)DIM * Q * ncells;   // one share of the phases
         const float* Hc = H + (long long)c * Q * ncells;
         Idx3 qi = idx3(w, P.wK[0], P.wK[1]);
         for (int qq = w; qq < Q; qq += kWaves, idx3_add4(qi, P.wK[0], P.wK[1])) {
@@ -272,8 +301,10 @@ k_wend_gather(const PairDesc P, const float* __restrict__ H, float scale, int ac
             if (cx < 0 || cx >= P.wncell[0] || cy < 0 || cy >= P.wncell[1] || cz < 0 ||
                 cz >= P.wncell[2])
                 continue;
-            s += Hc[(long long)qq * ncells + ((long long)cz * P.wncell[1] + cy) * P.wncell[0] +
-                    cx];
+            const long long o =
+                (long long)qq * ncells + ((long long)cz * P.wncell[1] + cy) * P.wncell[0] + cx;
+#pragma unroll
+            for (int pt = 0; pt < kTSplit; ++pt) s += Hc[pt * hpart + o];
         }
     }
     red[w][lane] = s;
@@ -316,13 +347,14 @@ hipError_t launch_wendland_expand(const PairDesc& P, const float* consts_dev, in
     return hipGetLastError();
 }
 
-// grad (+)= scale * B^T g. H: d * K^d * prod(wncell) floats of workspace.
+// grad (+)= scale * B^T g. H: wendland_h_parts() * d * K^d * prod(wncell)
+// floats of workspace.
 hipError_t launch_wendland_adjoint(const PairDesc& P, const float* consts_dev, int dim,
                                    const float* g, float scale, float* H, float* grad,
                                    bool accumulate, hipStream_t s) {
     const float* WT = consts_dev + P.wend_off[1];
     const int ngx = cdiv(P.wncell[0], kWCells);
-    const int blocks = ngx * P.wncell[1] * P.wncell[2] * (P.wpad[1] / 64);
+    const int blocks = ngx * P.wncell[1] * P.wncell[2] * (P.wpad[1] / 64) * kTSplit;
     const long long NC = (long long)dim * P.nc[0] * P.nc[1] * P.nc[2];
     const int gblocks = (int)((NC + 63) / 64);
     if (dim == 3) {
@@ -340,5 +372,7 @@ hipError_t launch_wendland_adjoint(const PairDesc& P, const float* consts_dev, i
 // Cells along x per wave in both contractions (the padded control grid is
 // rounded up to a multiple of it along x).
 int wendland_cells_per_wave() { return kWCells; }
+// Partial per-cell sums the transpose writes (summed by the gather).
+int wendland_h_parts() { return kTSplit; }
 
 }  // namespace air
