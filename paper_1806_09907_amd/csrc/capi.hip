@@ -35,7 +35,8 @@ hipError_t launch_compose(const PairDesc& P, int dim, const float* u, float* out
 hipError_t launch_field_reach(const PairDesc& P, int dim, const float* u, int nfields,
                               unsigned int* dmax, hipStream_t s);
 hipError_t launch_compose_adjoint(const PairDesc& P, int dim, const float* u, const float* gout,
-                                  const unsigned int* dmax, float* gin, hipStream_t s);
+                                  const unsigned int* dmax, unsigned int* gmax, float* gin,
+                                  hipStream_t s);
 hipError_t launch_velocity_adjoint(const PairDesc& P, const float* consts_dev, int transform,
                                    int dim, const float* g, float scale, float* t1, float* t2,
                                    float* grad, hipStream_t s, bool accumulate);
@@ -475,7 +476,7 @@ static air_status build_tables(air_plan* P) {
         }
         L.bsadj1 = off;  off = align256(off + t1 * 4);
         L.bsadj2 = off;  off = align256(off + t2 * 4);
-        L.reach = off;   off = align256(off + (size_t)(P->diffeo + 1) * 4);
+        L.reach = off;   off = align256(off + (size_t)(P->diffeo + 2) * 4);  // + max|gout|
     }
     if (P->reg != AIR_REG_DIFFUSION) {
         L.tvpart = off;  off = align256(off + (size_t)tv_partials() * 8);
@@ -654,7 +655,8 @@ static hipError_t run_diffeo(const air_plan* P, const DeviceTables* T, void* ws,
     unsigned int* reach = reinterpret_cast<unsigned int*>(w + P->L.reach);
     if (P->diffeo > 0) e = launch_field_reach(hp, P->dim, U, P->diffeo, reach, s);
     for (int k = P->diffeo - 1; k >= 0 && e == hipSuccess; --k) {
-        e = launch_compose_adjoint(hp, P->dim, U + k * dN, g, reach + k, o, s);
+        e = launch_compose_adjoint(hp, P->dim, U + k * dN, g, reach + k, reach + P->diffeo + 1,
+                                   o, s);
         float* t = g;
         g = o;
         o = t;

@@ -204,6 +204,29 @@ k_absmax(const PairDesc P, const float* __restrict__ u, unsigned int* out) {
     }
 }
 
+// Largest |g| over n values, as non-negative float bits (NaN above every
+// finite value); `out` must be zero before the launch.
+__global__ void __launch_bounds__(kBlock)
+k_absmax_plain(const float* __restrict__ g, long long n, unsigned int* out) {
+    __shared__ unsigned int red[kBlock / 64];
+    float m = 0.f;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kBlock) {
+        const float t = fabsf(g[i]);
+        m = (t > m || !(t == t)) ? t : m;
+    }
+    unsigned int b = __float_as_uint(m) & 0x7fffffffu;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) b = max(b, (unsigned int)__shfl_xor((int)b, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int r = red[0];
+        for (int w = 1; w < kBlock / 64; ++w) r = max(r, red[w]);
+        atomicMax(out, r);
+    }
+}
+
 __global__ void k_zero_u32(unsigned int* p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
@@ -214,18 +237,33 @@ __global__ void k_zero_u32(unsigned int* p, int n) {
 // sample point and adds w_q(p(x)) gout(x) into LDS for its corners q inside T;
 // then each target q gets gin(q) = gout(q) + s_a sum_c gout_c(q) du_c/dp_a
 // at p(q) + the accumulated transpose.
+// The transpose accumulates in 64-bit fixed point, scaled by the power of two
+// 2^(40 - e) with 2^e > max |gout| (gmax_bits): integer LDS atomics are much
+// faster than float ones here, and integer sums do not depend on their order,
+// so the result is bitwise repeatable. Each term is below 2^40 in magnitude,
+// so fewer than 2^23 terms per target cannot overflow; the rounding of a term
+// is below 2^-41 max|gout|. A non-finite max|gout| makes gin NaN.
+constexpr int kAdjBlock3 = 1024;   // threads per 3D tile (96 KB of accumulators)
 template <int DIM>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(DIM == 3 ? kAdjBlock3 : kBlock)
 k_compose_adj_tile(const PairDesc P, const float* __restrict__ u, const float* __restrict__ gout,
-                   const unsigned int* __restrict__ dmax_bits, float* __restrict__ gin) {
+                   const unsigned int* __restrict__ dmax_bits,
+                   const unsigned int* __restrict__ gmax_bits, float* __restrict__ gin) {
     constexpr int TS = DIM == 3 ? 16 : 64;  // 4096 targets per tile
     constexpr int TV = DIM == 3 ? TS * TS * TS : TS * TS;
-    __shared__ float acc[DIM][TV];
+    constexpr int NT = DIM == 3 ? kAdjBlock3 : kBlock;
+    __shared__ unsigned long long acc[DIM][TV];
     const long long N = P.nvox;
     const int nt0 = cdiv(P.n[0], TS), nt1 = cdiv(P.n[1], TS);
     const int b = blockIdx.x;
     int o[3] = {(b % nt0) * TS, ((b / nt0) % nt1) * TS, DIM == 3 ? (b / (nt0 * nt1)) * TS : 0};
-    for (int i = threadIdx.x; i < DIM * TV; i += kBlock) (&acc[0][0])[i] = 0.f;
+    for (int i = threadIdx.x; i < DIM * TV; i += NT) (&acc[0][0])[i] = 0ull;
+    const float gm = __uint_as_float(*gmax_bits);
+    const bool gfin = gm == gm && gm < 3.0e38f;
+    const int ge = gfin && gm > 0.f ? ilogbf(gm) + 1 : 0;   // 2^ge > max|gout|
+    const float scale = gfin ? ldexpf(1.f, 40 - ge) : 0.f;
+    const double unscale = ldexp(1.0, ge - 40);
+    const float poison = gfin ? 0.f : __uint_as_float(0x7fc00000u);   // NaN
     // reach: corners lie within floor(p) .. floor(p) + 1 and |p - x| <= dmax
     const float dm = __uint_as_float(*dmax_bits);
     int h = (dm == dm && dm < 1e6f) ? (int)ceilf(dm) + 1 : (1 << 20);
@@ -240,7 +278,7 @@ k_compose_adj_tile(const PairDesc P, const float* __restrict__ u, const float* _
     // the box holds at most N < 2^29 voxels: 32-bit index arithmetic
     const int box = ext[0] * ext[1] * ext[2];
     const int e01 = ext[0] * ext[1];
-    for (int i = threadIdx.x; i < box; i += kBlock) {
+    for (int i = threadIdx.x; i < box; i += NT) {
         int x[3];
         const int r = i / ext[0];
         x[0] = lo[0] + (i - r * ext[0]);
@@ -284,11 +322,12 @@ k_compose_adj_tile(const PairDesc P, const float* __restrict__ u, const float* _
             for (int a = 0; a < DIM; ++a) w *= ((cn >> a) & 1) ? f[a] : 1.f - f[a];
             const int t = (q[0] - o[0]) + TS * ((q[1] - o[1]) + (DIM == 3 ? TS * (q[2] - o[2]) : 0));
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) atomicAdd(&acc[c][t], w * go[c]);
+            for (int c = 0; c < DIM; ++c)
+                atomicAdd(&acc[c][t], (unsigned long long)__float2ll_rn(w * go[c] * scale));
         }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < TV; t += kBlock) {
+    for (int t = threadIdx.x; t < TV; t += NT) {
         int x[3];
         x[0] = o[0] + t % TS;
         x[1] = o[1] + (t / TS) % TS;
@@ -308,7 +347,8 @@ k_compose_adj_tile(const PairDesc P, const float* __restrict__ u, const float* _
             float tsum = 0.f;
 #pragma unroll
             for (int c = 0; c < DIM; ++c) tsum += go[c] * dv[c][a];
-            gin[a * N + v] = go[a] + P.s[a] * tsum + acc[a][t];
+            const float tr = (float)((double)(long long)acc[a][t] * unscale) + poison;
+            gin[a * N + v] = go[a] + P.s[a] * tsum + tr;
         }
     }
 }
@@ -379,16 +419,23 @@ hipError_t launch_field_reach(const PairDesc& P, int dim, const float* u, int nf
     return hipGetLastError();
 }
 
+// gin = the adjoint of one squaring at u applied to gout. gmax: one uint of
+// workspace (max |gout|, recomputed here).
 hipError_t launch_compose_adjoint(const PairDesc& P, int dim, const float* u, const float* gout,
-                                  const unsigned int* dmax, float* gin, hipStream_t s) {
+                                  const unsigned int* dmax, unsigned int* gmax, float* gin,
+                                  hipStream_t s) {
+    const long long n = (long long)dim * P.nvox;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, gmax, 1);
+    const int g = grid_for(n) < 1024 ? grid_for(n) : 1024;
+    hipLaunchKernelGGL(k_absmax_plain, dim3(g), dim3(kBlock), 0, s, gout, n, gmax);
     if (dim == 3) {
         const int nt = cdiv(P.n[0], 16) * cdiv(P.n[1], 16) * cdiv(P.n[2], 16);
-        hipLaunchKernelGGL(k_compose_adj_tile<3>, dim3(nt), dim3(kBlock), 0, s, P, u, gout, dmax,
-                           gin);
+        hipLaunchKernelGGL(k_compose_adj_tile<3>, dim3(nt), dim3(kAdjBlock3), 0, s, P, u, gout,
+                           dmax, gmax, gin);
     } else {
         const int nt = cdiv(P.n[0], 64) * cdiv(P.n[1], 64);
         hipLaunchKernelGGL(k_compose_adj_tile<2>, dim3(nt), dim3(kBlock), 0, s, P, u, gout, dmax,
-                           gin);
+                           gmax, gin);
     }
     return hipGetLastError();
 }

@@ -3,8 +3,8 @@ scaling and squaring) against the FP64 oracle on the same seeded FP32 inputs.
 
 Tolerances as for the other paths: objective relative error <= 1e-5,
 gradient norm-wise relative error <= 1e-4, displacement norm-wise <= 1e-5.
-The adjoint scatters with FP32 atomics, so repeated GPU runs agree to
-rounding, not bitwise.
+The adjoint's scatter sums in 64-bit fixed point, so repeated GPU runs are
+bitwise equal.
 """
 import functools
 
@@ -123,8 +123,9 @@ def test_regulariser_parity(tf):
     assert rel(g.double().cpu().numpy(), go) <= GRAD_TOL
 
 
-def test_repeat_runs_agree_to_rounding():
-    """The atomic scatter makes runs differ only in the last bits."""
+def test_repeat_runs_bitwise_equal():
+    """The scatter of the adjoint sums integers: repeated runs are bitwise
+    equal, in 3D and in 2D."""
     n = (33, 30, 28)
     p = api.Problem(n=n, transform=api.TF_DENSE, spacing=(1, 1, 1), similarity=api.SIM_MSE,
                     lambda_diff=1.0, diffeo_steps=6)
@@ -134,8 +135,18 @@ def test_repeat_runs_agree_to_rounding():
     v1, g1 = api.objective_and_grad(plan, gpu(F), gpu(M), th)
     g1 = g1.clone()
     v2, g2 = api.objective_and_grad(plan, gpu(F), gpu(M), th)
-    assert float(v1) == float(v2)   # the forward has no atomics
-    assert rel(g2.double().cpu().numpy(), g1.double().cpu().numpy()) <= 1e-6
+    assert float(v1) == float(v2)
+    assert torch.equal(g1, g2)
+    n2 = (48, 40)
+    p2 = api.Problem(n=n2, transform=api.TF_DENSE, spacing=(1, 1), similarity=api.SIM_NCC,
+                     lambda_diff=0.5, diffeo_steps=5)
+    F2, M2 = inputs(n2, 7)
+    th2 = gpu(theta_for(p2, 2))
+    plan2 = api.Plan(p2)
+    _, h1 = api.objective_and_grad(plan2, gpu(F2), gpu(M2), th2)
+    h1 = h1.clone()
+    _, h2 = api.objective_and_grad(plan2, gpu(F2), gpu(M2), th2)
+    assert torch.equal(h1, h2)
 
 
 def test_unsupported_combinations():
