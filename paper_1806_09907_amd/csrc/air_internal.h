@@ -66,8 +66,9 @@ struct WsLayout {
                          // (Wendland: the padded, scaled controls)
     size_t bsadj2;       // float [d][nz][ncy][ncx]: after y
                          // (Wendland: per-cell sums H [d][cells][K^d])
-    size_t reach;        // uint32 [K + 2]: largest displacement of each u_k, then the
-                         // largest |gradient| of the current squaring (float bits)
+    size_t reach;        // uint32 [K + 3]: largest displacement of each u_k, then two
+                         // slots for the largest |gradient| entering and leaving a
+                         // squaring's adjoint (float bits)
     size_t tvpart;       // double [TV blocks]: partial sums of a TV term
     // LCC passes (similarity AIR_SIM_LCC)
     size_t lcc_w;        // float [N]: warped image

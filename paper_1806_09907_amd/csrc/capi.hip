@@ -35,7 +35,8 @@ hipError_t launch_compose(const PairDesc& P, int dim, const float* u, float* out
 hipError_t launch_field_reach(const PairDesc& P, int dim, const float* u, int nfields,
                               unsigned int* dmax, hipStream_t s);
 hipError_t launch_compose_adjoint(const PairDesc& P, int dim, const float* u, const float* gout,
-                                  const unsigned int* dmax, unsigned int* gmax, float* gin,
+                                  const unsigned int* dmax, unsigned int* gmax_in,
+                                  bool measure_in, unsigned int* gmax_out, float* gin,
                                   hipStream_t s);
 hipError_t launch_velocity_adjoint(const PairDesc& P, const float* consts_dev, int transform,
                                    int dim, const float* g, float scale, float* t1, float* t2,
@@ -476,7 +477,7 @@ static air_status build_tables(air_plan* P) {
         }
         L.bsadj1 = off;  off = align256(off + t1 * 4);
         L.bsadj2 = off;  off = align256(off + t2 * 4);
-        L.reach = off;   off = align256(off + (size_t)(P->diffeo + 2) * 4);  // + max|gout|
+        L.reach = off;   off = align256(off + (size_t)(P->diffeo + 3) * 4);  // + 2 max|grad|
     }
     if (P->reg != AIR_REG_DIFFUSION) {
         L.tvpart = off;  off = align256(off + (size_t)tv_partials() * 8);
@@ -655,8 +656,12 @@ static hipError_t run_diffeo(const air_plan* P, const DeviceTables* T, void* ws,
     unsigned int* reach = reinterpret_cast<unsigned int*>(w + P->L.reach);
     if (P->diffeo > 0) e = launch_field_reach(hp, P->dim, U, P->diffeo, reach, s);
     for (int k = P->diffeo - 1; k >= 0 && e == hipSuccess; --k) {
-        e = launch_compose_adjoint(hp, P->dim, U + k * dN, g, reach + k, reach + P->diffeo + 1,
-                                   o, s);
+        // the max |gradient| slots alternate: each call measures its output
+        // for the next one
+        unsigned int* gm_in = reach + P->diffeo + 1 + ((P->diffeo - 1 - k) & 1);
+        unsigned int* gm_out = reach + P->diffeo + 1 + ((P->diffeo - k) & 1);
+        e = launch_compose_adjoint(hp, P->dim, U + k * dN, g, reach + k, gm_in,
+                                   k == P->diffeo - 1, gm_out, o, s);
         float* t = g;
         g = o;
         o = t;

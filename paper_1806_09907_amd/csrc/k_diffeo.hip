@@ -62,11 +62,46 @@ __device__ inline bool field_sample(const float* __restrict__ u, long long N, co
         }
         return false;
     }
-    // every corner inside the volume (the common case): no per-corner tests
+    // every corner inside the volume (the common case): each x-pair of
+    // corners is one 8-byte buffer load, and the weights are nested lerps
     bool interior = true;
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
         if (j[a] < 0 || j[a] > P.n[a] - 2) interior = false;
+    if (interior) {
+        const int nx = P.n[0], ny = P.n[1];
+        const int off = ((DIM == 3 ? j[2] * ny : 0) + j[1]) * nx * 4 + j[0] * 4;  // N * 4 < 2^31
+        const int sx4 = nx * 4, sxy4 = nx * ny * 4;
+        const float fx = f[0], fy = f[1], fz = DIM == 3 ? f[2] : 0.f;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const __amdgpu_buffer_rsrc_t r = make_rsrc(u + c * N, (uint32_t)(N * 4));
+            const v2f a00 = load2(r, off, 0), a10 = load2(r, off, sx4);
+            const float c00 = fmaf(fx, a00.y - a00.x, a00.x), c10 = fmaf(fx, a10.y - a10.x, a10.x);
+            const float c0 = fmaf(fy, c10 - c00, c00);
+            if (DIM == 2) {
+                val[c] = c0;
+                if (DERIV) {
+                    dval[c][0] = (1.f - fy) * (a00.y - a00.x) + fy * (a10.y - a10.x);
+                    dval[c][1] = c10 - c00;
+                }
+            } else {
+                const v2f a01 = load2(r, off, sxy4), a11 = load2(r, off, sxy4 + sx4);
+                const float c01 = fmaf(fx, a01.y - a01.x, a01.x),
+                            c11 = fmaf(fx, a11.y - a11.x, a11.x);
+                const float c1 = fmaf(fy, c11 - c01, c01);
+                val[c] = fmaf(fz, c1 - c0, c0);
+                if (DERIV) {
+                    const float dx0 = fmaf(fy, (a10.y - a10.x) - (a00.y - a00.x), a00.y - a00.x);
+                    const float dx1 = fmaf(fy, (a11.y - a11.x) - (a01.y - a01.x), a01.y - a01.x);
+                    dval[c][0] = fmaf(fz, dx1 - dx0, dx0);
+                    dval[c][1] = fmaf(fz, (c11 - c01) - (c10 - c00), c10 - c00);
+                    dval[c][2] = c1 - c0;
+                }
+            }
+        }
+        return true;
+    }
 #pragma unroll
     for (int cn = 0; cn < (1 << DIM); ++cn) {
         int q[3] = {0, 0, 0};
@@ -248,7 +283,8 @@ template <int DIM>
 __global__ void __launch_bounds__(DIM == 3 ? kAdjBlock3 : kBlock)
 k_compose_adj_tile(const PairDesc P, const float* __restrict__ u, const float* __restrict__ gout,
                    const unsigned int* __restrict__ dmax_bits,
-                   const unsigned int* __restrict__ gmax_bits, float* __restrict__ gin) {
+                   const unsigned int* __restrict__ gmax_bits, float* __restrict__ gin,
+                   unsigned int* __restrict__ gmax_out) {
     constexpr int TS = DIM == 3 ? 16 : 64;  // 4096 targets per tile
     constexpr int TV = DIM == 3 ? TS * TS * TS : TS * TS;
     constexpr int NT = DIM == 3 ? kAdjBlock3 : kBlock;
@@ -327,6 +363,7 @@ k_compose_adj_tile(const PairDesc P, const float* __restrict__ u, const float* _
         }
     }
     __syncthreads();
+    float gm_out = 0.f;
     for (int t = threadIdx.x; t < TV; t += NT) {
         int x[3];
         x[0] = o[0] + t % TS;
@@ -348,8 +385,23 @@ k_compose_adj_tile(const PairDesc P, const float* __restrict__ u, const float* _
 #pragma unroll
             for (int c = 0; c < DIM; ++c) tsum += go[c] * dv[c][a];
             const float tr = (float)((double)(long long)acc[a][t] * unscale) + poison;
-            gin[a * N + v] = go[a] + P.s[a] * tsum + tr;
+            const float gv = go[a] + P.s[a] * tsum + tr;
+            gin[a * N + v] = gv;
+            const float ag = fabsf(gv);
+            gm_out = (ag > gm_out || !(ag == ag)) ? ag : gm_out;
         }
+    }
+    // max |gin| of the block (the scale of the next squaring's adjoint)
+    __shared__ unsigned int redm[NT / 64];
+    unsigned int bm = __float_as_uint(gm_out) & 0x7fffffffu;
+#pragma unroll
+    for (int o2 = 32; o2 >= 1; o2 >>= 1) bm = max(bm, (unsigned int)__shfl_xor((int)bm, o2, 64));
+    if ((threadIdx.x & 63) == 0) redm[threadIdx.x >> 6] = bm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int r = redm[0];
+        for (int w = 1; w < NT / 64; ++w) r = max(r, redm[w]);
+        atomicMax(gmax_out, r);
     }
 }
 
@@ -419,23 +471,28 @@ hipError_t launch_field_reach(const PairDesc& P, int dim, const float* u, int nf
     return hipGetLastError();
 }
 
-// gin = the adjoint of one squaring at u applied to gout. gmax: one uint of
-// workspace (max |gout|, recomputed here).
+// gin = the adjoint of one squaring at u applied to gout. gmax_in: max |gout|
+// as float bits (computed here when `measure_in`, else left by the previous
+// call); gmax_out receives max |gin| for the next call. One uint each.
 hipError_t launch_compose_adjoint(const PairDesc& P, int dim, const float* u, const float* gout,
-                                  const unsigned int* dmax, unsigned int* gmax, float* gin,
+                                  const unsigned int* dmax, unsigned int* gmax_in,
+                                  bool measure_in, unsigned int* gmax_out, float* gin,
                                   hipStream_t s) {
     const long long n = (long long)dim * P.nvox;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, gmax, 1);
-    const int g = grid_for(n) < 1024 ? grid_for(n) : 1024;
-    hipLaunchKernelGGL(k_absmax_plain, dim3(g), dim3(kBlock), 0, s, gout, n, gmax);
+    if (measure_in) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, gmax_in, 1);
+        const int g = grid_for(n) < 1024 ? grid_for(n) : 1024;
+        hipLaunchKernelGGL(k_absmax_plain, dim3(g), dim3(kBlock), 0, s, gout, n, gmax_in);
+    }
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, gmax_out, 1);
     if (dim == 3) {
         const int nt = cdiv(P.n[0], 16) * cdiv(P.n[1], 16) * cdiv(P.n[2], 16);
         hipLaunchKernelGGL(k_compose_adj_tile<3>, dim3(nt), dim3(kAdjBlock3), 0, s, P, u, gout,
-                           dmax, gmax, gin);
+                           dmax, gmax_in, gin, gmax_out);
     } else {
         const int nt = cdiv(P.n[0], 64) * cdiv(P.n[1], 64);
         hipLaunchKernelGGL(k_compose_adj_tile<2>, dim3(nt), dim3(kBlock), 0, s, P, u, gout, dmax,
-                           gmax, gin);
+                           gmax_in, gin, gmax_out);
     }
     return hipGetLastError();
 }
