@@ -47,12 +47,23 @@ def progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+# Sources the dominant kernel of each counter-profiled workload is built
+# from (its own file and the shared headers): counters stay valid while
+# these are unchanged.
+KERNEL_SOURCES = {
+    "batch128": ["k_bspline.hip"],
+    "uneven48": ["k_bspline.hip"],
+    "dense256": ["k_dense.hip"],
+}
+SHARED_SOURCES = ["air_internal.h", "device_common.h", "../../include/airhip.h"]
+
+
+def kernel_source_hash(workload: str = "batch128") -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1806_09907_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
-        with open(f, "rb") as fh:
-            h.update(os.path.basename(f).encode())
+    for name in KERNEL_SOURCES.get(workload, []) + SHARED_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(os.path.basename(name).encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -65,7 +76,7 @@ def traffic_for(workload: str):
     except OSError:
         return None
     e = t.get(workload)
-    if not e or e.get("source_hash") != kernel_source_hash():
+    if not e or e.get("source_hash") != kernel_source_hash(workload):
         return None
     return e["bytes_per_launch"]
 
