@@ -589,11 +589,12 @@ def run_lcc128(args, dev):
     N = 128 ** 3
     nctrl = 19 ** 3
     # expansion (write u); diffusion pass (read u, write dR/du); sample (read
-    # u and M, write W, mask, dW/dp); statistics (read F, W, mask; box sums
-    # out and back, FP64); coefficients out and back; gradient pass (read W,
-    # F, mask, dW/dp, dR/du; write dL/du); transposed expansion (read dL/du)
-    bytes_eval = (4 * 3 * N + 4 * 6 * N + (4 * 4 + 4 + 1 + 12) * N + (9 + 2 * 48) * N
-                  + (12 + 2 * 24) * N + (9 + 12 + 12 + 12) * N + 12 * N + 4 * 2 * 3 * nctrl)
+    # u and M, write W, mask, dW/dp); statistics pass (read F, W, mask; write
+    # the three coefficient maps: the box sums stay on chip); gradient pass
+    # (read the coefficient maps, W, F, mask, dW/dp, dR/du; write dL/du);
+    # transposed expansion (read dL/du)
+    bytes_eval = (4 * 3 * N + 4 * 6 * N + (4 * 4 + 4 + 1 + 12) * N + (9 + 12) * N
+                  + (12 + 9 + 12 + 12 + 12) * N + 12 * N + 4 * 2 * 3 * nctrl)
     achieved = bytes_eval / (ms_l / 1e3) / 1e9
     return {
         "metric": "objective+grad evals/s, 128^3 B-spline LCC (radius 3) + 0.05 diffusion, "

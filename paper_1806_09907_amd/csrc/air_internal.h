@@ -74,7 +74,7 @@ struct WsLayout {
     size_t lcc_w;        // float [N]: warped image
     size_t lcc_mask;     // uint8 [N]: sample point inside the moving image
     size_t lcc_dw;       // float [d][N]: dW/dp (voxel units)
-    size_t lcc_s;        // double [6][N]: box sums (statistics, then coefficients)
+    size_t lcc_s;        // double [6][N]: box sums of the unfused passes (else empty)
     size_t lcc_a;        // float [3][N]: coefficient maps
     size_t lcc_part;     // double [2 * blocks]: (count, sum rho) per block
     size_t lcc_scal;     // double [1]: 1 / |X'|

@@ -51,6 +51,7 @@ int wendland_cells_per_wave();
 int wendland_h_parts();
 int lcc_partials(const PairDesc& P);
 size_t lcc_lds_bytes(int r);
+bool lcc_fused(int dim, int r);
 hipError_t launch_lcc(const PairDesc& P, int dim, int r, const float* F, const float* M,
                       const float* u, float* Wb, uint8_t* mk, float* dW, double* S, float* A,
                       double* part, double* scal, uint32_t* flag, float lambda, bool lam_acc,
@@ -488,7 +489,8 @@ static air_status build_tables(air_plan* P) {
         L.lcc_w = off;     off = align256(off + N * 4);
         L.lcc_mask = off;  off = align256(off + N);
         L.lcc_dw = off;    off = align256(off + (size_t)d * N * 4);
-        L.lcc_s = off;     off = align256(off + 6 * N * 8);
+        L.lcc_s = off;     // the FP64 box sums only where the passes are not fused
+        if (!lcc_fused(P->dim, P->lcc_radius)) off = align256(off + 6 * N * 8);
         L.lcc_a = off;     off = align256(off + 3 * N * 4);
         L.lcc_part = off;  off = align256(off + 2 * (size_t)lcc_partials(D) * 8);
         L.lcc_scal = off;  off = align256(off + 8);

@@ -13,7 +13,9 @@
 // and, as y is in N(x) exactly when x is in the window of y,
 //   dS/dW(y) = -(1/|X'|) m(y) (box(aB) + 2 W(y) box(aD) + F(y) box(aE))(y)
 // with a* = drho/d* on X' and 0 elsewhere. Every box sum is separable: an
-// LDS-tiled pass over x and y, then a running sum along z.
+// LDS-tiled pass over x and y, then a running sum along z — fused into one
+// kernel per direction in 3D for radii up to 4 (the z window as a register
+// ring), else as separate passes through FP64 maps.
 #include "device_common.h"
 
 namespace air {
@@ -23,6 +25,23 @@ namespace {
 constexpr int kTX = 32, kTY = 8;   // xy tile of the box passes (kBlock threads)
 constexpr int kZSeg = 16;          // voxels of z walked per thread in the z passes
 constexpr double kLccEps = 1e-10;  // eps of the denominator (image units^4)
+
+// Statistics -> rho and the coefficient maps (aB, aD, aE) on X' (two FP64
+// divisions per voxel: 1/n and 1/sqrt(V)).
+__device__ inline void lcc_coef(const double* s, float* aB, float* aD, float* aE, double* rho) {
+    const double in = 1.0 / s[0];
+    const double mf = s[1] * in, mw = s[2] * in;
+    const double vf = s[3] * in - mf * mf, vw = s[4] * in - mw * mw;
+    const double cv = s[5] * in - mf * mw;
+    const double V = vf * vw + kLccEps;
+    const double isq = 1.0 / sqrt(V);
+    const double r = cv * isq;
+    const double iV = isq * isq;
+    *aB = (float)(in * (r * vf * mw * iV - mf * isq));
+    *aD = (float)(-0.5 * r * vf * in * iV);
+    *aE = (float)(in * isq);
+    *rho = r;
+}
 
 // W, the mask and dW/dp (voxel units) at every voxel.
 template <int DIM>
@@ -168,16 +187,8 @@ k_lcc_stats_z(const PairDesc P, int rz, const double* __restrict__ S,
         z_walk<6>(P, rz, S, col, z0, z1, [&](int, long long v, const double* s) {
             float aB = 0.f, aD = 0.f, aE = 0.f;
             if (mk[v]) {
-                const double n = s[0];
-                const double mf = s[1] / n, mw = s[2] / n;
-                const double vf = s[3] / n - mf * mf, vw = s[4] / n - mw * mw;
-                const double cv = s[5] / n - mf * mw;
-                const double V = vf * vw + kLccEps;
-                const double sq = sqrt(V);
-                const double rho = cv / sq;
-                aB = (float)(-mf / (n * sq) + rho * vf * mw / (n * V));
-                aD = (float)(-rho * vf / (2.0 * n * V));
-                aE = (float)(1.0 / (n * sq));
+                double rho;
+                lcc_coef(s, &aB, &aD, &aE, &rho);
                 acc[0] += 1.0;
                 acc[1] += rho;
             }
@@ -245,6 +256,287 @@ k_lcc_grad_z(const PairDesc P, int rz, const double* __restrict__ T,
     });
 }
 
+// ---- fused box passes: xy sums in LDS, z window as a register ring ------
+// A block owns a kTX x kTY column tile and a chunk of kZc output planes. It
+// walks the planes of the chunk plus the R-plane halo on each side; for each
+// plane it forms the xy box sums of its columns in LDS (as k_lcc_box_xy),
+// adds them to a running z sum and subtracts the plane that leaves the
+// window, kept in a ring of 2R + 1 slots. The plane loop is unrolled by
+// 2R + 1 so that every ring slot is a fixed register. Global loads run one
+// plane ahead: the next plane's tile (and the next output plane's per-voxel
+// inputs) are in flight while the current plane is summed.
+constexpr int kZc = 16;   // output planes per block of the fused passes
+constexpr int kMaxFusedR = 4;   // radii the register ring covers (3D)
+
+template <int R>
+struct Halo {
+    static constexpr int HX = kTX + 2 * R, HY = kTY + 2 * R, NI = HX * HY;
+    static constexpr int NF = (NI + kBlock - 1) / kBlock;   // tile elements per thread
+};
+
+template <int R, int NCH>
+struct XYPlane {
+    alignas(16) float raw[3][Halo<R>::NI];   // NI is even: every row starts 8-byte aligned
+    alignas(16) double xs[NCH][Halo<R>::HY][kTX];
+};
+
+// One plane's tile with halo, as loaded (every load unconditional at a
+// clamped address; ok marks the elements inside the volume).
+template <int R>
+struct TileRegs {
+    float a[3][Halo<R>::NF];
+    uint8_t m[Halo<R>::NF];
+    uint32_t ok;
+};
+
+// MODE 0: a0 = F, a1 = W and mk the mask; MODE 1: three FP32 maps.
+template <int R, int MODE>
+__device__ inline void fetch_tile(const PairDesc& P, int bx, int by, int zz,
+                                  const float* __restrict__ a0, const float* __restrict__ a1,
+                                  const float* __restrict__ a2, const uint8_t* __restrict__ mk,
+                                  TileRegs<R>& t) {
+    using H = Halo<R>;
+    const int x0 = bx * kTX - R, y0 = by * kTY - R;
+    const bool zin = zz >= 0 && zz < P.n[2];
+    const long long plane = (long long)zz * P.n[0] * P.n[1];
+    t.ok = 0;
+#pragma unroll
+    for (int it = 0; it < H::NF; ++it) {
+        const int i = threadIdx.x + it * kBlock;
+        const int yy = y0 + i / H::HX, xx = x0 + i % H::HX;
+        const bool in = i < H::NI && zin && xx >= 0 && xx < P.n[0] && yy >= 0 && yy < P.n[1];
+        const long long v = in ? plane + (long long)yy * P.n[0] + xx : 0;
+        t.ok |= (in ? 1u : 0u) << it;
+        t.a[0][it] = a0[v];
+        t.a[1][it] = a1[v];
+        if (MODE == 0)
+            t.m[it] = mk[v];
+        else
+            t.a[2][it] = a2[v];
+    }
+}
+
+// The tile's channels into LDS: MODE 0 (m, mF, mW), MODE 1 the maps, zero
+// outside the volume.
+template <int R, int NCH, int MODE>
+__device__ inline void commit_tile(XYPlane<R, NCH>& L, const TileRegs<R>& t) {
+    using H = Halo<R>;
+#pragma unroll
+    for (int it = 0; it < H::NF; ++it) {
+        const int i = threadIdx.x + it * kBlock;
+        const bool ok = (t.ok >> it) & 1u;
+        float v0, v1, v2;
+        if (MODE == 0) {
+            const bool m = ok && t.m[it] != 0;
+            v0 = m ? 1.f : 0.f;
+            v1 = m ? t.a[0][it] : 0.f;
+            v2 = m ? t.a[1][it] : 0.f;
+        } else {
+            v0 = ok ? t.a[0][it] : 0.f;
+            v1 = ok ? t.a[1][it] : 0.f;
+            v2 = ok ? t.a[2][it] : 0.f;
+        }
+        if (H::NI % kBlock == 0 || i < H::NI) {
+            L.raw[0][i] = v0;
+            L.raw[1][i] = v1;
+            L.raw[2][i] = v2;
+        }
+    }
+}
+
+// x sums of the committed tile, then the column's y sums (out). MODE 0 forms
+// m, mF, mW, mF^2, mW^2, mFW (F and W are zero where m is). A thread forms
+// two neighbouring x sums, which share 2R of their 2R + 1 terms. Every
+// thread of the block calls it; raw must be complete (barrier before), and
+// xs is free again only after the next barrier.
+template <int R, int NCH, int MODE>
+__device__ inline void xy_sums(XYPlane<R, NCH>& L, double* out) {
+    using H = Halo<R>;
+    constexpr int XP = kTX / 2;   // pairs of x outputs per row
+    constexpr int NE = 2 * R + 2; // raw elements a pair reads
+    for (int i = threadIdx.x; i < H::HY * XP; i += kBlock) {
+        const int ry = i / XP, tx = 2 * (i % XP);
+        float e[3][NE];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int k = 0; k < NE; k += 2) {
+                const float2 q = *reinterpret_cast<const float2*>(&L.raw[c][ry * H::HX + tx + k]);
+                e[c][k] = q.x;
+                e[c][k + 1] = q.y;
+            }
+        double mid[NCH];   // the 2R shared terms
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) mid[c] = 0.0;
+#pragma unroll
+        for (int k = 1; k <= 2 * R; ++k) {
+            const double e0 = e[0][k], e1 = e[1][k], e2 = e[2][k];
+            mid[0] += e0;
+            mid[1] += e1;
+            mid[2] += e2;
+            if (MODE == 0) {
+                mid[3 % NCH] = fma(e1, e1, mid[3 % NCH]);
+                mid[4 % NCH] = fma(e2, e2, mid[4 % NCH]);
+                mid[5 % NCH] = fma(e1, e2, mid[5 % NCH]);
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = h ? NE - 1 : 0;
+            const double e0 = e[0][k], e1 = e[1][k], e2 = e[2][k];
+            double o[NCH];
+            o[0] = mid[0] + e0;
+            o[1] = mid[1] + e1;
+            o[2] = mid[2] + e2;
+            if (MODE == 0) {
+                o[3 % NCH] = fma(e1, e1, mid[3 % NCH]);
+                o[4 % NCH] = fma(e2, e2, mid[4 % NCH]);
+                o[5 % NCH] = fma(e1, e2, mid[5 % NCH]);
+            }
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) L.xs[c][ry][tx + h] = o[c];
+        }
+    }
+    __syncthreads();
+    const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int dy = 0; dy <= 2 * R; ++dy) t += L.xs[c][ty + dy][tx];
+        out[c] = t;
+    }
+}
+
+// Walk the planes of a chunk [z0, z1). pre(z) issues the loads of output
+// plane z's per-voxel inputs one plane before fin(z, sums) uses them.
+template <int R, int NCH, int MODE, typename Pre, typename Fin>
+__device__ inline void z_ring_walk(const PairDesc& P, XYPlane<R, NCH>& L, int bx, int by, int z0,
+                                   int z1, const float* a0, const float* a1, const float* a2,
+                                   const uint8_t* mk, Pre pre, Fin fin) {
+    constexpr int S = 2 * R + 1;
+    double ring[S][NCH];
+    double zs[NCH];
+#pragma unroll
+    for (int k = 0; k < S; ++k)
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) ring[k][c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) zs[c] = 0.0;
+    const int zlast = z1 - 1 + R;
+    TileRegs<R> t;
+    fetch_tile<R, MODE>(P, bx, by, z0 - R, a0, a1, a2, mk, t);
+    for (int zb = z0 - R; zb <= zlast; zb += S) {
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            const int zz = zb + k;
+            if (zz > zlast) break;  // uniform over the block
+            // raw is free: every thread passed the x sums of the last plane
+            commit_tile<R, NCH, MODE>(L, t);
+            __syncthreads();
+            if (zz < zlast) fetch_tile<R, MODE>(P, bx, by, zz + 1, a0, a1, a2, mk, t);
+            double p[NCH];
+            xy_sums<R, NCH, MODE>(L, p);
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                zs[c] += p[c] - ring[k][c];   // ring[k] holds plane zz - S, leaving now
+                ring[k][c] = p[c];
+            }
+            const int z = zz - R;              // its window [z - R, z + R] is complete
+            if (z >= z0) fin(z, zs);
+            if (z + 1 >= z0 && z + 1 < z1) pre(z + 1);
+        }
+    }
+}
+
+template <int R>
+__global__ void __launch_bounds__(kBlock)
+k_lcc_stats_fused(const PairDesc P, const float* __restrict__ F, const float* __restrict__ W,
+                  const uint8_t* __restrict__ mk, float* __restrict__ A, double* __restrict__ part) {
+    __shared__ XYPlane<R, 6> L;
+    __shared__ double red[2 * (kBlock / 64)];
+    const int ntx = cdiv(P.n[0], kTX), nty = cdiv(P.n[1], kTY);
+    const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty;
+    const int z0 = (blockIdx.x / (ntx * nty)) * kZc, z1 = min(P.n[2], z0 + kZc);
+    const int x = bx * kTX + threadIdx.x % kTX, y = by * kTY + threadIdx.x / kTX;
+    const bool col = x < P.n[0] && y < P.n[1];
+    const long long N = P.nvox;
+    const long long c0 = col ? (long long)y * P.n[0] + x : 0;
+    const long long sz = (long long)P.n[0] * P.n[1];
+    double acc[2] = {0.0, 0.0};
+    uint8_t mnext = 0;
+    z_ring_walk<R, 6, 0>(
+        P, L, bx, by, z0, z1, F, W, nullptr, mk,
+        [&](int z) { mnext = mk[z * sz + c0]; },
+        [&](int z, const double* s) {
+            float aB = 0.f, aD = 0.f, aE = 0.f;
+            if (col && mnext) {
+                double rho;
+                lcc_coef(s, &aB, &aD, &aE, &rho);
+                acc[0] += 1.0;
+                acc[1] += rho;
+            }
+            if (col) {
+                const long long v = z * sz + c0;
+                A[v] = aB;
+                A[N + v] = aD;
+                A[2 * N + v] = aE;
+            }
+        });
+    block_sum<kBlock, 2>(acc, red);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = acc[0];
+        part[2 * blockIdx.x + 1] = acc[1];
+    }
+}
+
+template <int R, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_lcc_grad_fused(const PairDesc P, const float* __restrict__ A, const float* __restrict__ F,
+                 const float* __restrict__ W, const uint8_t* __restrict__ mk,
+                 const float* __restrict__ dW, const double* __restrict__ scal, float lambda,
+                 int lam_acc, float* __restrict__ g) {
+    __shared__ XYPlane<R, 3> L;
+    const int ntx = cdiv(P.n[0], kTX), nty = cdiv(P.n[1], kTY);
+    const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty;
+    const int z0 = (blockIdx.x / (ntx * nty)) * kZc, z1 = min(P.n[2], z0 + kZc);
+    const int x = bx * kTX + threadIdx.x % kTX, y = by * kTY + threadIdx.x / kTX;
+    const bool col = x < P.n[0] && y < P.n[1];
+    const long long N = P.nvox;
+    const long long c0 = col ? (long long)y * P.n[0] + x : 0;
+    const long long sz = (long long)P.n[0] * P.n[1];
+    const double inv = scal[0];
+    // per-voxel inputs of the next output plane
+    uint8_t m = 0;
+    float w = 0.f, f = 0.f, d[DIM], g0[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) d[a] = g0[a] = 0.f;
+    z_ring_walk<R, 3, 1>(
+        P, L, bx, by, z0, z1, A, A + N, A + 2 * N, nullptr,
+        [&](int z) {
+            const long long v = z * sz + c0;
+            m = mk[v];
+            w = W[v];
+            f = F[v];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                d[a] = dW[a * N + v];
+                if (lam_acc) g0[a] = g[a * N + v];
+            }
+        },
+        [&](int z, const double* s) {
+            if (!col) return;
+            const long long v = z * sz + c0;
+            float dsdw = 0.f;
+            if (m) dsdw = (float)(-inv * (s[0] + 2.0 * (double)w * s[1] + (double)f * s[2]));
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                const float img = dsdw * d[a] * P.s[a];
+                g[a * N + v] = lam_acc ? fmaf(lambda, g0[a], img) : img;
+            }
+        });
+}
+
 __host__ inline int lcc_grid(long long n) {
     const long long b = (n + kBlock - 1) / kBlock;
     return (int)(b < 65536 ? (b < 1 ? 1 : b) : 65536);
@@ -257,11 +549,16 @@ __host__ inline size_t box_lds(int nch, int r) {
 
 }  // namespace
 
-// Blocks of the statistics z pass (its partial-sum slots).
+// Partial-sum slots of the statistics pass (the larger of the two forms).
 int lcc_partials(const PairDesc& P) {
     const long long items = (long long)P.n[0] * P.n[1] * cdiv(P.n[2], kZSeg);
-    return (int)((items + kBlock - 1) / kBlock);
+    const int zpass = (int)((items + kBlock - 1) / kBlock);
+    const int fused = cdiv(P.n[0], kTX) * cdiv(P.n[1], kTY) * cdiv(P.n[2], kZc);
+    return max(zpass, fused);
 }
+
+// Whether the fused passes (no FP64 box-sum maps) serve this dimension and radius.
+bool lcc_fused(int dim, int r) { return dim == 3 && r >= 1 && r <= kMaxFusedR; }
 
 // LDS of the box passes at radius r (the largest, six channels).
 size_t lcc_lds_bytes(int r) { return box_lds(6, r); }
@@ -277,7 +574,6 @@ hipError_t launch_lcc(const PairDesc& P, int dim, int r, const float* F, const f
                       float* value, float* grad, hipStream_t s) {
     const int rz = dim == 3 ? r : 0;
     const int nxy = cdiv(P.n[0], kTX) * cdiv(P.n[1], kTY) * P.n[2];
-    const int nblk = lcc_partials(P);
     const int acc = lam_acc ? 1 : 0;
     if (dim == 3)
         hipLaunchKernelGGL(k_lcc_sample<3>, dim3(lcc_grid(P.nvox)), dim3(kBlock), 0, s, P, M, u,
@@ -285,6 +581,51 @@ hipError_t launch_lcc(const PairDesc& P, int dim, int r, const float* F, const f
     else
         hipLaunchKernelGGL(k_lcc_sample<2>, dim3(lcc_grid(P.nvox)), dim3(kBlock), 0, s, P, M, u,
                            Wb, mk, dW);
+    if (lcc_fused(dim, r)) {
+        // fused passes: no FP64 maps in memory
+        const int nb = cdiv(P.n[0], kTX) * cdiv(P.n[1], kTY) * cdiv(P.n[2], kZc);
+        switch (r) {
+            case 1:
+                hipLaunchKernelGGL(k_lcc_stats_fused<1>, dim3(nb), dim3(kBlock), 0, s, P, F, Wb,
+                                   mk, A, part);
+                break;
+            case 2:
+                hipLaunchKernelGGL(k_lcc_stats_fused<2>, dim3(nb), dim3(kBlock), 0, s, P, F, Wb,
+                                   mk, A, part);
+                break;
+            case 3:
+                hipLaunchKernelGGL(k_lcc_stats_fused<3>, dim3(nb), dim3(kBlock), 0, s, P, F, Wb,
+                                   mk, A, part);
+                break;
+            default:
+                hipLaunchKernelGGL(k_lcc_stats_fused<4>, dim3(nb), dim3(kBlock), 0, s, P, F, Wb,
+                                   mk, A, part);
+                break;
+        }
+        hipLaunchKernelGGL(k_lcc_value, dim3(1), dim3(kBlock), 0, s, part, nb, lambda, acc, value,
+                           scal, flag);
+        if (!grad) return hipGetLastError();
+        switch (r) {
+            case 1:
+                hipLaunchKernelGGL((k_lcc_grad_fused<1, 3>), dim3(nb), dim3(kBlock), 0, s, P, A, F, Wb,
+                                   mk, dW, scal, lambda, acc, grad);
+                break;
+            case 2:
+                hipLaunchKernelGGL((k_lcc_grad_fused<2, 3>), dim3(nb), dim3(kBlock), 0, s, P, A, F, Wb,
+                                   mk, dW, scal, lambda, acc, grad);
+                break;
+            case 3:
+                hipLaunchKernelGGL((k_lcc_grad_fused<3, 3>), dim3(nb), dim3(kBlock), 0, s, P, A, F, Wb,
+                                   mk, dW, scal, lambda, acc, grad);
+                break;
+            default:
+                hipLaunchKernelGGL((k_lcc_grad_fused<4, 3>), dim3(nb), dim3(kBlock), 0, s, P, A, F, Wb,
+                                   mk, dW, scal, lambda, acc, grad);
+                break;
+        }
+        return hipGetLastError();
+    }
+    const int nblk = (int)(((long long)P.n[0] * P.n[1] * cdiv(P.n[2], kZSeg) + kBlock - 1) / kBlock);
     hipLaunchKernelGGL((k_lcc_box_xy<6, 0>), dim3(nxy), dim3(kBlock), box_lds(6, r), s, P, r, F,
                        Wb, nullptr, mk, S);
     hipLaunchKernelGGL(k_lcc_stats_z, dim3(nblk), dim3(kBlock), 0, s, P, rz, S, F, Wb, mk, A,
@@ -310,7 +651,31 @@ hipError_t launch_lcc_value(const PairDesc& P, int dim, int r, const float* F, c
                             uint32_t* flag, float* value, hipStream_t s) {
     const int rz = dim == 3 ? r : 0;
     const int nxy = cdiv(P.n[0], kTX) * cdiv(P.n[1], kTY) * P.n[2];
-    const int nblk = lcc_partials(P);
+    if (lcc_fused(dim, r)) {
+        const int nb = cdiv(P.n[0], kTX) * cdiv(P.n[1], kTY) * cdiv(P.n[2], kZc);
+        switch (r) {
+            case 1:
+                hipLaunchKernelGGL(k_lcc_stats_fused<1>, dim3(nb), dim3(kBlock), 0, s, P, F, Wimg,
+                                   mk, A, part);
+                break;
+            case 2:
+                hipLaunchKernelGGL(k_lcc_stats_fused<2>, dim3(nb), dim3(kBlock), 0, s, P, F, Wimg,
+                                   mk, A, part);
+                break;
+            case 3:
+                hipLaunchKernelGGL(k_lcc_stats_fused<3>, dim3(nb), dim3(kBlock), 0, s, P, F, Wimg,
+                                   mk, A, part);
+                break;
+            default:
+                hipLaunchKernelGGL(k_lcc_stats_fused<4>, dim3(nb), dim3(kBlock), 0, s, P, F, Wimg,
+                                   mk, A, part);
+                break;
+        }
+        hipLaunchKernelGGL(k_lcc_value, dim3(1), dim3(kBlock), 0, s, part, nb, 0.f, 0, value, scal,
+                           flag);
+        return hipGetLastError();
+    }
+    const int nblk = (int)(((long long)P.n[0] * P.n[1] * cdiv(P.n[2], kZSeg) + kBlock - 1) / kBlock);
     hipLaunchKernelGGL((k_lcc_box_xy<6, 0>), dim3(nxy), dim3(kBlock), box_lds(6, r), s, P, r, F,
                        Wimg, nullptr, mk, S);
     hipLaunchKernelGGL(k_lcc_stats_z, dim3(nblk), dim3(kBlock), 0, s, P, rz, S, F, Wimg, mk, A,
