@@ -292,6 +292,51 @@ def test_batched_c4_sizes_sampled_oracle():
         assert np.linalg.norm(gg - go) <= GRAD_TOL * np.linalg.norm(go)
 
 
+def test_batch64_128_launch_sampled_oracle():
+    """The 64 x 128^3 B-spline NCC (+ 0.05 diffusion) batch in one launch with
+    the tile configuration the benchmark uses (autotune cache, else the
+    default): every pair finite and unflagged and equal to its single call,
+    four pairs against the oracle. Eight image pairs, each under eight
+    different control grids."""
+    from paper_1806_09907_amd import tune
+    n = (128, 128, 128)
+    print("case batch64 128^3 launch", flush=True)
+    probs = [api.Problem(n=n, spacing=(8, 8, 8), similarity=api.SIM_NCC, lambda_diff=0.05)
+             for _ in range(64)]
+    imgs = []
+    for k in range(8):
+        rng = np.random.default_rng(synth.seed_for(1, 100 + k))
+        F = synth.blobs(probs[0].shape, 40, rng)
+        F = (F + rng.normal(0.0, 0.01, size=F.shape)).astype(np.float32)
+        M = np.ascontiguousarray(np.roll(F, (2, -1, 1), axis=(0, 1, 2)), dtype=np.float32)
+        imgs.append((F, M))
+    Ts = [synth.random_theta(n, (8, 8, 8), 1.0, 6000 + i) for i in range(64)]
+    Fg = [gpu(f) for f, _ in imgs]
+    Mg = [gpu(m) for _, m in imgs]
+    plan = api.Plan(probs)
+    tiling = tune.cached_tiling(plan)
+    if tiling is not None:
+        plan.set_tiling(tiling)
+    vals, grads, _ = api.objective_and_grad_batched(
+        plan, [Fg[i % 8] for i in range(64)], [Mg[i % 8] for i in range(64)],
+        [gpu(t) for t in Ts])
+    torch.cuda.synchronize()
+    assert not any(api.get_flags(plan))
+    assert bool(torch.isfinite(vals).all())
+    single = api.Plan(probs[0])
+    for i in range(64):
+        vs, gs = api.objective_and_grad(single, Fg[i % 8], Mg[i % 8], gpu(Ts[i]))
+        assert abs(float(vals[i]) - float(vs)) <= 1e-6 * abs(float(vs)), i
+        assert torch.linalg.norm(grads[i] - gs) <= 1e-6 * torch.linalg.norm(gs), i
+    for i in (0, 21, 42, 63):
+        F, M = imgs[i % 8]
+        vo, go, flags = O.objective_and_grad(oprob(probs[i]), F, M, Ts[i])
+        assert flags == 0
+        assert abs(float(vals[i]) - vo) <= VAL_TOL * abs(vo), i
+        gg = grads[i].double().cpu().numpy()
+        assert np.linalg.norm(gg - go) <= GRAD_TOL * np.linalg.norm(go), i
+
+
 # ------------------------------------------------------------------ edge cases
 
 def test_identical_images():
