@@ -81,6 +81,19 @@ def traffic_for(workload: str):
     return e["bytes_per_launch"]
 
 
+def pipes_for(workload: str):
+    """Pipe utilisation of the dominant kernel from committed counter runs
+    (same source hash as the traffic figure), or None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            e = json.load(f).get(workload)
+    except OSError:
+        return None
+    if not e or e.get("source_hash") != kernel_source_hash(workload) or "pipes" not in e:
+        return None
+    return {k: v for k, v in e["pipes"].items() if k not in ("definition", "command")}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -344,7 +357,8 @@ def run_batch(args, dev, sizes, workload, desc):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "k_fused3_s8 (NCC)", "kernel_ms": kern_ms,
-                     "algorithmic_bytes_per_launch": bytes_fused},
+                     "algorithmic_bytes_per_launch": bytes_fused,
+                     "pipes": pipes_for(workload)},
     }
 
 
