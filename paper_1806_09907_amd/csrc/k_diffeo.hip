@@ -311,35 +311,28 @@ k_compose_adj_tile(const PairDesc P, const float* __restrict__ u, const float* _
         ext[a] = hi - lo[a];
     }
     __syncthreads();
-    // the box holds at most N < 2^29 voxels: 32-bit index arithmetic
-    const int box = ext[0] * ext[1] * ext[2];
-    const int e01 = ext[0] * ext[1];
-    for (int i = threadIdx.x; i < box; i += NT) {
-        int x[3];
-        const int r = i / ext[0];
-        x[0] = lo[0] + (i - r * ext[0]);
-        x[1] = lo[1] + (DIM == 3 ? r % ext[1] : r);
-        x[2] = DIM == 3 ? lo[2] + i / e01 : 0;
-        const long long v = x[0] + (long long)P.n[0] * (x[1] + (DIM == 3 ? (long long)P.n[1] * x[2] : 0));
+    // One source voxel x (linear index v, displacement uv): its sample
+    // point, and if its cell reaches the tile, its corner terms.
+    auto source = [&](const int* x, long long v, const float* uv) {
         float f[3];
         int j[3];
         bool finite = true;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            const float pa0 = fmaf(u[a * N + v], P.s[a], (float)x[a]);
+            const float pa0 = fmaf(uv[a], P.s[a], (float)x[a]);
             if (!(pa0 == pa0) || pa0 == INFINITY || pa0 == -INFINITY) finite = false;
             const float pa = fminf(fmaxf(pa0, -1e9f), 1e9f);
             const float fl = floorf(pa);
             j[a] = (int)fl;
             f[a] = pa - fl;
         }
-        if (!finite) continue;
+        if (!finite) return;
         // skip sources whose cell misses the tile
         bool near = true;
 #pragma unroll
         for (int a = 0; a < DIM; ++a)
             if (j[a] + 1 < o[a] || j[a] > o[a] + TS - 1) near = false;
-        if (!near) continue;
+        if (!near) return;
         float go[3];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) go[c] = gout[c * N + v];
@@ -360,6 +353,39 @@ k_compose_adj_tile(const PairDesc P, const float* __restrict__ u, const float* _
 #pragma unroll
             for (int c = 0; c < DIM; ++c)
                 atomicAdd(&acc[c][t], (unsigned long long)__float2ll_rn(w * go[c] * scale));
+        }
+    };
+    // Scan of the box: a work item is one column of the box (all axes but
+    // the last) and a segment of ZS voxels along the last axis; the ZS
+    // displacement loads are all issued before the first is used. (The box
+    // holds at most N < 2^29 voxels: 32-bit index arithmetic.)
+    constexpr int ZS = 4;
+    constexpr int LA = DIM - 1;
+    const int ncol = DIM == 3 ? ext[0] * ext[1] : ext[0];
+    const int nseg = cdiv(ext[LA], ZS);
+    const long long stepv = DIM == 3 ? (long long)P.n[0] * P.n[1] : (long long)P.n[0];
+    for (int it = threadIdx.x; it < ncol * nseg; it += NT) {
+        const int col = it % ncol, seg = it / ncol;
+        int xb[3];
+        xb[0] = lo[0] + col % ext[0];
+        xb[1] = DIM == 3 ? lo[1] + col / ext[0] : lo[1] + seg * ZS;
+        xb[2] = DIM == 3 ? lo[2] + seg * ZS : 0;
+        const int zb = xb[LA], nz_ = min(ZS, lo[LA] + ext[LA] - zb);
+        const long long vb =
+            xb[0] + (long long)P.n[0] * (xb[1] + (DIM == 3 ? (long long)P.n[1] * xb[2] : 0));
+        float uu[ZS][3];
+#pragma unroll
+        for (int k = 0; k < ZS; ++k) {
+            const long long v = vb + (long long)min(k, nz_ - 1) * stepv;   // in the box
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) uu[k][a] = u[a * N + v];
+        }
+#pragma unroll
+        for (int k = 0; k < ZS; ++k) {
+            if (k >= nz_) break;
+            int x[3] = {xb[0], xb[1], xb[2]};
+            x[LA] = zb + k;
+            source(x, vb + k * stepv, uu[k]);
         }
     }
     __syncthreads();
