@@ -68,6 +68,8 @@ CASES = [
     ((40, 36, 44), api.TF_BSPLINE3, (8, 8, 8), (), 2, 0.05, 3, api.REG_DIFFUSION),
     ((40, 36, 44), api.TF_WENDLAND, (8, 8, 8), (16.0, 16.0, 16.0), 2, 0.05, 0,
      api.REG_DIFFUSION),
+    # the largest radius of the fused passes, ragged against their 32 x 8 x 16 blocks
+    ((45, 19, 35), api.TF_BSPLINE3, (8, 8, 8), (), 4, 0.05, 0, api.REG_DIFFUSION),
 ]
 
 
@@ -78,6 +80,24 @@ def test_objective_parity(n, tf, sp, sig, r, lam, K, reg):
                     lcc_radius=r, lambda_diff=lam, diffeo_steps=K, regulariser=reg)
     F, M = inputs(n, 7)
     th = theta_for(p, 2)
+    plan = api.Plan(p)
+    v, g = api.objective_and_grad(plan, gpu(F), gpu(M), gpu(th))
+    torch.cuda.synchronize()
+    vo, go, flags = O.objective_and_grad(oprob(p), F, M, th)
+    assert flags == 0 and api.get_flags(plan)[0] == 0
+    assert abs(float(v) - vo) <= VAL_TOL * abs(vo)
+    assert rel(g.double().cpu().numpy(), go) <= GRAD_TOL
+
+
+def test_window_larger_than_volume():
+    """A 6 x 5 x 4 volume under a radius-3 window (every window clipped on
+    every axis), dense field of 0.3 voxels."""
+    n = (6, 5, 4)
+    print("case lcc objective n=(6, 5, 4) r=3", flush=True)
+    p = api.Problem(n=n, transform=api.TF_DENSE, spacing=(1, 1, 1), similarity=api.SIM_LCC,
+                    lcc_radius=3, lambda_diff=0.1)
+    F, M = inputs(n, 7)
+    th = synth.smooth_dense(p.n, 0.3, 2, sigma=1.0)
     plan = api.Plan(p)
     v, g = api.objective_and_grad(plan, gpu(F), gpu(M), gpu(th))
     torch.cuda.synchronize()
