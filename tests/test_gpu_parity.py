@@ -91,8 +91,12 @@ def test_bspline_objective_parity(n, sp, sim, lam, kind):
     assert eg <= GRAD_TOL, eg
 
 
-@pytest.mark.parametrize("tiling", range(8))
+NTILING3 = 10   # air_tiling_count(3); the first check below keeps the two in step
+
+
+@pytest.mark.parametrize("tiling", range(NTILING3))
 def test_every_tiling_matches_oracle(tiling):
+    assert api.tiling_count(3) == NTILING3
     n, sp = (70, 45, 53), (8, 8, 8)
     for sim in (api.SIM_NCC, api.SIM_MSE):
         print(f"case tiling={tiling} sim={sim}", flush=True)
