@@ -76,6 +76,10 @@ static const TileCfg kCfg3[] = {
     {16, 16, 4}, {16, 16, 16}, {32, 8, 2}, {16, 16, 8}, {16, 16, 2},
 };
 static const TileCfg kCfg2[] = {{64, 1, 2}, {64, 1, 4}, {64, 1, 8}, {64, 1, 16}};
+// candidates of the default 3D spacing-8 configuration, longest column first
+// (16 x 16 with 16, 8, 4, 2 cells), and the tile count that fills the chip
+static const int kCfg3Fill[] = {6, 8, 5, 9};
+constexpr int kFillTiles = 4096;
 
 // kernel variant ids understood by launch_bspline (3D)
 static int variant_of(const TileCfg& c, bool all_s8) {
@@ -772,6 +776,27 @@ air_status air_plan_create(const air_problem* probs, int32_t npairs, air_plan** 
     if (st != AIR_OK) {
         delete P;
         return st;
+    }
+    // Default tile configuration of 3D spacing-8 B-spline plans: 16 x 16
+    // columns, the longest column (16, 8, 4, 2 cells) whose launch still has
+    // kFillTiles tiles, else the one with the most tiles. air_plan_set_tiling
+    // (and the autotuner) override it.
+    if (P->variant == 3) {
+        int chosen = -1;
+        for (int id : kCfg3Fill) {
+            P->tiling = id;
+            if (build_tables(P) != AIR_OK) continue;
+            chosen = id;
+            if (P->ntiles_total >= kFillTiles) break;
+        }
+        if (chosen != P->tiling) {
+            P->tiling = chosen >= 0 ? chosen : 0;
+            st = build_tables(P);
+            if (st != AIR_OK) {
+                delete P;
+                return st;
+            }
+        }
     }
     *out = P;
     return AIR_OK;

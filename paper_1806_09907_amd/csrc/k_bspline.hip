@@ -1107,10 +1107,18 @@ __device__ inline void tile_range(int j, int sp, int n, int T, int* lo, int* hi)
     *hi = (b >= a) ? b / T : -1;
 }
 
-template <int TX, int TY, int SIM, int DIM>
+// NS lanes per control (1, or 8 when the launch has few controls to fill the
+// chip with): the tiles whose window holds the control are visited in a
+// fixed order and slot s goes to lane s mod NS; the lanes' FP64 sums meet in
+// a fixed xor butterfly, so every lane holds the same, order-fixed total.
+constexpr int kFinLanes = 8;
+constexpr long long kFinFewControls = 1 << 17;   // below this many, NS = kFinLanes
+
+template <int TX, int TY, int SIM, int DIM, int NS>
 __global__ void __launch_bounds__(kBlock)
 k_finalize(const LaunchCtx C) {
     constexpr int NT = kBlock;
+    constexpr int CPB = NT / NS;   // controls per block
     constexpr int NF = (SIM == AIR_SIM_NCC) ? 3 : 1;
     const int pair = blockIdx.y;
     const PairDesc P = C.pairs[pair];
@@ -1125,66 +1133,73 @@ k_finalize(const LaunchCtx C) {
     k.degenerate = sc[6] != 0.0;
     uint32_t* flags = reinterpret_cast<uint32_t*>(C.ws + C.L.flags) + pair;
     const int nctrl = P.nc[0] * P.nc[1] * (DIM == 3 ? P.nc[2] : 1);
-    const int j = blockIdx.x * NT + threadIdx.x;
-    if (j >= nctrl) return;
-    const int jx = j % P.nc[0];
-    const int jy = (j / P.nc[0]) % P.nc[1];
-    const int jz = (DIM == 3) ? j / (P.nc[0] * P.nc[1]) : 0;
+    const int ls = threadIdx.x % NS;
+    const int j = blockIdx.x * CPB + threadIdx.x / NS;
+    const bool live = j < nctrl;
     const float* part = reinterpret_cast<const float*>(C.ws + C.L.part) + P.part_off;
     const float* rg = reinterpret_cast<const float*>(C.ws + C.L.reggrad) + P.param_off;
     float* grad = C.grad_tab ? C.grad_tab[pair] : C.grad0;
-    const int WxM = P.win[0], WyM = (DIM == 3) ? P.win[1] : 1, WzM = P.win[2];
+    const int WxM = P.win[0], WyM = (DIM == 3) ? P.win[1] : 1;
     double g[DIM];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) g[c] = 0.0;
-    // column axis: z in 3D, y in 2D
-    const int colax = DIM - 1;
-    const int jc = (DIM == 3) ? jz : jy;
-    const int ncell = (P.n[colax] - 1) / P.sp[colax] + 1;
-    const int tc_lo = max(0, jc - 3) / P.col_cells;
-    const int tc_hi = min(ncell - 1, jc) / P.col_cells;
-    int tx_lo, tx_hi, ty_lo = 0, ty_hi = 0;
-    tile_range(jx, P.sp[0], P.n[0], TX, &tx_lo, &tx_hi);
-    if (DIM == 3) tile_range(jy, P.sp[1], P.n[1], TY, &ty_lo, &ty_hi);
-    if (!k.degenerate) {
-        for (int tc = tc_lo; tc <= tc_hi; ++tc) {
+    if (live && !k.degenerate) {
+        const int jx = j % P.nc[0];
+        const int jy = (j / P.nc[0]) % P.nc[1];
+        const int jz = (DIM == 3) ? j / (P.nc[0] * P.nc[1]) : 0;
+        // column axis: z in 3D, y in 2D
+        const int colax = DIM - 1;
+        const int jc = (DIM == 3) ? jz : jy;
+        const int ncell = (P.n[colax] - 1) / P.sp[colax] + 1;
+        const int tc_lo = max(0, jc - 3) / P.col_cells;
+        const int tc_hi = min(ncell - 1, jc) / P.col_cells;
+        int tx_lo, tx_hi, ty_lo = 0, ty_hi = 0;
+        tile_range(jx, P.sp[0], P.n[0], TX, &tx_lo, &tx_hi);
+        if (DIM == 3) tile_range(jy, P.sp[1], P.n[1], TY, &ty_lo, &ty_hi);
+        int slot = 0;
+        for (int tc = tc_lo; tc <= tc_hi; ++tc)
+        for (int ty = ty_lo; ty <= ty_hi; ++ty)
+        for (int tx = tx_lo; tx <= tx_hi; ++tx) {
+            if ((slot++ & (NS - 1)) != ls) continue;
             const int kcl = jc - tc * P.col_cells;
-            for (int ty = ty_lo; ty <= ty_hi; ++ty) {
-                int kyl = 0;
-                if (DIM == 3) {
-                    int cy0, Wy;
-                    ctrl_window(ty * TY, min(ty * TY + TY, P.n[1]), P.sp[1], &cy0, &Wy);
-                    kyl = jy - cy0;
-                    if (kyl < 0 || kyl >= Wy) continue;
-                }
-                for (int tx = tx_lo; tx <= tx_hi; ++tx) {
-                    const int cells_t = min(P.col_cells, ncell - tc * P.col_cells);
-                    if (kcl >= cells_t + 3) continue;
-                    int cx0, Wx;
-                    ctrl_window(tx * TX, min(tx * TX + TX, P.n[0]), P.sp[0], &cx0, &Wx);
-                    const int kxl = jx - cx0;
-                    if (kxl < 0 || kxl >= Wx) continue;
-                    const int tl = (DIM == 3) ? (tc * P.ntile[1] + ty) * P.ntile[0] + tx
-                                              : tc * P.ntile[0] + tx;
-                    const float* pt = part + (long long)tl * P.part_stride;
-                    double cF = k.alpha, cW = k.beta, c1 = 0.0;
-                    if (SIM == AIR_SIM_NCC) {
-                        const double* s = stats + (long long)(P.tile_begin + tl) * kStatWords;
-                        c1 = k.alpha * (s[6] - k.muF) + k.beta * (s[7] - k.muW);
-                    }
-                    // partial layout [column][y][x][field * DIM + component]
-                    const float* q = pt + (((long long)kcl * WyM + kyl) * WxM + kxl) * (NF * DIM);
+            int kyl = 0;
+            if (DIM == 3) {
+                int cy0, Wy;
+                ctrl_window(ty * TY, min(ty * TY + TY, P.n[1]), P.sp[1], &cy0, &Wy);
+                kyl = jy - cy0;
+                if (kyl < 0 || kyl >= Wy) continue;
+            }
+            const int cells_t = min(P.col_cells, ncell - tc * P.col_cells);
+            if (kcl >= cells_t + 3) continue;
+            int cx0, Wx;
+            ctrl_window(tx * TX, min(tx * TX + TX, P.n[0]), P.sp[0], &cx0, &Wx);
+            const int kxl = jx - cx0;
+            if (kxl < 0 || kxl >= Wx) continue;
+            const int tl = (DIM == 3) ? (tc * P.ntile[1] + ty) * P.ntile[0] + tx
+                                      : tc * P.ntile[0] + tx;
+            const float* pt = part + (long long)tl * P.part_stride;
+            double cF = k.alpha, cW = k.beta, c1 = 0.0;
+            if (SIM == AIR_SIM_NCC) {
+                const double* st = stats + (long long)(P.tile_begin + tl) * kStatWords;
+                c1 = k.alpha * (st[6] - k.muF) + k.beta * (st[7] - k.muW);
+            }
+            // partial layout [column][y][x][field * DIM + component]
+            const float* q = pt + (((long long)kcl * WyM + kyl) * WxM + kxl) * (NF * DIM);
 #pragma unroll
-                    for (int c = 0; c < DIM; ++c) {
-                        if (SIM == AIR_SIM_NCC)
-                            g[c] += cF * q[c] + cW * q[DIM + c] + c1 * q[2 * DIM + c];
-                        else
-                            g[c] += cF * q[c];
-                    }
-                }
+            for (int c = 0; c < DIM; ++c) {
+                if (SIM == AIR_SIM_NCC)
+                    g[c] += cF * q[c] + cW * q[DIM + c] + c1 * q[2 * DIM + c];
+                else
+                    g[c] += cF * q[c];
             }
         }
     }
+    static_assert((NS & (NS - 1)) == 0 && NS <= 64, "NS: a power of two within a wave");
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+        for (int o = NS / 2; o >= 1; o >>= 1) g[c] += __shfl_xor(g[c], o, NS);
+    if (!live || ls != 0) return;
     uint32_t bad = 0;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
@@ -1192,7 +1207,6 @@ k_finalize(const LaunchCtx C) {
         grad[(long long)c * nctrl + j] = out;
         if (!isfinite(out)) bad = 1;
     }
-    (void)NF;
     if (bad) atomicOr(flags, AIR_FLAG_NONFINITE);
 }
 
@@ -1218,8 +1232,13 @@ static hipError_t launch_fin(const LaunchCtx& C, int max_ctrl, hipStream_t s) {
     hipLaunchKernelGGL((k_pair_coef<SIM>), dim3(C.npairs), dim3(kBlock), 0, s, C);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dim3 grid(cdiv(max_ctrl, kBlock), C.npairs);
-    hipLaunchKernelGGL((k_finalize<TX, TY, SIM, DIM>), grid, dim3(kBlock), 0, s, C);
+    if ((long long)max_ctrl * C.npairs < kFinFewControls) {
+        dim3 grid(cdiv(max_ctrl, kBlock / kFinLanes), C.npairs);
+        hipLaunchKernelGGL((k_finalize<TX, TY, SIM, DIM, kFinLanes>), grid, dim3(kBlock), 0, s, C);
+    } else {
+        dim3 grid(cdiv(max_ctrl, kBlock), C.npairs);
+        hipLaunchKernelGGL((k_finalize<TX, TY, SIM, DIM, 1>), grid, dim3(kBlock), 0, s, C);
+    }
     return hipGetLastError();
 }
 

@@ -258,7 +258,8 @@ def test_batched_uneven_matches_single_and_oracle():
             plan, [gpu(a) for a in Fs], [gpu(a) for a in Ms], [gpu(a) for a in Ts])
         torch.cuda.synchronize()
         for i, p in enumerate(probs):
-            vs, gs = api.objective_and_grad(api.Plan(p), gpu(Fs[i]), gpu(Ms[i]), gpu(Ts[i]))
+            vs, gs = api.objective_and_grad(api.Plan(p, tiling=plan.tiling), gpu(Fs[i]),
+                                            gpu(Ms[i]), gpu(Ts[i]))
             assert abs(float(vals[i]) - float(vs)) <= 1e-6 * abs(float(vs))
             assert torch.linalg.norm(grads[i] - gs) <= 1e-6 * torch.linalg.norm(gs)
             vo, go, _ = O.objective_and_grad(oprob(p), Fs[i], Ms[i], Ts[i])
@@ -286,7 +287,9 @@ def test_batched_c4_sizes_sampled_oracle():
         plan, [gpu(a) for a in Fs], [gpu(a) for a in Ms], [gpu(a) for a in Ts])
     torch.cuda.synchronize()
     for i in range(48):
-        vs, gs = api.objective_and_grad(api.Plan(probs[i]), gpu(Fs[i]), gpu(Ms[i]), gpu(Ts[i]))
+        # the same tile configuration: batching alone must not change the result
+        vs, gs = api.objective_and_grad(api.Plan(probs[i], tiling=plan.tiling), gpu(Fs[i]),
+                                        gpu(Ms[i]), gpu(Ts[i]))
         assert abs(float(vals[i]) - float(vs)) <= 1e-6 * abs(float(vs))
         assert torch.linalg.norm(grads[i] - gs) <= 1e-6 * torch.linalg.norm(gs)
     for i in (0, 7, 19, 23, 31, 47):
@@ -327,7 +330,7 @@ def test_batch64_128_launch_sampled_oracle():
     torch.cuda.synchronize()
     assert not any(api.get_flags(plan))
     assert bool(torch.isfinite(vals).all())
-    single = api.Plan(probs[0])
+    single = api.Plan(probs[0], tiling=plan.tiling)   # same tiles as the batch
     for i in range(64):
         vs, gs = api.objective_and_grad(single, Fg[i % 8], Mg[i % 8], gpu(Ts[i]))
         assert abs(float(vals[i]) - float(vs)) <= 1e-6 * abs(float(vs)), i
