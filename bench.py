@@ -108,6 +108,8 @@ def parse():
                     help="time every tile configuration on this batch, write the cache here")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-single-pair", action="store_true",
+                    help="skip the one-pair latency loop of the default workload")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
@@ -342,7 +344,8 @@ def run_batch(args, dev, sizes, workload, desc):
     traffic = traffic_for(workload)
     extra = {}
     if workload == "batch128":
-        extra["single_pair"] = single_pair_latency(Fs[0], Ms[0], Ts[0], probs[0])
+        if not args.no_single_pair:
+            extra["single_pair"] = single_pair_latency(Fs[0], Ms[0], Ts[0], probs[0])
     return {**extra,
         "metric": "objective+grad evals/s at 128^3 B-spline NCC" if workload == "batch128"
         else f"objective+grad evals/s, {desc}",
