@@ -648,12 +648,21 @@ def run_latency2d(args, dev):
                              lambda: api.objective_and_grad(plan, F, M, th, value, grad))
     bytes_eval = 4 * (2 * 64 * 64 + 2 * 2 * 11 * 11)
     achieved = bytes_eval / (kern_ms / 1e3) / 1e9
+    # the registration loop of this configuration (100 Adam iterations, lr
+    # 0.01, from zero): eager launches against replays of one captured graph
+    from paper_1806_09907_amd.registration import Registration
+    prob = plan.problems[0]
+    loop = {"iterations": 100, "graph_chunk": 25}
+    for mode, chunk in (("eager", 0), ("graph", 25)):
+        Registration(prob, F, M, lr=0.01, iterations=100).run(graph_chunk=chunk)   # warm-up
+        r = Registration(prob, F, M, lr=0.01, iterations=100).run(graph_chunk=chunk)
+        loop[f"{mode}_us_per_iteration"] = r.seconds * 1e6 / 100
     return {
         "metric": "objective+grad evals/s, 64^2 B-spline MSE + 0.1 diffusion (latency)",
         "value": 1e3 / ms_step, "unit": "evals/s", "ms_per_step": ms_step,
         "config": {"workload": "64^2 blobs, B-spline spacing 8, one pair per step",
                    "n": list(n), "algorithmic_bytes_per_step": bytes_eval,
-                   "us_per_eval": ms_step * 1e3},
+                   "us_per_eval": ms_step * 1e3, "registration_loop": loop},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None,
                      "kernel": "k_fused2 (MSE)", "kernel_ms": kern_ms,

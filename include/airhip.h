@@ -196,6 +196,19 @@ air_status air_adam_step(float* theta, const float* grad, float* m, float* v, in
                          float lr, float b1, float b2, float eps, int32_t step,
                          void* stream);
 
+/* The bias-corrected step sizes of Adam step `step` (>= 1), as air_adam_step
+ * uses them: out[0] = lr / (1 - b1^step), out[1] = 1 / sqrt(1 - b2^step),
+ * computed in double and rounded to float. Host only. */
+air_status air_adam_bias_terms(float lr, float b1, float b2, int32_t step, float* out);
+
+/* air_adam_step with the two factors of air_adam_bias_terms read from the
+ * device array coef[2] (8-byte aligned) when the kernel runs, so that one
+ * captured HIP graph of an optimisation loop serves every step: the caller
+ * refreshes coef between replays. Same arithmetic and rounding as
+ * air_adam_step with those factors. */
+air_status air_adam_step_dev(float* theta, const float* grad, float* m, float* v, int64_t n,
+                             const float* coef, float b1, float b2, float eps, void* stream);
+
 /* x[i] *= *s for i < n, with s a device scalar (autograd chain rule). */
 air_status air_scale(float* x, const float* s, int64_t n, void* stream);
 

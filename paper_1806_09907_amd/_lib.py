@@ -59,6 +59,8 @@ SIGNATURES = {
     "air_objective_and_grad": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "air_objective_and_grad_batched": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "air_adam_step": (_i32, [_vp, _vp, _vp, _vp, _i64, _f32, _f32, _f32, _f32, _i32, _vp]),
+    "air_adam_bias_terms": (_i32, [_f32, _f32, _f32, _i32, _vp]),
+    "air_adam_step_dev": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _f32, _f32, _f32, _vp]),
     "air_scale": (_i32, [_vp, _vp, _i64, _vp]),
     "air_get_flags": (_i32, [_vp, _vp, _vp, _vp]),
     "air_pyramid_workspace_bytes": (_i32, [_vp, ctypes.POINTER(_sz)]),

@@ -299,6 +299,31 @@ def adam_step(theta: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch
                               lr, b1, b2, eps, int(step), _stream()), "air_adam_step")
 
 
+def adam_bias_terms(first_step: int, count: int, lr: float = 0.01, b1: float = 0.9,
+                    b2: float = 0.999):
+    """[count][2] float32 host array of air_adam_bias_terms for steps
+    first_step .. first_step + count - 1."""
+    import numpy as np
+    out = np.empty((count, 2), dtype=np.float32)
+    for k in range(count):
+        check(lib().air_adam_bias_terms(lr, b1, b2, int(first_step + k),
+                                        out[k].ctypes.data_as(ctypes.c_void_p)),
+              "air_adam_bias_terms")
+    return out
+
+
+def adam_step_dev(theta: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+                  coef: torch.Tensor, b1: float = 0.9, b2: float = 0.999,
+                  eps: float = 1e-8) -> None:
+    """Adam with the step's two bias-correction factors read from the device
+    tensor coef [2] (capturable in a HIP graph)."""
+    for t, nm in ((theta, "theta"), (grad, "grad"), (m, "m"), (v, "v")):
+        _need(t, theta.shape, name=nm)
+    _need(coef, (2,), name="coef")
+    check(lib().air_adam_step_dev(_ptr(theta), _ptr(grad), _ptr(m), _ptr(v), theta.numel(),
+                                  _ptr(coef), b1, b2, eps, _stream()), "air_adam_step_dev")
+
+
 def scale_(x: torch.Tensor, s: torch.Tensor) -> torch.Tensor:
     _need(x, None, name="x")
     _need(s, (), name="s")

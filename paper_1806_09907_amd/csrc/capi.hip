@@ -26,6 +26,8 @@ hipError_t launch_warp(const PairDesc* dpairs, int pair, const PairDesc& hp, con
 hipError_t launch_similarity(const float* F, const float* W, const uint8_t* mask, long long N,
                              int sim, double* slots, int nslots, float* value, uint32_t* flag,
                              hipStream_t s);
+hipError_t launch_adam_dev(float* th, const float* g, float* m, float* v, long long n,
+                           const float* coef, float b1, float b2, float eps, hipStream_t s);
 hipError_t launch_adam(float* th, const float* g, float* m, float* v, long long n, float lr_bc1,
                        float b1, float b2, float inv_sqrt_bc2, float eps, hipStream_t s);
 hipError_t launch_scale(float* x, const float* s, long long n, hipStream_t st);
@@ -1009,19 +1011,48 @@ air_status air_objective_and_grad_batched(const air_plan* plan, const float* con
     return run_objective(plan, C, (hipStream_t)stream);
 }
 
-air_status air_adam_step(float* theta, const float* grad, float* m, float* v, int64_t n, float lr,
-                         float b1, float b2, float eps, int32_t step, void* stream) {
+air_status air_adam_bias_terms(float lr, float b1, float b2, int32_t step, float* out) {
+    if (!out) return AIR_ERR_INVALID_ARG;
+    if (step < 1) return AIR_ERR_SHAPE;
+    if (!(b1 >= 0.f && b1 < 1.f) || !(b2 >= 0.f && b2 < 1.f) || !(lr >= 0.f))
+        return AIR_ERR_INVALID_ARG;
+    const double bc1 = 1.0 - pow((double)b1, step);
+    const double bc2 = 1.0 - pow((double)b2, step);
+    out[0] = (float)(lr / bc1);
+    out[1] = (float)(1.0 / sqrt(bc2));
+    return AIR_OK;
+}
+
+static air_status adam_args(const float* theta, const float* grad, const float* m, const float* v,
+                            int64_t n, float b1, float b2, float eps) {
     if (!theta || !grad || !m || !v) return AIR_ERR_INVALID_ARG;
-    if (n < 0 || step < 1) return AIR_ERR_SHAPE;
-    if (!(b1 >= 0.f && b1 < 1.f) || !(b2 >= 0.f && b2 < 1.f) || !(eps >= 0.f) || !(lr >= 0.f))
+    if (n < 0) return AIR_ERR_SHAPE;
+    if (!(b1 >= 0.f && b1 < 1.f) || !(b2 >= 0.f && b2 < 1.f) || !(eps >= 0.f))
         return AIR_ERR_INVALID_ARG;
     if (!aligned16(theta) || !aligned16(grad) || !aligned16(m) || !aligned16(v))
         return AIR_ERR_ALIGN;
+    return AIR_OK;
+}
+
+air_status air_adam_step(float* theta, const float* grad, float* m, float* v, int64_t n, float lr,
+                         float b1, float b2, float eps, int32_t step, void* stream) {
+    air_status st = adam_args(theta, grad, m, v, n, b1, b2, eps);
+    if (st != AIR_OK) return st;
+    float c[2];
+    if ((st = air_adam_bias_terms(lr, b1, b2, step, c)) != AIR_OK) return st;
     if (n == 0) return AIR_OK;
-    const double bc1 = 1.0 - pow((double)b1, step);
-    const double bc2 = 1.0 - pow((double)b2, step);
-    hipError_t e = launch_adam(theta, grad, m, v, n, (float)(lr / bc1), b1, b2,
-                               (float)(1.0 / sqrt(bc2)), eps, (hipStream_t)stream);
+    hipError_t e = launch_adam(theta, grad, m, v, n, c[0], b1, b2, c[1], eps, (hipStream_t)stream);
+    return e == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_adam_step_dev(float* theta, const float* grad, float* m, float* v, int64_t n,
+                             const float* coef, float b1, float b2, float eps, void* stream) {
+    air_status st = adam_args(theta, grad, m, v, n, b1, b2, eps);
+    if (st != AIR_OK) return st;
+    if (!coef) return AIR_ERR_INVALID_ARG;
+    if (((uintptr_t)coef & 7u) != 0) return AIR_ERR_ALIGN;
+    if (n == 0) return AIR_OK;
+    hipError_t e = launch_adam_dev(theta, grad, m, v, n, coef, b1, b2, eps, (hipStream_t)stream);
     return e == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
 }
 

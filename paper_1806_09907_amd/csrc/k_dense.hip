@@ -745,6 +745,33 @@ hipError_t launch_adam(float* th, const float* g, float* m, float* v, long long 
     return hipGetLastError();
 }
 
+// The same update with the two bias-correction factors read from device
+// memory (coef[0] = lr / (1 - b1^t), coef[1] = 1 / sqrt(1 - b2^t)).
+__global__ void __launch_bounds__(kBlock)
+k_adam_dev(float* __restrict__ th, const float* __restrict__ g, float* __restrict__ m,
+           float* __restrict__ v, long long n, const float* __restrict__ coef, float b1, float b2,
+           float eps) {
+    const float lr_bc1 = coef[0], inv_sqrt_bc2 = coef[1];
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kBlock) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        th[i] -= lr_bc1 * mi / (sqrtf(vi) * inv_sqrt_bc2 + eps);
+    }
+}
+
+hipError_t launch_adam_dev(float* th, const float* g, float* m, float* v, long long n,
+                           const float* coef, float b1, float b2, float eps, hipStream_t s) {
+    long long nb = (n + kBlock - 1) / kBlock;
+    const int grid = (int)(nb < 16384 ? nb : 16384);
+    hipLaunchKernelGGL(k_adam_dev, dim3(grid), dim3(kBlock), 0, s, th, g, m, v, n, coef, b1, b2,
+                       eps);
+    return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_scale(float* __restrict__ x, const float* __restrict__ sc, long long n) {
     const float s = *sc;

@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1806_09907_amd import _lib
@@ -96,6 +97,10 @@ def test_entry_points_validate_before_launch():
     # Adam and scale argument checks
     assert L.air_adam_step(A, A, A, A, 10, 0.01, 0.9, 0.999, 1e-8, 0, None) == 2
     assert L.air_adam_step(A, A, A, A, 10, 0.01, 1.5, 0.999, 1e-8, 1, None) == 1
+    assert L.air_adam_step_dev(A, A, A, A, 10, None, 0.9, 0.999, 1e-8, None) == 1
+    assert L.air_adam_step_dev(A, A, A, A, 10, A + 4, 0.9, 0.999, 1e-8, None) == 3
+    assert L.air_adam_step_dev(A, A, A, A, -1, A, 0.9, 0.999, 1e-8, None) == 2
+    assert L.air_adam_step_dev(A, A, A, A, 10, A, 0.9, 1.0, 1e-8, None) == 1
     assert L.air_scale(A + 8, A, 4, None) == 3
     assert L.air_scale(None, A, 4, None) == 1
     assert L.air_get_flags(h, None, None, None) == 1
@@ -163,3 +168,21 @@ def test_lcc_plans_hold_one_pair():
     with pytest.raises(_lib.AirError) as e:
         Plan([P(similarity=2), P(similarity=2)])
     assert e.value.status == 5
+
+
+def test_adam_bias_terms_match_the_definition():
+    """The bias-corrected step sizes of Adam (Kingma & Ba, as Sec. III-G
+    cites it): lr / (1 - b1^t) and 1 / sqrt(1 - b2^t), in double from the
+    float arguments, rounded to float."""
+    from paper_1806_09907_amd import api
+    lr, b1, b2 = 0.01, 0.9, 0.999
+    got = api.adam_bias_terms(1, 50, lr, b1, b2)
+    f = lambda x: float(np.float32(x))
+    for k in range(50):
+        t = k + 1
+        e0 = np.float32(f(lr) / (1.0 - f(b1) ** t))
+        e1 = np.float32(1.0 / np.sqrt(1.0 - f(b2) ** t))
+        assert got[k, 0] == e0 and got[k, 1] == e1, t
+    with pytest.raises(RuntimeError):
+        api.adam_bias_terms(0, 1)
+
