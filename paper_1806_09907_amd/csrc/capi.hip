@@ -26,6 +26,7 @@ hipError_t launch_warp(const PairDesc* dpairs, int pair, const PairDesc& hp, con
 hipError_t launch_similarity(const float* F, const float* W, const uint8_t* mask, long long N,
                              int sim, double* slots, int nslots, float* value, uint32_t* flag,
                              hipStream_t s);
+int dense_blocks(int dim, const int* n);
 hipError_t launch_adam_dev(float* th, const float* g, float* m, float* v, long long n,
                            const float* coef, float b1, float b2, float eps, hipStream_t s);
 hipError_t launch_adam(float* th, const float* g, float* m, float* v, long long n, float lr_bc1,
@@ -442,9 +443,7 @@ static air_status build_tables(air_plan* P) {
             (void)bspline_cell_tables(d, D, P->consts);
         // dense passes: dense models, and the objective at exp(v) or with LCC
         if (!bs || P->field_route()) {
-            const int nbx = cdiv(D.n[0], kDenseTX), nby = cdiv(D.n[1], kDenseTY);
-            const int nbz = d == 3 ? cdiv(D.n[2], kDenseZc) : 1;
-            D.dense_nblk = nbx * nby * nbz;
+            D.dense_nblk = dense_blocks(d, D.n);
             D.dense_blk_off = (int)dense_n;
             dense_n += D.dense_nblk;
             max_dense = std::max(max_dense, D.dense_nblk);

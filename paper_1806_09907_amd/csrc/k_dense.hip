@@ -22,21 +22,35 @@ struct DenseTile {
     bool act;
 };
 
+// A 2D block covers DTX x (DTY * kDenseRows2) pixels: lane row ly takes rows
+// y0 + ly + DTY r, r < kDenseRows2 (the "z" range of its tile), so a large
+// image does not become tens of thousands of tiny blocks whose partial sums
+// the single-block reductions then walk.
+constexpr int kDenseRows2 = 8;
+
+// Dense-pass blocks of one pair (host and device).
+__host__ __device__ inline int dense_blocks_of(int dim, const int* n) {
+    const int nbx = cdiv(n[0], DTX);
+    if (dim == 3) return nbx * cdiv(n[1], DTY) * cdiv(n[2], kDenseZc);
+    return nbx * cdiv(n[1], DTY * kDenseRows2);
+}
+
 __device__ inline DenseTile dense_tile(const PairDesc& P, int blk, int zc, int dim) {
-    const int nbx = cdiv(P.n[0], DTX), nby = cdiv(P.n[1], DTY);
+    const int ty = dim == 3 ? DTY : DTY * kDenseRows2;   // rows of a block
+    const int nbx = cdiv(P.n[0], DTX), nby = cdiv(P.n[1], ty);
     const int bx = blk % nbx;
     const int rest = blk / nbx;
     const int by = rest % nby;
     const int bz = rest / nby;
     DenseTile T;
     T.x = bx * DTX + (threadIdx.x % DTX);
-    T.y = by * DTY + (threadIdx.x / DTX);
+    T.y = by * ty + (threadIdx.x / DTX);
     if (dim == 3) {
         T.z0 = bz * zc;
         T.z1 = min(T.z0 + zc, P.n[2]);
     } else {
         T.z0 = 0;
-        T.z1 = 1;
+        T.z1 = kDenseRows2;   // row groups; rows at or past n[1] are skipped
     }
     T.act = (T.x < P.n[0]) && (T.y < P.n[1]);
     return T;
@@ -129,9 +143,13 @@ k_dense_pre(const LaunchCtx C, int zc) {
     float cnt = 0.f;   // at most zc per lane: exact in FP32
     if (T.act) {
         for (int z = T.z0; z < T.z1; ++z) {
-            const long long vi = ((long long)z * P.n[1] + T.y) * P.n[0] + T.x;
+            // 3D: plane z of the column; 2D: row group z of the lane
+            const int yy = DIM == 3 ? T.y : T.y + z * DTY;
+            const int zz = DIM == 3 ? z : 0;
+            if (DIM == 2 && yy >= P.n[1]) break;
+            const long long vi = ((long long)zz * P.n[1] + yy) * P.n[0] + T.x;
             float p[3];
-            const int idx[3] = {T.x, T.y, z};
+            const int idx[3] = {T.x, yy, zz};
             bool in = true;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
@@ -246,8 +264,9 @@ k_dense_main(const LaunchCtx C, int zc, int reg_only, float* reg_grad_out) {
     // per-lane sums over the z chunk in FP32, widened once per chunk
     float sq = 0.f, rr = 0.f;   // MSE sum of squares, regulariser sum
     if (T.act) {
-        const int x = T.x, y = T.y;
-        const bool inx = x <= nx - 2, iny = y <= ny - 2;
+        const int x = T.x;
+        int y = T.y;
+        const bool inx = x <= nx - 2;
         float um[3], u0[3], up[3];
         long long vi = ((long long)T.z0 * ny + y) * nx + x;
 #pragma unroll
@@ -255,7 +274,15 @@ k_dense_main(const LaunchCtx C, int zc, int reg_only, float* reg_grad_out) {
             u0[c] = th[c * N + vi];
             um[c] = (DIM == 3 && T.z0 > 0) ? th[c * N + vi - sz] : 0.f;
         }
-        for (int z = T.z0; z < T.z1; ++z, vi += sz) {
+        // 3D: walk z; 2D: walk the lane's row groups (y advances by DTY)
+        for (int z = T.z0; z < T.z1;
+             ++z, vi += (DIM == 3 ? sz : (long long)DTY * sy), y += (DIM == 3 ? 0 : DTY)) {
+            if (DIM == 2) {
+                if (y >= ny) break;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) u0[c] = th[c * N + vi];
+            }
+            const bool iny = y <= ny - 2;
             const bool has_zp = DIM == 3 && z + 1 < nz;
 #pragma unroll
             for (int c = 0; c < DIM; ++c) up[c] = has_zp ? th[c * N + vi + sz] : 0.f;
@@ -573,6 +600,8 @@ hipError_t launch_dense(const LaunchCtx& C, int zc, int max_blk, hipStream_t s, 
 }
 
 // Regulariser of a dense field for one pair (context holds that pair only).
+int dense_blocks(int dim, const int* n) { return dense_blocks_of(dim, n); }
+
 hipError_t launch_reg_dense(const LaunchCtx& C, int pair_blocks, int zc, float* grad_out,
                             float* value_out, hipStream_t s) {
     dim3 grid(xcd_grid(pair_blocks, 0), 1);
