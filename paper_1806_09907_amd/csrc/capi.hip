@@ -34,9 +34,9 @@ hipError_t launch_adam(float* th, const float* g, float* m, float* v, long long 
 hipError_t launch_scale(float* x, const float* s, long long n, hipStream_t st);
 hipError_t launch_velocity(const PairDesc& P, const float* consts_dev, int transform, int dim,
                            const float* theta, float scale, float* out, hipStream_t s);
-hipError_t launch_compose(const PairDesc& P, int dim, const float* u, float* out, hipStream_t s);
-hipError_t launch_field_reach(const PairDesc& P, int dim, const float* u, int nfields,
-                              unsigned int* dmax, hipStream_t s);
+hipError_t launch_compose(const PairDesc& P, int dim, const float* u, float* out,
+                          unsigned int* dmax, hipStream_t s);
+hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t s);
 hipError_t launch_compose_adjoint(const PairDesc& P, int dim, const float* u, const float* gout,
                                   const unsigned int* dmax, unsigned int* gmax_in,
                                   bool measure_in, unsigned int* gmax_out, float* gin,
@@ -600,9 +600,12 @@ static hipError_t diffeo_forward(const air_plan* P, const DeviceTables* T, unsig
     const PairDesc& hp = P->pd[0];
     const long long dN = (long long)P->dim * hp.nvox;
     float* U = reinterpret_cast<float*>(w + P->L.fields);
+    // each squaring also measures its input's reach for the adjoint
+    unsigned int* reach = reinterpret_cast<unsigned int*>(w + P->L.reach);
     hipError_t e = expand_field(P, T, w, theta, ldexpf(1.f, -P->diffeo), U, s);
+    if (e == hipSuccess && P->diffeo > 0) e = launch_zero_u32(reach, P->diffeo, s);
     for (int k = 0; k < P->diffeo && e == hipSuccess; ++k)
-        e = launch_compose(hp, P->dim, U + k * dN, U + (k + 1) * dN, s);
+        e = launch_compose(hp, P->dim, U + k * dN, U + (k + 1) * dN, reach + k, s);
     *uK = U + P->diffeo * dN;
     return e;
 }
@@ -660,8 +663,7 @@ static hipError_t run_diffeo(const air_plan* P, const DeviceTables* T, void* ws,
     }
     if (e != hipSuccess || !grad) return e;
     const float* U = reinterpret_cast<const float*>(w + P->L.fields);
-    unsigned int* reach = reinterpret_cast<unsigned int*>(w + P->L.reach);
-    if (P->diffeo > 0) e = launch_field_reach(hp, P->dim, U, P->diffeo, reach, s);
+    unsigned int* reach = reinterpret_cast<unsigned int*>(w + P->L.reach);   // from the forward pass
     for (int k = P->diffeo - 1; k >= 0 && e == hipSuccess; --k) {
         // the max |gradient| slots alternate: each call measures its output
         // for the next one

@@ -190,11 +190,18 @@ k_scale_copy(const float* __restrict__ in, float scale, long long n, int accumul
         out[i] = accumulate ? out[i] + scale * in[i] : scale * in[i];
 }
 
-// One squaring: out(x) = u(x) + u(x + u(x)).
+// One squaring: out(x) = u(x) + u(x + u(x)). It also measures the largest
+// displacement of its input u in voxels (max over voxels and axes of
+// |u_a| (n_a - 1)/2) into dmax, as the bits of a non-negative float (ordered
+// like unsigned integers; NaN compares above every finite value): the reach
+// of this squaring's adjoint. dmax must be zero before the launch.
 template <int DIM>
 __global__ void __launch_bounds__(kBlock)
-k_compose(const PairDesc P, const float* __restrict__ u, float* __restrict__ out) {
+k_compose(const PairDesc P, const float* __restrict__ u, float* __restrict__ out,
+          unsigned int* __restrict__ dmax) {
+    __shared__ unsigned int red[kBlock / 64];
     const long long N = P.nvox;
+    float m = 0.f;
     for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < N;
          v += (long long)gridDim.x * kBlock) {
         int idx[3];
@@ -202,30 +209,15 @@ k_compose(const PairDesc P, const float* __restrict__ u, float* __restrict__ out
         float p[3], val[3], f[3];
         int j[3];
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) p[a] = fmaf(u[a * N + v], P.s[a], (float)idx[a]);
+        for (int a = 0; a < DIM; ++a) {
+            const float ua = u[a * N + v];
+            const float t = fabsf(ua) * P.s[a];
+            m = (t > m || !(t == t)) ? t : m;
+            p[a] = fmaf(ua, P.s[a], (float)idx[a]);
+        }
         field_sample<DIM, false>(u, N, P, p, val, nullptr, j, f);
 #pragma unroll
         for (int c = 0; c < DIM; ++c) out[c * N + v] = u[c * N + v] + val[c];
-    }
-}
-
-// Largest displacement of field u in voxels (max over voxels and axes of
-// |u_a| (n_a - 1)/2), as the bits of a non-negative float (ordered like
-// unsigned integers; NaN compares above every finite value). `out` must be
-// zero before the launch.
-template <int DIM>
-__global__ void __launch_bounds__(kBlock)
-k_absmax(const PairDesc P, const float* __restrict__ u, unsigned int* out) {
-    __shared__ unsigned int red[kBlock / 64];
-    const long long N = P.nvox;
-    float m = 0.f;
-    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < N;
-         v += (long long)gridDim.x * kBlock) {
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            const float t = fabsf(u[a * N + v]) * P.s[a];
-            m = (t > m || !(t == t)) ? t : m;
-        }
     }
     unsigned int b = __float_as_uint(m) & 0x7fffffffu;
 #pragma unroll
@@ -235,7 +227,7 @@ k_absmax(const PairDesc P, const float* __restrict__ u, unsigned int* out) {
     if (threadIdx.x == 0) {
         unsigned int r = red[0];
         for (int w = 1; w < kBlock / 64; ++w) r = max(r, red[w]);
-        atomicMax(out, r);
+        atomicMax(dmax, r);
     }
 }
 
@@ -473,27 +465,19 @@ hipError_t launch_velocity(const PairDesc& P, const float* consts_dev, int trans
     return hipGetLastError();
 }
 
-hipError_t launch_compose(const PairDesc& P, int dim, const float* u, float* out, hipStream_t s) {
+hipError_t launch_compose(const PairDesc& P, int dim, const float* u, float* out,
+                          unsigned int* dmax, hipStream_t s) {
     if (dim == 3)
-        hipLaunchKernelGGL(k_compose<3>, dim3(grid_for(P.nvox)), dim3(kBlock), 0, s, P, u, out);
+        hipLaunchKernelGGL(k_compose<3>, dim3(grid_for(P.nvox)), dim3(kBlock), 0, s, P, u, out,
+                           dmax);
     else
-        hipLaunchKernelGGL(k_compose<2>, dim3(grid_for(P.nvox)), dim3(kBlock), 0, s, P, u, out);
+        hipLaunchKernelGGL(k_compose<2>, dim3(grid_for(P.nvox)), dim3(kBlock), 0, s, P, u, out,
+                           dmax);
     return hipGetLastError();
 }
 
-// dmax[k] (uint bits of a float) = largest displacement of field k, for the
-// nfields fields u + k * dim * N.
-hipError_t launch_field_reach(const PairDesc& P, int dim, const float* u, int nfields,
-                              unsigned int* dmax, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, dmax, nfields);
-    const long long dN = (long long)dim * P.nvox;
-    const int g = grid_for(P.nvox) < 1024 ? grid_for(P.nvox) : 1024;
-    for (int k = 0; k < nfields; ++k) {
-        if (dim == 3)
-            hipLaunchKernelGGL(k_absmax<3>, dim3(g), dim3(kBlock), 0, s, P, u + k * dN, dmax + k);
-        else
-            hipLaunchKernelGGL(k_absmax<2>, dim3(g), dim3(kBlock), 0, s, P, u + k * dN, dmax + k);
-    }
+hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(cdiv(n, 64)), dim3(64), 0, s, p, n);
     return hipGetLastError();
 }
 
