@@ -48,6 +48,10 @@ struct PairDesc {
     int wpad[2];         // phases prod(sp) and prod(wK), rounded up to 64
     int wend_off[2];     // float offsets of W [wpad1][wpad0] and W^T [wpad0][wpad1]
     int wpad_;
+    // B-spline regulariser blocks: each handles reg_rows rows of one control
+    // plane (reg_nband bands per plane; one band when the plane fits in LDS)
+    int reg_rows;
+    int reg_nband;
 };
 
 // Workspace layout (byte offsets into the caller's workspace).

@@ -78,7 +78,7 @@ static const TileCfg kCfg3[] = {
     {32, 8, 4}, {32, 8, 8}, {32, 8, 16}, {64, 4, 4}, {64, 4, 16},
     {16, 16, 4}, {16, 16, 16}, {32, 8, 2}, {16, 16, 8}, {16, 16, 2},
 };
-static const TileCfg kCfg2[] = {{64, 1, 2}, {64, 1, 4}, {64, 1, 8}, {64, 1, 16}};
+static const TileCfg kCfg2[] = {{64, 1, 2}, {64, 1, 4}, {64, 1, 8}, {64, 1, 16}, {64, 1, 1}};
 // candidates of the default 3D spacing-8 configuration, longest column first
 // (16 x 16 with 16, 8, 4, 2 cells), and the tile count that fills the chip
 static const int kCfg3Fill[] = {6, 8, 5, 9};
@@ -96,6 +96,7 @@ constexpr int kGenericSlots = 1024;
 constexpr size_t kMaxLds = 64 * 1024;
 constexpr long long kMaxWendTable = 1LL << 21;  // entries of each Wendland weight table
 constexpr int kMaxLccRadius = 8;
+constexpr int kRegLdsFloats = 4096;   // LDS floats a regulariser band may always use
 constexpr int kMaxDevices = 64;
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -411,11 +412,8 @@ static air_status build_tables(air_plan* P) {
             D.part_stride = NF * d * D.win[2] * D.win[1] * D.win[0];
             D.part_off = (long long)part_n;
             part_n += (size_t)D.ntiles * D.part_stride;
-            D.nreg = (d == 3) ? 3 * D.nc[2] : 2;
-            D.reg_begin = regs;
-            regs += D.nreg;
-            D.regpart_off = (int)regpart_n;
-            regpart_n += D.nreg;
+            // regulariser bands: whole planes when five plane buffers fit in
+            // max(the fused kernel's own LDS, 16 KB), else bands of rows
             const int NT = cfg.tx * cfg.ty;
             size_t f;
             if (d == 3 && s8) {
@@ -430,7 +428,25 @@ static air_status build_tables(air_plan* P) {
                 f = a4(2 * D.win[2] * cfg.tx) + a4(NF * 2 * cfg.tx) + a4(cfg.tx * wxm) +
                     a4(4 * D.sp[1]);
             }
-            const size_t reg = 5 * (size_t)a4(D.nc[0] * D.nc[1]);
+            auto reg_floats = [&](int rows) {
+                const int ra = std::min(rows + 6, D.nc[1]);
+                return 2 * (size_t)a4(ra * D.nc[0]) + 3 * (size_t)a4(rows * D.nc[0]);
+            };
+            // (one-row bands of very wide planes may need more; kMaxLds below still applies)
+            const size_t budget = std::max({f, (size_t)kRegLdsFloats, reg_floats(1)});
+            D.reg_rows = D.nc[1];
+            if (reg_floats(D.reg_rows) > budget) {
+                D.reg_rows = (int)std::max(1LL, ((long long)(budget / (size_t)D.nc[0]) - 20) / 5);
+                while (D.reg_rows > 1 && reg_floats(D.reg_rows) > budget) --D.reg_rows;
+                if (D.reg_rows < 1 || reg_floats(D.reg_rows) > budget) return AIR_ERR_UNSUPPORTED;
+            }
+            D.reg_nband = cdiv(D.nc[1], D.reg_rows);
+            D.nreg = ((d == 3) ? 3 * D.nc[2] : 2) * D.reg_nband;
+            D.reg_begin = regs;
+            regs += D.nreg;
+            D.regpart_off = (int)regpart_n;
+            regpart_n += D.nreg;
+            const size_t reg = reg_floats(D.reg_rows);
             const size_t head = 8 * sizeof(double) * (NT / 64);
             lds_f = std::max(lds_f, head + 4 * std::max(f, reg));
             lds_r = std::max(lds_r, 8 * sizeof(double) * (kBlock / 64) + 4 * reg);

@@ -40,25 +40,38 @@ __device__ void reg_block(const PairDesc& P, const float* __restrict__ consts,
     const float* Dx = Px + 7 * ncx;
     const float* Py = consts + P.gram_off[1];
     const float* Dy = Py + 7 * ncy;
-    int c, kz;
-    if (dim == 3) { c = r / ncz; kz = r % ncz; } else { c = r; kz = 0; }
+    // block r: component c, control plane kz (3D), band of rows [y0, y1)
+    const int nb_ = P.reg_nband;
+    int c, kz, band;
+    if (dim == 3) {
+        c = r / (ncz * nb_);
+        kz = (r / nb_) % ncz;
+    } else {
+        c = r / nb_;
+        kz = 0;
+    }
+    band = r % nb_;
+    const int y0 = band * P.reg_rows, y1 = min(ncy, y0 + P.reg_rows);
+    const int ya = max(0, y0 - 3), yb = min(ncy, y1 + 3);   // rows the y taps reach
+    const int na = (yb - ya) * ncx, nbr = (y1 - y0) * ncx;
     const float* th = theta + (long long)c * ncz * plane;
-    float* A = lds;              // P_z theta (3D) or theta (2D)
-    float* Cz = A + plane;       // D_z theta (3D only)
-    float* AP = Cz + plane;
-    float* AD = AP + plane;
-    float* CP = AD + plane;
+    float* A = lds;              // P_z theta (3D) or theta (2D), rows [ya, yb)
+    float* Cz = A + a4(na);      // D_z theta (3D only), rows [ya, yb)
+    float* AP = Cz + a4(na);     // rows [y0, y1)
+    float* AD = AP + a4(nbr);
+    float* CP = AD + a4(nbr);
     const int tid = threadIdx.x;
     if (dim == 3) {
         const float* Pz = consts + P.gram_off[2];
         const float* Dz = Pz + 7 * ncz;
-        for (int i = tid; i < plane; i += NT) {
+        for (int i = tid; i < na; i += NT) {
+            const int g = ya * ncx + i;
             float a = 0.f, b = 0.f;
 #pragma unroll
             for (int o = -3; o <= 3; ++o) {
                 int k = kz + o;
                 if (k < 0 || k >= ncz) continue;
-                float t = th[(long long)k * plane + i];
+                float t = th[(long long)k * plane + g];
                 a += Pz[kz * 7 + o + 3] * t;
                 b += Dz[kz * 7 + o + 3] * t;
             }
@@ -66,20 +79,21 @@ __device__ void reg_block(const PairDesc& P, const float* __restrict__ consts,
             Cz[i] = b;
         }
     } else {
-        for (int i = tid; i < plane; i += NT) A[i] = th[i];
+        for (int i = tid; i < na; i += NT) A[i] = th[ya * ncx + i];
     }
     __syncthreads();
-    for (int i = tid; i < plane; i += NT) {
-        const int ky = i / ncx, kx = i % ncx;
+    for (int i = tid; i < nbr; i += NT) {
+        const int ky = y0 + i / ncx, kx = i % ncx;
         float ap = 0.f, ad = 0.f, cp = 0.f;
 #pragma unroll
         for (int o = -3; o <= 3; ++o) {
             int k = ky + o;
             if (k < 0 || k >= ncy) continue;
-            float a = A[k * ncx + kx];
+            const int j = (k - ya) * ncx + kx;
+            float a = A[j];
             ap += Py[ky * 7 + o + 3] * a;
             ad += Dy[ky * 7 + o + 3] * a;
-            if (dim == 3) cp += Py[ky * 7 + o + 3] * Cz[k * ncx + kx];
+            if (dim == 3) cp += Py[ky * 7 + o + 3] * Cz[j];
         }
         AP[i] = ap;
         AD[i] = ad;
@@ -87,16 +101,16 @@ __device__ void reg_block(const PairDesc& P, const float* __restrict__ consts,
     }
     __syncthreads();
     double acc[1] = {0.0};
-    const float* thp = th + (long long)kz * plane;
-    float* gp = out_grad + (long long)c * ncz * plane + (long long)kz * plane;
-    for (int i = tid; i < plane; i += NT) {
-        const int ky = i / ncx, kx = i % ncx;
+    const float* thp = th + (long long)kz * plane + (long long)y0 * ncx;
+    float* gp = out_grad + (long long)c * ncz * plane + (long long)kz * plane + (long long)y0 * ncx;
+    for (int i = tid; i < nbr; i += NT) {
+        const int kx = i % ncx, row = i - kx;
         float o_ = 0.f;
 #pragma unroll
         for (int o = -3; o <= 3; ++o) {
             int k = kx + o;
             if (k < 0 || k >= ncx) continue;
-            const int j = ky * ncx + k;
+            const int j = row + k;
             o_ += Dx[kx * 7 + o + 3] * AP[j] + Px[kx * 7 + o + 3] * (AD[j] + CP[j]);
         }
         gp[i] = scale * o_;

@@ -242,6 +242,36 @@ def test_regulariser_parity(n, sp, tf):
     assert np.linalg.norm(gg - go) <= GRAD_TOL * np.linalg.norm(go)
 
 
+# Control planes too large for one regulariser block's LDS are split into
+# bands of rows (with a 3-row halo for the 7-diagonal Gram factors).
+@pytest.mark.parametrize("n", [(600, 520), (480, 480, 16)])
+def test_regulariser_banded_planes(n):
+    print(f"case banded regulariser n={n}", flush=True)
+    sp = (8,) * len(n)
+    p = api.Problem(n=n, spacing=sp, similarity=api.SIM_MSE, lambda_diff=1.0)
+    th = theta_for(p, "rand", 73)
+    v, g = api.regulariser(api.Plan(p), gpu(th))
+    vo, go = O.regulariser(oprob(p), th)
+    assert abs(float(v.item()) - vo) <= VAL_TOL * abs(vo)
+    gg = g.double().cpu().numpy()
+    assert np.linalg.norm(gg - go) <= GRAD_TOL * np.linalg.norm(go)
+
+
+@pytest.mark.parametrize("n,sim", [((600, 520), api.SIM_MSE), ((480, 480, 16), api.SIM_NCC)])
+def test_objective_banded_regulariser(n, sim):
+    """The whole objective where the fused launch carries banded regulariser
+    blocks."""
+    print(f"case banded objective n={n} sim={sim}", flush=True)
+    sp = (8,) * len(n)
+    p = api.Problem(n=n, spacing=sp, similarity=sim, lambda_diff=0.1)
+    F, M = blob_inputs(n, 8, 31)
+    th = theta_for(p, "rand", 37)
+    ev, eg, gv, vo, of, gf = compare_objective(p, F, M, th)
+    assert of == 0 and gf == 0
+    assert ev <= VAL_TOL, (gv, vo, ev)
+    assert eg <= GRAD_TOL, eg
+
+
 # ------------------------------------------------------------------ batched
 
 def test_batched_uneven_matches_single_and_oracle():
