@@ -135,7 +135,9 @@ air_status air_plan_param_count(const air_plan* plan, int32_t pair, int64_t* cou
 /* Tile configurations of the fused kernel (the autotuner's search space). A
  * new 3D plan whose pairs all have spacing 8 starts with 16 x 16 columns, the
  * longest column (16, 8, 4, 2 cells) that gives the launch 4096 tiles, else
- * the one with the most tiles; other plans start with configuration 0. */
+ * the one with the most tiles; a 2D B-spline plan with the longest column
+ * (16, 8, 4, 2, 1 cells) that gives 2048 tiles, else the most tiles; other
+ * plans start with configuration 0. */
 int32_t air_tiling_count(int32_t dim);
 air_status air_tiling_describe(int32_t dim, int32_t id, int32_t* tile_x, int32_t* tile_y,
                                int32_t* column_cells);

@@ -83,6 +83,9 @@ static const TileCfg kCfg2[] = {{64, 1, 2}, {64, 1, 4}, {64, 1, 8}, {64, 1, 16},
 // (16 x 16 with 16, 8, 4, 2 cells), and the tile count that fills the chip
 static const int kCfg3Fill[] = {6, 8, 5, 9};
 constexpr int kFillTiles = 4096;
+// the same for 2D B-spline plans (64-lane columns of 16, 8, 4, 2, 1 cells)
+static const int kCfg2Fill[] = {3, 2, 1, 0, 4};
+constexpr int kFillTiles2 = 2048;
 
 // kernel variant ids understood by launch_bspline (3D)
 static int variant_of(const TileCfg& c, bool all_s8) {
@@ -798,15 +801,20 @@ air_status air_plan_create(const air_problem* probs, int32_t npairs, air_plan** 
     }
     // Default tile configuration of 3D spacing-8 B-spline plans: 16 x 16
     // columns, the longest column (16, 8, 4, 2 cells) whose launch still has
-    // kFillTiles tiles, else the one with the most tiles. air_plan_set_tiling
-    // (and the autotuner) override it.
-    if (P->variant == 3) {
+    // kFillTiles tiles, else the one with the most tiles; of 2D B-spline
+    // plans: the longest column (16 .. 1 cells) with kFillTiles2 tiles.
+    // air_plan_set_tiling (and the autotuner) override it.
+    const bool bs2 = P->dim == 2 && P->transform == AIR_TF_BSPLINE3;
+    if (P->variant == 3 || bs2) {
         int chosen = -1;
-        for (int id : kCfg3Fill) {
-            P->tiling = id;
+        const int* cand = bs2 ? kCfg2Fill : kCfg3Fill;
+        const int ncand = bs2 ? 5 : 4;
+        const int fill = bs2 ? kFillTiles2 : kFillTiles;
+        for (int k = 0; k < ncand; ++k) {
+            P->tiling = cand[k];
             if (build_tables(P) != AIR_OK) continue;
-            chosen = id;
-            if (P->ntiles_total >= kFillTiles) break;
+            chosen = cand[k];
+            if (P->ntiles_total >= fill) break;
         }
         if (chosen != P->tiling) {
             P->tiling = chosen >= 0 ? chosen : 0;

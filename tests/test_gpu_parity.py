@@ -107,6 +107,22 @@ def test_every_tiling_matches_oracle(tiling):
         assert ev <= VAL_TOL and eg <= GRAD_TOL, (ev, eg)
 
 
+NTILING2 = 5   # air_tiling_count(2)
+
+
+@pytest.mark.parametrize("tiling", range(NTILING2))
+def test_every_2d_tiling_matches_oracle(tiling):
+    assert api.tiling_count(2) == NTILING2
+    for n, sp in (((70, 53), (8, 8)), ((45, 37), (5, 6))):
+        for sim in (api.SIM_NCC, api.SIM_MSE):
+            print(f"case 2D tiling={tiling} n={n} sim={sim}", flush=True)
+            p = api.Problem(n=n, spacing=sp, similarity=sim, lambda_diff=0.1)
+            F, M = blob_inputs(n, sp[0], 9)
+            th = theta_for(p, "rand", 13)
+            ev, eg, *_ = compare_objective(p, F, M, th, plan=api.Plan(p, tiling=tiling))
+            assert ev <= VAL_TOL and eg <= GRAD_TOL, (ev, eg)
+
+
 def test_tilings_agree_closely():
     """The tile shape changes only the summation order."""
     n, sp = (64, 48, 40), (8, 8, 8)
