@@ -12,8 +12,8 @@
 // contributions of every source voxel whose sample point can reach the tile
 // (the reach is bounded by the field's largest displacement, measured once
 // per field), then adds the identity and sample-point terms and writes each
-// target once. The LDS additions are atomic, so the summation order -- and
-// the last bits of the result -- vary from run to run.
+// target once. The LDS additions are integer (fixed point), so their order,
+// which varies from run to run, does not change the result.
 #include "device_common.h"
 
 namespace air {
@@ -265,11 +265,12 @@ __global__ void k_zero_u32(unsigned int* p, int n) {
 // then each target q gets gin(q) = gout(q) + s_a sum_c gout_c(q) du_c/dp_a
 // at p(q) + the accumulated transpose.
 // The transpose accumulates in 64-bit fixed point, scaled by the power of two
-// 2^(40 - e) with 2^e > max |gout| (gmax_bits): integer LDS atomics are much
+// 2^(31 - e) with 2^e > max |gout| (gmax_bits): integer LDS atomics are much
 // faster than float ones here, and integer sums do not depend on their order,
-// so the result is bitwise repeatable. Each term is below 2^40 in magnitude,
-// so fewer than 2^23 terms per target cannot overflow; the rounding of a term
-// is below 2^-41 max|gout|. A non-finite max|gout| makes gin NaN.
+// so the result is bitwise repeatable. Each term is below 2^31 in magnitude,
+// so it converts with one 32-bit conversion (truncation: an error below
+// 2^-30 max|gout| per term) and fewer than 2^32 terms per target cannot
+// overflow. A non-finite max|gout| makes gin NaN.
 constexpr int kAdjBlock3 = 1024;   // threads per 3D tile (96 KB of accumulators)
 template <int DIM>
 __global__ void __launch_bounds__(DIM == 3 ? kAdjBlock3 : kBlock)
@@ -289,8 +290,8 @@ k_compose_adj_tile(const PairDesc P, const float* __restrict__ u, const float* _
     const float gm = __uint_as_float(*gmax_bits);
     const bool gfin = gm == gm && gm < 3.0e38f;
     const int ge = gfin && gm > 0.f ? ilogbf(gm) + 1 : 0;   // 2^ge > max|gout|
-    const float scale = gfin ? ldexpf(1.f, 40 - ge) : 0.f;
-    const double unscale = ldexp(1.0, ge - 40);
+    const float scale = gfin ? ldexpf(1.f, 31 - ge) : 0.f;
+    const double unscale = ldexp(1.0, ge - 31);
     const float poison = gfin ? 0.f : __uint_as_float(0x7fc00000u);   // NaN
     // reach: corners lie within floor(p) .. floor(p) + 1 and |p - x| <= dmax
     const float dm = __uint_as_float(*dmax_bits);
@@ -319,32 +320,39 @@ k_compose_adj_tile(const PairDesc P, const float* __restrict__ u, const float* _
             f[a] = pa - fl;
         }
         if (!finite) return;
-        // skip sources whose cell misses the tile
+        // corner bit b on axis a is q_a = j_a + b; it receives a term when
+        // it lies in the tile and in the volume (q_a >= o_a >= 0 already)
+        bool ok[3][2];
+        float wa[3][2];
+        int r[3] = {0, 0, 0};
         bool near = true;
 #pragma unroll
-        for (int a = 0; a < DIM; ++a)
-            if (j[a] + 1 < o[a] || j[a] > o[a] + TS - 1) near = false;
+        for (int a = 0; a < DIM; ++a) {
+            r[a] = j[a] - o[a];
+            ok[a][0] = (unsigned)r[a] < (unsigned)TS && j[a] <= P.n[a] - 1;
+            ok[a][1] = (unsigned)(r[a] + 1) < (unsigned)TS && j[a] + 1 <= P.n[a] - 1;
+            near = near && (ok[a][0] || ok[a][1]);
+            wa[a][0] = 1.f - f[a];
+            wa[a][1] = f[a];
+        }
+        // skip sources whose cell misses the tile
         if (!near) return;
-        float go[3];
+        // |gs| < 2^31 and a corner weight is at most 1
+        float gs[3];
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) go[c] = gout[c * N + v];
+        for (int c = 0; c < DIM; ++c) gs[c] = gout[c * N + v] * scale;
+        // tile index of corner 0 (possibly outside the tile; only corners
+        // that pass the checks are used)
+        const int t0 = r[0] + TS * (r[1] + (DIM == 3 ? TS * r[2] : 0));
 #pragma unroll
         for (int cn = 0; cn < (1 << DIM); ++cn) {
-            int q[3] = {0, 0, 0};
-            bool in = true;
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                q[a] = j[a] + ((cn >> a) & 1);
-                if (q[a] < o[a] || q[a] > o[a] + TS - 1 || q[a] > P.n[a] - 1) in = false;
-            }
-            if (!in) continue;
-            float w = 1.f;
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) w *= ((cn >> a) & 1) ? f[a] : 1.f - f[a];
-            const int t = (q[0] - o[0]) + TS * ((q[1] - o[1]) + (DIM == 3 ? TS * (q[2] - o[2]) : 0));
+            const int b0 = cn & 1, b1 = (cn >> 1) & 1, b2 = (cn >> 2) & 1;
+            if (!(ok[0][b0] && ok[1][b1] && (DIM < 3 || ok[2][b2]))) continue;
+            const float w = wa[0][b0] * wa[1][b1] * (DIM == 3 ? wa[2][b2] : 1.f);
+            const int t = t0 + b0 + TS * b1 + (DIM == 3 ? TS * TS * b2 : 0);
 #pragma unroll
             for (int c = 0; c < DIM; ++c)
-                atomicAdd(&acc[c][t], (unsigned long long)__float2ll_rn(w * go[c] * scale));
+                atomicAdd(&acc[c][t], (unsigned long long)(long long)(int)(w * gs[c]));
         }
     };
     // Scan of the box: a work item is one column of the box (all axes but
