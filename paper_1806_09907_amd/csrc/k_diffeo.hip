@@ -293,14 +293,23 @@ k_compose_adj_tile(const PairDesc P, const float* __restrict__ u, const float* _
     const float scale = gfin ? ldexpf(1.f, 31 - ge) : 0.f;
     const double unscale = ldexp(1.0, ge - 31);
     const float poison = gfin ? 0.f : __uint_as_float(0x7fc00000u);   // NaN
-    // reach: corners lie within floor(p) .. floor(p) + 1 and |p - x| <= dmax
+    // reach: a source x feeds corners floor(p) and floor(p) + 1 with
+    // |p - x| <= e, e = dmax plus a bound on the rounding of dmax and of p.
+    // A corner in [o, o + TS) needs p >= o - 1 and p < o + TS, so the
+    // sources lie in [o - 1 - floor(e), o + TS + ceil(e)) along each axis.
     const float dm = __uint_as_float(*dmax_bits);
-    int h = (dm == dm && dm < 1e6f) ? (int)ceilf(dm) + 1 : (1 << 20);
+    int hlo = 1 << 20, hhi = 1 << 20;
+    if (dm == dm && dm < 1e6f) {
+        const int nmax = max(P.n[0], max(P.n[1], P.n[2]));
+        const double e = (double)dm + ((double)dm + nmax) * 0x1p-20;
+        hlo = 1 + (int)floor(e);
+        hhi = (int)ceil(e);
+    }
     int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        lo[a] = max(0, o[a] - h);
-        const int hi = min(P.n[a], o[a] + TS + h);
+        lo[a] = max(0, o[a] - hlo);
+        const int hi = min(P.n[a], o[a] + TS + hhi);
         ext[a] = hi - lo[a];
     }
     __syncthreads();
