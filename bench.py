@@ -27,6 +27,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -49,7 +50,7 @@ def progress(msg):
 
 # Sources the dominant kernel of each counter-profiled workload is built
 # from (its own file and the shared headers): counters stay valid while
-# these are unchanged.
+# their code is unchanged (comments and layout are not hashed).
 KERNEL_SOURCES = {
     "batch128": ["k_bspline.hip"],
     "uneven48": ["k_bspline.hip"],
@@ -58,13 +59,22 @@ KERNEL_SOURCES = {
 SHARED_SOURCES = ["air_internal.h", "device_common.h", "../../include/airhip.h"]
 
 
+def code_tokens(text: str) -> str:
+    """C/C++ source without its comments, one non-empty line per line with
+    runs of blanks collapsed."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    lines = (" ".join(line.split()) for line in text.splitlines())
+    return "\n".join(line for line in lines if line)
+
+
 def kernel_source_hash(workload: str = "batch128") -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1806_09907_amd", "csrc")
     for name in KERNEL_SOURCES.get(workload, []) + SHARED_SOURCES:
-        with open(os.path.join(csrc, name), "rb") as fh:
+        with open(os.path.join(csrc, name), encoding="utf-8") as fh:
             h.update(os.path.basename(name).encode())
-            h.update(fh.read())
+            h.update(code_tokens(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

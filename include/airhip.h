@@ -91,7 +91,8 @@ enum { AIR_FLAG_NONFINITE = 1u, AIR_FLAG_DEGENERATE = 2u };
 
 typedef struct {
     int32_t dim;          /* 2 or 3 */
-    int32_t n[3];         /* voxels along x, y, z (n[2] == 1 in 2D), each >= 2 */
+    int32_t n[3];         /* voxels along x, y, z (n[2] == 1 in 2D), each in
+                             2..65536, fewer than 2^29 in all (AIR_ERR_SHAPE) */
     int32_t transform;    /* AIR_TF_* */
     int32_t spacing[3];   /* control spacing delta in voxels, 1..64 (B-spline,
                              Wendland) */
