@@ -195,29 +195,74 @@ k_scale_copy(const float* __restrict__ in, float scale, long long n, int accumul
 // |u_a| (n_a - 1)/2) into dmax, as the bits of a non-negative float (ordered
 // like unsigned integers; NaN compares above every finite value): the reach
 // of this squaring's adjoint. dmax must be zero before the launch.
+// A block owns kCompTX x kCompTY voxels of (x, y) and takes kCompSteps steps
+// along the last axis (3D: planes z; 2D: groups of kCompTY rows), so the
+// coordinates need no division and the next step's displacement loads are
+// issued before this step's gathers are used. Work items are XCD-contiguous,
+// so the gathers of neighbouring columns share an L2.
+constexpr int kCompTX = 64, kCompTY = 4, kCompSteps = 16;
+static_assert(kCompTX * kCompTY == kBlock, "one thread per (x, y) of a block");
+template <int DIM>
+__host__ __device__ inline int compose_items(const PairDesc& P) {
+    const int nbx = cdiv(P.n[0], kCompTX);
+    if (DIM == 3) return nbx * cdiv(P.n[1], kCompTY) * cdiv(P.n[2], kCompSteps);
+    return nbx * cdiv(P.n[1], kCompTY * kCompSteps);
+}
 template <int DIM>
 __global__ void __launch_bounds__(kBlock)
 k_compose(const PairDesc P, const float* __restrict__ u, float* __restrict__ out,
           unsigned int* __restrict__ dmax) {
     __shared__ unsigned int red[kBlock / 64];
     const long long N = P.nvox;
+    const int nx = P.n[0], ny = P.n[1];
+    const int nbx = cdiv(nx, kCompTX);
+    const int item = xcd_item(blockIdx.x, compose_items<DIM>(P), 0);
     float m = 0.f;
-    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < N;
-         v += (long long)gridDim.x * kBlock) {
-        int idx[3];
-        voxel_coords<DIM>(P, v, idx);
-        float p[3], val[3], f[3];
-        int j[3];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            const float ua = u[a * N + v];
-            const float t = fabsf(ua) * P.s[a];
-            m = (t > m || !(t == t)) ? t : m;
-            p[a] = fmaf(ua, P.s[a], (float)idx[a]);
+    if (item >= 0) {
+        const int x = (item % nbx) * kCompTX + (int)threadIdx.x % kCompTX;
+        const int ly = (int)threadIdx.x / kCompTX;
+        int y, z0, cnt;
+        long long step;
+        if (DIM == 3) {
+            const int nby = cdiv(ny, kCompTY);
+            y = ((item / nbx) % nby) * kCompTY + ly;
+            z0 = (item / (nbx * nby)) * kCompSteps;
+            cnt = min(kCompSteps, P.n[2] - z0);
+            step = (long long)nx * ny;
+        } else {
+            y = (item / nbx) * (kCompTY * kCompSteps) + ly;   // rows y + kCompTY k
+            z0 = 0;
+            cnt = y < ny ? min(kCompSteps, cdiv(ny - y, kCompTY)) : 0;
+            step = (long long)nx * kCompTY;
         }
-        field_sample<DIM, false>(u, N, P, p, val, nullptr, j, f);
+        if (x < nx && y < ny && cnt > 0) {
+            long long v = x + (long long)nx * (y + (DIM == 3 ? (long long)ny * z0 : 0));
+            float uc[3] = {0.f, 0.f, 0.f}, un[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) out[c * N + v] = u[c * N + v] + val[c];
+            for (int c = 0; c < DIM; ++c) uc[c] = u[c * N + v];
+            for (int k = 0; k < cnt; ++k) {
+                if (k + 1 < cnt) {
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) un[c] = u[c * N + v + step];
+                }
+                const int idx[3] = {x, DIM == 3 ? y : y + kCompTY * k, DIM == 3 ? z0 + k : 0};
+                float p[3], val[3], f[3];
+                int j[3];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    const float t = fabsf(uc[a]) * P.s[a];
+                    m = (t > m || !(t == t)) ? t : m;
+                    p[a] = fmaf(uc[a], P.s[a], (float)idx[a]);
+                }
+                field_sample<DIM, false>(u, N, P, p, val, nullptr, j, f);
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    out[c * N + v] = uc[c] + val[c];
+                    uc[c] = un[c];
+                }
+                v += step;
+            }
+        }
     }
     unsigned int b = __float_as_uint(m) & 0x7fffffffu;
 #pragma unroll
@@ -485,11 +530,11 @@ hipError_t launch_velocity(const PairDesc& P, const float* consts_dev, int trans
 hipError_t launch_compose(const PairDesc& P, int dim, const float* u, float* out,
                           unsigned int* dmax, hipStream_t s) {
     if (dim == 3)
-        hipLaunchKernelGGL(k_compose<3>, dim3(grid_for(P.nvox)), dim3(kBlock), 0, s, P, u, out,
-                           dmax);
+        hipLaunchKernelGGL(k_compose<3>, dim3(xcd_grid(compose_items<3>(P), 0)), dim3(kBlock), 0,
+                           s, P, u, out, dmax);
     else
-        hipLaunchKernelGGL(k_compose<2>, dim3(grid_for(P.nvox)), dim3(kBlock), 0, s, P, u, out,
-                           dmax);
+        hipLaunchKernelGGL(k_compose<2>, dim3(xcd_grid(compose_items<2>(P), 0)), dim3(kBlock), 0,
+                           s, P, u, out, dmax);
     return hipGetLastError();
 }
 
