@@ -292,8 +292,28 @@ def single_pair_latency(F, M, th, prob, calls=1000):
         api.objective_and_grad(plan, F, M, th, value, grad)
     b.record()
     torch.cuda.synchronize()
-    return {"us_per_eval": a.elapsed_time(b) * 1e3 / calls, "calls": calls,
-            "note": "one 128^3 pair evaluated back to back; served partly from the 256 MB "
+    eager_us = a.elapsed_time(b) * 1e3 / calls
+    # the same evaluations replayed from a HIP graph of `per_graph` calls:
+    # the device-side latency without Python's per-call cost
+    per_graph, replays = 20, max(1, calls // 20)
+    plan.prepare()
+    plan.workspace(F.device)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(per_graph):
+            api.objective_and_grad(plan, F, M, th, value, grad)
+    graph.replay()
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(replays):
+        graph.replay()
+    b.record()
+    torch.cuda.synchronize()
+    graph_us = a.elapsed_time(b) * 1e3 / (replays * per_graph)
+    return {"us_per_eval": eager_us, "calls": calls,
+            "graph_us_per_eval": graph_us, "graph_calls": replays * per_graph,
+            "note": "one 128^3 pair evaluated back to back, eagerly through the Python "
+                    "binding and as HIP graph replays; served partly from the 256 MB "
                     "Infinity Cache, so not an HBM figure"}
 
 
