@@ -53,6 +53,47 @@ def test_plan_create_and_queries():
             assert plan_t.tiling == t
 
 
+def _default_tiling(dim, sizes, fill):
+    """The documented default: among the columns of 16, 8, 4, 2 cells (3D,
+    16 x 16 tiles) or 16, 8, 4, 2, 1 cells (2D, 64 x 1), the longest whose
+    launch has `fill` tiles, else the one with the most tiles."""
+    from paper_1806_09907_amd import api
+
+    shape = (16, 16) if dim == 3 else (64, 1)
+    ids = {}
+    for t in range(api.tiling_count(dim)):
+        tx, ty, cells = api.tiling_describe(dim, t)
+        if (tx, ty) == shape:
+            ids[cells] = t
+    best, best_tiles = None, -1
+    for cells in ((16, 8, 4, 2) if dim == 3 else (16, 8, 4, 2, 1)):
+        tiles = 0
+        for n in sizes:
+            ncol = (n[dim - 1] - 1) // 8 + 1            # cells along the column axis
+            tiles += -(-n[0] // shape[0]) * (-(-n[1] // shape[1]) if dim == 3 else 1) * \
+                -(-ncol // cells)
+        if tiles >= fill:
+            return ids[cells]
+        if tiles > best_tiles:
+            best, best_tiles = ids[cells], tiles
+    return best
+
+
+@pytest.mark.parametrize("dim,sizes", [
+    (3, [(128, 128, 128)] * 64),   # 16-cell columns already give 4096 tiles
+    (3, [(128, 128, 128)] * 8),    # 2-cell columns
+    (3, [(128, 128, 128)]),        # no column reaches 4096 tiles: 2-cell, the most
+    (3, [(96, 112, 160), (144, 128, 96)] * 6),
+    (2, [(64, 64)]),
+    (2, [(1024, 1024)]),
+    (2, [(512, 512)] * 3),
+])
+def test_default_tiling_follows_the_documented_rule(dim, sizes):
+    probs = [Problem(n=n, spacing=(8,) * dim, similarity=SIM_NCC) for n in sizes]
+    plan = Plan(probs)
+    assert plan.tiling == _default_tiling(dim, sizes, 4096 if dim == 3 else 2048)
+
+
 @pytest.mark.parametrize("bad,code", [
     (dict(n=(1, 24, 20)), 2),
     (dict(spacing=(0, 8, 8)), 2),
