@@ -1126,6 +1126,10 @@ __device__ inline void tile_range(int j, int sp, int n, int T, int* lo, int* hi)
 // fixed order and slot s goes to lane s mod NS; the lanes' FP64 sums meet in
 // a fixed xor butterfly, so every lane holds the same, order-fixed total.
 constexpr int kFinLanes = 8;
+// tiles whose loads a lane issues together when a control has several lanes
+// (few controls, so memory latency is the cost); with one lane per control
+// the launch has threads enough to hide it, and registers matter more
+constexpr int kFinBatch = 4;
 constexpr long long kFinFewControls = 1 << 17;   // below this many, NS = kFinLanes
 
 template <int TX, int TY, int SIM, int DIM, int NS>
@@ -1170,6 +1174,49 @@ k_finalize(const LaunchCtx C) {
         int tx_lo, tx_hi, ty_lo = 0, ty_hi = 0;
         tile_range(jx, P.sp[0], P.n[0], TX, &tx_lo, &tx_hi);
         if (DIM == 3) tile_range(jy, P.sp[1], P.n[1], TY, &ty_lo, &ty_hi);
+        // this lane's tiles are taken NB at a time: their addresses first,
+        // then every load of the batch (all addresses valid: unused entries
+        // point at the pair's first partial), then the sums in slot order, so
+        // each batch waits for memory once
+        constexpr int NB = NS > 1 ? kFinBatch : 1;
+        const double* stb[NB];
+        const float* qb[NB];
+        int nb = 0;
+        const double* st0 = stats + (long long)P.tile_begin * kStatWords;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            stb[i] = st0;
+            qb[i] = part;
+        }
+        auto drain = [&]() {
+            double s6[NB], s7[NB];
+            float qv[NB][NF * DIM];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                if (SIM == AIR_SIM_NCC) {
+                    s6[i] = stb[i][6];
+                    s7[i] = stb[i][7];
+                }
+#pragma unroll
+                for (int e = 0; e < NF * DIM; ++e) qv[i][e] = qb[i][e];
+            }
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                if (i >= nb) break;
+                const double cF = k.alpha, cW = k.beta;
+                double c1 = 0.0;
+                if (SIM == AIR_SIM_NCC) c1 = k.alpha * (s6[i] - k.muF) + k.beta * (s7[i] - k.muW);
+                const float* q = qv[i];
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    if (SIM == AIR_SIM_NCC)
+                        g[c] += cF * q[c] + cW * q[DIM + c] + c1 * q[2 * DIM + c];
+                    else
+                        g[c] += cF * q[c];
+                }
+            }
+            nb = 0;
+        };
         int slot = 0;
         for (int tc = tc_lo; tc <= tc_hi; ++tc)
         for (int ty = ty_lo; ty <= ty_hi; ++ty)
@@ -1192,21 +1239,12 @@ k_finalize(const LaunchCtx C) {
             const int tl = (DIM == 3) ? (tc * P.ntile[1] + ty) * P.ntile[0] + tx
                                       : tc * P.ntile[0] + tx;
             const float* pt = part + (long long)tl * P.part_stride;
-            double cF = k.alpha, cW = k.beta, c1 = 0.0;
-            if (SIM == AIR_SIM_NCC) {
-                const double* st = stats + (long long)(P.tile_begin + tl) * kStatWords;
-                c1 = k.alpha * (st[6] - k.muF) + k.beta * (st[7] - k.muW);
-            }
+            stb[nb] = stats + (long long)(P.tile_begin + tl) * kStatWords;
             // partial layout [column][y][x][field * DIM + component]
-            const float* q = pt + (((long long)kcl * WyM + kyl) * WxM + kxl) * (NF * DIM);
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) {
-                if (SIM == AIR_SIM_NCC)
-                    g[c] += cF * q[c] + cW * q[DIM + c] + c1 * q[2 * DIM + c];
-                else
-                    g[c] += cF * q[c];
-            }
+            qb[nb] = pt + (((long long)kcl * WyM + kyl) * WxM + kxl) * (NF * DIM);
+            if (++nb == NB) drain();
         }
+        drain();
     }
     static_assert((NS & (NS - 1)) == 0 && NS <= 64, "NS: a power of two within a wave");
 #pragma unroll
