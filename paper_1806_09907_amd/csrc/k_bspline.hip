@@ -1084,7 +1084,27 @@ __device__ double pair_reg(const PairDesc& P, const double* regpart, double* red
     return v[0] * (double)P.inv_xr;
 }
 
-// scalars[pair]: [0] S, [1] alpha, [2] beta, [3] muF, [4] muW, [5] R, [6] degenerate
+// scalars[pair]: [0] S, [1] alpha, [2] beta, [3] muF, [4] muW, [5] R, [6] degenerate;
+// also the pair's objective value and flags (one thread)
+__device__ inline void store_pair_coef(const LaunchCtx& C, const PairDesc& P, int pair,
+                                       const Coef& k, double R) {
+    double* out = reinterpret_cast<double*>(C.ws + C.L.scalars) + (long long)pair * 8;
+    out[0] = k.S;
+    out[1] = k.alpha;
+    out[2] = k.beta;
+    out[3] = k.muF;
+    out[4] = k.muW;
+    out[5] = R;
+    out[6] = k.degenerate ? 1.0 : 0.0;
+    out[7] = 0.0;
+    uint32_t fl = k.degenerate ? AIR_FLAG_DEGENERATE : 0u;
+    const double value = k.S + (double)P.lambda * R;
+    if (!isfinite((float)value)) fl |= AIR_FLAG_NONFINITE;
+    if (fl) atomicOr(reinterpret_cast<uint32_t*>(C.ws + C.L.flags) + pair, fl);
+    float* vout = C.values ? C.values + pair : C.value0;
+    *vout = (float)value;
+}
+
 template <int SIM>
 __global__ void __launch_bounds__(kBlock)
 k_pair_coef(const LaunchCtx C) {
@@ -1093,23 +1113,7 @@ k_pair_coef(const LaunchCtx C) {
     const PairDesc P = C.pairs[pair];
     const Coef k = pair_coef<kBlock, SIM>(P, reinterpret_cast<const double*>(C.ws + C.L.stats), red);
     const double R = pair_reg<kBlock>(P, reinterpret_cast<const double*>(C.ws + C.L.regpart), red);
-    if (threadIdx.x == 0) {
-        double* out = reinterpret_cast<double*>(C.ws + C.L.scalars) + (long long)pair * 8;
-        out[0] = k.S;
-        out[1] = k.alpha;
-        out[2] = k.beta;
-        out[3] = k.muF;
-        out[4] = k.muW;
-        out[5] = R;
-        out[6] = k.degenerate ? 1.0 : 0.0;
-        out[7] = 0.0;
-        uint32_t fl = k.degenerate ? AIR_FLAG_DEGENERATE : 0u;
-        const double value = k.S + (double)P.lambda * R;
-        if (!isfinite((float)value)) fl |= AIR_FLAG_NONFINITE;
-        if (fl) atomicOr(reinterpret_cast<uint32_t*>(C.ws + C.L.flags) + pair, fl);
-        float* vout = C.values ? C.values + pair : C.value0;
-        *vout = (float)value;
-    }
+    if (threadIdx.x == 0) store_pair_coef(C, P, pair, k, R);
 }
 
 // Range of tiles (along one axis) whose voxel range meets the support of
@@ -1141,14 +1145,26 @@ k_finalize(const LaunchCtx C) {
     const int pair = blockIdx.y;
     const PairDesc P = C.pairs[pair];
     const double* stats = reinterpret_cast<const double*>(C.ws + C.L.stats);
-    const double* sc = reinterpret_cast<const double*>(C.ws + C.L.scalars) + (long long)pair * 8;
     Coef k;
-    k.S = sc[0];
-    k.alpha = sc[1];
-    k.beta = sc[2];
-    k.muF = sc[3];
-    k.muW = sc[4];
-    k.degenerate = sc[6] != 0.0;
+    if (NS > 1) {
+        // few controls: every block reduces the pair's tile statistics itself
+        // (the same fixed-order sums as k_pair_coef, so the same values) and
+        // block 0 stores them, which saves a launch on this latency-bound path
+        __shared__ double red[8 * (kBlock / 64)];
+        k = pair_coef<kBlock, SIM>(P, stats, red);
+        const double R =
+            pair_reg<kBlock>(P, reinterpret_cast<const double*>(C.ws + C.L.regpart), red);
+        if (blockIdx.x == 0 && threadIdx.x == 0) store_pair_coef(C, P, pair, k, R);
+    } else {
+        const double* sc =
+            reinterpret_cast<const double*>(C.ws + C.L.scalars) + (long long)pair * 8;
+        k.S = sc[0];
+        k.alpha = sc[1];
+        k.beta = sc[2];
+        k.muF = sc[3];
+        k.muW = sc[4];
+        k.degenerate = sc[6] != 0.0;
+    }
     uint32_t* flags = reinterpret_cast<uint32_t*>(C.ws + C.L.flags) + pair;
     const int nctrl = P.nc[0] * P.nc[1] * (DIM == 3 ? P.nc[2] : 1);
     const int ls = threadIdx.x % NS;
@@ -1281,13 +1297,14 @@ static hipError_t launch3s8(const LaunchCtx& C, size_t lds, hipStream_t s) {
 
 template <int TX, int TY, int SIM, int DIM>
 static hipError_t launch_fin(const LaunchCtx& C, int max_ctrl, hipStream_t s) {
-    hipLaunchKernelGGL((k_pair_coef<SIM>), dim3(C.npairs), dim3(kBlock), 0, s, C);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     if ((long long)max_ctrl * C.npairs < kFinFewControls) {
+        // the finalize blocks reduce the pair statistics themselves
         dim3 grid(cdiv(max_ctrl, kBlock / kFinLanes), C.npairs);
         hipLaunchKernelGGL((k_finalize<TX, TY, SIM, DIM, kFinLanes>), grid, dim3(kBlock), 0, s, C);
     } else {
+        hipLaunchKernelGGL((k_pair_coef<SIM>), dim3(C.npairs), dim3(kBlock), 0, s, C);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
         dim3 grid(cdiv(max_ctrl, kBlock), C.npairs);
         hipLaunchKernelGGL((k_finalize<TX, TY, SIM, DIM, 1>), grid, dim3(kBlock), 0, s, C);
     }
