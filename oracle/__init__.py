@@ -91,8 +91,6 @@ def lib():
                                        ctypes.c_int, ctypes.c_int, dp]),
             "airo_conv3d_bwd": (None, [dp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, dp,
                                        ctypes.c_int, dp, dp, dp, dp]),
-            "airo_set_point_precision": (None, [ctypes.c_int]),
-            "airo_get_point_precision": (ctypes.c_int, []),
             "airo_set_threads": (None, [ctypes.c_int]),
             "airo_get_threads": (ctypes.c_int, []),
         }
@@ -170,30 +168,6 @@ def _check(prob: Problem):
     if lib().airo_check(ctypes.byref(pc)) != 0:
         raise ValueError(f"invalid problem {prob}")
     return pc
-
-
-def set_point_precision(bits: int) -> None:
-    """32 (default): cell and mask decided on the FP32-rounded sample point;
-    64: on the FP64 point (for pins against FP64 library references)."""
-    lib().airo_set_point_precision(int(bits))
-
-
-def get_point_precision() -> int:
-    return int(lib().airo_get_point_precision())
-
-
-class point_precision:
-    """Context manager that sets the sample-point precision temporarily."""
-
-    def __init__(self, bits: int):
-        self.bits = bits
-
-    def __enter__(self):
-        self.old = get_point_precision()
-        set_point_precision(self.bits)
-
-    def __exit__(self, *exc):
-        set_point_precision(self.old)
 
 
 def set_threads(n: int) -> None:

@@ -22,15 +22,6 @@
 #endif
 
 static int g_threads = 0;
-/* Precision of the sample point p = x + u (n-1)/2 (bits): 32 rounds the
- * exactly computed point to FP32 before the cell (floor) and the mask are
- * decided, as a grid sampler over FP32 tensors does (Sec. III-C Image
- * Warping); 64 keeps it in FP64 (used to pin the sampler against FP64
- * library references). All arithmetic after the decision stays FP64. */
-static int g_point_bits = 32;
-
-void airo_set_point_precision(int bits) { g_point_bits = (bits == 64) ? 64 : 32; }
-int airo_get_point_precision(void) { return g_point_bits; }
 
 void airo_set_threads(int nthreads) { g_threads = nthreads > 0 ? nthreads : 0; }
 
@@ -374,8 +365,6 @@ void airo_sample(const airo_problem* p, const double* moving, const double* u,
                 int inside = 1, finite = 1;
                 for (int a = 0; a < d; ++a) {
                     pt[a] = idx[a] + u[a * N + v] * (n[a] - 1) / 2.0;
-                    if (g_point_bits == 32 && isfinite(pt[a]) && fabs(pt[a]) < 1e30)
-                        pt[a] = (double)(float)pt[a];
                     if (!isfinite(pt[a])) finite = 0;
                     if (!(pt[a] >= 0.0 && pt[a] <= n[a] - 1)) inside = 0;
                     /* far outside: every corner is padding; keep floor() in range */
@@ -477,8 +466,6 @@ void airo_compose_adjoint(const airo_problem* p, const double* u, const double* 
                 int finite = 1;
                 for (int a = 0; a < d; ++a) {
                     pt[a] = idx[a] + u[a * N + v] * (n[a] - 1) / 2.0;
-                    if (g_point_bits == 32 && isfinite(pt[a]) && fabs(pt[a]) < 1e30)
-                        pt[a] = (double)(float)pt[a];
                     if (!isfinite(pt[a])) finite = 0;
                     if (pt[a] > 1e9) pt[a] = 1e9;
                     if (pt[a] < -1e9) pt[a] = -1e9;

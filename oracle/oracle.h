@@ -127,7 +127,9 @@ void airo_exp(const airo_problem* p, const double* v, int K, double* u, double* 
 
 /* Sample `moving` at x + u(x); writes warped [N], mask [N] (nullable) and
  * dwdp [d][N] (nullable): the derivative of the sample with respect to the
- * sample point in voxel units, on the cell [floor(p), floor(p)+1]. */
+ * sample point in voxel units, on the cell [floor(p), floor(p)+1]. The point
+ * p = x + u (n-1)/2, the cell and the mask are taken in FP64 on the inputs as
+ * given (FP32 inputs widened exactly), which is the sampler's definition. */
 void airo_sample(const airo_problem* p, const double* moving, const double* u,
                  double* warped, unsigned char* mask, double* dwdp);
 void airo_warp(const airo_problem* p, const double* moving, const double* theta,
@@ -182,12 +184,6 @@ void airo_conv3d_fwd(const double* x, const int n[3], int cin, const double* wt,
                      const double* bias, int cout, int act, double* y);
 void airo_conv3d_bwd(const double* x, const int n[3], int cin, const double* wt, int cout,
                      const double* dy, double* dx, double* dwt, double* db);
-
-/* Precision (32 or 64 bits) of the sample point on which the interpolation
- * cell and the mask are decided; default 32 (a grid sampler over FP32
- * tensors, Sec. III-C). Arithmetic after the decision is FP64 either way. */
-void airo_set_point_precision(int bits);
-int airo_get_point_precision(void);
 
 /* Threads used by the parallel loops (OpenMP); 0 = runtime default. */
 void airo_set_threads(int nthreads);

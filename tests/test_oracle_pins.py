@@ -18,13 +18,6 @@ import oracle as O
 from paper_1806_09907_amd import synth
 
 
-@pytest.fixture(autouse=True)
-def fp64_points(oracle):
-    """Pins against FP64 library references and finite differences use the
-    FP64 sample point; the FP32 decision mode is pinned separately below."""
-    with O.point_precision(64):
-        yield
-
 
 def prob(n, **kw):
     d = len(n)
@@ -443,36 +436,6 @@ def test_adam_matches_torch(oracle):
         opt.step()
         O.adam_step(th, g, m, v, lr=0.01, step=step)
     assert np.max(np.abs(th - t.detach().numpy())) < 1e-14
-
-
-def test_fp32_point_decision_mode(oracle):
-    """In the default mode the cell and mask are decided on the sample point
-    rounded to FP32: the result equals the FP64-point sampler evaluated at
-    displacements that land exactly on those rounded points."""
-    rng = np.random.default_rng(15)
-    for n in ((23, 17), (11, 9, 13)):
-        d = len(n)
-        p = prob(n, transform=O.TF_DENSE, similarity=O.SIM_MSE)
-        moving = rng.normal(size=p.shape)
-        u = (rng.normal(size=(d,) + p.shape) * 0.3).astype(np.float32).astype(np.float64)
-        grids = np.meshgrid(*[np.arange(m) for m in reversed(n)], indexing="ij")
-        u_r = np.empty_like(u)
-        for a in range(d):
-            s = (n[a] - 1) / 2
-            pa = grids[d - 1 - a] + u[a] * s
-            u_r[a] = (pa.astype(np.float32).astype(np.float64) - grids[d - 1 - a]) / s
-        with O.point_precision(32):
-            w32, m32, d32 = O.sample(p, moving, u)
-        w64, m64, d64 = O.sample(p, moving, u_r)
-        assert np.max(np.abs(w32 - w64)) < 1e-12
-        assert np.array_equal(m32, m64)
-        assert np.max(np.abs(d32 - d64)) < 1e-12
-        # integer shifts stay exact array shifts in this mode too
-        with O.point_precision(32):
-            u0 = np.zeros((d,) + p.shape)
-            u0[0] = 2.0 * 3 / (n[0] - 1)
-            w, mask, _ = O.sample(p, moving, u0)
-        assert np.array_equal(w[..., :n[0] - 3], moving[..., 3:])
 
 
 def test_pyramid_down_matches_scipy(oracle):

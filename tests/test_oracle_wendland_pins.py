@@ -22,11 +22,6 @@ import oracle as O
 from paper_1806_09907_amd import synth
 
 
-@pytest.fixture(autouse=True)
-def fp64_points(oracle):
-    with O.point_precision(64):
-        yield
-
 
 def wprob(n, spacing, sigma, **kw):
     kw.setdefault("similarity", O.SIM_MSE)
