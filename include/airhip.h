@@ -28,7 +28,12 @@
  *   - a voxel is in the mask iff 0 <= p_a <= n_a - 1 on every axis; the
  *     similarity is averaged over the masked voxels (N'); the mask is held
  *     constant when differentiating; interpolation uses the cell
- *     [floor(p), floor(p) + 1] with zero padding outside the volume;
+ *     [floor(p), floor(p) + 1] with zero padding outside the volume. The
+ *     kernels never round p itself: they take the cell and the mask on the
+ *     exact sum of the integer i_a and the displacement in voxels
+ *     d_a = u_a (n_a - 1) / 2, rounded once to FP32, plus (for dense fields,
+ *     whose u is the input itself) that rounding's exact error, so dense
+ *     decisions are those of the exact point;
  *   - R uses forward differences of u (normalised units) over
  *     X_R = prod_a [0, n_a - 2], divided by |X_R|;
  *   - all tensor pointers are caller-owned DEVICE buffers, 16-byte aligned,
@@ -92,7 +97,8 @@ enum { AIR_FLAG_NONFINITE = 1u, AIR_FLAG_DEGENERATE = 2u };
 typedef struct {
     int32_t dim;          /* 2 or 3 */
     int32_t n[3];         /* voxels along x, y, z (n[2] == 1 in 2D), each in
-                             2..65536, fewer than 2^29 in all (AIR_ERR_SHAPE) */
+                             2..65536, fewer than 2^29 in all and
+                             n[1] * n[2] < 2^24 (AIR_ERR_SHAPE) */
     int32_t transform;    /* AIR_TF_* */
     int32_t spacing[3];   /* control spacing delta in voxels, 1..64 (B-spline,
                              Wendland) */

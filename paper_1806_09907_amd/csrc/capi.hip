@@ -318,6 +318,8 @@ static air_status validate_problem(const air_problem& p) {
     }
     if (p.dim == 2 && p.n[2] != 1) return AIR_ERR_SHAPE;
     if (N * 4 >= (1LL << 31)) return AIR_ERR_SHAPE;  // 32-bit byte offsets in the gathers
+    // the gathers form a row index j_z n_y + j_y with 24-bit multiplies
+    if ((long long)p.n[1] * (p.dim == 3 ? p.n[2] : 1) >= (1LL << 24)) return AIR_ERR_SHAPE;
     return AIR_OK;
 }
 

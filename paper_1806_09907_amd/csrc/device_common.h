@@ -91,21 +91,59 @@ __host__ __device__ inline int xcd_grid(int T, int R) {
     return 8 * ((T + 7) / 8 + (R + 7) / 8);
 }
 
-// Zero-padded multilinear sample at p (voxel units) with derivative; also
-// reports whether p lies inside the volume. Used where speed is secondary.
+// Displacement of a voxel along one axis in voxels, d = fl(u s), and the
+// exact rounding error e = u s - d (one fma returns it exactly). The sample
+// point x + u s is never formed in floating point: rounding it to FP32 would
+// move the interpolation weights by up to half an ulp of the point (4e-6
+// voxel at x ~ 100), while d carries an error below half an ulp of the
+// displacement itself. The cell and the mask are decided on x + d + e.
+struct Disp {
+    float d, e;
+};
+__device__ inline Disp disp_of(float u, float s) {
+    const float d = u * s;
+    return {d, fmaf(u, s, -d)};
+}
+// The cell [t, t + 1] holding the exact point x + d + e along one axis of n
+// voxels (t not clamped), the fraction f in [0, 1] (1 only when d is an
+// integer and e < 0: the point lies just below it), and whether
+// 0 <= x + d + e <= n - 1 (false for a non-finite d).
+struct AxisCell {
+    int t;
+    float f;
+    bool in;
+};
+__device__ inline AxisCell axis_cell(int x, Disp q, int n) {
+    const float lo = (float)(-x), hi = (float)(n - 1 - x);
+    AxisCell c;
+    c.in = (q.d > lo || (q.d == lo && q.e >= 0.f)) && (q.d < hi || (q.d == hi && q.e <= 0.f));
+    const float d = fminf(fmaxf(q.d, -1e9f), 1e9f);
+    const float fl = floorf(d);
+    c.f = d - fl;   // exact
+    c.t = x + (int)fl;
+    if (c.f == 0.f && q.e < 0.f) {
+        c.t -= 1;
+        c.f = 1.f;
+    }
+    return c;
+}
+
+// Zero-padded multilinear sample of M at x + d + e (voxel units) with its
+// derivative on the cell of axis_cell (right-sided at an integer point);
+// also reports whether the point lies inside the volume. Used where speed is
+// secondary.
 template <int DIM>
-__device__ inline float sample_general(const float* __restrict__ M, const int* n,
-                                       const float* p, bool* inside, float* dW) {
+__device__ inline float sample_general(const float* __restrict__ M, const int* n, const int* x,
+                                       const Disp* dq, bool* inside, float* dW) {
     float f[3];
     int j[3];
     bool in = true;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        const float pa = fminf(fmaxf(p[a], -1e9f), 1e9f);
-        if (!(p[a] >= 0.f && p[a] <= (float)(n[a] - 1))) in = false;
-        const float fl = floorf(pa);
-        j[a] = (int)fl;
-        f[a] = pa - fl;
+        const AxisCell c = axis_cell(x[a], dq[a], n[a]);
+        if (!c.in) in = false;
+        j[a] = c.t;
+        f[a] = c.f;
     }
     *inside = in;
     float W = 0.f;

@@ -259,8 +259,9 @@ k_fused3(const LaunchCtx C) {
     int cnt = 0;
     float m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f;
     const float snx = P.s[0], sny = P.s[1], snz = P.s[2];
-    const float hx = (float)(nx - 2), hy = (float)(ny - 2), hz = (float)(nz - 2);
     const int nx4 = nx * 4, nxy4 = nx * ny * 4;
+    const float nyf = (float)ny;
+    const int lane4 = (yc * nx + xc) * 4;   // byte offset of voxel (x, y, 0)
     const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, (uint32_t)(P.nvox * 4));
     float* part = reinterpret_cast<float*>(C.ws + C.L.part) + P.part_off +
                   (long long)(item - P.tile_begin) * P.part_stride;
@@ -307,16 +308,17 @@ k_fused3(const LaunchCtx C) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
                     u[c] = wz.x * V[c][0] + wz.y * V[c][1] + wz.z * V[c][2] + wz.w * V[c][3];
-                const float px = fmaf(u[0], snx, (float)x);
-                const float py = fmaf(u[1], sny, (float)y);
-                const float pz = fmaf(u[2], snz, (float)z);
-                const float flx = floorf(px), fly = floorf(py), flz = floorf(pz);
-                const float jxf = fminf(flx, hx), jyf = fminf(fly, hy), jzf = fminf(flz, hz);
-                const float fx = px - jxf, fy = py - jyf, fz = pz - jzf;
-                const bool in = (flx >= 0.f) & (fly >= 0.f) & (flz >= 0.f) &
-                                (fx <= 1.f) & (fy <= 1.f) & (fz <= 1.f);
+                // cell and mask of x + d, d = u (n - 1)/2 in voxels
+                const AxisCell ax = axis_cell(x, Disp{u[0] * snx, 0.f}, nx);
+                const AxisCell ay = axis_cell(y, Disp{u[1] * sny, 0.f}, ny);
+                const AxisCell az = axis_cell(z, Disp{u[2] * snz, 0.f}, nz);
+                const bool in = ax.in && ay.in && az.in;
                 if (in) {
-                    const int jx = (int)jxf, jy = (int)jyf, jz = (int)jzf;
+                    // a point on the last voxel takes the cell below with f = 1
+                    const bool ex = ax.t == nx - 1, ey = ay.t == ny - 1, ez = az.t == nz - 1;
+                    const int jx = ex ? nx - 2 : ax.t, jy = ey ? ny - 2 : ay.t;
+                    const int jz = ez ? nz - 2 : az.t;
+                    const float fx = ex ? 1.f : ax.f, fy = ey ? 1.f : ay.f, fz = ez ? 1.f : az.f;
                     const int off = ((jz * ny + jy) * nx + jx) * 4;
                     const v2f a00 = load2(rM, off, 0);
                     const v2f a10 = load2(rM, off, nx4);
@@ -337,9 +339,9 @@ k_fused3(const LaunchCtx C) {
                     const float h1 = dz01 + fy * (dz11 - dz01);
                     d[2] = h0 + fx * (h1 - h0);
                     // sample exactly on the last voxel: right-sided cell, zero padding
-                    if (fx == 1.f) d[0] = -W;
-                    if (fy == 1.f) d[1] = -W;
-                    if (fz == 1.f) d[2] = -W;
+                    if (ex) d[0] = -W;
+                    if (ey) d[1] = -W;
+                    if (ez) d[2] = -W;
                     cnt += 1;
                     if (SIM == AIR_SIM_NCC) {
                         const float dF = Fv - shF, dW = W - shW;
@@ -568,13 +570,14 @@ k_fused3_s8(const LaunchCtx C) {
     float cnt = 0.f;
     float m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f;
     const float snx = P.s[0], sny = P.s[1], snz = P.s[2];
-    const float nxm1 = (float)(nx - 1), nym1 = (float)(ny - 1), nzm1 = (float)(nz - 1);
-    // the sample point lies in [0, n - 1] iff its (non-negative) float bits do
-    const uint32_t limx = __float_as_uint((float)(nx - 1));
-    const uint32_t limy = __float_as_uint((float)(ny - 1));
-    const uint32_t limz = __float_as_uint((float)(nz - 1));
+    const float nzm2 = (float)(nz - 2);
+    // per lane, relative to the lane's voxel: cells start at lo = -x at
+    // least and at hc = n - 2 - x at most
+    const float lox = -(float)xc, hcx = (float)(nx - 2 - xc);
+    const float loy = -(float)yc, hcy = (float)(ny - 2 - yc);
     const int nx4 = nx * 4, nxy4 = nx * ny * 4;
-    const float xf = (float)x, yf = (float)y;
+    const float nyf = (float)ny;
+    const int lane4 = (yc * nx + xc) * 4;   // byte offset of voxel (x, y, 0)
     const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, (uint32_t)(P.nvox * 4));
     float* part = reinterpret_cast<float*>(C.ws + C.L.part) + P.part_off +
                   (long long)(item - P.tile_begin) * P.part_stride;
@@ -641,9 +644,9 @@ k_fused3_s8(const LaunchCtx C) {
     // stage 1 of layer r of cell cz; tap k of the cell is V slot (k + PH) & 3
     auto prep = [&](int r, float dv, auto ph) -> Prep {
         constexpr int PH = decltype(ph)::value;
-        // Branch-free: the sample point is clamped into the volume so every
-        // load is in range; m = 1 inside the mask, 0 outside (or for
-        // lanes / layers past the volume) scales every contribution.
+        // Branch-free: the cell is clamped into the volume so every load is
+        // in range; m = 1 inside the mask, 0 outside (or for lanes / layers
+        // past the volume) scales every contribution.
         const int z = cz * S + r;
         Prep q;
         q.Fv = __builtin_nontemporal_load(Fcol + (long long)min(z, nz - 1) * nxy);
@@ -660,26 +663,39 @@ k_fused3_s8(const LaunchCtx C) {
         for (int c = 0; c < 3; ++c)
             u[c] = w0 * V[c][PH] + w1 * V[c][(PH + 1) & 3] + w2 * V[c][(PH + 2) & 3] +
                    w3 * V[c][(PH + 3) & 3];
-        const float px = fmaf(u[0], sx_, xf);
-        const float py = fmaf(u[1], sy_, yf);
-        const float pz = fmaf(u[2], sz_, (float)z);
-        const bool in = act && z < nz && (__float_as_uint(px) <= limx) &&
-                        (__float_as_uint(py) <= limy) && (__float_as_uint(pz) <= limz);
-        q.m = in ? 1.f : 0.f;
-        const float qx = __builtin_amdgcn_fmed3f(px, 0.f, nxm1);
-        const float qy = __builtin_amdgcn_fmed3f(py, 0.f, nym1);
-        const float qz = __builtin_amdgcn_fmed3f(pz, 0.f, nzm1);
-        // q >= 0, so truncation is floor; the last voxel uses the cell
-        // [n-2, n-1] with f = 1 and a right-sided (zero-padded) derivative
-        const int tx_ = (int)qx, ty_ = (int)qy, tz_ = (int)qz;
-        q.ex = tx_ == nx - 1;
-        q.ey = ty_ == ny - 1;
-        q.ez = tz_ == nz - 1;
-        const int jx = min(tx_, nx - 2), jy = min(ty_, ny - 2), jz = min(tz_, nz - 2);
-        q.fx = qx - (float)jx;
-        q.fy = qy - (float)jy;
-        q.fz = qz - (float)jz;
-        const int off = (int)(__umul24(__umul24(jz, ny) + jy, nx) + jx) * 4;
+        // displacement in voxels: the cell and the mask are decided on the
+        // exact sum x + d (x an integer), never on a rounded sample point
+        // (fma with +0: a -0 product becomes +0, so f below is never -0)
+        const float dx = fmaf(u[0], sx_, 0.f), dy = fmaf(u[1], sy_, 0.f);
+        const float dz = fmaf(u[2], sz_, 0.f);
+        const float zf = (float)z;
+        const float mact = (act && z < nz) ? 1.f : 0.f;
+        // cell [x + c, x + c + 1] with c = floor(d) clamped to [-x, n - 2 - x]
+        // so that every load is in range. Then f = d - c is exact; it lies in
+        // [0, 1] iff x + d does in [0, n - 1], except for a point beyond the
+        // last voxel (c clamped down, "e"), which is inside only when d is
+        // the integer n - 1 - x (f == 1); its derivative is right-sided
+        // (zero padding)
+        const float flx = floorf(dx), fly = floorf(dy), flz = floorf(dz);
+        const float clx = __builtin_amdgcn_fmed3f(flx, lox, hcx);
+        const float cly = __builtin_amdgcn_fmed3f(fly, loy, hcy);
+        const float clz = __builtin_amdgcn_fmed3f(flz, -zf, nzm2 - zf);
+        q.ex = flx > clx;
+        q.ey = fly > cly;
+        q.ez = flz > clz;
+        q.fx = dx - clx;
+        q.fy = dy - cly;
+        q.fz = dz - clz;
+        constexpr uint32_t kOne = 0x3f800000u;   // bits of 1.0f: f in [0, 1]
+        const bool in = (__float_as_uint(q.fx) <= kOne) & (!q.ex | (dx == flx)) &
+                        (__float_as_uint(q.fy) <= kOne) & (!q.ey | (dy == fly)) &
+                        (__float_as_uint(q.fz) <= kOne) & (!q.ez | (dz == flz));
+        q.m = in ? mact : 0.f;
+        // byte offset of the cell's first corner: the row step clz ny + cly
+        // is an exact float (|.| < 2^24), the rest 24-bit integer arithmetic
+        const int rows = (int)fmaf(clz, nyf, cly);
+        const int off = (int)((unsigned)(__mul24(rows, nx) + (int)clx) * 4u + (unsigned)lane4 +
+                              (unsigned)z * (unsigned)nxy4);
         q.a00 = load2(rM, off, 0);
         q.a10 = load2(rM, off, nx4);
         q.a01 = load2(rM, off, nxy4);
@@ -745,10 +761,15 @@ k_fused3_s8(const LaunchCtx C) {
         // even layer finishes, A (next even layer) before the odd one. Layer
         // S of this cell (weights row t = 1, same V) is the next cell's layer
         // 0; past the last cell it is a clamped, in-range dummy.
+        // The scheduling barriers keep each layer's gathers issued before the
+        // other layer's stage 2 starts: without them the compiler may order
+        // the stages so that every iteration first waits for all loads.
         for (int r = 0; r < S; r += 2) {
             Prep B = prep(r + 1, dep(), ph);
+            __builtin_amdgcn_sched_barrier(0);
             finish(r, A, ph);
             A = prep(r + 2, dep(), ph);
+            __builtin_amdgcn_sched_barrier(0);
             finish(r + 1, B, ph);
         }
 #pragma unroll
@@ -894,7 +915,6 @@ k_fused2(const LaunchCtx C) {
     int cnt = 0;
     float m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f;
     const float snx = P.s[0], sny = P.s[1];
-    const float hx = (float)(nx - 2), hy = (float)(ny - 2);
     const int nx4 = nx * 4;
     const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, (uint32_t)(P.nvox * 4));
     float* part = reinterpret_cast<float*>(C.ws + C.L.part) + P.part_off +
@@ -927,14 +947,14 @@ k_fused2(const LaunchCtx C) {
 #pragma unroll
                 for (int c = 0; c < 2; ++c)
                     u[c] = wy.x * V[c][0] + wy.y * V[c][1] + wy.z * V[c][2] + wy.w * V[c][3];
-                const float px = fmaf(u[0], snx, (float)x);
-                const float py = fmaf(u[1], sny, (float)y);
-                const float flx = floorf(px), fly = floorf(py);
-                const float jxf = fminf(flx, hx), jyf = fminf(fly, hy);
-                const float fx = px - jxf, fy = py - jyf;
-                const bool in = (flx >= 0.f) & (fly >= 0.f) & (fx <= 1.f) & (fy <= 1.f);
-                if (in) {
-                    const int jx = (int)jxf, jy = (int)jyf;
+                // cell and mask of x + d, d = u (n - 1)/2 in voxels
+                const AxisCell ax = axis_cell(x, Disp{u[0] * snx, 0.f}, nx);
+                const AxisCell ay = axis_cell(y, Disp{u[1] * sny, 0.f}, ny);
+                if (ax.in && ay.in) {
+                    // a point on the last pixel takes the cell below with f = 1
+                    const bool ex = ax.t == nx - 1, ey = ay.t == ny - 1;
+                    const int jx = ex ? nx - 2 : ax.t, jy = ey ? ny - 2 : ay.t;
+                    const float fx = ex ? 1.f : ax.f, fy = ey ? 1.f : ay.f;
                     const int off = (jy * nx + jx) * 4;
                     const v2f a0 = load2(rM, off, 0);
                     const v2f a1 = load2(rM, off, nx4);
@@ -944,8 +964,8 @@ k_fused2(const LaunchCtx C) {
                     float d[2];
                     d[0] = g1 - g0;
                     d[1] = dy0 + fx * (dy1 - dy0);
-                    if (fx == 1.f) d[0] = -W;
-                    if (fy == 1.f) d[1] = -W;
+                    if (ex) d[0] = -W;
+                    if (ey) d[1] = -W;
                     cnt += 1;
                     if (SIM == AIR_SIM_NCC) {
                         const float dF = Fv - shF, dW = W - shW;

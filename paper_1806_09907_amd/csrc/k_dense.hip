@@ -56,10 +56,11 @@ __device__ inline DenseTile dense_tile(const PairDesc& P, int blk, int zc, int d
     return T;
 }
 
-// Trilinear sample of M at p (voxel units) with its gradient, branch-free:
-// the point is clamped into the volume so every load is in range, and m = 1
-// iff it lay inside [0, n-1]^3. At p_a = n_a - 1 the cell is
-// [n_a - 2, n_a - 1] with f = 1 and the derivative along a is the
+// Trilinear sample of M at the point (x, y, z) + d + e of a voxel (voxel
+// units; see axis_cell) with its gradient, branch-free: the cell is clamped
+// into the volume so every load is in range, and m = 1 iff the point lay
+// inside [0, n-1]^3. A point exactly on the last voxel uses the cell
+// [n_a - 2, n_a - 1] with f = 1, and its derivative along a is the
 // right-sided, zero-padded difference -W.
 struct Sample3 {
     float W, m, d[3];
@@ -71,24 +72,20 @@ struct Gather3 {
     float fx, fy, fz, m;
     bool ex, ey, ez;
 };
-__device__ inline Gather3 sample3_issue(__amdgpu_buffer_rsrc_t rM, float px, float py, float pz,
-                                        int nx, int ny, int nz) {
+__device__ inline Gather3 sample3_issue(__amdgpu_buffer_rsrc_t rM, int x, int y, int z, Disp qx,
+                                        Disp qy, Disp qz, int nx, int ny, int nz) {
     Gather3 g;
-    const bool in = (__float_as_uint(px) <= __float_as_uint((float)(nx - 1))) &&
-                    (__float_as_uint(py) <= __float_as_uint((float)(ny - 1))) &&
-                    (__float_as_uint(pz) <= __float_as_uint((float)(nz - 1)));
-    g.m = in ? 1.f : 0.f;
-    const float qx = __builtin_amdgcn_fmed3f(px, 0.f, (float)(nx - 1));
-    const float qy = __builtin_amdgcn_fmed3f(py, 0.f, (float)(ny - 1));
-    const float qz = __builtin_amdgcn_fmed3f(pz, 0.f, (float)(nz - 1));
-    const int tx = (int)qx, ty = (int)qy, tz = (int)qz;
-    g.ex = tx == nx - 1;
-    g.ey = ty == ny - 1;
-    g.ez = tz == nz - 1;
-    const int jx = min(tx, nx - 2), jy = min(ty, ny - 2), jz = min(tz, nz - 2);
-    g.fx = qx - (float)jx;
-    g.fy = qy - (float)jy;
-    g.fz = qz - (float)jz;
+    const AxisCell cx = axis_cell(x, qx, nx), cy = axis_cell(y, qy, ny), cz = axis_cell(z, qz, nz);
+    g.m = (cx.in && cy.in && cz.in) ? 1.f : 0.f;
+    g.ex = cx.t == nx - 1;
+    g.ey = cy.t == ny - 1;
+    g.ez = cz.t == nz - 1;
+    const int jx = min(max(cx.t, 0), nx - 2), jy = min(max(cy.t, 0), ny - 2);
+    const int jz = min(max(cz.t, 0), nz - 2);
+    // inside the mask f == 0 on the last voxel: its cell is the one below, f = 1
+    g.fx = g.ex ? 1.f : cx.f;
+    g.fy = g.ey ? 1.f : cy.f;
+    g.fz = g.ez ? 1.f : cz.f;
     const int off = (int)(__umul24(__umul24(jz, ny) + jy, nx) + jx) * 4;
     const int sx4 = nx * 4, sxy4 = nx * ny * 4;
     g.a00 = load2(rM, off, 0);
@@ -114,14 +111,9 @@ __device__ inline Sample3 sample3_finish(const Gather3& g) {
     r.d[2] = g.ez ? -r.W : h0 + fx * (h1 - h0);
     return r;
 }
-// Trilinear sample of M at p (voxel units) with its gradient, branch-free:
-// the point is clamped into the volume so every load is in range, and m = 1
-// iff it lay inside [0, n-1]^3. At p_a = n_a - 1 the cell is
-// [n_a - 2, n_a - 1] with f = 1 and the derivative along a is the
-// right-sided, zero-padded difference -W.
-__device__ inline Sample3 sample3(__amdgpu_buffer_rsrc_t rM, float px, float py, float pz,
-                                  int nx, int ny, int nz) {
-    return sample3_finish(sample3_issue(rM, px, py, pz, nx, ny, nz));
+__device__ inline Sample3 sample3(__amdgpu_buffer_rsrc_t rM, int x, int y, int z, Disp qx, Disp qy,
+                                  Disp qz, int nx, int ny, int nz) {
+    return sample3_finish(sample3_issue(rM, x, y, z, qx, qy, qz, nx, ny, nz));
 }
 
 template <int DIM, int SIM>
@@ -148,23 +140,24 @@ k_dense_pre(const LaunchCtx C, int zc) {
             const int zz = DIM == 3 ? z : 0;
             if (DIM == 2 && yy >= P.n[1]) break;
             const long long vi = ((long long)zz * P.n[1] + yy) * P.n[0] + T.x;
-            float p[3];
+            Disp q[3];
             const int idx[3] = {T.x, yy, zz};
             bool in = true;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
-                p[a] = fmaf(th[a * N + vi], P.s[a], (float)idx[a]);
-                if (!(p[a] >= 0.f && p[a] <= (float)(P.n[a] - 1))) in = false;
+                q[a] = disp_of(th[a * N + vi], P.s[a]);
+                if (!axis_cell(idx[a], q[a], P.n[a]).in) in = false;
             }
             if (SIM == AIR_SIM_MSE) {
                 cnt += in ? 1.f : 0.f;
             } else if (in) {
                 float W;
                 if constexpr (DIM == 3) {
-                    W = sample3(rM, p[0], p[1], p[2], P.n[0], P.n[1], P.n[2]).W;
+                    W = sample3(rM, idx[0], idx[1], idx[2], q[0], q[1], q[2], P.n[0], P.n[1],
+                                P.n[2]).W;
                 } else {
                     bool in2;
-                    W = sample_general<DIM>(M, P.n, p, &in2, nullptr);
+                    W = sample_general<DIM>(M, P.n, idx, q, &in2, nullptr);
                 }
                 const double f = F[vi], w = W;
                 v[0] += 1.0;
@@ -322,20 +315,20 @@ k_dense_main(const LaunchCtx C, int zc, int reg_only, float* reg_grad_out) {
                 const float Fv = F[vi];
                 float W, m, dW[3];
                 if constexpr (DIM == 3) {
-                    const Sample3 q = sample3(rM, fmaf(u0[0], P.s[0], (float)x),
-                                              fmaf(u0[1], P.s[1], (float)y),
-                                              fmaf(u0[2], P.s[2], (float)z), nx, ny, nz);
+                    const Sample3 q = sample3(rM, x, y, z, disp_of(u0[0], P.s[0]),
+                                              disp_of(u0[1], P.s[1]), disp_of(u0[2], P.s[2]),
+                                              nx, ny, nz);
                     W = q.W;
                     m = q.m;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) dW[c] = q.d[c];
                 } else {
-                    float p[3];
+                    Disp q[3];
                     const int idx[3] = {x, y, z};
 #pragma unroll
-                    for (int c = 0; c < DIM; ++c) p[c] = fmaf(u0[c], P.s[c], (float)idx[c]);
+                    for (int c = 0; c < DIM; ++c) q[c] = disp_of(u0[c], P.s[c]);
                     bool in;
-                    W = sample_general<DIM>(M, P.n, p, &in, dW);
+                    W = sample_general<DIM>(M, P.n, idx, q, &in, dW);
                     m = in ? 1.f : 0.f;
                 }
                 float e;
@@ -452,13 +445,12 @@ k_dense_main3(const LaunchCtx C, int zc, int reg_only, float* reg_grad_out) {
     }
     const float* Fc = F + vxy;
     const float s0 = P.s[0], s1 = P.s[1], s2 = P.s[2];
-    const float xf = (float)x, yf = (float)y;
     // regulariser-only calls have no images (F and M may be null): no loads
     float Fv = (act && !reg_only) ? Fc[z0 * sz] : 0.f;
     Gather3 G{};
     if (!reg_only)
-        G = sample3_issue(rM, fmaf(u0[0], s0, xf), fmaf(u0[1], s1, yf), fmaf(u0[2], s2, (float)z0),
-                          nx, ny, nz);
+        G = sample3_issue(rM, x, y, z0, disp_of(u0[0], s0), disp_of(u0[1], s1),
+                          disp_of(u0[2], s2), nx, ny, nz);
     float sq = 0.f, rr = 0.f;   // per-lane MSE and regulariser sums over the chunk
     for (int z = z0; z < z1; ++z) {
         const int bsel = (z - z0) & 1;
@@ -472,8 +464,8 @@ k_dense_main3(const LaunchCtx C, int zc, int reg_only, float* reg_grad_out) {
         const float Fn = (act && !reg_only) ? Fc[min(z + 1, nz - 1) * sz] : 0.f;
         Gather3 Gn{};
         if (!reg_only)
-            Gn = sample3_issue(rM, fmaf(up[0], s0, xf), fmaf(up[1], s1, yf),
-                               fmaf(up[2], s2, (float)(z + 1)), nx, ny, nz);
+            Gn = sample3_issue(rM, x, y, z + 1, disp_of(up[0], s0), disp_of(up[1], s1),
+                               disp_of(up[2], s2), nx, ny, nz);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             pl[bsel][c][own] = u0[c];
@@ -659,11 +651,11 @@ k_warp(const PairDesc* pairs, int pair, const float* consts, const float* __rest
                 u[c] = acc;
             }
         }
-        float p[3];
+        Disp q[3];
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) p[a] = fmaf(u[a], P.s[a], (float)idx[a]);
+        for (int a = 0; a < DIM; ++a) q[a] = disp_of(u[a], P.s[a]);
         bool in;
-        const float val = sample_general<DIM>(M, P.n, p, &in, nullptr);
+        const float val = sample_general<DIM>(M, P.n, idx, q, &in, nullptr);
         W[v] = val;
         if (mask) mask[v] = in ? 1 : 0;
     }

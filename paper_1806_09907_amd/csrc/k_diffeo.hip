@@ -27,23 +27,24 @@ __host__ inline int grid_for(long long total) {
     return (int)(b < kDiffeoBlocks ? (b < 1 ? 1 : b) : kDiffeoBlocks);
 }
 
-// Zero-padded multilinear sample of the DIM components of field u at p
-// (voxel units); with DERIV also dval[c][a] = d sample_c / d p_a on the cell
-// [floor(p), floor(p) + 1]. Returns false for a non-finite point (the values
-// are then NaN).
+// Zero-padded multilinear sample of the DIM components of field u at the
+// point x + d + e of a voxel (voxel units, see axis_cell); with DERIV also
+// dval[c][a] = d sample_c / d p_a on that point's cell (right-sided at an
+// integer point). Returns false for a non-finite point (the values are then
+// NaN). The value does not depend on the cell taken at an integer point, so
+// the forward squaring passes e = 0.
 template <int DIM, bool DERIV>
 __device__ inline bool field_sample(const float* __restrict__ u, long long N, const PairDesc& P,
-                                    const float* p, float* val, float (*dval)[3], int* j,
-                                    float* f) {
+                                    const int* x, const Disp* q, float* val, float (*dval)[3],
+                                    int* j, float* f) {
     bool finite = true;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        float pa = p[a];
-        if (!(pa == pa) || pa == INFINITY || pa == -INFINITY) finite = false;
-        pa = fminf(fmaxf(pa, -1e9f), 1e9f);
-        const float fl = floorf(pa);
-        j[a] = (int)fl;
-        f[a] = pa - fl;
+        const float d = q[a].d;
+        if (!(d == d) || d == INFINITY || d == -INFINITY) finite = false;
+        const AxisCell c = axis_cell(x[a], q[a], P.n[a]);
+        j[a] = c.t;
+        f[a] = c.f;
     }
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
@@ -246,15 +247,16 @@ k_compose(const PairDesc P, const float* __restrict__ u, float* __restrict__ out
                     for (int c = 0; c < DIM; ++c) un[c] = u[c * N + v + step];
                 }
                 const int idx[3] = {x, DIM == 3 ? y : y + kCompTY * k, DIM == 3 ? z0 + k : 0};
-                float p[3], val[3], f[3];
+                float val[3], f[3];
+                Disp q[3];
                 int j[3];
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) {
-                    const float t = fabsf(uc[a]) * P.s[a];
+                    q[a] = Disp{uc[a] * P.s[a], 0.f};
+                    const float t = fabsf(q[a].d);
                     m = (t > m || !(t == t)) ? t : m;
-                    p[a] = fmaf(uc[a], P.s[a], (float)idx[a]);
                 }
-                field_sample<DIM, false>(u, N, P, p, val, nullptr, j, f);
+                field_sample<DIM, false>(u, N, P, idx, q, val, nullptr, j, f);
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) {
                     out[c * N + v] = uc[c] + val[c];
@@ -338,10 +340,11 @@ k_compose_adj_tile(const PairDesc P, const float* __restrict__ u, const float* _
     const float scale = gfin ? ldexpf(1.f, 31 - ge) : 0.f;
     const double unscale = ldexp(1.0, ge - 31);
     const float poison = gfin ? 0.f : __uint_as_float(0x7fc00000u);   // NaN
-    // reach: a source x feeds corners floor(p) and floor(p) + 1 with
-    // |p - x| <= e, e = dmax plus a bound on the rounding of dmax and of p.
-    // A corner in [o, o + TS) needs p >= o - 1 and p < o + TS, so the
-    // sources lie in [o - 1 - floor(e), o + TS + ceil(e)) along each axis.
+    // reach: a source x feeds the corners t and t + 1 of its cell,
+    // t = x + floor(d) with |d| <= dmax < e (e = dmax plus a safety margin
+    // for the rounding of dmax). A corner in [o, o + TS) needs
+    // o - 1 <= t < o + TS, so the sources lie in
+    // [o - 1 - floor(e), o + TS + ceil(e)) along each axis.
     const float dm = __uint_as_float(*dmax_bits);
     int hlo = 1 << 20, hhi = 1 << 20;
     if (dm == dm && dm < 1e6f) {
@@ -366,12 +369,14 @@ k_compose_adj_tile(const PairDesc P, const float* __restrict__ u, const float* _
         bool finite = true;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            const float pa0 = fmaf(uv[a], P.s[a], (float)x[a]);
-            if (!(pa0 == pa0) || pa0 == INFINITY || pa0 == -INFINITY) finite = false;
-            const float pa = fminf(fmaxf(pa0, -1e9f), 1e9f);
-            const float fl = floorf(pa);
-            j[a] = (int)fl;
-            f[a] = pa - fl;
+            // the transposed weights (1 - f, f) of the cell below an integer
+            // point equal those of the cell above it, so e is not needed here
+            const float d0 = uv[a] * P.s[a];
+            if (!(d0 == d0) || d0 == INFINITY || d0 == -INFINITY) finite = false;
+            const float d = fminf(fmaxf(d0, -1e9f), 1e9f);
+            const float fl = floorf(d);
+            j[a] = x[a] + (int)fl;
+            f[a] = d - fl;
         }
         if (!finite) return;
         // corner bit b on axis a is q_a = j_a + b; it receives a term when
@@ -451,11 +456,12 @@ k_compose_adj_tile(const PairDesc P, const float* __restrict__ u, const float* _
         x[2] = DIM == 3 ? o[2] + t / (TS * TS) : 0;
         if (x[0] >= P.n[0] || x[1] >= P.n[1] || (DIM == 3 && x[2] >= P.n[2])) continue;
         const long long v = x[0] + (long long)P.n[0] * (x[1] + (DIM == 3 ? (long long)P.n[1] * x[2] : 0));
-        float p[3], val[3], f[3], dv[3][3];
+        float val[3], f[3], dv[3][3];
+        Disp q[3];
         int j[3];
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) p[a] = fmaf(u[a * N + v], P.s[a], (float)x[a]);
-        field_sample<DIM, true>(u, N, P, p, val, dv, j, f);
+        for (int a = 0; a < DIM; ++a) q[a] = disp_of(u[a * N + v], P.s[a]);
+        field_sample<DIM, true>(u, N, P, x, q, val, dv, j, f);
         float go[3];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) go[c] = gout[c * N + v];

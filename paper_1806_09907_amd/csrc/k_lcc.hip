@@ -53,12 +53,12 @@ k_lcc_sample(const PairDesc P, const float* __restrict__ M, const float* __restr
          v += (long long)gridDim.x * kBlock) {
         const int idx[3] = {(int)(v % P.n[0]), (int)((v / P.n[0]) % P.n[1]),
                             DIM == 3 ? (int)(v / ((long long)P.n[0] * P.n[1])) : 0};
-        float p[3];
+        Disp q[3];
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) p[a] = fmaf(u[a * N + v], P.s[a], (float)idx[a]);
+        for (int a = 0; a < DIM; ++a) q[a] = disp_of(u[a * N + v], P.s[a]);
         bool in;
         float d[3];
-        W[v] = sample_general<DIM>(M, P.n, p, &in, d);
+        W[v] = sample_general<DIM>(M, P.n, idx, q, &in, d);
         mk[v] = in ? 1 : 0;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) dW[a * N + v] = d[a];

@@ -102,6 +102,8 @@ def test_default_tiling_follows_the_documented_rule(dim, sizes):
     (dict(transform=9), 1),
     (dict(lambda_diff=-1.0), 1),
     (dict(n=(2048, 2048, 2048)), 2),
+    # fewer than 2^29 voxels, but n_y n_z reaches 2^24 (24-bit row index)
+    (dict(n=(8, 4096, 4096)), 2),
 ])
 def test_plan_rejects_bad_problems(bad, code):
     with pytest.raises(_lib.AirError) as e:

@@ -16,10 +16,10 @@ import oracle as O
 from paper_1806_09907_amd import api, synth
 from paper_1806_09907_amd._lib import AirError
 
+from parity import GRAD_TOL, VAL_TOL, check_grad
+
 pytestmark = pytest.mark.gpu
 
-VAL_TOL = 1e-5
-GRAD_TOL = 1e-4
 DEV = "cuda"
 
 
@@ -90,7 +90,7 @@ def test_objective_parity(n, tf, sp, sim, lam, K):
     vo, go, flags = O.objective_and_grad(oprob(p), F, M, th)
     assert flags == 0 and api.get_flags(plan)[0] == 0
     assert abs(float(v) - vo) <= VAL_TOL * abs(vo)
-    assert rel(g.double().cpu().numpy(), go) <= GRAD_TOL
+    check_grad(g, go, "diffeo")
 
 
 def test_objective_parity_128_bspline_ncc():
@@ -107,7 +107,7 @@ def test_objective_parity_128_bspline_ncc():
     vo, go, flags = O.objective_and_grad(oprob(p), pair.fixed, pair.moving, th)
     assert flags == 0
     assert abs(float(v) - vo) <= VAL_TOL * abs(vo)
-    assert rel(g.double().cpu().numpy(), go) <= GRAD_TOL
+    check_grad(g, go, "diffeo")
 
 
 @pytest.mark.parametrize("tf", [api.TF_DENSE, api.TF_BSPLINE3])
@@ -120,7 +120,7 @@ def test_regulariser_parity(tf):
     R, g = api.regulariser(api.Plan(p), gpu(th))
     Ro, go = O.regulariser(oprob(p), th)
     assert abs(float(R) - Ro) <= VAL_TOL * abs(Ro)
-    assert rel(g.double().cpu().numpy(), go) <= GRAD_TOL
+    check_grad(g, go, "diffeo")
 
 
 def test_repeat_runs_bitwise_equal():

@@ -11,10 +11,10 @@ import oracle as O
 from paper_1806_09907_amd import api, synth
 from paper_1806_09907_amd._lib import AirError
 
+from parity import GRAD_TOL, VAL_TOL, check_grad
+
 pytestmark = pytest.mark.gpu
 
-VAL_TOL = 1e-5
-GRAD_TOL = 1e-4
 DEV = "cuda"
 
 
@@ -73,7 +73,7 @@ def test_objective_parity_tv(kind, n, tf, sp, sim, lam, K):
     vo, go, flags = O.objective_and_grad(oprob(p), F, M, th)
     assert flags == 0
     assert abs(float(v) - vo) <= VAL_TOL * abs(vo)
-    assert rel(g.double().cpu().numpy(), go) <= GRAD_TOL
+    check_grad(g, go, "tv")
 
 
 @pytest.mark.parametrize("kind", KINDS)
@@ -87,7 +87,7 @@ def test_regulariser_parity_tv(kind, tf, K):
     R, g = api.regulariser(api.Plan(p), gpu(th))
     Ro, go = O.regulariser(oprob(p), th)
     assert abs(float(R) - Ro) <= VAL_TOL * abs(Ro)
-    assert rel(g.double().cpu().numpy(), go) <= GRAD_TOL
+    check_grad(g, go, "tv")
 
 
 def test_tv_128_bspline_ncc():
@@ -103,7 +103,7 @@ def test_tv_128_bspline_ncc():
     torch.cuda.synchronize()
     vo, go, _ = O.objective_and_grad(oprob(p), pair.fixed, pair.moving, th)
     assert abs(float(v) - vo) <= VAL_TOL * abs(vo)
-    assert rel(g.double().cpu().numpy(), go) <= GRAD_TOL
+    check_grad(g, go, "tv")
 
 
 def test_tv_rejections():

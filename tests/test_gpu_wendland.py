@@ -19,10 +19,10 @@ import oracle as O
 from paper_1806_09907_amd import api, synth
 from paper_1806_09907_amd._lib import AirError
 
+from parity import GRAD_TOL, VAL_TOL, check_grad
+
 pytestmark = pytest.mark.gpu
 
-VAL_TOL = 1e-5
-GRAD_TOL = 1e-4
 DEV = "cuda"
 
 
@@ -103,7 +103,7 @@ def test_objective_parity(n, sp, sig, sim, lam, K, reg):
     vo, go, flags = O.objective_and_grad(oprob(p), F, M, th)
     assert flags == 0 and api.get_flags(plan)[0] == 0
     assert abs(float(v) - vo) <= VAL_TOL * abs(vo)
-    assert rel(g.double().cpu().numpy(), go) <= GRAD_TOL
+    check_grad(g, go, "wendland")
 
 
 def test_objective_parity_128_ncc():
@@ -119,7 +119,7 @@ def test_objective_parity_128_ncc():
     vo, go, flags = O.objective_and_grad(oprob(p), pair.fixed, pair.moving, th)
     assert flags == 0
     assert abs(float(v) - vo) <= VAL_TOL * abs(vo)
-    assert rel(g.double().cpu().numpy(), go) <= GRAD_TOL
+    check_grad(g, go, "wendland")
 
 
 @pytest.mark.parametrize("reg", [api.REG_DIFFUSION, api.REG_ISO_TV])
@@ -130,7 +130,7 @@ def test_regulariser_parity(reg):
     R, g = api.regulariser(api.Plan(p), gpu(th))
     Ro, go = O.regulariser(oprob(p), th)
     assert abs(float(R) - Ro) <= VAL_TOL * abs(Ro)
-    assert rel(g.double().cpu().numpy(), go) <= GRAD_TOL
+    check_grad(g, go, "wendland")
 
 
 def test_unit_sigma_matches_dense_plan():
