@@ -188,6 +188,24 @@ air_status air_objective_and_grad(const air_plan* plan, const float* fixed,
                                   float* value, float* grad, void* ws, size_t ws_bytes,
                                   void* stream);
 
+/* air_objective_and_grad for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results, with the workspace taken from a library-owned
+ * device array of AIR_NOALLOC_SCRATCH_BYTES per GPU (held from the library's
+ * load on that GPU until the process ends) instead of a caller buffer. The
+ * call allocates nothing: the plan's tables must already be on the current
+ * device (air_plan_prepare, or an earlier launching call there), else
+ * AIR_ERR_DEVICE; plans whose air_plan_workspace_bytes exceeds
+ * AIR_NOALLOC_SCRATCH_BYTES return AIR_ERR_WORKSPACE (e.g. 128^3 B-spline
+ * NCC needs 2.4 MiB, 256^3 18.4 MiB, 256^3 dense 0.2 MiB; plans with the
+ * exponential need their fields and rarely fit). Every call on a GPU uses
+ * that GPU's one array: calls that overlap on one GPU (on different streams
+ * or threads) race and must be serialised by the caller. */
+#define AIR_NOALLOC_SCRATCH_BYTES (32u << 20)
+air_status air_objective_and_grad_noalloc(const air_plan* plan, const float* fixed,
+                                          const float* moving, const float* theta, float* value,
+                                          float* grad, void* stream);
+
 /* The same for every pair of the plan in one launch sequence. fixed, moving,
  * theta and grads are DEVICE arrays of npairs device pointers; values is a
  * device array of npairs floats. */

@@ -58,6 +58,7 @@ SIGNATURES = {
     "air_regulariser": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "air_objective_and_grad": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "air_objective_and_grad_batched": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "air_objective_and_grad_noalloc": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "air_adam_step": (_i32, [_vp, _vp, _vp, _vp, _i64, _f32, _f32, _f32, _f32, _i32, _vp]),
     "air_adam_bias_terms": (_i32, [_f32, _f32, _f32, _i32, _vp]),
     "air_adam_step_dev": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _f32, _f32, _f32, _vp]),

@@ -247,6 +247,26 @@ def objective_and_grad(plan: Plan, fixed: torch.Tensor, moving: torch.Tensor,
     return value, grad
 
 
+def objective_and_grad_noalloc(plan: Plan, fixed: torch.Tensor, moving: torch.Tensor,
+                               theta: torch.Tensor, value: Optional[torch.Tensor] = None,
+                               grad: Optional[torch.Tensor] = None):
+    """objective_and_grad through the entry point that allocates nothing (the
+    library's own per-GPU scratch array); the plan must be prepared on the
+    current device first (Plan.prepare)."""
+    p = plan.problems[0]
+    _need(fixed, p.shape, name="fixed")
+    _need(moving, p.shape, name="moving")
+    _need(theta, p.param_shape(), name="theta")
+    if value is None:
+        value = torch.empty((), dtype=torch.float32, device=theta.device)
+    if grad is None:
+        grad = torch.empty_like(theta)
+    check(lib().air_objective_and_grad_noalloc(plan.handle, _ptr(fixed), _ptr(moving),
+                                               _ptr(theta), _ptr(value), _ptr(grad), _stream()),
+          "air_objective_and_grad_noalloc")
+    return value, grad
+
+
 class PointerTable:
     """Device arrays of per-pair pointers for the batched entry point."""
 

@@ -574,6 +574,41 @@ static air_status ensure_device(const air_plan* cP, DeviceTables** out) {
 
 static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
+// The plan's tables on the current device if air_plan_prepare (or an earlier
+// launching call) put them there; never allocates.
+static air_status find_device(const air_plan* cP, DeviceTables** out) {
+    air_plan* P = const_cast<air_plan*>(cP);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return AIR_ERR_DEVICE;
+    std::lock_guard<std::mutex> g(P->mu);
+    if (!P->dev[dev].pairs) return AIR_ERR_DEVICE;
+    *out = &P->dev[dev];
+    return AIR_OK;
+}
+
+// Workspace of air_objective_and_grad_noalloc: one array per device, held
+// from the module's load until the process ends. Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol): the device address comes from hipGetSymbolAddress, once per
+// device, at that device's first call.
+static_assert(AIR_NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size");
+static __device__ __align__(256) unsigned char scratch[AIR_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+static air_status scratch_for_current_device(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return AIR_ERR_DEVICE;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return AIR_ERR_DEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return AIR_OK;
+}
+
 static LaunchCtx base_ctx(const air_plan* P, const DeviceTables* T, void* ws) {
     LaunchCtx C{};
     C.pairs = T->pairs;
@@ -1005,6 +1040,29 @@ air_status air_objective_and_grad(const air_plan* plan, const float* fixed, cons
     if (!aligned16(ws)) return AIR_ERR_ALIGN;
     DeviceTables* T = nullptr;
     air_status st = ensure_device(plan, &T);
+    if (st != AIR_OK) return st;
+    LaunchCtx C = base_ctx(plan, T, ws);
+    C.fixed0 = fixed;
+    C.moving0 = moving;
+    C.theta0 = theta;
+    C.grad0 = grad;
+    C.value0 = value;
+    return run_objective(plan, C, (hipStream_t)stream);
+}
+
+air_status air_objective_and_grad_noalloc(const air_plan* plan, const float* fixed,
+                                          const float* moving, const float* theta, float* value,
+                                          float* grad, void* stream) {
+    if (!plan || !fixed || !moving || !theta || !value || !grad) return AIR_ERR_INVALID_ARG;
+    if (plan->npairs != 1) return AIR_ERR_INVALID_ARG;
+    if (!aligned16(fixed) || !aligned16(moving) || !aligned16(theta) || !aligned16(grad))
+        return AIR_ERR_ALIGN;
+    if (plan->L.total > (size_t)AIR_NOALLOC_SCRATCH_BYTES) return AIR_ERR_WORKSPACE;
+    DeviceTables* T = nullptr;
+    air_status st = find_device(plan, &T);
+    if (st != AIR_OK) return st;
+    void* ws = nullptr;
+    st = scratch_for_current_device(&ws);
     if (st != AIR_OK) return st;
     LaunchCtx C = base_ctx(plan, T, ws);
     C.fixed0 = fixed;

@@ -260,8 +260,6 @@ k_fused3(const LaunchCtx C) {
     float m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f;
     const float snx = P.s[0], sny = P.s[1], snz = P.s[2];
     const int nx4 = nx * 4, nxy4 = nx * ny * 4;
-    const float nyf = (float)ny;
-    const int lane4 = (yc * nx + xc) * 4;   // byte offset of voxel (x, y, 0)
     const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, (uint32_t)(P.nvox * 4));
     float* part = reinterpret_cast<float*>(C.ws + C.L.part) + P.part_off +
                   (long long)(item - P.tile_begin) * P.part_stride;
@@ -687,9 +685,10 @@ k_fused3_s8(const LaunchCtx C) {
         q.fy = dy - cly;
         q.fz = dz - clz;
         constexpr uint32_t kOne = 0x3f800000u;   // bits of 1.0f: f in [0, 1]
-        const bool in = (__float_as_uint(q.fx) <= kOne) & (!q.ex | (dx == flx)) &
-                        (__float_as_uint(q.fy) <= kOne) & (!q.ey | (dy == fly)) &
-                        (__float_as_uint(q.fz) <= kOne) & (!q.ez | (dz == flz));
+        // (bitwise, not short-circuit: every test is a compare, no branch)
+        const bool in = (int)(__float_as_uint(q.fx) <= kOne) & (int)(!q.ex | (dx == flx)) &
+                        (int)(__float_as_uint(q.fy) <= kOne) & (int)(!q.ey | (dy == fly)) &
+                        (int)(__float_as_uint(q.fz) <= kOne) & (int)(!q.ez | (dz == flz));
         q.m = in ? mact : 0.f;
         // byte offset of the cell's first corner: the row step clz ny + cly
         // is an exact float (|.| < 2^24), the rest 24-bit integer arithmetic
