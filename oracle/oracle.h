@@ -38,7 +38,8 @@
  *   units      displacements and controls in normalised units; the sample
  *              point of voxel i is p_a = i_a + u_a * (n_a - 1) / 2 (voxels)
  *   mask       0 <= p_a <= n_a - 1 on every axis (inclusive), decided on p
- *              rounded to FP32 (the sampler's tensor precision), see below
+ *              computed in FP64 from the inputs as given (exact for FP32
+ *              inputs, see airo_sample)
  *   sampling   linear on the cell [floor(p), floor(p)+1], zero outside
  *   regulariser forward differences on u over X_R = prod_a [0, n_a - 2],
  *              normalised by |X_R|
