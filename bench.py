@@ -118,6 +118,8 @@ def parse():
                     help="time every tile configuration on this batch, write the cache here")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="default workload only: skip the uneven48 / dense256 / latency2d keys")
     ap.add_argument("--no-single-pair", action="store_true",
                     help="skip the one-pair latency loop of the default workload")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -127,18 +129,29 @@ def parse():
 
 
 def blob_batch(sizes, dev, seed_base=1):
-    """Blob pairs (40 blobs + noise) warped on the device by air_warp."""
+    """Blob pairs (40 blobs + noise) warped on the device by air_warp; pair i
+    draws from seed_for(seed_base, i)."""
     import torch
 
     from paper_1806_09907_amd import api, synth
 
-    Fs, Ms, Ts = [], [], []
-    plans = {}
-    for i, n3 in enumerate(sizes):
+    from concurrent.futures import ThreadPoolExecutor
+
+    def paint(i):
+        # each pair draws from its own seed, so the thread order is irrelevant
         rng = np.random.default_rng(synth.seed_for(seed_base, i))
+        n3 = sizes[i]
         fixed = synth.blobs(tuple(reversed(n3)), 40, rng)
         fixed = (fixed + rng.normal(0.0, 0.01, size=fixed.shape)).astype(np.float32)
         theta_gen = synth.control_field(n3, SPACING, 3.0, rng).astype(np.float32)
+        return fixed, theta_gen
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        painted = list(ex.map(paint, range(len(sizes))))
+    Fs, Ms, Ts = [], [], []
+    plans = {}
+    for i, n3 in enumerate(sizes):
+        fixed, theta_gen = painted[i]
         if n3 not in plans:
             plans[n3] = api.Plan(api.Problem(n=n3, spacing=SPACING, similarity=api.SIM_NCC))
         F = torch.from_numpy(fixed).to(dev)
@@ -230,10 +243,20 @@ def cpu_baseline(seconds, workload):
 
     cores = O.get_threads()
     n, el = rate(seconds)
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    cpu_model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     O.set_threads(1)
     n1, el1 = rate(seconds / 3)
     O.set_threads(cores)
     return {"value": scale * n / el, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model, "nproc": os.cpu_count(),
             "sample": f"{n} evaluations of {desc} in {el:.1f} s (FP64, OpenMP over slabs)",
             "value_one_core": scale * n1 / el1,
             "sample_one_core": f"{n1} evaluations in {el1:.1f} s on one thread"}
@@ -338,7 +361,7 @@ def timed(plan, steps, warmup, call):
     return ms_total / steps, k_ms / max(k_n, 1)
 
 
-def run_batch(args, dev, sizes, workload, desc):
+def run_batch(args, dev, sizes, workload, desc, seed_base=1):
     import torch
 
     from paper_1806_09907_amd import api, tune
@@ -346,7 +369,7 @@ def run_batch(args, dev, sizes, workload, desc):
     probs = [api.Problem(n=n3, spacing=SPACING, similarity=api.SIM_NCC, lambda_diff=0.05)
              for n3 in sizes]
     progress(f"painting {len(sizes)} pairs")
-    Fs, Ms, Ts = blob_batch(sizes, dev)
+    Fs, Ms, Ts = blob_batch(sizes, dev, seed_base)
     plan = api.Plan(probs)
     if args.autotune_out:
         rep = tune.autotune(plan, Fs, Ms, Ts, reps=10, cache_path=args.autotune_out, verbose=True)
@@ -393,6 +416,26 @@ def run_batch(args, dev, sizes, workload, desc):
                      "algorithmic_bytes_per_launch": bytes_fused,
                      "pipes": pipes_for(workload)},
     }
+
+
+def run_uneven48(args, dev):
+    from paper_1806_09907_amd import synth
+
+    return run_batch(args, dev, synth.uneven_sizes(48), "uneven48",
+                     "48 uneven 3D pairs (sides from {96,112,128,144,160}), B-spline NCC + "
+                     "0.05 diffusion, one launch", seed_base=3)
+
+
+def extra_line(out, kind):
+    """The part of another workload's result that the default line carries."""
+    r = out["roofline"]
+    keep = {k: r[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
+                              "kernel_ms") if k in r}
+    e = {"metric": out["metric"], "value": out["value"], "unit": out["unit"],
+         "ms_per_step": out["ms_per_step"], "config": out["config"], "roofline": keep}
+    if kind == "latency2d":
+        e["roofline"]["note"] = r.get("note")
+    return e
 
 
 def gpu_warp_fn(dev):
@@ -789,9 +832,7 @@ def main():
     elif args.workload == "uneven48":
         from paper_1806_09907_amd import synth
 
-        out = run_batch(args, dev, synth.uneven_sizes(48), "uneven48",
-                        "48 uneven 3D pairs (sides from {96,112,128,144,160}), B-spline NCC + "
-                        "0.05 diffusion, one launch")
+        out = run_uneven48(args, dev)
     elif args.workload == "dense256":
         out = run_dense(args, dev)
     elif args.workload in ("diffeo256", "diffeo2d"):
@@ -814,6 +855,21 @@ def main():
         line["roofline"]["frac_of_copy"] = line["roofline"]["achieved"] / cg
     if "single_pair" in out:
         line["single_pair"] = out["single_pair"]
+    if args.workload == "batch128" and not args.no_extra:
+        # the other configurations, measured by the same run: the 48-pair
+        # uneven batch, the 256^3 dense pair and the 64^2 latency case
+        import argparse as _ap
+        sub = _ap.Namespace(**{**vars(args), "steps": max(5, min(args.steps, 20)),
+                               "warmup": min(args.warmup, 3), "tiling": -1, "autotune_out": ""})
+        extra = {}
+        progress("extra workload: uneven48")
+        extra["uneven48"] = extra_line(run_uneven48(sub, dev), "uneven48")
+        progress("extra workload: dense256")
+        extra["dense256"] = extra_line(run_dense(sub, dev), "dense256")
+        progress("extra workload: latency2d")
+        sub2 = _ap.Namespace(**{**vars(sub), "steps": 200, "warmup": 20})
+        extra["latency2d"] = extra_line(run_latency2d(sub2, dev), "latency2d")
+        line["extra"] = extra
     if args.workload == "batch128" and not args.no_learned:
         progress("training and evaluating the learned initialisation")
         line["secondary"] = learned_secondary(dev)

@@ -1,10 +1,12 @@
 """torch.autograd.Function around the hand-written adjoint.
 
 forward() evaluates the objective and its gradient in one call of
-air_objective_and_grad and keeps the gradient; backward() multiplies the
-kept gradient by the incoming scalar with air_scale. PyTorch's tape never
-differentiates the registration itself (it replaces the automatic
-differentiation of the paper's Sec. III-A with a hand-written adjoint).
+air_objective_and_grad and keeps the gradient; backward() multiplies a copy
+of the kept gradient by the incoming scalar with air_scale, so the kept
+gradient is never changed (a second backward over a retained graph sees it
+intact). PyTorch's tape never differentiates the registration itself (it
+replaces the automatic differentiation of the paper's Sec. III-A with a
+hand-written adjoint).
 """
 from __future__ import annotations
 
@@ -28,8 +30,9 @@ class ObjectiveFn(torch.autograd.Function):
     @once_differentiable
     def backward(ctx, grad_out: torch.Tensor):
         (grad,) = ctx.saved_tensors
-        api.scale_(grad, grad_out.detach().to(torch.float32).contiguous())
-        return grad, None, None, None
+        out = grad.clone()
+        api.scale_(out, grad_out.detach().to(torch.float32).contiguous())
+        return out, None, None, None
 
 
 def objective(theta: torch.Tensor, plan: api.Plan, fixed: torch.Tensor,

@@ -97,13 +97,15 @@ def control_field(n_xyz: Sequence[int], spacing: Sequence[int], std_vox: float,
 def ellipsoid_volume(n: int, rng: np.random.Generator, count: int = 16,
                      semi=(8.0, 80.0), intensity=(-1000.0, 1000.0),
                      background=-1000.0, smooth_sigma=1.5) -> np.ndarray:
-    """CT-like piecewise-constant ellipsoids, smoothed by a Gaussian."""
+    """CT-like piecewise-constant ellipsoids, smoothed by a Gaussian.
+
+    Each ellipsoid (centre, semi-axes, rotation from a random unit quaternion,
+    intensity) is painted over the voxels with Rt (x - c) inside the axes,
+    in drawing order; only its bounding box is visited (half extent
+    sqrt(sum_j R_ij^2 a_j^2) along world axis i)."""
     from scipy.ndimage import gaussian_filter
 
     vol = np.full((n, n, n), background, dtype=np.float64)
-    zz, yy, xx = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
-    pts = np.stack([xx, yy, zz], axis=-1).reshape(-1, 3).astype(np.float64)
-    flat = vol.reshape(-1)
     for _ in range(count):
         centre = rng.uniform(0.0, n - 1, size=3)
         axes = rng.uniform(*semi, size=3)
@@ -116,9 +118,20 @@ def ellipsoid_volume(n: int, rng: np.random.Generator, count: int = 16,
             [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)],
         ])
         value = rng.uniform(*intensity)
-        local = (pts - centre) @ rot
-        inside = np.sum((local / axes) ** 2, axis=1) <= 1.0
-        flat[inside] = value
+        ext = np.sqrt((rot ** 2) @ (axes ** 2))
+        lo = np.clip(np.floor(centre - ext).astype(int) - 1, 0, n)
+        hi = np.clip(np.ceil(centre + ext).astype(int) + 2, 0, n)
+        if np.any(hi <= lo):
+            continue
+        dz = (np.arange(lo[2], hi[2], dtype=np.float64) - centre[2])[:, None, None]
+        dy = (np.arange(lo[1], hi[1], dtype=np.float64) - centre[1])[None, :, None]
+        dx = (np.arange(lo[0], hi[0], dtype=np.float64) - centre[0])[None, None, :]
+        r = 0.0
+        for j in range(3):
+            lj = dx * rot[0, j] + dy * rot[1, j] + dz * rot[2, j]
+            r = r + (lj / axes[j]) ** 2
+        box = vol[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+        box[r <= 1.0] = value
     return gaussian_filter(vol, sigma=smooth_sigma, mode="nearest", truncate=4.0)
 
 

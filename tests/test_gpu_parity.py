@@ -512,6 +512,20 @@ def test_autograd_function_matches_direct_and_oracle():
     check_grad(th.grad.double().cpu().numpy() / 2.0, go, "autograd")
 
 
+def test_autograd_second_backward_sees_the_kept_gradient():
+    """backward() scales a copy: two backward passes over a retained graph, or
+    torch.autograd.grad twice, return the same gradient."""
+    n = (33, 33, 33)
+    p = api.Problem(n=n, spacing=(8, 8, 8), similarity=api.SIM_NCC, lambda_diff=0.05)
+    F, M = blob_inputs(n, 8, 91)
+    plan = api.Plan(p)
+    th = gpu(theta_for(p, "rand", 95)).requires_grad_(True)
+    L = ObjectiveFn.apply(th, plan, gpu(F), gpu(M))
+    (g1,) = torch.autograd.grad(3.0 * L, th, retain_graph=True)
+    (g2,) = torch.autograd.grad(3.0 * L, th)
+    assert torch.equal(g1, g2)
+
+
 def test_autograd_finite_difference_fp32():
     """Loose FP32 central difference through the autograd Function. The field
     and the probe direction live on interior controls only (spacing 4 on a
