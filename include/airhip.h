@@ -324,6 +324,22 @@ air_status air_cnn_output_bwd(const float* dtheta, const int32_t gdims[3], int32
 /* a += b (FP32). */
 air_status air_add_f32(float* a, const float* b, int64_t n, void* stream);
 
+/* ---- Synthetic inputs (not part of the paper's method). ----
+ * Blob volumes of the 3D workloads painted on the device from parameters
+ * drawn by the caller: out[z][y][x] = sum_b amp_b exp(-|(x,y,z) - c_b|^2 /
+ * (2 sigma_b^2)) over dims = (nx, ny, nz), params a device FP32 array
+ * [nblobs][5] = (cx, cy, cz, sigma, amp), nblobs <= 256, fewer than 2^31
+ * voxels (AIR_ERR_SHAPE). */
+air_status air_synth_blobs(const float* params, int32_t nblobs, const int32_t dims[3], float* out,
+                           void* stream);
+/* x[i] += stddev * N_i for i < n, N_i the i-th standard normal variate of the
+ * stream `seed`: Philox4x32-10 (Salmon et al., SC 2011) at counter
+ * (i / 4, 0, 0, 0) and key (seed mod 2^32, seed / 2^32), word i mod 4, each
+ * word w mapped to u = (floor(w / 256) + 1/2) 2^-24 and the pairs (u0, u1),
+ * (u2, u3) of a counter turned into normals by the Box-Muller transform
+ * (sqrt(-2 ln u0) cos(2 pi u1), sqrt(-2 ln u0) sin(2 pi u1), ...). */
+air_status air_synth_add_normal(float* x, int64_t n, uint64_t seed, float stddev, void* stream);
+
 /* Kernel timing for benchmarks: reserve `launches` pairs of HIP events; each
  * following objective call records one pair on its stream around its main
  * kernel (the fused B-spline kernel, or the dense main pass) until the

@@ -59,6 +59,8 @@ SIGNATURES = {
     "air_objective_and_grad": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "air_objective_and_grad_batched": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "air_objective_and_grad_noalloc": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "air_synth_blobs": (_i32, [_vp, _i32, ctypes.POINTER(_i32), _vp, _vp]),
+    "air_synth_add_normal": (_i32, [_vp, _i64, ctypes.c_uint64, _f32, _vp]),
     "air_adam_step": (_i32, [_vp, _vp, _vp, _vp, _i64, _f32, _f32, _f32, _f32, _i32, _vp]),
     "air_adam_bias_terms": (_i32, [_f32, _f32, _f32, _i32, _vp]),
     "air_adam_step_dev": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _f32, _f32, _f32, _vp]),

@@ -267,6 +267,28 @@ def objective_and_grad_noalloc(plan: Plan, fixed: torch.Tensor, moving: torch.Te
     return value, grad
 
 
+def synth_blobs(params: torch.Tensor, shape_zyx, out: Optional[torch.Tensor] = None
+                ) -> torch.Tensor:
+    """Blob volume [nz][ny][nx] painted on the device from params [nb][5]
+    (cx, cy, cz, sigma, amplitude; FP32 device tensor)."""
+    _need(params, (params.shape[0], 5), name="params")
+    nz, ny, nx = (int(v) for v in shape_zyx)
+    if out is None:
+        out = torch.empty((nz, ny, nx), dtype=torch.float32, device=params.device)
+    dims = (ctypes.c_int32 * 3)(nx, ny, nz)
+    check(lib().air_synth_blobs(_ptr(params), int(params.shape[0]), dims, _ptr(out), _stream()),
+          "air_synth_blobs")
+    return out
+
+
+def synth_add_normal(x: torch.Tensor, seed: int, stddev: float) -> torch.Tensor:
+    """x += stddev * N(0, 1) noise of the counter-based stream `seed` (in place)."""
+    _need(x, None, name="x")
+    check(lib().air_synth_add_normal(_ptr(x), x.numel(), int(seed) & ((1 << 64) - 1),
+                                     float(stddev), _stream()), "air_synth_add_normal")
+    return x
+
+
 class PointerTable:
     """Device arrays of per-pair pointers for the batched entry point."""
 

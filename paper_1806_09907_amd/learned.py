@@ -1,19 +1,24 @@
 """Training and evaluation of the learned initialisation.
 
 Training pairs are made by the method itself: blob volumes (parameters drawn
-with numpy from per-pair seeds, painted on the device) warped with random
-cubic B-spline fields by air_warp. The loss is the registration objective
-(NCC + 0.05 diffusion) at the predicted control grid, whose gradient comes
-from air_objective_and_grad; an optional warm-up regresses the prediction
-onto -theta_gen (an approximate inverse for small fields).
+with numpy from per-pair seeds, painted and noised on the device) warped with
+random cubic B-spline fields by air_warp. The loss is the registration
+objective (NCC + 0.05 diffusion) at the predicted control grid, whose
+gradient comes from air_objective_and_grad; an optional warm-up regresses the
+prediction onto -theta_gen (an approximate inverse for small fields).
 
-Evaluation (held-out pairs): zero-init plain registration runs 200 Adam
-iterations (lr 0.01) and its final image MSE is the target; the learned run
-predicts theta0, keeps the better of theta0 and 0 by objective value (the
-start judge), and refines until the image MSE reaches the target (cap 200
-iterations). A pair whose learned run never reaches the target is a
-fallback: its learned time is charged as the learned attempt plus the full
-zero-init run.
+Evaluation (held-out pairs), timed per pair with HIP events:
+* zero start: 200 Adam iterations (lr 0.01) from theta = 0; its final image
+  MSE is the pair's target, and its time to target is the time until the
+  first monitored MSE at or below it;
+* learned start: the network predicts theta0, a start judge keeps the better
+  of theta0 and 0 by objective value, and the plain registration refines
+  from there (cap 200 iterations); its time to target counts from before the
+  network's forward pass;
+* fallback: when the refined result is worse than the zero start's (the
+  learned run's image MSE never reaches the target within the cap), the
+  method falls back to the zero start; that pair is charged the whole
+  learned attempt plus a full zero-start run.
 """
 from __future__ import annotations
 
@@ -38,13 +43,15 @@ LAMBDA = 0.05
 
 class PairGenerator:
     """Blob pairs on the device: F = sum of 40 Gaussian blobs + N(0, 0.01)
-    noise, M = warp(F, theta_gen) with theta_gen ~ N(0, 3 voxels)."""
+    noise, M = warp(F, theta_gen) with theta_gen ~ N(0, 3 voxels). The blob
+    parameters and theta_gen are drawn with numpy from the pair's seed; the
+    library paints the blobs, adds the noise (its counter-based stream keyed
+    by the seed) and warps."""
 
     def __init__(self, n: int, device):
         self.n = n
         self.dev = torch.device(device)
         self.plan = api.Plan(api.Problem(n=(n, n, n), spacing=SPACING, similarity=api.SIM_MSE))
-        self.ax = torch.arange(n, dtype=torch.float32, device=self.dev)
 
     def pair(self, seed: int, disp_vox: float = 3.0):
         n = self.n
@@ -53,16 +60,9 @@ class PairGenerator:
         s = rng.uniform(3.0, 10.0, size=40)
         a = rng.uniform(0.0, 1.0, size=40)
         theta = synth.control_field((n, n, n), SPACING, disp_vox, rng).astype(np.float32)
-        ct = torch.tensor(c, dtype=torch.float32, device=self.dev)
-        st = torch.tensor(s, dtype=torch.float32, device=self.dev)[:, None]
-        at = torch.tensor(a, dtype=torch.float32, device=self.dev)[:, None]
-        ex = torch.exp(-0.5 * ((self.ax[None, :] - ct[:, 0:1]) / st) ** 2) * at
-        ey = torch.exp(-0.5 * ((self.ax[None, :] - ct[:, 1:2]) / st) ** 2)
-        ez = torch.exp(-0.5 * ((self.ax[None, :] - ct[:, 2:3]) / st) ** 2)
-        F = torch.einsum("bz,by,bx->zyx", ez, ey, ex).contiguous()
-        g = torch.Generator(device=self.dev)
-        g.manual_seed(int(seed))
-        F = (F + 0.01 * torch.randn(F.shape, generator=g, device=self.dev)).contiguous()
+        prm = np.concatenate([c, s[:, None], a[:, None]], axis=1).astype(np.float32)
+        F = api.synth_blobs(torch.from_numpy(prm).to(self.dev), (n, n, n))
+        api.synth_add_normal(F, int(seed), 0.01)
         th = torch.from_numpy(theta).to(self.dev)
         M, _ = api.warp(self.plan, F, th, want_mask=False)
         return F, M, th
@@ -106,9 +106,33 @@ def train(net: InitNet, pairs: int = 2000, epochs: int = 2, lr: float = 1e-3,
             "objective_last": hist[max(0, step - 100):step].mean().item()}
 
 
-def _first_reach(monitor: torch.Tensor, target: float) -> Optional[int]:
-    ok = (monitor <= target).nonzero()
-    return int(ok[0]) if ok.numel() else None
+def first_reach(monitor, target: float) -> Optional[int]:
+    """Index of the first monitored MSE at or below the target, else None."""
+    for k, v in enumerate(monitor):
+        if float(v) <= target:
+            return k
+    return None
+
+
+def pair_outcome(target: float, zero_mon, zero_ms, learned_mon, learned_ms) -> dict:
+    """Time to the target from both starts, from measured monitor times.
+
+    zero_mon / zero_ms: image MSE at theta_k of the zero-start run and the
+    time (ms, from that run's start) at which it was known, k = 0 .. K.
+    learned_mon / learned_ms: the same for the learned run, times counted from
+    before the network's forward pass. If the learned run never reaches the
+    target, its refined result is worse than the zero start's: the pair falls
+    back to the zero start and is charged the whole learned attempt plus the
+    full zero-start run."""
+    k0 = first_reach(zero_mon, target)
+    if k0 is None:
+        raise ValueError("the zero-start run defines the target and must reach it")
+    t_zero = float(zero_ms[k0])
+    k1 = first_reach(learned_mon, target)
+    fallback = k1 is None
+    t_learned = (float(learned_ms[-1]) + float(zero_ms[-1])) if fallback else float(learned_ms[k1])
+    return {"k_zero": k0, "k_learned": k1, "fallback": fallback, "t_zero_ms": t_zero,
+            "t_learned_ms": t_learned, "speedup": t_zero / t_learned}
 
 
 def evaluate(net: InitNet, npairs: int = 100, iters: int = 200, lr: float = 0.01,
@@ -119,58 +143,45 @@ def evaluate(net: InitNet, npairs: int = 100, iters: int = 200, lr: float = 0.01
     prob = api.Problem(n=(n, n, n), spacing=SPACING, similarity=api.SIM_NCC, lambda_diff=LAMBDA)
     plan = api.Plan(prob)
     zero = torch.zeros(prob.param_shape(), dtype=torch.float32, device=dev)
-    # per-iteration cost of plain refinement (no monitoring), and CNN + judge cost
+    # warm-up of every kernel the timed runs use
     F, M, _ = gen.pair(synth.heldout_seed(0))
-    t_iter = Registration(prob, F, M, lr=lr, iterations=iters).run().seconds / iters
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for _ in range(3):
-        net.forward(F, M)
-    ev0.record()
-    reps = 20
-    for _ in range(reps):
-        th = net.forward(F, M)
-        api.objective_and_grad(plan, F, M, th)
-        api.objective_and_grad(plan, F, M, zero)
-    ev1.record()
-    torch.cuda.synchronize()
-    t_cnn_judge = ev0.elapsed_time(ev1) / 1e3 / reps
+    Registration(prob, F, M, lr=lr, iterations=5, monitor_mse=True).run(net.forward(F, M))
     rows = []
     for p in range(npairs):
         F, M, th_gen = gen.pair(synth.heldout_seed(p))
         reg = Registration(prob, F, M, lr=lr, iterations=iters, monitor_mse=True)
+        torch.cuda.synchronize()
         r0 = reg.run()
         target = float(r0.monitor[-1])
-        k0 = _first_reach(r0.monitor, target)
-        theta0 = net.forward(F, M).clone()
+        # learned start: network, start judge, refinement, all on the clock
+        t0 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        theta0 = net.forward(F, M)
         v_l, _ = api.objective_and_grad(plan, F, M, theta0)
         v_z, _ = api.objective_and_grad(plan, F, M, zero)
         judged_zero = float(v_l) >= float(v_z)
-        start = zero if judged_zero else theta0
-        r1 = reg.run(start)
-        k1 = _first_reach(r1.monitor, target)
-        t0 = k0 * t_iter
-        if k1 is None:
-            t1 = t_cnn_judge + iters * t_iter + t0
-        else:
-            t1 = t_cnn_judge + k1 * t_iter
-        rows.append({"pair": p, "target_mse": target, "mse0_start": float(r0.monitor[0]),
-                     "mse_learned_start": float(r1.monitor[0]), "k_zero": k0,
-                     "k_learned": k1, "judged_zero": judged_zero,
-                     "objective_zero_start": float(v_z), "objective_learned_start": float(v_l),
-                     "t_zero": t0, "t_learned": t1, "speedup": t0 / t1})
+        r1 = reg.run(zero if judged_zero else theta0, start_event=t0)
+        out = pair_outcome(target, r0.monitor, r0.monitor_ms, r1.monitor, r1.monitor_ms)
+        rows.append({"pair": p, "target_mse": target, "mse_zero_start": float(r0.monitor[0]),
+                     "mse_learned_start": float(r1.monitor[0]), "judged_zero": judged_zero,
+                     "objective_zero_start": float(v_z),
+                     "objective_learned_start": float(v_l), **out})
         if log and (p % 10 == 0 or p == npairs - 1):
-            log(f"eval pair {p}: target {target:.3e} k0 {k0} k1 {k1} "
-                f"judged_zero {judged_zero} speedup {t0 / t1:.2f}")
+            log(f"eval pair {p}: target {target:.3e} k0 {out['k_zero']} k1 {out['k_learned']} "
+                f"judged_zero {judged_zero} t0 {out['t_zero_ms']:.2f} ms "
+                f"t1 {out['t_learned_ms']:.2f} ms speedup {out['speedup']:.2f}")
     sp = np.array([r["speedup"] for r in rows])
-    reached = sum(r["k_learned"] is not None for r in rows)
-    return {"pairs": npairs, "iterations": iters, "t_iter_ms": t_iter * 1e3,
-            "t_cnn_judge_ms": t_cnn_judge * 1e3,
+    t0s = np.array([r["t_zero_ms"] for r in rows])
+    t1s = np.array([r["t_learned_ms"] for r in rows])
+    fb = sum(r["fallback"] for r in rows)
+    return {"pairs": npairs, "iterations": iters, "timing": "HIP events per pair",
             "median_speedup": float(np.median(sp)), "mean_speedup": float(np.mean(sp)),
-            "fraction_reached": reached / npairs,
+            "median_time_zero_ms": float(np.median(t0s)),
+            "median_time_learned_ms": float(np.median(t1s)),
+            "mean_time_zero_ms": float(np.mean(t0s)), "mean_time_learned_ms": float(np.mean(t1s)),
+            "fraction_reached": (npairs - fb) / npairs,
             "fallback_judge": int(sum(r["judged_zero"] for r in rows)),
-            "fallback_not_reached": npairs - reached,
-            "mean_time_zero_ms": float(np.mean([r["t_zero"] for r in rows]) * 1e3),
-            "mean_time_learned_ms": float(np.mean([r["t_learned"] for r in rows]) * 1e3),
+            "fallback_not_reached": int(fb),
             "mean_k_zero": float(np.mean([r["k_zero"] for r in rows])),
             "mean_k_learned": float(np.mean([r["k_learned"] if r["k_learned"] is not None
                                              else iters for r in rows])),

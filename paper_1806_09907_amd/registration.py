@@ -30,6 +30,9 @@ class RegistrationResult:
     monitor: Optional[torch.Tensor]     # monitored image MSE per iteration (host) or None
     seconds: float                      # GPU time of the loop (events)
     iterations: int
+    # with monitoring: milliseconds from the start event to the moment each
+    # monitored MSE (at theta_k, k = 0 .. iterations) was known on the device
+    monitor_ms: Optional[List[float]] = None
 
 
 class Registration:
@@ -52,7 +55,11 @@ class Registration:
 
     def run(self, theta0: Optional[torch.Tensor] = None,
             stop_below: Optional[float] = None, check_every: int = 10,
-            graph_chunk: int = 0) -> RegistrationResult:
+            graph_chunk: int = 0, start_event=None) -> RegistrationResult:
+        """Adam from theta0 (zero by default). With monitoring, a HIP event is
+        recorded after each monitored MSE, and monitor_ms holds their times
+        from `start_event` (recorded by the caller before work it wants
+        counted, e.g. a network forward pass) or from the loop's own start."""
         dev = self.fixed.device
         shape = self.problem.param_shape()
         theta = (torch.zeros(shape, dtype=torch.float32, device=dev) if theta0 is None
@@ -71,11 +78,16 @@ class Registration:
                 raise ValueError("graph mode does not monitor the image MSE")
             return self._run_graph(theta, grad, m, v, vals, graph_chunk, start, stop)
         start.record()
+        t0 = start if start_event is None else start_event
+        marks = [] if mon is not None else None
         done = self.iterations
         for it in range(self.iterations):
             if mon is not None:
                 api.objective_and_grad(self.monitor_plan, self.fixed, self.moving, theta,
                                        value=mon[it], grad=mgrad)
+                ev = torch.cuda.Event(enable_timing=True)
+                ev.record()
+                marks.append(ev)
                 if stop_below is not None and (it % check_every == 0):
                     if float(mon[it].item()) <= stop_below:
                         done = it
@@ -86,11 +98,16 @@ class Registration:
         if mon is not None and done == self.iterations:
             api.objective_and_grad(self.monitor_plan, self.fixed, self.moving, theta,
                                    value=mon[self.iterations], grad=mgrad)
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record()
+            marks.append(ev)
         stop.record()
         torch.cuda.synchronize()
+        ms = None if marks is None else [t0.elapsed_time(e) for e in marks[:done + 1]]
         return RegistrationResult(theta=theta, objective=vals[:max(done, 1)].cpu(),
                                   monitor=None if mon is None else mon[:done + 1].cpu(),
-                                  seconds=start.elapsed_time(stop) / 1e3, iterations=done)
+                                  seconds=start.elapsed_time(stop) / 1e3, iterations=done,
+                                  monitor_ms=ms)
 
 
     def _run_graph(self, theta, grad, m, v, vals, K, start, stop) -> RegistrationResult:
