@@ -111,7 +111,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batch128",
                     choices=["batch128", "uneven48", "dense256", "latency2d", "diffeo256",
-                             "diffeo2d", "tv128", "wendland128", "lcc128"])
+                             "diffeo2d", "tv128", "wendland128", "lcc128", "cnn128"])
     ap.add_argument("--pairs", type=int, default=64)
     ap.add_argument("--tiling", type=int, default=-1, help="-1: autotune cache or default")
     ap.add_argument("--autotune-out", default="",
@@ -791,6 +791,51 @@ def cnn_throughput(net, dev, reps=20):
                     "the convolutions"}
 
 
+def run_cnn128(args, dev):
+    """Training steps of the initialisation network (forward + backward of
+    one 128^3 pair, BF16 MFMA convolutions) and inference passes."""
+    import torch
+
+    from paper_1806_09907_amd import synth
+    from paper_1806_09907_amd.cnn import InitNet
+    from paper_1806_09907_amd.learned import PairGenerator
+
+    net = InitNet(n=128, device=dev, seed=0)
+    F, M, _ = PairGenerator(128, dev).pair(synth.heldout_seed(0))
+    dth = torch.full_like(net.forward(F, M), 1e-3)
+    fwd_fl, bwd_fl = cnn_flops(128)
+    for _ in range(args.warmup):
+        net.forward(F, M)
+        net.backward(dth)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(args.steps):
+        net.forward(F, M)
+    ev[1].record()
+    for _ in range(args.steps):
+        net.forward(F, M)
+        net.backward(dth)
+    ev[2].record()
+    torch.cuda.synchronize()
+    t_f = ev[0].elapsed_time(ev[1]) / args.steps
+    t_fb = ev[1].elapsed_time(ev[2]) / args.steps
+    ach = (fwd_fl + bwd_fl) / (t_fb / 1e3) / 1e12
+    return {
+        "metric": "learned-initialisation network training steps/s (forward + backward, 128^3)",
+        "value": 1e3 / t_fb, "unit": "steps/s", "ms_per_step": t_fb,
+        "config": {"workload": "3D encoder-decoder (16/32/48/64 channels) on one 128^3 pair, "
+                               "BF16 weights and activations, FP32 accumulation",
+                   "forward_ms": t_f, "forward_gflop": fwd_fl / 1e9,
+                   "backward_gflop": bwd_fl / 1e9,
+                   "forward_tflops": fwd_fl / (t_f / 1e3) / 1e12},
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": ach / 2500.0, "traffic": None,
+                     "kernel": "whole training step (convolutions and the kernels between)",
+                     "kernel_ms": t_fb},
+    }
+
+
 def learned_secondary(dev):
     """Train the initialisation network (2000 pairs x 2 epochs) and evaluate
     time to the zero-init target MSE on 100 held-out 128^3 pairs."""
@@ -847,6 +892,8 @@ def main():
         out = run_wendland128(args, dev)
     elif args.workload == "lcc128":
         out = run_lcc128(args, dev)
+    elif args.workload == "cnn128":
+        out = run_cnn128(args, dev)
     else:
         out = run_latency2d(args, dev)
     line = {"metric": out["metric"], "value": out["value"], "unit": out["unit"], "n_gpus": 1,
@@ -877,7 +924,7 @@ def main():
     if args.workload == "batch128" and not args.no_learned:
         progress("training and evaluating the learned initialisation")
         line["secondary"] = learned_secondary(dev)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload != "cnn128":
         progress("timing the CPU oracle")
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, args.workload)
     print(json.dumps(line), flush=True)

@@ -216,6 +216,28 @@ air_status air_objective_and_grad_batched(const air_plan* plan,
                                           float* const* grads, void* ws, size_t ws_bytes,
                                           void* stream);
 
+/* Tile autotuner of the fused B-spline launch (not in the paper; the plan's
+ * tile configuration, air_plan_set_tiling, only changes the summation
+ * order). air_autotune times every configuration valid for the plan on the
+ * caller's batch (arguments as air_objective_and_grad_batched; ws of at
+ * least air_autotune_workspace_bytes), one upload call and two warm-up
+ * launches then `reps` launches between two HIP events on `stream`; checks
+ * that each configuration's values and gradients agree with the first one's
+ * to 1e-6 relative (norm-wise per pair); keeps the fastest agreeing one in
+ * the plan (*chosen, *kernel_ms per launch) and, when cache_path is not NULL,
+ * writes it into that JSON file under the plan's key (GPU architecture,
+ * dimension, transform, similarity, spacing and size buckets of the batch),
+ * keeping the file's other entries. Synchronises the host; B-spline plans
+ * with the diffusion regulariser only (AIR_ERR_UNSUPPORTED otherwise).
+ * air_autotune_cached applies the cached configuration of the plan's key if
+ * the file has one (*tiling = its id, else -1). */
+air_status air_autotune_workspace_bytes(const air_plan* plan, size_t* bytes);
+air_status air_autotune(air_plan* plan, const float* const* fixed, const float* const* moving,
+                        const float* const* theta, float* values, float* const* grads, void* ws,
+                        size_t ws_bytes, int32_t reps, const char* cache_path, int32_t* chosen,
+                        double* kernel_ms, void* stream);
+air_status air_autotune_cached(air_plan* plan, const char* cache_path, int32_t* tiling);
+
 /* Adam (Sec. III-G; Kingma & Ba) with bias correction, in place:
  * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
  * theta -= lr * (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps). step >= 1. */
@@ -323,6 +345,37 @@ air_status air_cnn_output_bwd(const float* dtheta, const int32_t gdims[3], int32
                               float scale, float* dg, void* stream);
 /* a += b (FP32). */
 air_status air_add_f32(float* a, const float* b, int64_t n, void* stream);
+
+/* The whole network as one object (the layer schedule of an n^3 pair, n a
+ * multiple of 16 up to 1024), sequencing the kernels above:
+ *   x0 = avgpool2(F, M) (8 channels) at (n/2)^3; a1 = lrelu(conv 8->16);
+ *   a2 = lrelu(conv(pool a1) 16->32); a3 = lrelu(conv(pool a2) 32->48);
+ *   a4 = lrelu(conv(pool a3) 48->64) at (n/16)^3; d1 = lrelu(conv([a3 |
+ *   up2(a4)] 112->48)); o = conv(d1) 48->16 (FP32) at (n/8)^3;
+ *   theta0[c][j] = 0.05 o[clamp(j - 1, 0, g - 1)][c], g = n/8, as
+ *   [3][g+3][g+3][g+3] (a spacing-8 control grid).
+ * Parameters are one caller-owned FP32 buffer of param_floats floats: per
+ * layer l (0..5 in the order above) W [cout][27 cin] at w_offset and
+ * b [cout] at b_offset (air_cnn_layer). The workspace (ws_bytes, 16-byte
+ * aligned, caller-owned) holds the BF16 weight copies, the activations and
+ * the gradient buffers. */
+typedef struct air_cnn air_cnn;
+air_status air_cnn_create(int32_t n, air_cnn** out);
+void air_cnn_destroy(air_cnn* net);
+air_status air_cnn_sizes(const air_cnn* net, int64_t* param_floats, size_t* ws_bytes);
+air_status air_cnn_layer(const air_cnn* net, int32_t layer, int32_t* cin, int32_t* cout,
+                         int64_t* w_offset, int64_t* b_offset);
+/* theta0 = net(fixed, moving) for FP32 volumes [n][n][n]; refreshes the BF16
+ * weight copies from params and keeps the activations in ws for
+ * air_cnn_backward. */
+air_status air_cnn_forward(const air_cnn* net, const float* params, const float* fixed,
+                           const float* moving, float* theta0, void* ws, size_t ws_bytes,
+                           void* stream);
+/* grads (the parameter layout) = dL/dparams for dtheta = dL/dtheta0, after
+ * air_cnn_forward with the same workspace. BF16 operands, FP32 accumulation
+ * (weight gradients summed per voxel chunk in a fixed order). */
+air_status air_cnn_backward(const air_cnn* net, const float* dtheta, float* grads, void* ws,
+                            size_t ws_bytes, void* stream);
 
 /* ---- Synthetic inputs (not part of the paper's method). ----
  * Blob volumes of the 3D workloads painted on the device from parameters

@@ -60,6 +60,17 @@ SIGNATURES = {
     "air_objective_and_grad_batched": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "air_objective_and_grad_noalloc": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "air_synth_blobs": (_i32, [_vp, _i32, ctypes.POINTER(_i32), _vp, _vp]),
+    "air_autotune_workspace_bytes": (_i32, [_vp, ctypes.POINTER(_sz)]),
+    "air_autotune": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32, ctypes.c_char_p,
+                            ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double), _vp]),
+    "air_autotune_cached": (_i32, [_vp, ctypes.c_char_p, ctypes.POINTER(_i32)]),
+    "air_cnn_create": (_i32, [_i32, ctypes.POINTER(_vp)]),
+    "air_cnn_destroy": (None, [_vp]),
+    "air_cnn_sizes": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_sz)]),
+    "air_cnn_layer": (_i32, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                             ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "air_cnn_forward": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "air_cnn_backward": (_i32, [_vp, _vp, _vp, _vp, _sz, _vp]),
     "air_synth_add_normal": (_i32, [_vp, _i64, ctypes.c_uint64, _f32, _vp]),
     "air_adam_step": (_i32, [_vp, _vp, _vp, _vp, _i64, _f32, _f32, _f32, _f32, _i32, _vp]),
     "air_adam_bias_terms": (_i32, [_f32, _f32, _f32, _i32, _vp]),

@@ -3,9 +3,13 @@
 #include <math.h>
 #include <string.h>
 
+#include <stdio.h>
+
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "air_internal.h"
@@ -798,6 +802,79 @@ static void release_events(air_plan* P) {
     P->ev_next = 0;
 }
 
+// ------------------------------------------------------------------ autotune cache
+// The cache is a JSON object {key: {"kernel_ms": t, "shape": [tx, ty, cells],
+// "tiling": id}, ...}, keys sorted. The key names the GPU architecture, the
+// plan's dimension, transform, similarity and spacing, and size buckets of
+// the batch: "gfx950|d3|tf0|sim1|sp8|v<bits of voxels per pair>|p<bits of pairs>".
+static std::string tune_key(const air_plan* P) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t c = arch.find(':');
+        if (c != std::string::npos) arch = arch.substr(0, c);
+    }
+    long long vox = 0;
+    for (const air_problem& q : P->probs) vox += (long long)q.n[0] * q.n[1] * (q.dim == 3 ? q.n[2] : 1);
+    auto bits = [](long long v) {
+        int b = 0;
+        while (v > 0) {
+            ++b;
+            v >>= 1;
+        }
+        return b;
+    };
+    const long long per = std::max(vox / P->npairs, 1LL);
+    const int sp = P->transform == AIR_TF_BSPLINE3 ? P->probs[0].spacing[0] : 0;
+    char buf[160];
+    snprintf(buf, sizeof(buf), "%s|d%d|tf%d|sim%d|sp%d|v%d|p%d", arch.c_str(), P->dim,
+             P->transform, P->sim, sp, bits(per), bits(P->npairs));
+    return buf;
+}
+
+// Entries of a cache file: key -> the entry's JSON object text. Only the
+// layout this library writes is understood (a flat object of objects).
+static std::map<std::string, std::string> read_tune_cache(const char* path) {
+    std::map<std::string, std::string> out;
+    FILE* f = fopen(path, "rb");
+    if (!f) return out;
+    std::string t;
+    char buf[4096];
+    size_t k;
+    while ((k = fread(buf, 1, sizeof(buf), f)) > 0) t.append(buf, k);
+    fclose(f);
+    size_t i = t.find('{');
+    if (i == std::string::npos) return out;
+    ++i;
+    while (true) {
+        const size_t q0 = t.find('"', i);
+        if (q0 == std::string::npos) break;
+        const size_t q1 = t.find('"', q0 + 1);
+        const size_t b0 = t.find('{', q1);
+        if (q1 == std::string::npos || b0 == std::string::npos) break;
+        int depth = 0;
+        size_t j = b0;
+        for (; j < t.size(); ++j) {
+            if (t[j] == '{') ++depth;
+            if (t[j] == '}' && --depth == 0) break;
+        }
+        if (j >= t.size()) break;
+        out[t.substr(q0 + 1, q1 - q0 - 1)] = t.substr(b0, j - b0 + 1);
+        i = j + 1;
+    }
+    return out;
+}
+
+static int entry_tiling(const std::string& obj) {
+    const size_t p = obj.find("\"tiling\"");
+    if (p == std::string::npos) return -1;
+    const size_t c = obj.find(':', p);
+    return c == std::string::npos ? -1 : atoi(obj.c_str() + c + 1);
+}
+
 extern "C" {
 
 air_status air_plan_create(const air_problem* probs, int32_t npairs, air_plan** out) {
@@ -1204,6 +1281,158 @@ const char* air_strerror(air_status s) {
         case AIR_ERR_DEVICE: return "device query, allocation or copy failed";
     }
     return "unknown status";
+}
+
+
+air_status air_autotune_workspace_bytes(const air_plan* cplan, size_t* bytes) {
+    if (!cplan || !bytes) return AIR_ERR_INVALID_ARG;
+    air_plan* plan = const_cast<air_plan*>(cplan);
+    std::lock_guard<std::mutex> g(plan->mu);
+    const int old = plan->tiling;
+    size_t best = plan->L.total;
+    for (int t = 0; t < air_tiling_count(plan->dim); ++t) {
+        plan->tiling = t;
+        if (build_tables(plan) == AIR_OK) best = std::max(best, plan->L.total);
+    }
+    plan->tiling = old;
+    build_tables(plan);
+    *bytes = best;
+    return AIR_OK;
+}
+
+air_status air_autotune_cached(air_plan* plan, const char* cache_path, int32_t* tiling) {
+    if (!plan || !cache_path || !tiling) return AIR_ERR_INVALID_ARG;
+    *tiling = -1;
+    const std::map<std::string, std::string> c = read_tune_cache(cache_path);
+    const auto it = c.find(tune_key(plan));
+    if (it == c.end()) return AIR_OK;
+    const int t = entry_tiling(it->second);
+    if (t < 0 || t >= air_tiling_count(plan->dim)) return AIR_OK;
+    const air_status st = air_plan_set_tiling(plan, t);
+    if (st == AIR_OK) *tiling = t;
+    return st;
+}
+
+air_status air_autotune(air_plan* plan, const float* const* fixed, const float* const* moving,
+                        const float* const* theta, float* values, float* const* grads, void* ws,
+                        size_t ws_bytes, int32_t reps, const char* cache_path, int32_t* chosen,
+                        double* kernel_ms, void* stream) {
+    if (!plan || !fixed || !moving || !theta || !values || !grads || !chosen) return AIR_ERR_INVALID_ARG;
+    if (reps < 1 || reps > 10000) return AIR_ERR_INVALID_ARG;
+    if (plan->field_route() || plan->reg != AIR_REG_DIFFUSION || plan->transform != AIR_TF_BSPLINE3)
+        return AIR_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    const int np = plan->npairs;
+    // host copies of the gradient pointer table and room for every result
+    std::vector<float*> gptr(np);
+    if (hipMemcpy(gptr.data(), grads, sizeof(float*) * np, hipMemcpyDeviceToHost) != hipSuccess)
+        return AIR_ERR_DEVICE;
+    std::vector<long long> nparam(np);
+    long long ntot = 0;
+    for (int i = 0; i < np; ++i) {
+        nparam[i] = plan->pd[i].nparam;
+        ntot += nparam[i];
+    }
+    std::vector<float> v_ref(np), v_cur(np), g_ref(ntot), g_cur(ntot);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return AIR_ERR_DEVICE;
+    const int old = plan->tiling;
+    int best = -1, first = -1;
+    double best_ms = 0.0;
+    air_status st = AIR_OK;
+    for (int t = 0; t < air_tiling_count(plan->dim) && st == AIR_OK; ++t) {
+        if (air_plan_set_tiling(plan, t) != AIR_OK) continue;   // not valid for these sizes
+        if (ws_bytes < plan->L.total) {
+            st = AIR_ERR_WORKSPACE;
+            break;
+        }
+        // one call (tables upload) and two warm-up launches, then `reps` timed
+        for (int w = 0; w < 3 && st == AIR_OK; ++w)
+            st = air_objective_and_grad_batched(plan, fixed, moving, theta, values, grads, ws,
+                                                ws_bytes, stream);
+        if (st != AIR_OK) break;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps && st == AIR_OK; ++r)
+            st = air_objective_and_grad_batched(plan, fixed, moving, theta, values, grads, ws,
+                                                ws_bytes, stream);
+        (void)hipEventRecord(e1, s);
+        if (st != AIR_OK || hipEventSynchronize(e1) != hipSuccess) {
+            st = st == AIR_OK ? AIR_ERR_DEVICE : st;
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double per = (double)ms / reps;
+        // results of this configuration: the tile shape only changes the
+        // summation order, so they must agree with the first one to 1e-6
+        bool ok = hipMemcpy(v_cur.data(), values, sizeof(float) * np, hipMemcpyDeviceToHost) ==
+                  hipSuccess;
+        long long o = 0;
+        for (int i = 0; i < np && ok; ++i) {
+            ok = hipMemcpy(g_cur.data() + o, gptr[i], sizeof(float) * nparam[i],
+                           hipMemcpyDeviceToHost) == hipSuccess;
+            o += nparam[i];
+        }
+        if (!ok) {
+            st = AIR_ERR_DEVICE;
+            break;
+        }
+        bool agree = true;
+        if (first < 0) {
+            first = t;
+            v_ref = v_cur;
+            g_ref = g_cur;
+        } else {
+            o = 0;
+            for (int i = 0; i < np && agree; ++i) {
+                const double dv = fabs((double)v_cur[i] - v_ref[i]) / std::max(fabs((double)v_ref[i]), 1e-30);
+                double dn = 0.0, nn = 0.0;
+                for (long long k = 0; k < nparam[i]; ++k) {
+                    const double d = (double)g_cur[o + k] - g_ref[o + k];
+                    dn += d * d;
+                    nn += (double)g_ref[o + k] * g_ref[o + k];
+                }
+                o += nparam[i];
+                agree = dv <= 1e-6 && sqrt(dn) <= 1e-6 * std::max(sqrt(nn), 1e-30);
+            }
+        }
+        if (agree && (best < 0 || per < best_ms)) {
+            best = t;
+            best_ms = per;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != AIR_OK || best < 0) {
+        air_plan_set_tiling(plan, old);
+        return st != AIR_OK ? st : AIR_ERR_UNSUPPORTED;
+    }
+    st = air_plan_set_tiling(plan, best);
+    if (st != AIR_OK) return st;
+    *chosen = best;
+    if (kernel_ms) *kernel_ms = best_ms;
+    if (cache_path) {
+        std::map<std::string, std::string> c = read_tune_cache(cache_path);
+        int tx = 0, ty = 0, cells = 0;
+        (void)air_tiling_describe(plan->dim, best, &tx, &ty, &cells);
+        char obj[256];
+        snprintf(obj, sizeof(obj),
+                 "{\n  \"kernel_ms\": %.10g,\n  \"shape\": [\n   %d,\n   %d,\n   %d\n  ],\n  "
+                 "\"tiling\": %d\n }",
+                 best_ms, tx, ty, cells, best);
+        c[tune_key(plan)] = obj;
+        FILE* f = fopen(cache_path, "wb");
+        if (!f) return AIR_ERR_INVALID_ARG;
+        fputs("{\n", f);
+        size_t k = 0;
+        for (const auto& kv : c) {
+            fprintf(f, " \"%s\": %s%s\n", kv.first.c_str(), kv.second.c_str(),
+                    ++k < c.size() ? "," : "");
+        }
+        fputs("}", f);
+        fclose(f);
+    }
+    return AIR_OK;
 }
 
 }  // extern "C"

@@ -123,6 +123,21 @@ int main(void) {
         EXPECT(air_pyramid_workspace_bytes(n3, &pb) == AIR_OK);
         for (int st = 0; st <= 8; ++st) EXPECT(air_strerror((air_status)st) != NULL);
     }
+    /* the network object: layout queries only (no pass runs) */
+    {
+        air_cnn* net = NULL;
+        EXPECT(air_cnn_create(40, &net) == AIR_ERR_SHAPE && net == NULL);
+        EXPECT(air_cnn_create(64, &net) == AIR_OK && net != NULL);
+        int64_t np = 0, wo = 0, bo = 0;
+        size_t wsb = 0;
+        int32_t ci = 0, co = 0;
+        EXPECT(air_cnn_sizes(net, &np, &wsb) == AIR_OK && np > 0 && wsb > 0);
+        for (int l = 0; l < 6; ++l)
+            EXPECT(air_cnn_layer(net, l, &ci, &co, &wo, &bo) == AIR_OK && wo < np && bo < np);
+        EXPECT(air_cnn_layer(net, 6, &ci, &co, &wo, &bo) == AIR_ERR_SHAPE);
+        EXPECT(air_cnn_forward(net, NULL, NULL, NULL, NULL, NULL, 0, NULL) == AIR_ERR_INVALID_ARG);
+        air_cnn_destroy(net);
+    }
     printf("C-ABI host sanitizer driver: %d failures\n", g_bad);
     return g_bad ? 1 : 0;
 }

@@ -229,3 +229,31 @@ def test_adam_bias_terms_match_the_definition():
     with pytest.raises(RuntimeError):
         api.adam_bias_terms(0, 1)
 
+
+
+def test_cnn_object_layout():
+    """The network object is host-only until its passes run: layer table,
+    parameter offsets (16-byte aligned, non-overlapping) and workspace size."""
+    import ctypes as C
+    L = _lib.lib()
+    h = C.c_void_p()
+    assert L.air_cnn_create(40, C.byref(h)) == 2          # not a multiple of 16
+    assert L.air_cnn_create(128, C.byref(h)) == 0
+    npar, wsb = C.c_int64(), C.c_size_t()
+    assert L.air_cnn_sizes(h, C.byref(npar), C.byref(wsb)) == 0
+    expect = [(8, 16), (16, 32), (32, 48), (48, 64), (112, 48), (48, 16)]
+    end = 0
+    for i, (cin, cout) in enumerate(expect):
+        ci, co, wo, bo = C.c_int32(), C.c_int32(), C.c_int64(), C.c_int64()
+        assert L.air_cnn_layer(h, i, C.byref(ci), C.byref(co), C.byref(wo), C.byref(bo)) == 0
+        assert (ci.value, co.value) == (cin, cout)
+        assert wo.value % 4 == 0 and wo.value >= end
+        assert bo.value == wo.value + 27 * cin * cout
+        end = bo.value + cout
+    assert npar.value >= end and npar.value - end < 4
+    assert L.air_cnn_layer(h, 6, None, None, None, None) == 2
+    assert wsb.value > 0
+    # passes need a workspace
+    assert L.air_cnn_forward(h, C.c_void_p(256), C.c_void_p(256), C.c_void_p(256),
+                             C.c_void_p(256), None, 0, None) == 4
+    L.air_cnn_destroy(h)

@@ -453,6 +453,45 @@ def test_batch64_128_launch_sampled_oracle():
         check_grad(grads[i], go, f"batch64 pair {i}")
 
 
+def test_autotune_writes_and_applies_its_cache(tmp_path):
+    """air_autotune on a small batch: the chosen configuration is one of the
+    plan's, the JSON cache gets the plan's key (other entries kept), a fresh
+    plan of the same batch shape picks it up through air_autotune_cached, and
+    the tuned plan still matches the oracle."""
+    import json
+
+    from paper_1806_09907_amd import tune
+    sizes = [(48, 40, 56)] * 6
+    probs = [api.Problem(n=n, spacing=(8, 8, 8), similarity=api.SIM_NCC, lambda_diff=0.05)
+             for n in sizes]
+    Fs, Ms, Ts = [], [], []
+    for i, p in enumerate(probs):
+        F, M = blob_inputs(p.n, 8, 400 + i)
+        Fs.append(F); Ms.append(M); Ts.append(theta_for(p, "rand", 500 + i))
+    cache = tmp_path / "cache.json"
+    cache.write_text(json.dumps({"other|key": {"kernel_ms": 1.0, "shape": [1, 2, 3],
+                                               "tiling": 0}}))
+    plan = api.Plan(probs)
+    rep = tune.autotune(plan, [gpu(a) for a in Fs], [gpu(a) for a in Ms], [gpu(a) for a in Ts],
+                        reps=3, cache_path=str(cache))
+    print("autotune", rep, flush=True)
+    assert 0 <= rep["tiling"] < api.tiling_count(3) and rep["kernel_ms"] > 0
+    assert plan.tiling == rep["tiling"]
+    data = json.loads(cache.read_text())
+    assert "other|key" in data and len(data) == 2
+    (key, entry), = [(k, v) for k, v in data.items() if k != "other|key"]
+    assert key.startswith("gfx950|d3|tf0|sim1|sp8|") and entry["tiling"] == rep["tiling"]
+    fresh = api.Plan(probs)
+    assert tune.cached_tiling(fresh, str(cache)) == rep["tiling"] and fresh.tiling == rep["tiling"]
+    vals, grads, _ = api.objective_and_grad_batched(
+        fresh, [gpu(a) for a in Fs], [gpu(a) for a in Ms], [gpu(a) for a in Ts])
+    torch.cuda.synchronize()
+    for i in (0, 5):
+        vo, go, _ = O.objective_and_grad(oprob(probs[i]), Fs[i], Ms[i], Ts[i])
+        assert abs(float(vals[i]) - vo) <= VAL_TOL * abs(vo)
+        check_grad(grads[i], go, f"autotuned pair {i}")
+
+
 # ------------------------------------------------------------------ edge cases
 
 def test_identical_images():
