@@ -113,6 +113,8 @@ def parse():
                     choices=["batch128", "uneven48", "dense256", "latency2d", "diffeo256",
                              "diffeo2d", "tv128", "wendland128", "lcc128", "cnn128"])
     ap.add_argument("--pairs", type=int, default=64)
+    ap.add_argument("--cnn-batch", type=int, default=8,
+                    help="pairs per network pass for the cnn128 workload")
     ap.add_argument("--tiling", type=int, default=-1, help="-1: autotune cache or default")
     ap.add_argument("--autotune-out", default="",
                     help="time every tile configuration on this batch, write the cache here")
@@ -756,19 +758,30 @@ def cnn_flops(n=128):
     return fwd, 2 * fwd - e1
 
 
-def cnn_throughput(net, dev, reps=20):
+def cnn_pairs(n, batch, dev):
+    """`batch` held-out blob pairs as [batch][n]^3 tensors (or [n]^3 for one)."""
     import torch
 
     from paper_1806_09907_amd import synth
     from paper_1806_09907_amd.learned import PairGenerator
 
-    F, M, _ = PairGenerator(net.n, dev).pair(synth.heldout_seed(0))
+    gen = PairGenerator(n, dev)
+    Fs, Ms = zip(*[gen.pair(synth.heldout_seed(b))[:2] for b in range(batch)])
+    if batch == 1:
+        return Fs[0], Ms[0]
+    return torch.stack(Fs).contiguous(), torch.stack(Ms).contiguous()
+
+
+def cnn_time(net, F, M, warmup, reps):
+    """Mean seconds of one forward pass and of one forward + backward pass,
+    HIP events around `reps` back-to-back passes on the current stream."""
+    import torch
+
     dth = torch.full_like(net.forward(F, M), 1e-3)
-    fwd_fl, bwd_fl = cnn_flops(net.n)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    for _ in range(3):
+    for _ in range(warmup):
         net.forward(F, M)
         net.backward(dth)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     torch.cuda.synchronize()
     ev[0].record()
     for _ in range(reps):
@@ -779,60 +792,63 @@ def cnn_throughput(net, dev, reps=20):
         net.backward(dth)
     ev[2].record()
     torch.cuda.synchronize()
-    t_f = ev[0].elapsed_time(ev[1]) / reps / 1e3
-    t_fb = ev[1].elapsed_time(ev[2]) / reps / 1e3
+    return ev[0].elapsed_time(ev[1]) / reps / 1e3, ev[1].elapsed_time(ev[2]) / reps / 1e3
+
+
+def cnn_throughput(net, dev, reps=20, batch=8):
+    """Training-pass throughput of the trained network: one pair per pass
+    (as trained) and `batch` pairs per pass (the same weights)."""
+    from paper_1806_09907_amd.cnn import InitNet
+
+    fwd_fl, bwd_fl = cnn_flops(net.n)
+    F, M = cnn_pairs(net.n, 1, dev)
+    t_f, t_fb = cnn_time(net, F, M, 3, reps)
+    netb = InitNet(n=net.n, device=dev, seed=0, batch=batch)
+    netb.flat.copy_(net.flat)
+    Fb, Mb = cnn_pairs(net.n, batch, dev)
+    tb_f, tb_fb = cnn_time(netb, Fb, Mb, 3, reps)
+    del netb
+    fb = (fwd_fl + bwd_fl) / tb_fb / 1e12
     return {"forward_ms": t_f * 1e3, "forward_backward_ms": t_fb * 1e3,
             "forward_gflop": fwd_fl / 1e9, "backward_gflop": bwd_fl / 1e9,
             "forward_tflops": fwd_fl / t_f / 1e12,
-            "forward_backward_tflops": (fwd_fl + bwd_fl) / t_fb / 1e12,
+            "forward_backward_tflops_1pair": (fwd_fl + bwd_fl) / t_fb / 1e12,
+            "frac_forward_backward_1pair": (fwd_fl + bwd_fl) / t_fb / 1e12 / 2500.0,
+            "batch": batch,
+            "forward_backward_ms_batch": tb_fb * 1e3,
+            "forward_ms_batch": tb_f * 1e3,
+            "forward_backward_tflops": batch * fb,
             "peak_tflops_bf16": 2500.0,
-            "frac_forward_backward": (fwd_fl + bwd_fl) / t_fb / 1e12 / 2500.0,
-            "note": "includes the pooling, upsampling, activation and cast kernels between "
-                    "the convolutions"}
+            "frac_forward_backward": batch * fb / 2500.0,
+            "note": "flops per pair x pairs per pass / pass time; the passes include the "
+                    "pooling, upsampling and activation kernels between the convolutions; "
+                    "frac_forward_backward is at `batch` pairs per pass, "
+                    "frac_forward_backward_1pair at one"}
 
 
 def run_cnn128(args, dev):
-    """Training steps of the initialisation network (forward + backward of
-    one 128^3 pair, BF16 MFMA convolutions) and inference passes."""
-    import torch
-
-    from paper_1806_09907_amd import synth
+    """Training passes of the initialisation network (forward + backward of
+    a batch of 128^3 pairs, BF16 MFMA convolutions) and inference passes."""
     from paper_1806_09907_amd.cnn import InitNet
-    from paper_1806_09907_amd.learned import PairGenerator
 
-    net = InitNet(n=128, device=dev, seed=0)
-    F, M, _ = PairGenerator(128, dev).pair(synth.heldout_seed(0))
-    dth = torch.full_like(net.forward(F, M), 1e-3)
+    B = args.cnn_batch
+    net = InitNet(n=128, device=dev, seed=0, batch=B)
+    F, M = cnn_pairs(128, B, dev)
     fwd_fl, bwd_fl = cnn_flops(128)
-    for _ in range(args.warmup):
-        net.forward(F, M)
-        net.backward(dth)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    torch.cuda.synchronize()
-    ev[0].record()
-    for _ in range(args.steps):
-        net.forward(F, M)
-    ev[1].record()
-    for _ in range(args.steps):
-        net.forward(F, M)
-        net.backward(dth)
-    ev[2].record()
-    torch.cuda.synchronize()
-    t_f = ev[0].elapsed_time(ev[1]) / args.steps
-    t_fb = ev[1].elapsed_time(ev[2]) / args.steps
-    ach = (fwd_fl + bwd_fl) / (t_fb / 1e3) / 1e12
+    t_f, t_fb = cnn_time(net, F, M, args.warmup, args.steps)
+    ach = B * (fwd_fl + bwd_fl) / t_fb / 1e12
     return {
-        "metric": "learned-initialisation network training steps/s (forward + backward, 128^3)",
-        "value": 1e3 / t_fb, "unit": "steps/s", "ms_per_step": t_fb,
-        "config": {"workload": "3D encoder-decoder (16/32/48/64 channels) on one 128^3 pair, "
-                               "BF16 weights and activations, FP32 accumulation",
-                   "forward_ms": t_f, "forward_gflop": fwd_fl / 1e9,
-                   "backward_gflop": bwd_fl / 1e9,
-                   "forward_tflops": fwd_fl / (t_f / 1e3) / 1e12},
+        "metric": "learned-initialisation network training pairs/s (forward + backward, 128^3)",
+        "value": B / t_fb, "unit": "pairs/s", "ms_per_step": t_fb * 1e3,
+        "config": {"workload": f"3D encoder-decoder (16/32/48/64 channels), {B} 128^3 pairs per "
+                               f"pass, BF16 weights and activations, FP32 accumulation",
+                   "batch": B, "forward_ms": t_f * 1e3, "forward_gflop_per_pair": fwd_fl / 1e9,
+                   "backward_gflop_per_pair": bwd_fl / 1e9,
+                   "forward_tflops": B * fwd_fl / t_f / 1e12},
         "roofline": {"bound": "mfma", "achieved": ach, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": ach / 2500.0, "traffic": None,
-                     "kernel": "whole training step (convolutions and the kernels between)",
-                     "kernel_ms": t_fb},
+                     "kernel": "whole training pass (convolutions and the kernels between)",
+                     "kernel_ms": t_fb * 1e3},
     }
 
 

@@ -289,29 +289,42 @@ air_status air_field_resample(const float* in, const int32_t n[3], const int32_t
  * Activations are NDHWC bf16 (uint16_t storage) [z][y][x][C], C a multiple
  * of 8; weights are Wt[co][k], k = tap * C_in + ci, tap = (dz*3+dy)*3+dx.
  *
+ * A batch of volumes is a stack along z: dims = (nx, ny, nz) of one volume,
+ * the tensor holds batch * nz planes, and the 3x3x3 convolutions pad each
+ * volume with zeros on its own (no tap reaches into a neighbour). The
+ * pooling, upsampling and elementwise calls below are independent per
+ * volume when nz is even, so they take the whole stack as one volume of
+ * depth batch * nz.
+ *
  * 3x3x3 convolution, stride 1, zero padding 1, on BF16 MFMA (16x16x32)
- * with FP32 accumulation: y = act(conv(x) + bias). act: 0 none, 1 LeakyReLU
- * 0.1. Outputs (either may be NULL): bf16 y_bf16[v * ldy + yoff + co] and
- * FP32 y_f32[v * ldyf + co]. bias nullable. dims = (nx, ny, nz). */
-air_status air_conv3d_fwd(const uint16_t* x, const int32_t dims[3], int32_t cin,
+ * with FP32 accumulation: v = conv(x) + bias, then act 0: y = v; act 1:
+ * y = LeakyReLU_0.1(v); act 2: y = v * LeakyReLU_0.1'(a) with a the stored
+ * bf16 activation gate[v * ldg + goff + co] (for backward-data through an
+ * activation; gate unused otherwise). Outputs (either may be NULL): bf16
+ * y_bf16[v * ldy + yoff + co] and FP32 y_f32[v * ldyf + co]. bias nullable.
+ * x and wt 16-byte aligned (AIR_ERR_ALIGN), cin a multiple of 8, cout <= 128
+ * (AIR_ERR_SHAPE). */
+air_status air_conv3d_fwd(const uint16_t* x, const int32_t dims[3], int32_t batch, int32_t cin,
                           const uint16_t* wt, const float* bias, int32_t cout, int32_t act,
-                          uint16_t* y_bf16, int32_t ldy, int32_t yoff, float* y_f32,
-                          int32_t ldyf, void* stream);
+                          const uint16_t* gate, int32_t ldg, int32_t goff, uint16_t* y_bf16,
+                          int32_t ldy, int32_t yoff, float* y_f32, int32_t ldyf, void* stream);
 /* Backward-data of the convolution = air_conv3d_fwd on the gradient with
  * these weights: wf[ci][tap' * C_out + co] = bf16(wt[co][(26 - tap') C_in + ci]). */
 air_status air_conv3d_flip_weights(const float* wt, int32_t cin, int32_t cout, uint16_t* wf,
                                    void* stream);
 /* Backward-weight: dwt[co][k] = sum_v dy[v][co] x[v + off(tap)][ci] (FP32),
- * db[co] = sum_v dy[v][co] (nullable). x is bf16 [v][cin], dy bf16 [v][cout],
- * both 16-byte aligned; cin and cout multiples of 8, cout <= 128 (else
- * AIR_ERR_SHAPE / AIR_ERR_ALIGN). Voxels are reduced in chunks of `chunk`
- * (multiple of 32) into workspace partials (cout * (27 cin + 1) floats per
- * chunk) summed in a fixed order. */
-air_status air_conv3d_bwd_weight_workspace(const int32_t dims[3], int32_t cin, int32_t cout,
-                                           int32_t chunk, size_t* bytes);
-air_status air_conv3d_bwd_weight(const uint16_t* x, const int32_t dims[3], int32_t cin,
-                                 const uint16_t* dy, int32_t cout, int32_t chunk, float* dwt,
-                                 float* db, void* ws, size_t ws_bytes, void* stream);
+ * db[co] = sum_v dy[v][co] (nullable), summed over every volume of the
+ * batch. x is bf16 [v][cin], dy bf16 [v][cout], both 16-byte aligned; cin
+ * and cout multiples of 8, cout <= 128 (else AIR_ERR_SHAPE / AIR_ERR_ALIGN).
+ * Voxels are reduced in chunks of `chunk` (a multiple of 128; 0 = the
+ * library's choice, about one resident round of blocks) into workspace
+ * partials (cout * (27 cin + 1) floats per chunk, at most 65535 chunks)
+ * summed in a fixed order, so results repeat bit for bit. */
+air_status air_conv3d_bwd_weight_workspace(const int32_t dims[3], int32_t batch, int32_t cin,
+                                           int32_t cout, int32_t chunk, size_t* bytes);
+air_status air_conv3d_bwd_weight(const uint16_t* x, const int32_t dims[3], int32_t batch,
+                                 int32_t cin, const uint16_t* dy, int32_t cout, int32_t chunk,
+                                 float* dwt, float* db, void* ws, size_t ws_bytes, void* stream);
 /* y = bf16(x), round to nearest even. */
 air_status air_cast_bf16(const float* x, uint16_t* y, int64_t n, void* stream);
 /* 2x average pooling (even dims) of the channel slice x[v * ldx + xoff + c]
@@ -332,22 +345,40 @@ air_status air_up2_bwd(const float* dy, const int32_t dims[3], int32_t c, int32_
 air_status air_lrelu_bwd(const float* dy, int32_t ld, int32_t off, const uint16_t* yact,
                          int32_t ldyact, int32_t yoff, int64_t nvox, int32_t c, uint16_t* dx,
                          void* stream);
+/* Fused adjoints of pool-then-activation and upsample-then-activation
+ * (dims = the fine size for pool, the coarse size for up; gate = the stored
+ * bf16 activation of the fine / coarse tensor):
+ *   pool:  dx[v][c] = bf16(lrelu'(gate[v]) (add[v * ldadd + addoff + c] +
+ *          dy[v/2][c] / 8)), dy FP32 [v/2][c] contiguous, add nullable;
+ *   up:    dx[u][c] = bf16(lrelu'(gate[u]) sum of the 8 children
+ *          dy[v * ldy + yoff + c]), dy FP32 at the fine size. */
+air_status air_pool2_lrelu_bwd(const float* dy, const int32_t dims[3], int32_t c,
+                              const float* add, int32_t ldadd, int32_t addoff,
+                              const uint16_t* gate, int32_t ldg, int32_t goff, uint16_t* dx,
+                              void* stream);
+air_status air_up2_lrelu_bwd(const float* dy, const int32_t dims[3], int32_t c, int32_t ldy,
+                             int32_t yoff, const uint16_t* gate, int32_t ldg, int32_t goff,
+                             uint16_t* dx, void* stream);
 /* Network input: (fixed, moving) FP32 volumes (dims even) -> 2x averaged,
  * 8-channel bf16 tensor (fixed, moving, six zero channels). */
 air_status air_cnn_input(const float* fixed, const float* moving, const int32_t dims[3],
                          uint16_t* x, void* stream);
-/* Network output: FP32 features g [gz][gy][gx][ld] (one cell per control
- * cell; channels 0..2 used) -> control grid theta [3][gz+3][gy+3][gx+3]:
- * theta[c][j] = scale * g[clamp(j - 1, 0, g - 1)][c] per axis; and its adjoint. */
-air_status air_cnn_output(const float* g, const int32_t gdims[3], int32_t ld, float scale,
-                          float* theta, void* stream);
-air_status air_cnn_output_bwd(const float* dtheta, const int32_t gdims[3], int32_t ld,
-                              float scale, float* dg, void* stream);
+/* Network output, per volume b of the batch: FP32 features g
+ * [b][gz][gy][gx][ld] (one cell per control cell; channels 0..2 used) ->
+ * control grids theta [b][3][gz+3][gy+3][gx+3]: theta[c][j] = scale *
+ * g[clamp(j - 1, 0, g - 1)][c] per axis; and its adjoint into FP32 dg
+ * and/or bf16 dg_bf16 (either nullable, not both; channels 3.. are zero). */
+air_status air_cnn_output(const float* g, const int32_t gdims[3], int32_t batch, int32_t ld,
+                          float scale, float* theta, void* stream);
+air_status air_cnn_output_bwd(const float* dtheta, const int32_t gdims[3], int32_t batch,
+                              int32_t ld, float scale, float* dg, uint16_t* dg_bf16,
+                              void* stream);
 /* a += b (FP32). */
 air_status air_add_f32(float* a, const float* b, int64_t n, void* stream);
 
-/* The whole network as one object (the layer schedule of an n^3 pair, n a
- * multiple of 16 up to 1024), sequencing the kernels above:
+/* The whole network as one object (the layer schedule of `batch` n^3 pairs,
+ * n a multiple of 16 up to 1024, batch * n^3 < 2^31), sequencing the kernels
+ * above on the z-stack of the batch:
  *   x0 = avgpool2(F, M) (8 channels) at (n/2)^3; a1 = lrelu(conv 8->16);
  *   a2 = lrelu(conv(pool a1) 16->32); a3 = lrelu(conv(pool a2) 32->48);
  *   a4 = lrelu(conv(pool a3) 48->64) at (n/16)^3; d1 = lrelu(conv([a3 |
@@ -360,20 +391,22 @@ air_status air_add_f32(float* a, const float* b, int64_t n, void* stream);
  * aligned, caller-owned) holds the BF16 weight copies, the activations and
  * the gradient buffers. */
 typedef struct air_cnn air_cnn;
-air_status air_cnn_create(int32_t n, air_cnn** out);
+air_status air_cnn_create(int32_t n, int32_t batch, air_cnn** out);
 void air_cnn_destroy(air_cnn* net);
 air_status air_cnn_sizes(const air_cnn* net, int64_t* param_floats, size_t* ws_bytes);
 air_status air_cnn_layer(const air_cnn* net, int32_t layer, int32_t* cin, int32_t* cout,
                          int64_t* w_offset, int64_t* b_offset);
-/* theta0 = net(fixed, moving) for FP32 volumes [n][n][n]; refreshes the BF16
- * weight copies from params and keeps the activations in ws for
- * air_cnn_backward. */
+/* theta0[b] = net(fixed[b], moving[b]) for FP32 volumes fixed, moving
+ * [batch][n][n][n] (contiguous, 16-byte aligned) into theta0
+ * [batch][3][g+3][g+3][g+3]; refreshes the BF16 weight copies from params
+ * and keeps the activations in ws for air_cnn_backward. */
 air_status air_cnn_forward(const air_cnn* net, const float* params, const float* fixed,
                            const float* moving, float* theta0, void* ws, size_t ws_bytes,
                            void* stream);
-/* grads (the parameter layout) = dL/dparams for dtheta = dL/dtheta0, after
- * air_cnn_forward with the same workspace. BF16 operands, FP32 accumulation
- * (weight gradients summed per voxel chunk in a fixed order). */
+/* grads (the parameter layout) = dL/dparams for dtheta = dL/dtheta0
+ * [batch][3][g+3]^3, summed over the batch, after air_cnn_forward with the
+ * same workspace. BF16 operands, FP32 accumulation (weight gradients summed
+ * per voxel chunk in a fixed order). */
 air_status air_cnn_backward(const air_cnn* net, const float* dtheta, float* grads, void* ws,
                             size_t ws_bytes, void* stream);
 

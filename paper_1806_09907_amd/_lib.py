@@ -64,7 +64,7 @@ SIGNATURES = {
     "air_autotune": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32, ctypes.c_char_p,
                             ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double), _vp]),
     "air_autotune_cached": (_i32, [_vp, ctypes.c_char_p, ctypes.POINTER(_i32)]),
-    "air_cnn_create": (_i32, [_i32, ctypes.POINTER(_vp)]),
+    "air_cnn_create": (_i32, [_i32, _i32, ctypes.POINTER(_vp)]),
     "air_cnn_destroy": (None, [_vp]),
     "air_cnn_sizes": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_sz)]),
     "air_cnn_layer": (_i32, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
@@ -80,19 +80,23 @@ SIGNATURES = {
     "air_pyramid_workspace_bytes": (_i32, [_vp, ctypes.POINTER(_sz)]),
     "air_pyramid_down": (_i32, [_vp, _vp, _f32, _vp, _vp, _sz, _vp]),
     "air_field_resample": (_i32, [_vp, _vp, _vp, _vp, _vp]),
-    "air_conv3d_fwd": (_i32, [_vp, _vp, _i32, _vp, _vp, _i32, _i32, _vp, _i32, _i32, _vp, _i32, _vp]),
+    "air_conv3d_fwd": (_i32, [_vp, _vp, _i32, _i32, _vp, _vp, _i32, _i32, _vp, _i32, _i32, _vp,
+                              _i32, _i32, _vp, _i32, _vp]),
     "air_conv3d_flip_weights": (_i32, [_vp, _i32, _i32, _vp, _vp]),
-    "air_conv3d_bwd_weight_workspace": (_i32, [_vp, _i32, _i32, _i32, ctypes.POINTER(_sz)]),
-    "air_conv3d_bwd_weight": (_i32, [_vp, _vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "air_conv3d_bwd_weight_workspace": (_i32, [_vp, _i32, _i32, _i32, _i32, ctypes.POINTER(_sz)]),
+    "air_conv3d_bwd_weight": (_i32, [_vp, _vp, _i32, _i32, _vp, _i32, _i32, _vp, _vp, _vp, _sz,
+                                     _vp]),
     "air_cast_bf16": (_i32, [_vp, _vp, _i64, _vp]),
     "air_pool2": (_i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp]),
     "air_pool2_bwd": (_i32, [_vp, _vp, _i32, _vp, _i32, _i32, _i32, _vp]),
     "air_up2": (_i32, [_vp, _vp, _i32, _vp, _i32, _i32, _vp]),
     "air_up2_bwd": (_i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp]),
     "air_lrelu_bwd": (_i32, [_vp, _i32, _i32, _vp, _i32, _i32, _i64, _i32, _vp, _vp]),
+    "air_pool2_lrelu_bwd": (_i32, [_vp, _vp, _i32, _vp, _i32, _i32, _vp, _i32, _i32, _vp, _vp]),
+    "air_up2_lrelu_bwd": (_i32, [_vp, _vp, _i32, _i32, _i32, _vp, _i32, _i32, _vp, _vp]),
     "air_cnn_input": (_i32, [_vp, _vp, _vp, _vp, _vp]),
-    "air_cnn_output": (_i32, [_vp, _vp, _i32, _f32, _vp, _vp]),
-    "air_cnn_output_bwd": (_i32, [_vp, _vp, _i32, _f32, _vp, _vp]),
+    "air_cnn_output": (_i32, [_vp, _vp, _i32, _i32, _f32, _vp, _vp]),
+    "air_cnn_output_bwd": (_i32, [_vp, _vp, _i32, _i32, _f32, _vp, _vp, _vp]),
     "air_add_f32": (_i32, [_vp, _vp, _i64, _vp]),
     "air_plan_timing": (_i32, [_vp, _i32]),
     "air_plan_timing_read": (_i32, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)]),

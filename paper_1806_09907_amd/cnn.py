@@ -44,7 +44,6 @@ LAYERS = [  # name, cin, cout, activation
 ]
 CAT = 112
 OUT_SCALE = 0.05
-BWDW_CHUNK = 256
 
 
 def _i3(v):
@@ -60,10 +59,11 @@ def _s():
 
 
 def conv_fwd(x, dims, cin, wt_bf, bias, cout, act, y_bf=None, ldy=None, yoff=0, y_f32=None,
-             ldyf=None):
-    check(lib().air_conv3d_fwd(_p(x), _i3(dims), cin, _p(wt_bf), _p(bias), cout, act, _p(y_bf),
-                               ldy if ldy is not None else cout, yoff, _p(y_f32),
-                               ldyf if ldyf is not None else cout, _s()), "air_conv3d_fwd")
+             ldyf=None, batch=1, gate=None, ldg=0, goff=0):
+    check(lib().air_conv3d_fwd(_p(x), _i3(dims), int(batch), cin, _p(wt_bf), _p(bias), cout, act,
+                               _p(gate), ldg, goff, _p(y_bf), ldy if ldy is not None else cout,
+                               yoff, _p(y_f32), ldyf if ldyf is not None else cout, _s()),
+          "air_conv3d_fwd")
 
 
 class Workspace:
@@ -79,13 +79,15 @@ class Workspace:
         return self.buf
 
 
-def conv_bwd_weight(x, dims, cin, dy_bf, cout, dwt, db, ws: Workspace):
+def conv_bwd_weight(x, dims, cin, dy_bf, cout, dwt, db, ws: Workspace, batch=1, chunk=0):
+    """chunk = voxels per partial (a multiple of 128), 0 for the library's choice."""
     need = ctypes.c_size_t()
-    check(lib().air_conv3d_bwd_weight_workspace(_i3(dims), cin, cout, BWDW_CHUNK,
+    check(lib().air_conv3d_bwd_weight_workspace(_i3(dims), int(batch), cin, cout, int(chunk),
                                                 ctypes.byref(need)), "bwd_weight_workspace")
     buf = ws.get(int(need.value))
-    check(lib().air_conv3d_bwd_weight(_p(x), _i3(dims), cin, _p(dy_bf), cout, BWDW_CHUNK, _p(dwt),
-                                      _p(db), _p(buf), buf.numel(), _s()), "air_conv3d_bwd_weight")
+    check(lib().air_conv3d_bwd_weight(_p(x), _i3(dims), int(batch), cin, _p(dy_bf), cout,
+                                      int(chunk), _p(dwt), _p(db), _p(buf), buf.numel(), _s()),
+          "air_conv3d_bwd_weight")
 
 
 @dataclass
@@ -103,13 +105,14 @@ class InitNet:
     moments are flat FP32 device buffers in the library's layout; the forward
     and backward passes are one call each."""
 
-    def __init__(self, n: int = 128, device="cuda", seed: int = 0):
-        assert n % 16 == 0
+    def __init__(self, n: int = 128, device="cuda", seed: int = 0, batch: int = 1):
+        assert n % 16 == 0 and batch >= 1
         self.n = n
+        self.batch = batch
         self.dev = torch.device(device)
         self.g = n // 8
         h = ctypes.c_void_p()
-        check(lib().air_cnn_create(int(n), ctypes.byref(h)), "air_cnn_create")
+        check(lib().air_cnn_create(int(n), int(batch), ctypes.byref(h)), "air_cnn_create")
         self._h = h
         npar, wsb = ctypes.c_int64(), ctypes.c_size_t()
         check(lib().air_cnn_sizes(h, ctypes.byref(npar), ctypes.byref(wsb)), "air_cnn_sizes")
@@ -140,8 +143,9 @@ class InitNet:
         self.m = torch.zeros_like(self.flat)
         self.v = torch.zeros_like(self.flat)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=d)
-        self.theta = torch.empty((3, self.g + 3, self.g + 3, self.g + 3), dtype=torch.float32,
-                                 device=d)
+        c = self.g + 3
+        self.theta = torch.empty((batch, 3, c, c, c) if batch > 1 else (3, c, c, c),
+                                 dtype=torch.float32, device=d)
         self.params: Dict[str, Param] = {}
         for name, (cin, cout, wo, bo) in self.layout.items():
             self.params[name] = Param(w=self.flat[wo:wo + cout * 27 * cin].view(cout, 27 * cin),
@@ -160,13 +164,22 @@ class InitNet:
             self._h = None
 
     def forward(self, fixed: torch.Tensor, moving: torch.Tensor) -> torch.Tensor:
-        """Returns theta0 [3][g+3]^3 (FP32, device)."""
+        """theta0 for the pair (batch 1: [n]^3 volumes -> [3][g+3]^3) or the
+        batch ([B][n]^3 -> [B][3][g+3]^3), FP32 on the device. The result is
+        the net's own buffer, overwritten by the next call."""
+        shape = (self.n,) * 3 if self.batch == 1 else (self.batch,) + (self.n,) * 3
+        for t in (fixed, moving):
+            if tuple(t.shape) != shape or t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError(f"expected contiguous FP32 {shape}, got {tuple(t.shape)}")
         check(lib().air_cnn_forward(self._h, _p(self.flat), _p(fixed), _p(moving), _p(self.theta),
                                     _p(self.ws), self.ws_bytes, _s()), "air_cnn_forward")
         return self.theta
 
     def backward(self, dtheta: torch.Tensor) -> None:
-        """Weight and bias gradients for dL/dtheta0 (after forward())."""
+        """Weight and bias gradients (summed over the batch) for dL/dtheta0,
+        after forward()."""
+        if tuple(dtheta.shape) != tuple(self.theta.shape):
+            raise ValueError(f"dtheta must be {tuple(self.theta.shape)}")
         check(lib().air_cnn_backward(self._h, _p(dtheta.contiguous()), _p(self.grad), _p(self.ws),
                                      self.ws_bytes, _s()), "air_cnn_backward")
 

@@ -1,8 +1,9 @@
 // The learned-initialisation network as one object of the C-ABI: the layer
-// schedule of a 3D encoder-decoder for an n^3 pair (n a multiple of 16), its
-// parameter layout and its workspace, and the forward and backward passes
-// sequenced over the library's BF16 MFMA convolutions and the pooling,
-// upsampling and activation kernels (k_cnn.hip).
+// schedule of a 3D encoder-decoder for a batch of n^3 pairs (n a multiple of
+// 16), its parameter layout and its workspace, and the forward and backward
+// passes sequenced over the library's BF16 MFMA convolutions and the
+// pooling, upsampling and activation kernels (k_cnn.hip). The batch is one
+// stack along z; the convolutions pad each volume on its own.
 //
 // Architecture (g = n / 8 control cells per axis):
 //   x0 = avgpool2(F, M), 8 channels (F, M, six zero channels)     (n/2)^3
@@ -31,7 +32,6 @@ typedef unsigned short u16;
 constexpr int kLayers = 6;
 constexpr int kCat = 112;
 constexpr float kOutScale = 0.05f;
-constexpr int kBwdwChunk = 256;
 
 struct LayerDef {
     int cin, cout, act;
@@ -84,15 +84,14 @@ inline size_t up256(size_t b) { return (b + 255) & ~size_t(255); }
 using namespace air;
 
 struct air_cnn {
-    int n = 0;
+    int n = 0, batch = 1;
     int h = 0, q = 0, e = 0, s = 0;   // sides at n/2, n/4, n/8, n/16
     int w_off[kLayers] = {}, b_off[kLayers] = {};
     int64_t nparam = 0;
     // workspace byte offsets
     size_t wb[kLayers] = {}, wf[kLayers] = {};
     size_t x0, a1, p1, a2, p2, cat, p3, a4, d1, out;
-    size_t g_out, g_out_bf, g_d1, g_d1_bf, g_cat, g_a4, g_a4_bf, g_p3, g_a3_bf, g_p2, g_a2,
-        g_a2_bf, g_p1, g_a1, g_a1_bf, bwdw;
+    size_t g_out_bf, g_d1_bf, g_cat, g_a4_bf, g_p3, g_a3_bf, g_p2, g_a2_bf, g_p1, g_a1_bf, bwdw;
     size_t bwdw_bytes = 0;
     size_t total = 0;
     RefreshArgs refresh{};
@@ -111,13 +110,15 @@ void layer_dims(const air_cnn* N, int l, int32_t d[3]) {
 
 extern "C" {
 
-air_status air_cnn_create(int32_t n, air_cnn** out) {
+air_status air_cnn_create(int32_t n, int32_t batch, air_cnn** out) {
     if (!out) return AIR_ERR_INVALID_ARG;
     *out = nullptr;
-    if (n < 16 || n % 16 || n > 1024) return AIR_ERR_SHAPE;
+    if (n < 16 || n % 16 || n > 1024 || batch < 1) return AIR_ERR_SHAPE;
+    if (cube(n) * batch >= (1LL << 31)) return AIR_ERR_SHAPE;
     air_cnn* N = new (std::nothrow) air_cnn();
     if (!N) return AIR_ERR_DEVICE;
     N->n = n;
+    N->batch = batch;
     N->h = n / 2;
     N->q = n / 4;
     N->e = n / 8;
@@ -150,7 +151,9 @@ air_status air_cnn_create(int32_t n, air_cnn** out) {
         total += (int)nw;
     }
     N->refresh.total = total;
-    const long long H = cube(N->h), Q = cube(N->q), E = cube(N->e), S = cube(N->s);
+    const long long B = batch;
+    const long long H = cube(N->h) * B, Q = cube(N->q) * B, E = cube(N->e) * B,
+                    S = cube(N->s) * B;
     N->x0 = take(2 * H * 8);
     N->a1 = take(2 * H * 16);
     N->p1 = take(2 * Q * 16);
@@ -161,27 +164,22 @@ air_status air_cnn_create(int32_t n, air_cnn** out) {
     N->a4 = take(2 * S * 64);
     N->d1 = take(2 * E * 48);
     N->out = take(4 * E * 16);
-    N->g_out = take(4 * E * 16);
     N->g_out_bf = take(2 * E * 16);
-    N->g_d1 = take(4 * E * 48);
     N->g_d1_bf = take(2 * E * 48);
     N->g_cat = take(4 * E * kCat);
-    N->g_a4 = take(4 * S * 64);
     N->g_a4_bf = take(2 * S * 64);
     N->g_p3 = take(4 * S * 48);
     N->g_a3_bf = take(2 * E * 48);
     N->g_p2 = take(4 * E * 32);
-    N->g_a2 = take(4 * Q * 32);
     N->g_a2_bf = take(2 * Q * 32);
     N->g_p1 = take(4 * Q * 16);
-    N->g_a1 = take(4 * H * 16);
     N->g_a1_bf = take(2 * H * 16);
     size_t bw = 0;
     for (int l = 0; l < kLayers; ++l) {
         int32_t d[3];
         layer_dims(N, l, d);
         size_t b = 0;
-        if (air_conv3d_bwd_weight_workspace(d, kDef[l].cin, kDef[l].cout, kBwdwChunk, &b) !=
+        if (air_conv3d_bwd_weight_workspace(d, batch, kDef[l].cin, kDef[l].cout, 0, &b) !=
             AIR_OK) {
             delete N;
             return AIR_ERR_SHAPE;
@@ -239,27 +237,31 @@ air_status air_cnn_forward(const air_cnn* N, const float* params, const float* f
                            params, reinterpret_cast<u16*>(w), N->refresh);
         if (hipGetLastError() != hipSuccess) return AIR_ERR_LAUNCH;
     }
-    const int32_t full[3] = {N->n, N->n, N->n};
+    const int B = N->batch;
+    // stack sizes (pooling, upsampling, input) and one volume's (convolutions)
+    const int32_t full[3] = {N->n, N->n, N->n * B};
+    const int32_t Hs[3] = {N->h, N->h, N->h * B}, Qs[3] = {N->q, N->q, N->q * B};
+    const int32_t Es[3] = {N->e, N->e, N->e * B}, Ss[3] = {N->s, N->s, N->s * B};
     const int32_t H[3] = {N->h, N->h, N->h}, Q[3] = {N->q, N->q, N->q};
     const int32_t E[3] = {N->e, N->e, N->e}, S[3] = {N->s, N->s, N->s};
+    auto conv = [&](const uint16_t* x, const int32_t* d, int l, uint16_t* ybf, int ldy,
+                    float* yf) {
+        return air_conv3d_fwd(x, d, B, kDef[l].cin, b16(N->wb[l]), params + N->b_off[l],
+                              kDef[l].cout, kDef[l].act, nullptr, 0, 0, ybf, ldy, 0, yf,
+                              kDef[l].cout, stream);
+    };
     AIR_TRY(air_cnn_input(fixed, moving, full, b16(N->x0), stream));
-    AIR_TRY(air_conv3d_fwd(b16(N->x0), H, 8, b16(N->wb[0]), params + N->b_off[0], 16, 1,
-                           b16(N->a1), 16, 0, nullptr, 16, stream));
-    AIR_TRY(air_pool2(b16(N->a1), H, 16, 16, 0, b16(N->p1), stream));
-    AIR_TRY(air_conv3d_fwd(b16(N->p1), Q, 16, b16(N->wb[1]), params + N->b_off[1], 32, 1,
-                           b16(N->a2), 32, 0, nullptr, 32, stream));
-    AIR_TRY(air_pool2(b16(N->a2), Q, 32, 32, 0, b16(N->p2), stream));
-    AIR_TRY(air_conv3d_fwd(b16(N->p2), E, 32, b16(N->wb[2]), params + N->b_off[2], 48, 1,
-                           b16(N->cat), kCat, 0, nullptr, 48, stream));
-    AIR_TRY(air_pool2(b16(N->cat), E, 48, kCat, 0, b16(N->p3), stream));
-    AIR_TRY(air_conv3d_fwd(b16(N->p3), S, 48, b16(N->wb[3]), params + N->b_off[3], 64, 1,
-                           b16(N->a4), 64, 0, nullptr, 64, stream));
-    AIR_TRY(air_up2(b16(N->a4), S, 64, b16(N->cat), kCat, 48, stream));
-    AIR_TRY(air_conv3d_fwd(b16(N->cat), E, kCat, b16(N->wb[4]), params + N->b_off[4], 48, 1,
-                           b16(N->d1), 48, 0, nullptr, 48, stream));
-    AIR_TRY(air_conv3d_fwd(b16(N->d1), E, 48, b16(N->wb[5]), params + N->b_off[5], 16, 0,
-                           nullptr, 16, 0, f32(N->out), 16, stream));
-    return air_cnn_output(f32(N->out), E, 16, kOutScale, theta0, stream);
+    AIR_TRY(conv(b16(N->x0), H, 0, b16(N->a1), 16, nullptr));
+    AIR_TRY(air_pool2(b16(N->a1), Hs, 16, 16, 0, b16(N->p1), stream));
+    AIR_TRY(conv(b16(N->p1), Q, 1, b16(N->a2), 32, nullptr));
+    AIR_TRY(air_pool2(b16(N->a2), Qs, 32, 32, 0, b16(N->p2), stream));
+    AIR_TRY(conv(b16(N->p2), E, 2, b16(N->cat), kCat, nullptr));
+    AIR_TRY(air_pool2(b16(N->cat), Es, 48, kCat, 0, b16(N->p3), stream));
+    AIR_TRY(conv(b16(N->p3), S, 3, b16(N->a4), 64, nullptr));
+    AIR_TRY(air_up2(b16(N->a4), Ss, 64, b16(N->cat), kCat, 48, stream));
+    AIR_TRY(conv(b16(N->cat), E, 4, b16(N->d1), 48, nullptr));
+    AIR_TRY(conv(b16(N->d1), E, 5, nullptr, 16, f32(N->out)));
+    return air_cnn_output(f32(N->out), E, B, 16, kOutScale, theta0, stream);
 }
 
 air_status air_cnn_backward(const air_cnn* N, const float* dtheta, float* grads, void* ws,
@@ -272,51 +274,46 @@ air_status air_cnn_backward(const air_cnn* N, const float* dtheta, float* grads,
     auto f32 = [&](size_t off) { return reinterpret_cast<float*>(w + off); };
     void* bw = w + N->bwdw;
     const size_t bwb = N->bwdw_bytes;
+    const int B = N->batch;
     const int32_t H[3] = {N->h, N->h, N->h}, Q[3] = {N->q, N->q, N->q};
     const int32_t E[3] = {N->e, N->e, N->e}, S[3] = {N->s, N->s, N->s};
-    const long long VE = cube(N->e), VS = cube(N->s), VQ = cube(N->q), VH = cube(N->h);
-    auto gw = [&](int l) { return grads + N->w_off[l]; };
-    auto gb = [&](int l) { return grads + N->b_off[l]; };
-    AIR_TRY(air_cnn_output_bwd(dtheta, E, 16, kOutScale, f32(N->g_out), stream));
-    AIR_TRY(air_cast_bf16(f32(N->g_out), b16(N->g_out_bf), VE * 16, stream));
-    AIR_TRY(air_conv3d_bwd_weight(b16(N->d1), E, 48, b16(N->g_out_bf), 16, kBwdwChunk, gw(5),
-                                  gb(5), bw, bwb, stream));
-    AIR_TRY(air_conv3d_fwd(b16(N->g_out_bf), E, 16, b16(N->wf[5]), nullptr, 48, 0, nullptr, 48, 0,
-                           f32(N->g_d1), 48, stream));
-    AIR_TRY(air_lrelu_bwd(f32(N->g_d1), 48, 0, b16(N->d1), 48, 0, VE, 48, b16(N->g_d1_bf),
-                          stream));
-    AIR_TRY(air_conv3d_bwd_weight(b16(N->cat), E, kCat, b16(N->g_d1_bf), 48, kBwdwChunk, gw(4),
-                                  gb(4), bw, bwb, stream));
-    AIR_TRY(air_conv3d_fwd(b16(N->g_d1_bf), E, 48, b16(N->wf[4]), nullptr, kCat, 0, nullptr,
-                           kCat, 0, f32(N->g_cat), kCat, stream));
+    const int32_t Hs[3] = {N->h, N->h, N->h * B}, Qs[3] = {N->q, N->q, N->q * B};
+    const int32_t Es[3] = {N->e, N->e, N->e * B}, Ss[3] = {N->s, N->s, N->s * B};
+    // weight and bias gradient of layer l from its input x and output gradient dy
+    auto bwdw = [&](const uint16_t* x, const int32_t* d, int l, const uint16_t* dy) {
+        return air_conv3d_bwd_weight(x, d, B, kDef[l].cin, dy, kDef[l].cout, 0,
+                                     grads + N->w_off[l], grads + N->b_off[l], bw, bwb, stream);
+    };
+    // input gradient of layer l (flipped weights), optionally through the
+    // activation `gate` of the layer below (act 2), as bf16 or FP32
+    auto bwdd = [&](const uint16_t* dy, const int32_t* d, int l, const uint16_t* gate, int ldg,
+                    uint16_t* dxbf, float* dxf) {
+        return air_conv3d_fwd(dy, d, B, kDef[l].cout, b16(N->wf[l]), nullptr, kDef[l].cin,
+                              gate ? 2 : 0, gate, ldg, 0, dxbf, kDef[l].cin, 0, dxf, kDef[l].cin,
+                              stream);
+    };
+    AIR_TRY(air_cnn_output_bwd(dtheta, E, B, 16, kOutScale, nullptr, b16(N->g_out_bf), stream));
+    AIR_TRY(bwdw(b16(N->d1), E, 5, b16(N->g_out_bf)));
+    AIR_TRY(bwdd(b16(N->g_out_bf), E, 5, b16(N->d1), 48, b16(N->g_d1_bf), nullptr));
+    AIR_TRY(bwdw(b16(N->cat), E, 4, b16(N->g_d1_bf)));
+    AIR_TRY(bwdd(b16(N->g_d1_bf), E, 4, nullptr, 0, nullptr, f32(N->g_cat)));
     // the decoder input is [a3 | up2(a4)]
-    AIR_TRY(air_up2_bwd(f32(N->g_cat), S, 64, kCat, 48, f32(N->g_a4), stream));
-    AIR_TRY(air_lrelu_bwd(f32(N->g_a4), 64, 0, b16(N->a4), 64, 0, VS, 64, b16(N->g_a4_bf),
-                          stream));
-    AIR_TRY(air_conv3d_bwd_weight(b16(N->p3), S, 48, b16(N->g_a4_bf), 64, kBwdwChunk, gw(3),
-                                  gb(3), bw, bwb, stream));
-    AIR_TRY(air_conv3d_fwd(b16(N->g_a4_bf), S, 64, b16(N->wf[3]), nullptr, 48, 0, nullptr, 48, 0,
-                           f32(N->g_p3), 48, stream));
+    AIR_TRY(air_up2_lrelu_bwd(f32(N->g_cat), Ss, 64, kCat, 48, b16(N->a4), 64, 0,
+                              b16(N->g_a4_bf), stream));
+    AIR_TRY(bwdw(b16(N->p3), S, 3, b16(N->g_a4_bf)));
+    AIR_TRY(bwdd(b16(N->g_a4_bf), S, 3, nullptr, 0, nullptr, f32(N->g_p3)));
     // a3 feeds both the decoder (g_cat[:, 0:48]) and the pool
-    AIR_TRY(air_pool2_bwd(f32(N->g_p3), E, 48, f32(N->g_cat), kCat, 0, 1, stream));
-    AIR_TRY(air_lrelu_bwd(f32(N->g_cat), kCat, 0, b16(N->cat), kCat, 0, VE, 48,
-                          b16(N->g_a3_bf), stream));
-    AIR_TRY(air_conv3d_bwd_weight(b16(N->p2), E, 32, b16(N->g_a3_bf), 48, kBwdwChunk, gw(2),
-                                  gb(2), bw, bwb, stream));
-    AIR_TRY(air_conv3d_fwd(b16(N->g_a3_bf), E, 48, b16(N->wf[2]), nullptr, 32, 0, nullptr, 32, 0,
-                           f32(N->g_p2), 32, stream));
-    AIR_TRY(air_pool2_bwd(f32(N->g_p2), Q, 32, f32(N->g_a2), 32, 0, 0, stream));
-    AIR_TRY(air_lrelu_bwd(f32(N->g_a2), 32, 0, b16(N->a2), 32, 0, VQ, 32, b16(N->g_a2_bf),
-                          stream));
-    AIR_TRY(air_conv3d_bwd_weight(b16(N->p1), Q, 16, b16(N->g_a2_bf), 32, kBwdwChunk, gw(1),
-                                  gb(1), bw, bwb, stream));
-    AIR_TRY(air_conv3d_fwd(b16(N->g_a2_bf), Q, 32, b16(N->wf[1]), nullptr, 16, 0, nullptr, 16, 0,
-                           f32(N->g_p1), 16, stream));
-    AIR_TRY(air_pool2_bwd(f32(N->g_p1), H, 16, f32(N->g_a1), 16, 0, 0, stream));
-    AIR_TRY(air_lrelu_bwd(f32(N->g_a1), 16, 0, b16(N->a1), 16, 0, VH, 16, b16(N->g_a1_bf),
-                          stream));
-    return air_conv3d_bwd_weight(b16(N->x0), H, 8, b16(N->g_a1_bf), 16, kBwdwChunk, gw(0), gb(0),
-                                 bw, bwb, stream);
+    AIR_TRY(air_pool2_lrelu_bwd(f32(N->g_p3), Es, 48, f32(N->g_cat), kCat, 0, b16(N->cat), kCat,
+                                0, b16(N->g_a3_bf), stream));
+    AIR_TRY(bwdw(b16(N->p2), E, 2, b16(N->g_a3_bf)));
+    AIR_TRY(bwdd(b16(N->g_a3_bf), E, 2, nullptr, 0, nullptr, f32(N->g_p2)));
+    AIR_TRY(air_pool2_lrelu_bwd(f32(N->g_p2), Qs, 32, nullptr, 0, 0, b16(N->a2), 32, 0,
+                                b16(N->g_a2_bf), stream));
+    AIR_TRY(bwdw(b16(N->p1), Q, 1, b16(N->g_a2_bf)));
+    AIR_TRY(bwdd(b16(N->g_a2_bf), Q, 1, nullptr, 0, nullptr, f32(N->g_p1)));
+    AIR_TRY(air_pool2_lrelu_bwd(f32(N->g_p1), Hs, 16, nullptr, 0, 0, b16(N->a1), 16, 0,
+                                b16(N->g_a1_bf), stream));
+    return bwdw(b16(N->x0), H, 0, b16(N->g_a1_bf));
 }
 
 }  // extern "C"

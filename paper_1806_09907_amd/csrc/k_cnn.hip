@@ -33,77 +33,123 @@ __device__ inline u16 f2bf(float f) {
     return (u16)(u >> 16);
 }
 
+// A batch of volumes is stacked along z: nz = batch * nzv, and a tap that
+// would cross from one volume into the next reads zero padding instead.
 struct ConvDims {
     int nx, ny, nz;
+    int nzv;         // depth of one volume of the stack
     int cin, cout;
     int K, Kpad;     // 27 * cin, rounded up to a multiple of 32
 };
 
-__device__ inline bf16x8 load_a(const u16* __restrict__ X, const ConvDims& D, int vx, int vy,
-                                int vz, bool valid, int k) {
-    bf16x8 r;
-    const int tap = k / D.cin, ci = k - tap * D.cin;
-    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-    const int x = vx + dx, y = vy + dy, z = vz + dz;
-    const bool in = valid && tap < 27 && (unsigned)x < (unsigned)D.nx &&
-                    (unsigned)y < (unsigned)D.ny && (unsigned)z < (unsigned)D.nz;
-    if (in) {
-        const long long v = ((long long)z * D.ny + y) * D.nx + x;
-        const uint4 q = *reinterpret_cast<const uint4*>(X + v * D.cin + ci);
-        r = __builtin_bit_cast(bf16x8, q);
-    } else {
-        r = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+// Epilogue of the forward form: v = acc + bias[co], then act 0: v, act 1:
+// LeakyReLU(0.1)(v), act 2: v * LeakyReLU'(a) with a the stored bf16
+// activation gate[row * ldg + goff + co] (the adjoint of the activation, for
+// backward-data). Written as bf16 and/or FP32.
+struct ConvEpi {
+    const float* bias;
+    int act;
+    const u16* gate;
+    int ldg, goff;
+    u16* ybf;
+    int ldy, yoff;
+    float* yf;
+    int ldyf;
+};
+
+__device__ inline void conv_store(const ConvEpi& E, long long row, int co, float v, float b) {
+    v += b;
+    if (E.act == 1) {
+        v = v > 0.f ? v : 0.1f * v;
+    } else if (E.act == 2) {
+        const float a = bf2f(E.gate[row * E.ldg + E.goff + co]);
+        v = a > 0.f ? v : 0.1f * v;
     }
-    return r;
+    if (E.ybf) E.ybf[row * E.ldy + E.yoff + co] = f2bf(v);
+    if (E.yf) E.yf[row * E.ldyf + co] = v;
 }
 
-// One block = 4 waves = 64 output voxels; NT16 = ceil(cout / 16) column tiles.
-template <int NT16>
+// output voxel of one lane: stack coordinates and the depth within its volume
+struct Vox {
+    int x, y, z, zl;
+    bool valid;
+};
+
+__device__ inline Vox vox_of(long long m, const ConvDims& D, long long N) {
+    Vox v;
+    v.valid = m < N;
+    v.x = (int)(m % D.nx);
+    v.y = (int)((m / D.nx) % D.ny);
+    v.z = (int)(m / ((long long)D.nx * D.ny));
+    v.zl = v.z % D.nzv;
+    return v;
+}
+
+__device__ inline bf16x8 load_a(const u16* __restrict__ X, const ConvDims& D, const Vox& p,
+                                int tap, int ci) {
+    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    const int x = p.x + dx, y = p.y + dy;
+    const bool in = p.valid && tap < 27 && (unsigned)x < (unsigned)D.nx &&
+                    (unsigned)y < (unsigned)D.ny && (unsigned)(p.zl + dz) < (unsigned)D.nzv;
+    uint4 q = make_uint4(0, 0, 0, 0);
+    if (in) {
+        const long long v = ((long long)(p.z + dz) * D.ny + y) * D.nx + x;
+        q = *reinterpret_cast<const uint4*>(X + v * D.cin + ci);
+    }
+    return __builtin_bit_cast(bf16x8, q);
+}
+
+__device__ inline bf16x8 load_w(const u16* __restrict__ Wt, const ConvDims& D, int co, int k) {
+    uint4 q = make_uint4(0, 0, 0, 0);
+    if (co < D.cout && k < D.K) q = *reinterpret_cast<const uint4*>(Wt + (long long)co * D.K + k);
+    return __builtin_bit_cast(bf16x8, q);
+}
+
+// One block = 4 waves; a wave computes MT tiles of 16 output voxels x all
+// NT16 = ceil(cout / 16) column tiles, so each weight operand it loads
+// feeds MT products.
+template <int NT16, int MT>
 __global__ void __launch_bounds__(256)
-k_conv_fwd(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ Wt,
-           const float* __restrict__ bias, int act, u16* __restrict__ Ybf, int ldy, int yoff,
-           float* __restrict__ Yf, int ldyf) {
+k_conv_fwd(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ Wt, ConvEpi E) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long long N = (long long)D.nx * D.ny * D.nz;
-    const long long m0 = ((long long)blockIdx.x * 4 + wave) * 16;
+    const long long m0 = ((long long)blockIdx.x * 4 + wave) * (16 * MT);
     if (m0 >= N) return;
-    const long long m = m0 + (lane & 15);
-    const bool valid = m < N;
-    const int vx = (int)(m % D.nx), vy = (int)((m / D.nx) % D.ny), vz = (int)(m / ((long long)D.nx * D.ny));
     const int g = lane >> 4;
-    f32x4 acc[NT16];
+    Vox p[MT];
 #pragma unroll
-    for (int t = 0; t < NT16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < MT; ++t) p[t] = vox_of(m0 + 16 * t + (lane & 15), D, N);
+    f32x4 acc[MT][NT16];
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int j = 0; j < NT16; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int kc = 0; kc < D.Kpad; kc += 32) {
         const int k = kc + 8 * g;
-        const bf16x8 a = load_a(X, D, vx, vy, vz, valid, k);
+        const int tap = k / D.cin, ci = k - tap * D.cin;
+        bf16x8 a[MT];
 #pragma unroll
-        for (int t = 0; t < NT16; ++t) {
-            const int co = t * 16 + (lane & 15);
-            bf16x8 b;
-            if (co < D.cout && k < D.K) {
-                const uint4 q = *reinterpret_cast<const uint4*>(Wt + (long long)co * D.K + k);
-                b = __builtin_bit_cast(bf16x8, q);
-            } else {
-                b = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
-            }
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+        for (int t = 0; t < MT; ++t) a[t] = load_a(X, D, p[t], tap, ci);
+#pragma unroll
+        for (int j = 0; j < NT16; ++j) {
+            const bf16x8 b = load_w(Wt, D, j * 16 + (lane & 15), k);
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+                acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b, acc[t][j], 0, 0, 0);
         }
     }
 #pragma unroll
-    for (int t = 0; t < NT16; ++t) {
-        const int co = t * 16 + (lane & 15);
+    for (int j = 0; j < NT16; ++j) {
+        const int co = j * 16 + (lane & 15);
         if (co >= D.cout) continue;
-        const float b = bias ? bias[co] : 0.f;
+        const float b = E.bias ? E.bias[co] : 0.f;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const long long row = m0 + 4 * g + i;
-            if (row >= N) continue;
-            float v = acc[t][i] + b;
-            if (act == 1) v = v > 0.f ? v : 0.1f * v;
-            if (Ybf) Ybf[row * ldy + yoff + co] = f2bf(v);
-            if (Yf) Yf[row * ldyf + co] = v;
-        }
+        for (int t = 0; t < MT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long long row = m0 + 16 * t + 4 * g + i;
+                if (row < N) conv_store(E, row, co, acc[t][j][i], b);
+            }
     }
 }
 
@@ -113,35 +159,24 @@ k_conv_fwd(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ Wt,
 // LDS before the same epilogue.
 template <int NT16>
 __global__ void __launch_bounds__(256)
-k_conv_fwd_sk(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ Wt,
-              const float* __restrict__ bias, int act, u16* __restrict__ Ybf, int ldy, int yoff,
-              float* __restrict__ Yf, int ldyf) {
+k_conv_fwd_sk(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ Wt, ConvEpi E) {
     __shared__ f32x4 red[4][NT16][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long long N = (long long)D.nx * D.ny * D.nz;
     const long long m0 = (long long)blockIdx.x * 16;
-    const long long m = m0 + (lane & 15);
-    const bool valid = m < N;
-    const int vx = (int)(m % D.nx), vy = (int)((m / D.nx) % D.ny), vz = (int)(m / ((long long)D.nx * D.ny));
+    const Vox p = vox_of(m0 + (lane & 15), D, N);
     const int g = lane >> 4;
     f32x4 acc[NT16];
 #pragma unroll
     for (int t = 0; t < NT16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int kc = 32 * wave; kc < D.Kpad; kc += 128) {
         const int k = kc + 8 * g;
-        const bf16x8 a = load_a(X, D, vx, vy, vz, valid, k);
+        const int tap = k / D.cin, ci = k - tap * D.cin;
+        const bf16x8 a = load_a(X, D, p, tap, ci);
 #pragma unroll
-        for (int t = 0; t < NT16; ++t) {
-            const int co = t * 16 + (lane & 15);
-            bf16x8 b;
-            if (co < D.cout && k < D.K) {
-                const uint4 q = *reinterpret_cast<const uint4*>(Wt + (long long)co * D.K + k);
-                b = __builtin_bit_cast(bf16x8, q);
-            } else {
-                b = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
-            }
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
-        }
+        for (int t = 0; t < NT16; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                a, load_w(Wt, D, t * 16 + (lane & 15), k), acc[t], 0, 0, 0);
     }
 #pragma unroll
     for (int t = 0; t < NT16; ++t) red[wave][t][lane] = acc[t];
@@ -150,40 +185,44 @@ k_conv_fwd_sk(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ Wt,
         const f32x4 v = ((red[0][t][lane] + red[1][t][lane]) + red[2][t][lane]) + red[3][t][lane];
         const int co = t * 16 + (lane & 15);
         if (co >= D.cout) continue;
-        const float b = bias ? bias[co] : 0.f;
+        const float b = E.bias ? E.bias[co] : 0.f;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const long long row = m0 + 4 * g + i;
-            if (row >= N) continue;
-            float y = v[i] + b;
-            if (act == 1) y = y > 0.f ? y : 0.1f * y;
-            if (Ybf) Ybf[row * ldy + yoff + co] = f2bf(y);
-            if (Yf) Yf[row * ldyf + co] = y;
+            if (row < N) conv_store(E, row, co, v[i], b);
         }
     }
 }
 
-// dWt partial for voxel chunk `blockIdx.z`: one wave computes the 16 output
-// channels co0.. of tile blockIdx.y against BWK k-tiles of 16 reduction
-// columns (k = tap * C_in + ci). Per step of 32 voxels every lane loads one
-// 16-byte channel vector of dY and of each shifted input, the wave transposes
-// them through LDS into [channel][voxel] tiles, and each MFMA operand is one
-// 16-byte LDS read (8 consecutive voxels of one channel). The k-group-0 wave
-// of each co tile also sums dY over the chunk for the bias gradient.
+// dWt partial of voxel chunk `blockIdx.z` (`chunk` voxels, a multiple of
+// 128): the block's four waves compute the 16 output channels co0.. of tile
+// blockIdx.y against BWK k-tiles of 16 reduction columns (k = tap * C_in +
+// ci), each wave taking 32 voxels of every 128-voxel step. Per step every
+// lane loads one 16-byte channel vector of dY and of each shifted input, the
+// wave transposes them through its own LDS tiles into [channel][voxel]
+// rows, and each MFMA operand is one 16-byte LDS read (8 consecutive voxels
+// of one channel). The four waves' sums are added in wave order through LDS
+// into one partial per chunk. The k-group-0 block of each co tile also sums
+// dY over the chunk for the bias gradient.
 constexpr int BWK = 7;    // k tiles per wave
 constexpr int BWP = 40;   // LDS row pitch in bf16 (32 voxels + pad, 16-byte multiple)
-__global__ void __launch_bounds__(64)
+constexpr int kBwStep = 128;
+__global__ void __launch_bounds__(256)
 k_conv_bwdw(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ dY, int chunk,
             float* __restrict__ part) {
-    __shared__ __align__(16) u16 sA[16 * BWP];
-    __shared__ __align__(16) u16 sB[BWK * 16 * BWP];
-    const int lane = threadIdx.x;
+    constexpr int kTileA = 16 * BWP, kTileB = BWK * 16 * BWP;   // u16 per wave
+    __shared__ __align__(16) u16 lds[4 * (kTileA + kTileB)];
+    static_assert(sizeof(lds) >= (4 * BWK * 64) * sizeof(f32x4) + 4 * 64 * sizeof(float),
+                  "the wave reduction reuses the operand tiles");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    u16* sA = lds + wave * (kTileA + kTileB);
+    u16* sB = sA + kTileA;
     const int co0 = blockIdx.y * 16, kt0 = blockIdx.x * BWK;
     const long long N = (long long)D.nx * D.ny * D.nz;
     const long long mb = (long long)blockIdx.z * chunk;
     const long long me = mb + chunk < N ? mb + chunk : N;
     const int g = lane >> 4, r = lane & 15;
-    // loader role: voxel lv of the step, channel half lh (8 channels)
+    // loader role: voxel lv of the wave's 32, channel half lh (8 channels)
     const int lv = lane >> 1, lh = lane & 1;
     const bool co_ok = co0 + 8 * lh < D.cout;
     // each loader's B rows: k = (kt0 + t) * 16 + 8 * lh .. + 8, one tap
@@ -198,26 +237,26 @@ k_conv_bwdw(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ dY, i
 #pragma unroll
     for (int t = 0; t < BWK; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     float bsum = 0.f;
-    // this lane's 16-byte vectors of one 32-voxel step (zero past the chunk)
+    // this lane's 16-byte vectors of one step (zero past the chunk)
     struct Step {
         uint4 a, b[BWK];
     };
     auto load = [&](long long mc) -> Step {
         Step q;
-        const long long m = mc + lv;
-        const bool vok = m < me;
-        const int vx = (int)(m % D.nx), vy = (int)((m / D.nx) % D.ny);
-        const int vz = (int)(m / ((long long)D.nx * D.ny));
+        const Vox p = vox_of(mc + 32 * wave + lv, D, me);
         q.a = make_uint4(0, 0, 0, 0);
-        if (vok && co_ok) q.a = *reinterpret_cast<const uint4*>(dY + m * D.cout + co0 + 8 * lh);
+        if (p.valid && co_ok)
+            q.a = *reinterpret_cast<const uint4*>(dY + (mc + 32 * wave + lv) * D.cout + co0 +
+                                                  8 * lh);
 #pragma unroll
         for (int t = 0; t < BWK; ++t) {
-            q.b[t] = make_uint4(0, 0, 0, 0);
             const int tap = ltap[t];
-            const int x = vx + tap % 3 - 1, y = vy + (tap / 3) % 3 - 1, z = vz + tap / 9 - 1;
-            if (vok && tap < 27 && (unsigned)x < (unsigned)D.nx && (unsigned)y < (unsigned)D.ny &&
-                (unsigned)z < (unsigned)D.nz) {
-                const long long v = ((long long)z * D.ny + y) * D.nx + x;
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            const int x = p.x + dx, y = p.y + dy;
+            q.b[t] = make_uint4(0, 0, 0, 0);
+            if (p.valid && tap < 27 && (unsigned)x < (unsigned)D.nx &&
+                (unsigned)y < (unsigned)D.ny && (unsigned)(p.zl + dz) < (unsigned)D.nzv) {
+                const long long v = ((long long)(p.z + dz) * D.ny + y) * D.nx + x;
                 q.b[t] = *reinterpret_cast<const uint4*>(X + v * D.cin + lci[t]);
             }
         }
@@ -253,14 +292,29 @@ k_conv_bwdw(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ dY, i
         }
     };
     // two register sets: the loads of the next step are in flight while the
-    // current one is transposed and multiplied
+    // current one is transposed and multiplied (the trip count is the same
+    // for every wave, so the barriers in process() are uniform)
     Step q0 = load(mb);
-    for (long long mc = mb; mc < me; mc += 64) {
-        const Step q1 = load(mc + 32);
+    for (long long mc = mb; mc < me; mc += 2 * kBwStep) {
+        const Step q1 = load(mc + kBwStep);
         process(q0);
-        q0 = load(mc + 64);
-        if (mc + 32 < me) process(q1);
+        q0 = load(mc + 2 * kBwStep);
+        if (mc + kBwStep < me) process(q1);
     }
+    // the four waves' tiles, added in wave order
+    __syncthreads();
+    f32x4* red = reinterpret_cast<f32x4*>(lds);       // [4][BWK][64]
+    float* bred = reinterpret_cast<float*>(red + 4 * BWK * 64);   // [4][64]
+#pragma unroll
+    for (int t = 0; t < BWK; ++t) red[(wave * BWK + t) * 64 + lane] = acc[t];
+    bred[wave * 64 + lane] = bsum;
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int t = 0; t < BWK; ++t)
+        acc[t] = ((red[t * 64 + lane] + red[(BWK + t) * 64 + lane]) +
+                  red[(2 * BWK + t) * 64 + lane]) + red[(3 * BWK + t) * 64 + lane];
+    bsum = ((bred[lane] + bred[64 + lane]) + bred[128 + lane]) + bred[192 + lane];
     // partial layout per chunk: dWt [cout][K], then db [cout]
     float* P = part + (long long)blockIdx.z * D.cout * (D.K + 1);
 #pragma unroll
@@ -443,53 +497,113 @@ k_cnn_input(const float* __restrict__ F, const float* __restrict__ M, int nx, in
     }
 }
 
-// output map: feature grid g (cells of the control spacing) [gz][gy][gx][ld]
-// (first 3 channels) -> controls theta [3][gz+3][gy+3][gx+3] with
-// theta[j] = scale * g[clamp(j - 1, 0, g - 1)] per axis (edge replication).
+// gradient through pool then LeakyReLU(0.1), in one pass:
+// dX[v][c] = bf16(lrelu'(a[v][c]) * (add[v][c] + dY[v/2][c] / 8)), with dY the
+// FP32 gradient of the pooled tensor [v/2][C], the optional FP32 slice
+// add[v * ldadd + addoff + c] (a second consumer of the activation) and the
+// stored activation a = gate[v * ldg + goff + c].
 __global__ void __launch_bounds__(kBlock)
-k_cnn_output(const float* __restrict__ G, int gx, int gy, int gz, int ld, float scale,
-             float* __restrict__ theta) {
-    const int cx = gx + 3, cy = gy + 3, cz = gz + 3;
-    const long long total = 3LL * cx * cy * cz;
+k_pool2_lrelu_bwd(const float* __restrict__ dY, int nx, int ny, int nz, int C,
+                  const float* __restrict__ add, int ldadd, int addoff,
+                  const u16* __restrict__ gate, int ldg, int goff, u16* __restrict__ dX) {
+    const long long total = (long long)nx * ny * nz * C;
+    const int mx = nx / 2, my = ny / 2;
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total;
          i += (long long)gridDim.x * kBlock) {
-        const int c = (int)(i / ((long long)cx * cy * cz));
-        const long long j = i - (long long)c * cx * cy * cz;
-        const int jx = (int)(j % cx), jy = (int)((j / cx) % cy), jz = (int)(j / ((long long)cx * cy));
-        const int x = min(max(jx - 1, 0), gx - 1), y = min(max(jy - 1, 0), gy - 1),
-                  z = min(max(jz - 1, 0), gz - 1);
-        theta[i] = scale * G[(((long long)z * gy + y) * gx + x) * ld + c];
+        const int c = (int)(i % C);
+        const long long v = i / C;
+        const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((long long)nx * ny));
+        float g = 0.125f * dY[(((long long)(z / 2) * my + y / 2) * mx + x / 2) * C + c];
+        if (add) g = add[v * ldadd + addoff + c] + g;
+        const float a = bf2f(gate[v * ldg + goff + c]);
+        dX[i] = f2bf(a > 0.f ? g : 0.1f * g);
     }
 }
 
-// adjoint of k_cnn_output: dG[v][c] = scale * sum of the controls mapped to v
-// (written for c < 3, zero for the other ld - 3 channels), as FP32.
+// gradient through nearest upsampling then LeakyReLU(0.1):
+// dX[u][c] = bf16(lrelu'(a[u][c]) * sum of the 8 children dY[v][yoff + c]),
+// dY FP32 at the fine size, a = gate[u * ldg + goff + c] at the coarse size.
 __global__ void __launch_bounds__(kBlock)
-k_cnn_output_bwd(const float* __restrict__ dtheta, int gx, int gy, int gz, int ld, float scale,
-                 float* __restrict__ dG) {
+k_up2_lrelu_bwd(const float* __restrict__ dY, int mx, int my, int mz, int C, int ldy, int yoff,
+                const u16* __restrict__ gate, int ldg, int goff, u16* __restrict__ dX) {
+    const int nx = 2 * mx, ny = 2 * my;
+    const long long total = (long long)mx * my * mz * C;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (long long)gridDim.x * kBlock) {
+        const int c = (int)(i % C);
+        const long long u = i / C;
+        const int x = (int)(u % mx), y = (int)((u / mx) % my), z = (int)(u / ((long long)mx * my));
+        float s = 0.f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int xx = 2 * x + (q & 1), yy = 2 * y + ((q >> 1) & 1), zz = 2 * z + (q >> 2);
+            s += dY[(((long long)zz * ny + yy) * nx + xx) * ldy + yoff + c];
+        }
+        const float a = bf2f(gate[u * ldg + goff + c]);
+        dX[i] = f2bf(a > 0.f ? s : 0.1f * s);
+    }
+}
+
+// output map, per volume b of the batch: feature grid g (cells of the
+// control spacing) [b][gz][gy][gx][ld] (first 3 channels) -> controls
+// theta [b][3][gz+3][gy+3][gx+3] with theta[j] = scale * g[clamp(j - 1, 0,
+// g - 1)] per axis (edge replication).
+__global__ void __launch_bounds__(kBlock)
+k_cnn_output(const float* __restrict__ G, int gx, int gy, int gz, int nb, int ld, float scale,
+             float* __restrict__ theta) {
     const int cx = gx + 3, cy = gy + 3, cz = gz + 3;
-    const long long total = (long long)gx * gy * gz * ld;
+    const long long per = 3LL * cx * cy * cz;
+    const long long total = per * nb;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (long long)gridDim.x * kBlock) {
+        const int b = (int)(i / per);
+        const long long ib = i - b * per;
+        const int c = (int)(ib / ((long long)cx * cy * cz));
+        const long long j = ib - (long long)c * cx * cy * cz;
+        const int jx = (int)(j % cx), jy = (int)((j / cx) % cy), jz = (int)(j / ((long long)cx * cy));
+        const int x = min(max(jx - 1, 0), gx - 1), y = min(max(jy - 1, 0), gy - 1),
+                  z = min(max(jz - 1, 0), gz - 1);
+        theta[i] = scale * G[((((long long)b * gz + z) * gy + y) * gx + x) * ld + c];
+    }
+}
+
+// adjoint of k_cnn_output: dG[b][v][c] = scale * sum of the controls mapped to
+// v (channels c < 3; the other ld - 3 channels are zero), as FP32 and/or
+// bf16 (either pointer may be null).
+__global__ void __launch_bounds__(kBlock)
+k_cnn_output_bwd(const float* __restrict__ dtheta, int gx, int gy, int gz, int nb, int ld,
+                 float scale, float* __restrict__ dG, u16* __restrict__ dGbf) {
+    const int cx = gx + 3, cy = gy + 3, cz = gz + 3;
+    const long long vol = (long long)gx * gy * gz;
+    const long long total = vol * nb * ld;
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total;
          i += (long long)gridDim.x * kBlock) {
         const int c = (int)(i % ld);
-        const long long v = i / ld;
-        if (c >= 3) { dG[i] = 0.f; continue; }
-        const int x = (int)(v % gx), y = (int)((v / gx) % gy), z = (int)(v / ((long long)gx * gy));
-        // controls j with clamp(j - 1) == x: j = x + 1, plus j = 0 at x = 0,
-        // plus j in [gx + 1, gx + 2] at x = gx - 1
-        int jx0 = x + 1, jx1 = x + 1, jy0 = y + 1, jy1 = y + 1, jz0 = z + 1, jz1 = z + 1;
-        if (x == 0) jx0 = 0;
-        if (x == gx - 1) jx1 = gx + 2;
-        if (y == 0) jy0 = 0;
-        if (y == gy - 1) jy1 = gy + 2;
-        if (z == 0) jz0 = 0;
-        if (z == gz - 1) jz1 = gz + 2;
+        const long long vb = i / ld;
+        const int b = (int)(vb / vol);
+        const long long v = vb - b * vol;
         float s = 0.f;
-        for (int jz = jz0; jz <= jz1; ++jz)
-            for (int jy = jy0; jy <= jy1; ++jy)
-                for (int jx = jx0; jx <= jx1; ++jx)
-                    s += dtheta[(((long long)c * cz + jz) * cy + jy) * cx + jx];
-        dG[i] = scale * s;
+        if (c < 3) {
+            const int x = (int)(v % gx), y = (int)((v / gx) % gy),
+                      z = (int)(v / ((long long)gx * gy));
+            // controls j with clamp(j - 1) == x: j = x + 1, plus j = 0 at x = 0,
+            // plus j in [gx + 1, gx + 2] at x = gx - 1
+            int jx0 = x + 1, jx1 = x + 1, jy0 = y + 1, jy1 = y + 1, jz0 = z + 1, jz1 = z + 1;
+            if (x == 0) jx0 = 0;
+            if (x == gx - 1) jx1 = gx + 2;
+            if (y == 0) jy0 = 0;
+            if (y == gy - 1) jy1 = gy + 2;
+            if (z == 0) jz0 = 0;
+            if (z == gz - 1) jz1 = gz + 2;
+            const float* T = dtheta + ((long long)b * 3 + c) * cx * cy * cz;
+            for (int jz = jz0; jz <= jz1; ++jz)
+                for (int jy = jy0; jy <= jy1; ++jy)
+                    for (int jx = jx0; jx <= jx1; ++jx)
+                        s += T[((long long)jz * cy + jy) * cx + jx];
+            s *= scale;
+        }
+        if (dG) dG[i] = s;
+        if (dGbf) dGbf[i] = f2bf(s);
     }
 }
 
@@ -513,33 +627,40 @@ using namespace air;
 
 extern "C" {
 
-air_status air_conv3d_fwd(const uint16_t* x, const int32_t dims[3], int32_t cin,
+air_status air_conv3d_fwd(const uint16_t* x, const int32_t dims[3], int32_t batch, int32_t cin,
                           const uint16_t* wt, const float* bias, int32_t cout, int32_t act,
-                          uint16_t* y_bf16, int32_t ldy, int32_t yoff, float* y_f32,
-                          int32_t ldyf, void* stream) {
+                          const uint16_t* gate, int32_t ldg, int32_t goff, uint16_t* y_bf16,
+                          int32_t ldy, int32_t yoff, float* y_f32, int32_t ldyf, void* stream) {
     if (!x || !dims || !wt || (!y_bf16 && !y_f32)) return AIR_ERR_INVALID_ARG;
-    if (cin < 8 || cin % 8 || cout < 1 || cout > 128 || act < 0 || act > 1)
+    if (cin < 8 || cin % 8 || cout < 1 || cout > 128 || act < 0 || act > 2 || batch < 1)
         return AIR_ERR_SHAPE;
     if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1) return AIR_ERR_SHAPE;
+    if (act == 2 && (!gate || goff < 0 || ldg < goff + cout)) return AIR_ERR_INVALID_ARG;
     if (y_bf16 && (ldy < yoff + cout || yoff < 0)) return AIR_ERR_SHAPE;
     if (y_f32 && ldyf < cout) return AIR_ERR_SHAPE;
     if (!a16(x) || !a16(wt)) return AIR_ERR_ALIGN;
-    ConvDims D{dims[0], dims[1], dims[2], cin, cout, 27 * cin, (27 * cin + 31) / 32 * 32};
-    if ((27 * cin) % 8) return AIR_ERR_SHAPE;
+    const long long nz = (long long)dims[2] * batch;
+    if (nz > (1LL << 30)) return AIR_ERR_SHAPE;
+    ConvDims D{dims[0], dims[1], (int)nz, dims[2], cin, cout, 27 * cin, (27 * cin + 31) / 32 * 32};
+    ConvEpi E{bias, act, act == 2 ? (const u16*)gate : nullptr, ldg, goff, (u16*)y_bf16, ldy, yoff,
+              y_f32, ldyf};
     const long long N = (long long)D.nx * D.ny * D.nz;
-    const int nblk = (int)((N + 63) / 64);
     hipStream_t s = (hipStream_t)stream;
     const int nt = (cout + 15) / 16;
-    // below 1024 blocks of 64 voxels the split-K form keeps the chip busy
-    const bool sk = nblk < 1024;
-    const int nsk = (int)((N + 15) / 16);
-    switch (nt) {
-#define CASE(T) case T: \
-        if (sk) hipLaunchKernelGGL(k_conv_fwd_sk<T>, dim3(nsk), dim3(256), 0, s, (const u16*)x, D, \
-            (const u16*)wt, bias, act, (u16*)y_bf16, ldy, yoff, y_f32, ldyf); \
-        else hipLaunchKernelGGL(k_conv_fwd<T>, dim3(nblk), dim3(256), 0, s, (const u16*)x, D, \
-            (const u16*)wt, bias, act, (u16*)y_bf16, ldy, yoff, y_f32, ldyf); \
-        break;
+    // the most voxels per wave that still give 1024 blocks of four waves;
+    // below that, the split-K form keeps the chip busy
+    const int mt = N >= 4096LL * 64 ? 4 : N >= 2048LL * 64 ? 2 : N >= 1024LL * 64 ? 1 : 0;
+    const long long nblk = mt ? (N + 64LL * mt - 1) / (64LL * mt) : (N + 15) / 16;
+    if (nblk > 0x7fffffffLL) return AIR_ERR_SHAPE;
+    const dim3 grid((unsigned)nblk), blk(256);
+    const u16* X = (const u16*)x;
+    const u16* W = (const u16*)wt;
+    switch (nt * 8 + mt) {
+#define CASE(T)                                                                       \
+    case T * 8 + 0: hipLaunchKernelGGL(k_conv_fwd_sk<T>, grid, blk, 0, s, X, D, W, E); break; \
+    case T * 8 + 1: hipLaunchKernelGGL((k_conv_fwd<T, 1>), grid, blk, 0, s, X, D, W, E); break; \
+    case T * 8 + 2: hipLaunchKernelGGL((k_conv_fwd<T, 2>), grid, blk, 0, s, X, D, W, E); break; \
+    case T * 8 + 4: hipLaunchKernelGGL((k_conv_fwd<T, 4>), grid, blk, 0, s, X, D, W, E); break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
         default: return AIR_ERR_SHAPE;
@@ -547,32 +668,49 @@ air_status air_conv3d_fwd(const uint16_t* x, const int32_t dims[3], int32_t cin,
     return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
 }
 
-air_status air_conv3d_bwd_weight_workspace(const int32_t dims[3], int32_t cin, int32_t cout,
-                                           int32_t chunk, size_t* bytes) {
-    if (!dims || !bytes || chunk < 32 || chunk % 32) return AIR_ERR_INVALID_ARG;
-    const long long N = (long long)dims[0] * dims[1] * dims[2];
-    const long long nch = (N + chunk - 1) / chunk;
+// voxels per partial of the backward-weight GEMM: about one resident round
+// of blocks (three 40 KB blocks per CU) over the whole reduction
+static long long bwdw_chunk(long long N, int cin, int cout) {
+    const int xb = ((27 * cin + 15) / 16 + BWK - 1) / BWK, ct = (cout + 15) / 16;
+    long long nbz = 768 / (xb * ct);
+    if (nbz < 1) nbz = 1;
+    long long c = (N + nbz - 1) / nbz;
+    c = (c + kBwStep - 1) / kBwStep * kBwStep;
+    return c < kBwStep ? kBwStep : c;
+}
+
+air_status air_conv3d_bwd_weight_workspace(const int32_t dims[3], int32_t batch, int32_t cin,
+                                           int32_t cout, int32_t chunk, size_t* bytes) {
+    if (!dims || !bytes || chunk < 0 || chunk % kBwStep || batch < 1) return AIR_ERR_INVALID_ARG;
+    if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1 || cin < 1 || cout < 1) return AIR_ERR_SHAPE;
+    const long long N = (long long)dims[0] * dims[1] * dims[2] * batch;
+    const long long c = chunk ? chunk : bwdw_chunk(N, cin, cout);
+    const long long nch = (N + c - 1) / c;
+    if (nch > 65535) return AIR_ERR_SHAPE;
     *bytes = (size_t)(4LL * nch * cout * (27LL * cin + 1));
     return AIR_OK;
 }
 
-air_status air_conv3d_bwd_weight(const uint16_t* x, const int32_t dims[3], int32_t cin,
-                                 const uint16_t* dy, int32_t cout, int32_t chunk, float* dwt,
-                                 float* db, void* ws, size_t ws_bytes, void* stream) {
+air_status air_conv3d_bwd_weight(const uint16_t* x, const int32_t dims[3], int32_t batch,
+                                 int32_t cin, const uint16_t* dy, int32_t cout, int32_t chunk,
+                                 float* dwt, float* db, void* ws, size_t ws_bytes, void* stream) {
     if (!x || !dims || !dy || !dwt) return AIR_ERR_INVALID_ARG;
     if (cin < 8 || cin % 8 || cout < 8 || cout % 8 || cout > 128) return AIR_ERR_SHAPE;
     if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(dy)) & 15) return AIR_ERR_ALIGN;
     size_t need = 0;
-    air_status st = air_conv3d_bwd_weight_workspace(dims, cin, cout, chunk, &need);
+    air_status st = air_conv3d_bwd_weight_workspace(dims, batch, cin, cout, chunk, &need);
     if (st != AIR_OK) return st;
     if (!ws || ws_bytes < need) return AIR_ERR_WORKSPACE;
-    ConvDims D{dims[0], dims[1], dims[2], cin, cout, 27 * cin, (27 * cin + 31) / 32 * 32};
+    const long long nz = (long long)dims[2] * batch;
+    if (nz > (1LL << 30)) return AIR_ERR_SHAPE;
+    ConvDims D{dims[0], dims[1], (int)nz, dims[2], cin, cout, 27 * cin, (27 * cin + 31) / 32 * 32};
     const long long N = (long long)D.nx * D.ny * D.nz;
-    const int nch = (int)((N + chunk - 1) / chunk);
+    const long long c = chunk ? chunk : bwdw_chunk(N, cin, cout);
+    const int nch = (int)((N + c - 1) / c);
     hipStream_t s = (hipStream_t)stream;
     const int ktiles = (D.K + 15) / 16;
     dim3 grid((ktiles + BWK - 1) / BWK, (cout + 15) / 16, nch);
-    hipLaunchKernelGGL(k_conv_bwdw, grid, dim3(64), 0, s, (const u16*)x, D, (const u16*)dy, chunk,
+    hipLaunchKernelGGL(k_conv_bwdw, grid, dim3(256), 0, s, (const u16*)x, D, (const u16*)dy, (int)c,
                        (float*)ws);
     const int total = cout * (D.K + 1);
     hipLaunchKernelGGL(k_conv_bwdw_reduce, dim3((total + 63) / 64), dim3(kRedThreads), 0, s,
@@ -644,6 +782,36 @@ air_status air_lrelu_bwd(const float* dy, int32_t ld, int32_t off, const uint16_
     return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
 }
 
+air_status air_pool2_lrelu_bwd(const float* dy, const int32_t dims[3], int32_t c,
+                              const float* add, int32_t ldadd, int32_t addoff,
+                              const uint16_t* gate, int32_t ldg, int32_t goff, uint16_t* dx,
+                              void* stream) {
+    if (!dy || !dims || !gate || !dx || c < 1 || goff < 0 || ldg < goff + c)
+        return AIR_ERR_INVALID_ARG;
+    if (add && (addoff < 0 || ldadd < addoff + c)) return AIR_ERR_INVALID_ARG;
+    if (dims[0] < 2 || dims[1] < 2 || dims[2] < 2 || dims[0] % 2 || dims[1] % 2 || dims[2] % 2)
+        return AIR_ERR_SHAPE;
+    const long long t = (long long)dims[0] * dims[1] * dims[2] * c;
+    hipLaunchKernelGGL(k_pool2_lrelu_bwd, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream, dy,
+                       dims[0], dims[1], dims[2], c, add, ldadd, addoff, (const u16*)gate, ldg, goff,
+                       (u16*)dx);
+    return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
+air_status air_up2_lrelu_bwd(const float* dy, const int32_t dims[3], int32_t c, int32_t ldy,
+                             int32_t yoff, const uint16_t* gate, int32_t ldg, int32_t goff,
+                             uint16_t* dx, void* stream) {
+    if (!dy || !dims || !gate || !dx || c < 1 || yoff < 0 || ldy < yoff + c || goff < 0 ||
+        ldg < goff + c)
+        return AIR_ERR_INVALID_ARG;
+    if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1) return AIR_ERR_SHAPE;
+    const long long t = (long long)dims[0] * dims[1] * dims[2] * c;
+    hipLaunchKernelGGL(k_up2_lrelu_bwd, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream, dy,
+                       dims[0], dims[1], dims[2], c, ldy, yoff, (const u16*)gate, ldg, goff,
+                       (u16*)dx);
+    return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+}
+
 air_status air_cnn_input(const float* fixed, const float* moving, const int32_t dims[3],
                          uint16_t* x, void* stream) {
     if (!fixed || !moving || !dims || !x) return AIR_ERR_INVALID_ARG;
@@ -654,21 +822,25 @@ air_status air_cnn_input(const float* fixed, const float* moving, const int32_t 
     return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
 }
 
-air_status air_cnn_output(const float* g, const int32_t gdims[3], int32_t ld, float scale,
-                          float* theta, void* stream) {
-    if (!g || !gdims || !theta || ld < 3) return AIR_ERR_INVALID_ARG;
-    const long long t = 3LL * (gdims[0] + 3) * (gdims[1] + 3) * (gdims[2] + 3);
+air_status air_cnn_output(const float* g, const int32_t gdims[3], int32_t batch, int32_t ld,
+                          float scale, float* theta, void* stream) {
+    if (!g || !gdims || !theta || ld < 3 || batch < 1) return AIR_ERR_INVALID_ARG;
+    if (gdims[0] < 1 || gdims[1] < 1 || gdims[2] < 1) return AIR_ERR_SHAPE;
+    const long long t = 3LL * (gdims[0] + 3) * (gdims[1] + 3) * (gdims[2] + 3) * batch;
     hipLaunchKernelGGL(k_cnn_output, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream, g,
-                       gdims[0], gdims[1], gdims[2], ld, scale, theta);
+                       gdims[0], gdims[1], gdims[2], (int)batch, ld, scale, theta);
     return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
 }
 
-air_status air_cnn_output_bwd(const float* dtheta, const int32_t gdims[3], int32_t ld, float scale,
-                              float* dg, void* stream) {
-    if (!dtheta || !gdims || !dg || ld < 3) return AIR_ERR_INVALID_ARG;
-    const long long t = (long long)gdims[0] * gdims[1] * gdims[2] * ld;
+air_status air_cnn_output_bwd(const float* dtheta, const int32_t gdims[3], int32_t batch,
+                              int32_t ld, float scale, float* dg, uint16_t* dg_bf16,
+                              void* stream) {
+    if (!dtheta || !gdims || (!dg && !dg_bf16) || ld < 3 || batch < 1) return AIR_ERR_INVALID_ARG;
+    if (gdims[0] < 1 || gdims[1] < 1 || gdims[2] < 1) return AIR_ERR_SHAPE;
+    const long long t = (long long)gdims[0] * gdims[1] * gdims[2] * ld * batch;
     hipLaunchKernelGGL(k_cnn_output_bwd, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream,
-                       dtheta, gdims[0], gdims[1], gdims[2], ld, scale, dg);
+                       dtheta, gdims[0], gdims[1], gdims[2], (int)batch, ld, scale, dg,
+                       (u16*)dg_bf16);
     return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
 }
 

@@ -126,8 +126,8 @@ int main(void) {
     /* the network object: layout queries only (no pass runs) */
     {
         air_cnn* net = NULL;
-        EXPECT(air_cnn_create(40, &net) == AIR_ERR_SHAPE && net == NULL);
-        EXPECT(air_cnn_create(64, &net) == AIR_OK && net != NULL);
+        EXPECT(air_cnn_create(40, 1, &net) == AIR_ERR_SHAPE && net == NULL);
+        EXPECT(air_cnn_create(64, 2, &net) == AIR_OK && net != NULL);
         int64_t np = 0, wo = 0, bo = 0;
         size_t wsb = 0;
         int32_t ci = 0, co = 0;

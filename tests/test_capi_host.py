@@ -237,10 +237,19 @@ def test_cnn_object_layout():
     import ctypes as C
     L = _lib.lib()
     h = C.c_void_p()
-    assert L.air_cnn_create(40, C.byref(h)) == 2          # not a multiple of 16
-    assert L.air_cnn_create(128, C.byref(h)) == 0
+    assert L.air_cnn_create(40, 1, C.byref(h)) == 2       # not a multiple of 16
+    assert L.air_cnn_create(128, 0, C.byref(h)) == 2      # empty batch
+    assert L.air_cnn_create(1024, 4, C.byref(h)) == 2     # batch * n^3 beyond 2^31
+    assert L.air_cnn_create(128, 1, C.byref(h)) == 0
     npar, wsb = C.c_int64(), C.c_size_t()
     assert L.air_cnn_sizes(h, C.byref(npar), C.byref(wsb)) == 0
+    # a batch of four: the same parameters, a larger workspace
+    h4 = C.c_void_p()
+    assert L.air_cnn_create(128, 4, C.byref(h4)) == 0
+    npar4, wsb4 = C.c_int64(), C.c_size_t()
+    assert L.air_cnn_sizes(h4, C.byref(npar4), C.byref(wsb4)) == 0
+    assert npar4.value == npar.value and 2 * wsb.value < wsb4.value <= 4 * wsb.value
+    L.air_cnn_destroy(h4)
     expect = [(8, 16), (16, 32), (32, 48), (48, 64), (112, 48), (48, 16)]
     end = 0
     for i, (cin, cout) in enumerate(expect):

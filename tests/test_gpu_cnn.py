@@ -75,6 +75,128 @@ def test_conv_forward_parity_large(cin, cout, dims):
     assert rel(y.double().cpu().numpy().reshape(ref.shape), ref) <= 1e-5
 
 
+@pytest.mark.parametrize("cin,cout,dims,batch", [
+    (8, 16, (64, 64, 64), 1),      # four 16-voxel tiles per wave
+    (16, 32, (64, 64, 32), 1),     # two tiles per wave
+    (16, 48, (9, 7, 5), 3),        # split-K form, ragged, three volumes
+    (8, 32, (32, 32, 32), 8),      # four tiles per wave across volume seams
+])
+def test_conv_forward_tiles_and_batch(cin, cout, dims, batch):
+    """Every kernel form, and a z-stack of volumes: each volume is padded on
+    its own, so the stack equals the volumes convolved one by one."""
+    rng = np.random.default_rng(cin * 3 + cout + batch)
+    nx, ny, nz = dims
+    x = bf16_round(rng.normal(size=(batch * nz, ny, nx, cin)))
+    wt = bf16_round(rng.normal(size=(cout, 27 * cin)) / np.sqrt(27 * cin))
+    b = rng.normal(size=cout).astype(np.float32).astype(np.float64)
+    y = torch.empty(batch * nz * ny * nx * cout, dtype=torch.float32, device=DEV)
+    cnn.conv_fwd(to_bf16_tensor(x), dims, cin, to_bf16_tensor(wt),
+                 torch.tensor(b, dtype=torch.float32, device=DEV), cout, 1, y_f32=y, batch=batch)
+    got = y.double().cpu().numpy().reshape(batch * nz, ny, nx, cout)
+    for v in range(batch):
+        ref = O.conv3d_fwd(x[v * nz:(v + 1) * nz], wt, b, 1)
+        assert rel(got[v * nz:(v + 1) * nz], ref) <= 1e-5, v
+
+
+@pytest.mark.parametrize("dims,batch", [((6, 5, 7), 2), ((64, 64, 32), 1)])
+def test_conv_gate_epilogue(dims, batch):
+    """act 2: the output times LeakyReLU'(a) of a stored bf16 activation slice
+    (the backward-data convolution fused with the activation's adjoint)."""
+    rng = np.random.default_rng(11)
+    cin, cout, ldg, goff = 16, 32, 40, 8
+    nx, ny, nz = dims
+    nv = batch * nx * ny * nz
+    x = bf16_round(rng.normal(size=(batch * nz, ny, nx, cin)))
+    wt = bf16_round(rng.normal(size=(cout, 27 * cin)) / np.sqrt(27 * cin))
+    gate = bf16_round(rng.normal(size=(nv, ldg)))
+    y = torch.empty(nv * cout, dtype=torch.float32, device=DEV)
+    ybf = torch.empty(nv * cout, dtype=torch.int16, device=DEV)
+    cnn.conv_fwd(to_bf16_tensor(x), dims, cin, to_bf16_tensor(wt), None, cout, 2, y_bf=ybf,
+                 y_f32=y, batch=batch, gate=to_bf16_tensor(gate), ldg=ldg, goff=goff)
+    pre = np.concatenate([O.conv3d_fwd(x[v * nz:(v + 1) * nz], wt) for v in range(batch)])
+    ref = pre.reshape(nv, cout) * np.where(gate[:, goff:goff + cout] > 0, 1.0, 0.1)
+    got = y.double().cpu().numpy().reshape(nv, cout)
+    assert rel(got, ref) <= 1e-5
+    assert np.array_equal(from_bf16_tensor(ybf).reshape(nv, cout), bf16_round(got))
+
+
+@pytest.mark.parametrize("cin,cout,dims,batch,chunk", [
+    (16, 32, (9, 7, 6), 3, 128),     # many small chunks, ragged, across seams
+    (8, 16, (32, 32, 32), 4, 0),     # the library's chunk
+    (112, 48, (16, 16, 16), 2, 0),   # the decoder's wide reduction
+])
+def test_bwd_weight_batched(cin, cout, dims, batch, chunk):
+    """Backward-weight over a z-stack = the sum of the volumes' gradients;
+    two calls give the same bits (fixed summation order)."""
+    rng = np.random.default_rng(cin + 5 * cout + batch)
+    nx, ny, nz = dims
+    x = bf16_round(rng.normal(size=(batch * nz, ny, nx, cin)))
+    dy = bf16_round(rng.normal(size=(batch * nz, ny, nx, cout)))
+    wt = np.zeros((cout, 27 * cin))
+    rdw, rdb = 0.0, 0.0
+    for v in range(batch):
+        _, dw_v, db_v = O.conv3d_bwd(x[v * nz:(v + 1) * nz], wt, dy[v * nz:(v + 1) * nz])
+        rdw, rdb = rdw + dw_v, rdb + db_v
+    ws = cnn.Workspace(torch.device(DEV))
+    outs = []
+    for _ in range(2):
+        dw = torch.empty((cout, 27 * cin), dtype=torch.float32, device=DEV)
+        db = torch.empty(cout, dtype=torch.float32, device=DEV)
+        cnn.conv_bwd_weight(to_bf16_tensor(x), dims, cin, to_bf16_tensor(dy), cout, dw, db, ws,
+                            batch=batch, chunk=chunk)
+        outs.append((dw.cpu().numpy(), db.cpu().numpy()))
+    assert rel(outs[0][0].astype(np.float64), rdw) <= 1e-5
+    assert rel(outs[0][1].astype(np.float64), rdb) <= 1e-5
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def _bf16_bits(a32):
+    """float32 array -> bf16 bit patterns (nearest even), as the kernels round."""
+    u = np.ascontiguousarray(a32, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+def test_fused_activation_adjoints():
+    """pool-then-LeakyReLU and upsample-then-LeakyReLU adjoints, against the
+    same FP32 operations written out in numpy (bit for bit)."""
+    rng = np.random.default_rng(21)
+    f32 = np.float32
+    nx, ny, nz, c = 8, 6, 10, 16
+    # pool: dx[v] = lrelu'(gate[v]) * (add[v] + dy[v/2] / 8)
+    dy = rng.normal(size=(nz // 2, ny // 2, nx // 2, c)).astype(f32)
+    ldadd, addoff, ldg, goff = 24, 4, 20, 2
+    add = rng.normal(size=(nz, ny, nx, ldadd)).astype(f32)
+    gate = bf16_round(rng.normal(size=(nz, ny, nx, ldg)))
+    dx = torch.empty(nz * ny * nx * c, dtype=torch.int16, device=DEV)
+    dyt, addt = torch.from_numpy(dy).to(DEV), torch.from_numpy(add).to(DEV)
+    gt = to_bf16_tensor(gate)
+    for use_add in (True, False):
+        check(lib().air_pool2_lrelu_bwd(dyt.data_ptr(), cnn._i3((nx, ny, nz)), c,
+                                        addt.data_ptr() if use_add else None, ldadd, addoff,
+                                        gt.data_ptr(), ldg, goff, dx.data_ptr(), None), "pool")
+        up = np.repeat(np.repeat(np.repeat(dy, 2, 0), 2, 1), 2, 2) * f32(0.125)
+        g = (add[..., addoff:addoff + c] + up) if use_add else up
+        ref = np.where(gate[..., goff:goff + c] > 0, g, f32(0.1) * g).astype(f32)
+        got = dx.cpu().numpy().view(np.uint16).reshape(ref.shape)
+        assert np.array_equal(got, _bf16_bits(ref)), use_add
+    # up: dx[u] = lrelu'(gate[u]) * sum of the 8 children dy[v][yoff + c]
+    mx, my, mz, ldy, yoff = 4, 3, 5, 40, 24
+    dyf = rng.normal(size=(2 * mz, 2 * my, 2 * mx, ldy)).astype(f32)
+    gate_c = bf16_round(rng.normal(size=(mz, my, mx, ldg)))
+    dxu = torch.empty(mz * my * mx * c, dtype=torch.int16, device=DEV)
+    # operands held in variables: a temporary freed before the launch could
+    # be reused by the next upload, which runs ahead of the kernel
+    dyft, gct = torch.from_numpy(dyf).to(DEV), to_bf16_tensor(gate_c)
+    check(lib().air_up2_lrelu_bwd(dyft.data_ptr(), cnn._i3((mx, my, mz)), c, ldy, yoff,
+                                  gct.data_ptr(), ldg, goff, dxu.data_ptr(), None), "up")
+    s = np.zeros((mz, my, mx, c), dtype=f32)
+    for q in range(8):   # the kernel's order: x fastest, then y, then z
+        qx, qy, qz = q & 1, (q >> 1) & 1, q >> 2
+        s = s + dyf[qz::2, qy::2, qx::2, yoff:yoff + c]
+    ref = np.where(gate_c[..., goff:goff + c] > 0, s, f32(0.1) * s).astype(f32)
+    assert np.array_equal(dxu.cpu().numpy().view(np.uint16).reshape(ref.shape), _bf16_bits(ref))
+
+
 @pytest.mark.parametrize("cin,cout,dims", SHAPES)
 def test_conv_backward_parity(cin, cout, dims):
     rng = np.random.default_rng(100 + cin + cout)
@@ -213,6 +335,40 @@ def test_network_forward_backward_matches_oracle():
         print(name, rel(gw, dw), rel(gb, db))
         assert rel(gw, dw) <= ulp, name
         assert rel(gb, db) <= ulp, name
+
+
+def test_network_batch_matches_single_pairs():
+    """A batch of two pairs = the two pairs one at a time: the same theta0
+    per pair and the sum of the per-pair weight gradients."""
+    n = 32
+    g = n // 8
+    rng = np.random.default_rng(8)
+    single = cnn.InitNet(n=n, seed=5)
+    pair2 = cnn.InitNet(n=n, seed=5, batch=2)
+    w = np.zeros((16, 27 * 48), dtype=np.float32)
+    w[:3] = rng.normal(0, 0.05, size=(3, 27 * 48))
+    for net in (single, pair2):
+        net.params["d2"].w.copy_(torch.from_numpy(w))
+    F = rng.uniform(size=(2, n, n, n)).astype(np.float32)
+    M = rng.uniform(size=(2, n, n, n)).astype(np.float32)
+    dth = rng.normal(size=(2, 3, g + 3, g + 3, g + 3)).astype(np.float32)
+    th2 = pair2.forward(torch.from_numpy(F).to(DEV), torch.from_numpy(M).to(DEV)).clone()
+    pair2.backward(torch.from_numpy(dth).to(DEV))
+    ths, grads = [], 0.0
+    for b in range(2):
+        ths.append(single.forward(torch.from_numpy(F[b]).to(DEV),
+                                  torch.from_numpy(M[b]).to(DEV)).clone())
+        single.backward(torch.from_numpy(dth[b]).to(DEV))
+        grads = grads + single.grad.double().cpu().numpy()
+    torch.cuda.synchronize()
+    # at this size every layer takes the same kernel form for one pair and
+    # for two, so the forward pass is the same arithmetic: bit for bit
+    for b in range(2):
+        assert torch.equal(th2[b], ths[b]), b
+    # the batch sums each weight gradient over both pairs inside its chunks,
+    # a different FP32 order from adding two per-pair sums
+    gb = pair2.grad.double().cpu().numpy()
+    assert rel(gb, grads) <= 1e-5
 
 
 def test_training_steps_reduce_objective():
