@@ -319,12 +319,24 @@ air_status air_conv3d_flip_weights(const float* wt, int32_t cin, int32_t cout, u
  * Voxels are reduced in chunks of `chunk` (a multiple of 128; 0 = the
  * library's choice, about one resident round of blocks) into workspace
  * partials (cout * (27 cin + 1) floats per chunk, at most 65535 chunks)
- * summed in a fixed order, so results repeat bit for bit. */
+ * summed in a fixed order, so results repeat bit for bit. When nx is a
+ * multiple of 8 and cout <= 64 the workspace also holds x-blocked copies of
+ * x and dy (8 consecutive x-voxels of one channel per 16 bytes), which feed
+ * the MFMA operands directly. */
 air_status air_conv3d_bwd_weight_workspace(const int32_t dims[3], int32_t batch, int32_t cin,
                                            int32_t cout, int32_t chunk, size_t* bytes);
 air_status air_conv3d_bwd_weight(const uint16_t* x, const int32_t dims[3], int32_t batch,
                                  int32_t cin, const uint16_t* dy, int32_t cout, int32_t chunk,
                                  float* dwt, float* db, void* ws, size_t ws_bytes, void* stream);
+/* The same on operands already in the x-blocked layout (nx a multiple of 8,
+ * cout <= 64): xb[b][ci][j] = x[voxel 8 b + j][ci], dyb likewise, blocks b
+ * in voxel order. The workspace holds only the partials. */
+air_status air_conv3d_bwd_weight_xb_workspace(const int32_t dims[3], int32_t batch, int32_t cin,
+                                              int32_t cout, int32_t chunk, size_t* bytes);
+air_status air_conv3d_bwd_weight_xb(const uint16_t* xb, const int32_t dims[3], int32_t batch,
+                                    int32_t cin, const uint16_t* dyb, int32_t cout, int32_t chunk,
+                                    float* dwt, float* db, void* ws, size_t ws_bytes,
+                                    void* stream);
 /* y = bf16(x), round to nearest even. */
 air_status air_cast_bf16(const float* x, uint16_t* y, int64_t n, void* stream);
 /* 2x average pooling (even dims) of the channel slice x[v * ldx + xoff + c]
@@ -350,19 +362,24 @@ air_status air_lrelu_bwd(const float* dy, int32_t ld, int32_t off, const uint16_
  * bf16 activation of the fine / coarse tensor):
  *   pool:  dx[v][c] = bf16(lrelu'(gate[v]) (add[v * ldadd + addoff + c] +
  *          dy[v/2][c] / 8)), dy FP32 [v/2][c] contiguous, add nullable;
+ *          xblocked != 0 writes dx in the x-blocked layout of
+ *          air_conv3d_bwd_weight_xb instead (no add; nx a multiple of 8,
+ *          c, ldg and goff multiples of 8, 16-byte aligned tensors);
  *   up:    dx[u][c] = bf16(lrelu'(gate[u]) sum of the 8 children
  *          dy[v * ldy + yoff + c]), dy FP32 at the fine size. */
 air_status air_pool2_lrelu_bwd(const float* dy, const int32_t dims[3], int32_t c,
                               const float* add, int32_t ldadd, int32_t addoff,
-                              const uint16_t* gate, int32_t ldg, int32_t goff, uint16_t* dx,
-                              void* stream);
+                              const uint16_t* gate, int32_t ldg, int32_t goff, int32_t xblocked,
+                              uint16_t* dx, void* stream);
 air_status air_up2_lrelu_bwd(const float* dy, const int32_t dims[3], int32_t c, int32_t ldy,
                              int32_t yoff, const uint16_t* gate, int32_t ldg, int32_t goff,
                              uint16_t* dx, void* stream);
 /* Network input: (fixed, moving) FP32 volumes (dims even) -> 2x averaged,
- * 8-channel bf16 tensor (fixed, moving, six zero channels). */
+ * 8-channel bf16 tensor (fixed, moving, six zero channels); x_xb
+ * (nullable; dims[0] / 2 a multiple of 8) also receives it in the x-blocked
+ * layout of air_conv3d_bwd_weight_xb. */
 air_status air_cnn_input(const float* fixed, const float* moving, const int32_t dims[3],
-                         uint16_t* x, void* stream);
+                         uint16_t* x, uint16_t* x_xb, void* stream);
 /* Network output, per volume b of the batch: FP32 features g
  * [b][gz][gy][gx][ld] (one cell per control cell; channels 0..2 used) ->
  * control grids theta [b][3][gz+3][gy+3][gx+3]: theta[c][j] = scale *

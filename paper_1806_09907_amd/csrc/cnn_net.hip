@@ -90,8 +90,8 @@ struct air_cnn {
     int64_t nparam = 0;
     // workspace byte offsets
     size_t wb[kLayers] = {}, wf[kLayers] = {};
-    size_t x0, a1, p1, a2, p2, cat, p3, a4, d1, out;
-    size_t g_out_bf, g_d1_bf, g_cat, g_a4_bf, g_p3, g_a3_bf, g_p2, g_a2_bf, g_p1, g_a1_bf, bwdw;
+    size_t x0, x0_xb, a1, p1, a2, p2, cat, p3, a4, d1, out;
+    size_t g_out_bf, g_d1_bf, g_cat, g_a4_bf, g_p3, g_a3_bf, g_p2, g_a2_bf, g_p1, g_a1_xb, bwdw;
     size_t bwdw_bytes = 0;
     size_t total = 0;
     RefreshArgs refresh{};
@@ -155,6 +155,7 @@ air_status air_cnn_create(int32_t n, int32_t batch, air_cnn** out) {
     const long long H = cube(N->h) * B, Q = cube(N->q) * B, E = cube(N->e) * B,
                     S = cube(N->s) * B;
     N->x0 = take(2 * H * 8);
+    N->x0_xb = take(2 * H * 8);
     N->a1 = take(2 * H * 16);
     N->p1 = take(2 * Q * 16);
     N->a2 = take(2 * Q * 32);
@@ -173,14 +174,17 @@ air_status air_cnn_create(int32_t n, int32_t batch, air_cnn** out) {
     N->g_p2 = take(4 * E * 32);
     N->g_a2_bf = take(2 * Q * 32);
     N->g_p1 = take(4 * Q * 16);
-    N->g_a1_bf = take(2 * H * 16);
+    N->g_a1_xb = take(2 * H * 16);
     size_t bw = 0;
     for (int l = 0; l < kLayers; ++l) {
         int32_t d[3];
         layer_dims(N, l, d);
         size_t b = 0;
-        if (air_conv3d_bwd_weight_workspace(d, batch, kDef[l].cin, kDef[l].cout, 0, &b) !=
-            AIR_OK) {
+        // the first layer takes x-blocked operands from its producers
+        const air_status st =
+            l == 0 ? air_conv3d_bwd_weight_xb_workspace(d, batch, kDef[l].cin, kDef[l].cout, 0, &b)
+                   : air_conv3d_bwd_weight_workspace(d, batch, kDef[l].cin, kDef[l].cout, 0, &b);
+        if (st != AIR_OK) {
             delete N;
             return AIR_ERR_SHAPE;
         }
@@ -250,7 +254,7 @@ air_status air_cnn_forward(const air_cnn* N, const float* params, const float* f
                               kDef[l].cout, kDef[l].act, nullptr, 0, 0, ybf, ldy, 0, yf,
                               kDef[l].cout, stream);
     };
-    AIR_TRY(air_cnn_input(fixed, moving, full, b16(N->x0), stream));
+    AIR_TRY(air_cnn_input(fixed, moving, full, b16(N->x0), b16(N->x0_xb), stream));
     AIR_TRY(conv(b16(N->x0), H, 0, b16(N->a1), 16, nullptr));
     AIR_TRY(air_pool2(b16(N->a1), Hs, 16, 16, 0, b16(N->p1), stream));
     AIR_TRY(conv(b16(N->p1), Q, 1, b16(N->a2), 32, nullptr));
@@ -304,16 +308,20 @@ air_status air_cnn_backward(const air_cnn* N, const float* dtheta, float* grads,
     AIR_TRY(bwdd(b16(N->g_a4_bf), S, 3, nullptr, 0, nullptr, f32(N->g_p3)));
     // a3 feeds both the decoder (g_cat[:, 0:48]) and the pool
     AIR_TRY(air_pool2_lrelu_bwd(f32(N->g_p3), Es, 48, f32(N->g_cat), kCat, 0, b16(N->cat), kCat,
-                                0, b16(N->g_a3_bf), stream));
+                                0, 0, b16(N->g_a3_bf), stream));
     AIR_TRY(bwdw(b16(N->p2), E, 2, b16(N->g_a3_bf)));
     AIR_TRY(bwdd(b16(N->g_a3_bf), E, 2, nullptr, 0, nullptr, f32(N->g_p2)));
-    AIR_TRY(air_pool2_lrelu_bwd(f32(N->g_p2), Qs, 32, nullptr, 0, 0, b16(N->a2), 32, 0,
+    AIR_TRY(air_pool2_lrelu_bwd(f32(N->g_p2), Qs, 32, nullptr, 0, 0, b16(N->a2), 32, 0, 0,
                                 b16(N->g_a2_bf), stream));
     AIR_TRY(bwdw(b16(N->p1), Q, 1, b16(N->g_a2_bf)));
     AIR_TRY(bwdd(b16(N->g_a2_bf), Q, 1, nullptr, 0, nullptr, f32(N->g_p1)));
-    AIR_TRY(air_pool2_lrelu_bwd(f32(N->g_p1), Hs, 16, nullptr, 0, 0, b16(N->a1), 16, 0,
-                                b16(N->g_a1_bf), stream));
-    return bwdw(b16(N->x0), H, 0, b16(N->g_a1_bf));
+    // the first layer's output gradient feeds only its weight gradient:
+    // written x-blocked, beside the x-blocked input of the forward pass
+    AIR_TRY(air_pool2_lrelu_bwd(f32(N->g_p1), Hs, 16, nullptr, 0, 0, b16(N->a1), 16, 0, 1,
+                                b16(N->g_a1_xb), stream));
+    return air_conv3d_bwd_weight_xb(b16(N->x0_xb), H, B, kDef[0].cin, b16(N->g_a1_xb),
+                                    kDef[0].cout, 0, grads + N->w_off[0], grads + N->b_off[0], bw,
+                                    bwb, stream);
 }
 
 }  // extern "C"

@@ -33,6 +33,31 @@ __device__ inline u16 f2bf(float f) {
     return (u16)(u >> 16);
 }
 
+// 8 bf16 values of a 16-byte vector <-> FP32
+__device__ inline void unpack8(uint4 q, float* f) {
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        f[2 * j] = __uint_as_float(w[j] << 16);
+        f[2 * j + 1] = __uint_as_float(w[j] & 0xffff0000u);
+    }
+}
+
+__device__ inline uint4 pack8(const float* f) {
+    uint32_t w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        w[j] = (uint32_t)f2bf(f[2 * j]) | ((uint32_t)f2bf(f[2 * j + 1]) << 16);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__device__ inline void load8f(const float* p, float* f) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    const float4 b = *reinterpret_cast<const float4*>(p + 4);
+    f[0] = a.x; f[1] = a.y; f[2] = a.z; f[3] = a.w;
+    f[4] = b.x; f[5] = b.y; f[6] = b.z; f[7] = b.w;
+}
+
 // A batch of volumes is stacked along z: nz = batch * nzv, and a tap that
 // would cross from one volume into the next reads zero padding instead.
 struct ConvDims {
@@ -153,43 +178,143 @@ k_conv_fwd(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ Wt, Co
     }
 }
 
-// Split-K form for small volumes (too few 64-voxel blocks to fill the
-// chip): a block takes 16 voxels, its four waves take every fourth 32-wide
-// reduction step, and the four partial tiles are added in wave order through
-// LDS before the same epilogue.
-template <int NT16>
+// Brick form: a block computes 16 x 4 x 4 output voxels (x, y, z; whole
+// bricks only) from an input tile with a one-voxel halo, 18 x 6 x 6 voxels,
+// staged in LDS one slice of CS channels at a time (channel-last, so an
+// MFMA operand, 8 channels of one tap, is one aligned 16-byte LDS read).
+// Wave w takes the plane z0 + w and four 16-voxel rows y0 .. y0 + 3 of it;
+// within a slice the reduction runs over kk = tap * CS + c, and its global
+// column is k = tap * cin + slice * CS + c (weights read from global memory
+// / cache). Each input voxel is fetched from global memory once per slice
+// instead of once per tap.
+constexpr int kBrX = 16, kBrY = 4, kBrZ = 4;
+constexpr int kHaX = kBrX + 2, kHaY = kBrY + 2, kHaZ = kBrZ + 2;
+template <int NT16, int CS>
+__global__ void __launch_bounds__(256)
+k_conv_fwd_brick(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ Wt, ConvEpi E) {
+    __shared__ __align__(16) u16 tile[kHaZ * kHaY * kHaX * CS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    // brick coordinates: x fastest, then y, then z within the volume, then volume
+    const int bx = D.nx / kBrX, by = D.ny / kBrY, bzv = D.nzv / kBrZ;
+    int b = blockIdx.x;
+    const int x0 = (b % bx) * kBrX; b /= bx;
+    const int y0 = (b % by) * kBrY; b /= by;
+    const int zb = (b % bzv) * kBrZ, vol = b / bzv;
+    const int zv0 = vol * D.nzv;   // first plane of the volume in the stack
+    constexpr int KK = 27 * CS, KKpad = (KK + 31) / 32 * 32, V8 = CS / 8;
+    f32x4 acc[kBrY][NT16];
+#pragma unroll
+    for (int t = 0; t < kBrY; ++t)
+#pragma unroll
+        for (int j = 0; j < NT16; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int ci0 = 0; ci0 < D.cin; ci0 += CS) {
+        __syncthreads();   // the previous slice's reads are done
+        for (int i = threadIdx.x; i < kHaZ * kHaY * kHaX * V8; i += 256) {
+            const int c8 = i % V8, v = i / V8;
+            const int hx = v % kHaX, hy = (v / kHaX) % kHaY, hz = v / (kHaX * kHaY);
+            const int x = x0 + hx - 1, y = y0 + hy - 1, zl = zb + hz - 1;
+            uint4 q = make_uint4(0, 0, 0, 0);
+            if ((unsigned)x < (unsigned)D.nx && (unsigned)y < (unsigned)D.ny &&
+                (unsigned)zl < (unsigned)D.nzv)
+                q = *reinterpret_cast<const uint4*>(
+                    X + (((long long)(zv0 + zl) * D.ny + y) * D.nx + x) * D.cin + ci0 + 8 * c8);
+            *reinterpret_cast<uint4*>(tile + v * CS + 8 * c8) = q;
+        }
+        __syncthreads();
+        for (int kc = 0; kc < KKpad; kc += 32) {
+            const int kk = kc + 8 * g;
+            const int tap = kk / CS, c = kk - tap * CS;
+            const bool kin = kk < KK;
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // halo offsets
+            bf16x8 a[kBrY];
+#pragma unroll
+            for (int t = 0; t < kBrY; ++t) {
+                uint4 q = make_uint4(0, 0, 0, 0);
+                if (kin)
+                    q = *reinterpret_cast<const uint4*>(
+                        tile + (((wave + dz) * kHaY + t + dy) * kHaX + r + dx) * CS + c);
+                a[t] = __builtin_bit_cast(bf16x8, q);
+            }
+            const int k = tap * D.cin + ci0 + c;
+#pragma unroll
+            for (int j = 0; j < NT16; ++j) {
+                const bf16x8 bw = kin ? load_w(Wt, D, j * 16 + r, k)
+                                      : __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+#pragma unroll
+                for (int t = 0; t < kBrY; ++t)
+                    acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], bw, acc[t][j], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NT16; ++j) {
+        const int co = j * 16 + r;
+        if (co >= D.cout) continue;
+        const float bias = E.bias ? E.bias[co] : 0.f;
+#pragma unroll
+        for (int t = 0; t < kBrY; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                // D rows 4g + i: voxel x0 + 4g + i of row (y0 + t, plane zb + wave)
+                const long long row = (((long long)(zv0 + zb + wave) * D.ny + y0 + t) * D.nx) + x0 +
+                                      4 * g + i;
+                conv_store(E, row, co, acc[t][j][i], bias);
+            }
+    }
+}
+
+// Split-K form for small volumes (too few blocks of the forms above to
+// fill the chip): a block takes MT tiles of 16 voxels, its four waves take
+// every fourth 32-wide reduction step (each weight operand a wave loads
+// feeds MT products), and the four partial tiles are added in wave order
+// through LDS, one voxel tile at a time, before the same epilogue.
+template <int NT16, int MT>
 __global__ void __launch_bounds__(256)
 k_conv_fwd_sk(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ Wt, ConvEpi E) {
     __shared__ f32x4 red[4][NT16][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long long N = (long long)D.nx * D.ny * D.nz;
-    const long long m0 = (long long)blockIdx.x * 16;
-    const Vox p = vox_of(m0 + (lane & 15), D, N);
+    const long long m0 = (long long)blockIdx.x * 16 * MT;
     const int g = lane >> 4;
-    f32x4 acc[NT16];
+    Vox p[MT];
 #pragma unroll
-    for (int t = 0; t < NT16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < MT; ++t) p[t] = vox_of(m0 + 16 * t + (lane & 15), D, N);
+    f32x4 acc[MT][NT16];
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int j = 0; j < NT16; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int kc = 32 * wave; kc < D.Kpad; kc += 128) {
         const int k = kc + 8 * g;
         const int tap = k / D.cin, ci = k - tap * D.cin;
-        const bf16x8 a = load_a(X, D, p, tap, ci);
+        bf16x8 a[MT];
 #pragma unroll
-        for (int t = 0; t < NT16; ++t)
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                a, load_w(Wt, D, t * 16 + (lane & 15), k), acc[t], 0, 0, 0);
+        for (int t = 0; t < MT; ++t) a[t] = load_a(X, D, p[t], tap, ci);
+#pragma unroll
+        for (int j = 0; j < NT16; ++j) {
+            const bf16x8 b = load_w(Wt, D, j * 16 + (lane & 15), k);
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+                acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b, acc[t][j], 0, 0, 0);
+        }
     }
 #pragma unroll
-    for (int t = 0; t < NT16; ++t) red[wave][t][lane] = acc[t];
-    __syncthreads();
-    for (int t = wave; t < NT16; t += 4) {
-        const f32x4 v = ((red[0][t][lane] + red[1][t][lane]) + red[2][t][lane]) + red[3][t][lane];
-        const int co = t * 16 + (lane & 15);
-        if (co >= D.cout) continue;
-        const float b = E.bias ? E.bias[co] : 0.f;
+    for (int t = 0; t < MT; ++t) {
+        if (t) __syncthreads();   // the previous tile's reads are done
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const long long row = m0 + 4 * g + i;
-            if (row < N) conv_store(E, row, co, v[i], b);
+        for (int j = 0; j < NT16; ++j) red[wave][j][lane] = acc[t][j];
+        __syncthreads();
+        for (int j = wave; j < NT16; j += 4) {
+            const f32x4 v = ((red[0][j][lane] + red[1][j][lane]) + red[2][j][lane]) + red[3][j][lane];
+            const int co = j * 16 + (lane & 15);
+            if (co >= D.cout) continue;
+            const float b = E.bias ? E.bias[co] : 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long long row = m0 + 16 * t + 4 * g + i;
+                if (row < N) conv_store(E, row, co, v[i], b);
+            }
         }
     }
 }
@@ -333,6 +458,186 @@ k_conv_bwdw(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ dY, i
         bsum += __shfl_xor(bsum, 16, 64);
         bsum += __shfl_xor(bsum, 32, 64);
         if (g == 0 && co0 + r < D.cout) P[(long long)D.cout * D.K + co0 + r] = bsum;
+    }
+}
+
+// ---- Backward-weight on x-blocked operands (nx a multiple of 8).
+// The GEMM reduces over voxels, so each MFMA lane needs 8 consecutive voxels
+// of one channel, while activations are stored channel-last. The operands
+// are first rewritten once in the x-blocked layout XB[b][c][8]: block b =
+// (z * ny + y) * nx/8 + x/8 holds, per channel c, the 8 voxels x = 8 (x/8)
+// .. + 7 in one 16-byte vector. A tap's input vector is then one load at the
+// block shifted by (dy, dz); a tap with dx = +-1 takes one more dword from
+// the neighbouring block and a funnel shift by one element (v_alignbyte).
+
+// XB[b][c][j] = X[voxel 8b + j][off + c] for c < C (8x8 transposes in registers)
+__global__ void __launch_bounds__(kBlock)
+k_to_xb(const u16* __restrict__ X, long long nblk, int C, int ld, int off, u16* __restrict__ XB) {
+    const int C8 = C / 8;
+    const long long total = nblk * C8;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (long long)gridDim.x * kBlock) {
+        const int cg = (int)(i % C8);
+        const long long b = i / C8;
+        uint32_t w[8][4];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint4 q = *reinterpret_cast<const uint4*>(X + (b * 8 + j) * ld + off + 8 * cg);
+            w[j][0] = q.x; w[j][1] = q.y; w[j][2] = q.z; w[j][3] = q.w;
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            // channel c of voxels 2k, 2k+1: the low (c even) or high halves of dword c/2
+            const uint32_t sel = (c & 1) ? 0x07060302u : 0x05040100u;
+            uint4 o;
+            o.x = __builtin_amdgcn_perm(w[1][c / 2], w[0][c / 2], sel);
+            o.y = __builtin_amdgcn_perm(w[3][c / 2], w[2][c / 2], sel);
+            o.z = __builtin_amdgcn_perm(w[5][c / 2], w[4][c / 2], sel);
+            o.w = __builtin_amdgcn_perm(w[7][c / 2], w[6][c / 2], sel);
+            *reinterpret_cast<uint4*>(XB + (b * C + 8 * cg + c) * 8) = o;
+        }
+    }
+}
+
+// dWt partial of voxel chunk `blockIdx.z` from x-blocked X and dY: the
+// block's four waves take 32 voxels (4 x-blocks) of every 128-voxel step;
+// a wave accumulates BWK k-tiles of 16 reduction columns against CT tiles of
+// 16 output channels, every A operand (dY) feeding BWK products and every
+// B operand (X) CT. The wave sums are added in wave order through LDS into
+// one partial per chunk, as in k_conv_bwdw.
+template <int CT>
+__global__ void __launch_bounds__(256)
+k_conv_bwdw_xb(const u16* __restrict__ XB, ConvDims D, const u16* __restrict__ dYB, int chunk,
+               float* __restrict__ part) {
+    __shared__ f32x4 red[4][CT][64];
+    __shared__ float bred[4][CT][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    const int kt0 = blockIdx.x * BWK;
+    const int nxb = D.nx / 8;
+    const long long N = (long long)D.nx * D.ny * D.nz;
+    const long long mb = (long long)blockIdx.z * chunk;
+    const long long me = mb + chunk < N ? mb + chunk : N;
+    const long long C8in = (long long)D.cin * 8, C8out = (long long)D.cout * 8;
+    // this lane's B column of each k tile: element offset of the tap's
+    // block and channel from the lane's own block, and the packed tap
+    // (dx + 1) | (dy + 1) << 2 | (dz + 1) << 4, or -1 past the last column
+    int toff[BWK], tcode[BWK];
+#pragma unroll
+    for (int t = 0; t < BWK; ++t) {
+        const int k = (kt0 + t) * 16 + r;
+        const int tap = k < D.K ? k / D.cin : 13;
+        const int ci = k < D.K ? k - tap * D.cin : 0;
+        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+        toff[t] = ((dz * D.ny + dy) * nxb) * (int)C8in + ci * 8;
+        tcode[t] = k < D.K ? (dx + 1) | (dy + 1) << 2 | (dz + 1) << 4 : -1;
+    }
+    f32x4 acc[BWK][CT];
+#pragma unroll
+    for (int t = 0; t < BWK; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) bsum[c] = 0.f;
+
+    for (long long mc = mb + 32 * wave; mc < me; mc += kBwStep) {
+        const long long blk = mc / 8 + g;     // this lane group's x-block
+        const bool ok = blk * 8 < me;
+        const int xb = (int)(blk % nxb);
+        const long long row = blk / nxb;
+        const int y = (int)(row % D.ny);
+        const int zl = (int)((row / D.ny) % D.nzv);
+        uint4 qa[CT], qv[BWK];
+        uint32_t qn[BWK];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const int co = 16 * c + r;
+            qa[c] = make_uint4(0, 0, 0, 0);
+            if (ok && co < D.cout)
+                qa[c] = *reinterpret_cast<const uint4*>(dYB + blk * C8out + (long long)co * 8);
+        }
+#pragma unroll
+        for (int t = 0; t < BWK; ++t) {
+            qv[t] = make_uint4(0, 0, 0, 0);
+            qn[t] = 0;
+            const int dx = (tcode[t] & 3) - 1, dy = ((tcode[t] >> 2) & 3) - 1,
+                      dz = ((tcode[t] >> 4) & 3) - 1;
+            const bool in = ok && tcode[t] >= 0 && (unsigned)(y + dy) < (unsigned)D.ny &&
+                            (unsigned)(zl + dz) < (unsigned)D.nzv;
+            if (in) {
+                const u16* p = XB + blk * C8in + toff[t];
+                qv[t] = *reinterpret_cast<const uint4*>(p);
+                // dx = +1: element 0 of the next block; dx = -1: element 7 of
+                // the previous one (the high half of its last dword)
+                if (dx != 0 && (unsigned)(xb + dx) < (unsigned)nxb)
+                    qn[t] = *reinterpret_cast<const uint32_t*>(p + dx * (int)C8in + (dx > 0 ? 0 : 6));
+            }
+        }
+        bf16x8 a[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            a[c] = __builtin_bit_cast(bf16x8, qa[c]);
+            if (blockIdx.x == 0) {
+                float f[8];
+                unpack8(qa[c], f);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) bsum[c] += f[j];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < BWK; ++t) {
+            const uint32_t v[4] = {qv[t].x, qv[t].y, qv[t].z, qv[t].w};
+            const int dx = (tcode[t] & 3) - 1;
+            const bool up = dx > 0, dn = dx < 0;
+            const uint32_t sh = dx != 0 ? 2u : 0u;
+            uint32_t w[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                // element j of the result = element j + dx of the 8-voxel window
+                const uint32_t hi = up ? (k < 3 ? v[k + 1] : qn[t]) : v[k];
+                const uint32_t lo = dn ? (k > 0 ? v[k - 1] : qn[t]) : v[k];
+                w[k] = __builtin_amdgcn_alignbyte(hi, lo, sh);
+            }
+            const bf16x8 b = __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c], b, acc[t][c], 0, 0, 0);
+        }
+    }
+    // the four waves' tiles, added in wave order, one k tile at a time
+    float* P = part + (long long)blockIdx.z * D.cout * (D.K + 1);
+#pragma unroll
+    for (int t = 0; t < BWK; ++t) {
+        __syncthreads();   // the previous tile's reads are done
+#pragma unroll
+        for (int c = 0; c < CT; ++c) red[wave][c][lane] = acc[t][c];
+        __syncthreads();
+        const int k = (kt0 + t) * 16 + r;
+        if (wave != 0 || k >= D.K) continue;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const f32x4 v = ((red[0][c][lane] + red[1][c][lane]) + red[2][c][lane]) + red[3][c][lane];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * c + 4 * g + i;
+                if (row < D.cout) P[(long long)row * D.K + k] = v[i];
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CT; ++c) bred[wave][c][lane] = bsum[c];
+    __syncthreads();
+    if (wave != 0) return;
+    if (blockIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            float b = ((bred[0][c][lane] + bred[1][c][lane]) + bred[2][c][lane]) + bred[3][c][lane];
+            // lanes r, r + 16, r + 32, r + 48 hold the four voxel groups of row r
+            b += __shfl_xor(b, 16, 64);
+            b += __shfl_xor(b, 32, 64);
+            if (g == 0 && 16 * c + r < D.cout) P[(long long)D.cout * D.K + 16 * c + r] = b;
+        }
     }
 }
 
@@ -544,6 +849,198 @@ k_up2_lrelu_bwd(const float* __restrict__ dY, int mx, int my, int mz, int C, int
     }
 }
 
+// ---- 8-channel forms of the pooling, upsampling and activation-adjoint
+// kernels: one thread moves one 16-byte bf16 vector (or two float4) per
+// voxel, for channel counts, row strides and offsets that are multiples of 8
+// and 16-byte aligned tensors. Per channel they do the same FP32 operations
+// in the same order as the kernels above, so the results are identical.
+
+__global__ void __launch_bounds__(kBlock)
+k_pool2_v8(const u16* __restrict__ X, int nx, int ny, int nz, int C, int ldx, int xoff,
+           u16* __restrict__ Y) {
+    const int mx = nx / 2, my = ny / 2, mz = nz / 2, C8 = C / 8;
+    const int total = mx * my * mz * C8;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
+        const int cg = i % C8, v = i / C8;
+        const int x = v % mx, y = (v / mx) % my, z = v / (mx * my);
+        float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int xx = 2 * x + (q & 1), yy = 2 * y + ((q >> 1) & 1), zz = 2 * z + (q >> 2);
+            float f[8];
+            unpack8(*reinterpret_cast<const uint4*>(
+                        X + ((long long)(zz * ny + yy) * nx + xx) * ldx + xoff + 8 * cg), f);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s[j] += f[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s[j] = 0.125f * s[j];
+        *reinterpret_cast<uint4*>(Y + (long long)v * C + 8 * cg) = pack8(s);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_up2_v8(const u16* __restrict__ X, int mx, int my, int mz, int C, u16* __restrict__ Y, int ldy,
+         int yoff) {
+    const int nx = 2 * mx, ny = 2 * my, C8 = C / 8;
+    const int total = mx * my * mz * C8;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
+        const int cg = i % C8, u = i / C8;
+        const int x = u % mx, y = (u / mx) % my, z = u / (mx * my);
+        const uint4 q = *reinterpret_cast<const uint4*>(X + (long long)u * C + 8 * cg);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int xx = 2 * x + (k & 1), yy = 2 * y + ((k >> 1) & 1), zz = 2 * z + (k >> 2);
+            *reinterpret_cast<uint4*>(Y + ((long long)(zz * ny + yy) * nx + xx) * ldy + yoff +
+                                      8 * cg) = q;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_pool2_lrelu_bwd_v8(const float* __restrict__ dY, int nx, int ny, int nz, int C,
+                     const float* __restrict__ add, int ldadd, int addoff,
+                     const u16* __restrict__ gate, int ldg, int goff, u16* __restrict__ dX) {
+    const int mx = nx / 2, my = ny / 2, C8 = C / 8;
+    const int total = nx * ny * nz * C8;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
+        const int cg = i % C8, v = i / C8;
+        const int x = v % nx, y = (v / nx) % ny, z = v / (nx * ny);
+        float g[8], a[8];
+        load8f(dY + ((long long)((z / 2) * my + y / 2) * mx + x / 2) * C + 8 * cg, g);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) g[j] = 0.125f * g[j];
+        if (add) {
+            float t[8];
+            load8f(add + (long long)v * ldadd + addoff + 8 * cg, t);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) g[j] = t[j] + g[j];
+        }
+        unpack8(*reinterpret_cast<const uint4*>(gate + (long long)v * ldg + goff + 8 * cg), a);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) g[j] = a[j] > 0.f ? g[j] : 0.1f * g[j];
+        *reinterpret_cast<uint4*>(dX + (long long)v * C + 8 * cg) = pack8(g);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_up2_lrelu_bwd_v8(const float* __restrict__ dY, int mx, int my, int mz, int C, int ldy,
+                   int yoff, const u16* __restrict__ gate, int ldg, int goff,
+                   u16* __restrict__ dX) {
+    const int nx = 2 * mx, ny = 2 * my, C8 = C / 8;
+    const int total = mx * my * mz * C8;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
+        const int cg = i % C8, u = i / C8;
+        const int x = u % mx, y = (u / mx) % my, z = u / (mx * my);
+        float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, a[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int xx = 2 * x + (q & 1), yy = 2 * y + ((q >> 1) & 1), zz = 2 * z + (q >> 2);
+            float f[8];
+            load8f(dY + ((long long)(zz * ny + yy) * nx + xx) * ldy + yoff + 8 * cg, f);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s[j] += f[j];
+        }
+        unpack8(*reinterpret_cast<const uint4*>(gate + (long long)u * ldg + goff + 8 * cg), a);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s[j] = a[j] > 0.f ? s[j] : 0.1f * s[j];
+        *reinterpret_cast<uint4*>(dX + (long long)u * C + 8 * cg) = pack8(s);
+    }
+}
+
+// the network input with its x-blocked copy (mx a multiple of 8): one
+// thread per pooled voxel, the same sums as k_cnn_input; the 8 lanes of an
+// x-block (8 consecutive voxels, 8 consecutive lanes) trade their bf16
+// (F, M) pairs so that lane 0 writes the block's F vector, lane 1 its M
+// vector and lanes 2..7 the zero channels
+__global__ void __launch_bounds__(kBlock)
+k_cnn_input_xb(const float* __restrict__ F, const float* __restrict__ M, int nx, int ny, int nz,
+               u16* __restrict__ X, u16* __restrict__ XB) {
+    const int mx = nx / 2, my = ny / 2, mz = nz / 2;
+    const long long total = (long long)mx * my * mz;
+    const int lane = threadIdx.x & 63, j = lane & 7;
+    // whole waves run every iteration (total and the stride are multiples
+    // of 8, so an x-block's lanes are all active or all idle)
+    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v - lane < total;
+         v += (long long)gridDim.x * kBlock) {
+        const bool act = v < total;
+        uint32_t fm = 0;
+        if (act) {
+            const int x = (int)(v % mx), y = (int)((v / mx) % my),
+                      z = (int)(v / ((long long)mx * my));
+            float sf = 0.f, sm = 0.f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const long long s = ((long long)(2 * z + (q >> 2)) * ny + 2 * y + ((q >> 1) & 1)) *
+                                        nx + 2 * x + (q & 1);
+                sf += F[s];
+                sm += M[s];
+            }
+            fm = (uint32_t)f2bf(0.125f * sf) | ((uint32_t)f2bf(0.125f * sm) << 16);
+            *reinterpret_cast<uint4*>(X + v * 8) = make_uint4(fm, 0, 0, 0);
+        }
+        uint32_t h[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) h[k] = (uint32_t)__shfl((int)fm, (lane & ~7) + k, 64);
+        // lane 0: F halves (low), lane 1: M halves (high), others zero
+        const uint32_t sel = j == 0 ? 0x05040100u : 0x07060302u;
+        uint4 o = make_uint4(0, 0, 0, 0);
+        if (j < 2) {
+            o.x = __builtin_amdgcn_perm(h[1], h[0], sel);
+            o.y = __builtin_amdgcn_perm(h[3], h[2], sel);
+            o.z = __builtin_amdgcn_perm(h[5], h[4], sel);
+            o.w = __builtin_amdgcn_perm(h[7], h[6], sel);
+        }
+        if (act) *reinterpret_cast<uint4*>(XB + (v - j) * 8 + 8 * j) = o;
+    }
+}
+
+// k_pool2_lrelu_bwd_v8 written x-blocked (nx a multiple of 8): thread i
+// takes voxel 8 b + j (j = i % 8) and channels 8 cg .. + 7, so that the 8
+// lanes of one x-block are consecutive; each wave stores its 64 results
+// channel-last in LDS and reads them back as dXB[b][8 cg + j][0..7].
+__global__ void __launch_bounds__(kBlock)
+k_pool2_lrelu_bwd_xb(const float* __restrict__ dY, int nx, int ny, int nz, int C,
+                     const u16* __restrict__ gate, int ldg, int goff, u16* __restrict__ dXB) {
+    __shared__ __align__(16) u16 tr[kBlock * 8];
+    const int mx = nx / 2, my = ny / 2, C8 = C / 8;
+    const int total = nx * ny * nz * C8;
+    const int j = threadIdx.x & 7;
+    u16* mine = tr + (threadIdx.x >> 3) * 64;   // this x-block group's 8 x 8 tile
+    // the loop runs while any thread of the block has work: the barriers
+    // below are reached by every thread
+    for (int i0 = blockIdx.x * kBlock; i0 < total; i0 += gridDim.x * kBlock) {
+        const int i = i0 + threadIdx.x;
+        const bool act = i < total;
+        const int cg = (i / 8) % C8, b = i / (8 * C8);
+        const int v = 8 * b + j;
+        uint4 out = make_uint4(0, 0, 0, 0);
+        if (act) {
+            const int x = v % nx, y = (v / nx) % ny, z = v / (nx * ny);
+            float g[8], a[8];
+            load8f(dY + ((long long)((z / 2) * my + y / 2) * mx + x / 2) * C + 8 * cg, g);
+            unpack8(*reinterpret_cast<const uint4*>(gate + (long long)v * ldg + goff + 8 * cg), a);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const float t = 0.125f * g[c];
+                g[c] = a[c] > 0.f ? t : 0.1f * t;
+            }
+            out = pack8(g);
+        }
+        __syncthreads();   // the previous iteration's reads are done
+        *reinterpret_cast<uint4*>(mine + 8 * j) = out;   // [voxel j][channel]
+        __syncthreads();
+        if (act) {
+            uint32_t w[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                w[k] = (uint32_t)mine[(2 * k) * 8 + j] | ((uint32_t)mine[(2 * k + 1) * 8 + j] << 16);
+            *reinterpret_cast<uint4*>(dXB + ((long long)b * C + 8 * cg + j) * 8) =
+                make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+}
+
 // output map, per volume b of the batch: feature grid g (cells of the
 // control spacing) [b][gz][gy][gx][ld] (first 3 channels) -> controls
 // theta [b][3][gz+3][gy+3][gx+3] with theta[j] = scale * g[clamp(j - 1, 0,
@@ -647,17 +1144,40 @@ air_status air_conv3d_fwd(const uint16_t* x, const int32_t dims[3], int32_t batc
     const long long N = (long long)D.nx * D.ny * D.nz;
     hipStream_t s = (hipStream_t)stream;
     const int nt = (cout + 15) / 16;
-    // the most voxels per wave that still give 1024 blocks of four waves;
-    // below that, the split-K form keeps the chip busy
-    const int mt = N >= 4096LL * 64 ? 4 : N >= 2048LL * 64 ? 2 : N >= 1024LL * 64 ? 1 : 0;
-    const long long nblk = mt ? (N + 64LL * mt - 1) / (64LL * mt) : (N + 15) / 16;
-    if (nblk > 0x7fffffffLL) return AIR_ERR_SHAPE;
-    const dim3 grid((unsigned)nblk), blk(256);
     const u16* X = (const u16*)x;
     const u16* W = (const u16*)wt;
+    // whole 16 x 4 x 4 bricks and at least one per CU: the LDS brick form
+    const long long nbrick = (D.nx % kBrX == 0 && D.ny % kBrY == 0 && D.nzv % kBrZ == 0)
+                                 ? (long long)(D.nx / kBrX) * (D.ny / kBrY) * (D.nz / kBrZ) : 0;
+    if (nbrick >= 256 && nbrick < 0x7fffffffLL) {
+        const int cs = (cin == 8 || cin == 16 || cin == 32 || cin == 48) ? cin
+                       : cin % 16 == 0 ? 16 : 8;
+        const dim3 grid((unsigned)nbrick), blk(256);
+        switch (nt * 64 + cs) {
+#define CASE2(T, C) case T * 64 + C: \
+        hipLaunchKernelGGL((k_conv_fwd_brick<T, C>), grid, blk, 0, s, X, D, W, E); break;
+#define CASE(T) CASE2(T, 8) CASE2(T, 16) CASE2(T, 32) CASE2(T, 48)
+            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+#undef CASE2
+            default: return AIR_ERR_SHAPE;
+        }
+        return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+    }
+    // the most voxels per wave that still give 1024 blocks of four waves;
+    // below that, the split-K form with four or one 16-voxel tiles per block
+    // keeps the chip busy (code 0: one tile, 3: four tiles)
+    // (four tiles only for large weight matrices, whose re-reads dominate)
+    const int mt = N >= 4096LL * 64 ? 4 : N >= 2048LL * 64 ? 2 : N >= 1024LL * 64 ? 1
+                   : (N >= 512LL * 64 && (long long)cout * D.K >= 65536) ? 3 : 0;
+    const long long nblk = mt == 3 ? (N + 63) / 64
+                           : mt ? (N + 64LL * mt - 1) / (64LL * mt) : (N + 15) / 16;
+    if (nblk > 0x7fffffffLL) return AIR_ERR_SHAPE;
+    const dim3 grid((unsigned)nblk), blk(256);
     switch (nt * 8 + mt) {
 #define CASE(T)                                                                       \
-    case T * 8 + 0: hipLaunchKernelGGL(k_conv_fwd_sk<T>, grid, blk, 0, s, X, D, W, E); break; \
+    case T * 8 + 0: hipLaunchKernelGGL((k_conv_fwd_sk<T, 1>), grid, blk, 0, s, X, D, W, E); break; \
+    case T * 8 + 3: hipLaunchKernelGGL((k_conv_fwd_sk<T, 4>), grid, blk, 0, s, X, D, W, E); break; \
     case T * 8 + 1: hipLaunchKernelGGL((k_conv_fwd<T, 1>), grid, blk, 0, s, X, D, W, E); break; \
     case T * 8 + 2: hipLaunchKernelGGL((k_conv_fwd<T, 2>), grid, blk, 0, s, X, D, W, E); break; \
     case T * 8 + 4: hipLaunchKernelGGL((k_conv_fwd<T, 4>), grid, blk, 0, s, X, D, W, E); break;
@@ -668,11 +1188,16 @@ air_status air_conv3d_fwd(const uint16_t* x, const int32_t dims[3], int32_t batc
     return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
 }
 
+// the x-blocked form: whole 8-voxel x blocks and at most four 16-channel
+// output tiles per wave
+static bool bwdw_xb(const int32_t dims[3], int cout) { return dims[0] % 8 == 0 && cout <= 64; }
+
 // voxels per partial of the backward-weight GEMM: about one resident round
-// of blocks (three 40 KB blocks per CU) over the whole reduction
-static long long bwdw_chunk(long long N, int cin, int cout) {
-    const int xb = ((27 * cin + 15) / 16 + BWK - 1) / BWK, ct = (cout + 15) / 16;
-    long long nbz = 768 / (xb * ct);
+// of blocks (`target` blocks) over the whole reduction
+static long long bwdw_chunk(long long N, int cin, int cout, bool xb) {
+    const int kx = ((27 * cin + 15) / 16 + BWK - 1) / BWK;
+    const int per = xb ? kx : kx * ((cout + 15) / 16);
+    long long nbz = (xb ? 512 : 768) / per;
     if (nbz < 1) nbz = 1;
     long long c = (N + nbz - 1) / nbz;
     c = (c + kBwStep - 1) / kBwStep * kBwStep;
@@ -684,10 +1209,14 @@ air_status air_conv3d_bwd_weight_workspace(const int32_t dims[3], int32_t batch,
     if (!dims || !bytes || chunk < 0 || chunk % kBwStep || batch < 1) return AIR_ERR_INVALID_ARG;
     if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1 || cin < 1 || cout < 1) return AIR_ERR_SHAPE;
     const long long N = (long long)dims[0] * dims[1] * dims[2] * batch;
-    const long long c = chunk ? chunk : bwdw_chunk(N, cin, cout);
+    const bool xb = bwdw_xb(dims, cout);
+    const long long c = chunk ? chunk : bwdw_chunk(N, cin, cout, xb);
     const long long nch = (N + c - 1) / c;
     if (nch > 65535) return AIR_ERR_SHAPE;
-    *bytes = (size_t)(4LL * nch * cout * (27LL * cin + 1));
+    size_t b = (size_t)(4LL * nch * cout * (27LL * cin + 1));
+    // x-blocked copies of x and dy
+    if (xb) b = ((b + 255) & ~size_t(255)) + (size_t)((2 * N * cin + 255) & ~255LL) + 2 * N * cout;
+    *bytes = b;
     return AIR_OK;
 }
 
@@ -696,7 +1225,9 @@ air_status air_conv3d_bwd_weight(const uint16_t* x, const int32_t dims[3], int32
                                  float* dwt, float* db, void* ws, size_t ws_bytes, void* stream) {
     if (!x || !dims || !dy || !dwt) return AIR_ERR_INVALID_ARG;
     if (cin < 8 || cin % 8 || cout < 8 || cout % 8 || cout > 128) return AIR_ERR_SHAPE;
-    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(dy)) & 15) return AIR_ERR_ALIGN;
+    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(dy) |
+         reinterpret_cast<uintptr_t>(ws)) & 15)
+        return AIR_ERR_ALIGN;
     size_t need = 0;
     air_status st = air_conv3d_bwd_weight_workspace(dims, batch, cin, cout, chunk, &need);
     if (st != AIR_OK) return st;
@@ -705,16 +1236,80 @@ air_status air_conv3d_bwd_weight(const uint16_t* x, const int32_t dims[3], int32
     if (nz > (1LL << 30)) return AIR_ERR_SHAPE;
     ConvDims D{dims[0], dims[1], (int)nz, dims[2], cin, cout, 27 * cin, (27 * cin + 31) / 32 * 32};
     const long long N = (long long)D.nx * D.ny * D.nz;
-    const long long c = chunk ? chunk : bwdw_chunk(N, cin, cout);
+    const bool xb = bwdw_xb(dims, cout);
+    const long long c = chunk ? chunk : bwdw_chunk(N, cin, cout, xb);
     const int nch = (int)((N + c - 1) / c);
     hipStream_t s = (hipStream_t)stream;
+    float* part = (float*)ws;
+    if (!xb) {
+        const int ktiles = (D.K + 15) / 16;
+        dim3 grid((ktiles + BWK - 1) / BWK, (cout + 15) / 16, nch);
+        hipLaunchKernelGGL(k_conv_bwdw, grid, dim3(256), 0, s, (const u16*)x, D, (const u16*)dy,
+                           (int)c, part);
+        hipLaunchKernelGGL(k_conv_bwdw_reduce, dim3((cout * (D.K + 1) + 63) / 64),
+                           dim3(kRedThreads), 0, s, (const float*)part, nch, cout, D.K, dwt, db);
+        return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+    }
+    const size_t pb = ((size_t)(4LL * nch * cout * (27LL * cin + 1)) + 255) & ~size_t(255);
+    u16* XB = reinterpret_cast<u16*>(static_cast<unsigned char*>(ws) + pb);
+    u16* dYB = XB + ((2 * N * cin + 255) & ~255LL) / 2;
+    const long long nblk = N / 8;
+    hipLaunchKernelGGL(k_to_xb, dim3(grid1(nblk * (cin / 8))), dim3(kBlock), 0, s, (const u16*)x,
+                       nblk, (int)cin, (int)cin, 0, XB);
+    hipLaunchKernelGGL(k_to_xb, dim3(grid1(nblk * (cout / 8))), dim3(kBlock), 0, s, (const u16*)dy,
+                       nblk, (int)cout, (int)cout, 0, dYB);
+    return air_conv3d_bwd_weight_xb(XB, dims, batch, cin, dYB, cout, chunk, dwt, db, ws, pb,
+                                    stream);
+}
+
+air_status air_conv3d_bwd_weight_xb_workspace(const int32_t dims[3], int32_t batch, int32_t cin,
+                                              int32_t cout, int32_t chunk, size_t* bytes) {
+    if (!dims || !bytes || chunk < 0 || chunk % kBwStep || batch < 1) return AIR_ERR_INVALID_ARG;
+    if (dims[0] < 8 || dims[0] % 8 || dims[1] < 1 || dims[2] < 1 || cin < 1 || cout < 1 ||
+        cout > 64)
+        return AIR_ERR_SHAPE;
+    const long long N = (long long)dims[0] * dims[1] * dims[2] * batch;
+    const long long c = chunk ? chunk : bwdw_chunk(N, cin, cout, true);
+    const long long nch = (N + c - 1) / c;
+    if (nch > 65535) return AIR_ERR_SHAPE;
+    *bytes = (size_t)(4LL * nch * cout * (27LL * cin + 1));
+    return AIR_OK;
+}
+
+air_status air_conv3d_bwd_weight_xb(const uint16_t* xb, const int32_t dims[3], int32_t batch,
+                                    int32_t cin, const uint16_t* dyb, int32_t cout, int32_t chunk,
+                                    float* dwt, float* db, void* ws, size_t ws_bytes,
+                                    void* stream) {
+    if (!xb || !dims || !dyb || !dwt) return AIR_ERR_INVALID_ARG;
+    if (cin < 8 || cin % 8 || cout < 8 || cout % 8) return AIR_ERR_SHAPE;
+    if ((reinterpret_cast<uintptr_t>(xb) | reinterpret_cast<uintptr_t>(dyb) |
+         reinterpret_cast<uintptr_t>(ws)) & 15)
+        return AIR_ERR_ALIGN;
+    size_t need = 0;
+    air_status st = air_conv3d_bwd_weight_xb_workspace(dims, batch, cin, cout, chunk, &need);
+    if (st != AIR_OK) return st;
+    if (!ws || ws_bytes < need) return AIR_ERR_WORKSPACE;
+    const long long nz = (long long)dims[2] * batch;
+    if (nz > (1LL << 30)) return AIR_ERR_SHAPE;
+    ConvDims D{dims[0], dims[1], (int)nz, dims[2], cin, cout, 27 * cin, (27 * cin + 31) / 32 * 32};
+    const long long N = (long long)D.nx * D.ny * D.nz;
+    // element offsets of a tap's block from the lane's own fit in 32 bits
+    if (2LL * D.ny * (D.nx / 8) * cin * 8 + 27LL * cin * 8 >= (1LL << 31)) return AIR_ERR_SHAPE;
+    const long long c = chunk ? chunk : bwdw_chunk(N, cin, cout, true);
+    const int nch = (int)((N + c - 1) / c);
+    hipStream_t s = (hipStream_t)stream;
+    float* part = (float*)ws;
     const int ktiles = (D.K + 15) / 16;
-    dim3 grid((ktiles + BWK - 1) / BWK, (cout + 15) / 16, nch);
-    hipLaunchKernelGGL(k_conv_bwdw, grid, dim3(256), 0, s, (const u16*)x, D, (const u16*)dy, (int)c,
-                       (float*)ws);
-    const int total = cout * (D.K + 1);
-    hipLaunchKernelGGL(k_conv_bwdw_reduce, dim3((total + 63) / 64), dim3(kRedThreads), 0, s,
-                       (const float*)ws, nch, cout, D.K, dwt, db);
+    const dim3 grid((ktiles + BWK - 1) / BWK, 1, nch);
+    switch ((cout + 15) / 16) {
+#define CASE(T) case T: hipLaunchKernelGGL(k_conv_bwdw_xb<T>, grid, dim3(256), 0, s, \
+                                           (const u16*)xb, D, (const u16*)dyb, (int)c, part); break;
+        CASE(1) CASE(2) CASE(3) CASE(4)
+#undef CASE
+        default: return AIR_ERR_SHAPE;
+    }
+    hipLaunchKernelGGL(k_conv_bwdw_reduce, dim3((cout * (D.K + 1) + 63) / 64), dim3(kRedThreads), 0,
+                       s, (const float*)part, nch, cout, D.K, dwt, db);
     return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
 }
 
@@ -734,13 +1329,24 @@ air_status air_cast_bf16(const float* x, uint16_t* y, int64_t n, void* stream) {
     return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
 }
 
+// the 8-channel kernels: channel counts, strides and offsets in whole
+// 16-byte vectors, aligned tensors, 32-bit thread indices
+static bool v8(int c, int ld, int off, const void* p, const void* q, long long threads) {
+    return c % 8 == 0 && ld % 8 == 0 && off % 8 == 0 && a16(p) && a16(q) &&
+           threads < (1LL << 31) - (long long)kBlock * 16384;
+}
+
 air_status air_pool2(const uint16_t* x, const int32_t dims[3], int32_t c, int32_t ldx,
                      int32_t xoff, uint16_t* y, void* stream) {
     if (!x || !dims || !y || c < 1 || xoff < 0 || ldx < xoff + c) return AIR_ERR_INVALID_ARG;
     if (dims[0] % 2 || dims[1] % 2 || dims[2] % 2) return AIR_ERR_SHAPE;
     const long long t = (long long)dims[0] * dims[1] * dims[2] / 8 * c;
-    hipLaunchKernelGGL(k_pool2, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream, (const u16*)x,
-                       dims[0], dims[1], dims[2], c, ldx, xoff, (u16*)y);
+    if (v8(c, ldx, xoff, x, y, t / 8))
+        hipLaunchKernelGGL(k_pool2_v8, dim3(grid1(t / 8)), dim3(kBlock), 0, (hipStream_t)stream,
+                           (const u16*)x, dims[0], dims[1], dims[2], c, ldx, xoff, (u16*)y);
+    else
+        hipLaunchKernelGGL(k_pool2, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream,
+                           (const u16*)x, dims[0], dims[1], dims[2], c, ldx, xoff, (u16*)y);
     return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
 }
 
@@ -756,10 +1362,14 @@ air_status air_pool2_bwd(const float* dy, const int32_t dims[3], int32_t c, floa
 
 air_status air_up2(const uint16_t* x, const int32_t dims[3], int32_t c, uint16_t* y, int32_t ldy,
                    int32_t yoff, void* stream) {
-    if (!x || !dims || !y || c < 1 || ldy < yoff + c) return AIR_ERR_INVALID_ARG;
+    if (!x || !dims || !y || c < 1 || yoff < 0 || ldy < yoff + c) return AIR_ERR_INVALID_ARG;
     const long long t = 8LL * dims[0] * dims[1] * dims[2] * c;
-    hipLaunchKernelGGL(k_up2, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream, (const u16*)x,
-                       dims[0], dims[1], dims[2], c, (u16*)y, ldy, yoff);
+    if (v8(c, ldy, yoff, x, y, t / 64))
+        hipLaunchKernelGGL(k_up2_v8, dim3(grid1(t / 64)), dim3(kBlock), 0, (hipStream_t)stream,
+                           (const u16*)x, dims[0], dims[1], dims[2], c, (u16*)y, ldy, yoff);
+    else
+        hipLaunchKernelGGL(k_up2, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream,
+                           (const u16*)x, dims[0], dims[1], dims[2], c, (u16*)y, ldy, yoff);
     return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
 }
 
@@ -784,17 +1394,30 @@ air_status air_lrelu_bwd(const float* dy, int32_t ld, int32_t off, const uint16_
 
 air_status air_pool2_lrelu_bwd(const float* dy, const int32_t dims[3], int32_t c,
                               const float* add, int32_t ldadd, int32_t addoff,
-                              const uint16_t* gate, int32_t ldg, int32_t goff, uint16_t* dx,
-                              void* stream) {
+                              const uint16_t* gate, int32_t ldg, int32_t goff, int32_t xblocked,
+                              uint16_t* dx, void* stream) {
     if (!dy || !dims || !gate || !dx || c < 1 || goff < 0 || ldg < goff + c)
         return AIR_ERR_INVALID_ARG;
     if (add && (addoff < 0 || ldadd < addoff + c)) return AIR_ERR_INVALID_ARG;
     if (dims[0] < 2 || dims[1] < 2 || dims[2] < 2 || dims[0] % 2 || dims[1] % 2 || dims[2] % 2)
         return AIR_ERR_SHAPE;
     const long long t = (long long)dims[0] * dims[1] * dims[2] * c;
-    hipLaunchKernelGGL(k_pool2_lrelu_bwd, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream, dy,
-                       dims[0], dims[1], dims[2], c, add, ldadd, addoff, (const u16*)gate, ldg, goff,
-                       (u16*)dx);
+    if (xblocked) {
+        if (add || dims[0] % 8 || !v8(c, ldg, goff, gate, dx, t / 8) || !a16(dy))
+            return AIR_ERR_SHAPE;
+        hipLaunchKernelGGL(k_pool2_lrelu_bwd_xb, dim3(grid1(t / 8)), dim3(kBlock), 0,
+                           (hipStream_t)stream, dy, dims[0], dims[1], dims[2], c, (const u16*)gate,
+                           ldg, goff, (u16*)dx);
+        return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+    }
+    if (v8(c, ldg, goff, gate, dx, t / 8) && a16(dy) && (!add || v8(c, ldadd, addoff, add, dy, 0)))
+        hipLaunchKernelGGL(k_pool2_lrelu_bwd_v8, dim3(grid1(t / 8)), dim3(kBlock), 0,
+                           (hipStream_t)stream, dy, dims[0], dims[1], dims[2], c, add, ldadd,
+                           addoff, (const u16*)gate, ldg, goff, (u16*)dx);
+    else
+        hipLaunchKernelGGL(k_pool2_lrelu_bwd, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream,
+                           dy, dims[0], dims[1], dims[2], c, add, ldadd, addoff, (const u16*)gate,
+                           ldg, goff, (u16*)dx);
     return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
 }
 
@@ -806,17 +1429,29 @@ air_status air_up2_lrelu_bwd(const float* dy, const int32_t dims[3], int32_t c, 
         return AIR_ERR_INVALID_ARG;
     if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1) return AIR_ERR_SHAPE;
     const long long t = (long long)dims[0] * dims[1] * dims[2] * c;
-    hipLaunchKernelGGL(k_up2_lrelu_bwd, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream, dy,
-                       dims[0], dims[1], dims[2], c, ldy, yoff, (const u16*)gate, ldg, goff,
-                       (u16*)dx);
+    if (v8(c, ldg, goff, gate, dx, t / 8) && v8(c, ldy, yoff, dy, dy, 0))
+        hipLaunchKernelGGL(k_up2_lrelu_bwd_v8, dim3(grid1(t / 8)), dim3(kBlock), 0,
+                           (hipStream_t)stream, dy, dims[0], dims[1], dims[2], c, ldy, yoff,
+                           (const u16*)gate, ldg, goff, (u16*)dx);
+    else
+        hipLaunchKernelGGL(k_up2_lrelu_bwd, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream,
+                           dy, dims[0], dims[1], dims[2], c, ldy, yoff, (const u16*)gate, ldg, goff,
+                           (u16*)dx);
     return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
 }
 
 air_status air_cnn_input(const float* fixed, const float* moving, const int32_t dims[3],
-                         uint16_t* x, void* stream) {
+                         uint16_t* x, uint16_t* x_xb, void* stream) {
     if (!fixed || !moving || !dims || !x) return AIR_ERR_INVALID_ARG;
     if (dims[0] % 2 || dims[1] % 2 || dims[2] % 2) return AIR_ERR_SHAPE;
     const long long t = (long long)dims[0] * dims[1] * dims[2] / 8;
+    if (x_xb) {
+        if ((dims[0] / 2) % 8 || !a16(x) || !a16(x_xb)) return AIR_ERR_SHAPE;
+        hipLaunchKernelGGL(k_cnn_input_xb, dim3(grid1(t)), dim3(kBlock), 0,
+                           (hipStream_t)stream, fixed, moving, dims[0], dims[1], dims[2], (u16*)x,
+                           (u16*)x_xb);
+        return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
+    }
     hipLaunchKernelGGL(k_cnn_input, dim3(grid1(t)), dim3(kBlock), 0, (hipStream_t)stream, fixed,
                        moving, dims[0], dims[1], dims[2], (u16*)x);
     return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
