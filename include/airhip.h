@@ -330,13 +330,16 @@ air_status air_conv3d_bwd_weight(const uint16_t* x, const int32_t dims[3], int32
                                  float* dwt, float* db, void* ws, size_t ws_bytes, void* stream);
 /* The same on operands already in the x-blocked layout (nx a multiple of 8,
  * cout <= 64): xb[b][ci][j] = x[voxel 8 b + j][ci], dyb likewise, blocks b
- * in voxel order. The workspace holds only the partials. */
+ * in voxel order. cin_used (0 = cin) declares input channels cin_used ..
+ * cin - 1 zero (padding): their weight gradients are written as zero
+ * without being computed. The workspace holds only the partials. */
 air_status air_conv3d_bwd_weight_xb_workspace(const int32_t dims[3], int32_t batch, int32_t cin,
-                                              int32_t cout, int32_t chunk, size_t* bytes);
+                                              int32_t cin_used, int32_t cout, int32_t chunk,
+                                              size_t* bytes);
 air_status air_conv3d_bwd_weight_xb(const uint16_t* xb, const int32_t dims[3], int32_t batch,
-                                    int32_t cin, const uint16_t* dyb, int32_t cout, int32_t chunk,
-                                    float* dwt, float* db, void* ws, size_t ws_bytes,
-                                    void* stream);
+                                    int32_t cin, int32_t cin_used, const uint16_t* dyb,
+                                    int32_t cout, int32_t chunk, float* dwt, float* db, void* ws,
+                                    size_t ws_bytes, void* stream);
 /* y = bf16(x), round to nearest even. */
 air_status air_cast_bf16(const float* x, uint16_t* y, int64_t n, void* stream);
 /* 2x average pooling (even dims) of the channel slice x[v * ldx + xoff + c]

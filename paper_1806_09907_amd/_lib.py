@@ -94,10 +94,10 @@ SIGNATURES = {
     "air_lrelu_bwd": (_i32, [_vp, _i32, _i32, _vp, _i32, _i32, _i64, _i32, _vp, _vp]),
     "air_pool2_lrelu_bwd": (_i32, [_vp, _vp, _i32, _vp, _i32, _i32, _vp, _i32, _i32, _i32, _vp,
                                    _vp]),
-    "air_conv3d_bwd_weight_xb_workspace": (_i32, [_vp, _i32, _i32, _i32, _i32,
+    "air_conv3d_bwd_weight_xb_workspace": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32,
                                                   ctypes.POINTER(_sz)]),
-    "air_conv3d_bwd_weight_xb": (_i32, [_vp, _vp, _i32, _i32, _vp, _i32, _i32, _vp, _vp, _vp, _sz,
-                                        _vp]),
+    "air_conv3d_bwd_weight_xb": (_i32, [_vp, _vp, _i32, _i32, _i32, _vp, _i32, _i32, _vp, _vp, _vp,
+                                        _sz, _vp]),
     "air_up2_lrelu_bwd": (_i32, [_vp, _vp, _i32, _i32, _i32, _vp, _i32, _i32, _vp, _vp]),
     "air_cnn_input": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "air_cnn_output": (_i32, [_vp, _vp, _i32, _i32, _f32, _vp, _vp]),

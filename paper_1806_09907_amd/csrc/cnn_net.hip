@@ -32,6 +32,7 @@ typedef unsigned short u16;
 constexpr int kLayers = 6;
 constexpr int kCat = 112;
 constexpr float kOutScale = 0.05f;
+constexpr int kInUsed = 2;   // channels of x0 that carry data (F, M); the rest are zero
 
 struct LayerDef {
     int cin, cout, act;
@@ -182,7 +183,8 @@ air_status air_cnn_create(int32_t n, int32_t batch, air_cnn** out) {
         size_t b = 0;
         // the first layer takes x-blocked operands from its producers
         const air_status st =
-            l == 0 ? air_conv3d_bwd_weight_xb_workspace(d, batch, kDef[l].cin, kDef[l].cout, 0, &b)
+            l == 0 ? air_conv3d_bwd_weight_xb_workspace(d, batch, kDef[l].cin, kInUsed,
+                                                        kDef[l].cout, 0, &b)
                    : air_conv3d_bwd_weight_workspace(d, batch, kDef[l].cin, kDef[l].cout, 0, &b);
         if (st != AIR_OK) {
             delete N;
@@ -319,7 +321,7 @@ air_status air_cnn_backward(const air_cnn* N, const float* dtheta, float* grads,
     // written x-blocked, beside the x-blocked input of the forward pass
     AIR_TRY(air_pool2_lrelu_bwd(f32(N->g_p1), Hs, 16, nullptr, 0, 0, b16(N->a1), 16, 0, 1,
                                 b16(N->g_a1_xb), stream));
-    return air_conv3d_bwd_weight_xb(b16(N->x0_xb), H, B, kDef[0].cin, b16(N->g_a1_xb),
+    return air_conv3d_bwd_weight_xb(b16(N->x0_xb), H, B, kDef[0].cin, kInUsed, b16(N->g_a1_xb),
                                     kDef[0].cout, 0, grads + N->w_off[0], grads + N->b_off[0], bw,
                                     bwb, stream);
 }

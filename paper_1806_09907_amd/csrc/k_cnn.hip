@@ -507,8 +507,8 @@ k_to_xb(const u16* __restrict__ X, long long nblk, int C, int ld, int off, u16* 
 // one partial per chunk, as in k_conv_bwdw.
 template <int CT>
 __global__ void __launch_bounds__(256)
-k_conv_bwdw_xb(const u16* __restrict__ XB, ConvDims D, const u16* __restrict__ dYB, int chunk,
-               float* __restrict__ part) {
+k_conv_bwdw_xb(const u16* __restrict__ XB, ConvDims D, int cu, const u16* __restrict__ dYB,
+               int chunk, float* __restrict__ part) {
     __shared__ f32x4 red[4][CT][64];
     __shared__ float bred[4][CT][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -519,6 +519,9 @@ k_conv_bwdw_xb(const u16* __restrict__ XB, ConvDims D, const u16* __restrict__ d
     const long long mb = (long long)blockIdx.z * chunk;
     const long long me = mb + chunk < N ? mb + chunk : N;
     const long long C8in = (long long)D.cin * 8, C8out = (long long)D.cout * 8;
+    // computed columns: k = tap * cu + ci over the first cu input channels
+    // (the others are known to be zero)
+    const int Ku = 27 * cu;
     // this lane's B column of each k tile: element offset of the tap's
     // block and channel from the lane's own block, and the packed tap
     // (dx + 1) | (dy + 1) << 2 | (dz + 1) << 4, or -1 past the last column
@@ -526,11 +529,11 @@ k_conv_bwdw_xb(const u16* __restrict__ XB, ConvDims D, const u16* __restrict__ d
 #pragma unroll
     for (int t = 0; t < BWK; ++t) {
         const int k = (kt0 + t) * 16 + r;
-        const int tap = k < D.K ? k / D.cin : 13;
-        const int ci = k < D.K ? k - tap * D.cin : 0;
+        const int tap = k < Ku ? k / cu : 13;
+        const int ci = k < Ku ? k - tap * cu : 0;
         const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
         toff[t] = ((dz * D.ny + dy) * nxb) * (int)C8in + ci * 8;
-        tcode[t] = k < D.K ? (dx + 1) | (dy + 1) << 2 | (dz + 1) << 4 : -1;
+        tcode[t] = k < Ku ? (dx + 1) | (dy + 1) << 2 | (dz + 1) << 4 : -1;
     }
     f32x4 acc[BWK][CT];
 #pragma unroll
@@ -605,8 +608,9 @@ k_conv_bwdw_xb(const u16* __restrict__ XB, ConvDims D, const u16* __restrict__ d
                 acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c], b, acc[t][c], 0, 0, 0);
         }
     }
-    // the four waves' tiles, added in wave order, one k tile at a time
-    float* P = part + (long long)blockIdx.z * D.cout * (D.K + 1);
+    // the four waves' tiles, added in wave order, one k tile at a time;
+    // partial layout per chunk: [cout][Ku] over the computed columns, then db
+    float* P = part + (long long)blockIdx.z * D.cout * (Ku + 1);
 #pragma unroll
     for (int t = 0; t < BWK; ++t) {
         __syncthreads();   // the previous tile's reads are done
@@ -614,14 +618,14 @@ k_conv_bwdw_xb(const u16* __restrict__ XB, ConvDims D, const u16* __restrict__ d
         for (int c = 0; c < CT; ++c) red[wave][c][lane] = acc[t][c];
         __syncthreads();
         const int k = (kt0 + t) * 16 + r;
-        if (wave != 0 || k >= D.K) continue;
+        if (wave != 0 || k >= Ku) continue;
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
             const f32x4 v = ((red[0][c][lane] + red[1][c][lane]) + red[2][c][lane]) + red[3][c][lane];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = 16 * c + 4 * g + i;
-                if (row < D.cout) P[(long long)row * D.K + k] = v[i];
+                if (row < D.cout) P[(long long)row * Ku + k] = v[i];
             }
         }
     }
@@ -636,26 +640,37 @@ k_conv_bwdw_xb(const u16* __restrict__ XB, ConvDims D, const u16* __restrict__ d
             // lanes r, r + 16, r + 32, r + 48 hold the four voxel groups of row r
             b += __shfl_xor(b, 16, 64);
             b += __shfl_xor(b, 32, 64);
-            if (g == 0 && 16 * c + r < D.cout) P[(long long)D.cout * D.K + 16 * c + r] = b;
+            if (g == 0 && 16 * c + r < D.cout) P[(long long)D.cout * Ku + 16 * c + r] = b;
         }
     }
 }
 
 // dWt and db = sums of the chunk partials: a block takes 64 outputs, its 16
 // waves sum every 16th chunk, and the 16 sums are added in wave order (a
-// fixed order, so the result is repeatable).
+// fixed order, so the result is repeatable). The partials hold the columns
+// k = tap * cu + ci of the first cu input channels (cu = cin: all); the
+// columns of the other channels are written as zero.
 constexpr int kRedThreads = 1024;
 __global__ void __launch_bounds__(kRedThreads)
-k_conv_bwdw_reduce(const float* __restrict__ part, int nchunk, int cout, int K,
+k_conv_bwdw_reduce(const float* __restrict__ part, int nchunk, int cout, int cin, int cu,
                    float* __restrict__ dW, float* __restrict__ db) {
     constexpr int NW = kRedThreads / 64;
     __shared__ float red[kRedThreads];
-    const int total = cout * (K + 1);
+    const int K = 27 * cin, Ku = 27 * cu;
+    const int total = cout * (K + 1), ptotal = cout * (Ku + 1);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = blockIdx.x * 64 + lane;
+    // the partial column of output i, or -1 for a known-zero channel
+    int src = -1;
+    if (i < cout * K) {
+        const int co = i / K, k = i - co * K, tap = k / cin, ci = k - tap * cin;
+        if (ci < cu) src = co * Ku + tap * cu + ci;
+    } else if (i < total) {
+        src = cout * Ku + (i - cout * K);
+    }
     float s = 0.f;
-    if (i < total)
-        for (int c = w; c < nchunk; c += NW) s += part[(long long)c * total + i];
+    if (src >= 0)
+        for (int c = w; c < nchunk; c += NW) s += part[(long long)c * ptotal + src];
     red[threadIdx.x] = s;
     __syncthreads();
     if (w != 0 || i >= total) return;
@@ -1247,7 +1262,8 @@ air_status air_conv3d_bwd_weight(const uint16_t* x, const int32_t dims[3], int32
         hipLaunchKernelGGL(k_conv_bwdw, grid, dim3(256), 0, s, (const u16*)x, D, (const u16*)dy,
                            (int)c, part);
         hipLaunchKernelGGL(k_conv_bwdw_reduce, dim3((cout * (D.K + 1) + 63) / 64),
-                           dim3(kRedThreads), 0, s, (const float*)part, nch, cout, D.K, dwt, db);
+                           dim3(kRedThreads), 0, s, (const float*)part, nch, cout, cin, cin, dwt,
+                           db);
         return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
     }
     const size_t pb = ((size_t)(4LL * nch * cout * (27LL * cin + 1)) + 255) & ~size_t(255);
@@ -1258,35 +1274,38 @@ air_status air_conv3d_bwd_weight(const uint16_t* x, const int32_t dims[3], int32
                        nblk, (int)cin, (int)cin, 0, XB);
     hipLaunchKernelGGL(k_to_xb, dim3(grid1(nblk * (cout / 8))), dim3(kBlock), 0, s, (const u16*)dy,
                        nblk, (int)cout, (int)cout, 0, dYB);
-    return air_conv3d_bwd_weight_xb(XB, dims, batch, cin, dYB, cout, chunk, dwt, db, ws, pb,
+    return air_conv3d_bwd_weight_xb(XB, dims, batch, cin, 0, dYB, cout, chunk, dwt, db, ws, pb,
                                     stream);
 }
 
 air_status air_conv3d_bwd_weight_xb_workspace(const int32_t dims[3], int32_t batch, int32_t cin,
-                                              int32_t cout, int32_t chunk, size_t* bytes) {
+                                              int32_t cin_used, int32_t cout, int32_t chunk,
+                                              size_t* bytes) {
     if (!dims || !bytes || chunk < 0 || chunk % kBwStep || batch < 1) return AIR_ERR_INVALID_ARG;
     if (dims[0] < 8 || dims[0] % 8 || dims[1] < 1 || dims[2] < 1 || cin < 1 || cout < 1 ||
-        cout > 64)
+        cout > 64 || cin_used < 0 || cin_used > cin)
         return AIR_ERR_SHAPE;
+    const int cu = cin_used ? cin_used : cin;
     const long long N = (long long)dims[0] * dims[1] * dims[2] * batch;
-    const long long c = chunk ? chunk : bwdw_chunk(N, cin, cout, true);
+    const long long c = chunk ? chunk : bwdw_chunk(N, cu, cout, true);
     const long long nch = (N + c - 1) / c;
     if (nch > 65535) return AIR_ERR_SHAPE;
-    *bytes = (size_t)(4LL * nch * cout * (27LL * cin + 1));
+    *bytes = (size_t)(4LL * nch * cout * (27LL * cu + 1));
     return AIR_OK;
 }
 
 air_status air_conv3d_bwd_weight_xb(const uint16_t* xb, const int32_t dims[3], int32_t batch,
-                                    int32_t cin, const uint16_t* dyb, int32_t cout, int32_t chunk,
-                                    float* dwt, float* db, void* ws, size_t ws_bytes,
-                                    void* stream) {
+                                    int32_t cin, int32_t cin_used, const uint16_t* dyb,
+                                    int32_t cout, int32_t chunk, float* dwt, float* db, void* ws,
+                                    size_t ws_bytes, void* stream) {
     if (!xb || !dims || !dyb || !dwt) return AIR_ERR_INVALID_ARG;
     if (cin < 8 || cin % 8 || cout < 8 || cout % 8) return AIR_ERR_SHAPE;
     if ((reinterpret_cast<uintptr_t>(xb) | reinterpret_cast<uintptr_t>(dyb) |
          reinterpret_cast<uintptr_t>(ws)) & 15)
         return AIR_ERR_ALIGN;
     size_t need = 0;
-    air_status st = air_conv3d_bwd_weight_xb_workspace(dims, batch, cin, cout, chunk, &need);
+    air_status st =
+        air_conv3d_bwd_weight_xb_workspace(dims, batch, cin, cin_used, cout, chunk, &need);
     if (st != AIR_OK) return st;
     if (!ws || ws_bytes < need) return AIR_ERR_WORKSPACE;
     const long long nz = (long long)dims[2] * batch;
@@ -1295,21 +1314,23 @@ air_status air_conv3d_bwd_weight_xb(const uint16_t* xb, const int32_t dims[3], i
     const long long N = (long long)D.nx * D.ny * D.nz;
     // element offsets of a tap's block from the lane's own fit in 32 bits
     if (2LL * D.ny * (D.nx / 8) * cin * 8 + 27LL * cin * 8 >= (1LL << 31)) return AIR_ERR_SHAPE;
-    const long long c = chunk ? chunk : bwdw_chunk(N, cin, cout, true);
+    const int cu = cin_used ? cin_used : cin;
+    const long long c = chunk ? chunk : bwdw_chunk(N, cu, cout, true);
     const int nch = (int)((N + c - 1) / c);
     hipStream_t s = (hipStream_t)stream;
     float* part = (float*)ws;
-    const int ktiles = (D.K + 15) / 16;
+    const int ktiles = (27 * cu + 15) / 16;
     const dim3 grid((ktiles + BWK - 1) / BWK, 1, nch);
     switch ((cout + 15) / 16) {
 #define CASE(T) case T: hipLaunchKernelGGL(k_conv_bwdw_xb<T>, grid, dim3(256), 0, s, \
-                                           (const u16*)xb, D, (const u16*)dyb, (int)c, part); break;
+                                           (const u16*)xb, D, cu, (const u16*)dyb, (int)c, part); \
+                break;
         CASE(1) CASE(2) CASE(3) CASE(4)
 #undef CASE
         default: return AIR_ERR_SHAPE;
     }
     hipLaunchKernelGGL(k_conv_bwdw_reduce, dim3((cout * (D.K + 1) + 63) / 64), dim3(kRedThreads), 0,
-                       s, (const float*)part, nch, cout, D.K, dwt, db);
+                       s, (const float*)part, nch, cout, cin, cu, dwt, db);
     return hipGetLastError() == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
 }
 

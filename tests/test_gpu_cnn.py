@@ -158,6 +158,47 @@ def test_bwd_weight_batched(cin, cout, dims, batch, chunk):
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
+@pytest.mark.parametrize("cin,cu,cout,dims,batch", [
+    (8, 2, 16, (16, 12, 10), 2),     # the network's first layer: 2 of 8 channels carry data
+    (16, 0, 32, (24, 8, 6), 3),      # all channels
+])
+def test_bwd_weight_xblocked_operands(cin, cu, cout, dims, batch):
+    """air_conv3d_bwd_weight_xb on operands given in the x-blocked layout;
+    with cin_used = cu the remaining input channels are zero and their
+    gradient columns come back zero."""
+    rng = np.random.default_rng(cin + cu + cout)
+    nx, ny, nz = dims
+    x = bf16_round(rng.normal(size=(batch * nz, ny, nx, cin)))
+    if cu:
+        x[..., cu:] = 0.0
+    dy = bf16_round(rng.normal(size=(batch * nz, ny, nx, cout)))
+    rdw, rdb = 0.0, 0.0
+    for v in range(batch):
+        _, dw_v, db_v = O.conv3d_bwd(x[v * nz:(v + 1) * nz], np.zeros((cout, 27 * cin)),
+                                     dy[v * nz:(v + 1) * nz])
+        rdw, rdb = rdw + dw_v, rdb + db_v
+
+    def xblocked(a):
+        c = a.shape[3]
+        return np.ascontiguousarray(a.reshape(batch * nz, ny, nx // 8, 8, c).transpose(0, 1, 2, 4, 3))
+
+    xb, dyb = to_bf16_tensor(xblocked(x)), to_bf16_tensor(xblocked(dy))
+    need = ctypes.c_size_t()
+    check(lib().air_conv3d_bwd_weight_xb_workspace(cnn._i3(dims), batch, cin, cu, cout, 0,
+                                                   ctypes.byref(need)), "ws")
+    ws = torch.empty(int(need.value), dtype=torch.uint8, device=DEV)
+    dw = torch.full((cout, 27 * cin), float("nan"), dtype=torch.float32, device=DEV)
+    db = torch.empty(cout, dtype=torch.float32, device=DEV)
+    check(lib().air_conv3d_bwd_weight_xb(xb.data_ptr(), cnn._i3(dims), batch, cin, cu,
+                                         dyb.data_ptr(), cout, 0, dw.data_ptr(), db.data_ptr(),
+                                         ws.data_ptr(), ws.numel(), None), "bwd_xb")
+    got = dw.double().cpu().numpy()
+    assert rel(got, rdw) <= 1e-5
+    assert rel(db.double().cpu().numpy(), rdb) <= 1e-5
+    if cu:
+        assert np.all(got.reshape(cout, 27, cin)[:, :, cu:] == 0.0)
+
+
 def _bf16_bits(a32):
     """float32 array -> bf16 bit patterns (nearest even), as the kernels round."""
     u = np.ascontiguousarray(a32, dtype=np.float32).view(np.uint32).astype(np.uint64)
