@@ -22,6 +22,9 @@ __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t by
 }
 
 // Two consecutive floats at byte offset voff + soff (dword aligned).
+// cache-policy operand of the buffer builtins: non-temporal (streamed data)
+constexpr int kNonTemporal = 2;
+
 __device__ inline v2f load2(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
     return __builtin_bit_cast(v2f, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }

@@ -577,10 +577,10 @@ k_fused3_s8(const LaunchCtx C) {
     const float nyf = (float)ny;
     const int lane4 = (yc * nx + xc) * 4;   // byte offset of voxel (x, y, 0)
     const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, (uint32_t)(P.nvox * 4));
+    const __amdgpu_buffer_rsrc_t rF = make_rsrc(F, (uint32_t)(P.nvox * 4));
+    const int fl4 = (yc * nx + xc) * 4;   // byte offset of F at (x, y, 0)
     float* part = reinterpret_cast<float*>(C.ws + C.L.part) + P.part_off +
                   (long long)(item - P.tile_begin) * P.part_stride;
-    const float* Fcol = F + (long long)yc * nx + xc;
-    const long long nxy = (long long)nx * ny;
 
     // y and x passes of control plane kzl, whose z sums the threads have
     // written to E
@@ -647,7 +647,10 @@ k_fused3_s8(const LaunchCtx C) {
         // past the volume) scales every contribution.
         const int z = cz * S + r;
         Prep q;
-        q.Fv = __builtin_nontemporal_load(Fcol + (long long)min(z, nz - 1) * nxy);
+        // F through its buffer descriptor: the lane's offset is fixed, the
+        // plane's is a scalar (streamed once: non-temporal)
+        q.Fv = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                             rF, fl4, min(z, nz - 1) * nxy4, kNonTemporal));
         float w0 = kW8.w[r][0], w1 = kW8.w[r][1], w2 = kW8.w[r][2], w3 = kW8.w[r][3];
         float sx_ = snx, sy_ = sny, sz_ = snz;
         // every uniform input of this stage passes through an empty asm that
@@ -667,13 +670,13 @@ k_fused3_s8(const LaunchCtx C) {
         const float dx = fmaf(u[0], sx_, 0.f), dy = fmaf(u[1], sy_, 0.f);
         const float dz = fmaf(u[2], sz_, 0.f);
         const float zf = (float)z;
-        const float mact = (act && z < nz) ? 1.f : 0.f;
         // cell [x + c, x + c + 1] with c = floor(d) clamped to [-x, n - 2 - x]
-        // so that every load is in range. Then f = d - c is exact; it lies in
-        // [0, 1] iff x + d does in [0, n - 1], except for a point beyond the
-        // last voxel (c clamped down, "e"), which is inside only when d is
-        // the integer n - 1 - x (f == 1); its derivative is right-sided
-        // (zero padding)
+        // so that every load is in range. Then f = d - c is exact (c is an
+        // integer no larger in magnitude than d's integer part), and it lies
+        // in [0, 1] iff x + d lies in [0, n - 1]: below the range c is
+        // clamped up and f < 0; above it c is clamped down ("e") and f > 1,
+        // except for d the integer n - 1 - x (f == 1), the last voxel, whose
+        // derivative is right-sided (zero padding)
         const float flx = floorf(dx), fly = floorf(dy), flz = floorf(dz);
         const float clx = __builtin_amdgcn_fmed3f(flx, lox, hcx);
         const float cly = __builtin_amdgcn_fmed3f(fly, loy, hcy);
@@ -685,11 +688,12 @@ k_fused3_s8(const LaunchCtx C) {
         q.fy = dy - cly;
         q.fz = dz - clz;
         constexpr uint32_t kOne = 0x3f800000u;   // bits of 1.0f: f in [0, 1]
-        // (bitwise, not short-circuit: every test is a compare, no branch)
-        const bool in = (int)(__float_as_uint(q.fx) <= kOne) & (int)(!q.ex | (dx == flx)) &
-                        (int)(__float_as_uint(q.fy) <= kOne) & (int)(!q.ey | (dy == fly)) &
-                        (int)(__float_as_uint(q.fz) <= kOne) & (int)(!q.ez | (dz == flz));
-        q.m = in ? mact : 0.f;
+        // (bitwise, not short-circuit: every test is a compare, no branch;
+        // a negative f has its sign bit set and fails like f > 1)
+        const bool in = (int)(__float_as_uint(q.fx) <= kOne) &
+                        (int)(__float_as_uint(q.fy) <= kOne) &
+                        (int)(__float_as_uint(q.fz) <= kOne) & (int)act & (int)(z < nz);
+        q.m = in ? 1.f : 0.f;
         // byte offset of the cell's first corner: the row step clz ny + cly
         // is an exact float (|.| < 2^24), the rest 24-bit integer arithmetic
         const int rows = (int)fmaf(clz, nyf, cly);
