@@ -119,7 +119,9 @@ struct AxisCell {
 __device__ inline AxisCell axis_cell(int x, Disp q, int n) {
     const float lo = (float)(-x), hi = (float)(n - 1 - x);
     AxisCell c;
-    c.in = (q.d > lo || (q.d == lo && q.e >= 0.f)) && (q.d < hi || (q.d == hi && q.e <= 0.f));
+    // (bitwise: compares only, no branches)
+    c.in = ((int)(q.d > lo) | ((int)(q.d == lo) & (int)(q.e >= 0.f))) &
+           ((int)(q.d < hi) | ((int)(q.d == hi) & (int)(q.e <= 0.f)));
     const float d = fminf(fmaxf(q.d, -1e9f), 1e9f);
     const float fl = floorf(d);
     c.f = d - fl;   // exact

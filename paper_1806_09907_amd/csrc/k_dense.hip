@@ -134,6 +134,8 @@ k_dense_pre(const LaunchCtx C, int zc) {
     const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, (uint32_t)(N * 4));
     float cnt = 0.f;   // at most zc per lane: exact in FP32
     if (T.act) {
+        // unrolled so that several planes' loads are in flight per wave
+#pragma unroll 4
         for (int z = T.z0; z < T.z1; ++z) {
             // 3D: plane z of the column; 2D: row group z of the lane
             const int yy = DIM == 3 ? T.y : T.y + z * DTY;
@@ -142,11 +144,11 @@ k_dense_pre(const LaunchCtx C, int zc) {
             const long long vi = ((long long)zz * P.n[1] + yy) * P.n[0] + T.x;
             Disp q[3];
             const int idx[3] = {T.x, yy, zz};
-            bool in = true;
+            int in = 1;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
                 q[a] = disp_of(th[a * N + vi], P.s[a]);
-                if (!axis_cell(idx[a], q[a], P.n[a]).in) in = false;
+                in &= (int)axis_cell(idx[a], q[a], P.n[a]).in;
             }
             if (SIM == AIR_SIM_MSE) {
                 cnt += in ? 1.f : 0.f;
