@@ -281,6 +281,16 @@ air_status air_pyramid_down(const float* in, const int32_t n[3], float sigma, fl
 air_status air_field_resample(const float* in, const int32_t n[3], const int32_t m[3],
                               float* out, void* stream);
 
+/* Bounds checks of the debug build (libairhip_debug.so, compiled with
+ * -DAIR_DEBUG_BOUNDS): the kernels check their computed gather indices
+ * against their buffers and record a violation as a bit instead of reading
+ * out of range (bit 0: fused B-spline moving-image gathers, 1: fixed-image
+ * loads, 2: dense/warp sampler gathers, 3: exponential squaring gathers,
+ * 4: CNN convolution loads, 5: CNN weight-gradient loads). This call waits
+ * for the device, returns the bits set since the last call in *flags and
+ * clears them. The regular library returns AIR_ERR_UNSUPPORTED. */
+air_status air_debug_bounds_take(uint32_t* flags);
+
 /* ---- Learned initialisation CNN (BF16 operands, FP32 accumulation). ----
  * Not part of the paper's method: the paper lists learning-based
  * registration as an upcoming feature (Sec. III-I). A small 3D encoder-

@@ -9,7 +9,10 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libairhip.so")
+# AIRHIP_LIB_VARIANT=debug selects the bounds-checked debug build
+# (libairhip_debug.so, the same entry points).
+LIB_PATH = os.path.join(HERE, "libairhip_debug.so" if os.environ.get("AIRHIP_LIB_VARIANT") == "debug"
+                        else "libairhip.so")
 
 AIR_OK = 0
 STATUS_NAMES = {
@@ -106,13 +109,14 @@ SIGNATURES = {
     "air_plan_timing": (_i32, [_vp, _i32]),
     "air_plan_timing_read": (_i32, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)]),
     "air_strerror": (ctypes.c_char_p, [_i32]),
+    "air_debug_bounds_take": (_i32, [ctypes.POINTER(ctypes.c_uint32)]),
 }
 
 _lib = None
 
 
 def lib():
-    """Load libairhip.so (raises if it has not been built)."""
+    """Load the library (raises if it has not been built)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):

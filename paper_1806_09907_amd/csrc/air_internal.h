@@ -5,8 +5,19 @@
 #include <stdint.h>
 
 #include "../../include/airhip.h"
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 namespace air {
+
+// A roctx range over a host scope: the stages of an evaluation appear as
+// named ranges in a marker trace (rocprofv3 --marker-trace); without a
+// profiler attached the calls return at once.
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 constexpr int kMaxPairs = 4096;
 constexpr int kMaxSpacing = 64;

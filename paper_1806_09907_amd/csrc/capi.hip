@@ -681,8 +681,13 @@ static hipError_t run_diffeo(const air_plan* P, const DeviceTables* T, void* ws,
     const PairDesc& hp = P->pd[0];
     const long long dN = (long long)P->dim * hp.nvox;
     float* uK = nullptr;
-    hipError_t e = diffeo_forward(P, T, w, theta, s, &uK);
+    hipError_t e;
+    {
+        TraceRange r("air.stage.expand_and_squarings");
+        e = diffeo_forward(P, T, w, theta, s, &uK);
+    }
     if (e != hipSuccess) return e;
+    TraceRange r_eval("air.stage.field_evaluation");
     float* g = reinterpret_cast<float*>(w + P->L.gfield);
     float* o = g + dN;
     LaunchCtx C = base_ctx(P, T, ws);
@@ -722,6 +727,7 @@ static hipError_t run_diffeo(const air_plan* P, const DeviceTables* T, void* ws,
                           value, true, s);
     }
     if (e != hipSuccess || !grad) return e;
+    TraceRange r_adj("air.stage.squaring_adjoints_and_field_adjoint");
     const float* U = reinterpret_cast<const float*>(w + P->L.fields);
     unsigned int* reach = reinterpret_cast<unsigned int*>(w + P->L.reach);   // from the forward pass
     for (int k = P->diffeo - 1; k >= 0 && e == hipSuccess; --k) {
@@ -783,11 +789,14 @@ static air_status run_objective(const air_plan* cP, LaunchCtx& C, hipStream_t s)
         return e == hipSuccess ? AIR_OK : AIR_ERR_LAUNCH;
     }
     if (P->transform == AIR_TF_BSPLINE3) {
+        TraceRange r("air.stage.fused_bspline_and_finalize");
         e = launch_bspline(C, P->variant, P->lds_fused, P->max_ctrl, s, e0, e1);
     } else {
+        TraceRange r("air.stage.dense_passes");
         e = launch_dense(C, kDenseZc, P->max_dense_blk, s, e0, e1);
     }
     if (e == hipSuccess && P->reg != AIR_REG_DIFFUSION) {
+        TraceRange r("air.stage.tv");
         DeviceTables T{};
         T.pairs = const_cast<PairDesc*>(C.pairs);
         T.consts = const_cast<float*>(C.consts);
@@ -875,7 +884,28 @@ static int entry_tiling(const std::string& obj) {
     return c == std::string::npos ? -1 : atoi(obj.c_str() + c + 1);
 }
 
+#ifdef AIR_DEBUG_BOUNDS
+namespace air {
+uint32_t debug_take_bspline();
+uint32_t debug_take_dense();
+uint32_t debug_take_diffeo();
+uint32_t debug_take_cnn();
+}  // namespace air
+#endif
+
 extern "C" {
+
+air_status air_debug_bounds_take(uint32_t* flags) {
+    if (!flags) return AIR_ERR_INVALID_ARG;
+    *flags = 0;
+#ifdef AIR_DEBUG_BOUNDS
+    if (hipDeviceSynchronize() != hipSuccess) return AIR_ERR_DEVICE;
+    *flags = debug_take_bspline() | debug_take_dense() | debug_take_diffeo() | debug_take_cnn();
+    return AIR_OK;
+#else
+    return AIR_ERR_UNSUPPORTED;
+#endif
+}
 
 air_status air_plan_create(const air_problem* probs, int32_t npairs, air_plan** out) {
     if (!out) return AIR_ERR_INVALID_ARG;
@@ -1007,6 +1037,7 @@ air_status air_plan_get_tiling(const air_plan* plan, int32_t* id) {
 
 air_status air_warp(const air_plan* plan, int32_t pair, const float* moving, const float* theta,
                     float* warped, uint8_t* mask, void* stream) {
+    TraceRange trace_("air_warp");
     if (!plan || !moving || !theta || !warped) return AIR_ERR_INVALID_ARG;
     if (pair < 0 || pair >= plan->npairs) return AIR_ERR_SHAPE;
     if (plan->expanded()) return AIR_ERR_UNSUPPORTED;
@@ -1023,6 +1054,7 @@ air_status air_warp(const air_plan* plan, int32_t pair, const float* moving, con
 
 air_status air_displacement(const air_plan* plan, int32_t pair, const float* theta, float* u,
                             void* ws, size_t ws_bytes, void* stream) {
+    TraceRange trace_("air_displacement");
     if (!plan || !theta || !u) return AIR_ERR_INVALID_ARG;
     if (pair < 0 || pair >= plan->npairs) return AIR_ERR_SHAPE;
     if (!aligned16(theta) || !aligned16(u)) return AIR_ERR_ALIGN;
@@ -1048,6 +1080,7 @@ air_status air_displacement(const air_plan* plan, int32_t pair, const float* the
 air_status air_similarity(const air_plan* plan, int32_t pair, const float* fixed,
                           const float* warped, const uint8_t* mask, float* value, void* ws,
                           size_t ws_bytes, void* stream) {
+    TraceRange trace_("air_similarity");
     if (!plan || !fixed || !warped || !value) return AIR_ERR_INVALID_ARG;
     if (pair < 0 || pair >= plan->npairs) return AIR_ERR_SHAPE;
     if (!aligned16(fixed) || !aligned16(warped) || (mask && !aligned16(mask)))
@@ -1073,6 +1106,7 @@ air_status air_similarity(const air_plan* plan, int32_t pair, const float* fixed
 
 air_status air_regulariser(const air_plan* plan, int32_t pair, const float* theta, float* value,
                            float* grad, void* ws, size_t ws_bytes, void* stream) {
+    TraceRange trace_("air_regulariser");
     if (!plan || !theta || !value) return AIR_ERR_INVALID_ARG;
     if (pair < 0 || pair >= plan->npairs) return AIR_ERR_SHAPE;
     if (!aligned16(theta) || (grad && !aligned16(grad))) return AIR_ERR_ALIGN;
@@ -1109,6 +1143,7 @@ air_status air_regulariser(const air_plan* plan, int32_t pair, const float* thet
 air_status air_objective_and_grad(const air_plan* plan, const float* fixed, const float* moving,
                                   const float* theta, float* value, float* grad, void* ws,
                                   size_t ws_bytes, void* stream) {
+    TraceRange trace_("air_objective_and_grad");
     if (!plan || !fixed || !moving || !theta || !value || !grad) return AIR_ERR_INVALID_ARG;
     if (plan->npairs != 1) return AIR_ERR_INVALID_ARG;
     if (!aligned16(fixed) || !aligned16(moving) || !aligned16(theta) || !aligned16(grad))
@@ -1130,6 +1165,7 @@ air_status air_objective_and_grad(const air_plan* plan, const float* fixed, cons
 air_status air_objective_and_grad_noalloc(const air_plan* plan, const float* fixed,
                                           const float* moving, const float* theta, float* value,
                                           float* grad, void* stream) {
+    TraceRange trace_("air_objective_and_grad_noalloc");
     if (!plan || !fixed || !moving || !theta || !value || !grad) return AIR_ERR_INVALID_ARG;
     if (plan->npairs != 1) return AIR_ERR_INVALID_ARG;
     if (!aligned16(fixed) || !aligned16(moving) || !aligned16(theta) || !aligned16(grad))
@@ -1154,6 +1190,7 @@ air_status air_objective_and_grad_batched(const air_plan* plan, const float* con
                                           const float* const* moving, const float* const* theta,
                                           float* values, float* const* grads, void* ws,
                                           size_t ws_bytes, void* stream) {
+    TraceRange trace_("air_objective_and_grad_batched");
     if (!plan || !fixed || !moving || !theta || !values || !grads) return AIR_ERR_INVALID_ARG;
     if (plan->field_route() || plan->reg != AIR_REG_DIFFUSION) return AIR_ERR_UNSUPPORTED;
     if (((uintptr_t)fixed | (uintptr_t)moving | (uintptr_t)theta | (uintptr_t)grads) & 7u)
@@ -1198,6 +1235,7 @@ static air_status adam_args(const float* theta, const float* grad, const float* 
 
 air_status air_adam_step(float* theta, const float* grad, float* m, float* v, int64_t n, float lr,
                          float b1, float b2, float eps, int32_t step, void* stream) {
+    TraceRange trace_("air_adam_step");
     air_status st = adam_args(theta, grad, m, v, n, b1, b2, eps);
     if (st != AIR_OK) return st;
     float c[2];
@@ -1209,6 +1247,7 @@ air_status air_adam_step(float* theta, const float* grad, float* m, float* v, in
 
 air_status air_adam_step_dev(float* theta, const float* grad, float* m, float* v, int64_t n,
                              const float* coef, float b1, float b2, float eps, void* stream) {
+    TraceRange trace_("air_adam_step_dev");
     air_status st = adam_args(theta, grad, m, v, n, b1, b2, eps);
     if (st != AIR_OK) return st;
     if (!coef) return AIR_ERR_INVALID_ARG;
@@ -1317,6 +1356,7 @@ air_status air_autotune(air_plan* plan, const float* const* fixed, const float* 
                         const float* const* theta, float* values, float* const* grads, void* ws,
                         size_t ws_bytes, int32_t reps, const char* cache_path, int32_t* chosen,
                         double* kernel_ms, void* stream) {
+    TraceRange trace_("air_autotune");
     if (!plan || !fixed || !moving || !theta || !values || !grads || !chosen) return AIR_ERR_INVALID_ARG;
     if (reps < 1 || reps > 10000) return AIR_ERR_INVALID_ARG;
     if (plan->field_route() || plan->reg != AIR_REG_DIFFUSION || plan->transform != AIR_TF_BSPLINE3)

@@ -228,6 +228,7 @@ air_status air_cnn_layer(const air_cnn* net, int32_t layer, int32_t* cin, int32_
 air_status air_cnn_forward(const air_cnn* N, const float* params, const float* fixed,
                            const float* moving, float* theta0, void* ws, size_t ws_bytes,
                            void* stream) {
+    TraceRange trace_("air_cnn_forward");
     if (!N || !params || !fixed || !moving || !theta0) return AIR_ERR_INVALID_ARG;
     if (!ws || ws_bytes < N->total) return AIR_ERR_WORKSPACE;
     if (((uintptr_t)ws | (uintptr_t)params | (uintptr_t)fixed | (uintptr_t)moving |
@@ -272,6 +273,7 @@ air_status air_cnn_forward(const air_cnn* N, const float* params, const float* f
 
 air_status air_cnn_backward(const air_cnn* N, const float* dtheta, float* grads, void* ws,
                             size_t ws_bytes, void* stream) {
+    TraceRange trace_("air_cnn_backward");
     if (!N || !dtheta || !grads) return AIR_ERR_INVALID_ARG;
     if (!ws || ws_bytes < N->total) return AIR_ERR_WORKSPACE;
     if (((uintptr_t)ws | (uintptr_t)dtheta | (uintptr_t)grads) & 15u) return AIR_ERR_ALIGN;

@@ -21,13 +21,51 @@ __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t by
     return __builtin_amdgcn_make_buffer_rsrc(q, (short)0, (int)nb, 0x00020000);
 }
 
-// Two consecutive floats at byte offset voff + soff (dword aligned).
 // cache-policy operand of the buffer builtins: non-temporal (streamed data)
 constexpr int kNonTemporal = 2;
 
+// Two consecutive floats at byte offset voff + soff (dword aligned).
 __device__ inline v2f load2(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
     return __builtin_bit_cast(v2f, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
+
+// Bounds checks of computed indices, compiled in the debug build
+// (-DAIR_DEBUG_BOUNDS, libairhip_debug.so) and empty otherwise. A failed
+// check sets its bit in the flag word of its translation unit (a buffer
+// load out of range would silently read zero, a global one could fault);
+// air_debug_bounds_take reads and clears every unit's word. Bits:
+enum DebugBit : unsigned {
+    kDbgMovingGather = 0,   // fused B-spline kernels: moving-image corner gathers
+    kDbgFixedLoad = 1,      // fused B-spline kernels: fixed-image loads
+    kDbgSampler = 2,        // dense / warp samplers: corner gathers
+    kDbgCompose = 3,        // exponential: squaring gathers
+    kDbgConvInput = 4,      // CNN convolutions: input and weight loads
+    kDbgConvWgrad = 5,      // CNN weight gradient: operand loads
+};
+#ifdef AIR_DEBUG_BOUNDS
+static __device__ unsigned int air_dbg_flags;
+#define AIR_CHECK(cond, bit)                                                 \
+    do {                                                                     \
+        if (!(cond)) atomicOr(&air_dbg_flags, 1u << (unsigned)(bit));       \
+    } while (0)
+// defines air::debug_take_<name>(): this unit's flags, cleared
+#define AIR_DEBUG_UNIT(name)                                                 \
+    namespace air {                                                          \
+    uint32_t debug_take_##name() {                                           \
+        unsigned int v = 0, z = 0;                                           \
+        if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(air_dbg_flags), sizeof(v)) != \
+            hipSuccess)                                                      \
+            return 0x80000000u;                                              \
+        (void)hipMemcpyToSymbol(HIP_SYMBOL(air_dbg_flags), &z, sizeof(z));   \
+        return v;                                                            \
+    }                                                                        \
+    }
+#else
+#define AIR_CHECK(cond, bit) \
+    do {                     \
+    } while (0)
+#define AIR_DEBUG_UNIT(name)
+#endif
 
 template <typename T>
 __device__ inline T wave_sum(T v) {

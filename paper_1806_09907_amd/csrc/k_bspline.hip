@@ -318,6 +318,8 @@ k_fused3(const LaunchCtx C) {
                     const int jz = ez ? nz - 2 : az.t;
                     const float fx = ex ? 1.f : ax.f, fy = ey ? 1.f : ay.f, fz = ez ? 1.f : az.f;
                     const int off = ((jz * ny + jy) * nx + jx) * 4;
+                    AIR_CHECK(off >= 0 && (long long)off + nxy4 + nx4 + 8 <= P.nvox * 4,
+                              kDbgMovingGather);
                     const v2f a00 = load2(rM, off, 0);
                     const v2f a10 = load2(rM, off, nx4);
                     const v2f a01 = load2(rM, off, nxy4);
@@ -649,6 +651,8 @@ k_fused3_s8(const LaunchCtx C) {
         Prep q;
         // F through its buffer descriptor: the lane's offset is fixed, the
         // plane's is a scalar (streamed once: non-temporal)
+        AIR_CHECK((long long)fl4 + (long long)min(z, nz - 1) * nxy4 + 4 <= P.nvox * 4,
+                  kDbgFixedLoad);
         q.Fv = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
                                              rF, fl4, min(z, nz - 1) * nxy4, kNonTemporal));
         float w0 = kW8.w[r][0], w1 = kW8.w[r][1], w2 = kW8.w[r][2], w3 = kW8.w[r][3];
@@ -699,6 +703,7 @@ k_fused3_s8(const LaunchCtx C) {
         const int rows = (int)fmaf(clz, nyf, cly);
         const int off = (int)((unsigned)(__mul24(rows, nx) + (int)clx) * 4u + (unsigned)lane4 +
                               (unsigned)z * (unsigned)nxy4);
+        AIR_CHECK(off >= 0 && (long long)off + nxy4 + nx4 + 8 <= P.nvox * 4, kDbgMovingGather);
         q.a00 = load2(rM, off, 0);
         q.a10 = load2(rM, off, nx4);
         q.a01 = load2(rM, off, nxy4);
@@ -959,6 +964,8 @@ k_fused2(const LaunchCtx C) {
                     const int jx = ex ? nx - 2 : ax.t, jy = ey ? ny - 2 : ay.t;
                     const float fx = ex ? 1.f : ax.f, fy = ey ? 1.f : ay.f;
                     const int off = (jy * nx + jx) * 4;
+                    AIR_CHECK(off >= 0 && (long long)off + nx4 + 8 <= P.nvox * 4,
+                              kDbgMovingGather);
                     const v2f a0 = load2(rM, off, 0);
                     const v2f a1 = load2(rM, off, nx4);
                     const float dy0 = a1.x - a0.x, dy1 = a1.y - a0.y;
@@ -1405,3 +1412,6 @@ hipError_t launch_reg_bspline(const PairDesc* dpairs, const PairDesc& hp, int pa
 }
 
 }  // namespace air
+
+// this unit's bounds-check flags (debug build only)
+AIR_DEBUG_UNIT(bspline)

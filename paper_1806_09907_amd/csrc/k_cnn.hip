@@ -119,6 +119,8 @@ __device__ inline bf16x8 load_a(const u16* __restrict__ X, const ConvDims& D, co
     uint4 q = make_uint4(0, 0, 0, 0);
     if (in) {
         const long long v = ((long long)(p.z + dz) * D.ny + y) * D.nx + x;
+        AIR_CHECK(v >= 0 && v < (long long)D.nx * D.ny * D.nz && ci >= 0 && ci + 8 <= D.cin,
+                  kDbgConvInput);
         q = *reinterpret_cast<const uint4*>(X + v * D.cin + ci);
     }
     return __builtin_bit_cast(bf16x8, q);
@@ -126,6 +128,7 @@ __device__ inline bf16x8 load_a(const u16* __restrict__ X, const ConvDims& D, co
 
 __device__ inline bf16x8 load_w(const u16* __restrict__ Wt, const ConvDims& D, int co, int k) {
     uint4 q = make_uint4(0, 0, 0, 0);
+    AIR_CHECK(co >= D.cout || k >= D.K || (co >= 0 && k >= 0 && k + 8 <= D.K), kDbgConvInput);
     if (co < D.cout && k < D.K) q = *reinterpret_cast<const uint4*>(Wt + (long long)co * D.K + k);
     return __builtin_bit_cast(bf16x8, q);
 }
@@ -216,9 +219,11 @@ k_conv_fwd_brick(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ 
             const int x = x0 + hx - 1, y = y0 + hy - 1, zl = zb + hz - 1;
             uint4 q = make_uint4(0, 0, 0, 0);
             if ((unsigned)x < (unsigned)D.nx && (unsigned)y < (unsigned)D.ny &&
-                (unsigned)zl < (unsigned)D.nzv)
+                (unsigned)zl < (unsigned)D.nzv) {
+                AIR_CHECK(zv0 + zl < D.nz && ci0 + 8 * c8 + 8 <= D.cin, kDbgConvInput);
                 q = *reinterpret_cast<const uint4*>(
                     X + (((long long)(zv0 + zl) * D.ny + y) * D.nx + x) * D.cin + ci0 + 8 * c8);
+            }
             *reinterpret_cast<uint4*>(tile + v * CS + 8 * c8) = q;
         }
         __syncthreads();
@@ -557,8 +562,10 @@ k_conv_bwdw_xb(const u16* __restrict__ XB, ConvDims D, int cu, const u16* __rest
         for (int c = 0; c < CT; ++c) {
             const int co = 16 * c + r;
             qa[c] = make_uint4(0, 0, 0, 0);
-            if (ok && co < D.cout)
+            if (ok && co < D.cout) {
+                AIR_CHECK(blk * C8out + (long long)co * 8 + 8 <= N * D.cout, kDbgConvWgrad);
                 qa[c] = *reinterpret_cast<const uint4*>(dYB + blk * C8out + (long long)co * 8);
+            }
         }
 #pragma unroll
         for (int t = 0; t < BWK; ++t) {
@@ -570,11 +577,17 @@ k_conv_bwdw_xb(const u16* __restrict__ XB, ConvDims D, int cu, const u16* __rest
                             (unsigned)(zl + dz) < (unsigned)D.nzv;
             if (in) {
                 const u16* p = XB + blk * C8in + toff[t];
+                AIR_CHECK(blk * C8in + toff[t] >= 0 && blk * C8in + toff[t] + 8 <= N * D.cin,
+                          kDbgConvWgrad);
                 qv[t] = *reinterpret_cast<const uint4*>(p);
                 // dx = +1: element 0 of the next block; dx = -1: element 7 of
                 // the previous one (the high half of its last dword)
-                if (dx != 0 && (unsigned)(xb + dx) < (unsigned)nxb)
+                if (dx != 0 && (unsigned)(xb + dx) < (unsigned)nxb) {
+                    AIR_CHECK(blk * C8in + toff[t] + dx * C8in + (dx > 0 ? 0 : 6) >= 0 &&
+                                  blk * C8in + toff[t] + dx * C8in + 8 <= N * D.cin,
+                              kDbgConvWgrad);
                     qn[t] = *reinterpret_cast<const uint32_t*>(p + dx * (int)C8in + (dx > 0 ? 0 : 6));
+                }
             }
         }
         bf16x8 a[CT];
@@ -1508,3 +1521,6 @@ air_status air_add_f32(float* a, const float* b, int64_t n, void* stream) {
 }
 
 }  // extern "C"
+
+// this unit's bounds-check flags (debug build only)
+AIR_DEBUG_UNIT(cnn)

@@ -88,6 +88,8 @@ __device__ inline Gather3 sample3_issue(__amdgpu_buffer_rsrc_t rM, int x, int y,
     g.fz = g.ez ? 1.f : cz.f;
     const int off = (int)(__umul24(__umul24(jz, ny) + jy, nx) + jx) * 4;
     const int sx4 = nx * 4, sxy4 = nx * ny * 4;
+    AIR_CHECK(off >= 0 && (long long)off + sxy4 + sx4 + 8 <= (long long)nx * ny * nz * 4,
+              kDbgSampler);
     g.a00 = load2(rM, off, 0);
     g.a10 = load2(rM, off, sx4);
     g.a01 = load2(rM, off, sxy4);
@@ -811,3 +813,6 @@ hipError_t launch_scale(float* x, const float* s, long long n, hipStream_t st) {
 }
 
 }  // namespace air
+
+// this unit's bounds-check flags (debug build only)
+AIR_DEBUG_UNIT(dense)

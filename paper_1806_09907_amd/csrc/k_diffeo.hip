@@ -73,6 +73,8 @@ __device__ inline bool field_sample(const float* __restrict__ u, long long N, co
         const int nx = P.n[0], ny = P.n[1];
         const int off = ((DIM == 3 ? j[2] * ny : 0) + j[1]) * nx * 4 + j[0] * 4;  // N * 4 < 2^31
         const int sx4 = nx * 4, sxy4 = nx * ny * 4;
+        AIR_CHECK(off >= 0 && (long long)off + (DIM == 3 ? sxy4 : 0) + sx4 + 8 <= N * 4,
+                  kDbgCompose);
         const float fx = f[0], fy = f[1], fz = DIM == 3 ? f[2] : 0.f;
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
@@ -612,3 +614,6 @@ hipError_t launch_velocity_adjoint(const PairDesc& P, const float* consts_dev, i
 }
 
 }  // namespace air
+
+// this unit's bounds-check flags (debug build only)
+AIR_DEBUG_UNIT(diffeo)

@@ -100,6 +100,7 @@ air_status air_pyramid_workspace_bytes(const int32_t n[3], size_t* bytes) {
 
 air_status air_pyramid_down(const float* in, const int32_t n[3], float sigma, float* out,
                             void* ws, size_t ws_bytes, void* stream) {
+    TraceRange trace_("air_pyramid_down");
     if (!in || !n || !out) return AIR_ERR_INVALID_ARG;
     if (!(sigma > 0.f) || (int)ceilf(3.f * sigma) * 2 + 1 > kMaxTaps) return AIR_ERR_INVALID_ARG;
     size_t need = 0;
@@ -132,6 +133,7 @@ air_status air_pyramid_down(const float* in, const int32_t n[3], float sigma, fl
 
 air_status air_field_resample(const float* in, const int32_t n[3], const int32_t m[3], float* out,
                               void* stream) {
+    TraceRange trace_("air_field_resample");
     if (!in || !n || !m || !out) return AIR_ERR_INVALID_ARG;
     for (int a = 0; a < 3; ++a)
         if (n[a] < 2 || m[a] < 1) return AIR_ERR_SHAPE;

@@ -266,3 +266,14 @@ def test_cnn_object_layout():
     assert L.air_cnn_forward(h, C.c_void_p(256), C.c_void_p(256), C.c_void_p(256),
                              C.c_void_p(256), None, 0, None) == 4
     L.air_cnn_destroy(h)
+
+
+def test_debug_bounds_entry_in_the_release_build():
+    """The regular library exports the debug-build query and answers that it
+    is not the debug build, with cleared flags."""
+    import ctypes as C
+    L = _lib.lib()
+    f = C.c_uint32(7)
+    assert L.air_debug_bounds_take(C.byref(f)) == 5      # AIR_ERR_UNSUPPORTED
+    assert f.value == 0
+    assert L.air_debug_bounds_take(None) == 1            # AIR_ERR_INVALID_ARG

@@ -5,7 +5,7 @@ import torch
 
 import oracle as O
 from paper_1806_09907_amd import api, synth
-from paper_1806_09907_amd.registration import Registration, pyramid_register
+from paper_1806_09907_amd.registration import Registration, RegistrationState, pyramid_register
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -76,6 +76,30 @@ def test_graph_replay_matches_eager_loop(dim, iters, chunk):
     # a second graph run on the same driver object replays a fresh capture
     again = Registration(prob, F, M, lr=0.01, iterations=iters).run(graph_chunk=chunk)
     assert torch.equal(again.theta, eager.theta)
+
+
+@pytest.mark.parametrize("chunk", [0, 5])
+def test_checkpoint_resume_is_bitwise(tmp_path, chunk):
+    """A registration stopped after 15 iterations, saved to an .npz
+    checkpoint (parameters, Adam moments, step count), loaded and continued
+    for 15 more ends exactly where 30 uninterrupted iterations do, eagerly
+    and as graph replays; the continued run's objective values are the
+    uninterrupted run's last 15."""
+    print(f"case checkpoint resume chunk={chunk}", flush=True)
+    pair = synth.pair_2d(warp=O.warp_fn_fp32)
+    prob = api.Problem(n=(64, 64), spacing=(8, 8), similarity=api.SIM_MSE, lambda_diff=0.1)
+    F, M = gpu(pair.fixed), gpu(pair.moving)
+    whole = Registration(prob, F, M, lr=0.01, iterations=30).run(graph_chunk=chunk)
+    first = Registration(prob, F, M, lr=0.01, iterations=15).run(graph_chunk=chunk)
+    path = str(tmp_path / "state.npz")
+    first.state().save(path)
+    st = RegistrationState.load(path)
+    assert st.step == 15 and st.level == 0
+    rest = Registration(prob, F, M, lr=0.01, iterations=15).run(graph_chunk=chunk, resume=st)
+    assert rest.step == 30
+    assert torch.equal(rest.theta, whole.theta)
+    assert torch.equal(rest.m, whole.m) and torch.equal(rest.v, whole.v)
+    assert torch.equal(rest.objective, whole.objective[15:])
 
 
 def test_3d_blob_registration_ncc_improves():

@@ -66,7 +66,8 @@ def test_capi_host_code_under_asan_ubsan(tmp_path):
         assert rc == 0, out
     lib = str(tmp_path / "libairhip_asan.so")
     rc, out = run([HIPCC, "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address",
-                   "-Xarch_host", "-fsanitize=undefined", *[o for _, _, o in res], "-o", lib])
+                   "-Xarch_host", "-fsanitize=undefined", *[o for _, _, o in res], "-o", lib,
+                   "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"])
     assert rc == 0, out
     exe = str(tmp_path / "capi_asan")
     rc, out = run([CLANG, "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
