@@ -12,6 +12,15 @@ namespace air {
 // A roctx range over a host scope: the stages of an evaluation appear as
 // named ranges in a marker trace (rocprofv3 --marker-trace); without a
 // profiler attached the calls return at once.
+// The network's first-layer convolution (channels 2.. of its 8 input
+// channels zero) on 16 x 4 x 4 bricks; returns false when the shape does not
+// allow it (the caller then uses air_conv3d_fwd), else launches on `s` and
+// stores the launch status in *err.
+bool conv3d_fwd_in2(const uint16_t* x, const int32_t dims[3], int32_t batch,
+                    const uint16_t* wt, const float* bias, int32_t cout, int32_t act,
+                    uint16_t* y_bf16, int32_t ldy, float* y_f32, int32_t ldyf, hipStream_t s,
+                    hipError_t* err);
+
 struct TraceRange {
     explicit TraceRange(const char* name) { roctxRangePushA(name); }
     ~TraceRange() { roctxRangePop(); }

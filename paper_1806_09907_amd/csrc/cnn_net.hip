@@ -258,7 +258,16 @@ air_status air_cnn_forward(const air_cnn* N, const float* params, const float* f
                               kDef[l].cout, stream);
     };
     AIR_TRY(air_cnn_input(fixed, moving, full, b16(N->x0), b16(N->x0_xb), stream));
-    AIR_TRY(conv(b16(N->x0), H, 0, b16(N->a1), 16, nullptr));
+    {
+        // the first layer reads only the two data channels of x0
+        hipError_t err = hipSuccess;
+        if (conv3d_fwd_in2(b16(N->x0), H, B, b16(N->wb[0]), params + N->b_off[0], 16, 1,
+                           b16(N->a1), 16, nullptr, 16, s, &err)) {
+            if (err != hipSuccess) return AIR_ERR_LAUNCH;
+        } else {
+            AIR_TRY(conv(b16(N->x0), H, 0, b16(N->a1), 16, nullptr));
+        }
+    }
     AIR_TRY(air_pool2(b16(N->a1), Hs, 16, 16, 0, b16(N->p1), stream));
     AIR_TRY(conv(b16(N->p1), Q, 1, b16(N->a2), 32, nullptr));
     AIR_TRY(air_pool2(b16(N->a2), Qs, 32, 32, 0, b16(N->p2), stream));

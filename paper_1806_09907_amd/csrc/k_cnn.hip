@@ -269,6 +269,93 @@ k_conv_fwd_brick(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ 
     }
 }
 
+// Brick form for an input whose channels 2.. are zero (the network's first
+// layer: fixed and moving image, six zero pads): only channels 0 and 1 are
+// staged (4 bytes per voxel) and the reduction runs over kk = tap * 2 + c,
+// 54 columns in two 32-wide steps instead of 216 in seven; an operand's 8
+// columns are 4 taps x 2 channels (four 4-byte LDS reads), the weights'
+// the matching 4 x 2 entries of Wt[co][tap * cin + c]. The zero channels'
+// products are exact zeros, so the sum is the full convolution's.
+template <int NT16>
+__global__ void __launch_bounds__(256)
+k_conv_fwd_brick_in2(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ Wt,
+                     ConvEpi E) {
+    __shared__ __align__(16) uint32_t tile[kHaZ * kHaY * kHaX];   // (c0, c1) per voxel
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    const int bx = D.nx / kBrX, by = D.ny / kBrY, bzv = D.nzv / kBrZ;
+    int b = blockIdx.x;
+    const int x0 = (b % bx) * kBrX; b /= bx;
+    const int y0 = (b % by) * kBrY; b /= by;
+    const int zb = (b % bzv) * kBrZ, vol = b / bzv;
+    const int zv0 = vol * D.nzv;
+    for (int i = threadIdx.x; i < kHaZ * kHaY * kHaX; i += 256) {
+        const int hx = i % kHaX, hy = (i / kHaX) % kHaY, hz = i / (kHaX * kHaY);
+        const int x = x0 + hx - 1, y = y0 + hy - 1, zl = zb + hz - 1;
+        uint32_t q = 0;
+        if ((unsigned)x < (unsigned)D.nx && (unsigned)y < (unsigned)D.ny &&
+            (unsigned)zl < (unsigned)D.nzv) {
+            AIR_CHECK(zv0 + zl < D.nz, kDbgConvInput);
+            q = *reinterpret_cast<const uint32_t*>(
+                X + (((long long)(zv0 + zl) * D.ny + y) * D.nx + x) * D.cin);
+        }
+        tile[i] = q;
+    }
+    __syncthreads();
+    f32x4 acc[kBrY][NT16];
+#pragma unroll
+    for (int t = 0; t < kBrY; ++t)
+#pragma unroll
+        for (int j = 0; j < NT16; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < 64; kc += 32) {
+        // this lane group's taps t0 .. t0 + 3 (27 and beyond: zero columns)
+        const int t0 = (kc + 8 * g) / 2;
+        bf16x8 a[kBrY];
+#pragma unroll
+        for (int t = 0; t < kBrY; ++t) {
+            uint32_t w[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int tap = t0 + i;
+                const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // halo offsets
+                w[i] = tap < 27 ? tile[((wave + dz) * kHaY + t + dy) * kHaX + r + dx] : 0u;
+            }
+            a[t] = __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
+        }
+#pragma unroll
+        for (int j = 0; j < NT16; ++j) {
+            const int co = j * 16 + r;
+            uint32_t w[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int tap = t0 + i;
+                w[i] = (co < D.cout && tap < 27)
+                           ? *reinterpret_cast<const uint32_t*>(Wt + (long long)co * D.K + tap * D.cin)
+                           : 0u;
+            }
+            const bf16x8 bw = __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
+#pragma unroll
+            for (int t = 0; t < kBrY; ++t)
+                acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], bw, acc[t][j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NT16; ++j) {
+        const int co = j * 16 + r;
+        if (co >= D.cout) continue;
+        const float bias = E.bias ? E.bias[co] : 0.f;
+#pragma unroll
+        for (int t = 0; t < kBrY; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long long row = (((long long)(zv0 + zb + wave) * D.ny + y0 + t) * D.nx) + x0 +
+                                      4 * g + i;
+                conv_store(E, row, co, acc[t][j][i], bias);
+            }
+    }
+}
+
 // Split-K form for small volumes (too few blocks of the forms above to
 // fill the chip): a block takes MT tiles of 16 voxels, its four waves take
 // every fourth 32-wide reduction step (each weight operand a wave loads
@@ -475,15 +562,24 @@ k_conv_bwdw(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ dY, i
 // block shifted by (dy, dz); a tap with dx = +-1 takes one more dword from
 // the neighbouring block and a funnel shift by one element (v_alignbyte).
 
-// XB[b][c][j] = X[voxel 8b + j][off + c] for c < C (8x8 transposes in registers)
+// XB[b][c][j] = X[voxel 8b + j][c] for c < C (8x8 transposes in registers),
+// for two tensors with the same voxels in one launch: items [0, nblk C0/8)
+// transpose X0 (C0 channels), the rest X1 (C1 channels)
 __global__ void __launch_bounds__(kBlock)
-k_to_xb(const u16* __restrict__ X, long long nblk, int C, int ld, int off, u16* __restrict__ XB) {
-    const int C8 = C / 8;
-    const long long total = nblk * C8;
+k_to_xb(const u16* __restrict__ X0, int C0, u16* __restrict__ XB0, const u16* __restrict__ X1,
+        int C1, u16* __restrict__ XB1, long long nblk) {
+    const long long n0 = nblk * (C0 / 8);
+    const long long total = n0 + nblk * (C1 / 8);
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total;
          i += (long long)gridDim.x * kBlock) {
-        const int cg = (int)(i % C8);
-        const long long b = i / C8;
+        const bool second = i >= n0;
+        const u16* X = second ? X1 : X0;
+        u16* XB = second ? XB1 : XB0;
+        const int C = second ? C1 : C0, ld = C, off = 0;
+        const long long k = second ? i - n0 : i;
+        const int C8 = C / 8;
+        const int cg = (int)(k % C8);
+        const long long b = k / C8;
         uint32_t w[8][4];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -1139,6 +1235,34 @@ k_add_f32(float* __restrict__ a, const float* __restrict__ b, long long n) {
         a[i] += b[i];
 }
 
+// the first layer's convolution over 8 channels of which only 0 and 1 carry
+// data (whole 16 x 4 x 4 bricks; see k_conv_fwd_brick_in2); false: not this shape
+bool conv3d_fwd_in2(const uint16_t* x, const int32_t dims[3], int32_t batch,
+                    const uint16_t* wt, const float* bias, int32_t cout, int32_t act,
+                    uint16_t* y_bf16, int32_t ldy, float* y_f32, int32_t ldyf, hipStream_t s,
+                    hipError_t* err) {
+    if (dims[0] % kBrX || dims[1] % kBrY || dims[2] % kBrZ || cout < 1 || cout > 64 || batch < 1)
+        return false;
+    const long long nz = (long long)dims[2] * batch;
+    const long long nbrick = (long long)(dims[0] / kBrX) * (dims[1] / kBrY) * (nz / kBrZ);
+    if (nz > (1LL << 30) || nbrick >= 0x7fffffffLL) return false;
+    ConvDims D{dims[0], dims[1], (int)nz, dims[2], 8, cout, 27 * 8, 27 * 8 + 8};
+    ConvEpi E{bias, act, nullptr, 0, 0, (u16*)y_bf16, ldy, 0, y_f32, ldyf};
+    const dim3 grid((unsigned)nbrick), blk(256);
+    switch ((cout + 15) / 16) {
+        case 1: hipLaunchKernelGGL(k_conv_fwd_brick_in2<1>, grid, blk, 0, s, (const u16*)x, D,
+                                   (const u16*)wt, E); break;
+        case 2: hipLaunchKernelGGL(k_conv_fwd_brick_in2<2>, grid, blk, 0, s, (const u16*)x, D,
+                                   (const u16*)wt, E); break;
+        case 3: hipLaunchKernelGGL(k_conv_fwd_brick_in2<3>, grid, blk, 0, s, (const u16*)x, D,
+                                   (const u16*)wt, E); break;
+        default: hipLaunchKernelGGL(k_conv_fwd_brick_in2<4>, grid, blk, 0, s, (const u16*)x, D,
+                                    (const u16*)wt, E); break;
+    }
+    *err = hipGetLastError();
+    return true;
+}
+
 static int grid1(long long n) {
     long long b = (n + kBlock - 1) / kBlock;
     return (int)(b < 16384 ? b : 16384);
@@ -1283,10 +1407,8 @@ air_status air_conv3d_bwd_weight(const uint16_t* x, const int32_t dims[3], int32
     u16* XB = reinterpret_cast<u16*>(static_cast<unsigned char*>(ws) + pb);
     u16* dYB = XB + ((2 * N * cin + 255) & ~255LL) / 2;
     const long long nblk = N / 8;
-    hipLaunchKernelGGL(k_to_xb, dim3(grid1(nblk * (cin / 8))), dim3(kBlock), 0, s, (const u16*)x,
-                       nblk, (int)cin, (int)cin, 0, XB);
-    hipLaunchKernelGGL(k_to_xb, dim3(grid1(nblk * (cout / 8))), dim3(kBlock), 0, s, (const u16*)dy,
-                       nblk, (int)cout, (int)cout, 0, dYB);
+    hipLaunchKernelGGL(k_to_xb, dim3(grid1(nblk * ((cin + cout) / 8))), dim3(kBlock), 0, s,
+                       (const u16*)x, (int)cin, XB, (const u16*)dy, (int)cout, dYB, nblk);
     return air_conv3d_bwd_weight_xb(XB, dims, batch, cin, 0, dYB, cout, chunk, dwt, db, ws, pb,
                                     stream);
 }
