@@ -94,6 +94,59 @@ __device__ inline void conv_store(const ConvEpi& E, long long row, int co, float
     if (E.yf) E.yf[row * E.ldyf + co] = v;
 }
 
+// Epilogue of the brick forms through LDS: the wave's 4 x 16 output voxels
+// x 16 NT16 channels, with bias (and act 1) applied, are staged as FP32 rows
+// of kEpiPitch(NT16) floats, then every lane writes whole 8-channel vectors
+// (16 bytes of bf16 and/or 32 bytes of FP32; act 2 multiplies by the
+// activation slopes read as 16-byte gate vectors). Needs ldy, yoff, ldyf,
+// ldg, goff multiples of 8 and 16-byte aligned outputs (checked by the host).
+__host__ __device__ constexpr int kEpiPitch(int nt16) { return nt16 * 16 + 4; }
+
+template <int NT16>
+__device__ inline void brick_epilogue(const ConvEpi& E, const ConvDims& D, const f32x4 (&acc)[4][NT16],
+                                      float* stage, long long row0, int lane) {
+    constexpr int CP = kEpiPitch(NT16);
+    const int g = lane >> 4, r = lane & 15;
+#pragma unroll
+    for (int j = 0; j < NT16; ++j) {
+        const int co = j * 16 + r;
+        const float b = (co < D.cout && E.bias) ? E.bias[co] : 0.f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float v = acc[t][j][i] + b;
+                if (E.act == 1) v = v > 0.f ? v : 0.1f * v;
+                stage[(t * 16 + 4 * g + i) * CP + co] = v;   // voxel (row t, x 4g + i)
+            }
+    }
+    __syncthreads();   // every thread of the block calls this
+    const int C8 = (D.cout + 7) / 8;
+    for (int it = lane; it < 64 * C8; it += 64) {
+        const int lv = it / C8, c8 = it - lv * C8;
+        if (8 * c8 >= D.cout) continue;
+        const long long row = row0 + (long long)(lv >> 4) * D.nx + (lv & 15);
+        float v[8];
+        const float4 lo = *reinterpret_cast<const float4*>(stage + lv * CP + 8 * c8);
+        const float4 hi = *reinterpret_cast<const float4*>(stage + lv * CP + 8 * c8 + 4);
+        v[0] = lo.x; v[1] = lo.y; v[2] = lo.z; v[3] = lo.w;
+        v[4] = hi.x; v[5] = hi.y; v[6] = hi.z; v[7] = hi.w;
+        if (E.act == 2) {
+            float a[8];
+            unpack8(*reinterpret_cast<const uint4*>(E.gate + row * E.ldg + E.goff + 8 * c8), a);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = a[k] > 0.f ? v[k] : 0.1f * v[k];
+        }
+        if (E.ybf)
+            *reinterpret_cast<uint4*>(E.ybf + row * E.ldy + E.yoff + 8 * c8) = pack8(v);
+        if (E.yf) {
+            float* o = E.yf + row * E.ldyf + 8 * c8;
+            *reinterpret_cast<float4*>(o) = make_float4(v[0], v[1], v[2], v[3]);
+            *reinterpret_cast<float4*>(o + 4) = make_float4(v[4], v[5], v[6], v[7]);
+        }
+    }
+}
+
 // output voxel of one lane: stack coordinates and the depth within its volume
 struct Vox {
     int x, y, z, zl;
@@ -195,7 +248,11 @@ constexpr int kHaX = kBrX + 2, kHaY = kBrY + 2, kHaZ = kBrZ + 2;
 template <int NT16, int CS>
 __global__ void __launch_bounds__(256)
 k_conv_fwd_brick(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ Wt, ConvEpi E) {
-    __shared__ __align__(16) u16 tile[kHaZ * kHaY * kHaX * CS];
+    // the input tile, and afterwards the four waves' epilogue stages
+    constexpr int kTileBytes = kHaZ * kHaY * kHaX * CS * 2;
+    constexpr int kEpiBytes = 4 * 64 * kEpiPitch(NT16) * 4;
+    __shared__ __align__(16) unsigned char lds[kTileBytes > kEpiBytes ? kTileBytes : kEpiBytes];
+    u16* tile = reinterpret_cast<u16*>(lds);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r = lane & 15;
     // brick coordinates: x fastest, then y, then z within the volume, then volume
@@ -252,21 +309,11 @@ k_conv_fwd_brick(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ 
             }
         }
     }
-#pragma unroll
-    for (int j = 0; j < NT16; ++j) {
-        const int co = j * 16 + r;
-        if (co >= D.cout) continue;
-        const float bias = E.bias ? E.bias[co] : 0.f;
-#pragma unroll
-        for (int t = 0; t < kBrY; ++t)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                // D rows 4g + i: voxel x0 + 4g + i of row (y0 + t, plane zb + wave)
-                const long long row = (((long long)(zv0 + zb + wave) * D.ny + y0 + t) * D.nx) + x0 +
-                                      4 * g + i;
-                conv_store(E, row, co, acc[t][j][i], bias);
-            }
-    }
+    __syncthreads();   // every wave is done with the tile
+    // D rows 4g + i of tile t: voxel x0 + 4g + i of row (y0 + t, plane zb + wave)
+    brick_epilogue<NT16>(E, D, acc,
+                         reinterpret_cast<float*>(lds) + wave * 64 * kEpiPitch(NT16),
+                         ((long long)(zv0 + zb + wave) * D.ny + y0) * D.nx + x0, lane);
 }
 
 // Brick form for an input whose channels 2.. are zero (the network's first
@@ -280,7 +327,11 @@ template <int NT16>
 __global__ void __launch_bounds__(256)
 k_conv_fwd_brick_in2(const u16* __restrict__ X, ConvDims D, const u16* __restrict__ Wt,
                      ConvEpi E) {
-    __shared__ __align__(16) uint32_t tile[kHaZ * kHaY * kHaX];   // (c0, c1) per voxel
+    // the input tile (c0, c1) per voxel, then the waves' epilogue stages
+    constexpr int kEpiBytes = 4 * 64 * kEpiPitch(NT16) * 4;
+    __shared__ __align__(16) unsigned char lds[kEpiBytes > kHaZ * kHaY * kHaX * 4
+                                                   ? kEpiBytes : kHaZ * kHaY * kHaX * 4];
+    uint32_t* tile = reinterpret_cast<uint32_t*>(lds);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r = lane & 15;
     const int bx = D.nx / kBrX, by = D.ny / kBrY, bzv = D.nzv / kBrZ;
@@ -340,20 +391,10 @@ k_conv_fwd_brick_in2(const u16* __restrict__ X, ConvDims D, const u16* __restric
                 acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], bw, acc[t][j], 0, 0, 0);
         }
     }
-#pragma unroll
-    for (int j = 0; j < NT16; ++j) {
-        const int co = j * 16 + r;
-        if (co >= D.cout) continue;
-        const float bias = E.bias ? E.bias[co] : 0.f;
-#pragma unroll
-        for (int t = 0; t < kBrY; ++t)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const long long row = (((long long)(zv0 + zb + wave) * D.ny + y0 + t) * D.nx) + x0 +
-                                      4 * g + i;
-                conv_store(E, row, co, acc[t][j][i], bias);
-            }
-    }
+    __syncthreads();   // every wave is done with the tile
+    brick_epilogue<NT16>(E, D, acc,
+                         reinterpret_cast<float*>(lds) + wave * 64 * kEpiPitch(NT16),
+                         ((long long)(zv0 + zb + wave) * D.ny + y0) * D.nx + x0, lane);
 }
 
 // Split-K form for small volumes (too few blocks of the forms above to
@@ -1235,19 +1276,32 @@ k_add_f32(float* __restrict__ a, const float* __restrict__ b, long long n) {
         a[i] += b[i];
 }
 
+// the brick forms' epilogue stores whole 8-channel vectors: channel counts,
+// strides and offsets in multiples of 8 elements, 16-byte aligned tensors
+static bool vector_epilogue_ok(const ConvEpi& E, int cout) {
+    auto al = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
+    if (cout % 8) return false;
+    if (E.ybf && (E.ldy % 8 || E.yoff % 8 || !al(E.ybf))) return false;
+    if (E.yf && (E.ldyf % 8 || !al(E.yf))) return false;
+    if (E.act == 2 && (!E.gate || E.ldg % 8 || E.goff % 8 || !al(E.gate))) return false;
+    return true;
+}
+
 // the first layer's convolution over 8 channels of which only 0 and 1 carry
 // data (whole 16 x 4 x 4 bricks; see k_conv_fwd_brick_in2); false: not this shape
 bool conv3d_fwd_in2(const uint16_t* x, const int32_t dims[3], int32_t batch,
                     const uint16_t* wt, const float* bias, int32_t cout, int32_t act,
                     uint16_t* y_bf16, int32_t ldy, float* y_f32, int32_t ldyf, hipStream_t s,
                     hipError_t* err) {
-    if (dims[0] % kBrX || dims[1] % kBrY || dims[2] % kBrZ || cout < 1 || cout > 64 || batch < 1)
+    if (dims[0] % kBrX || dims[1] % kBrY || dims[2] % kBrZ || cout < 1 || cout > 64 || batch < 1 ||
+        act < 0 || act > 1 || (!y_bf16 && !y_f32) || ((uintptr_t)x & 15) || ((uintptr_t)wt & 3))
         return false;
     const long long nz = (long long)dims[2] * batch;
     const long long nbrick = (long long)(dims[0] / kBrX) * (dims[1] / kBrY) * (nz / kBrZ);
     if (nz > (1LL << 30) || nbrick >= 0x7fffffffLL) return false;
     ConvDims D{dims[0], dims[1], (int)nz, dims[2], 8, cout, 27 * 8, 27 * 8 + 8};
     ConvEpi E{bias, act, nullptr, 0, 0, (u16*)y_bf16, ldy, 0, y_f32, ldyf};
+    if (!vector_epilogue_ok(E, cout)) return false;
     const dim3 grid((unsigned)nbrick), blk(256);
     switch ((cout + 15) / 16) {
         case 1: hipLaunchKernelGGL(k_conv_fwd_brick_in2<1>, grid, blk, 0, s, (const u16*)x, D,
@@ -1299,9 +1353,10 @@ air_status air_conv3d_fwd(const uint16_t* x, const int32_t dims[3], int32_t batc
     const u16* X = (const u16*)x;
     const u16* W = (const u16*)wt;
     // whole 16 x 4 x 4 bricks and at least one per CU: the LDS brick form
+    // (its epilogue writes whole 8-channel vectors)
     const long long nbrick = (D.nx % kBrX == 0 && D.ny % kBrY == 0 && D.nzv % kBrZ == 0)
                                  ? (long long)(D.nx / kBrX) * (D.ny / kBrY) * (D.nz / kBrZ) : 0;
-    if (nbrick >= 256 && nbrick < 0x7fffffffLL) {
+    if (nbrick >= 256 && nbrick < 0x7fffffffLL && cout <= 64 && vector_epilogue_ok(E, cout)) {
         const int cs = (cin == 8 || cin == 16 || cin == 32 || cin == 48) ? cin
                        : cin % 16 == 0 ? 16 : 8;
         const dim3 grid((unsigned)nbrick), blk(256);
