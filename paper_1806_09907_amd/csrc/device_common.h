@@ -21,9 +21,6 @@ __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t by
     return __builtin_amdgcn_make_buffer_rsrc(q, (short)0, (int)nb, 0x00020000);
 }
 
-// cache-policy operand of the buffer builtins: non-temporal (streamed data)
-constexpr int kNonTemporal = 2;
-
 // Two consecutive floats at byte offset voff + soff (dword aligned).
 __device__ inline v2f load2(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
     return __builtin_bit_cast(v2f, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));

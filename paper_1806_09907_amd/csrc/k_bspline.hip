@@ -650,11 +650,13 @@ k_fused3_s8(const LaunchCtx C) {
         const int z = cz * S + r;
         Prep q;
         // F through its buffer descriptor: the lane's offset is fixed, the
-        // plane's is a scalar (streamed once: non-temporal)
+        // plane's is a scalar. Default cache policy: a 16-lane tile row reads
+        // half of each 128-byte line and the neighbouring tile the other half
+        // (a non-temporal hint fetched every F line from HBM twice)
         AIR_CHECK((long long)fl4 + (long long)min(z, nz - 1) * nxy4 + 4 <= P.nvox * 4,
                   kDbgFixedLoad);
         q.Fv = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
-                                             rF, fl4, min(z, nz - 1) * nxy4, kNonTemporal));
+                                             rF, fl4, min(z, nz - 1) * nxy4, 0));
         float w0 = kW8.w[r][0], w1 = kW8.w[r][1], w2 = kW8.w[r][2], w3 = kW8.w[r][3];
         float sx_ = snx, sy_ = sny, sz_ = snz;
         // every uniform input of this stage passes through an empty asm that
