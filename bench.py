@@ -104,11 +104,23 @@ def pipes_for(workload: str):
     return {k: v for k, v in e["pipes"].items() if k not in ("definition", "command")}
 
 
+# Untimed warm-up steps per workload: about 0.1 s of GPU work each. Under
+# sustained load the GPU's clock ramps up over the first few tens of ms; the
+# timed region should see the steady state a continuous job runs at (128^3
+# batch: fused kernel 0.5525 ms after 5 warm-up steps, 0.523-0.525 ms after
+# 100 to 5000).
+DEFAULT_WARMUP = {"batch128": 200, "uneven48": 200, "dense256": 400, "latency2d": 4000,
+                  "diffeo256": 20, "diffeo2d": 40, "tv128": 800, "wendland128": 700,
+                  "lcc128": 500, "cnn128": 150}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed warm-up steps; default: per workload, about 0.1 s of GPU "
+                         "work (the GPU's clock ramps up over the first tens of ms of load)")
     ap.add_argument("--workload", default="batch128",
                     choices=["batch128", "uneven48", "dense256", "latency2d", "diffeo256",
                              "diffeo2d", "tv128", "wendland128", "lcc128", "cnn128"])
@@ -127,7 +139,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.warmup is None:
+        args.warmup = DEFAULT_WARMUP[args.workload]
+    return args
 
 
 def blob_batch(sizes, dev, seed_base=1):
@@ -879,8 +894,8 @@ def learned_secondary(dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported",
-              file=sys.stderr)
+        print(f"bench.py: the registration path runs on one GPU; --gpus {args.gpus} is not "
+              "supported", file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -926,16 +941,16 @@ def main():
         # the other configurations, measured by the same run: the 48-pair
         # uneven batch, the 256^3 dense pair and the 64^2 latency case
         import argparse as _ap
-        sub = _ap.Namespace(**{**vars(args), "steps": max(5, min(args.steps, 20)),
-                               "warmup": min(args.warmup, 3), "tiling": -1, "autotune_out": ""})
+        def sub_for(w, steps):
+            return _ap.Namespace(**{**vars(args), "steps": steps, "warmup": DEFAULT_WARMUP[w],
+                                    "tiling": -1, "autotune_out": ""})
+        steps = max(5, min(args.steps, 20))
         extra = {}
-        progress("extra workload: uneven48")
-        extra["uneven48"] = extra_line(run_uneven48(sub, dev), "uneven48")
-        progress("extra workload: dense256")
-        extra["dense256"] = extra_line(run_dense(sub, dev), "dense256")
-        progress("extra workload: latency2d")
-        sub2 = _ap.Namespace(**{**vars(sub), "steps": 200, "warmup": 20})
-        extra["latency2d"] = extra_line(run_latency2d(sub2, dev), "latency2d")
+        for w, fn, n in (("uneven48", run_uneven48, steps), ("dense256", run_dense, steps),
+                         ("latency2d", run_latency2d, 200)):
+            progress(f"extra workload: {w}")
+            sa = sub_for(w, n)
+            extra[w] = {**extra_line(fn(sa, dev), w), "steps": sa.steps, "warmup": sa.warmup}
         line["extra"] = extra
     if args.workload == "batch128" and not args.no_learned:
         progress("training and evaluating the learned initialisation")

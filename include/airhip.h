@@ -286,7 +286,8 @@ air_status air_field_resample(const float* in, const int32_t n[3], const int32_t
  * against their buffers and record a violation as a bit instead of reading
  * out of range (bit 0: fused B-spline moving-image gathers, 1: fixed-image
  * loads, 2: dense/warp sampler gathers, 3: exponential squaring gathers,
- * 4: CNN convolution loads, 5: CNN weight-gradient loads). This call waits
+ * 4: CNN convolution loads, 5: CNN weight-gradient loads, 6: fused B-spline
+ * control-window loads). This call waits
  * for the device, returns the bits set since the last call in *flags and
  * clears them. The regular library returns AIR_ERR_UNSUPPORTED. */
 air_status air_debug_bounds_take(uint32_t* flags);

@@ -38,6 +38,7 @@ enum DebugBit : unsigned {
     kDbgCompose = 3,        // exponential: squaring gathers
     kDbgConvInput = 4,      // CNN convolutions: input and weight loads
     kDbgConvWgrad = 5,      // CNN weight gradient: operand loads
+    kDbgControlLoad = 6,    // fused B-spline kernels: control-window loads
 };
 #ifdef AIR_DEBUG_BOUNDS
 static __device__ unsigned int air_dbg_flags;

@@ -214,18 +214,33 @@ k_fused3(const LaunchCtx C) {
 
     // 1. x-pass of the control window: T1[c][kz][ky][lx]
     {
-        const long long NC = (long long)ncx * ncy * P.nc[2];
-        for (int r = ly; r < 3 * Wz * Wy; r += TY) {
-            const int c = r / (Wz * Wy);
-            const int rem = r - c * Wz * Wy;
-            const int kz = rem / Wy, ky = rem - kz * Wy;
-            float v = 0.f;
-            if (x < nx) {
-                const float* th = theta + c * NC +
-                                  ((long long)(cz0 + kz) * ncy + (cy0 + ky)) * ncx + ix;
-                v = wx0 * th[0] + wx1 * th[1] + wx2 * th[2] + wx3 * th[3];
+        // each lane walks its rows j = kz Wy + ky (step TY) of every
+        // component with a running (kz, ky) pair: no division per row
+        const int NC = ncx * ncy * P.nc[2];
+        const __amdgpu_buffer_rsrc_t rT = make_rsrc(theta, (uint32_t)(3 * NC * 4));
+        const int dkz = TY / Wy, dky = TY - dkz * Wy;
+        const int kzs = ly / Wy, kys = ly - kzs * Wy;
+        const int tb = (cz0 * ncy + cy0) * ncx + ix;   // control (ix, cy0, cz0)
+        const int ncxy = ncx * ncy;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            int kz = kzs, ky = kys;
+            for (int j = ly; j < Wz * Wy; j += TY) {
+                float v = 0.f;
+                if (x < nx) {
+                    const int o = (c * NC + tb + __mul24(kz, ncxy) + __mul24(ky, ncx)) * 4;
+                    AIR_CHECK(o >= 0 && o + 16 <= 3 * NC * 4, kDbgControlLoad);
+                    const v2f t01 = load2(rT, o, 0), t23 = load2(rT, o + 8, 0);
+                    v = wx0 * t01.x + wx1 * t01.y + wx2 * t23.x + wx3 * t23.y;
+                }
+                T1[((c * WzM + kz) * WyM + ky) * TX + lx] = v;
+                kz += dkz;
+                ky += dky;
+                if (ky >= Wy) {
+                    ky -= Wy;
+                    ++kz;
+                }
             }
-            T1[((c * WzM + kz) * WyM + ky) * TX + lx] = v;
         }
     }
     // per-tile shift for the NCC moments (a sample of F and M in the tile)
@@ -519,19 +534,39 @@ k_fused3_s8(const LaunchCtx C) {
         }
     }
     const int ky0 = iy - cy0;
+    // z-controls of each lane's column are kept multiplied by the axis scale
+    // s_a (voxels per unit of u), so a layer's displacement in voxels is one
+    // weighted sum of them
+    const float snx = P.s[0], sny = P.s[1], snz = P.s[2];
     {
-        const long long NC = (long long)ncx * ncy * P.nc[2];
-        for (int r = ly; r < 3 * Wz * Wy; r += TY) {
-            const int c = r / (Wz * Wy);
-            const int rem = r - c * Wz * Wy;
-            const int kz = rem / Wy, ky = rem - kz * Wy;
-            float v = 0.f;
-            if (x < nx) {
-                const float* th = theta + c * NC +
-                                  ((long long)(cz0 + kz) * ncy + (cy0 + ky)) * ncx + ix;
-                v = wx[0] * th[0] + wx[1] * th[1] + wx[2] * th[2] + wx[3] * th[3];
+        // rows (kz, ky) of the x-interpolated control window, component by
+        // component; each lane walks its rows j = kz Wy + ky (step TY) with a
+        // running (kz, ky) pair instead of a division per row
+        const int NC = ncx * ncy * P.nc[2];
+        const __amdgpu_buffer_rsrc_t rT = make_rsrc(theta, (uint32_t)(3 * NC * 4));
+        const int dkz = TY / Wy, dky = TY - dkz * Wy;
+        const int kzs = ly / Wy, kys = ly - kzs * Wy;
+        const int tb = (cz0 * ncy + cy0) * ncx + ix;   // control (ix, cy0, cz0)
+        const int ncxy = ncx * ncy;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            int kz = kzs, ky = kys;
+            for (int j = ly; j < Wz * Wy; j += TY) {
+                float v = 0.f;
+                if (x < nx) {
+                    const int o = (c * NC + tb + __mul24(kz, ncxy) + __mul24(ky, ncx)) * 4;
+                    AIR_CHECK(o >= 0 && o + 16 <= 3 * NC * 4, kDbgControlLoad);
+                    const v2f t01 = load2(rT, o, 0), t23 = load2(rT, o + 8, 0);
+                    v = wx[0] * t01.x + wx[1] * t01.y + wx[2] * t23.x + wx[3] * t23.y;
+                }
+                T1[((c * WzM + kz) * WYC + ky) * TX + lx] = v;
+                kz += dkz;
+                ky += dky;
+                if (ky >= Wy) {
+                    ky -= Wy;
+                    ++kz;
+                }
             }
-            T1[((c * WzM + kz) * WYC + ky) * TX + lx] = v;
         }
     }
     float shF = 0.f, shW = 0.f;
@@ -544,9 +579,10 @@ k_fused3_s8(const LaunchCtx C) {
     }
     __syncthreads();
 
+    const float sc[3] = {snx, sny, snz};
     auto vcol = [&](int c, int kz) -> float {
         const float* r = T1 + ((c * WzM + kz) * WYC + ky0) * TX + lx;
-        return wy[0] * r[0] + wy[1] * r[TX] + wy[2] * r[2 * TX] + wy[3] * r[3 * TX];
+        return (wy[0] * r[0] + wy[1] * r[TX] + wy[2] * r[2 * TX] + wy[3] * r[3 * TX]) * sc[c];
     };
     float V[3][4];
 #pragma unroll
@@ -569,7 +605,6 @@ k_fused3_s8(const LaunchCtx C) {
 
     float cnt = 0.f;
     float m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f;
-    const float snx = P.s[0], sny = P.s[1], snz = P.s[2];
     const float nzm2 = (float)(nz - 2);
     // per lane, relative to the lane's voxel: cells start at lo = -x at
     // least and at hc = n - 2 - x at most
@@ -604,9 +639,11 @@ k_fused3_s8(const LaunchCtx C) {
             for (int k = 0; k < WYC; ++k) G[(fc * WYC + k) * GP + q] = o[k];
         }
         __syncthreads();
-        // x: task (fc, ky) -> Wx outputs of one partial row
-        for (int task = tid; task < FC * Wy; task += NT) {
-            const int ky = task % Wy, fc = task / Wy;
+        // x: task (fc, ky) -> Wx outputs of one partial row (tasks laid out
+        // over the compile-time row count, so no runtime division)
+        for (int task = tid; task < FC * WYC; task += NT) {
+            const int ky = task % WYC, fc = task / WYC;
+            if (ky >= Wy) continue;
             const float* g = G + (fc * WYC + ky) * GP;
             float o[WXC];
 #pragma unroll
@@ -658,23 +695,22 @@ k_fused3_s8(const LaunchCtx C) {
         q.Fv = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
                                              rF, fl4, min(z, nz - 1) * nxy4, 0));
         float w0 = kW8.w[r][0], w1 = kW8.w[r][1], w2 = kW8.w[r][2], w3 = kW8.w[r][3];
-        float sx_ = snx, sy_ = sny, sz_ = snz;
         // every uniform input of this stage passes through an empty asm that
         // also reads `dv` (produced by the previous layer's stage 2), so
         // neither the arithmetic nor the gathers of this layer can be
         // hoisted more than one layer ahead of their use
-        asm volatile("" : "+s"(w0), "+s"(w1), "+s"(w2), "+s"(w3), "+s"(sx_), "+s"(sy_),
-                          "+s"(sz_) : "v"(dv));
-        float u[3];
+        asm volatile("" : "+s"(w0), "+s"(w1), "+s"(w2), "+s"(w3) : "v"(dv));
+        // displacement in voxels d = s u (V holds s times the z-controls):
+        // the cell and the mask are decided on the exact sum x + d (x an
+        // integer), never on a rounded sample point (the first term is an
+        // fma with +0: a -0 product becomes +0, so f below is never -0)
+        float dd[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            u[c] = w0 * V[c][PH] + w1 * V[c][(PH + 1) & 3] + w2 * V[c][(PH + 2) & 3] +
-                   w3 * V[c][(PH + 3) & 3];
-        // displacement in voxels: the cell and the mask are decided on the
-        // exact sum x + d (x an integer), never on a rounded sample point
-        // (fma with +0: a -0 product becomes +0, so f below is never -0)
-        const float dx = fmaf(u[0], sx_, 0.f), dy = fmaf(u[1], sy_, 0.f);
-        const float dz = fmaf(u[2], sz_, 0.f);
+            dd[c] = fmaf(w3, V[c][(PH + 3) & 3],
+                         fmaf(w2, V[c][(PH + 2) & 3],
+                              fmaf(w1, V[c][(PH + 1) & 3], fmaf(w0, V[c][PH], 0.f))));
+        const float dx = dd[0], dy = dd[1], dz = dd[2];
         const float zf = (float)z;
         // cell [x + c, x + c + 1] with c = floor(d) clamped to [-x, n - 2 - x]
         // so that every load is in range. Then f = d - c is exact (c is an
