@@ -1173,17 +1173,6 @@ __device__ inline void store_pair_coef(const LaunchCtx& C, const PairDesc& P, in
     *vout = (float)value;
 }
 
-template <int SIM>
-__global__ void __launch_bounds__(kBlock)
-k_pair_coef(const LaunchCtx C) {
-    __shared__ double red[8 * (kBlock / 64)];
-    const int pair = blockIdx.x;
-    const PairDesc P = C.pairs[pair];
-    const Coef k = pair_coef<kBlock, SIM>(P, reinterpret_cast<const double*>(C.ws + C.L.stats), red);
-    const double R = pair_reg<kBlock>(P, reinterpret_cast<const double*>(C.ws + C.L.regpart), red);
-    if (threadIdx.x == 0) store_pair_coef(C, P, pair, k, R);
-}
-
 // Range of tiles (along one axis) whose voxel range meets the support of
 // control j: voxels [(j - 3) sp, (j + 1) sp - 1].
 __device__ inline void tile_range(int j, int sp, int n, int T, int* lo, int* hi) {
@@ -1213,26 +1202,13 @@ k_finalize(const LaunchCtx C) {
     const int pair = blockIdx.y;
     const PairDesc P = C.pairs[pair];
     const double* stats = reinterpret_cast<const double*>(C.ws + C.L.stats);
-    Coef k;
-    if (NS > 1) {
-        // few controls: every block reduces the pair's tile statistics itself
-        // (the same fixed-order sums as k_pair_coef, so the same values) and
-        // block 0 stores them, which saves a launch on this latency-bound path
-        __shared__ double red[8 * (kBlock / 64)];
-        k = pair_coef<kBlock, SIM>(P, stats, red);
-        const double R =
-            pair_reg<kBlock>(P, reinterpret_cast<const double*>(C.ws + C.L.regpart), red);
-        if (blockIdx.x == 0 && threadIdx.x == 0) store_pair_coef(C, P, pair, k, R);
-    } else {
-        const double* sc =
-            reinterpret_cast<const double*>(C.ws + C.L.scalars) + (long long)pair * 8;
-        k.S = sc[0];
-        k.alpha = sc[1];
-        k.beta = sc[2];
-        k.muF = sc[3];
-        k.muW = sc[4];
-        k.degenerate = sc[6] != 0.0;
-    }
+    // every block reduces the pair's tile statistics itself, in the same
+    // fixed order, so every block holds the same coefficients; block 0
+    // stores them with the pair's value (no separate launch)
+    __shared__ double red[8 * (kBlock / 64)];
+    const Coef k = pair_coef<kBlock, SIM>(P, stats, red);
+    const double R = pair_reg<kBlock>(P, reinterpret_cast<const double*>(C.ws + C.L.regpart), red);
+    if (blockIdx.x == 0 && threadIdx.x == 0) store_pair_coef(C, P, pair, k, R);
     uint32_t* flags = reinterpret_cast<uint32_t*>(C.ws + C.L.flags) + pair;
     const int nctrl = P.nc[0] * P.nc[1] * (DIM == 3 ? P.nc[2] : 1);
     const int ls = threadIdx.x % NS;
@@ -1366,13 +1342,9 @@ static hipError_t launch3s8(const LaunchCtx& C, size_t lds, hipStream_t s) {
 template <int TX, int TY, int SIM, int DIM>
 static hipError_t launch_fin(const LaunchCtx& C, int max_ctrl, hipStream_t s) {
     if ((long long)max_ctrl * C.npairs < kFinFewControls) {
-        // the finalize blocks reduce the pair statistics themselves
         dim3 grid(cdiv(max_ctrl, kBlock / kFinLanes), C.npairs);
         hipLaunchKernelGGL((k_finalize<TX, TY, SIM, DIM, kFinLanes>), grid, dim3(kBlock), 0, s, C);
     } else {
-        hipLaunchKernelGGL((k_pair_coef<SIM>), dim3(C.npairs), dim3(kBlock), 0, s, C);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
         dim3 grid(cdiv(max_ctrl, kBlock), C.npairs);
         hipLaunchKernelGGL((k_finalize<TX, TY, SIM, DIM, 1>), grid, dim3(kBlock), 0, s, C);
     }
