@@ -1277,32 +1277,78 @@ k_finalize(const LaunchCtx C) {
             }
             nb = 0;
         };
+        // The tiles of tile_range are exactly those whose control window holds
+        // the control, so its local indices lie inside each window. A tile's
+        // window starts at control floor(t T / sp) along x (and y). With
+        // several lanes per control (few controls, latency-bound) the origins
+        // are stepped from the first tile with a running remainder, one
+        // division per axis; with one lane per control, registers matter more
+        // and each origin is one division.
+        constexpr bool kStep = NS > 1;
+        const int spx = P.sp[0];
+        const int qx = TX / spx, rx = TX - qx * spx;
+        const int cxs = (tx_lo * TX) / spx, rxs = tx_lo * TX - cxs * spx;
+        int spy = 1, qy = 0, ry = 0, cys = 0, rys = 0;
+        if (DIM == 3) {
+            spy = P.sp[1];
+            qy = TY / spy;
+            ry = TY - qy * spy;
+            cys = (ty_lo * TY) / spy;
+            rys = ty_lo * TY - cys * spy;
+        }
         int slot = 0;
-        for (int tc = tc_lo; tc <= tc_hi; ++tc)
-        for (int ty = ty_lo; ty <= ty_hi; ++ty)
-        for (int tx = tx_lo; tx <= tx_hi; ++tx) {
-            if ((slot++ & (NS - 1)) != ls) continue;
+        for (int tc = tc_lo; tc <= tc_hi; ++tc) {
             const int kcl = jc - tc * P.col_cells;
-            int kyl = 0;
-            if (DIM == 3) {
-                int cy0, Wy;
-                ctrl_window(ty * TY, min(ty * TY + TY, P.n[1]), P.sp[1], &cy0, &Wy);
-                kyl = jy - cy0;
-                if (kyl < 0 || kyl >= Wy) continue;
+            AIR_CHECK(kcl >= 0 && kcl < min(P.col_cells, ncell - tc * P.col_cells) + 3,
+                      kDbgControlLoad);
+            int cy0 = cys, ryr = rys;
+            for (int ty = ty_lo; ty <= ty_hi; ++ty) {
+                int cx0 = cxs, rxr = rxs;
+                for (int tx = tx_lo; tx <= tx_hi; ++tx) {
+                    if ((slot++ & (NS - 1)) == ls) {
+                        if (!kStep) {
+                            cx0 = (tx * TX) / spx;
+                            if (DIM == 3) cy0 = (ty * TY) / spy;
+                        }
+                        const int kyl = (DIM == 3) ? jy - cy0 : 0;
+                        const int kxl = jx - cx0;
+#ifdef AIR_DEBUG_BOUNDS
+                        {
+                            int c0, w;
+                            ctrl_window(tx * TX, min(tx * TX + TX, P.n[0]), spx, &c0, &w);
+                            AIR_CHECK(c0 == cx0 && kxl >= 0 && kxl < w, kDbgControlLoad);
+                            if (DIM == 3) {
+                                ctrl_window(ty * TY, min(ty * TY + TY, P.n[1]), spy, &c0, &w);
+                                AIR_CHECK(c0 == cy0 && kyl >= 0 && kyl < w, kDbgControlLoad);
+                            }
+                        }
+#endif
+                        const int tl = (DIM == 3) ? (tc * P.ntile[1] + ty) * P.ntile[0] + tx
+                                                  : tc * P.ntile[0] + tx;
+                        const float* pt = part + (long long)tl * P.part_stride;
+                        stb[nb] = stats + (long long)(P.tile_begin + tl) * kStatWords;
+                        // partial layout [column][y][x][field * DIM + component]
+                        qb[nb] = pt + (((long long)kcl * WyM + kyl) * WxM + kxl) * (NF * DIM);
+                        if (++nb == NB) drain();
+                    }
+                    if (kStep) {
+                        cx0 += qx;
+                        rxr += rx;
+                        if (rxr >= spx) {
+                            rxr -= spx;
+                            ++cx0;
+                        }
+                    }
+                }
+                if (kStep) {
+                    cy0 += qy;
+                    ryr += ry;
+                    if (ryr >= spy) {
+                        ryr -= spy;
+                        ++cy0;
+                    }
+                }
             }
-            const int cells_t = min(P.col_cells, ncell - tc * P.col_cells);
-            if (kcl >= cells_t + 3) continue;
-            int cx0, Wx;
-            ctrl_window(tx * TX, min(tx * TX + TX, P.n[0]), P.sp[0], &cx0, &Wx);
-            const int kxl = jx - cx0;
-            if (kxl < 0 || kxl >= Wx) continue;
-            const int tl = (DIM == 3) ? (tc * P.ntile[1] + ty) * P.ntile[0] + tx
-                                      : tc * P.ntile[0] + tx;
-            const float* pt = part + (long long)tl * P.part_stride;
-            stb[nb] = stats + (long long)(P.tile_begin + tl) * kStatWords;
-            // partial layout [column][y][x][field * DIM + component]
-            qb[nb] = pt + (((long long)kcl * WyM + kyl) * WxM + kxl) * (NF * DIM);
-            if (++nb == NB) drain();
         }
         drain();
     }
