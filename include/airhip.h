@@ -218,10 +218,13 @@ air_status air_objective_and_grad_batched(const air_plan* plan,
 
 /* Tile autotuner of the fused B-spline launch (not in the paper; the plan's
  * tile configuration, air_plan_set_tiling, only changes the summation
- * order). air_autotune times every configuration valid for the plan on the
- * caller's batch (arguments as air_objective_and_grad_batched; ws of at
- * least air_autotune_workspace_bytes), one upload call and two warm-up
- * launches then `reps` launches between two HIP events on `stream`; checks
+ * order). air_autotune first runs the caller's batch for about 0.1 s on the
+ * plan's current configuration (the GPU's clock ramps up under sustained
+ * load), then times every configuration valid for the plan on that batch
+ * (arguments as air_objective_and_grad_batched; ws of at least
+ * air_autotune_workspace_bytes) in two rounds, each one upload call and two
+ * warm-up launches then `reps` launches between two HIP events on `stream`,
+ * keeping each configuration's faster reading; checks
  * that each configuration's values and gradients agree with the first one's
  * to 1e-6 relative (norm-wise per pair); keeps the fastest agreeing one in
  * the plan (*chosen, *kernel_ms per launch) and, when cache_path is not NULL,

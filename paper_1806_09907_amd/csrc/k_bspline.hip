@@ -254,9 +254,13 @@ k_fused3(const LaunchCtx C) {
     }
     __syncthreads();
 
+    // z-controls kept multiplied by the axis scale s_a (voxels per unit of
+    // u), as in k_fused3_s8, so both kernels form the same displacements
+    const float snx = P.s[0], sny = P.s[1], snz = P.s[2];
+    const float sc[3] = {snx, sny, snz};
     auto vcol = [&](int c, int kz) -> float {
         const float* r = T1 + ((c * WzM + kz) * WyM + ky0) * TX + lx;
-        return wy[0] * r[0] + wy[1] * r[TX] + wy[2] * r[2 * TX] + wy[3] * r[3 * TX];
+        return (wy[0] * r[0] + wy[1] * r[TX] + wy[2] * r[2 * TX] + wy[3] * r[3 * TX]) * sc[c];
     };
     float V[3][4];
 #pragma unroll
@@ -273,7 +277,6 @@ k_fused3(const LaunchCtx C) {
 
     int cnt = 0;
     float m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f;
-    const float snx = P.s[0], sny = P.s[1], snz = P.s[2];
     const int nx4 = nx * 4, nxy4 = nx * ny * 4;
     const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, (uint32_t)(P.nvox * 4));
     float* part = reinterpret_cast<float*>(C.ws + C.L.part) + P.part_off +
@@ -317,14 +320,16 @@ k_fused3(const LaunchCtx C) {
             if (act) {
                 const long long v = ((long long)z * ny + y) * nx + x;
                 const float Fv = F[v];
-                float u[3];
+                // displacement in voxels, d = u (n - 1)/2, summed in the same
+                // order as k_fused3_s8; cell and mask of x + d
+                float dd[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    u[c] = wz.x * V[c][0] + wz.y * V[c][1] + wz.z * V[c][2] + wz.w * V[c][3];
-                // cell and mask of x + d, d = u (n - 1)/2 in voxels
-                const AxisCell ax = axis_cell(x, Disp{u[0] * snx, 0.f}, nx);
-                const AxisCell ay = axis_cell(y, Disp{u[1] * sny, 0.f}, ny);
-                const AxisCell az = axis_cell(z, Disp{u[2] * snz, 0.f}, nz);
+                    dd[c] = fmaf(wz.w, V[c][3],
+                                 fmaf(wz.z, V[c][2], fmaf(wz.y, V[c][1], fmaf(wz.x, V[c][0], 0.f))));
+                const AxisCell ax = axis_cell(x, Disp{dd[0], 0.f}, nx);
+                const AxisCell ay = axis_cell(y, Disp{dd[1], 0.f}, ny);
+                const AxisCell az = axis_cell(z, Disp{dd[2], 0.f}, nz);
                 const bool in = ax.in && ay.in && az.in;
                 if (in) {
                     // a point on the last voxel takes the cell below with f = 1

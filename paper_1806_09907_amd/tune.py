@@ -1,7 +1,9 @@
 """Tile autotuner for the fused objective kernel (marshalling only).
 
-air_autotune (library, host C++) times every tile configuration of the plan
-on the caller's own batch with HIP events, checks that each reproduces the
+air_autotune (library, host C++) warms the GPU up on the caller's batch for
+about 0.1 s, then times every tile configuration of the plan on that batch
+with HIP events in two rounds (the faster reading counts), checks that each
+reproduces the
 first configuration's values and gradients to 1e-6 relative (the tile shape
 only changes the summation order), keeps the fastest, and records it in a
 JSON cache keyed by GPU architecture, dimension, transform, similarity,
