@@ -218,15 +218,15 @@ air_status air_objective_and_grad_batched(const air_plan* plan,
 
 /* Tile autotuner of the fused B-spline launch (not in the paper; the plan's
  * tile configuration, air_plan_set_tiling, only changes the summation
- * order). air_autotune first runs the caller's batch for about 0.1 s on the
- * plan's current configuration (the GPU's clock ramps up under sustained
- * load), then times every configuration valid for the plan on that batch
- * (arguments as air_objective_and_grad_batched; ws of at least
- * air_autotune_workspace_bytes) in two rounds, each one upload call and two
+ * order). air_autotune runs every configuration valid for the plan once on
+ * the caller's batch (arguments as air_objective_and_grad_batched; ws of at
+ * least air_autotune_workspace_bytes) and checks that its values and
+ * gradients agree with the first one's to 1e-5 relative (norm-wise per pair;
+ * summation order alone moves them by up to ~1.3e-6). It then runs the batch
+ * for about 0.1 s (the GPU's clock ramps up under sustained load) and times
+ * every agreeing configuration in two rounds, each one upload call and two
  * warm-up launches then `reps` launches between two HIP events on `stream`,
- * keeping each configuration's faster reading; checks
- * that each configuration's values and gradients agree with the first one's
- * to 1e-6 relative (norm-wise per pair); keeps the fastest agreeing one in
+ * keeping each configuration's faster reading; keeps the fastest one in
  * the plan (*chosen, *kernel_ms per launch) and, when cache_path is not NULL,
  * writes it into that JSON file under the plan's key (GPU architecture,
  * dimension, transform, similarity, spacing and size buckets of the batch),

@@ -1,14 +1,14 @@
 """Tile autotuner for the fused objective kernel (marshalling only).
 
-air_autotune (library, host C++) warms the GPU up on the caller's batch for
-about 0.1 s, then times every tile configuration of the plan on that batch
-with HIP events in two rounds (the faster reading counts), checks that each
-reproduces the
-first configuration's values and gradients to 1e-6 relative (the tile shape
-only changes the summation order), keeps the fastest, and records it in a
-JSON cache keyed by GPU architecture, dimension, transform, similarity,
-spacing and size buckets of the batch. air_autotune_cached applies a cached
-choice.
+air_autotune (library, host C++) runs every tile configuration of the plan
+once on the caller's own batch and checks that it reproduces the first
+configuration's values and gradients to 1e-5 relative (the tile shape only
+changes the summation order, which moves them by up to ~1.3e-6); it then
+warms the GPU up on that batch for about 0.1 s and times every agreeing
+configuration with HIP events in two rounds (the faster reading counts),
+keeps the fastest, and records it in a JSON cache keyed by GPU architecture,
+dimension, transform, similarity, spacing and size buckets of the batch.
+air_autotune_cached applies a cached choice.
 """
 from __future__ import annotations
 
