@@ -406,6 +406,35 @@ def test_batched_uneven_matches_single_and_oracle():
             check_grad(grads[i], go, f"batched pair {i} sim={sim}")
 
 
+def test_batched_generic_spacing_many_controls():
+    """A launch with at least 2^17 controls takes one finalize lane per
+    control; with spacings that do not divide the tile width, each tile's
+    control-window origin there is a division per tile (the few-controls
+    path steps it instead). Two pairs, 194,672 controls, spacings 3 and
+    (3, 5, 6), against the oracle and against single calls."""
+    cases = [((128, 128, 128), (3, 3, 3)), ((120, 112, 104), (3, 5, 6))]
+    probs = [api.Problem(n=n, spacing=sp, similarity=api.SIM_NCC, lambda_diff=0.05)
+             for n, sp in cases]
+    assert max(int(np.prod(p.ncontrol())) for p in probs) * len(probs) >= 1 << 17
+    Fs, Ms, Ts = [], [], []
+    for i, p in enumerate(probs):
+        F, M = blob_inputs(p.n, 8, 300 + i)
+        Fs.append(F); Ms.append(M); Ts.append(theta_for(p, "rand", 400 + i))
+    plan = api.Plan(probs)
+    print(f"case generic-spacing batch, tiling {plan.tiling}", flush=True)
+    vals, grads, _ = api.objective_and_grad_batched(
+        plan, [gpu(a) for a in Fs], [gpu(a) for a in Ms], [gpu(a) for a in Ts])
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        vs, gs = api.objective_and_grad(api.Plan(p, tiling=plan.tiling), gpu(Fs[i]),
+                                        gpu(Ms[i]), gpu(Ts[i]))
+        assert abs(float(vals[i]) - float(vs)) <= 1e-6 * abs(float(vs))
+        assert torch.linalg.norm(grads[i] - gs) <= 1e-5 * torch.linalg.norm(gs)
+        vo, go, _ = O.objective_and_grad(oprob(p), Fs[i], Ms[i], Ts[i])
+        assert abs(float(vals[i]) - vo) <= VAL_TOL * abs(vo)
+        check_grad(grads[i], go, f"generic-spacing batch pair {i}")
+
+
 def test_batched_c4_sizes_sampled_oracle():
     """48 uneven 3D pairs (sides from {96..160}) in one launch sequence, made
     by the uneven-batch recipe (the 128^3 blob recipe at each pair's size,
