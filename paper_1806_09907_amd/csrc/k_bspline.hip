@@ -225,20 +225,34 @@ k_fused3(const LaunchCtx C) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             int kz = kzs, ky = kys;
-            for (int j = ly; j < Wz * Wy; j += TY) {
-                float v = 0.f;
-                if (x < nx) {
-                    const int o = (c * NC + tb + __mul24(kz, ncxy) + __mul24(ky, ncx)) * 4;
+            // four rows at a time: the batch's loads are issued before any is
+            // used (rows past the window read the first control instead)
+            for (int j = ly; j < Wz * Wy; j += 4 * TY) {
+                v2f t01[4], t23[4];
+                int kzr[4], kyr[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    kzr[i] = kz;
+                    kyr[i] = ky;
+                    const bool ok = j + i * TY < Wz * Wy;
+                    const int o =
+                        ok ? (c * NC + tb + __mul24(kz, ncxy) + __mul24(ky, ncx)) * 4 : tb * 4;
                     AIR_CHECK(o >= 0 && o + 16 <= 3 * NC * 4, kDbgControlLoad);
-                    const v2f t01 = load2(rT, o, 0), t23 = load2(rT, o + 8, 0);
-                    v = wx0 * t01.x + wx1 * t01.y + wx2 * t23.x + wx3 * t23.y;
+                    t01[i] = load2(rT, o, 0);
+                    t23[i] = load2(rT, o + 8, 0);
+                    kz += dkz;
+                    ky += dky;
+                    if (ky >= Wy) {
+                        ky -= Wy;
+                        ++kz;
+                    }
                 }
-                T1[((c * WzM + kz) * WyM + ky) * TX + lx] = v;
-                kz += dkz;
-                ky += dky;
-                if (ky >= Wy) {
-                    ky -= Wy;
-                    ++kz;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (j + i * TY < Wz * Wy) {
+                        const float v = wx0 * t01[i].x + wx1 * t01[i].y + wx2 * t23[i].x + wx3 * t23[i].y;
+                        T1[((c * WzM + kzr[i]) * WyM + kyr[i]) * TX + lx] = x < nx ? v : 0.f;
+                    }
                 }
             }
         }
@@ -556,20 +570,34 @@ k_fused3_s8(const LaunchCtx C) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             int kz = kzs, ky = kys;
-            for (int j = ly; j < Wz * Wy; j += TY) {
-                float v = 0.f;
-                if (x < nx) {
-                    const int o = (c * NC + tb + __mul24(kz, ncxy) + __mul24(ky, ncx)) * 4;
+            // four rows at a time: the batch's loads are issued before any is
+            // used (rows past the window read the first control instead)
+            for (int j = ly; j < Wz * Wy; j += 4 * TY) {
+                v2f t01[4], t23[4];
+                int kzr[4], kyr[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    kzr[i] = kz;
+                    kyr[i] = ky;
+                    const bool ok = j + i * TY < Wz * Wy;
+                    const int o =
+                        ok ? (c * NC + tb + __mul24(kz, ncxy) + __mul24(ky, ncx)) * 4 : tb * 4;
                     AIR_CHECK(o >= 0 && o + 16 <= 3 * NC * 4, kDbgControlLoad);
-                    const v2f t01 = load2(rT, o, 0), t23 = load2(rT, o + 8, 0);
-                    v = wx[0] * t01.x + wx[1] * t01.y + wx[2] * t23.x + wx[3] * t23.y;
+                    t01[i] = load2(rT, o, 0);
+                    t23[i] = load2(rT, o + 8, 0);
+                    kz += dkz;
+                    ky += dky;
+                    if (ky >= Wy) {
+                        ky -= Wy;
+                        ++kz;
+                    }
                 }
-                T1[((c * WzM + kz) * WYC + ky) * TX + lx] = v;
-                kz += dkz;
-                ky += dky;
-                if (ky >= Wy) {
-                    ky -= Wy;
-                    ++kz;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (j + i * TY < Wz * Wy) {
+                        const float v = wx[0] * t01[i].x + wx[1] * t01[i].y + wx[2] * t23[i].x + wx[3] * t23[i].y;
+                        T1[((c * WzM + kzr[i]) * WYC + kyr[i]) * TX + lx] = x < nx ? v : 0.f;
+                    }
                 }
             }
         }
@@ -920,27 +948,42 @@ k_fused2(const LaunchCtx C) {
     const int xc = min(x, nx - 1), ix = xc / sx;
     const float* wtx = C.consts + P.wtab_off[0] + (xc - ix * sx) * 4;
     const float wx0 = wtx[0], wx1 = wtx[1], wx2 = wtx[2], wx3 = wtx[3];
-    for (int i = tid; i < TX * WxM; i += NT) {
-        const int q = i / WxM, k = i % WxM;
-        float w = 0.f;
-        const int xq = x0 + q;
-        if (xq < nx) {
-            const int kk = k - (xq / sx - cx0);
-            if (kk >= 0 && kk < 4) w = C.consts[P.wtab_off[0] + (xq % sx) * 4 + kk];
+    // x weights of this lane's pixel for the window's controls (one thread
+    // per lane): its own four weights at controls ix - cx0 .. ix - cx0 + 3
+    {
+        const int kb = ix - cx0;
+        for (int k = 0; k < WxM; ++k) {
+            const int kk = k - kb;
+            const float w = kk == 0 ? wx0 : kk == 1 ? wx1 : kk == 2 ? wx2 : wx3;
+            WXT[lx * WxM + k] = (act && kk >= 0 && kk < 4) ? w : 0.f;
         }
-        WXT[i] = w;
     }
     for (int i = tid; i < sy * 4; i += NT) WYT[i] = C.consts[P.wtab_off[1] + i];
     {
-        const long long NC = (long long)ncx * P.nc[1];
-        for (int r = 0; r < 2 * Wy; ++r) {
-            const int c = r / Wy, ky = r % Wy;
-            float v = 0.f;
-            if (act) {
-                const float* th = theta + c * NC + (long long)(cy0 + ky) * ncx + ix;
-                v = wx0 * th[0] + wx1 * th[1] + wx2 * th[2] + wx3 * th[3];
+        // rows r = c Wy + ky of the x-interpolated window, four at a time:
+        // the loads of a batch are issued before any is used
+        const int NC = ncx * P.nc[1];
+        const __amdgpu_buffer_rsrc_t rT = make_rsrc(theta, (uint32_t)(2 * NC * 4));
+        for (int r0 = 0; r0 < 2 * Wy; r0 += 4) {
+            v2f t01[4], t23[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = min(r0 + i, 2 * Wy - 1);
+                const int c = r >= Wy ? 1 : 0, ky = r - c * Wy;
+                const int o = (c * NC + (cy0 + ky) * ncx + ix) * 4;
+                AIR_CHECK(o >= 0 && o + 16 <= 2 * NC * 4, kDbgControlLoad);
+                t01[i] = load2(rT, o, 0);
+                t23[i] = load2(rT, o + 8, 0);
             }
-            T1[(c * WyM + ky) * TX + lx] = v;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = r0 + i;
+                if (r < 2 * Wy) {
+                    const int c = r >= Wy ? 1 : 0, ky = r - c * Wy;
+                    const float v = wx0 * t01[i].x + wx1 * t01[i].y + wx2 * t23[i].x + wx3 * t23[i].y;
+                    T1[(c * WyM + ky) * TX + lx] = act ? v : 0.f;
+                }
+            }
         }
     }
     float shF = 0.f, shW = 0.f;
@@ -989,36 +1032,57 @@ k_fused2(const LaunchCtx C) {
     for (int cy = cy_b; cy < cy_e; ++cy) {
         const int kyl = cy - cy0;
         const int yb = cy * sy, ye = min(yb + sy, ny);
-        for (int y = yb; y < ye; ++y) {
-            const float4 wy = *reinterpret_cast<const float4*>(WYT + (y - yb) * 4);
-            if (act) {
-                const long long v = (long long)y * nx + x;
-                const float Fv = F[v];
+        // Rows in groups of RB: the loads of a whole group (F and the two
+        // corner pairs of each row, at cells clamped into the image so that
+        // every address is valid) are issued before any row's arithmetic,
+        // so a group waits for memory once; the rows are then added in
+        // order, as one at a time would.
+        constexpr int RB = 4;
+        for (int yg = yb; yg < ye; yg += RB) {
+            float4 wyr[RB];
+            float Fr[RB], fxr[RB], fyr[RB];
+            v2f a0r[RB], a1r[RB];
+            bool inr[RB], exr[RB], eyr[RB];
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                const int y = min(yg + i, ye - 1);
+                wyr[i] = *reinterpret_cast<const float4*>(WYT + (y - yb) * 4);
+                Fr[i] = F[(long long)y * nx + xc];
                 float u[2];
 #pragma unroll
                 for (int c = 0; c < 2; ++c)
-                    u[c] = wy.x * V[c][0] + wy.y * V[c][1] + wy.z * V[c][2] + wy.w * V[c][3];
+                    u[c] = wyr[i].x * V[c][0] + wyr[i].y * V[c][1] + wyr[i].z * V[c][2] +
+                           wyr[i].w * V[c][3];
                 // cell and mask of x + d, d = u (n - 1)/2 in voxels
                 const AxisCell ax = axis_cell(x, Disp{u[0] * snx, 0.f}, nx);
                 const AxisCell ay = axis_cell(y, Disp{u[1] * sny, 0.f}, ny);
-                if (ax.in && ay.in) {
-                    // a point on the last pixel takes the cell below with f = 1
-                    const bool ex = ax.t == nx - 1, ey = ay.t == ny - 1;
-                    const int jx = ex ? nx - 2 : ax.t, jy = ey ? ny - 2 : ay.t;
-                    const float fx = ex ? 1.f : ax.f, fy = ey ? 1.f : ay.f;
-                    const int off = (jy * nx + jx) * 4;
-                    AIR_CHECK(off >= 0 && (long long)off + nx4 + 8 <= P.nvox * 4,
-                              kDbgMovingGather);
-                    const v2f a0 = load2(rM, off, 0);
-                    const v2f a1 = load2(rM, off, nx4);
+                inr[i] = act && yg + i < ye && ax.in && ay.in;
+                // a point on the last pixel takes the cell below with f = 1
+                exr[i] = ax.t == nx - 1;
+                eyr[i] = ay.t == ny - 1;
+                const int jx = min(max(exr[i] ? nx - 2 : ax.t, 0), nx - 2);
+                const int jy = min(max(eyr[i] ? ny - 2 : ay.t, 0), ny - 2);
+                fxr[i] = exr[i] ? 1.f : ax.f;
+                fyr[i] = eyr[i] ? 1.f : ay.f;
+                const int off = (jy * nx + jx) * 4;
+                AIR_CHECK(off >= 0 && (long long)off + nx4 + 8 <= P.nvox * 4, kDbgMovingGather);
+                a0r[i] = load2(rM, off, 0);
+                a1r[i] = load2(rM, off, nx4);
+            }
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                if (inr[i]) {
+                    const float4 wy = wyr[i];
+                    const float Fv = Fr[i], fx = fxr[i], fy = fyr[i];
+                    const v2f a0 = a0r[i], a1 = a1r[i];
                     const float dy0 = a1.x - a0.x, dy1 = a1.y - a0.y;
                     const float g0 = a0.x + fy * dy0, g1 = a0.y + fy * dy1;
                     const float W = g0 + fx * (g1 - g0);
                     float d[2];
                     d[0] = g1 - g0;
                     d[1] = dy0 + fx * (dy1 - dy0);
-                    if (ex) d[0] = -W;
-                    if (ey) d[1] = -W;
+                    if (exr[i]) d[0] = -W;
+                    if (eyr[i]) d[1] = -W;
                     cnt += 1;
                     if (SIM == AIR_SIM_NCC) {
                         const float dF = Fv - shF, dW = W - shW;
