@@ -321,7 +321,19 @@ k_fused3(const LaunchCtx C) {
             const int q0 = max(0, (cx0 + kx - 3) * sx - x0);
             const int q1 = min(TX, (cx0 + kx + 1) * sx - x0);
             float s = 0.f;
-            for (int q = q0; q < q1; ++q) s += WXT[q * WxM + kx] * g[q];
+            // eight lanes' terms loaded ahead of their sums, added in lane
+            // order (a term past q1 is 0)
+            for (int q8 = q0; q8 < q1; q8 += 8) {
+                float w[8], e[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int q = min(q8 + i, q1 - 1);
+                    w[i] = q8 + i < q1 ? WXT[q * WxM + kx] : 0.f;
+                    e[i] = g[q];
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) s += w[i] * e[i];
+            }
             part[((kzl * WyM + ky) * WxM + kx) * (NF * 3) + fc] = s;
         }
     };
@@ -1024,7 +1036,19 @@ k_fused2(const LaunchCtx C) {
             const int q0 = max(0, (cx0 + kx - 3) * sx - x0);
             const int q1 = min(TX, (cx0 + kx + 1) * sx - x0);
             float s = 0.f;
-            for (int q = q0; q < q1; ++q) s += WXT[q * WxM + kx] * E[fc * TX + q];
+            // eight lanes' terms loaded ahead of their sums, added in lane
+            // order (a term past q1 is 0)
+            for (int q8 = q0; q8 < q1; q8 += 8) {
+                float w[8], e[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int q = min(q8 + i, q1 - 1);
+                    w[i] = q8 + i < q1 ? WXT[q * WxM + kx] : 0.f;
+                    e[i] = E[fc * TX + q];
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) s += w[i] * e[i];
+            }
             part[(kyl * WxM + kx) * (NF * 2) + fc] = s;
         }
         __syncthreads();
