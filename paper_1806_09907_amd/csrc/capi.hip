@@ -88,6 +88,11 @@ static const TileCfg kCfg2[] = {{64, 1, 2}, {64, 1, 4}, {64, 1, 8}, {64, 1, 16},
 // (16 x 16 with 16, 8, 4, 2 cells), and the tile count that fills the chip
 static const int kCfg3Fill[] = {6, 8, 5, 9};
 constexpr int kFillTiles = 4096;
+// a launch with fewer tiles takes the longest column that still gives every
+// CU one tile: with the tile set-up and tail cheap, a longer walk pays more
+// than a second resident block (one 128^3 pair: 4-cell columns, 256 tiles,
+// 30.2 us per evaluation against 31.8 us with 2-cell columns, 512 tiles)
+constexpr int kOneTilePerCu = 256;
 // the same for 2D B-spline plans (64-lane columns of 16, 8, 4, 2, 1 cells)
 static const int kCfg2Fill[] = {3, 2, 1, 0, 4};
 constexpr int kFillTiles2 = 2048;
@@ -946,12 +951,13 @@ air_status air_plan_create(const air_problem* probs, int32_t npairs, air_plan** 
     }
     // Default tile configuration of 3D spacing-8 B-spline plans: 16 x 16
     // columns, the longest column (16, 8, 4, 2 cells) whose launch still has
-    // kFillTiles tiles, else the one with the most tiles; of 2D B-spline
-    // plans: the longest column (16 .. 1 cells) with kFillTiles2 tiles.
+    // kFillTiles tiles, else the longest with one tile per CU (kOneTilePerCu),
+    // else the one with the most tiles; of 2D B-spline plans: the longest
+    // column (16 .. 1 cells) with kFillTiles2 tiles, else the most tiles.
     // air_plan_set_tiling (and the autotuner) override it.
     const bool bs2 = P->dim == 2 && P->transform == AIR_TF_BSPLINE3;
     if (P->variant == 3 || bs2) {
-        int chosen = -1;
+        int chosen = -1, per_cu = -1;
         const int* cand = bs2 ? kCfg2Fill : kCfg3Fill;
         const int ncand = bs2 ? 5 : 4;
         const int fill = bs2 ? kFillTiles2 : kFillTiles;
@@ -960,7 +966,9 @@ air_status air_plan_create(const air_problem* probs, int32_t npairs, air_plan** 
             if (build_tables(P) != AIR_OK) continue;
             chosen = cand[k];
             if (P->ntiles_total >= fill) break;
+            if (!bs2 && per_cu < 0 && P->ntiles_total >= kOneTilePerCu) per_cu = cand[k];
         }
+        if (P->ntiles_total < fill && per_cu >= 0) chosen = per_cu;
         if (chosen != P->tiling) {
             P->tiling = chosen >= 0 ? chosen : 0;
             st = build_tables(P);

@@ -56,7 +56,8 @@ def test_plan_create_and_queries():
 def _default_tiling(dim, sizes, fill):
     """The documented default: among the columns of 16, 8, 4, 2 cells (3D,
     16 x 16 tiles) or 16, 8, 4, 2, 1 cells (2D, 64 x 1), the longest whose
-    launch has `fill` tiles, else the one with the most tiles."""
+    launch has `fill` tiles, else (3D) the longest with at least 256 tiles,
+    one per CU, else the one with the most tiles."""
     from paper_1806_09907_amd import api
 
     shape = (16, 16) if dim == 3 else (64, 1)
@@ -65,7 +66,7 @@ def _default_tiling(dim, sizes, fill):
         tx, ty, cells = api.tiling_describe(dim, t)
         if (tx, ty) == shape:
             ids[cells] = t
-    best, best_tiles = None, -1
+    best, best_tiles, per_cu = None, -1, None
     for cells in ((16, 8, 4, 2) if dim == 3 else (16, 8, 4, 2, 1)):
         tiles = 0
         for n in sizes:
@@ -74,15 +75,18 @@ def _default_tiling(dim, sizes, fill):
                 -(-ncol // cells)
         if tiles >= fill:
             return ids[cells]
+        if dim == 3 and per_cu is None and tiles >= 256:
+            per_cu = ids[cells]
         if tiles > best_tiles:
             best, best_tiles = ids[cells], tiles
-    return best
+    return per_cu if per_cu is not None else best
 
 
 @pytest.mark.parametrize("dim,sizes", [
     (3, [(128, 128, 128)] * 64),   # 16-cell columns already give 4096 tiles
     (3, [(128, 128, 128)] * 8),    # 2-cell columns
-    (3, [(128, 128, 128)]),        # no column reaches 4096 tiles: 2-cell, the most
+    (3, [(128, 128, 128)]),        # no column reaches 4096 tiles: 4-cell, 256 tiles
+    (3, [(64, 64, 64)]),           # none reaches 256 tiles either: 2-cell, the most
     (3, [(96, 112, 160), (144, 128, 96)] * 6),
     (2, [(64, 64)]),
     (2, [(1024, 1024)]),
