@@ -1193,11 +1193,17 @@ struct Coef {
     bool degenerate;
 };
 
+// Per-thread parts of a pair's reduction: the tile moments (v[0..5], or
+// v[0..1] for MSE) and the regulariser partials (v[6]); block_sum then adds
+// them in a fixed order. The first tile and the first partial of each thread
+// are loaded together, so that (with at most one of each, the usual case)
+// the thread waits for memory once.
 template <int NT, int SIM>
-__device__ Coef pair_coef(const PairDesc& P, const double* stats, double* red) {
-    double v[6] = {0, 0, 0, 0, 0, 0};
-    for (int t = threadIdx.x; t < P.ntiles; t += NT) {
-        const double* s = stats + (long long)(P.tile_begin + t) * kStatWords;
+__device__ void pair_sums_local(const PairDesc& P, const double* stats, const double* regpart,
+                                double (&v)[7]) {
+#pragma unroll
+    for (int i = 0; i < 7; ++i) v[i] = 0.0;
+    auto tile = [&](const double (&s)[8]) {
         const double n = s[0];
         if (SIM == AIR_SIM_NCC) {
             const double a = s[6], b = s[7];
@@ -1211,8 +1217,29 @@ __device__ Coef pair_coef(const PairDesc& P, const double* stats, double* red) {
             v[0] += n;
             v[1] += s[1];
         }
+    };
+    auto fetch = [&](int t, double (&s)[8]) {
+        const double* p = stats + (long long)(P.tile_begin + t) * kStatWords;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s[i] = p[i];
+    };
+    const int t0 = threadIdx.x;
+    double s0[8];
+    if (t0 < P.ntiles) fetch(t0, s0);
+    const double r0 = t0 < P.nreg ? regpart[P.regpart_off + t0] : 0.0;
+    if (t0 < P.ntiles) tile(s0);
+    for (int t = t0 + NT; t < P.ntiles; t += NT) {
+        double s1[8];
+        fetch(t, s1);
+        tile(s1);
     }
-    block_sum<NT, 6>(v, red);
+    v[6] += r0;
+    for (int i = t0 + NT; i < P.nreg; i += NT) v[6] += regpart[P.regpart_off + i];
+}
+
+// The similarity's coefficients from the pair's summed moments.
+template <int SIM>
+__device__ Coef coef_from_sums(const double (&v)[7]) {
     Coef k{0.0, 0.0, 0.0, 0.0, 0.0, false};
     const double N = v[0];
     if (SIM == AIR_SIM_MSE) {
@@ -1235,14 +1262,6 @@ __device__ Coef pair_coef(const PairDesc& P, const double* stats, double* red) {
     k.muF = muF;
     k.muW = muW;
     return k;
-}
-
-template <int NT>
-__device__ double pair_reg(const PairDesc& P, const double* regpart, double* red) {
-    double v[1] = {0.0};
-    for (int i = threadIdx.x; i < P.nreg; i += NT) v[0] += regpart[P.regpart_off + i];
-    block_sum<NT, 1>(v, red);
-    return v[0] * (double)P.inv_xr;
 }
 
 // scalars[pair]: [0] S, [1] alpha, [2] beta, [3] muF, [4] muW, [5] R, [6] degenerate;
@@ -1295,13 +1314,7 @@ k_finalize(const LaunchCtx C) {
     const int pair = blockIdx.y;
     const PairDesc P = C.pairs[pair];
     const double* stats = reinterpret_cast<const double*>(C.ws + C.L.stats);
-    // every block reduces the pair's tile statistics itself, in the same
-    // fixed order, so every block holds the same coefficients; block 0
-    // stores them with the pair's value (no separate launch)
     __shared__ double red[8 * (kBlock / 64)];
-    const Coef k = pair_coef<kBlock, SIM>(P, stats, red);
-    const double R = pair_reg<kBlock>(P, reinterpret_cast<const double*>(C.ws + C.L.regpart), red);
-    if (blockIdx.x == 0 && threadIdx.x == 0) store_pair_coef(C, P, pair, k, R);
     uint32_t* flags = reinterpret_cast<uint32_t*>(C.ws + C.L.flags) + pair;
     const int nctrl = P.nc[0] * P.nc[1] * (DIM == 3 ? P.nc[2] : 1);
     const int ls = threadIdx.x % NS;
@@ -1311,10 +1324,65 @@ k_finalize(const LaunchCtx C) {
     const float* rg = reinterpret_cast<const float*>(C.ws + C.L.reggrad) + P.param_off;
     float* grad = C.grad_tab ? C.grad_tab[pair] : C.grad0;
     const int WxM = P.win[0], WyM = (DIM == 3) ? P.win[1] : 1;
+    // this lane's tiles are taken NB at a time: their addresses first, then
+    // every load of the batch (all addresses valid: unused entries point at
+    // the pair's first partial), then the sums in slot order, so each batch
+    // waits for memory once
+    constexpr int NB = NS > 1 ? kFinBatch : 1;
+    const double* stb[NB];
+    const float* qb[NB];
+    double s6[NB], s7[NB];
+    float qv[NB][NF * DIM];
+    int nb = 0;
+    const double* st0 = stats + (long long)P.tile_begin * kStatWords;
+    auto reset = [&]() {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            stb[i] = st0;
+            qb[i] = part;
+        }
+        nb = 0;
+    };
+    auto load = [&]() {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            if (SIM == AIR_SIM_NCC) {
+                s6[i] = stb[i][6];
+                s7[i] = stb[i][7];
+            }
+#pragma unroll
+            for (int e = 0; e < NF * DIM; ++e) qv[i][e] = qb[i][e];
+        }
+    };
     double g[DIM];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) g[c] = 0.0;
-    if (live && !k.degenerate) {
+    auto add = [&](const Coef& k, int n) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            if (i >= n) break;
+            const double cF = k.alpha, cW = k.beta;
+            double c1 = 0.0;
+            if (SIM == AIR_SIM_NCC) c1 = k.alpha * (s6[i] - k.muF) + k.beta * (s7[i] - k.muW);
+            const float* q = qv[i];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                if (SIM == AIR_SIM_NCC)
+                    g[c] += cF * q[c] + cW * q[DIM + c] + c1 * q[2 * DIM + c];
+                else
+                    g[c] += cF * q[c];
+            }
+        }
+    };
+    // Walk this lane's tiles in slot order, calling visit(stats, partial) for
+    // each. The tiles of tile_range are exactly those whose control window
+    // holds the control, so its local indices lie inside each window. A
+    // tile's window starts at control floor(t T / sp) along x (and y). With
+    // several lanes per control (few controls, latency-bound) the origins are
+    // stepped from the first tile with a running remainder, one division per
+    // axis; with one lane per control, registers matter more and each origin
+    // is one division.
+    auto walk = [&](auto&& visit) {
         const int jx = j % P.nc[0];
         const int jy = (j / P.nc[0]) % P.nc[1];
         const int jz = (DIM == 3) ? j / (P.nc[0] * P.nc[1]) : 0;
@@ -1327,56 +1395,6 @@ k_finalize(const LaunchCtx C) {
         int tx_lo, tx_hi, ty_lo = 0, ty_hi = 0;
         tile_range(jx, P.sp[0], P.n[0], TX, &tx_lo, &tx_hi);
         if (DIM == 3) tile_range(jy, P.sp[1], P.n[1], TY, &ty_lo, &ty_hi);
-        // this lane's tiles are taken NB at a time: their addresses first,
-        // then every load of the batch (all addresses valid: unused entries
-        // point at the pair's first partial), then the sums in slot order, so
-        // each batch waits for memory once
-        constexpr int NB = NS > 1 ? kFinBatch : 1;
-        const double* stb[NB];
-        const float* qb[NB];
-        int nb = 0;
-        const double* st0 = stats + (long long)P.tile_begin * kStatWords;
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            stb[i] = st0;
-            qb[i] = part;
-        }
-        auto drain = [&]() {
-            double s6[NB], s7[NB];
-            float qv[NB][NF * DIM];
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                if (SIM == AIR_SIM_NCC) {
-                    s6[i] = stb[i][6];
-                    s7[i] = stb[i][7];
-                }
-#pragma unroll
-                for (int e = 0; e < NF * DIM; ++e) qv[i][e] = qb[i][e];
-            }
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                if (i >= nb) break;
-                const double cF = k.alpha, cW = k.beta;
-                double c1 = 0.0;
-                if (SIM == AIR_SIM_NCC) c1 = k.alpha * (s6[i] - k.muF) + k.beta * (s7[i] - k.muW);
-                const float* q = qv[i];
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) {
-                    if (SIM == AIR_SIM_NCC)
-                        g[c] += cF * q[c] + cW * q[DIM + c] + c1 * q[2 * DIM + c];
-                    else
-                        g[c] += cF * q[c];
-                }
-            }
-            nb = 0;
-        };
-        // The tiles of tile_range are exactly those whose control window holds
-        // the control, so its local indices lie inside each window. A tile's
-        // window starts at control floor(t T / sp) along x (and y). With
-        // several lanes per control (few controls, latency-bound) the origins
-        // are stepped from the first tile with a running remainder, one
-        // division per axis; with one lane per control, registers matter more
-        // and each origin is one division.
         constexpr bool kStep = NS > 1;
         const int spx = P.sp[0];
         const int qx = TX / spx, rx = TX - qx * spx;
@@ -1419,10 +1437,9 @@ k_finalize(const LaunchCtx C) {
                         const int tl = (DIM == 3) ? (tc * P.ntile[1] + ty) * P.ntile[0] + tx
                                                   : tc * P.ntile[0] + tx;
                         const float* pt = part + (long long)tl * P.part_stride;
-                        stb[nb] = stats + (long long)(P.tile_begin + tl) * kStatWords;
                         // partial layout [column][y][x][field * DIM + component]
-                        qb[nb] = pt + (((long long)kcl * WyM + kyl) * WxM + kxl) * (NF * DIM);
-                        if (++nb == NB) drain();
+                        visit(stats + (long long)(P.tile_begin + tl) * kStatWords,
+                              pt + (((long long)kcl * WyM + kyl) * WxM + kxl) * (NF * DIM));
                     }
                     if (kStep) {
                         cx0 += qx;
@@ -1443,7 +1460,59 @@ k_finalize(const LaunchCtx C) {
                 }
             }
         }
-        drain();
+    };
+    // With several lanes per control (few controls, latency-bound) the
+    // lane's first batch is loaded before the pair's reduction, so that both
+    // wait for memory together, and a lane with more than NB tiles walks them
+    // again for the rest. With one lane per control the walk runs once, after
+    // the reduction (a second walk would repeat the control's index
+    // arithmetic, and the launch has waves enough to hide the wait).
+    constexpr bool kEarly = NS > 1;
+    reset();
+    int mine = 0;
+    if (kEarly) {
+        if (live)
+            walk([&](const double* sp, const float* qp) {
+                if (mine < NB) {
+                    stb[mine] = sp;
+                    qb[mine] = qp;
+                }
+                ++mine;
+            });
+        load();
+    }
+    // every block reduces the pair's tile statistics itself, in the same
+    // fixed order, so every block holds the same coefficients; block 0
+    // stores them with the pair's value (no separate launch)
+    double v[7];
+    pair_sums_local<kBlock, SIM>(P, stats, reinterpret_cast<const double*>(C.ws + C.L.regpart),
+                                 v);
+    block_sum<kBlock, 7>(v, red);
+    const Coef k = coef_from_sums<SIM>(v);
+    const double R = v[6] * (double)P.inv_xr;
+    if (blockIdx.x == 0 && threadIdx.x == 0) store_pair_coef(C, P, pair, k, R);
+    if (live && !k.degenerate) {
+        int skip = 0;
+        if (kEarly) {
+            add(k, min(mine, NB));
+            skip = NB;
+        }
+        if (!kEarly || mine > NB) {
+            reset();
+            int seen = 0;
+            walk([&](const double* sp, const float* qp) {
+                if (seen++ < skip) return;
+                stb[nb] = sp;
+                qb[nb] = qp;
+                if (++nb == NB) {
+                    load();
+                    add(k, NB);
+                    reset();
+                }
+            });
+            load();
+            add(k, nb);
+        }
     }
     static_assert((NS & (NS - 1)) == 0 && NS <= 64, "NS: a power of two within a wave");
 #pragma unroll
