@@ -440,7 +440,7 @@ static air_status build_tables(air_plan* P) {
                     a4(NF * 3 * wym * cfg.tx) + a4(cfg.tx * wxm) + a4(cfg.ty * wym) +
                     a4(4 * D.sp[2]);
             } else {
-                f = a4(2 * D.win[2] * cfg.tx) + a4(NF * 2 * cfg.tx) + a4(cfg.tx * wxm) +
+                f = a4(2 * D.win[2] * cfg.tx) + a4(3 * NF * 2 * cfg.tx) + a4(cfg.tx * wxm) +
                     a4(4 * D.sp[1]);
             }
             auto reg_floats = [&](int rows) {

@@ -952,8 +952,8 @@ k_fused2(const LaunchCtx C) {
     const int cy0 = cy_b, Wy = cy_e - cy_b + 3;
 
     float* T1 = lds;                     // [2][WyM][TX]
-    float* E = T1 + a4(2 * WyM * TX);    // [NF*2][TX]
-    float* WXT = E + a4(NF * 2 * TX);    // [TX][WxM]
+    float* E = T1 + a4(2 * WyM * TX);    // [3][NF*2][TX] (three control rows at the end)
+    float* WXT = E + a4(3 * NF * 2 * TX);    // [TX][WxM]
     float* WYT = WXT + a4(TX * WxM);     // [sy][4]
     const int lx = tid, x = x0 + lx;
     const bool act = x < nx;
@@ -1025,31 +1025,40 @@ k_fused2(const LaunchCtx C) {
     const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, (uint32_t)(P.nvox * 4));
     float* part = reinterpret_cast<float*>(C.ws + C.L.part) + P.part_off +
                   (long long)(item - P.tile_begin) * P.part_stride;
-    auto flush = [&](int kyl) {
+    // x-transpose of the nr completed control rows kyl .. kyl + nr - 1
+    // (accumulator slots 0 .. nr - 1) into this tile's partials
+    auto flush = [&](int kyl, int nr) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f)
+        for (int r = 0; r < 3; ++r)
+            if (r < nr)
 #pragma unroll
-            for (int c = 0; c < 2; ++c) E[(f * 2 + c) * TX + lx] = acc[f][c][0];
+                for (int f = 0; f < NF; ++f)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) E[((r * NF + f) * 2 + c) * TX + lx] = acc[f][c][r];
         __syncthreads();
-        for (int o = tid; o < NF * 2 * Wx; o += NT) {
-            const int kx = o % Wx, fc = o / Wx;
+        for (int o = tid; o < nr * NF * 2 * Wx; o += NT) {
+            const int kx = o % Wx, rfc = o / Wx;
+            const int r = rfc / (NF * 2), fc = rfc - r * (NF * 2);
             const int q0 = max(0, (cx0 + kx - 3) * sx - x0);
             const int q1 = min(TX, (cx0 + kx + 1) * sx - x0);
             float s = 0.f;
-            // eight lanes' terms loaded ahead of their sums, added in lane
-            // order (a term past q1 is 0)
-            for (int q8 = q0; q8 < q1; q8 += 8) {
-                float w[8], e[8];
+            // QB lanes' terms loaded ahead of their sums, added in lane
+            // order (a term past q1 is 0): one round for spacing <= 8 with
+            // MSE; NCC takes 8 at a time, as 32 cost its 4096^2 launch more
+            // registers than the shorter wait saved
+            constexpr int QB = SIM == AIR_SIM_NCC ? 8 : 32;
+            for (int q8 = q0; q8 < q1; q8 += QB) {
+                float w[QB], e[QB];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
+                for (int i = 0; i < QB; ++i) {
                     const int q = min(q8 + i, q1 - 1);
                     w[i] = q8 + i < q1 ? WXT[q * WxM + kx] : 0.f;
-                    e[i] = E[fc * TX + q];
+                    e[i] = E[rfc * TX + q];
                 }
 #pragma unroll
-                for (int i = 0; i < 8; ++i) s += w[i] * e[i];
+                for (int i = 0; i < QB; ++i) s += w[i] * e[i];
             }
-            part[(kyl * WxM + kx) * (NF * 2) + fc] = s;
+            part[((kyl + r) * WxM + kx) * (NF * 2) + fc] = s;
         }
         __syncthreads();
     };
@@ -1141,7 +1150,7 @@ k_fused2(const LaunchCtx C) {
                 }
             }
         }
-        flush(kyl);
+        flush(kyl, 1);
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -1159,18 +1168,8 @@ k_fused2(const LaunchCtx C) {
             V[c][3] = (kyl + 4 < Wy) ? T1[(c * WyM + kyl + 4) * TX + lx] : 0.f;
         }
     }
-    for (int k = Wy - 3; k < Wy; ++k) {
-        flush(k);
-#pragma unroll
-        for (int f = 0; f < NF; ++f)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                acc[f][c][0] = acc[f][c][1];
-                acc[f][c][1] = acc[f][c][2];
-                acc[f][c][2] = acc[f][c][3];
-                acc[f][c][3] = 0.f;
-            }
-    }
+    // the last three control rows in one pass (one wait instead of three)
+    flush(Wy - 3, 3);
     double st[6] = {(double)cnt, (double)m1, (double)m2, (double)m3, (double)m4, (double)m5};
     block_sum<NT, 6>(st, red);
     if (tid == 0) {
