@@ -972,14 +972,16 @@ k_fused2(const LaunchCtx C) {
     }
     for (int i = tid; i < sy * 4; i += NT) WYT[i] = C.consts[P.wtab_off[1] + i];
     {
-        // rows r = c Wy + ky of the x-interpolated window, four at a time:
-        // the loads of a batch are issued before any is used
+        // rows r = c Wy + ky of the x-interpolated window, eight at a time
+        // (the whole window of a 1-cell column): the loads of a batch are
+        // issued before any is used
         const int NC = ncx * P.nc[1];
         const __amdgpu_buffer_rsrc_t rT = make_rsrc(theta, (uint32_t)(2 * NC * 4));
-        for (int r0 = 0; r0 < 2 * Wy; r0 += 4) {
-            v2f t01[4], t23[4];
+        constexpr int RW = 8;
+        for (int r0 = 0; r0 < 2 * Wy; r0 += RW) {
+            v2f t01[RW], t23[RW];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < RW; ++i) {
                 const int r = min(r0 + i, 2 * Wy - 1);
                 const int c = r >= Wy ? 1 : 0, ky = r - c * Wy;
                 const int o = (c * NC + (cy0 + ky) * ncx + ix) * 4;
@@ -988,7 +990,7 @@ k_fused2(const LaunchCtx C) {
                 t23[i] = load2(rT, o + 8, 0);
             }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < RW; ++i) {
                 const int r = r0 + i;
                 if (r < 2 * Wy) {
                     const int c = r >= Wy ? 1 : 0, ky = r - c * Wy;
@@ -1070,7 +1072,7 @@ k_fused2(const LaunchCtx C) {
         // every address is valid) are issued before any row's arithmetic,
         // so a group waits for memory once; the rows are then added in
         // order, as one at a time would.
-        constexpr int RB = 4;
+        constexpr int RB = 8;
         for (int yg = yb; yg < ye; yg += RB) {
             float4 wyr[RB];
             float Fr[RB], fxr[RB], fyr[RB];
