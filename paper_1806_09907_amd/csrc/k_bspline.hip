@@ -579,35 +579,40 @@ k_fused3_s8(const LaunchCtx C) {
         const int kzs = ly / Wy, kys = ly - kzs * Wy;
         const int tb = (cz0 * ncy + cy0) * ncx + ix;   // control (ix, cy0, cz0)
         const int ncxy = ncx * ncy;
+        int kz = kzs, ky = kys;
+        // four rows at a time, all three components: the batch's loads are
+        // issued before any is used (rows past the window read the first
+        // control instead)
+        for (int j = ly; j < Wz * Wy; j += 4 * TY) {
+            v2f t01[4][3], t23[4][3];
+            int kzr[4], kyr[4];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            int kz = kzs, ky = kys;
-            // four rows at a time: the batch's loads are issued before any is
-            // used (rows past the window read the first control instead)
-            for (int j = ly; j < Wz * Wy; j += 4 * TY) {
-                v2f t01[4], t23[4];
-                int kzr[4], kyr[4];
+            for (int i = 0; i < 4; ++i) {
+                kzr[i] = kz;
+                kyr[i] = ky;
+                const bool ok = j + i * TY < Wz * Wy;
+                const int o0 = ok ? (tb + __mul24(kz, ncxy) + __mul24(ky, ncx)) * 4 : tb * 4;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    kzr[i] = kz;
-                    kyr[i] = ky;
-                    const bool ok = j + i * TY < Wz * Wy;
-                    const int o =
-                        ok ? (c * NC + tb + __mul24(kz, ncxy) + __mul24(ky, ncx)) * 4 : tb * 4;
+                for (int c = 0; c < 3; ++c) {
+                    const int o = o0 + c * NC * 4;
                     AIR_CHECK(o >= 0 && o + 16 <= 3 * NC * 4, kDbgControlLoad);
-                    t01[i] = load2(rT, o, 0);
-                    t23[i] = load2(rT, o + 8, 0);
-                    kz += dkz;
-                    ky += dky;
-                    if (ky >= Wy) {
-                        ky -= Wy;
-                        ++kz;
-                    }
+                    t01[i][c] = load2(rT, o, 0);
+                    t23[i][c] = load2(rT, o + 8, 0);
                 }
+                kz += dkz;
+                ky += dky;
+                if (ky >= Wy) {
+                    ky -= Wy;
+                    ++kz;
+                }
+            }
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    if (j + i * TY < Wz * Wy) {
-                        const float v = wx[0] * t01[i].x + wx[1] * t01[i].y + wx[2] * t23[i].x + wx[3] * t23[i].y;
+            for (int i = 0; i < 4; ++i) {
+                if (j + i * TY < Wz * Wy) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const float v = wx[0] * t01[i][c].x + wx[1] * t01[i][c].y +
+                                        wx[2] * t23[i][c].x + wx[3] * t23[i][c].y;
                         T1[((c * WzM + kzr[i]) * WYC + kyr[i]) * TX + lx] = x < nx ? v : 0.f;
                     }
                 }
