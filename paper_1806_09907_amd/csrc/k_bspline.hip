@@ -1051,9 +1051,9 @@ k_fused2(const LaunchCtx C) {
             float s = 0.f;
             // QB lanes' terms loaded ahead of their sums, added in lane
             // order (a term past q1 is 0): one round for spacing <= 8 with
-            // MSE; NCC takes 8 at a time, as 32 cost its 4096^2 launch more
+            // MSE; NCC takes 16 at a time, as 32 cost its 4096^2 launch more
             // registers than the shorter wait saved
-            constexpr int QB = SIM == AIR_SIM_NCC ? 8 : 32;
+            constexpr int QB = SIM == AIR_SIM_NCC ? 16 : 32;
             for (int q8 = q0; q8 < q1; q8 += QB) {
                 float w[QB], e[QB];
 #pragma unroll
