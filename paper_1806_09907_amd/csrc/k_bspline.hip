@@ -1311,7 +1311,9 @@ constexpr int kFinLanes = 8;
 constexpr int kFinBatch = 4;
 constexpr long long kFinFewControls = 1 << 17;   // below this many, NS = kFinLanes
 
-template <int TX, int TY, int SIM, int DIM, int NS>
+// SP: the spacing of every axis when the launch's plans share it at compile
+// time (8, the spacing-8 kernel's plans), else 0 (read from the pair)
+template <int TX, int TY, int SIM, int DIM, int NS, int SP>
 __global__ void __launch_bounds__(kBlock)
 k_finalize(const LaunchCtx C) {
     constexpr int NT = kBlock;
@@ -1395,19 +1397,21 @@ k_finalize(const LaunchCtx C) {
         // column axis: z in 3D, y in 2D
         const int colax = DIM - 1;
         const int jc = (DIM == 3) ? jz : jy;
-        const int ncell = (P.n[colax] - 1) / P.sp[colax] + 1;
+        AIR_CHECK(SP == 0 || (P.sp[0] == SP && P.sp[1] == SP && P.sp[colax] == SP),
+                  kDbgControlLoad);
+        const int ncell = (P.n[colax] - 1) / (SP ? SP : P.sp[colax]) + 1;
         const int tc_lo = max(0, jc - 3) / P.col_cells;
         const int tc_hi = min(ncell - 1, jc) / P.col_cells;
         int tx_lo, tx_hi, ty_lo = 0, ty_hi = 0;
-        tile_range(jx, P.sp[0], P.n[0], TX, &tx_lo, &tx_hi);
-        if (DIM == 3) tile_range(jy, P.sp[1], P.n[1], TY, &ty_lo, &ty_hi);
+        tile_range(jx, SP ? SP : P.sp[0], P.n[0], TX, &tx_lo, &tx_hi);
+        if (DIM == 3) tile_range(jy, SP ? SP : P.sp[1], P.n[1], TY, &ty_lo, &ty_hi);
         constexpr bool kStep = NS > 1;
-        const int spx = P.sp[0];
+        const int spx = SP ? SP : P.sp[0];
         const int qx = TX / spx, rx = TX - qx * spx;
         const int cxs = (tx_lo * TX) / spx, rxs = tx_lo * TX - cxs * spx;
         int spy = 1, qy = 0, ry = 0, cys = 0, rys = 0;
         if (DIM == 3) {
-            spy = P.sp[1];
+            spy = SP ? SP : P.sp[1];
             qy = TY / spy;
             ry = TY - qy * spy;
             cys = (ty_lo * TY) / spy;
@@ -1553,14 +1557,14 @@ static hipError_t launch3s8(const LaunchCtx& C, size_t lds, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int TX, int TY, int SIM, int DIM>
+template <int TX, int TY, int SIM, int DIM, int SP = 0>
 static hipError_t launch_fin(const LaunchCtx& C, int max_ctrl, hipStream_t s) {
     if ((long long)max_ctrl * C.npairs < kFinFewControls) {
         dim3 grid(cdiv(max_ctrl, kBlock / kFinLanes), C.npairs);
-        hipLaunchKernelGGL((k_finalize<TX, TY, SIM, DIM, kFinLanes>), grid, dim3(kBlock), 0, s, C);
+        hipLaunchKernelGGL((k_finalize<TX, TY, SIM, DIM, kFinLanes, SP>), grid, dim3(kBlock), 0, s, C);
     } else {
         dim3 grid(cdiv(max_ctrl, kBlock), C.npairs);
-        hipLaunchKernelGGL((k_finalize<TX, TY, SIM, DIM, 1>), grid, dim3(kBlock), 0, s, C);
+        hipLaunchKernelGGL((k_finalize<TX, TY, SIM, DIM, 1, SP>), grid, dim3(kBlock), 0, s, C);
     }
     return hipGetLastError();
 }
@@ -1583,9 +1587,12 @@ hipError_t launch_bspline(const LaunchCtx& C, int cfg, size_t lds, int max_ctrl,
         if (e != hipSuccess) return e;
         if (ev1) (void)hipEventRecord(ev1, s);
         switch (cfg) {
-            case 0: case 3: return ncc ? launch_fin<32, 8, 1, 3>(C, max_ctrl, s) : launch_fin<32, 8, 0, 3>(C, max_ctrl, s);
+            case 0: return ncc ? launch_fin<32, 8, 1, 3>(C, max_ctrl, s) : launch_fin<32, 8, 0, 3>(C, max_ctrl, s);
             case 1: return ncc ? launch_fin<64, 4, 1, 3>(C, max_ctrl, s) : launch_fin<64, 4, 0, 3>(C, max_ctrl, s);
-            default: return ncc ? launch_fin<16, 16, 1, 3>(C, max_ctrl, s) : launch_fin<16, 16, 0, 3>(C, max_ctrl, s);
+            case 2: return ncc ? launch_fin<16, 16, 1, 3>(C, max_ctrl, s) : launch_fin<16, 16, 0, 3>(C, max_ctrl, s);
+            // the spacing-8 kernel's plans: spacing 8 on every axis
+            case 3: return ncc ? launch_fin<32, 8, 1, 3, 8>(C, max_ctrl, s) : launch_fin<32, 8, 0, 3, 8>(C, max_ctrl, s);
+            default: return ncc ? launch_fin<16, 16, 1, 3, 8>(C, max_ctrl, s) : launch_fin<16, 16, 0, 3, 8>(C, max_ctrl, s);
         }
     }
     const int nblk = xcd_grid(C.ntiles_total, C.nreg_total);
