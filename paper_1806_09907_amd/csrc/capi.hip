@@ -339,12 +339,14 @@ static air_status build_tables(air_plan* P) {
     const bool wend = P->transform == AIR_TF_WENDLAND;
     const TileCfg cfg = (d == 3) ? kCfg3[P->tiling] : kCfg2[P->tiling];
     const int NF = P->sim == AIR_SIM_NCC ? 3 : 1;
-    bool all_s8 = bs && d == 3;
+    bool all_s8 = bs;
     for (int i = 0; i < P->npairs && all_s8; ++i)
-        for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < d; ++a)
             if (P->probs[i].spacing[a] != 8) all_s8 = false;
-    P->variant = (d == 3) ? variant_of(cfg, all_s8) : 0;
-    const bool s8 = P->variant >= 3 && P->variant != 1;
+    // 3D: the tile configuration and its kernel; 2D: 8 when every pair has
+    // spacing 8 (its finalize then takes the spacing at compile time)
+    P->variant = (d == 3) ? variant_of(cfg, all_s8) : (all_s8 ? 8 : 0);
+    const bool s8 = d == 3 && (P->variant == 3 || P->variant == 4);
     P->pd.assign(P->npairs, PairDesc{});
     P->consts.clear();
     size_t stats_n = 0, part_n = 0, param_n = 0, regpart_n = 0, dense_n = 0;

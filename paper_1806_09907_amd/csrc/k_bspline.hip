@@ -1569,7 +1569,8 @@ static hipError_t launch_fin(const LaunchCtx& C, int max_ctrl, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Tile configurations (id -> TX, TY). Column cells come from the plan.
+// cfg: in 3D the tile configuration (id -> TX, TY); in 2D 8 when every pair
+// has spacing 8, else 0. Column cells come from the plan.
 hipError_t launch_bspline(const LaunchCtx& C, int cfg, size_t lds, int max_ctrl,
                           hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     hipError_t e = hipSuccess;
@@ -1603,6 +1604,9 @@ hipError_t launch_bspline(const LaunchCtx& C, int cfg, size_t lds, int max_ctrl,
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev1) (void)hipEventRecord(ev1, s);
+    if (cfg == 8)   // every pair has spacing 8
+        return C.sim == AIR_SIM_NCC ? launch_fin<64, 1, 1, 2, 8>(C, max_ctrl, s)
+                                    : launch_fin<64, 1, 0, 2, 8>(C, max_ctrl, s);
     return C.sim == AIR_SIM_NCC ? launch_fin<64, 1, 1, 2>(C, max_ctrl, s)
                                 : launch_fin<64, 1, 0, 2>(C, max_ctrl, s);
 }
