@@ -88,11 +88,12 @@ static const TileCfg kCfg2[] = {{64, 1, 2}, {64, 1, 4}, {64, 1, 8}, {64, 1, 16},
 // (16 x 16 with 16, 8, 4, 2 cells), and the tile count that fills the chip
 static const int kCfg3Fill[] = {6, 8, 5, 9};
 constexpr int kFillTiles = 4096;
-// a launch with fewer tiles takes the longest column that still gives every
-// CU one tile: with the tile set-up and tail cheap, a longer walk pays more
-// than a second resident block (one 128^3 pair: 4-cell columns, 256 tiles,
-// 30.2 us per evaluation against 31.8 us with 2-cell columns, 512 tiles)
-constexpr int kOneTilePerCu = 256;
+// a launch with fewer tiles takes the longest column that still gives the
+// CUs about two tiles each: one 128^3 pair 26.3 us per evaluation with 2-cell
+// columns (512 tiles) against 27.9 us with 4-cell (256); 160^3 33.3 us with
+// 4-cell (500 tiles) against 46.1 with 8-cell (300) and 39.3 with 2-cell
+// (1000)
+constexpr int kTwoTilesPerCu = 448;
 // the same for 2D B-spline plans (64-lane columns of 16, 8, 4, 2, 1 cells)
 static const int kCfg2Fill[] = {3, 2, 1, 0, 4};
 constexpr int kFillTiles2 = 2048;
@@ -953,7 +954,7 @@ air_status air_plan_create(const air_problem* probs, int32_t npairs, air_plan** 
     }
     // Default tile configuration of 3D spacing-8 B-spline plans: 16 x 16
     // columns, the longest column (16, 8, 4, 2 cells) whose launch still has
-    // kFillTiles tiles, else the longest with one tile per CU (kOneTilePerCu),
+    // kFillTiles tiles, else the longest with about two per CU (kTwoTilesPerCu),
     // else the one with the most tiles; of 2D B-spline plans: the longest
     // column (16 .. 1 cells) with kFillTiles2 tiles, else the most tiles.
     // air_plan_set_tiling (and the autotuner) override it.
@@ -968,7 +969,7 @@ air_status air_plan_create(const air_problem* probs, int32_t npairs, air_plan** 
             if (build_tables(P) != AIR_OK) continue;
             chosen = cand[k];
             if (P->ntiles_total >= fill) break;
-            if (!bs2 && per_cu < 0 && P->ntiles_total >= kOneTilePerCu) per_cu = cand[k];
+            if (!bs2 && per_cu < 0 && P->ntiles_total >= kTwoTilesPerCu) per_cu = cand[k];
         }
         if (P->ntiles_total < fill && per_cu >= 0) chosen = per_cu;
         if (chosen != P->tiling) {

@@ -56,8 +56,8 @@ def test_plan_create_and_queries():
 def _default_tiling(dim, sizes, fill):
     """The documented default: among the columns of 16, 8, 4, 2 cells (3D,
     16 x 16 tiles) or 16, 8, 4, 2, 1 cells (2D, 64 x 1), the longest whose
-    launch has `fill` tiles, else (3D) the longest with at least 256 tiles,
-    one per CU, else the one with the most tiles."""
+    launch has `fill` tiles, else (3D) the longest with at least 448 tiles,
+    about two per CU, else the one with the most tiles."""
     from paper_1806_09907_amd import api
 
     shape = (16, 16) if dim == 3 else (64, 1)
@@ -75,7 +75,7 @@ def _default_tiling(dim, sizes, fill):
                 -(-ncol // cells)
         if tiles >= fill:
             return ids[cells]
-        if dim == 3 and per_cu is None and tiles >= 256:
+        if dim == 3 and per_cu is None and tiles >= 448:
             per_cu = ids[cells]
         if tiles > best_tiles:
             best, best_tiles = ids[cells], tiles
@@ -85,8 +85,9 @@ def _default_tiling(dim, sizes, fill):
 @pytest.mark.parametrize("dim,sizes", [
     (3, [(128, 128, 128)] * 64),   # 16-cell columns already give 4096 tiles
     (3, [(128, 128, 128)] * 8),    # 2-cell columns
-    (3, [(128, 128, 128)]),        # no column reaches 4096 tiles: 4-cell, 256 tiles
-    (3, [(64, 64, 64)]),           # none reaches 256 tiles either: 2-cell, the most
+    (3, [(128, 128, 128)]),        # no column reaches 4096 tiles: 2-cell, 512 tiles
+    (3, [(160, 160, 160)]),        # 4-cell, 500 tiles
+    (3, [(64, 64, 64)]),           # none reaches 448 tiles either: 2-cell, the most
     (3, [(96, 112, 160), (144, 128, 96)] * 6),
     (2, [(64, 64)]),
     (2, [(1024, 1024)]),
